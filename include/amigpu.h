@@ -1,0 +1,170 @@
+/*
+ * amigpu -- batched algorithmic Matsubara integration (AMI) on MI355X (gfx950).
+ *
+ * C ABI of libamigpu.so.  The method is that of Burke & LeBlanc, "TorchAmi:
+ * Generalized CPU/GPU Implementation of Algorithmic Matsubara Integration"
+ * (arXiv 2311.17189):
+ *
+ *   construct: the integrand of Eq. (1), a product of propagators Eq. (2)
+ *              G_j = 1 / (sum_l alpha_jl w_l + sum_i eps_ji E_i), is summed over
+ *              the fermionic Matsubara frequencies nu_1..nu_n (w_l = i nu_l) by
+ *              repeated residues (Eqs. (3)-(4)), giving terms A * FT * R (Eq. (6));
+ *   evaluate:  the terms are evaluated for a batch of N_E energy rows and N_F
+ *              external-frequency rows, giving an [N_F, N_E] result (Sec. 2.3).
+ *
+ * Conventions shared by every call:
+ *   - Integers labelling a diagram are row-major int8.  Frequency slot order is
+ *     the summed frequencies first, external frequencies last (Sec. 5.1.1).
+ *   - Complex values are interleaved (re, im) float64 pairs (complex128).
+ *   - Buffers passed to evaluate calls are DEVICE pointers on the device that is
+ *     current on the calling thread; the caller owns them.  Scalars and arrays
+ *     documented as host arrays are read before the call returns.
+ *   - Evaluate calls are asynchronous on `hip_stream` (a hipStream_t; NULL is the
+ *     default stream).  All argument checks happen on the host before any launch;
+ *     a non-AMI_OK status means nothing was launched.  The message of the last
+ *     failure on the calling thread is returned by amiLastError().
+ *   - An AmiTerms handle may be used from several threads for evaluation once it
+ *     has been uploaded to a device (amiTermsUpload); construction and amiFree
+ *     must not race with other uses of the same handle.
+ */
+#ifndef AMIGPU_H
+#define AMIGPU_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    AMI_OK = 0,
+    AMI_E_ARG = -1,         /* bad pointer, size, stride or flag                  */
+    AMI_E_LABEL = -2,       /* invalid labels (see amiConstruct)                   */
+    AMI_E_MULTIPOLE = -3,   /* two denominators share a pole (Eq. (5) not handled) */
+    AMI_E_COEFF = -4,       /* summed frequency with coefficient other than +-1    */
+    AMI_E_HIP = -5,         /* a HIP runtime call failed                           */
+    AMI_E_OOM = -6,         /* allocation failed                                   */
+    AMI_E_UNSUPPORTED = -7  /* valid input outside what this build evaluates       */
+} AmiStatus;
+
+/* amiConstruct flags */
+#define AMI_FACTORIZE 1u    /* also build the factorized Fermi tree (Sec. 2.1, Fig. 1) */
+
+typedef struct AmiTerms AmiTerms;
+
+/*
+ * amiConstruct -- symbolic solution of one integrand (Sec. 2.2; Sec. 5.1.2).
+ *
+ *   n_g       number of propagators in R0 (rows), >= 1
+ *   n_eps     length of each epsilon_t row (energy placeholders), 1..32
+ *   n_freq    length of each alpha_t row (summed + external frequencies), 1..16
+ *   n_int     number of nested sums, 0..n_freq; slots 0..n_int-1 are summed in order
+ *   alpha     host int8 [n_g][n_freq], entries in {-1,0,1}
+ *   eps       host int8 [n_g][n_eps],  entries in {-1,0,1}
+ *   fermionic host uint8 [n_freq]: nonzero = fermionic frequency; NULL = all
+ *             fermionic.  Summed slots must be fermionic (Eq. (3)).
+ *   flags     0 or AMI_FACTORIZE
+ *   out       receives a new handle (owned by the caller, release with amiFree)
+ *
+ * Host-only: no device memory is touched.  Errors: AMI_E_ARG (sizes/pointers),
+ * AMI_E_LABEL (coefficients outside {-1,0,1}, bosonic summed slot, a summed
+ * frequency absent from every denominator of a term), AMI_E_COEFF (a summed
+ * frequency reached coefficient +-2 through a substitution), AMI_E_MULTIPOLE
+ * (coincident poles, or a denominator that vanishes identically).
+ */
+AmiStatus amiConstruct(int32_t n_g, int32_t n_eps, int32_t n_freq, int32_t n_int,
+                       const int8_t *alpha, const int8_t *eps, const uint8_t *fermionic,
+                       uint32_t flags, AmiTerms **out);
+
+/* Release a handle and its device tables (every device it was uploaded to). */
+void amiFree(AmiTerms *terms);
+
+/*
+ * amiTermsInfo -- sizes of the solution, info[0..15] (host array):
+ *   0 T       flat terms after canonical merging (FACTORIZE=false form, Sec. 2.2)
+ *   1 n_int   2 n_eps   3 n_freq   4 n_ext (= n_freq - n_int)
+ *   5 L       distinct leaves (Fermi/Bose functions of an energy combination)
+ *   6 D       distinct denominators
+ *   7 G       groups of terms sharing the same denominators (the top level of
+ *             the factorized form: FT_g * R_g)
+ *   8 tree nodes of the factorized Fermi tree (0 unless built with AMI_FACTORIZE)
+ *   9 raw terms before canonical merging
+ *   10 leaves per term (= n_int)   11 denominators per term (= n_g - n_int)
+ *   12..15 reserved (0)
+ */
+AmiStatus amiTermsInfo(const AmiTerms *terms, int64_t info[16]);
+
+/*
+ * amiTermsCanonical -- the canonical flat term list as an int32 stream:
+ *   header n_int, n_eps, n_freq, T; then per term: prefactor s; n_int leaves as
+ *   (sigma, e[0..n_eps)); (n_g - n_int) denominators as (e[0..n_eps), a[0..n_freq)).
+ * sigma = +1 is the Fermi function 1/(exp(y)+1), -1 is 1/(1-exp(y)) (= -n_B).
+ * Canonical: each denominator's first non-zero coefficient is positive (its sign
+ * moved into s), leaves sorted by (sigma, e), denominators by (e, a), equal
+ * terms merged, terms sorted by (leaves, denominators).
+ * With `from_tree` nonzero the list is the expansion of the factorized tree
+ * (requires AMI_FACTORIZE).  If buf is NULL or cap is too small, *len gets the
+ * required length and AMI_E_ARG is returned when buf is non-NULL.
+ */
+AmiStatus amiTermsCanonical(const AmiTerms *terms, int32_t from_tree, int32_t *buf,
+                            int64_t cap, int64_t *len);
+
+/* Upload the evaluation tables to the current device (done on first evaluate
+ * otherwise; call it before capturing evaluate calls into a HIP graph). */
+AmiStatus amiTermsUpload(AmiTerms *terms);
+
+/*
+ * amiEvaluate -- batched evaluation (Sec. 2.3):
+ *   out[f][s] = sum_t s_t * prod_leaves f_sigma(beta*(e.E_s) [+ beta*e_reg if sigma=-1])
+ *                          / prod_dens (e.E_s + a_ext . w_f)
+ *
+ *   energies   device float64, element (s, i) at energies[s*stride_s + i*stride_i],
+ *              s < n_e, i < n_eps.  (The paper's energy_t [N_E][N] is stride_s =
+ *              n_eps, stride_i = 1.)  Real energies.
+ *   n_e        energy rows (>= 0; 0 launches nothing but still zeroes out_sum)
+ *   ext_freqs  device complex128 [n_f][n_ext]: the external slots of frequency_t
+ *              (i nu for Matsubara, omega + i Gamma for real frequency, Sec. 1)
+ *   n_f        frequency rows (>= 1)
+ *   beta       inverse temperature (> 0); e_reg regulator added to the energy
+ *              argument of Bose-type leaves only (0 disables it)
+ *   out        device complex128 [n_f][n_e], or NULL
+ *   out_sum    device complex128 [n_f] = sum over s of out[f][s] (the Monte-Carlo
+ *              row sum of Sec. 2.3), or NULL.  Reduced in a fixed order: repeated
+ *              calls give bitwise-equal results.
+ * At least one of out/out_sum must be non-NULL.  Uses an internal workspace for
+ * the row sums (allocated on first need, grown on demand).
+ */
+AmiStatus amiEvaluate(AmiTerms *terms,
+                      const double *energies, int64_t n_e, int64_t stride_s, int64_t stride_i,
+                      const double *ext_freqs, int64_t n_f,
+                      double beta, double e_reg,
+                      double *out, double *out_sum, void *hip_stream);
+
+/*
+ * amiEvaluateHubbard -- amiEvaluate with the energies computed in the kernel
+ * from momenta (Sec. 5.2): K_j = sum_l alpha_jl k_l with the external momentum
+ * q in the external slot, E_j = -eps(K_j) = 2t(cos K_jx + cos K_jy) + mu (2D
+ * square lattice).  Requires n_eps == n_g (one energy per propagator).
+ *
+ *   k        device float64 [n_e][2*n_int] row-major (k1x k1y k2x k2y ...),
+ *            row stride stride_k (>= 2*n_int) in doubles
+ *   q        host float64 [2*n_ext]
+ */
+AmiStatus amiEvaluateHubbard(AmiTerms *terms,
+                             const double *k, int64_t n_e, int64_t stride_k,
+                             const double *q, double t, double mu,
+                             const double *ext_freqs, int64_t n_f,
+                             double beta, double e_reg,
+                             double *out, double *out_sum, void *hip_stream);
+
+/* Message of the last failed call on this thread ("" if none). */
+const char *amiLastError(void);
+
+/* Library version string. */
+const char *amiVersion(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* AMIGPU_H */

@@ -1,0 +1,16 @@
+"""Batched algorithmic Matsubara integration (AMI) on MI355X (gfx950).
+
+Python face of ``libamigpu.so`` (C ABI declared in ``include/amigpu.h``): a
+thin ctypes layer that only marshals arguments.  Construction of the symbolic
+solution (Burke & LeBlanc, arXiv 2311.17189, Sec. 2.2) runs in the library's
+C++ host code; every evaluation step runs in its HIP kernels.  PyTorch is used
+only to hold device memory and to name the stream.
+
+The library must have been built (``paper_2311_17189_amd.build.build()`` or
+``__graft_entry__.build()``); importing this package without it raises.
+"""
+from ._lib import (AmiError, Terms, evaluate, evaluate_hubbard, lib_path,  # noqa: F401
+                   load_library, version)
+
+__all__ = ["AmiError", "Terms", "evaluate", "evaluate_hubbard", "lib_path",
+           "load_library", "version"]

@@ -1,0 +1,236 @@
+"""ctypes binding of libamigpu.so: argument marshalling only.
+
+Names follow the C ABI (``include/amigpu.h``): :class:`Terms` wraps
+``amiConstruct`` / ``amiTermsInfo`` / ``amiTermsCanonical`` / ``amiFree``;
+:func:`evaluate` and :func:`evaluate_hubbard` wrap ``amiEvaluate`` and
+``amiEvaluateHubbard``, passing device pointers of torch tensors and the
+current torch stream.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from typing import Optional, Sequence
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_LIB_NAME = "libamigpu.so"
+
+AMI_FACTORIZE = 1
+
+_STATUS = {0: "AMI_OK", -1: "AMI_E_ARG", -2: "AMI_E_LABEL", -3: "AMI_E_MULTIPOLE",
+           -4: "AMI_E_COEFF", -5: "AMI_E_HIP", -6: "AMI_E_OOM", -7: "AMI_E_UNSUPPORTED"}
+
+
+class AmiError(RuntimeError):
+    """A non-AMI_OK status; ``.status`` holds the code name."""
+
+    def __init__(self, code: int, msg: str):
+        self.code = code
+        self.status = _STATUS.get(code, str(code))
+        super().__init__(f"{self.status}: {msg}")
+
+
+_lib = None
+
+
+def lib_path() -> str:
+    return os.path.join(_HERE, _LIB_NAME)
+
+
+def load_library():
+    """Load libamigpu.so once; raise if it has not been built."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    path = lib_path()
+    if not os.path.exists(path):
+        raise ImportError(f"{path} is missing: build it with paper_2311_17189_amd.build.build()")
+    lib = ctypes.CDLL(path)
+    c_i32, c_i64, c_u32, c_dbl = ctypes.c_int32, ctypes.c_int64, ctypes.c_uint32, ctypes.c_double
+    vp = ctypes.c_void_p
+    lib.amiConstruct.argtypes = [c_i32, c_i32, c_i32, c_i32, vp, vp, vp, c_u32, ctypes.POINTER(vp)]
+    lib.amiConstruct.restype = c_i32
+    lib.amiFree.argtypes = [vp]
+    lib.amiFree.restype = None
+    lib.amiTermsInfo.argtypes = [vp, vp]
+    lib.amiTermsInfo.restype = c_i32
+    lib.amiTermsCanonical.argtypes = [vp, c_i32, vp, c_i64, ctypes.POINTER(c_i64)]
+    lib.amiTermsCanonical.restype = c_i32
+    lib.amiTermsUpload.argtypes = [vp]
+    lib.amiTermsUpload.restype = c_i32
+    lib.amiEvaluate.argtypes = [vp, vp, c_i64, c_i64, c_i64, vp, c_i64, c_dbl, c_dbl, vp, vp, vp]
+    lib.amiEvaluate.restype = c_i32
+    lib.amiEvaluateHubbard.argtypes = [vp, vp, c_i64, c_i64, vp, c_dbl, c_dbl, vp, c_i64, c_dbl,
+                                       c_dbl, vp, vp, vp]
+    lib.amiEvaluateHubbard.restype = c_i32
+    lib.amiLastError.argtypes = []
+    lib.amiLastError.restype = ctypes.c_char_p
+    lib.amiVersion.argtypes = []
+    lib.amiVersion.restype = ctypes.c_char_p
+    _lib = lib
+    return lib
+
+
+def _check(code: int):
+    if code != 0:
+        msg = load_library().amiLastError().decode()
+        raise AmiError(code, msg)
+
+
+def version() -> str:
+    return load_library().amiVersion().decode()
+
+
+class Terms:
+    """Symbolic AMI solution of one integrand (``amiConstruct``).
+
+    ``alpha`` int [nG, nF] (summed slots first, external last), ``eps`` int
+    [nG, nE], ``n_int`` number of sums, ``fermionic`` optional 0/1 [nF].
+    """
+
+    def __init__(self, alpha, eps, n_int: int, fermionic=None, factorize: bool = False):
+        lib = load_library()
+        a = np.ascontiguousarray(np.asarray(alpha, dtype=np.int8))
+        e = np.ascontiguousarray(np.asarray(eps, dtype=np.int8))
+        if a.ndim != 2 or e.ndim != 2:
+            raise AmiError(-1, "alpha and eps must be 2-D")
+        f = None
+        if fermionic is not None:
+            f = np.ascontiguousarray(np.asarray(fermionic, dtype=np.uint8).reshape(-1))
+        h = ctypes.c_void_p()
+        code = lib.amiConstruct(a.shape[0], e.shape[1], a.shape[1], int(n_int),
+                                a.ctypes.data, e.ctypes.data,
+                                None if f is None else f.ctypes.data,
+                                AMI_FACTORIZE if factorize else 0, ctypes.byref(h))
+        _check(code)
+        self._h = h
+        self.n_g, self.n_freq = a.shape
+        self.n_eps = e.shape[1]
+        self.n_int = int(n_int)
+        self.alpha = a
+        self.eps = e
+
+    @classmethod
+    def from_diagram(cls, d, factorize: bool = False) -> "Terms":
+        return cls(d.alpha, d.eps, d.n_int, d.fermionic, factorize)
+
+    @property
+    def handle(self) -> int:
+        return self._h.value
+
+    def info(self) -> dict:
+        buf = np.zeros(16, dtype=np.int64)
+        _check(load_library().amiTermsInfo(self._h, buf.ctypes.data))
+        keys = ["T", "n_int", "n_eps", "n_freq", "n_ext", "L", "D", "G", "tree_nodes",
+                "raw_terms", "leaves_per_term", "dens_per_term"]
+        return {k: int(buf[i]) for i, k in enumerate(keys)}
+
+    def canonical(self, from_tree: bool = False) -> np.ndarray:
+        lib = load_library()
+        n = ctypes.c_int64()
+        _check(lib.amiTermsCanonical(self._h, int(from_tree), None, 0, ctypes.byref(n)))
+        buf = np.zeros(n.value, dtype=np.int32)
+        _check(lib.amiTermsCanonical(self._h, int(from_tree), buf.ctypes.data, n.value, ctypes.byref(n)))
+        return buf
+
+    def upload(self):
+        _check(load_library().amiTermsUpload(self._h))
+
+    def close(self):
+        if getattr(self, "_h", None) is not None and self._h.value:
+            load_library().amiFree(self._h)
+            self._h = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def _stream_ptr(stream) -> Optional[int]:
+    import torch
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return s.cuda_stream
+
+
+def _freqs(ext_freqs, terms: Terms):
+    import torch
+    w = ext_freqs
+    if w.dim() == 1:
+        w = w.reshape(-1, 1)
+    n_ext = terms.n_freq - terms.n_int
+    if w.shape[1] == terms.n_freq and n_ext != terms.n_freq:
+        w = w[:, terms.n_int:]          # full frequency_t rows: keep the external slots
+    if w.dtype != torch.complex128 or not w.is_cuda:
+        raise AmiError(-1, "ext_freqs must be a complex128 CUDA tensor")
+    if w.shape[1] != n_ext:
+        raise AmiError(-1, f"ext_freqs needs {n_ext} external columns")
+    return w.contiguous()
+
+
+def _outputs(n_f, n_e, device, want_out, want_sum, out, out_sum):
+    import torch
+    if want_out and out is None:
+        out = torch.empty((n_f, n_e), dtype=torch.complex128, device=device)
+    if want_sum and out_sum is None:
+        out_sum = torch.empty((n_f,), dtype=torch.complex128, device=device)
+    if out is not None and (out.dtype != torch.complex128 or tuple(out.shape) != (n_f, n_e)
+                            or not out.is_contiguous() or out.device != device):
+        raise AmiError(-1, f"out must be a contiguous complex128 [{n_f}, {n_e}] tensor on {device}")
+    if out_sum is not None and (out_sum.dtype != torch.complex128 or tuple(out_sum.shape) != (n_f,)
+                                or not out_sum.is_contiguous() or out_sum.device != device):
+        raise AmiError(-1, f"out_sum must be a contiguous complex128 [{n_f}] tensor on {device}")
+    return out, out_sum
+
+
+def evaluate(terms: Terms, energies, ext_freqs, beta: float, e_reg: float = 0.0,
+             want_out: bool = True, want_sum: bool = False, out=None, out_sum=None,
+             stream=None):
+    """``amiEvaluate``: energies float64 CUDA [N_E, nE] (any strides), ext_freqs
+    complex128 CUDA [N_F, n_ext] (or the full [N_F, nF] rows of Sec. 2.3).
+    Returns ``(out [N_F, N_E] or None, out_sum [N_F] or None)``."""
+    import torch
+    if energies.dtype != torch.float64 or not energies.is_cuda or energies.dim() != 2:
+        raise AmiError(-1, "energies must be a 2-D float64 CUDA tensor")
+    if energies.shape[1] != terms.n_eps:
+        raise AmiError(-1, f"energies needs {terms.n_eps} columns")
+    w = _freqs(ext_freqs, terms)
+    n_e, n_f = energies.shape[0], w.shape[0]
+    out, out_sum = _outputs(n_f, n_e, energies.device, want_out, want_sum, out, out_sum)
+    st_s, st_i = energies.stride()
+    code = load_library().amiEvaluate(
+        terms._h, energies.data_ptr() if n_e else None, n_e, max(st_s, 1), max(st_i, 1),
+        w.data_ptr(), n_f, float(beta), float(e_reg),
+        out.data_ptr() if out is not None else None,
+        out_sum.data_ptr() if out_sum is not None else None,
+        _stream_ptr(stream))
+    _check(code)
+    return out, out_sum
+
+
+def evaluate_hubbard(terms: Terms, k, q: Sequence[float], t: float, mu: float, ext_freqs,
+                     beta: float, e_reg: float = 0.0, want_out: bool = True,
+                     want_sum: bool = False, out=None, out_sum=None, stream=None):
+    """``amiEvaluateHubbard``: momenta k float64 CUDA [N_E, 2*n_int] (row-major
+    rows, Sec. 5.2), external momentum q (host, 2*n_ext values), hopping t and
+    chemical potential mu of eps(k) = -2t(cos kx + cos ky) - mu."""
+    import torch
+    if k.dtype != torch.float64 or not k.is_cuda or k.dim() != 2:
+        raise AmiError(-1, "k must be a 2-D float64 CUDA tensor")
+    if k.shape[1] != 2 * terms.n_int or (k.shape[0] > 0 and k.stride(1) != 1):
+        raise AmiError(-1, "k must be [N_E, 2*n_int] with unit column stride")
+    w = _freqs(ext_freqs, terms)
+    n_e, n_f = k.shape[0], w.shape[0]
+    out, out_sum = _outputs(n_f, n_e, k.device, want_out, want_sum, out, out_sum)
+    qa = np.ascontiguousarray(np.asarray(q, dtype=np.float64).reshape(-1))
+    code = load_library().amiEvaluateHubbard(
+        terms._h, k.data_ptr() if n_e else None, n_e, max(k.stride(0), 2 * terms.n_int),
+        qa.ctypes.data, float(t), float(mu), w.data_ptr(), n_f, float(beta), float(e_reg),
+        out.data_ptr() if out is not None else None,
+        out_sum.data_ptr() if out_sum is not None else None,
+        _stream_ptr(stream))
+    _check(code)
+    return out, out_sum

@@ -1,0 +1,73 @@
+"""Helpers for GPU-vs-oracle parity tests (test infrastructure).
+
+Error metric: at every (frequency, sample) point the absolute difference is
+divided by ``sum_t |v_t|``, the sum of the magnitudes of the flat terms
+computed by the oracle.  That is the scale of the rounding error of any
+evaluation of the sum, so the bound holds whether or not the terms cancel.
+Points within ``near`` of a pole of one term -- a Bose-type leaf argument
+``|e.E| < near`` or a denominator ``|D| < near`` -- lose digits to the
+rounding of their arguments in float64 on both sides of the comparison and are
+held to the looser ``tol_near``.
+"""
+from __future__ import annotations
+
+import numpy as np
+
+from oracle.construct import canonical, construct
+from oracle.evaluate import evaluate_terms, energies_from_k, term_magnitudes
+
+TOL = 1e-10        # relative to sum_t |v_t|, away from poles
+TOL_NEAR = 1e-6    # within NEAR of a pole of one term
+NEAR = 1e-6
+
+
+def oracle_terms(d):
+    return canonical(construct(d.alpha, d.eps, d.n_int, d.fermionic))
+
+
+def pole_distance(terms, n_int, E, w, e_reg=0.0):
+    """min over Bose-type leaves of |e.E (+e_reg)| and over denominators of
+    |D|, per (frequency, sample)."""
+    E = np.asarray(E, dtype=np.float64)
+    w = np.asarray(w)
+    if w.ndim == 1:
+        w = w[:, None]
+    dist = np.full((w.shape[0], E.shape[0]), np.inf)
+    for _, leaves, dens in terms:
+        for sigma, e in leaves:
+            if sigma == -1:
+                x = np.abs(E @ np.asarray(e, dtype=np.float64) + e_reg)
+                dist = np.minimum(dist, x[None, :])
+        for e, a in dens:
+            base = E @ np.asarray(e, dtype=np.float64)
+            ext = np.asarray(a[n_int:], dtype=np.float64)
+            dd = np.abs(base[None, :] + (w @ ext)[:, None])
+            dist = np.minimum(dist, dd)
+    return dist
+
+
+def reference(d, E, w, beta, e_reg=0.0, terms=None):
+    terms = terms if terms is not None else oracle_terms(d)
+    ref = evaluate_terms(terms, d.n_int, E, w, beta, e_reg).astype(np.complex128)
+    scale = term_magnitudes(terms, d.n_int, E, w, beta, e_reg).astype(np.float64)
+    dist = pole_distance(terms, d.n_int, E, w, e_reg)
+    return ref, scale, dist
+
+
+def reference_hubbard(d, k, q, t, mu, w, beta, e_reg=0.0, terms=None):
+    E = energies_from_k(d.alpha, k, q, t, mu)
+    ref, scale, dist = reference(d, E, w, beta, e_reg, terms)
+    return ref, scale, dist, E.astype(np.float64)
+
+
+def check(got, ref, scale, dist, tol=TOL, tol_near=TOL_NEAR, near=NEAR, label=""):
+    got = np.asarray(got)
+    err = np.abs(got - ref) / np.maximum(scale, 1e-300)
+    far = dist >= near
+    assert np.all(np.isfinite(got[far])), f"{label}: non-finite output away from poles"
+    worst = float(err[far].max()) if far.any() else 0.0
+    assert worst <= tol, f"{label}: max error {worst:.3e} > {tol:.1e} (away from poles)"
+    if (~far).any():
+        worst_near = float(np.nanmax(err[~far]))
+        assert worst_near <= tol_near, f"{label}: max error {worst_near:.3e} near poles"
+    return worst
