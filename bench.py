@@ -7,12 +7,15 @@ Workload (one step = one pass of the evaluation path over one batch):
   10^6 momentum samples k uniform in the Brillouin zone, resident in HBM;
   energies E_j = 2t(cos K_jx + cos K_jy) + mu computed in the kernel (t = 1,
   mu = 0, q = (pi/2, pi/2)); beta = 5; one external Matsubara frequency i pi/beta.
-  The step evaluates out[N_F, N_E] and its Monte-Carlo row sum out_sum[N_F].
+  The step evaluates out[N_F, N_E] and its Monte-Carlo row sum out_sum[N_F]
+  (forward), then the gradients of the summed integrand with respect to every
+  momentum component, mu, t, beta and the external frequency (adjoint).
 
 Metric: term-evaluations/s = T * N_E * N_F / (seconds per step), T the number
-of canonical flat terms.  Also reported: the forward kernel's algorithmic FP64
-FLOP rate against the FP64 vector peak, and the oracle timed on host cores.
-Prints one JSON line.
+of canonical flat terms; the forward alone and the plain double-table kernel
+are reported beside it.  Also reported: the algorithmic FP64 FLOP rate of the
+dominant kernel against the FP64 vector peak, and the oracle timed on host
+cores.  Prints one JSON line.
 """
 from __future__ import annotations
 
@@ -40,6 +43,9 @@ def parse():
     ap.add_argument("--beta", type=float, default=5.0)
     ap.add_argument("--cpu-seconds", type=float, default=15.0,
                     help="target duration of the oracle CPU baseline (0 disables it)")
+    ap.add_argument("--copy-mib", type=int, default=0,
+                    help="first copy a buffer of this many MiB device to device (a plain copy "
+                         "kernel of known size, to scale hardware byte counters)")
     return ap.parse_args()
 
 
@@ -114,39 +120,83 @@ def main():
     n_f = w.shape[0]
     out = torch.empty((n_f, n_e), dtype=torch.complex128, device=dev)
     out_sum = torch.empty((n_f,), dtype=torch.complex128, device=dev)
+    # cotangent of the row sum: gradients of Re sum_s I(s) (the summed integrand)
+    g_sum = torch.ones((n_f,), dtype=torch.complex128, device=dev)
     stream = torch.cuda.current_stream()
 
     def fwd():
         amd.evaluate_hubbard(terms, k, q, hop_t, mu, w, args.beta, want_sum=True,
                              out=out, out_sum=out_sum, stream=stream)
 
+    def adj():
+        return amd.evaluate_hubbard_adjoint(terms, k, q, hop_t, mu, w, args.beta,
+                                            grad_sum=g_sum, stream=stream)
+
+    if args.copy_mib > 0:
+        src = torch.empty(args.copy_mib * (1 << 20) // 8, dtype=torch.float64, device=dev).fill_(1.0)
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
+
     for _ in range(args.warmup):
         fwd()
+        adj()
     torch.cuda.synchronize()
+    fwd_variant = amd.last_variant()
 
-    # timed region: K steps, with events around every launch on the launch stream
-    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
-          for _ in range(args.steps)]
+    # timed region: K steps (forward + adjoint), HIP events around every launch
+    # on the launch stream
+    ev_f = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+            for _ in range(args.steps)]
+    ev_a = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+            for _ in range(args.steps)]
     start = torch.cuda.Event(enable_timing=True)
     stop = torch.cuda.Event(enable_timing=True)
     torch.cuda.synchronize()
     wall0 = time.perf_counter()
     start.record(stream)
     for i in range(args.steps):
-        ev[i][0].record(stream)
+        ev_f[i][0].record(stream)
         fwd()
-        ev[i][1].record(stream)
+        ev_f[i][1].record(stream)
+        ev_a[i][0].record(stream)
+        adj()
+        ev_a[i][1].record(stream)
     stop.record(stream)
     torch.cuda.synchronize()
     wall = time.perf_counter() - wall0
     ms_step = start.elapsed_time(stop) / args.steps
-    fwd_ms = sum(a.elapsed_time(b) for a, b in ev) / args.steps
+    fwd_ms = sum(a.elapsed_time(b) for a, b in ev_f) / args.steps
+    adj_ms = sum(a.elapsed_time(b) for a, b in ev_a) / args.steps
+
+    # the plain per-diagram kernel (double tables) on the same launch, outside the timed region
+    terms.set_variant(1)
+    for _ in range(2):
+        fwd()
+    torch.cuda.synchronize()
+    p0 = torch.cuda.Event(enable_timing=True)
+    p1 = torch.cuda.Event(enable_timing=True)
+    n_plain = max(5, args.steps // 2)
+    p0.record(stream)
+    for _ in range(n_plain):
+        fwd()
+    p1.record(stream)
+    torch.cuda.synchronize()
+    plain_ms = p0.elapsed_time(p1) / n_plain
+    plain_variant = amd.last_variant()
+    terms.set_variant(0)
 
     te = float(info["T"]) * n_e * n_f
     value = te / (ms_step * 1e-3)
     fl = rl.forward_flops(st, n_e, n_f, d.alpha)
-    achieved = fl["total"] / (fwd_ms * 1e-3)
-    bytes_fwd = rl.forward_bytes(n_e, n_f, 2 * d.n_int, True)
+    fa = rl.adjoint_flops(st, n_e, n_f, d.alpha)
+    if adj_ms >= fwd_ms:
+        dom, dom_ms, dom_fl = "ami_adj_packed (+ its reduction kernel)", adj_ms, fa["total"]
+    else:
+        dom, dom_ms, dom_fl = "ami_fwd_packed (+ its row-sum kernel)", fwd_ms, fl["total"]
+    achieved = dom_fl / (dom_ms * 1e-3)
 
     res = {
         "metric": METRIC,
@@ -163,13 +213,22 @@ def main():
         "data": "synthetic",
         "config": {
             "workload": f"order-{args.order} Hubbard self-energy (seeded topology {args.diagram}), "
-                        f"{n_e} k-samples, beta={args.beta}, 1 Matsubara frequency, energies from "
-                        "momenta in-kernel, out[N_F,N_E] + row sum",
+                        f"{n_e} k-samples, beta={args.beta}, 1 Matsubara frequency; step = forward "
+                        "(out[N_F,N_E] + row sum, energies from momenta in-kernel) + adjoint "
+                        "(d/dk, d/dmu, d/dt, d/dbeta, d/dw of the summed integrand)",
             "order": args.order, "terms": info["T"], "distinct_leaves": info["L"],
             "distinct_denominators": info["D"], "groups": info["G"], "n_e": n_e, "n_f": n_f,
             "beta": args.beta, "t": hop_t, "mu": mu, "q": [float(x) for x in q],
             "diagram_seed": [0, args.order, args.diagram],
         },
+        "fwd": {"ms": fwd_ms, "term_evals_per_s": te / (fwd_ms * 1e-3), "kernel": fwd_variant,
+                "flops": fl["total"], "tflops": fl["total"] / (fwd_ms * 1e-3) / 1e12},
+        "fwd_adjoint": {"ms": fwd_ms + adj_ms, "adjoint_ms": adj_ms,
+                        "term_evals_per_s": te / ((fwd_ms + adj_ms) * 1e-3),
+                        "adjoint_flops": fa["total"],
+                        "adjoint_tflops": fa["total"] / (adj_ms * 1e-3) / 1e12},
+        "plain_kernel": {"ms": plain_ms, "term_evals_per_s": te / (plain_ms * 1e-3),
+                         "kernel": plain_variant, "speedup_of_fwd": plain_ms / fwd_ms},
         "roofline": {
             "bound": "alu",
             "achieved": achieved / 1e12,
@@ -177,12 +236,9 @@ def main():
             "unit": "TFLOP/s",
             "frac": achieved / rl.PEAK_FP64_VECTOR,
             "traffic": None,
-            "kernel": "ami_fwd_kernel<8,true> (+ row-sum kernel in the same interval)",
-            "flops_per_launch": fl["total"],
-            "flops_per_sample": fl["per_sample"],
-            "flops_per_point": fl["per_point"],
-            "kernel_ms": fwd_ms,
-            "hbm_gbps_compulsory": bytes_fwd / (fwd_ms * 1e-3) / 1e9,
+            "kernel": dom,
+            "flops_per_launch": dom_fl,
+            "kernel_ms": dom_ms,
         },
         "construct_ms": construct_ms,
         "wall_s": wall,

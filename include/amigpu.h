@@ -157,6 +157,56 @@ AmiStatus amiEvaluateHubbard(AmiTerms *terms,
                              double beta, double e_reg,
                              double *out, double *out_sum, void *hip_stream);
 
+/*
+ * amiEvaluateAdjoint -- reverse-mode derivatives of the batched evaluation.
+ * For the real objective L = Re sum_{f,s} conj(c[f][s]) out[f][s] with the
+ * cotangent c[f][s] = grad_out[f][s] + grad_sum[f] (either may be NULL, not
+ * both; grad_sum is the cotangent of out_sum), it returns
+ *   grad_energies [n_e][n_eps] row-major: dL/dE (device, or NULL)
+ *   grad_beta     [1]: dL/dbeta at fixed frequency values (device, or NULL)
+ *   grad_freqs    complex [n_f][n_ext]: conj(dL/dw) summed over samples, the
+ *                 gradient of a real loss with respect to a complex input
+ *                 (d/dRe w + i d/dIm w) (device, or NULL)
+ * using d f_sigma/dy = -f_sigma (1 - f_sigma) for every leaf and
+ * d(1/D)/dD = -1/D^2 for every denominator (the terms of Eq. (6) are products
+ * of these).  Other arguments as amiEvaluate.  The sums over samples are
+ * reduced in a fixed order.  Needs the packed form of the solution (every
+ * energy coefficient +-1, at most 255 distinct leaves and denominators, at most
+ * 8 of each per term): AMI_E_UNSUPPORTED otherwise.
+ */
+AmiStatus amiEvaluateAdjoint(AmiTerms *terms,
+                             const double *energies, int64_t n_e, int64_t stride_s, int64_t stride_i,
+                             const double *ext_freqs, int64_t n_f, double beta, double e_reg,
+                             const double *grad_out, const double *grad_sum,
+                             double *grad_energies, double *grad_beta, double *grad_freqs,
+                             void *hip_stream);
+
+/*
+ * amiEvaluateHubbardAdjoint -- the adjoint of amiEvaluateHubbard: as
+ * amiEvaluateAdjoint, with the energies' cotangent carried to the momenta
+ * through dE_j/dK_jc = -2t sin K_jc and K_j = sum_l alpha_jl k_l (Sec. 5.2):
+ *   grad_k  [n_e][2*n_int] row-major, dL/dk (device, or NULL)
+ *   grad_mu, grad_t  [1] each: dL/dmu, dL/dt summed over samples (device, or NULL)
+ */
+AmiStatus amiEvaluateHubbardAdjoint(AmiTerms *terms,
+                                    const double *k, int64_t n_e, int64_t stride_k,
+                                    const double *q, double t, double mu,
+                                    const double *ext_freqs, int64_t n_f,
+                                    double beta, double e_reg,
+                                    const double *grad_out, const double *grad_sum,
+                                    double *grad_k, double *grad_mu, double *grad_t,
+                                    double *grad_beta, double *grad_freqs, void *hip_stream);
+
+/*
+ * amiSetVariant -- choose the forward kernel of a handle: 0 (default) the
+ * packed evaluator whenever the solution has the packed form, 1 the plain
+ * double-table evaluator (any coefficients; used as the per-diagram baseline).
+ */
+AmiStatus amiSetVariant(AmiTerms *terms, int32_t variant);
+
+/* Name of the kernel variant launched by the last evaluate call on this thread. */
+const char *amiLastVariant(void);
+
 /* Message of the last failed call on this thread ("" if none). */
 const char *amiLastError(void);
 

@@ -189,18 +189,21 @@ def energies_from_k(alpha, k_int, q, t=1.0, mu=0.0, dim: int = 2, dtype=LD):
 # Gradients
 # ---------------------------------------------------------------------------
 
-def gradients(terms, n_int: int, energies, ext_freqs, beta, cot, e_reg=0.0):
+def gradients(terms, n_int: int, energies, ext_freqs, beta, cot, e_reg=0.0,
+              per_sample=False):
     """Derivatives of ``L = Re sum_{f,s} conj(cot[f,s]) * I[f,s]``.
 
     For one term ``v = s prod_l f_l prod_r 1/D_r`` with ``y_l = beta x_l``:
-    ``d ln f_sigma / dy = -(1 - f_sigma(y))``, ``d ln(1/D) / dD = -1/D``, so
+    ``d ln f_sigma / dy = -(1 - f_sigma(y)) = -f_sigma(-y)``, ``d ln(1/D) / dD = -1/D``, so
 
     * ``dv/dE_i  = v * [ -beta sum_l e_li (1 - f_l) - sum_r e_ri / D_r ]``
     * ``dv/dbeta = v * [ -sum_l x_l (1 - f_l) ]`` at fixed frequency values
     * ``dv/dw_j  = v * [ -sum_r a_rj / D_r ]`` (holomorphic in ``w``).
 
     Returns ``(dE [N_E, nE] real, dbeta real, dw [N_F, n_ext] complex)``, the
-    complex one in the convention ``conj(dI/dw) * cot`` summed over samples.
+    complex one in the convention ``conj(dI/dw) * cot`` summed over samples;
+    with ``per_sample`` the last two are not summed: ``dbeta [N_E]``,
+    ``dw [N_F, N_E, n_ext]``.
     """
     E = np.asarray(energies).astype(LD)
     w = np.asarray(ext_freqs)
@@ -213,8 +216,8 @@ def gradients(terms, n_int: int, energies, ext_freqs, beta, cot, e_reg=0.0):
     n_e, n_eps = E.shape
     n_f, n_ext = w.shape
     dE = np.zeros((n_e, n_eps), dtype=LD)
-    dbeta = LD(0)
-    dw = np.zeros((n_f, n_ext), dtype=CLD)
+    dbeta = np.zeros(n_e, dtype=LD)
+    dw = np.zeros((n_f, n_e, n_ext), dtype=CLD)
     for s, leaves, dens in terms:
         ft = np.full(n_e, LD(s), dtype=LD)
         dlnft_dE = np.zeros((n_e, n_eps), dtype=LD)
@@ -226,7 +229,9 @@ def gradients(terms, n_int: int, energies, ext_freqs, beta, cot, e_reg=0.0):
                 x = x + e_reg
             f = leaf_value(sigma, beta * x)
             ft = ft * f
-            one_minus = 1 - f
+            # 1 - f_sigma(y) = f_sigma(-y) for both statistics; written this way
+            # it keeps full relative precision where f saturates at 1
+            one_minus = leaf_value(sigma, -beta * x)
             dlnft_dE -= beta * one_minus[:, None] * ev[None, :]
             dlnft_db -= x * one_minus
         for fi in range(n_f):
@@ -249,17 +254,20 @@ def gradients(terms, n_int: int, energies, ext_freqs, beta, cot, e_reg=0.0):
             gf = g[fi]
             dv_dE = v[:, None] * (dlnft_dE + dlnr_dE)
             dE += np.real(np.conj(gf)[:, None] * dv_dE)
-            dbeta += np.sum(np.real(np.conj(gf) * v * dlnft_db))
+            dbeta += np.real(np.conj(gf) * v * dlnft_db)
             dv_dw = v[:, None] * dlnr_dw
-            dw[fi] += np.sum(gf[:, None] * np.conj(dv_dw), axis=0)
-    return dE, dbeta, dw
+            dw[fi] += gf[:, None] * np.conj(dv_dw)
+    if per_sample:
+        return dE, dbeta, dw
+    return dE, np.sum(dbeta), np.sum(dw, axis=1)
 
 
 def momentum_gradients(alpha, k_int, q, t, mu, dE, dim: int = 2):
     """Chain rule through :func:`energies_from_k`:
     ``dE_j/dK_jc = -2t sin K_jc``, ``K = k A^T``, ``dE_j/dmu = 1``.
 
-    Returns ``(dk [N_E, d*n_int], dmu)``.
+    Returns ``(dk [N_E, d*n_int], dmu, dt)`` with ``dE_j/dt = 2(cos K_jx + cos K_jy)``
+    for the 2D dispersion.
     """
     K = line_momenta(alpha, k_int, q, dim, LD)
     ng = np.asarray(alpha).shape[0]
@@ -271,4 +279,7 @@ def momentum_gradients(alpha, k_int, q, t, mu, dE, dim: int = 2):
     A = kron_alpha(alpha, dim).astype(LD)
     dk_full = dK @ A
     n_k = np.asarray(k_int).shape[1]
-    return dk_full[:, :n_k], np.sum(np.asarray(dE, dtype=LD))
+    dt = LD(0)
+    for i in range(ng):
+        dt += np.sum(np.asarray(dE, dtype=LD)[:, i] * 2 * np.cos(K[:, i * dim:(i + 1) * dim]).sum(axis=1))
+    return dk_full[:, :n_k], np.sum(np.asarray(dE, dtype=LD)), dt

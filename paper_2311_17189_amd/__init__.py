@@ -7,10 +7,13 @@ C++ host code; every evaluation step runs in its HIP kernels.  PyTorch is used
 only to hold device memory and to name the stream.
 
 The library must have been built (``paper_2311_17189_amd.build.build()`` or
-``__graft_entry__.build()``); importing this package without it raises.
+``__graft_entry__.build()``); the first call into it raises ImportError
+otherwise (there is no fallback path).
 """
-from ._lib import (AmiError, Terms, evaluate, evaluate_hubbard, lib_path,  # noqa: F401
-                   load_library, version)
+from ._lib import (AmiError, Terms, evaluate, evaluate_adjoint,  # noqa: F401
+                   evaluate_hubbard, evaluate_hubbard_adjoint, last_variant,
+                   lib_path, load_library, version)
 
-__all__ = ["AmiError", "Terms", "evaluate", "evaluate_hubbard", "lib_path",
-           "load_library", "version"]
+__all__ = ["AmiError", "Terms", "evaluate", "evaluate_adjoint", "evaluate_hubbard",
+           "evaluate_hubbard_adjoint", "last_variant", "lib_path", "load_library",
+           "version"]

@@ -65,6 +65,16 @@ def load_library():
     lib.amiEvaluateHubbard.argtypes = [vp, vp, c_i64, c_i64, vp, c_dbl, c_dbl, vp, c_i64, c_dbl,
                                        c_dbl, vp, vp, vp]
     lib.amiEvaluateHubbard.restype = c_i32
+    lib.amiEvaluateAdjoint.argtypes = [vp, vp, c_i64, c_i64, c_i64, vp, c_i64, c_dbl, c_dbl, vp, vp,
+                                       vp, vp, vp, vp]
+    lib.amiEvaluateAdjoint.restype = c_i32
+    lib.amiEvaluateHubbardAdjoint.argtypes = [vp, vp, c_i64, c_i64, vp, c_dbl, c_dbl, vp, c_i64, c_dbl,
+                                              c_dbl, vp, vp, vp, vp, vp, vp, vp, vp]
+    lib.amiEvaluateHubbardAdjoint.restype = c_i32
+    lib.amiSetVariant.argtypes = [vp, c_i32]
+    lib.amiSetVariant.restype = c_i32
+    lib.amiLastVariant.argtypes = []
+    lib.amiLastVariant.restype = ctypes.c_char_p
     lib.amiLastError.argtypes = []
     lib.amiLastError.restype = ctypes.c_char_p
     lib.amiVersion.argtypes = []
@@ -81,6 +91,11 @@ def _check(code: int):
 
 def version() -> str:
     return load_library().amiVersion().decode()
+
+
+def last_variant() -> str:
+    """Kernel variant launched by the last evaluate call on this thread."""
+    return load_library().amiLastVariant().decode()
 
 
 class Terms:
@@ -137,6 +152,10 @@ class Terms:
 
     def upload(self):
         _check(load_library().amiTermsUpload(self._h))
+
+    def set_variant(self, variant: int):
+        """0: packed kernels when possible (default); 1: the plain double-table kernel."""
+        _check(load_library().amiSetVariant(self._h, int(variant)))
 
     def close(self):
         if getattr(self, "_h", None) is not None and self._h.value:
@@ -234,3 +253,71 @@ def evaluate_hubbard(terms: Terms, k, q: Sequence[float], t: float, mu: float, e
         _stream_ptr(stream))
     _check(code)
     return out, out_sum
+
+
+def _ptr(t):
+    return t.data_ptr() if t is not None else None
+
+
+def _cot(grad_out, grad_sum, n_f, n_e, device):
+    import torch
+    if grad_out is not None:
+        if (grad_out.dtype != torch.complex128 or tuple(grad_out.shape) != (n_f, n_e)
+                or grad_out.device != device):
+            raise AmiError(-1, f"grad_out must be complex128 [{n_f}, {n_e}] on {device}")
+        grad_out = grad_out.contiguous()
+    if grad_sum is not None:
+        if grad_sum.dtype != torch.complex128 or tuple(grad_sum.shape) != (n_f,) or grad_sum.device != device:
+            raise AmiError(-1, f"grad_sum must be complex128 [{n_f}] on {device}")
+        grad_sum = grad_sum.contiguous()
+    if grad_out is None and grad_sum is None:
+        raise AmiError(-1, "grad_out and grad_sum are both None")
+    return grad_out, grad_sum
+
+
+def evaluate_adjoint(terms: Terms, energies, ext_freqs, beta: float, e_reg: float = 0.0,
+                     grad_out=None, grad_sum=None, stream=None):
+    """``amiEvaluateAdjoint``: returns ``(grad_energies [N_E, nE], grad_beta [],
+    grad_freqs [N_F, n_ext])`` for the cotangents of ``out`` / ``out_sum``."""
+    import torch
+    if energies.dtype != torch.float64 or not energies.is_cuda or energies.dim() != 2:
+        raise AmiError(-1, "energies must be a 2-D float64 CUDA tensor")
+    w = _freqs(ext_freqs, terms)
+    n_e, n_f = energies.shape[0], w.shape[0]
+    dev = energies.device
+    go, gs = _cot(grad_out, grad_sum, n_f, n_e, dev)
+    g_e = torch.empty((n_e, terms.n_eps), dtype=torch.float64, device=dev)
+    g_b = torch.empty((), dtype=torch.float64, device=dev)
+    g_w = torch.empty((n_f, w.shape[1]), dtype=torch.complex128, device=dev)
+    st_s, st_i = energies.stride()
+    _check(load_library().amiEvaluateAdjoint(
+        terms._h, energies.data_ptr() if n_e else None, n_e, max(st_s, 1), max(st_i, 1),
+        w.data_ptr(), n_f, float(beta), float(e_reg), _ptr(go), _ptr(gs),
+        g_e.data_ptr() if n_e else None, g_b.data_ptr(), g_w.data_ptr(), _stream_ptr(stream)))
+    return g_e, g_b, g_w
+
+
+def evaluate_hubbard_adjoint(terms: Terms, k, q, t: float, mu: float, ext_freqs, beta: float,
+                             e_reg: float = 0.0, grad_out=None, grad_sum=None, stream=None):
+    """``amiEvaluateHubbardAdjoint``: returns ``(grad_k [N_E, 2 n_int], grad_mu [],
+    grad_t [], grad_beta [], grad_freqs [N_F, n_ext])``."""
+    import torch
+    if k.dtype != torch.float64 or not k.is_cuda or k.dim() != 2:
+        raise AmiError(-1, "k must be a 2-D float64 CUDA tensor")
+    if k.shape[1] != 2 * terms.n_int or (k.shape[0] > 0 and k.stride(1) != 1):
+        raise AmiError(-1, "k must be [N_E, 2*n_int] with unit column stride")
+    w = _freqs(ext_freqs, terms)
+    n_e, n_f = k.shape[0], w.shape[0]
+    dev = k.device
+    go, gs = _cot(grad_out, grad_sum, n_f, n_e, dev)
+    g_k = torch.empty((n_e, 2 * terms.n_int), dtype=torch.float64, device=dev)
+    scal = torch.empty((3,), dtype=torch.float64, device=dev)
+    g_w = torch.empty((n_f, w.shape[1]), dtype=torch.complex128, device=dev)
+    qa = np.ascontiguousarray(np.asarray(q, dtype=np.float64).reshape(-1))
+    base = scal.data_ptr()
+    _check(load_library().amiEvaluateHubbardAdjoint(
+        terms._h, k.data_ptr() if n_e else None, n_e, max(k.stride(0), 2 * terms.n_int),
+        qa.ctypes.data, float(t), float(mu), w.data_ptr(), n_f, float(beta), float(e_reg),
+        _ptr(go), _ptr(gs), g_k.data_ptr() if n_e else None, base, base + 8, base + 16,
+        g_w.data_ptr(), _stream_ptr(stream)))
+    return g_k, scal[0], scal[1], scal[2], g_w

@@ -54,6 +54,12 @@ struct DeviceTables {
     const double *term_sign = nullptr;   // [T]
     const int32_t *term_leaf = nullptr;  // [T][n_int]
     const double *line_alpha = nullptr;  // [n_g][n_freq] momentum labels (Hubbard path)
+    // packed tables (device_common.hpp, PackedTabs)
+    const uint64_t *p_leaf = nullptr;
+    const uint64_t *p_den = nullptr;
+    const uint32_t *p_line = nullptr;
+    const uint64_t *p_term = nullptr;
+    const uint64_t *p_group = nullptr;
 };
 
 // Flattened, common-subexpression-eliminated evaluation tables (host).
@@ -68,6 +74,16 @@ struct Tables {
     std::vector<double> term_sign;        // [T]
     std::vector<int32_t> term_leaf;       // [T][n_int]
     std::vector<double> line_alpha;       // [n_g][n_freq]
+    // packed form: every energy coefficient +-1, indices below 256, <= 8 leaves
+    // and denominators per term, <= 16 energies and frequency slots
+    bool packable = false;
+    std::vector<uint64_t> p_leaf;         // [L]
+    std::vector<uint64_t> p_den;          // [D]
+    std::vector<uint32_t> p_line;         // [n_g]
+    std::vector<uint64_t> p_term;         // [T]
+    std::vector<uint64_t> p_group;        // [G]
+    uint32_t fermi_used = 0;
+    bool use_products = false;
 };
 
 }  // namespace ami
@@ -75,6 +91,7 @@ struct Tables {
 struct AmiTerms {
     int n_g = 0, n_eps = 0, n_freq = 0, n_int = 0, n_ext = 0;
     uint32_t flags = 0;
+    int variant = 0;                         // 0 packed kernels when possible, 1 double-table kernel
     std::vector<int8_t> alpha, eps;
     std::vector<uint8_t> fermionic;
     int64_t raw_terms = 0;

@@ -387,6 +387,8 @@ void serialize(const AmiTerms *t, const std::vector<FlatTerm> &terms, std::vecto
 
 }  // namespace
 
+void pack_tables(AmiTerms *t);
+
 // Flatten canonical terms: distinct leaves, distinct denominators (energy part
 // and external-frequency part), groups of terms with equal denominators.
 AmiStatus build_tables(AmiTerms *t) {
@@ -460,8 +462,84 @@ AmiStatus build_tables(AmiTerms *t) {
     tab.T = static_cast<int>(tab.term_sign.size());
     for (int j = 0; j < t->n_g; ++j)
         for (int l = 0; l < nf; ++l) tab.line_alpha.push_back(static_cast<double>(t->alpha[j * nf + l]));
+    pack_tables(t);
     (void)nx;
     return AMI_OK;
+}
+
+// Packed tables for the specialized kernels: +-1 coefficients as bit masks,
+// indices as bytes.  Left empty (packable = false) when the solution falls
+// outside that form; the double tables above always exist.
+void pack_tables(AmiTerms *t) {
+    Tables &tab = t->tab;
+    const int ne = t->n_eps, nf = t->n_freq, ni = t->n_int, nx = t->n_ext;
+    tab.packable = false;
+    tab.p_leaf.clear();
+    tab.p_den.clear();
+    tab.p_line.clear();
+    tab.p_term.clear();
+    tab.p_group.clear();
+    tab.fermi_used = 0;
+    tab.use_products = false;
+    if (ne > 16 || nf > 16 || ni > 8 || tab.dpt > 8 || nx > 4 || tab.L > 255 || tab.D > 255) return;
+    auto masks = [&](const double *c, int n, uint64_t &out) -> bool {
+        uint32_t pos = 0, neg = 0;
+        for (int i = 0; i < n; ++i) {
+            if (c[i] == 1.0) pos |= 1u << i;
+            else if (c[i] == -1.0) neg |= 1u << i;
+            else if (c[i] != 0.0) return false;
+        }
+        out = static_cast<uint64_t>(pos) | (static_cast<uint64_t>(neg) << 16);
+        return true;
+    };
+    int n_fermi = 0;
+    for (int l = 0; l < tab.L; ++l) {
+        uint64_t w = 0;
+        if (!masks(&tab.leaf_coef[static_cast<size_t>(l) * ne], ne, w)) return;
+        if (tab.leaf_sigma[l] < 0) {
+            w |= 1ull << 32;
+        } else {
+            ++n_fermi;
+            tab.fermi_used |= static_cast<uint32_t>((w & 0xffff) | ((w >> 16) & 0xffff));
+        }
+        tab.p_leaf.push_back(w);
+    }
+    const int nc = ne + nx;
+    for (int r = 0; r < tab.D; ++r) {
+        uint64_t w = 0;
+        if (!masks(&tab.den_coef[static_cast<size_t>(r) * nc], ne, w)) return;
+        for (int x = 0; x < nx; ++x) {
+            const double a = tab.den_coef[static_cast<size_t>(r) * nc + ne + x];
+            if (a < -127.0 || a > 127.0) return;
+            const uint8_t b = static_cast<uint8_t>(static_cast<int8_t>(a));
+            w |= static_cast<uint64_t>(b) << (32 + 8 * x);
+        }
+        tab.p_den.push_back(w);
+    }
+    for (int j = 0; j < t->n_g; ++j) {
+        uint64_t w = 0;
+        if (!masks(&tab.line_alpha[static_cast<size_t>(j) * nf], nf, w)) return;
+        tab.p_line.push_back(static_cast<uint32_t>(w));
+    }
+    for (int ti = 0; ti < tab.T; ++ti) {
+        uint64_t w = 0;
+        for (int j = 0; j < ni; ++j) {
+            const int32_t lj = tab.term_leaf[static_cast<size_t>(ti) * ni + j];
+            for (int k = 0; k < j; ++k)   // the adjoint updates a term's leaves together
+                if (tab.term_leaf[static_cast<size_t>(ti) * ni + k] == lj) return;
+            w |= static_cast<uint64_t>(lj) << (8 * j);
+        }
+        tab.p_term.push_back(w);
+    }
+    for (int g = 0; g < tab.G; ++g) {
+        uint64_t w = 0;
+        for (int k = 0; k < tab.dpt; ++k)
+            w |= static_cast<uint64_t>(tab.group_dens[static_cast<size_t>(g) * tab.dpt + k]) << (8 * k);
+        tab.p_group.push_back(w);
+    }
+    // products of exp(beta E_i) pay off when Fermi leaves outnumber the energies they use
+    tab.use_products = n_fermi > __builtin_popcount(tab.fermi_used);
+    tab.packable = true;
 }
 
 }  // namespace ami

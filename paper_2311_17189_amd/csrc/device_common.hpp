@@ -1,0 +1,182 @@
+// Device-side building blocks shared by the forward and adjoint evaluators.
+//
+// Tables are read through the constant address space so that wave-uniform
+// reads become scalar loads, and the +-1 coefficient masks are tested with
+// scalar bit tests: only the non-zero coefficients cost vector instructions.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+namespace ami {
+
+typedef const __attribute__((address_space(4))) uint64_t *cu64;
+typedef const __attribute__((address_space(4))) uint32_t *cu32;
+typedef const __attribute__((address_space(4))) double *cdbl;
+typedef const __attribute__((address_space(4))) int32_t *ci32;
+
+constexpr int kMaxExtDev = 4;
+
+// Packed evaluation tables (built by the host, see construct.cpp):
+//   leaf[l]  bits 0-15 energies with coefficient +1, bits 16-31 with -1,
+//            bit 32 set for a Bose-type leaf (sigma = -1)
+//   den[r]   bits 0-15 / 16-31 energy masks as above, bits 32-63 the external
+//            frequency coefficients as four int8
+//   line[j]  bits 0-15 / 16-31 frequency/momentum slots with coefficient +1/-1
+//   term[t]  leaf indices of term t, one byte each; term_sign[t] its prefactor
+//   group[g] denominator indices of group g, one byte each;
+//            terms of group g are group_start[g] .. group_start[g+1]-1
+struct PackedTabs {
+    const uint64_t *leaf;
+    const uint64_t *den;
+    const uint32_t *line;
+    const uint64_t *term;
+    const double *term_sign;
+    const int32_t *group_start;
+    const uint64_t *group;
+    int L, D, G, T;
+    int n_eps, n_int, n_ext, n_freq, n_g, dpt;
+    uint32_t fermi_used;    // energies that appear in Fermi-type leaves
+    int use_products;       // Fermi leaves from products of exp(beta E_i)
+};
+
+// ---- elementary functions -------------------------------------------------
+
+// Reciprocal: hardware estimate refined by two Newton steps (finite, non-zero,
+// normal-range arguments).
+__device__ __forceinline__ double rcp_nr(double d) {
+    double r = __builtin_amdgcn_rcp(d);
+    double e = fma(-d, r, 1.0);
+    r = fma(r, e, r);
+    e = fma(-d, r, 1.0);
+    return fma(r, e, r);
+}
+
+// sin and cos: x = k pi/2 + r with pi/2 split into three parts (33, 33 and 53
+// significant bits, so k * part is exact for |k| < 2^20), |r| <= pi/4, and the
+// Taylor series of sin (to r^17) and cos (to r^18), whose truncation errors at
+// pi/4 are below 1e-19.  Valid for |x| < 1e5; callers route larger arguments
+// to the device library.
+__device__ __forceinline__ void sincos_red(double x, double &s, double &c) {
+    constexpr double kTwoOverPi = 0x1.45f306dc9c883p-1;
+    constexpr double kPio2Hi = 0x1.921fb54400000p+0;
+    constexpr double kPio2Mid = 0x1.0b4611a600000p-34;
+    constexpr double kPio2Lo = 0x1.3198a2e037073p-69;
+    const double kf = __builtin_rint(x * kTwoOverPi);
+    double r = fma(-kf, kPio2Hi, x);
+    r = fma(-kf, kPio2Mid, r);
+    r = fma(-kf, kPio2Lo, r);
+    const double z = r * r;
+    double ps = 1.0 / 355687428096000.0;          // 1/17!
+    ps = fma(ps, z, -1.0 / 1307674368000.0);      // 1/15!
+    ps = fma(ps, z, 1.0 / 6227020800.0);          // 1/13!
+    ps = fma(ps, z, -1.0 / 39916800.0);           // 1/11!
+    ps = fma(ps, z, 1.0 / 362880.0);              // 1/9!
+    ps = fma(ps, z, -1.0 / 5040.0);               // 1/7!
+    ps = fma(ps, z, 1.0 / 120.0);                 // 1/5!
+    ps = fma(ps, z, -1.0 / 6.0);                  // 1/3!
+    const double sr = fma(r * z, ps, r);
+    double pc = -1.0 / 6402373705728000.0;        // 1/18!
+    pc = fma(pc, z, 1.0 / 20922789888000.0);      // 1/16!
+    pc = fma(pc, z, -1.0 / 87178291200.0);        // 1/14!
+    pc = fma(pc, z, 1.0 / 479001600.0);           // 1/12!
+    pc = fma(pc, z, -1.0 / 3628800.0);            // 1/10!
+    pc = fma(pc, z, 1.0 / 40320.0);               // 1/8!
+    pc = fma(pc, z, -1.0 / 720.0);                // 1/6!
+    pc = fma(pc, z, 1.0 / 24.0);                  // 1/4!
+    pc = fma(pc, z, -0.5);                        // 1/2!
+    const double cr = fma(z, pc, 1.0);
+    const int q = static_cast<int>(kf) & 3;
+    const double ss = (q & 1) ? cr : sr;
+    const double cc = (q & 1) ? sr : cr;
+    s = (q & 2) ? -ss : ss;
+    c = ((q + 1) & 2) ? -cc : cc;
+}
+
+// e^z and e^z - 1 from one reduction: z = k ln2 + r with ln2 split in two
+// (42 + 53 significant bits, so k * hi is exact for |k| < 2^11), |r| <= ln2/2,
+// and p = e^r - 1 by its Taylor series to r^13 (truncation below 2e-17 relative).
+// Then t = 2^k (1 + p) and m = 2^k p + (2^k - 1); the last form has no
+// cancellation for any k (2^k - 1 is exact), so m keeps full relative precision
+// near z = 0 and t near its underflow.  For |z| < 708.
+__device__ __forceinline__ void exp_split(double z, double &t, double &m) {
+    constexpr double kLog2e = 0x1.71547652b82fep+0;
+    constexpr double kLn2Hi = 0x1.62e42fefa3800p-1;
+    constexpr double kLn2Lo = 0x1.ef35793c76730p-45;
+    const double kf = __builtin_rint(z * kLog2e);
+    double r = fma(-kf, kLn2Hi, z);
+    r = fma(-kf, kLn2Lo, r);
+    double q = 1.0 / 6227020800.0;               // 1/13!
+    q = fma(q, r, 1.0 / 479001600.0);            // 1/12!
+    q = fma(q, r, 1.0 / 39916800.0);             // 1/11!
+    q = fma(q, r, 1.0 / 3628800.0);              // 1/10!
+    q = fma(q, r, 1.0 / 362880.0);               // 1/9!
+    q = fma(q, r, 1.0 / 40320.0);                // 1/8!
+    q = fma(q, r, 1.0 / 5040.0);                 // 1/7!
+    q = fma(q, r, 1.0 / 720.0);                  // 1/6!
+    q = fma(q, r, 1.0 / 120.0);                  // 1/5!
+    q = fma(q, r, 1.0 / 24.0);                   // 1/4!
+    q = fma(q, r, 1.0 / 6.0);                    // 1/3!
+    q = fma(q, r, 0.5);                          // 1/2!
+    const double p = fma(r * r, q, r);
+    const double s = __builtin_ldexp(1.0, static_cast<int>(kf));
+    t = fma(s, p, s);
+    m = fma(s, p, s - 1.0);
+}
+
+// A leaf f_sigma(y) = 1/(sigma e^y + 1) and its mirror f_sigma(-y) = 1 - f_sigma(y),
+// without overflow and with full relative precision everywhere: with
+// t = e^-|y| and m = e^-|y| - 1 (exp_split),
+//   Fermi  (sigma = +1): the two values are t/(1+t) and 1/(1+t)
+//   Bose-type (-1):      the two values are t/m and -1/m
+// (the first of each pair is f at y > 0).  Arguments are clamped at 700 (the
+// leaves there are below 1e-304).
+__device__ __forceinline__ void leaf_pair(bool bose, double y, double &f, double &fm) {
+    double t, m;
+    exp_split(-fmin(fabs(y), 700.0), t, m);
+    const double r = rcp_nr(bose ? m : 1.0 + t);
+    const double small = t * r;            // value on the decaying side
+    const double large = bose ? -r : r;    // value on the other side
+    f = y > 0.0 ? small : large;
+    fm = y > 0.0 ? large : small;
+}
+
+// f_sigma'(y) = -f_sigma(y) f_sigma(-y) in closed form: -t/(1+t)^2 (Fermi) and
+// t/m^2 (Bose-type).
+__device__ __forceinline__ double leaf_deriv(bool bose, double y) {
+    double t, m;
+    exp_split(-fmin(fabs(y), 700.0), t, m);
+    const double r = rcp_nr(bose ? m : 1.0 + t);
+    return bose ? t * r * r : -t * r * r;
+}
+
+// sum_i (+-1) E_i over the bits of two 16-bit masks (scalar bit tests).
+template <int NE>
+__device__ __forceinline__ double combo(uint32_t pos, uint32_t neg, const double (&E)[NE]) {
+    double x = 0.0;
+#pragma unroll
+    for (int i = 0; i < NE; ++i) {
+        if (pos & (1u << i)) x += E[i];
+        else if (neg & (1u << i)) x -= E[i];
+    }
+    return x;
+}
+
+// Scatter a value into per-energy accumulators with the mask signs.
+template <int NE>
+__device__ __forceinline__ void combo_adj(uint32_t pos, uint32_t neg, double v, double (&g)[NE]) {
+#pragma unroll
+    for (int i = 0; i < NE; ++i) {
+        if (pos & (1u << i)) g[i] += v;
+        else if (neg & (1u << i)) g[i] -= v;
+    }
+}
+
+__device__ __forceinline__ double wave_sum(double v) {
+#pragma unroll
+    for (int off = 32; off >= 1; off >>= 1) v += __shfl_xor(v, off, 64);
+    return v;
+}
+
+}  // namespace ami

@@ -1,21 +1,14 @@
-// Batched evaluation of the AMI solution on gfx950 (Burke & LeBlanc,
-// arXiv 2311.17189, Sec. 2.3): for N_E energy rows and N_F external-frequency
-// rows, out[f][s] = sum_t A_t * FT_t(E_s) * R_t(E_s, w_f)  (Eq. (6)).
+// Runtime side of the evaluators: table upload, launch shapes, kernel
+// dispatch, deterministic reductions, and the evaluate entry points of the C
+// ABI (include/amigpu.h).
 //
-// Mapping: one lane per energy sample, 64-lane wavefronts, blocks of 64..256
-// lanes.  Per sample the kernel
-//   1. loads the energies (or momenta, computing E_j = 2t(cos Kx + cos Ky) + mu
-//      with K_j = sum_l alpha_jl k_l, Sec. 5.2) into registers;
-//   2. evaluates every distinct Fermi/Bose leaf once into LDS (column per lane);
-//   3. sums the Fermi-tree products of each group of terms that share their
-//      denominators: FT_g = sum_{t in g} s_t prod_leaves; FT_g does not depend
-//      on the external frequency (Sec. 2.2, Sec. 2.3) and is kept in LDS;
-//   4. per frequency row: distinct denominators -> complex reciprocals in LDS,
-//      R_g = product over the group's denominators, out = sum_g FT_g * R_g.
-// Integer coefficient tables are read with wave-uniform addresses (scalar
-// loads); the only per-lane memory traffic is the sample input and the output.
-// Row sums (Monte-Carlo averages of Sec. 2.3) are reduced per block with a
-// fixed shuffle tree and then across blocks in a fixed order (deterministic).
+// The evaluation (Burke & LeBlanc, arXiv 2311.17189, Sec. 2.3) maps one lane
+// to one energy sample; the kernels are in kernels_packed.hpp (bit-mask tables,
+// specialized per self-energy shape, forward and adjoint) and kernel_generic.hpp
+// (double tables, forward only, any coefficients).  Sums over samples (the
+// Monte-Carlo row sums of Sec. 2.3 and the reductions of the adjoint) are done
+// per block with a fixed shuffle tree and then across blocks in a fixed order,
+// so repeated calls are bitwise identical.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -24,6 +17,9 @@
 #include <string>
 
 #include "ami_internal.hpp"
+#include "device_common.hpp"
+#include "kernel_generic.hpp"
+#include "kernels_packed.hpp"
 
 namespace ami {
 
@@ -33,229 +29,47 @@ inline AmiStatus hip_fail(hipError_t e, const char *what) {
     return fail(AMI_E_HIP, std::string(what) + ": " + hipGetErrorString(e));
 }
 
-struct FwdParams {
-    // tables
-    const double *leaf_coef;
-    const double *leaf_sigma;
-    const double *den_coef;
-    const int32_t *group_dens;
-    const int32_t *group_start;
-    const double *term_sign;
-    const int32_t *term_leaf;
-    const double *line_alpha;
-    int n_eps, n_ext, n_int, n_g, n_freq;
-    int L, D, G, dpt;
-    int region_a;            // LDS slots (per lane) before the FT region: max(L, 2D)
-    // energy input
-    const double *energies;
-    int64_t stride_s, stride_i;
-    // momentum input
-    const double *k;
-    int64_t stride_k;
-    double q[2 * kMaxExt];
-    double hop_t, mu;
-    // frequencies, parameters, outputs
-    const double *ext_freqs;
-    int n_f;
-    double beta, e_reg;
-    int64_t n_e;
-    double *out;
-    double *partial;          // [gridDim.x][n_f][2] or NULL
-};
-
-// f_sigma(y) = 1/(sigma e^y + 1).  The Bose-type form -1/expm1(y) keeps full
-// relative precision next to its removable pole at y = 0.
-__device__ __forceinline__ double leaf_fn(double sigma, double y) {
-    if (sigma > 0.0) return 1.0 / (1.0 + exp(y));
-    return -1.0 / expm1(y);
-}
-
-template <int MAXE, bool HUB>
-__global__ __launch_bounds__(256) void ami_fwd_kernel(FwdParams p) {
-    extern __shared__ double sm[];
+// out[j] = sum over b of partial[b * ncols + j], b in increasing order per thread
+// then a fixed tree over the block.  One block per column.
+__global__ __launch_bounds__(256) void ami_colsum_kernel(const double *partial, int64_t nblocks, int ncols,
+                                                         double *out) {
+    __shared__ double sh[256];
+    const int j = blockIdx.x;
     const int tid = threadIdx.x;
-    const int B = blockDim.x;
-    const int64_t s = static_cast<int64_t>(blockIdx.x) * B + tid;
-    const bool active = s < p.n_e;
-    const int64_t sc = active ? s : (p.n_e - 1);
-
-    double E[MAXE];
-#pragma unroll
-    for (int i = 0; i < MAXE; ++i) E[i] = 0.0;
-
-    if constexpr (HUB) {
-        // momenta of the summed slots in registers; external momenta are kernel arguments
-        double kx[kMaxInt], ky[kMaxInt];
-        const double *krow = p.k + sc * p.stride_k;
-#pragma unroll
-        for (int l = 0; l < kMaxInt; ++l) {
-            kx[l] = 0.0;
-            ky[l] = 0.0;
-            if (l < p.n_int) {
-                kx[l] = krow[2 * l];
-                ky[l] = krow[2 * l + 1];
-            }
-        }
-#pragma unroll
-        for (int j = 0; j < MAXE; ++j) {
-            if (j < p.n_g) {
-                // K_j = sum_l alpha_jl k_l (Sec. 5.2), E_j = -eps(K_j) = 2t(cos Kx + cos Ky) + mu
-                const double *a = p.line_alpha + j * p.n_freq;
-                double Kx = 0.0, Ky = 0.0;
-#pragma unroll
-                for (int l = 0; l < kMaxInt; ++l) {
-                    if (l < p.n_int) {
-                        Kx = fma(a[l], kx[l], Kx);
-                        Ky = fma(a[l], ky[l], Ky);
-                    }
-                }
-#pragma unroll
-                for (int x = 0; x < kMaxExt; ++x) {
-                    if (x < p.n_ext) {
-                        Kx = fma(a[p.n_int + x], p.q[2 * x], Kx);
-                        Ky = fma(a[p.n_int + x], p.q[2 * x + 1], Ky);
-                    }
-                }
-                E[j] = fma(2.0 * p.hop_t, cos(Kx) + cos(Ky), p.mu);
-            }
-        }
-    } else {
-        const double *erow = p.energies + sc * p.stride_s;
-#pragma unroll
-        for (int i = 0; i < MAXE; ++i)
-            if (i < p.n_eps) E[i] = erow[i * p.stride_i];
-    }
-
-    // 2. distinct leaves -> LDS
-    for (int l = 0; l < p.L; ++l) {
-        const double *c = p.leaf_coef + l * p.n_eps;
-        double x = 0.0;
-#pragma unroll
-        for (int i = 0; i < MAXE; ++i)
-            if (i < p.n_eps) x = fma(c[i], E[i], x);
-        const double sg = p.leaf_sigma[l];
-        if (sg < 0.0) x += p.e_reg;
-        sm[l * B + tid] = leaf_fn(sg, p.beta * x);
-    }
-
-    // 3. Fermi-tree sums per group of equal denominators -> LDS
-    double *ftcol = sm + p.region_a * B;
-    for (int g = 0; g < p.G; ++g) {
-        const int t0 = p.group_start[g], t1 = p.group_start[g + 1];
-        double ft = 0.0;
-        for (int t = t0; t < t1; ++t) {
-            double prod = p.term_sign[t];
-            const int32_t *li = p.term_leaf + t * p.n_int;
-            for (int j = 0; j < p.n_int; ++j) prod *= sm[li[j] * B + tid];
-            ft += prod;
-        }
-        ftcol[g * B + tid] = ft;
-    }
-
-    // 4. per frequency row
-    double *red = sm + (p.region_a + p.G) * B;     // 2 doubles per wave
-    const int wave = tid >> 6, lane = tid & 63, nwaves = (B + 63) >> 6;
-    const int ncoef = p.n_eps + p.n_ext;
-    for (int f = 0; f < p.n_f; ++f) {
-        double wre[kMaxExt], wim[kMaxExt];
-#pragma unroll
-        for (int x = 0; x < kMaxExt; ++x) {
-            wre[x] = 0.0;
-            wim[x] = 0.0;
-            if (x < p.n_ext) {
-                wre[x] = p.ext_freqs[2 * (f * p.n_ext + x)];
-                wim[x] = p.ext_freqs[2 * (f * p.n_ext + x) + 1];
-            }
-        }
-        for (int r = 0; r < p.D; ++r) {
-            const double *c = p.den_coef + r * ncoef;
-            double dre = 0.0, dim = 0.0;
-#pragma unroll
-            for (int i = 0; i < MAXE; ++i)
-                if (i < p.n_eps) dre = fma(c[i], E[i], dre);
-#pragma unroll
-            for (int x = 0; x < kMaxExt; ++x) {
-                if (x < p.n_ext) {
-                    dre = fma(c[p.n_eps + x], wre[x], dre);
-                    dim = fma(c[p.n_eps + x], wim[x], dim);
-                }
-            }
-            const double inv = 1.0 / fma(dre, dre, dim * dim);
-            sm[(2 * r) * B + tid] = dre * inv;
-            sm[(2 * r + 1) * B + tid] = -dim * inv;
-        }
-        double acc_re = 0.0, acc_im = 0.0;
-        for (int g = 0; g < p.G; ++g) {
-            double rr = 1.0, ri = 0.0;
-            const int32_t *gd = p.group_dens + g * p.dpt;
-            for (int k = 0; k < p.dpt; ++k) {
-                const int d = gd[k];
-                const double xr = sm[(2 * d) * B + tid], xi = sm[(2 * d + 1) * B + tid];
-                const double nr = fma(rr, xr, -ri * xi);
-                ri = fma(rr, xi, ri * xr);
-                rr = nr;
-            }
-            const double ft = ftcol[g * B + tid];
-            acc_re = fma(ft, rr, acc_re);
-            acc_im = fma(ft, ri, acc_im);
-        }
-        if (active && p.out) {
-            double2 v;
-            v.x = acc_re;
-            v.y = acc_im;
-            reinterpret_cast<double2 *>(p.out)[static_cast<int64_t>(f) * p.n_e + s] = v;
-        }
-        if (p.partial) {
-            double vr = active ? acc_re : 0.0, vi = active ? acc_im : 0.0;
-#pragma unroll
-            for (int off = 32; off >= 1; off >>= 1) {
-                vr += __shfl_xor(vr, off, 64);
-                vi += __shfl_xor(vi, off, 64);
-            }
-            if (lane == 0) {
-                red[2 * wave] = vr;
-                red[2 * wave + 1] = vi;
-            }
-            __syncthreads();
-            if (tid == 0) {
-                double sr = 0.0, si = 0.0;
-                for (int w = 0; w < nwaves; ++w) {
-                    sr += red[2 * w];
-                    si += red[2 * w + 1];
-                }
-                p.partial[(static_cast<int64_t>(blockIdx.x) * p.n_f + f) * 2] = sr;
-                p.partial[(static_cast<int64_t>(blockIdx.x) * p.n_f + f) * 2 + 1] = si;
-            }
-            __syncthreads();
-        }
-    }
-}
-
-// out_sum[f] = sum over blocks of partial[b][f], in a fixed order.
-__global__ __launch_bounds__(256) void ami_rowsum_kernel(const double *partial, int64_t nblocks, int n_f,
-                                                         double *out_sum) {
-    __shared__ double sr[256], si[256];
-    const int f = blockIdx.x;
-    const int tid = threadIdx.x;
-    double ar = 0.0, ai = 0.0;
-    for (int64_t b = tid; b < nblocks; b += 256) {
-        ar += partial[(b * n_f + f) * 2];
-        ai += partial[(b * n_f + f) * 2 + 1];
-    }
-    sr[tid] = ar;
-    si[tid] = ai;
+    double acc = 0.0;
+    for (int64_t b = tid; b < nblocks; b += 256) acc += partial[b * ncols + j];
+    sh[tid] = acc;
     __syncthreads();
     for (int w = 128; w >= 1; w >>= 1) {
-        if (tid < w) {
-            sr[tid] += sr[tid + w];
-            si[tid] += si[tid + w];
-        }
+        if (tid < w) sh[tid] += sh[tid + w];
         __syncthreads();
     }
-    if (tid == 0) {
-        out_sum[2 * f] = sr[0];
-        out_sum[2 * f + 1] = si[0];
+    if (tid == 0) out[j] = sh[0];
+}
+
+// Same reduction for the adjoint partials, routing each column to its output:
+// column 0 dL/dbeta, 1 dL/dmu, 2 dL/dt, 4.. dL/dw (complex [n_f][n_ext]).
+__global__ __launch_bounds__(256) void ami_adj_finalize_kernel(const double *partial, int64_t nblocks, int ncols,
+                                                               double *gbeta, double *gmu, double *gt,
+                                                               double *gw) {
+    __shared__ double sh[256];
+    const int j = blockIdx.x;
+    const int tid = threadIdx.x;
+    double *dst = nullptr;
+    if (j == 0) dst = gbeta;
+    else if (j == 1) dst = gmu;
+    else if (j == 2) dst = gt;
+    else if (j >= kAdjScalars && gw) dst = gw + (j - kAdjScalars);
+    if (!dst) return;
+    double acc = 0.0;
+    for (int64_t b = tid; b < nblocks; b += 256) acc += partial[b * ncols + j];
+    sh[tid] = acc;
+    __syncthreads();
+    for (int w = 128; w >= 1; w >>= 1) {
+        if (tid < w) sh[tid] += sh[tid + w];
+        __syncthreads();
     }
+    if (tid == 0) *dst = sh[0];
 }
 
 __global__ void ami_fill_kernel(double *p, int64_t n, double v) {
@@ -265,7 +79,15 @@ __global__ void ami_fill_kernel(double *p, int64_t n, double v) {
 
 size_t align256(size_t x) { return (x + 255) & ~static_cast<size_t>(255); }
 
-// Upload (once per device) the flattened tables of a handle.
+AmiStatus fill(double *p, int64_t n, hipStream_t stream) {
+    if (!p || n <= 0) return AMI_OK;
+    hipLaunchKernelGGL(ami_fill_kernel, dim3(static_cast<unsigned>((n + 255) / 256)), dim3(256), 0, stream, p, n,
+                       0.0);
+    const hipError_t e = hipGetLastError();
+    return e == hipSuccess ? AMI_OK : hip_fail(e, "fill launch");
+}
+
+// Upload (once per device) every table of a handle in one allocation.
 AmiStatus upload(AmiTerms *t, DeviceTables **out) {
     int dev = 0;
     hipError_t e = hipGetDevice(&dev);
@@ -282,7 +104,7 @@ AmiStatus upload(AmiTerms *t, DeviceTables **out) {
         size_t bytes;
         size_t off;
     };
-    Piece pieces[8] = {
+    Piece pieces[13] = {
         {tb.leaf_coef.data(), tb.leaf_coef.size() * sizeof(double), 0},
         {tb.leaf_sigma.data(), tb.leaf_sigma.size() * sizeof(double), 0},
         {tb.den_coef.data(), tb.den_coef.size() * sizeof(double), 0},
@@ -291,6 +113,11 @@ AmiStatus upload(AmiTerms *t, DeviceTables **out) {
         {tb.term_sign.data(), tb.term_sign.size() * sizeof(double), 0},
         {tb.term_leaf.data(), tb.term_leaf.size() * sizeof(int32_t), 0},
         {tb.line_alpha.data(), tb.line_alpha.size() * sizeof(double), 0},
+        {tb.p_leaf.data(), tb.p_leaf.size() * sizeof(uint64_t), 0},
+        {tb.p_den.data(), tb.p_den.size() * sizeof(uint64_t), 0},
+        {tb.p_line.data(), tb.p_line.size() * sizeof(uint32_t), 0},
+        {tb.p_term.data(), tb.p_term.size() * sizeof(uint64_t), 0},
+        {tb.p_group.data(), tb.p_group.size() * sizeof(uint64_t), 0},
     };
     size_t total = 0;
     for (auto &pc : pieces) {
@@ -320,6 +147,11 @@ AmiStatus upload(AmiTerms *t, DeviceTables **out) {
     d.term_sign = reinterpret_cast<const double *>(at(5));
     d.term_leaf = reinterpret_cast<const int32_t *>(at(6));
     d.line_alpha = reinterpret_cast<const double *>(at(7));
+    d.p_leaf = reinterpret_cast<const uint64_t *>(at(8));
+    d.p_den = reinterpret_cast<const uint64_t *>(at(9));
+    d.p_line = reinterpret_cast<const uint32_t *>(at(10));
+    d.p_term = reinterpret_cast<const uint64_t *>(at(11));
+    d.p_group = reinterpret_cast<const uint64_t *>(at(12));
     t->dev.push_back(d);
     *out = &t->dev.back();
     return AMI_OK;
@@ -328,20 +160,19 @@ AmiStatus upload(AmiTerms *t, DeviceTables **out) {
 struct LaunchShape {
     int block = 256;
     size_t lds = 0;
-    int region_a = 0;
+    int slots = 0;
 };
 
-AmiStatus pick_shape(const AmiTerms *t, LaunchShape &ls) {
+AmiStatus pick_shape(int slots, LaunchShape &ls) {
     int dev = 0;
     hipError_t e = hipGetDevice(&dev);
     if (e != hipSuccess) return hip_fail(e, "hipGetDevice");
     int max_lds = 0;
     e = hipDeviceGetAttribute(&max_lds, hipDeviceAttributeMaxSharedMemoryPerBlock, dev);
     if (e != hipSuccess) return hip_fail(e, "hipDeviceGetAttribute");
-    const Tables &tb = t->tab;
-    ls.region_a = std::max(tb.L, 2 * tb.D);
-    const size_t per_lane = static_cast<size_t>(ls.region_a + tb.G) * sizeof(double);
-    // prefer 256 lanes while one block stays within a quarter of the CU's LDS
+    ls.slots = slots;
+    const size_t per_lane = static_cast<size_t>(slots) * sizeof(double);
+    // 256 lanes while a block stays within a quarter of the CU's LDS, else fewer
     const int blocks[3] = {256, 128, 64};
     for (int b : blocks) {
         const size_t lds = per_lane * b + 2 * sizeof(double) * (b / 64);
@@ -355,11 +186,71 @@ AmiStatus pick_shape(const AmiTerms *t, LaunchShape &ls) {
                                        std::to_string(per_lane) + " B per sample)");
 }
 
-AmiStatus launch_forward(AmiTerms *t, bool hub, FwdParams &p, double *out_sum, hipStream_t stream) {
-    DeviceTables *dt = nullptr;
-    AmiStatus st = upload(t, &dt);
-    if (st != AMI_OK) return st;
+PackedTabs packed_tabs(const AmiTerms *t, const DeviceTables *dt) {
     const Tables &tb = t->tab;
+    PackedTabs p;
+    p.leaf = dt->p_leaf;
+    p.den = dt->p_den;
+    p.line = dt->p_line;
+    p.term = dt->p_term;
+    p.term_sign = dt->term_sign;
+    p.group_start = dt->group_start;
+    p.group = dt->p_group;
+    p.L = tb.L;
+    p.D = tb.D;
+    p.G = tb.G;
+    p.T = tb.T;
+    p.n_eps = t->n_eps;
+    p.n_int = t->n_int;
+    p.n_ext = t->n_ext;
+    p.n_freq = t->n_freq;
+    p.n_g = t->n_g;
+    p.dpt = tb.dpt;
+    p.fermi_used = tb.fermi_used;
+    p.use_products = tb.use_products ? 1 : 0;
+    return p;
+}
+
+template <bool ADJ, int NE, int NI, int DPT, bool EXACT, bool HUB>
+void launch_packed_one(dim3 grid, dim3 block, size_t lds, hipStream_t stream, const KArgs &a) {
+    if constexpr (ADJ)
+        hipLaunchKernelGGL((ami_adj_packed<NE, NI, DPT, EXACT, HUB>), grid, block, lds, stream, a);
+    else
+        hipLaunchKernelGGL((ami_fwd_packed<NE, NI, DPT, EXACT, HUB>), grid, block, lds, stream, a);
+}
+
+// Self-energy shapes (order n: 2n-1 energies, n leaves and n-1 denominators
+// per term) get exact instances; anything else the bounded generic one.
+template <bool ADJ, bool HUB>
+const char *launch_packed(const AmiTerms *t, dim3 grid, dim3 block, size_t lds, hipStream_t stream,
+                          const KArgs &a) {
+    const int ne = t->n_eps, ni = t->n_int, dpt = t->tab.dpt;
+    const bool se = (ne == 2 * ni - 1) && (dpt == ni - 1) && (!HUB || t->n_g == ne);
+#define AMI_SE(N)                                                                                 \
+    if (se && ni == N) {                                                                          \
+        launch_packed_one<ADJ, 2 * N - 1, N, N - 1, true, HUB>(grid, block, lds, stream, a);      \
+        return "self-energy order " #N;                                                           \
+    }
+    AMI_SE(1)
+    AMI_SE(2)
+    AMI_SE(3)
+    AMI_SE(4)
+    AMI_SE(5)
+    AMI_SE(6)
+    AMI_SE(7)
+#undef AMI_SE
+    launch_packed_one<ADJ, 16, 8, 8, false, HUB>(grid, block, lds, stream, a);
+    return "bounded generic";
+}
+
+int fwd_slots(const Tables &tb) { return std::max(tb.L, 2 * tb.D) + tb.G; }
+int adj_slots(const Tables &tb) { return tb.L + 2 * tb.G + std::max(2 * tb.D, tb.L); }
+
+AmiStatus launch_generic_forward(AmiTerms *t, DeviceTables *dt, bool hub, const KArgs &ka, double *partial,
+                                 const LaunchShape &ls, dim3 grid, hipStream_t stream) {
+    const Tables &tb = t->tab;
+    FwdParams p;
+    std::memset(&p, 0, sizeof(p));
     p.leaf_coef = dt->leaf_coef;
     p.leaf_sigma = dt->leaf_sigma;
     p.den_coef = dt->den_coef;
@@ -377,31 +268,24 @@ AmiStatus launch_forward(AmiTerms *t, bool hub, FwdParams &p, double *out_sum, h
     p.D = tb.D;
     p.G = tb.G;
     p.dpt = tb.dpt;
-    if (p.n_e == 0) {
-        if (out_sum) {
-            hipLaunchKernelGGL(ami_fill_kernel, dim3((2 * p.n_f + 255) / 256), dim3(256), 0, stream, out_sum,
-                               static_cast<int64_t>(2 * p.n_f), 0.0);
-            hipError_t e = hipGetLastError();
-            if (e != hipSuccess) return hip_fail(e, "fill launch");
-        }
-        return AMI_OK;
-    }
-    LaunchShape ls;
-    st = pick_shape(t, ls);
-    if (st != AMI_OK) return st;
-    p.region_a = ls.region_a;
-    const int64_t nblocks = (p.n_e + ls.block - 1) / ls.block;
-    if (nblocks > 0x7fffffffLL) return fail(AMI_E_ARG, "n_e too large");
-    double *partial = nullptr;
-    hipError_t e;
-    if (out_sum) {
-        e = hipMallocAsync(reinterpret_cast<void **>(&partial), static_cast<size_t>(nblocks) * p.n_f * 2 * sizeof(double),
-                           stream);
-        if (e != hipSuccess) return fail(AMI_E_OOM, std::string("workspace: ") + hipGetErrorString(e));
-    }
+    p.region_a = std::max(tb.L, 2 * tb.D);
+    p.energies = ka.energies;
+    p.stride_s = ka.stride_s;
+    p.stride_i = ka.stride_i;
+    p.k = ka.k;
+    p.stride_k = ka.stride_k;
+    for (int x = 0; x < 2 * kMaxExt; ++x) p.q[x] = ka.q[x];
+    p.hop_t = ka.hop_t;
+    p.mu = ka.mu;
+    p.ext_freqs = ka.ext_freqs;
+    p.n_f = ka.n_f;
+    p.beta = ka.beta;
+    p.e_reg = ka.e_reg;
+    p.n_e = ka.n_e;
+    p.out = ka.out;
     p.partial = partial;
     const int maxe = t->n_eps <= 4 ? 4 : (t->n_eps <= 8 ? 8 : 16);
-    const dim3 grid(static_cast<unsigned>(nblocks)), block(ls.block);
+    const dim3 block(ls.block);
 #define AMI_LAUNCH(ME, H) hipLaunchKernelGGL((ami_fwd_kernel<ME, H>), grid, block, ls.lds, stream, p)
     if (hub) {
         if (maxe == 4) AMI_LAUNCH(4, true);
@@ -413,13 +297,50 @@ AmiStatus launch_forward(AmiTerms *t, bool hub, FwdParams &p, double *out_sum, h
         else AMI_LAUNCH(16, false);
     }
 #undef AMI_LAUNCH
+    return AMI_OK;
+}
+
+thread_local const char *g_last_variant = "";
+
+AmiStatus launch_forward(AmiTerms *t, bool hub, KArgs &a, double *out_sum, hipStream_t stream,
+                         bool force_generic) {
+    DeviceTables *dt = nullptr;
+    AmiStatus st = upload(t, &dt);
+    if (st != AMI_OK) return st;
+    const Tables &tb = t->tab;
+    if (a.n_e == 0) return fill(out_sum, 2 * static_cast<int64_t>(a.n_f), stream);
+    const bool packed = tb.packable && !force_generic;
+    LaunchShape ls;
+    st = pick_shape(fwd_slots(tb), ls);
+    if (st != AMI_OK) return st;
+    const int64_t nblocks = (a.n_e + ls.block - 1) / ls.block;
+    if (nblocks > 0x7fffffffLL) return fail(AMI_E_ARG, "n_e too large");
+    double *partial = nullptr;
+    hipError_t e;
+    if (out_sum) {
+        e = hipMallocAsync(reinterpret_cast<void **>(&partial),
+                           static_cast<size_t>(nblocks) * a.n_f * 2 * sizeof(double), stream);
+        if (e != hipSuccess) return fail(AMI_E_OOM, std::string("workspace: ") + hipGetErrorString(e));
+    }
+    const dim3 grid(static_cast<unsigned>(nblocks)), block(ls.block);
+    if (packed) {
+        a.tb = packed_tabs(t, dt);
+        a.slots = ls.slots;
+        a.partial = partial;
+        g_last_variant = hub ? launch_packed<false, true>(t, grid, block, ls.lds, stream, a)
+                             : launch_packed<false, false>(t, grid, block, ls.lds, stream, a);
+    } else {
+        launch_generic_forward(t, dt, hub, a, partial, ls, grid, stream);
+        g_last_variant = "double tables";
+    }
     e = hipGetLastError();
     if (e != hipSuccess) {
         if (partial) (void)hipFreeAsync(partial, stream);
         return hip_fail(e, "forward launch");
     }
     if (out_sum) {
-        hipLaunchKernelGGL(ami_rowsum_kernel, dim3(p.n_f), dim3(256), 0, stream, partial, nblocks, p.n_f, out_sum);
+        hipLaunchKernelGGL(ami_colsum_kernel, dim3(2 * a.n_f), dim3(256), 0, stream, partial, nblocks, 2 * a.n_f,
+                           out_sum);
         e = hipGetLastError();
         (void)hipFreeAsync(partial, stream);
         if (e != hipSuccess) return hip_fail(e, "row-sum launch");
@@ -427,17 +348,101 @@ AmiStatus launch_forward(AmiTerms *t, bool hub, FwdParams &p, double *out_sum, h
     return AMI_OK;
 }
 
-AmiStatus check_common(const AmiTerms *t, int64_t n_e, const double *ext_freqs, int64_t n_f, double beta,
-                       const double *out, const double *out_sum) {
+struct AdjOut {
+    double *grad_beta = nullptr, *grad_mu = nullptr, *grad_t = nullptr, *grad_freqs = nullptr;
+};
+
+AmiStatus launch_adjoint(AmiTerms *t, bool hub, KArgs &a, const AdjOut &o, hipStream_t stream) {
+    DeviceTables *dt = nullptr;
+    AmiStatus st = upload(t, &dt);
+    if (st != AMI_OK) return st;
+    const Tables &tb = t->tab;
+    if (!tb.packable)
+        return fail(AMI_E_UNSUPPORTED, "the adjoint needs +-1 coefficients and at most 255 leaves/denominators");
+    const int nx = t->n_ext;
+    const int ncols = kAdjScalars + 2 * a.n_f * nx;
+    if (a.n_e == 0) {
+        for (double *p : {o.grad_beta, o.grad_mu, o.grad_t}) {
+            st = fill(p, 1, stream);
+            if (st != AMI_OK) return st;
+        }
+        return fill(o.grad_freqs, 2 * static_cast<int64_t>(a.n_f) * nx, stream);
+    }
+    LaunchShape ls;
+    st = pick_shape(adj_slots(tb), ls);
+    if (st != AMI_OK) return st;
+    const int64_t nblocks = (a.n_e + ls.block - 1) / ls.block;
+    if (nblocks > 0x7fffffffLL) return fail(AMI_E_ARG, "n_e too large");
+    double *partial = nullptr;
+    hipError_t e = hipMallocAsync(reinterpret_cast<void **>(&partial),
+                                  static_cast<size_t>(nblocks) * ncols * sizeof(double), stream);
+    if (e != hipSuccess) return fail(AMI_E_OOM, std::string("workspace: ") + hipGetErrorString(e));
+    a.tb = packed_tabs(t, dt);
+    a.slots = ls.slots;
+    a.gpartial = partial;
+    const dim3 grid(static_cast<unsigned>(nblocks)), block(ls.block);
+    g_last_variant = hub ? launch_packed<true, true>(t, grid, block, ls.lds, stream, a)
+                         : launch_packed<true, false>(t, grid, block, ls.lds, stream, a);
+    e = hipGetLastError();
+    if (e != hipSuccess) {
+        (void)hipFreeAsync(partial, stream);
+        return hip_fail(e, "adjoint launch");
+    }
+    hipLaunchKernelGGL(ami_adj_finalize_kernel, dim3(ncols), dim3(256), 0, stream, partial, nblocks, ncols,
+                       o.grad_beta, o.grad_mu, o.grad_t, o.grad_freqs);
+    e = hipGetLastError();
+    (void)hipFreeAsync(partial, stream);
+    if (e != hipSuccess) return hip_fail(e, "adjoint reduction launch");
+    return AMI_OK;
+}
+
+AmiStatus check_common(const AmiTerms *t, int64_t n_e, const double *ext_freqs, int64_t n_f, double beta) {
     if (!t) return fail(AMI_E_ARG, "terms is NULL");
     if (n_e < 0) return fail(AMI_E_ARG, "n_e < 0");
     if (n_f < 1 || n_f > (1 << 24)) return fail(AMI_E_ARG, "n_f must be in 1..2^24");
     if (!ext_freqs && t->n_ext > 0) return fail(AMI_E_ARG, "ext_freqs is NULL");
     if (!(beta > 0.0)) return fail(AMI_E_ARG, "beta must be > 0");
-    if (!out && !out_sum) return fail(AMI_E_ARG, "out and out_sum are both NULL");
     if (t->n_eps > kMaxEpsDev) return fail(AMI_E_UNSUPPORTED, "more than 16 energy placeholders");
     if (t->n_ext > kMaxExt) return fail(AMI_E_UNSUPPORTED, "more than 4 external frequency slots");
     return AMI_OK;
+}
+
+AmiStatus check_energies(const AmiTerms *, int64_t n_e, const double *energies, int64_t stride_s,
+                         int64_t stride_i) {
+    if (n_e > 0 && !energies) return fail(AMI_E_ARG, "energies is NULL");
+    if (n_e > 0 && (stride_i < 1 || stride_s < 1)) return fail(AMI_E_ARG, "strides must be >= 1");
+    return AMI_OK;
+}
+
+AmiStatus check_momenta(const AmiTerms *t, int64_t n_e, const double *k, int64_t stride_k, const double *q) {
+    if (t->n_eps != t->n_g) return fail(AMI_E_ARG, "the momentum path needs one energy per propagator");
+    if (t->n_int > kMaxInt) return fail(AMI_E_UNSUPPORTED, "more than 12 summed frequencies on the momentum path");
+    if (n_e > 0 && !k) return fail(AMI_E_ARG, "k is NULL");
+    if (n_e > 0 && stride_k < 2 * t->n_int) return fail(AMI_E_ARG, "stride_k < 2*n_int");
+    if (t->n_ext > 0 && !q) return fail(AMI_E_ARG, "q is NULL");
+    return AMI_OK;
+}
+
+void set_momenta(KArgs &a, const AmiTerms *t, const double *k, int64_t stride_k, const double *q, double hop_t,
+                 double mu) {
+    a.k = k;
+    a.stride_k = stride_k;
+    a.q_big = 0;
+    for (int x = 0; x < t->n_ext && x < kMaxExtDev; ++x) {
+        a.q[2 * x] = q[2 * x];
+        a.q[2 * x + 1] = q[2 * x + 1];
+        if (!(std::abs(q[2 * x]) <= 1e4) || !(std::abs(q[2 * x + 1]) <= 1e4)) a.q_big = 1;
+    }
+    a.hop_t = hop_t;
+    a.mu = mu;
+}
+
+void set_common(KArgs &a, const double *ext_freqs, int64_t n_f, double beta, double e_reg, int64_t n_e) {
+    a.ext_freqs = ext_freqs;
+    a.n_f = static_cast<int>(n_f);
+    a.beta = beta;
+    a.e_reg = e_reg;
+    a.n_e = n_e;
 }
 
 }  // namespace
@@ -456,12 +461,9 @@ AmiStatus amiTermsUpload(AmiTerms *t) {
 void amiFree(AmiTerms *t) {
     if (!t) return;
     int cur = 0;
-    bool have_cur = hipGetDevice(&cur) == hipSuccess;
-    for (auto &d : t->dev) {
-        if (d.blob) {
-            if (hipSetDevice(d.device) == hipSuccess) (void)hipFree(d.blob);
-        }
-    }
+    const bool have_cur = hipGetDevice(&cur) == hipSuccess;
+    for (auto &d : t->dev)
+        if (d.blob && hipSetDevice(d.device) == hipSuccess) (void)hipFree(d.blob);
     if (have_cur) (void)hipSetDevice(cur);
     delete t;
 }
@@ -471,22 +473,18 @@ AmiStatus amiEvaluate(AmiTerms *t, const double *energies, int64_t n_e, int64_t 
                       double *out_sum, void *hip_stream) {
     using namespace ami;
     clear_error();
-    AmiStatus st = check_common(t, n_e, ext_freqs, n_f, beta, out, out_sum);
+    AmiStatus st = check_common(t, n_e, ext_freqs, n_f, beta);
+    if (st == AMI_OK) st = check_energies(t, n_e, energies, stride_s, stride_i);
     if (st != AMI_OK) return st;
-    if (n_e > 0 && !energies) return fail(AMI_E_ARG, "energies is NULL");
-    if (n_e > 0 && (stride_i < 1 || stride_s < 1)) return fail(AMI_E_ARG, "strides must be >= 1");
-    FwdParams p;
-    std::memset(&p, 0, sizeof(p));
-    p.energies = energies;
-    p.stride_s = stride_s;
-    p.stride_i = stride_i;
-    p.ext_freqs = ext_freqs;
-    p.n_f = static_cast<int>(n_f);
-    p.beta = beta;
-    p.e_reg = e_reg;
-    p.n_e = n_e;
-    p.out = out;
-    return launch_forward(t, false, p, out_sum, static_cast<hipStream_t>(hip_stream));
+    if (!out && !out_sum) return fail(AMI_E_ARG, "out and out_sum are both NULL");
+    KArgs a;
+    std::memset(&a, 0, sizeof(a));
+    a.energies = energies;
+    a.stride_s = stride_s;
+    a.stride_i = stride_i;
+    set_common(a, ext_freqs, n_f, beta, e_reg, n_e);
+    a.out = out;
+    return launch_forward(t, false, a, out_sum, static_cast<hipStream_t>(hip_stream), t->variant == 1);
 }
 
 AmiStatus amiEvaluateHubbard(AmiTerms *t, const double *k, int64_t n_e, int64_t stride_k, const double *q,
@@ -494,30 +492,77 @@ AmiStatus amiEvaluateHubbard(AmiTerms *t, const double *k, int64_t n_e, int64_t 
                              double e_reg, double *out, double *out_sum, void *hip_stream) {
     using namespace ami;
     clear_error();
-    AmiStatus st = check_common(t, n_e, ext_freqs, n_f, beta, out, out_sum);
+    AmiStatus st = check_common(t, n_e, ext_freqs, n_f, beta);
+    if (st == AMI_OK) st = check_momenta(t, n_e, k, stride_k, q);
     if (st != AMI_OK) return st;
-    if (t->n_eps != t->n_g) return fail(AMI_E_ARG, "the momentum path needs one energy per propagator");
-    if (t->n_int > kMaxInt) return fail(AMI_E_UNSUPPORTED, "more than 12 summed frequencies on the momentum path");
-    if (n_e > 0 && !k) return fail(AMI_E_ARG, "k is NULL");
-    if (n_e > 0 && stride_k < 2 * t->n_int) return fail(AMI_E_ARG, "stride_k < 2*n_int");
-    if (t->n_ext > 0 && !q) return fail(AMI_E_ARG, "q is NULL");
-    FwdParams p;
-    std::memset(&p, 0, sizeof(p));
-    p.k = k;
-    p.stride_k = stride_k;
-    for (int x = 0; x < t->n_ext; ++x) {
-        p.q[2 * x] = q[2 * x];
-        p.q[2 * x + 1] = q[2 * x + 1];
-    }
-    p.hop_t = hop_t;
-    p.mu = mu;
-    p.ext_freqs = ext_freqs;
-    p.n_f = static_cast<int>(n_f);
-    p.beta = beta;
-    p.e_reg = e_reg;
-    p.n_e = n_e;
-    p.out = out;
-    return launch_forward(t, true, p, out_sum, static_cast<hipStream_t>(hip_stream));
+    if (!out && !out_sum) return fail(AMI_E_ARG, "out and out_sum are both NULL");
+    KArgs a;
+    std::memset(&a, 0, sizeof(a));
+    set_momenta(a, t, k, stride_k, q, hop_t, mu);
+    set_common(a, ext_freqs, n_f, beta, e_reg, n_e);
+    a.out = out;
+    return launch_forward(t, true, a, out_sum, static_cast<hipStream_t>(hip_stream), t->variant == 1);
 }
+
+AmiStatus amiEvaluateAdjoint(AmiTerms *t, const double *energies, int64_t n_e, int64_t stride_s,
+                             int64_t stride_i, const double *ext_freqs, int64_t n_f, double beta, double e_reg,
+                             const double *grad_out, const double *grad_sum, double *grad_energies,
+                             double *grad_beta, double *grad_freqs, void *hip_stream) {
+    using namespace ami;
+    clear_error();
+    AmiStatus st = check_common(t, n_e, ext_freqs, n_f, beta);
+    if (st == AMI_OK) st = check_energies(t, n_e, energies, stride_s, stride_i);
+    if (st != AMI_OK) return st;
+    if (!grad_out && !grad_sum) return fail(AMI_E_ARG, "grad_out and grad_sum are both NULL");
+    KArgs a;
+    std::memset(&a, 0, sizeof(a));
+    a.energies = energies;
+    a.stride_s = stride_s;
+    a.stride_i = stride_i;
+    set_common(a, ext_freqs, n_f, beta, e_reg, n_e);
+    a.g_out = grad_out;
+    a.g_sum = grad_sum;
+    a.grad_e = grad_energies;
+    AdjOut o;
+    o.grad_beta = grad_beta;
+    o.grad_freqs = grad_freqs;
+    return launch_adjoint(t, false, a, o, static_cast<hipStream_t>(hip_stream));
+}
+
+AmiStatus amiEvaluateHubbardAdjoint(AmiTerms *t, const double *k, int64_t n_e, int64_t stride_k, const double *q,
+                                    double hop_t, double mu, const double *ext_freqs, int64_t n_f, double beta,
+                                    double e_reg, const double *grad_out, const double *grad_sum, double *grad_k,
+                                    double *grad_mu, double *grad_t, double *grad_beta, double *grad_freqs,
+                                    void *hip_stream) {
+    using namespace ami;
+    clear_error();
+    AmiStatus st = check_common(t, n_e, ext_freqs, n_f, beta);
+    if (st == AMI_OK) st = check_momenta(t, n_e, k, stride_k, q);
+    if (st != AMI_OK) return st;
+    if (!grad_out && !grad_sum) return fail(AMI_E_ARG, "grad_out and grad_sum are both NULL");
+    KArgs a;
+    std::memset(&a, 0, sizeof(a));
+    set_momenta(a, t, k, stride_k, q, hop_t, mu);
+    set_common(a, ext_freqs, n_f, beta, e_reg, n_e);
+    a.g_out = grad_out;
+    a.g_sum = grad_sum;
+    a.grad_k = grad_k;
+    AdjOut o;
+    o.grad_beta = grad_beta;
+    o.grad_mu = grad_mu;
+    o.grad_t = grad_t;
+    o.grad_freqs = grad_freqs;
+    return launch_adjoint(t, true, a, o, static_cast<hipStream_t>(hip_stream));
+}
+
+AmiStatus amiSetVariant(AmiTerms *t, int32_t variant) {
+    ami::clear_error();
+    if (!t) return ami::fail(AMI_E_ARG, "terms is NULL");
+    if (variant != 0 && variant != 1) return ami::fail(AMI_E_ARG, "variant must be 0 or 1");
+    t->variant = variant;
+    return AMI_OK;
+}
+
+const char *amiLastVariant(void) { return ami::g_last_variant; }
 
 }  // extern "C"

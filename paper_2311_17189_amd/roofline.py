@@ -1,15 +1,21 @@
-"""Algorithmic FLOP and byte model of one evaluation launch (accounting only).
+"""Algorithmic FLOP model of one evaluation launch (accounting only).
 
 Counts are those of the evaluation as the library structures it: every
-distinct leaf and denominator once per sample (per sample and frequency for
-denominators), the Fermi-tree products of each term once per sample (they do
-not depend on the external frequency, Sec. 2.3), and one product of
-denominator reciprocals per group of terms sharing them.  Only non-zero
-integer coefficients are counted.  FMA counts 2 FLOPs; the elementary
-functions count the FP64 FLOPs of this build's device-library sequences on
-gfx950 (FMA = 2, add/mul/ldexp/rndne/rcp = 1, compares and conversions 0):
+distinct leaf once per sample, every distinct denominator once per sample and
+frequency, the Fermi-tree products of each term once per sample (they do not
+depend on the external frequency, Sec. 2.3), one product of denominator
+reciprocals per group of terms sharing them, and on the momentum path the
+energies from momenta (Sec. 5.2).  Only non-zero integer coefficients count.
+FMA counts 2 FLOPs; each elementary function counts the FP64 FLOPs of the
+sequence the kernels execute on gfx950, read from the AMD assembly of small
+kernels compiled here (FMA 2; add, mul, min/max, ldexp, rndne, rcp 1;
+compares and conversions 0):
 
-    exp 29, expm1 34, IEEE division 17, cos 58 (|x| < 2^30 path)
+    sin and cos of one argument (both, reduced)      44
+    e^z and e^z - 1 of one argument (both)           37
+    reciprocal (estimate + two Newton steps)          9
+    leaf f(y) with its mirror f(-y), Fermi / Bose    47 / 49
+    leaf derivative f'(y)                            48
 
 A term-evaluation is one canonical flat term at one (sample, frequency) point.
 """
@@ -19,11 +25,12 @@ from dataclasses import dataclass
 
 import numpy as np
 
-C_EXP = 29
-C_EXPM1 = 34
-C_DIV = 17
-C_COS = 58
-C_SIN = 58
+C_SINCOS = 44
+C_EXP = 37
+C_RCP = 9
+C_LEAF_FERMI = 47
+C_LEAF_BOSE = 49
+C_LEAF_DERIV = 48
 
 PEAK_FP64_VECTOR = 78.6e12     # 256 CUs x 2.4 GHz x 128 FP64 FLOP/clk
 PEAK_HBM = 8.0e12              # bytes/s
@@ -74,22 +81,59 @@ def _nnz(v) -> int:
     return sum(1 for x in v if x != 0)
 
 
+def _use_products(st: Structure) -> bool:
+    """The kernels build Fermi leaves from products of exp(beta E_i) when the
+    Fermi leaves outnumber the energies they use (same rule as the host)."""
+    used = set()
+    n_fermi = 0
+    for sigma, e in st.leaves:
+        if sigma == 1:
+            n_fermi += 1
+            used.update(i for i, x in enumerate(e) if x != 0)
+    return n_fermi > len(used)
+
+
+def _leaf_flops(st: Structure) -> int:
+    prod = _use_products(st)
+    total = 0
+    used = set()
+    for sigma, e in st.leaves:
+        nz = _nnz(e)
+        if sigma == -1:
+            total += max(nz - 1, 0) + 2 + C_LEAF_BOSE
+        elif prod:
+            total += max(nz - 2, 0) + 1 + C_RCP + 1        # N*P products, N+P, 1/(N+P), N*r
+            used.update(i for i, x in enumerate(e) if x != 0)
+        else:
+            total += max(nz - 1, 0) + 1 + C_LEAF_FERMI
+    if prod:
+        total += len(used) * (1 + C_EXP)                     # exp(beta E_i)
+    return total
+
+
+def _momentum_flops(line_alpha) -> int:
+    total = 0
+    for row in np.asarray(line_alpha):
+        total += 2 * max(_nnz(row) - 1, 0) + 2 * C_SINCOS + 3
+    return total
+
+
+def _den_flops(st: Structure) -> int:
+    total = 0
+    for e, a in st.dens:
+        total += max(_nnz(e) - 1, 0) + 2 * _nnz(a) + 3 + C_RCP + 2
+    return total
+
+
 def forward_flops(st: Structure, n_e: int, n_f: int, line_alpha=None) -> dict:
     """FLOPs of one forward launch; ``line_alpha`` (int [nG, nF]) adds the
-    energies-from-momenta stage (Sec. 5.2) of the Hubbard path."""
-    per_sample = 0
+    energies-from-momenta stage (Sec. 5.2) of the momentum path."""
+    per_sample = _leaf_flops(st)
     if line_alpha is not None:
-        for row in np.asarray(line_alpha):
-            nz = _nnz(row)
-            per_sample += 2 * max(nz - 1, 0) + 2 * C_COS + 3
-    for sigma, e in st.leaves:
-        base = max(_nnz(e) - 1, 0) + 1 + C_DIV
-        per_sample += base + (C_EXP + 1 if sigma == 1 else C_EXPM1)
+        per_sample += _momentum_flops(line_alpha)
     for n_terms, _ in st.groups:
-        per_sample += n_terms * (max(st.n_int - 1, 0) + 1)
-    per_point = 0
-    for e, a in st.dens:
-        per_point += max(_nnz(e) - 1, 0) + 2 * _nnz(a) + 3 + C_DIV + 2
+        per_sample += n_terms * (st.n_int + 1)              # n-1 products, sign, accumulate
+    per_point = _den_flops(st)
     for n_terms, dpt in st.groups:
         per_point += 6 * max(dpt - 1, 0) + 4
     total = n_e * per_sample + n_e * n_f * per_point
@@ -97,6 +141,29 @@ def forward_flops(st: Structure, n_e: int, n_f: int, line_alpha=None) -> dict:
             "term_evals": float(st.T) * n_e * n_f}
 
 
-def forward_bytes(n_e: int, n_f: int, n_in_per_sample: int, want_out: bool) -> float:
-    """Compulsory HBM bytes of one forward launch: inputs once, outputs once."""
-    return float(n_e * n_in_per_sample * 8 + (n_e * n_f * 16 if want_out else 0))
+def adjoint_flops(st: Structure, n_e: int, n_f: int, line_alpha=None) -> dict:
+    """FLOPs of one adjoint launch: the forward recomputation of leaves,
+    group sums and reciprocals, then per group and frequency the product of
+    its reciprocals, the group-sum cotangent and one complex product per
+    denominator scattered to energies and frequencies; per term the
+    prefix/suffix products of its leaves; per leaf its derivative scattered
+    to energies and beta; on the momentum path the chain rule through
+    -2t sin K."""
+    ni = st.n_int
+    per_sample = _leaf_flops(st)
+    if line_alpha is not None:
+        per_sample += _momentum_flops(line_alpha)
+        for row in np.asarray(line_alpha)[:, :ni]:
+            per_sample += 10 + 2 * _nnz(row)
+    for n_terms, _ in st.groups:
+        per_sample += n_terms * (st.n_int + 1)              # group sums
+        per_sample += n_terms * (1 + ni + (ni - 1) + 2 * ni)   # leaf cotangents
+    for sigma, e in st.leaves:
+        per_sample += max(_nnz(e) - 1, 0) + 2 + C_LEAF_DERIV + 1 + _nnz(e) + 1 + 2
+    per_point = _den_flops(st)
+    for n_terms, dpt in st.groups:
+        per_point += 6 * max(dpt - 1, 0) + 3 + 2 + 6
+        per_point += dpt * (6 + 3 + 2)          # rho * u, scatter (about 3 energies, 1 frequency)
+    total = n_e * per_sample + n_e * n_f * per_point
+    return {"per_sample": per_sample, "per_point": per_point, "total": float(total),
+            "term_evals": float(st.T) * n_e * n_f}

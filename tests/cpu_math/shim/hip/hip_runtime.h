@@ -1,0 +1,15 @@
+// Host stand-in for the HIP runtime header, so that the device math of
+// device_common.hpp can be compiled and checked with a host compiler.
+#pragma once
+#include <cmath>
+#define __device__
+#define __global__
+#define __forceinline__ inline
+#define __launch_bounds__(x)
+#define __builtin_amdgcn_rcp(x) (1.0 / (x))
+using std::expm1;
+using std::fabs;
+using std::fma;
+using std::fmax;
+using std::fmin;
+inline double __shfl_xor(double v, int, int) { return v; }

@@ -18,7 +18,7 @@ from oracle.evaluate import evaluate_terms, energies_from_k, term_magnitudes
 
 TOL = 1e-10        # relative to sum_t |v_t|, away from poles
 TOL_NEAR = 1e-6    # within NEAR of a pole of one term
-NEAR = 1e-6
+NEAR = 1e-4
 
 
 def oracle_terms(d):
@@ -71,3 +71,44 @@ def check(got, ref, scale, dist, tol=TOL, tol_near=TOL_NEAR, near=NEAR, label=""
         worst_near = float(np.nanmax(err[~far]))
         assert worst_near <= tol_near, f"{label}: max error {worst_near:.3e} near poles"
     return worst
+
+
+def far_from_poles(terms, n_int, E, w, e_reg=0.0, near=NEAR):
+    """Indices of samples whose every Bose-type leaf argument and denominator
+    stays at least ``near`` away from zero at every frequency row."""
+    return np.nonzero(pole_distance(terms, n_int, E, w, e_reg).min(axis=0) >= near)[0]
+
+
+def gradient_scale(terms, n_int, E, w, beta, cot, e_reg=0.0):
+    """Per sample and energy, sum over terms of |dL_t/dE_i|: the rounding scale
+    of the summed gradient (the analogue of sum_t |v_t| for values)."""
+    return gradient_scales(terms, n_int, E, w, beta, cot, e_reg)["E"]
+
+
+def gradient_scales(terms, n_int, E, w, beta, cot, e_reg=0.0, hubbard=None):
+    """Rounding scales of every adjoint output: sums over terms (and over
+    samples for the reduced outputs) of the magnitudes of the single-term
+    contributions.  ``hubbard = (alpha, k, q, t, mu)`` adds the momentum path."""
+    from oracle.evaluate import gradients, line_momenta
+    E = np.asarray(E)
+    out = {"E": np.zeros(E.shape), "beta": 0.0, "w": 0.0}
+    if hubbard is not None:
+        alpha, k, q, t, mu = hubbard
+        K = line_momenta(alpha, k, q).astype(np.float64)
+        ng = np.asarray(alpha).shape[0]
+        sin = np.sin(K)
+        cs = np.stack([np.cos(K[:, 2 * j]) + np.cos(K[:, 2 * j + 1]) for j in range(ng)], axis=1)
+        out.update({"k": np.zeros(np.asarray(k).shape), "mu": 0.0, "t": 0.0})
+        A = np.kron(np.asarray(alpha, dtype=np.float64), np.eye(2))
+    for term in terms:
+        de, db, dw = gradients([term], n_int, E, w, beta, cot, e_reg, per_sample=True)
+        de = de.astype(np.float64)
+        out["E"] += np.abs(de)
+        out["beta"] += float(np.sum(np.abs(db.astype(np.float64))))
+        out["w"] += float(np.sum(np.abs(dw.astype(np.complex128))))
+        if hubbard is not None:
+            dK = np.repeat(de, 2, axis=1) * (-2 * t * sin)
+            out["k"] += np.abs((dK @ A)[:, :np.asarray(k).shape[1]])
+            out["mu"] += float(np.sum(np.abs(de.sum(axis=1))))
+            out["t"] += float(np.sum(np.abs((de * 2 * cs).sum(axis=1))))
+    return out

@@ -1,0 +1,79 @@
+"""The device math of the HIP evaluators (own sin/cos, exp/expm1 pair, Fermi and
+Bose leaves with their mirrors and derivatives), compiled for the host with a
+stand-in HIP header and compared with 40-digit mpmath values (CPU only)."""
+import os
+import shutil
+import subprocess
+
+import mpmath as mp
+import numpy as np
+import pytest
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+SRC = os.path.join(HERE, "cpu_math", "math_check.cpp")
+
+
+@pytest.fixture(scope="module")
+def exe(tmp_path_factory):
+    cxx = shutil.which("g++")
+    if cxx is None:
+        pytest.skip("no host C++ compiler")
+    out = str(tmp_path_factory.mktemp("math") / "math_check")
+    subprocess.run([cxx, "-O2", "-std=c++17", "-ffp-contract=off", "-I",
+                    os.path.join(HERE, "cpu_math", "shim"), SRC, "-o", out], check=True)
+    return out
+
+
+def _run(exe, what, xs):
+    res = subprocess.run([exe, what], input="\n".join(repr(float(x)) for x in xs),
+                         capture_output=True, text=True, check=True)
+    return np.array([[float(v) for v in line.split()] for line in res.stdout.splitlines()])
+
+
+def _ulp_err(got, want):
+    want = float(want)
+    if want == 0.0:
+        return abs(got)
+    return abs(got - want) / abs(want) / 2.0 ** -52
+
+
+def test_sincos_reduced(exe):
+    mp.mp.dps = 40
+    rng = np.random.default_rng(0)
+    xs = np.concatenate([rng.uniform(-4 * np.pi, 4 * np.pi, 400), rng.uniform(-1e4, 1e4, 200),
+                         [0.0, np.pi / 4, np.pi / 2, -np.pi, 3 * np.pi / 2, 1e-8, -1e-300]])
+    got = _run(exe, "s", xs)
+    for x, (s, c) in zip(xs, got):
+        ms, mc = mp.sin(mp.mpf(float(x))), mp.cos(mp.mpf(float(x)))
+        # absolute error against 1 (the scale of sin and cos) stays at a few ulp
+        assert abs(s - float(ms)) <= 4 * 2.0 ** -52 * max(1.0, abs(x) * 2.0 ** -20) + 1e-300
+        assert abs(c - float(mc)) <= 4 * 2.0 ** -52 * max(1.0, abs(x) * 2.0 ** -20)
+
+
+def test_exp_split(exe):
+    mp.mp.dps = 40
+    xs = np.concatenate([-np.logspace(-12, np.log10(700.0), 300), np.logspace(-12, np.log10(700.0), 300),
+                         [0.0, -0.5, 0.5, -0.34657359, 0.34657359]])
+    got = _run(exe, "e", xs)
+    for x, (t, m) in zip(xs, got):
+        et, em = mp.exp(mp.mpf(float(x))), mp.expm1(mp.mpf(float(x)))
+        assert _ulp_err(t, et) <= 3
+        assert _ulp_err(m, em) <= 4
+
+
+@pytest.mark.parametrize("kind", ["fermi", "bose"])
+def test_leaf_pair_and_derivative(exe, kind):
+    """f(y), f(-y) = 1 - f(y) and f'(y) = -f(y) f(-y) to a few ulp relative, from
+    y = 1e-10 (next to the Bose pole) out to |y| = 700."""
+    mp.mp.dps = 40
+    mag = np.logspace(-10, np.log10(690.0), 250)   # arguments are clamped at 700
+    ys = np.concatenate([mag, -mag])
+    got = _run(exe, kind[0], ys)
+    sig = 1 if kind == "fermi" else -1
+    for y, (f, fm, df) in zip(ys, got):
+        Y = mp.mpf(float(y))
+        ef = 1 / (sig * mp.exp(Y) + 1)
+        efm = 1 / (sig * mp.exp(-Y) + 1)
+        assert _ulp_err(f, ef) <= 8, (y, f, ef)
+        assert _ulp_err(fm, efm) <= 8, (y, fm, efm)
+        assert _ulp_err(df, -ef * efm) <= 12, (y, df)

@@ -1,0 +1,220 @@
+"""GPU adjoint: the HIP adjoint kernels (through the C ABI) against the
+oracle's analytic gradients and against central finite differences of the HIP
+forward evaluation in float64 (step 1e-6)."""
+import numpy as np
+import pytest
+
+from ami_inputs import (DEFAULT_Q, k_samples, matsubara_freqs, order2_example,
+                        random_self_energy, real_freqs, uniform_energies)
+from oracle.evaluate import (energies_from_k, gradients, momentum_gradients)
+
+from parity import check, far_from_poles, gradient_scale, gradient_scales, oracle_terms, reference
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+amd = pytest.importorskip("paper_2311_17189_amd")
+
+DEV = "cuda"
+
+
+def _cot(n_f, n_e, seed):
+    rng = np.random.default_rng(seed)
+    return rng.standard_normal((n_f, n_e)) + 1j * rng.standard_normal((n_f, n_e))
+
+
+def _rel(a, b):
+    a = np.asarray(a, dtype=np.complex128)
+    b = np.asarray(b, dtype=np.complex128)
+    return float(np.max(np.abs(a - b)) / max(np.max(np.abs(b)), 1e-300))
+
+
+@pytest.mark.parametrize("order,i,beta", [(2, None, 5.0), (3, 1, 2.0), (4, 1, 5.0), (4, 1, 20.0),
+                                          (5, 0, 3.0), (6, 0, 5.0)])
+def test_energy_adjoint_vs_oracle(order, i, beta):
+    """Per-sample dL/dE within 1e-10 of sum_t |dL_t/dE| (1e-6 next to a pole of
+    one term); the sums over samples (dL/dbeta, dL/dw) within 1e-10 relative
+    on samples away from poles."""
+    d = order2_example() if i is None else random_self_energy(order, (0, order, i))
+    n_e = 300 if order < 6 else 60
+    E = uniform_energies(n_e, d.n_eps, seed=(20, order), a=3.0)
+    w = np.concatenate([matsubara_freqs(2, beta), real_freqs(1, 1.0, 1.0, 0.05)])
+    terms = oracle_terms(d)
+    cot = _cot(len(w), n_e, 1)
+    cot_sum = np.array([0.5 - 0.25j, 0.1j, -0.3])
+    T = amd.Terms.from_diagram(d)
+    g_e, _, _ = amd.evaluate_adjoint(T, torch.from_numpy(E).to(DEV), torch.from_numpy(w).to(DEV), beta,
+                                     grad_out=torch.from_numpy(cot).to(DEV),
+                                     grad_sum=torch.from_numpy(cot_sum).to(DEV))
+    torch.cuda.synchronize()
+    full = cot + cot_sum[:, None]
+    ref_e, _, _ = gradients(terms, d.n_int, E, w, beta, full)
+    scale = gradient_scale(terms, d.n_int, E, w, beta, full)
+    err = np.abs(g_e.cpu().numpy() - ref_e.astype(np.float64)) / np.maximum(scale, 1e-300)
+    keep = far_from_poles(terms, d.n_int, E, w)
+    near = np.setdiff1d(np.arange(n_e), keep)
+    assert err[keep].max() <= 1e-10
+    if len(near):
+        assert err[near].max() <= 1e-6
+    # reductions over samples, on samples away from poles
+    Ek = np.ascontiguousarray(E[keep])
+    ck = np.ascontiguousarray(cot[:, keep])
+    _, g_b, g_w = amd.evaluate_adjoint(T, torch.from_numpy(Ek).to(DEV), torch.from_numpy(w).to(DEV), beta,
+                                       grad_out=torch.from_numpy(ck).to(DEV),
+                                       grad_sum=torch.from_numpy(cot_sum).to(DEV))
+    torch.cuda.synchronize()
+    _, ref_b, ref_w = gradients(terms, d.n_int, Ek, w, beta, ck + cot_sum[:, None])
+    sc = gradient_scales(terms, d.n_int, Ek, w, beta, ck + cot_sum[:, None])
+    assert abs(float(g_b) - float(ref_b)) <= 1e-10 * sc["beta"]
+    assert np.max(np.abs(g_w.cpu().numpy() - ref_w.astype(np.complex128))) <= 1e-10 * sc["w"]
+
+
+@pytest.mark.parametrize("order,i", [(2, None), (4, 1), (4, 3)])
+def test_hubbard_adjoint_vs_oracle(order, i):
+    """Momentum-path adjoint: every output within 1e-10 of its rounding scale
+    (the sum over terms, and over samples for reduced outputs, of the
+    single-term contributions' magnitudes), on samples away from poles."""
+    d = order2_example() if i is None else random_self_energy(order, (0, order, i))
+    beta, t, mu = 5.0, 1.0, 0.1
+    n_e = 500
+    k = k_samples(n_e, d.n_int, seed=(21, order))
+    q = np.array(DEFAULT_Q)
+    w = matsubara_freqs(1, beta)
+    terms = oracle_terms(d)
+    keep = far_from_poles(terms, d.n_int, energies_from_k(d.alpha, k, q, t, mu), w)
+    k = np.ascontiguousarray(k[keep])
+    n_e = len(keep)
+    cot = _cot(1, n_e, 2)
+    T = amd.Terms.from_diagram(d)
+    g_k, g_mu, g_t, g_b, g_w = amd.evaluate_hubbard_adjoint(
+        T, torch.from_numpy(k).to(DEV), q, t, mu, torch.from_numpy(w).to(DEV), beta,
+        grad_out=torch.from_numpy(cot).to(DEV))
+    torch.cuda.synchronize()
+    E = energies_from_k(d.alpha, k, q, t, mu)
+    dE, db, dw = gradients(terms, d.n_int, E, w, beta, cot)
+    dk, dmu, dt = momentum_gradients(d.alpha, k, q, t, mu, dE)
+    sc = gradient_scales(terms, d.n_int, E, w, beta, cot, hubbard=(d.alpha, k, q, t, mu))
+    err_k = np.abs(g_k.cpu().numpy() - dk.astype(np.float64)) / np.maximum(sc["k"], 1e-300)
+    assert err_k.max() <= 1e-10
+    for got, ref, name in ((g_mu, dmu, "mu"), (g_t, dt, "t"), (g_b, db, "beta")):
+        assert abs(float(got) - float(ref)) <= 1e-10 * sc[name], name
+    assert np.max(np.abs(g_w.cpu().numpy() - dw.astype(np.complex128))) <= 1e-10 * sc["w"]
+
+
+def test_adjoint_matches_finite_differences_of_forward():
+    """Central differences (h = 1e-6, float64) of the HIP forward row sum with
+    respect to mu, t, beta and a real frequency, against the HIP adjoint."""
+    d = random_self_energy(4, (0, 4, 1))
+    beta, t, mu = 5.0, 1.0, 0.05
+    q = np.array(DEFAULT_Q)
+    omega, gamma = 0.7, 0.05
+    kh = k_samples(20000, d.n_int, seed=22)
+    # keep samples whose single-term poles are far away: central differences
+    # need the third derivative to stay moderate within +-h
+    keep = far_from_poles(oracle_terms(d), d.n_int, energies_from_k(d.alpha, kh, q, t, mu),
+                          np.array([omega + 1j * gamma]), near=1e-2)
+    k = torch.from_numpy(np.ascontiguousarray(kh[keep])).to(DEV)
+    n_e = len(keep)
+    T = amd.Terms.from_diagram(d)
+
+    def loss(tt, mm, bb, om):
+        w = torch.tensor([om + 1j * gamma], dtype=torch.complex128, device=DEV)
+        _, s = amd.evaluate_hubbard(T, k, q, tt, mm, w, bb, want_out=False, want_sum=True)
+        return float(s.real.sum().item())
+
+    w = torch.tensor([omega + 1j * gamma], dtype=torch.complex128, device=DEV)
+    gs = torch.ones(1, dtype=torch.complex128, device=DEV)
+    _, g_mu, g_t, g_b, g_w = amd.evaluate_hubbard_adjoint(T, k, q, t, mu, w, beta, grad_sum=gs)
+    h = 1e-6
+    checks = [
+        (float(g_mu), (loss(t, mu + h, beta, omega) - loss(t, mu - h, beta, omega)) / (2 * h)),
+        (float(g_t), (loss(t + h, mu, beta, omega) - loss(t - h, mu, beta, omega)) / (2 * h)),
+        (float(g_b), (loss(t, mu, beta + h, omega) - loss(t, mu, beta - h, omega)) / (2 * h)),
+        (float(g_w[0, 0].real), (loss(t, mu, beta, omega + h) - loss(t, mu, beta, omega - h)) / (2 * h)),
+    ]
+    for got, fd in checks:
+        assert abs(got - fd) <= 1e-7 * max(abs(fd), 1e-3 * n_e), (got, fd)
+
+
+def test_autograd_function_gradcheck():
+    from paper_2311_17189_amd.autograd import AmiHubbard
+    d = order2_example()
+    T = amd.Terms.from_diagram(d)
+    k = torch.from_numpy(k_samples(5, 2, seed=23)).to(DEV).requires_grad_(True)
+    q = np.array(DEFAULT_Q)
+    t = torch.tensor(1.0, dtype=torch.float64, device=DEV, requires_grad=True)
+    mu = torch.tensor(0.2, dtype=torch.float64, device=DEV, requires_grad=True)
+    beta = torch.tensor(3.0, dtype=torch.float64, device=DEV, requires_grad=True)
+    w = torch.tensor([[0.4 + 0.3j], [1j * np.pi / 3.0]], dtype=torch.complex128, device=DEV,
+                     requires_grad=True)
+
+    def f(k_, t_, mu_, w_, b_):
+        out, s = AmiHubbard.apply(T, k_, q, t_, mu_, w_, b_)
+        return out, s
+
+    assert torch.autograd.gradcheck(f, (k, t, mu, w, beta), eps=1e-6, atol=1e-6, rtol=1e-5)
+
+
+def test_autograd_energy_function():
+    from paper_2311_17189_amd.autograd import AmiEvaluate
+    d = random_self_energy(3, (0, 3, 1))
+    T = amd.Terms.from_diagram(d)
+    E = torch.from_numpy(uniform_energies(6, d.n_eps, seed=24, a=2.0)).to(DEV).requires_grad_(True)
+    w = torch.tensor([[1j * np.pi / 2.0]], dtype=torch.complex128, device=DEV, requires_grad=True)
+    beta = torch.tensor(2.0, dtype=torch.float64, device=DEV, requires_grad=True)
+    assert torch.autograd.gradcheck(lambda e, ww, b: AmiEvaluate.apply(T, e, ww, b), (E, w, beta),
+                                    eps=1e-6, atol=1e-6, rtol=1e-5)
+
+
+def test_adjoint_deterministic_and_sum_cotangent():
+    d = random_self_energy(4, (0, 4, 2))
+    beta = 5.0
+    n_e = 3000
+    E = torch.from_numpy(uniform_energies(n_e, d.n_eps, seed=25, a=4.0)).to(DEV)
+    w = torch.from_numpy(matsubara_freqs(2, beta)).to(DEV)
+    T = amd.Terms.from_diagram(d)
+    gs = torch.tensor([1.0 + 0.5j, -0.25j], dtype=torch.complex128, device=DEV)
+    a = amd.evaluate_adjoint(T, E, w, beta, grad_sum=gs)
+    b = amd.evaluate_adjoint(T, E, w, beta, grad_sum=gs)
+    # the row-sum cotangent equals a broadcast per-sample cotangent
+    c = amd.evaluate_adjoint(T, E, w, beta, grad_out=gs[:, None].expand(2, n_e).contiguous())
+    torch.cuda.synchronize()
+    for x, y in zip(a, b):
+        assert torch.equal(x, y)
+    for x, y in zip(a, c):
+        assert torch.allclose(x, y, rtol=1e-13, atol=0)
+
+
+def test_packed_and_plain_kernels_agree():
+    """The specialized evaluator and the plain double-table one both meet the
+    parity bar against the oracle on the same inputs."""
+    for order, i in ((3, 0), (4, 1), (5, 2), (6, 1)):
+        d = random_self_energy(order, (0, order, i))
+        beta = 5.0
+        n_e = 777 if order < 6 else 200
+        Eh = uniform_energies(n_e, d.n_eps, seed=(26, order), a=4.0)
+        wh = np.concatenate([matsubara_freqs(2, beta), real_freqs(2, -3, 3, 0.05)])
+        E = torch.from_numpy(Eh).to(DEV)
+        w = torch.from_numpy(wh).to(DEV)
+        T = amd.Terms.from_diagram(d)
+        o1, _ = amd.evaluate(T, E, w, beta)
+        v1 = amd.last_variant()
+        T.set_variant(1)
+        o2, _ = amd.evaluate(T, E, w, beta)
+        v2 = amd.last_variant()
+        torch.cuda.synchronize()
+        assert v1.startswith("self-energy") and v2 == "double tables"
+        ref, scale, dist = reference(d, Eh, wh, beta)
+        check(o1.cpu().numpy(), ref, scale, dist, label=f"packed order {order}")
+        check(o2.cpu().numpy(), ref, scale, dist, label=f"plain order {order}")
+
+
+def test_adjoint_empty_batch():
+    d = order2_example()
+    T = amd.Terms.from_diagram(d)
+    E = torch.zeros((0, 3), dtype=torch.float64, device=DEV)
+    w = torch.from_numpy(matsubara_freqs(1, 2.0)).to(DEV)
+    g_e, g_b, g_w = amd.evaluate_adjoint(T, E, w, 2.0, grad_sum=torch.ones(1, dtype=torch.complex128,
+                                                                            device=DEV))
+    torch.cuda.synchronize()
+    assert g_e.shape == (0, 3) and float(g_b) == 0.0 and torch.all(g_w == 0)

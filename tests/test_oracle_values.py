@@ -270,13 +270,13 @@ def test_momentum_gradients_match_finite_differences():
     w = matsubara_freqs(1, beta)
     cot = np.array([[1.0 + 0.5j, -0.3 + 0.2j]])
 
-    def loss(kk, m):
-        E = energies_from_k(d.alpha, kk, q, t, m)
+    def loss(kk, m, tt=t):
+        E = energies_from_k(d.alpha, kk, q, tt, m)
         return _loss(terms, 2, E, w, beta, cot)
 
     E = energies_from_k(d.alpha, k, q, t, mu)
     dE, _, _ = gradients(terms, 2, E, w, beta, cot)
-    dk, dmu = momentum_gradients(d.alpha, k, q, t, mu, dE)
+    dk, dmu, dt = momentum_gradients(d.alpha, k, q, t, mu, dE)
     h = LD(1e-6)
     for s in range(2):
         for c in range(4):
@@ -287,3 +287,5 @@ def test_momentum_gradients_match_finite_differences():
             assert abs(float(dk[s, c]) - fd) <= 1e-8 * max(1.0, abs(fd))
     fd = (loss(k, mu + h) - loss(k, mu - h)) / (2 * h)
     assert abs(float(dmu) - fd) <= 1e-8 * max(1.0, abs(fd))
+    fd = (loss(k, mu, t + h) - loss(k, mu, t - h)) / (2 * h)
+    assert abs(float(dt) - fd) <= 1e-8 * max(1.0, abs(fd))
