@@ -43,6 +43,9 @@ def parse():
     ap.add_argument("--beta", type=float, default=5.0)
     ap.add_argument("--cpu-seconds", type=float, default=15.0,
                     help="target duration of the oracle CPU baseline (0 disables it)")
+    ap.add_argument("--no-batch", action="store_true",
+                    help="skip the persistent mixed-diagram batch section")
+    ap.add_argument("--batch-n-e", type=int, default=200_000)
     ap.add_argument("--copy-mib", type=int, default=0,
                     help="first copy a buffer of this many MiB device to device (a plain copy "
                          "kernel of known size, to scale hardware byte counters)")
@@ -84,6 +87,109 @@ def _oracle_chunk(args):
     terms, d, k, q, beta, t, mu, w = args
     E = energies_from_k(d.alpha, k, q, t, mu, dtype=np.float64)
     return evaluate_terms(terms, d.n_int, E, w, beta, dtype=np.float64)
+
+
+def kernel_source_hash() -> str:
+    """sha256 over the HIP/C++ sources of the library: hardware byte counters
+    recorded for one build are reported only while the sources are unchanged."""
+    import hashlib
+    csrc = os.path.join(ROOT, "paper_2311_17189_amd", "csrc")
+    h = hashlib.sha256()
+    for name in sorted(os.listdir(csrc)):
+        if name.endswith((".hip", ".hpp", ".cpp")):
+            with open(os.path.join(csrc, name), "rb") as fh:
+                h.update(name.encode())
+                h.update(fh.read())
+    return h.hexdigest()
+
+
+def recorded_traffic(kernel: str, workload: str):
+    """HBM bytes per launch of `kernel` on `workload` from the committed
+    rocprofv3 counter summary (profiles/traffic.json), or None when absent or
+    taken on other kernel sources."""
+    path = os.path.join(ROOT, "profiles", "traffic.json")
+    if not os.path.exists(path):
+        return None
+    with open(path) as fh:
+        rec = json.load(fh)
+    if rec.get("source_sha256") != kernel_source_hash():
+        return None
+    entry = rec.get("kernels", {}).get(kernel, {}).get(workload)
+    if not entry:
+        return None
+    return entry["fetch_bytes"] + entry["write_bytes"]
+
+
+def batch_section(args, torch, dev):
+    """Persistent mixed batch: 64 seeded diagrams of orders 2-6 (13/13/13/13/12),
+    16 external Matsubara frequencies and N samples each, one graph launch with
+    an autotuned tiling, against 64 separate launches of the packed and of the
+    plain kernel."""
+    import numpy as np
+
+    import paper_2311_17189_amd as amd
+    from ami_inputs import DEFAULT_Q, k_samples, matsubara_freqs, random_self_energy
+    from paper_2311_17189_amd.autotune import autotune, time_batch
+
+    orders = [2] * 13 + [3] * 13 + [4] * 13 + [5] * 13 + [6] * 12
+    beta, n_f, n_e = 5.0, 16, args.batch_n_e
+    w = torch.from_numpy(matsubara_freqs(n_f, beta)).to(dev)
+    items, seen = [], {}
+    for order in orders:
+        i = seen.get(order, 0)
+        seen[order] = i + 1
+        d = random_self_energy(order, (5, order, i))
+        T = amd.Terms.from_diagram(d)
+        k = torch.from_numpy(k_samples(n_e, d.n_int, seed=(200, order, i))).to(dev)
+        items.append({"terms": T, "k": k, "q": list(DEFAULT_Q), "t": 1.0, "mu": 0.0, "ext_freqs": w,
+                      "beta": beta,
+                      "out": torch.empty((n_f, n_e), dtype=torch.complex128, device=dev),
+                      "out_sum": torch.empty((n_f,), dtype=torch.complex128, device=dev)})
+    term_counts = [it["terms"].info()["T"] for it in items]
+    te = float(sum(term_counts)) * n_e * n_f
+    t0 = time.perf_counter()
+    best, timings = autotune(items, reps=3)
+    tune_s = time.perf_counter() - t0
+    b = amd.Batch(items, best)
+    batch_ms = time_batch(b, reps=5)
+    info = b.info()
+    stream = torch.cuda.current_stream()
+
+    def separate():
+        for it in items:
+            amd.evaluate_hubbard(it["terms"], it["k"], it["q"], it["t"], it["mu"], w, beta,
+                                 want_sum=True, out=it["out"], out_sum=it["out_sum"], stream=stream)
+
+    def timed(fn, reps=3):
+        fn()
+        torch.cuda.synchronize()
+        ts = []
+        for _ in range(reps):
+            a0 = torch.cuda.Event(enable_timing=True)
+            a1 = torch.cuda.Event(enable_timing=True)
+            a0.record(stream)
+            fn()
+            a1.record(stream)
+            torch.cuda.synchronize()
+            ts.append(a0.elapsed_time(a1))
+        return sorted(ts)[len(ts) // 2]
+
+    sep_ms = timed(separate)
+    for it in items:
+        it["terms"].set_variant(1)
+    plain_ms = timed(separate)
+    for it in items:
+        it["terms"].set_variant(0)
+    return {
+        "workload": f"64 seeded self-energy diagrams, orders 2-6 (13/13/13/13/12), {n_f} Matsubara "
+                    f"frequencies, {n_e} k-samples each, beta={beta}, out[N_F,N_E] + row sums",
+        "terms_min": min(term_counts), "terms_max": max(term_counts), "terms_total": sum(term_counts),
+        "term_evals": te,
+        "batch_ms": batch_ms, "batch_term_evals_per_s": te / (batch_ms * 1e-3),
+        "separate_packed_ms": sep_ms, "separate_packed_term_evals_per_s": te / (sep_ms * 1e-3),
+        "separate_plain_ms": plain_ms, "separate_plain_term_evals_per_s": te / (plain_ms * 1e-3),
+        "tuning": best, "tuning_candidates": len(timings), "tuning_s": tune_s, "info": info,
+    }
 
 
 def main():
@@ -193,10 +299,14 @@ def main():
     fl = rl.forward_flops(st, n_e, n_f, d.alpha)
     fa = rl.adjoint_flops(st, n_e, n_f, d.alpha)
     if adj_ms >= fwd_ms:
-        dom, dom_ms, dom_fl = "ami_adj_packed (+ its reduction kernel)", adj_ms, fa["total"]
+        dom, dom_key, dom_ms, dom_fl = ("ami_adj_packed (+ its reduction kernel)", "ami_adj_packed",
+                                        adj_ms, fa["total"])
     else:
-        dom, dom_ms, dom_fl = "ami_fwd_packed (+ its row-sum kernel)", fwd_ms, fl["total"]
+        dom, dom_key, dom_ms, dom_fl = ("ami_fwd_packed (+ its row-sum kernel)", "ami_fwd_packed",
+                                        fwd_ms, fl["total"])
     achieved = dom_fl / (dom_ms * 1e-3)
+    workload_key = f"order{args.order}-diagram{args.diagram}-ne{n_e}-nf{n_f}-beta{args.beta:g}"
+    traffic = recorded_traffic(dom_key, workload_key)
 
     res = {
         "metric": METRIC,
@@ -220,6 +330,7 @@ def main():
             "distinct_denominators": info["D"], "groups": info["G"], "n_e": n_e, "n_f": n_f,
             "beta": args.beta, "t": hop_t, "mu": mu, "q": [float(x) for x in q],
             "diagram_seed": [0, args.order, args.diagram],
+            "key": workload_key,
         },
         "fwd": {"ms": fwd_ms, "term_evals_per_s": te / (fwd_ms * 1e-3), "kernel": fwd_variant,
                 "flops": fl["total"], "tflops": fl["total"] / (fwd_ms * 1e-3) / 1e12},
@@ -235,7 +346,8 @@ def main():
             "peak": rl.PEAK_FP64_VECTOR / 1e12,
             "unit": "TFLOP/s",
             "frac": achieved / rl.PEAK_FP64_VECTOR,
-            "traffic": None,
+            "traffic": traffic,
+            "traffic_unit": "bytes per launch (rocprofv3 FETCH_SIZE + WRITE_SIZE, copy-scaled)",
             "kernel": dom,
             "flops_per_launch": dom_fl,
             "kernel_ms": dom_ms,
@@ -243,6 +355,8 @@ def main():
         "construct_ms": construct_ms,
         "wall_s": wall,
     }
+    if not args.no_batch:
+        res["batch"] = batch_section(args, torch, dev)
     if args.cpu_seconds > 0:
         res["cpu_baseline"] = cpu_baseline(d, k_host, q, args.beta, hop_t, mu, w_host,
                                            args.cpu_seconds)

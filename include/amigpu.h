@@ -207,6 +207,70 @@ AmiStatus amiSetVariant(AmiTerms *terms, int32_t variant);
 /* Name of the kernel variant launched by the last evaluate call on this thread. */
 const char *amiLastVariant(void);
 
+/*
+ * Persistent mixed-diagram batch (one HIP graph launch over many diagrams).
+ *
+ * Each item is one diagram with its own samples, frequency rows and outputs,
+ * exactly as one amiEvaluateHubbard call (k != NULL) or amiEvaluate call
+ * (energies != NULL); all items of a batch use the same one of the two paths.
+ * Pointers are device pointers on the current device and are baked into the
+ * batch at creation: the batch evaluates whatever those buffers hold when it
+ * runs.  Every item needs the packed form of its solution (see
+ * amiEvaluateAdjoint).
+ */
+typedef struct AmiBatch AmiBatch;
+
+typedef struct {
+    AmiTerms *terms;
+    const double *energies;      /* energy path: as amiEvaluate, or NULL       */
+    int64_t stride_s, stride_i;
+    const double *k;             /* momentum path: as amiEvaluateHubbard, or NULL */
+    int64_t stride_k;
+    double q[8];                 /* external momenta (2 per external slot)     */
+    double t, mu;
+    int64_t n_e;                 /* samples (>= 1)                              */
+    const double *ext_freqs;     /* complex128 [n_f][n_ext]                     */
+    int64_t n_f;
+    double beta, e_reg;
+    double *out;                 /* complex128 [n_f][n_e] or NULL               */
+    double *out_sum;             /* complex128 [n_f] or NULL (not both NULL)    */
+} AmiBatchItem;
+
+/* Tuning of a batch (chosen by the autotuner of the Python package):
+ *   block        lanes per work-item tile: 64, 128, 256, or 0 for the choice
+ *                amiEvaluate makes for the largest item
+ *   waves_per_cu resident waves per compute unit of the persistent grid, 1..32
+ *   tile_factor  each work item costs about tile_factor times the most
+ *                expensive single tile of the batch, 1..1024 */
+typedef struct {
+    int32_t block;
+    int32_t waves_per_cu;
+    int32_t tile_factor;
+    int32_t reserved;
+} AmiBatchTuning;
+
+/*
+ * amiBatchCreate -- build the work list (a diagram's sample tiles grouped into
+ * items of similar cost, queued from most to least expensive), upload it with
+ * the item descriptors, allocate the row-sum workspace, and instantiate the
+ * graph (counter reset -> persistent kernel -> fixed-order row sums).  All
+ * allocation happens here.  tuning may be NULL (defaults {0, 8, 1, 0}).
+ * Every output equals the corresponding per-diagram evaluate call's bit for
+ * bit when the block size matches the one that call uses.
+ */
+AmiStatus amiBatchCreate(const AmiBatchItem *items, int32_t n_items, const AmiBatchTuning *tuning,
+                         AmiBatch **out);
+
+/* Launch the batch graph on hip_stream (asynchronous; allocates nothing). */
+AmiStatus amiBatchRun(AmiBatch *batch, void *hip_stream);
+
+/* info[0..7]: items, work items, grid blocks, block lanes, LDS bytes per block,
+ * row-sum columns, momentum path (1) or energy path (0), reserved. */
+AmiStatus amiBatchInfo(const AmiBatch *batch, int64_t info[8]);
+
+/* Release a batch (its device workspace and graph). */
+void amiBatchFree(AmiBatch *batch);
+
 /* Message of the last failed call on this thread ("" if none). */
 const char *amiLastError(void);
 

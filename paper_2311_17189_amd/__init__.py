@@ -10,10 +10,10 @@ The library must have been built (``paper_2311_17189_amd.build.build()`` or
 ``__graft_entry__.build()``); the first call into it raises ImportError
 otherwise (there is no fallback path).
 """
-from ._lib import (AmiError, Terms, evaluate, evaluate_adjoint,  # noqa: F401
+from ._lib import (AmiError, Batch, Terms, evaluate, evaluate_adjoint,  # noqa: F401
                    evaluate_hubbard, evaluate_hubbard_adjoint, last_variant,
                    lib_path, load_library, version)
 
-__all__ = ["AmiError", "Terms", "evaluate", "evaluate_adjoint", "evaluate_hubbard",
+__all__ = ["AmiError", "Batch", "Terms", "evaluate", "evaluate_adjoint", "evaluate_hubbard",
            "evaluate_hubbard_adjoint", "last_variant", "lib_path", "load_library",
            "version"]

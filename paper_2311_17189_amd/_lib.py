@@ -35,6 +35,23 @@ class AmiError(RuntimeError):
 _lib = None
 
 
+class AmiBatchItem(ctypes.Structure):
+    """Mirror of the C struct AmiBatchItem (include/amigpu.h)."""
+    _fields_ = [("terms", ctypes.c_void_p), ("energies", ctypes.c_void_p),
+                ("stride_s", ctypes.c_int64), ("stride_i", ctypes.c_int64),
+                ("k", ctypes.c_void_p), ("stride_k", ctypes.c_int64),
+                ("q", ctypes.c_double * 8), ("t", ctypes.c_double), ("mu", ctypes.c_double),
+                ("n_e", ctypes.c_int64), ("ext_freqs", ctypes.c_void_p), ("n_f", ctypes.c_int64),
+                ("beta", ctypes.c_double), ("e_reg", ctypes.c_double),
+                ("out", ctypes.c_void_p), ("out_sum", ctypes.c_void_p)]
+
+
+class AmiBatchTuning(ctypes.Structure):
+    """Mirror of the C struct AmiBatchTuning."""
+    _fields_ = [("block", ctypes.c_int32), ("waves_per_cu", ctypes.c_int32),
+                ("tile_factor", ctypes.c_int32), ("reserved", ctypes.c_int32)]
+
+
 def lib_path() -> str:
     return os.path.join(_HERE, _LIB_NAME)
 
@@ -75,6 +92,15 @@ def load_library():
     lib.amiSetVariant.restype = c_i32
     lib.amiLastVariant.argtypes = []
     lib.amiLastVariant.restype = ctypes.c_char_p
+    lib.amiBatchCreate.argtypes = [ctypes.POINTER(AmiBatchItem), c_i32, ctypes.POINTER(AmiBatchTuning),
+                                   ctypes.POINTER(vp)]
+    lib.amiBatchCreate.restype = c_i32
+    lib.amiBatchRun.argtypes = [vp, vp]
+    lib.amiBatchRun.restype = c_i32
+    lib.amiBatchInfo.argtypes = [vp, vp]
+    lib.amiBatchInfo.restype = c_i32
+    lib.amiBatchFree.argtypes = [vp]
+    lib.amiBatchFree.restype = None
     lib.amiLastError.argtypes = []
     lib.amiLastError.restype = ctypes.c_char_p
     lib.amiVersion.argtypes = []
@@ -321,3 +347,89 @@ def evaluate_hubbard_adjoint(terms: Terms, k, q, t: float, mu: float, ext_freqs,
         _ptr(go), _ptr(gs), g_k.data_ptr() if n_e else None, base, base + 8, base + 16,
         g_w.data_ptr(), _stream_ptr(stream)))
     return g_k, scal[0], scal[1], scal[2], g_w
+
+
+class Batch:
+    """Persistent mixed-diagram batch (``amiBatchCreate`` / ``amiBatchRun``).
+
+    ``items`` is a list of dicts, one per diagram, each with ``terms``
+    (:class:`Terms`), either ``k`` (float64 CUDA [N_E, 2 n_int], momentum path,
+    with ``q``, ``t``, ``mu``) or ``energies`` (float64 CUDA [N_E, nE]),
+    ``ext_freqs`` (complex128 CUDA [N_F, n_ext]), ``beta``, optional ``e_reg``,
+    and the outputs ``out`` (complex128 [N_F, N_E]) and/or ``out_sum``
+    (complex128 [N_F]).  The tensors are referenced by the batch; every
+    :meth:`run` evaluates what they hold.  ``tuning`` is a dict with ``block``,
+    ``waves_per_cu`` and ``tile_factor`` (see :mod:`.autotune`).
+    """
+
+    def __init__(self, items, tuning=None):
+        import torch
+        lib = load_library()
+        self._keep = []
+        arr = (AmiBatchItem * len(items))()
+        for i, it in enumerate(items):
+            c = arr[i]
+            t = it["terms"]
+            c.terms = t.handle
+            w = _freqs(it["ext_freqs"], t)
+            n_f = w.shape[0]
+            if "k" in it and it["k"] is not None:
+                k = it["k"]
+                if k.dtype != torch.float64 or not k.is_cuda or k.dim() != 2 or k.shape[1] != 2 * t.n_int \
+                        or k.stride(1) != 1:
+                    raise AmiError(-1, f"item {i}: k must be float64 CUDA [N_E, 2*n_int]")
+                c.k = k.data_ptr()
+                c.stride_k = k.stride(0)
+                n_e = k.shape[0]
+                qa = np.asarray(it.get("q", ()), dtype=np.float64).reshape(-1)
+                for j, v in enumerate(qa[:8]):
+                    c.q[j] = float(v)
+                c.t = float(it.get("t", 1.0))
+                c.mu = float(it.get("mu", 0.0))
+                self._keep.append(k)
+            else:
+                e = it["energies"]
+                if e.dtype != torch.float64 or not e.is_cuda or e.dim() != 2 or e.shape[1] != t.n_eps:
+                    raise AmiError(-1, f"item {i}: energies must be float64 CUDA [N_E, nE]")
+                c.energies = e.data_ptr()
+                c.stride_s, c.stride_i = e.stride()
+                n_e = e.shape[0]
+                self._keep.append(e)
+            c.n_e = n_e
+            c.ext_freqs = w.data_ptr()
+            c.n_f = n_f
+            c.beta = float(it["beta"])
+            c.e_reg = float(it.get("e_reg", 0.0))
+            out, out_sum = _outputs(n_f, n_e, w.device, False, False, it.get("out"), it.get("out_sum"))
+            c.out = out.data_ptr() if out is not None else None
+            c.out_sum = out_sum.data_ptr() if out_sum is not None else None
+            self._keep += [w, out, out_sum, t]
+        tun = None
+        if tuning is not None:
+            tun = AmiBatchTuning(int(tuning.get("block", 0)), int(tuning.get("waves_per_cu", 8)),
+                                 int(tuning.get("tile_factor", 1)), 0)
+        h = ctypes.c_void_p()
+        _check(lib.amiBatchCreate(arr, len(items), ctypes.byref(tun) if tun is not None else None,
+                                  ctypes.byref(h)))
+        self._h = h
+        self.tuning = dict(tuning) if tuning is not None else None
+
+    def run(self, stream=None):
+        _check(load_library().amiBatchRun(self._h, _stream_ptr(stream)))
+
+    def info(self) -> dict:
+        buf = np.zeros(8, dtype=np.int64)
+        _check(load_library().amiBatchInfo(self._h, buf.ctypes.data))
+        keys = ["items", "work_items", "grid", "block", "lds_bytes", "rowsum_columns", "momentum_path"]
+        return {k: int(buf[i]) for i, k in enumerate(keys)}
+
+    def close(self):
+        if getattr(self, "_h", None) is not None and self._h.value:
+            load_library().amiBatchFree(self._h)
+            self._h = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

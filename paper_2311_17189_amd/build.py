@@ -10,7 +10,7 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libamigpu.so")
 
-SOURCES = ["abi.cpp", "construct.cpp", "evaluate.hip"]
+SOURCES = ["abi.cpp", "construct.cpp", "evaluate.hip", "batch.hip"]
 
 HIPCC_FLAGS = [
     "--offload-arch=gfx950",

@@ -1,0 +1,449 @@
+// Persistent mixed-diagram batch: many diagrams of different order and term
+// count, each with its own samples and frequency rows, evaluated by one
+// persistent kernel launch that pulls (diagram, tile range) work items from a
+// queue, replayed as one HIP graph (reset counter -> persistent kernel ->
+// fixed-order row sums).
+//
+// Work items are built on the host: a diagram's sample tiles are grouped so
+// that every item costs about the same (a multiple, the tuning's tile factor,
+// of the most expensive single tile, estimated from the solution's table
+// sizes), and the items are queued from the most to the least expensive
+// (largest-first list scheduling).  Each item is evaluated by the same tile
+// function as the per-diagram kernel (fwd_tile), so every output value is
+// bitwise the one the per-diagram launch computes; the row sums are reduced
+// over the same tiles in the same order.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "ami_internal.hpp"
+#include "device_common.hpp"
+#include "kernels_packed.hpp"
+#include "runtime.hpp"
+
+namespace ami {
+
+namespace {
+
+// Shapes with their own instance in the batch kernel: self-energy order n
+// (2n-1 energies, n leaves and n-1 denominators per term), n = 1..7, then the
+// bounded generic instance (index 0).
+constexpr int kShapeGeneric = 0;
+
+struct BatchDesc {
+    KArgs a;
+    int32_t shape;
+    int32_t pad;
+};
+
+struct Work {
+    int32_t item;
+    int32_t ntiles;
+    int64_t tile0;
+};
+
+struct RowSumJob {
+    const double *partial;   // [nblocks][ncols] of one item
+    double *dst;             // one double of out_sum
+    int64_t nblocks;
+    int32_t ncols;
+    int32_t col;
+};
+
+typedef const __attribute__((address_space(4))) BatchDesc *cdesc;
+typedef const __attribute__((address_space(4))) Work *cwork;
+
+// ALL: every shape; otherwise self-energy orders 1..6 only (fewer registers,
+// chosen when every item of the batch has one of those shapes).
+template <bool HUB, bool ALL>
+__device__ __forceinline__ void run_item(const KArgs &a, int shape, int64_t tile0, int ntiles, double *sm) {
+    for (int64_t tile = tile0; tile < tile0 + ntiles; ++tile) {
+        switch (shape) {
+        case 1: fwd_tile<1, 1, 0, true, HUB>(a, tile, sm); break;
+        case 2: fwd_tile<3, 2, 1, true, HUB>(a, tile, sm); break;
+        case 3: fwd_tile<5, 3, 2, true, HUB>(a, tile, sm); break;
+        case 4: fwd_tile<7, 4, 3, true, HUB>(a, tile, sm); break;
+        case 5: fwd_tile<9, 5, 4, true, HUB>(a, tile, sm); break;
+        case 6: fwd_tile<11, 6, 5, true, HUB>(a, tile, sm); break;
+        default:
+            if constexpr (ALL) {
+                if (shape == 7) fwd_tile<13, 7, 6, true, HUB>(a, tile, sm);
+                else fwd_tile<16, 8, 8, false, HUB>(a, tile, sm);
+            }
+            break;
+        }
+        __syncthreads();   // the next tile reuses the LDS columns
+    }
+}
+
+// Every block takes work items from the counter until the queue is empty;
+// each block sees the counter pass n_work, so every wave exits.
+template <bool HUB, bool ALL>
+__global__ __launch_bounds__(256) void ami_batch_kernel(const BatchDesc *desc, const Work *work, int n_work,
+                                                        unsigned int *counter) {
+    extern __shared__ double sm[];
+    __shared__ int next;
+    cdesc cd = (cdesc)(desc);
+    cwork cw = (cwork)(work);
+    for (;;) {
+        if (threadIdx.x == 0) next = static_cast<int>(atomicAdd(counter, 1u));
+        __syncthreads();
+        const int wi = __builtin_amdgcn_readfirstlane(next);
+        __syncthreads();
+        if (wi >= n_work) break;
+        const int item = cw[wi].item;
+        const int ntiles = cw[wi].ntiles;
+        const int64_t tile0 = cw[wi].tile0;
+        // fields are read on demand through the constant address space
+        const KArgs &a = *(const KArgs *)((const void *)&cd[item].a);
+        run_item<HUB, ALL>(a, cd[item].shape, tile0, ntiles, sm);
+    }
+}
+
+__global__ void ami_batch_reset_kernel(unsigned int *counter) {
+    if (threadIdx.x == 0 && blockIdx.x == 0) *counter = 0u;
+}
+
+__global__ __launch_bounds__(256) void ami_batch_rowsum_kernel(const RowSumJob *jobs) {
+    __shared__ double sh[256];
+    const RowSumJob j = jobs[blockIdx.x];
+    const int tid = threadIdx.x;
+    double acc = 0.0;
+    for (int64_t b = tid; b < j.nblocks; b += 256) acc += j.partial[b * j.ncols + j.col];
+    sh[tid] = acc;
+    __syncthreads();
+    for (int w = 128; w >= 1; w >>= 1) {
+        if (tid < w) sh[tid] += sh[tid + w];
+        __syncthreads();
+    }
+    if (tid == 0) *j.dst = sh[0];
+}
+
+// Cost of one sample of an item: leaves and term products once, denominators
+// and group products per frequency row (relative units).
+double sample_cost(const AmiTerms *t, int64_t n_f) {
+    const Tables &tb = t->tab;
+    const double per_sample = 50.0 * tb.L + (t->n_int + 1.0) * tb.T + 44.0 * 2 * t->n_g;
+    const double per_point = 30.0 * tb.D + (6.0 * std::max(tb.dpt - 1, 0) + 4.0) * tb.G;
+    return per_sample + per_point * static_cast<double>(n_f);
+}
+
+int shape_of(const AmiTerms *t, bool hub) {
+    const int ne = t->n_eps, ni = t->n_int, dpt = t->tab.dpt;
+    const bool se = (ne == 2 * ni - 1) && (dpt == ni - 1) && (!hub || t->n_g == ne);
+    return (se && ni >= 1 && ni <= 7) ? ni : kShapeGeneric;
+}
+
+}  // namespace
+
+}  // namespace ami
+
+struct AmiBatch {
+    int device = -1;
+    bool hub = false;
+    int n_items = 0;
+    int block = 0;
+    int grid = 0;
+    size_t lds = 0;
+    int64_t n_work = 0;
+    int64_t n_jobs = 0;
+    void *blob = nullptr;                  // descriptors, work list, jobs, counter, partial sums
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+};
+
+namespace ami {
+namespace {
+
+AmiStatus batch_fail_free(AmiBatch *b, AmiStatus st) {
+    if (b->exec) (void)hipGraphExecDestroy(b->exec);
+    if (b->graph) (void)hipGraphDestroy(b->graph);
+    if (b->blob) (void)hipFree(b->blob);
+    delete b;
+    return st;
+}
+
+}  // namespace
+}  // namespace ami
+
+extern "C" {
+
+AmiStatus amiBatchCreate(const AmiBatchItem *items, int32_t n_items, const AmiBatchTuning *tuning,
+                         AmiBatch **out) {
+    using namespace ami;
+    clear_error();
+    if (!out) return fail(AMI_E_ARG, "out is NULL");
+    *out = nullptr;
+    if (!items || n_items < 1) return fail(AMI_E_ARG, "no items");
+    AmiBatchTuning tun = {0, 8, 1, 0};
+    if (tuning) tun = *tuning;
+    if (tun.waves_per_cu < 1 || tun.waves_per_cu > 32) return fail(AMI_E_ARG, "waves_per_cu must be in 1..32");
+    if (tun.tile_factor < 1 || tun.tile_factor > 1024) return fail(AMI_E_ARG, "tile_factor must be in 1..1024");
+    if (tun.block != 0 && tun.block != 64 && tun.block != 128 && tun.block != 256)
+        return fail(AMI_E_ARG, "block must be 0 (automatic), 64, 128 or 256");
+    const bool hub = items[0].k != nullptr;
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return hip_fail(e, "hipGetDevice");
+
+    // per-item checks and descriptors
+    std::vector<BatchDesc> desc(n_items);
+    int max_slots = 0;
+    for (int i = 0; i < n_items; ++i) {
+        const AmiBatchItem &it = items[i];
+        AmiTerms *t = it.terms;
+        if (!t) return fail(AMI_E_ARG, "item " + std::to_string(i) + ": terms is NULL");
+        if ((it.k != nullptr) != hub)
+            return fail(AMI_E_ARG, "all items must use the same path (momenta or energies)");
+        if (!t->tab.packable) return fail(AMI_E_UNSUPPORTED, "item " + std::to_string(i) + ": not in packed form");
+        if (t->n_eps > kMaxEpsDev || t->n_ext > kMaxExt) return fail(AMI_E_UNSUPPORTED, "item shape too large");
+        if (it.n_e < 1) return fail(AMI_E_ARG, "item " + std::to_string(i) + ": n_e must be >= 1");
+        if (it.n_f < 1 || it.n_f > (1 << 24)) return fail(AMI_E_ARG, "n_f must be in 1..2^24");
+        if (!(it.beta > 0.0)) return fail(AMI_E_ARG, "beta must be > 0");
+        if (!it.out && !it.out_sum) return fail(AMI_E_ARG, "item " + std::to_string(i) + ": no output");
+        if (t->n_ext > 0 && !it.ext_freqs) return fail(AMI_E_ARG, "ext_freqs is NULL");
+        if (hub) {
+            if (t->n_eps != t->n_g) return fail(AMI_E_ARG, "the momentum path needs one energy per propagator");
+            if (it.stride_k < 2 * t->n_int) return fail(AMI_E_ARG, "stride_k < 2*n_int");
+        } else {
+            if (!it.energies || it.stride_s < 1 || it.stride_i < 1) return fail(AMI_E_ARG, "bad energies");
+        }
+        DeviceTables *dt = nullptr;
+        AmiStatus st = upload(t, &dt);
+        if (st != AMI_OK) return st;
+        BatchDesc &d = desc[i];
+        std::memset(&d, 0, sizeof(d));
+        d.a.tb = packed_tabs(t, dt);
+        d.a.energies = it.energies;
+        d.a.stride_s = it.stride_s;
+        d.a.stride_i = it.stride_i;
+        d.a.k = it.k;
+        d.a.stride_k = it.stride_k;
+        for (int x = 0; x < t->n_ext && x < kMaxExtDev; ++x) {
+            d.a.q[2 * x] = it.q[2 * x];
+            d.a.q[2 * x + 1] = it.q[2 * x + 1];
+            if (!(std::abs(it.q[2 * x]) <= 1e4) || !(std::abs(it.q[2 * x + 1]) <= 1e4)) d.a.q_big = 1;
+        }
+        d.a.hop_t = it.t;
+        d.a.mu = it.mu;
+        d.a.ext_freqs = it.ext_freqs;
+        d.a.n_f = static_cast<int>(it.n_f);
+        d.a.beta = it.beta;
+        d.a.e_reg = it.e_reg;
+        d.a.n_e = it.n_e;
+        d.a.out = it.out;
+        d.shape = shape_of(t, hub);
+        max_slots = std::max(max_slots, fwd_slots(t->tab));
+    }
+    // one block size for the whole batch (LDS sized for the largest item)
+    LaunchShape ls;
+    AmiStatus st = pick_shape(max_slots, ls);
+    if (st != AMI_OK) return st;
+    if (tun.block != 0) {
+        int max_lds = 0;
+        e = hipDeviceGetAttribute(&max_lds, hipDeviceAttributeMaxSharedMemoryPerBlock, dev);
+        if (e != hipSuccess) return hip_fail(e, "hipDeviceGetAttribute");
+        const size_t lds = static_cast<size_t>(max_slots) * sizeof(double) * tun.block +
+                           2 * sizeof(double) * (tun.block / 64);
+        if (lds > static_cast<size_t>(max_lds)) return fail(AMI_E_UNSUPPORTED, "tuning block too large for LDS");
+        ls.block = tun.block;
+        ls.lds = lds;
+    }
+    {
+        int max_lds = 0;
+        e = hipDeviceGetAttribute(&max_lds, hipDeviceAttributeMaxSharedMemoryPerBlock, dev);
+        if (e != hipSuccess) return hip_fail(e, "hipDeviceGetAttribute");
+        if (ls.lds + 64 > static_cast<size_t>(max_lds))     // the kernel's own queue slot
+            return fail(AMI_E_UNSUPPORTED, "batch items too large for the LDS of one block");
+    }
+    for (auto &d : desc) d.a.slots = max_slots;
+
+    // work items and row-sum jobs
+    std::vector<double> tile_cost(n_items);
+    std::vector<int64_t> tiles(n_items);
+    double max_tile = 0.0;
+    for (int i = 0; i < n_items; ++i) {
+        tiles[i] = (items[i].n_e + ls.block - 1) / ls.block;
+        tile_cost[i] = sample_cost(items[i].terms, items[i].n_f) * ls.block;
+        max_tile = std::max(max_tile, tile_cost[i]);
+    }
+    const double target = max_tile * tun.tile_factor;
+    struct HostWork {
+        Work w;
+        double cost;
+    };
+    std::vector<HostWork> hw;
+    size_t partial_total = 0;
+    std::vector<size_t> partial_off(n_items, 0);
+    std::vector<RowSumJob> jobs;
+    for (int i = 0; i < n_items; ++i) {
+        const int64_t per = std::max<int64_t>(1, static_cast<int64_t>(target / tile_cost[i]));
+        for (int64_t t0 = 0; t0 < tiles[i]; t0 += per) {
+            HostWork h;
+            h.w.item = i;
+            h.w.tile0 = t0;
+            h.w.ntiles = static_cast<int32_t>(std::min<int64_t>(per, tiles[i] - t0));
+            h.cost = tile_cost[i] * h.w.ntiles;
+            hw.push_back(h);
+        }
+        if (items[i].out_sum) {
+            partial_off[i] = partial_total;
+            partial_total += static_cast<size_t>(tiles[i]) * items[i].n_f * 2;
+        }
+    }
+    std::stable_sort(hw.begin(), hw.end(), [](const HostWork &x, const HostWork &y) { return x.cost > y.cost; });
+    if (hw.size() > 0x7fffffffu - 65536u) return fail(AMI_E_ARG, "too many work items");
+
+    // one device allocation: descriptors | work | jobs | counter | partials
+    const size_t sz_desc = sizeof(BatchDesc) * n_items;
+    const size_t off_work = (sz_desc + 255) & ~size_t(255);
+    const size_t sz_work = sizeof(Work) * hw.size();
+    const size_t off_jobs = (off_work + sz_work + 255) & ~size_t(255);
+    size_t n_jobs = 0;
+    for (int i = 0; i < n_items; ++i)
+        if (items[i].out_sum) n_jobs += 2 * static_cast<size_t>(items[i].n_f);
+    const size_t sz_jobs = sizeof(RowSumJob) * std::max<size_t>(n_jobs, 1);
+    const size_t off_ctr = (off_jobs + sz_jobs + 255) & ~size_t(255);
+    const size_t off_part = off_ctr + 256;
+    const size_t total = off_part + sizeof(double) * std::max<size_t>(partial_total, 1);
+
+    AmiBatch *b = new (std::nothrow) AmiBatch();
+    if (!b) return fail(AMI_E_OOM, "out of host memory");
+    b->device = dev;
+    b->hub = hub;
+    b->n_items = n_items;
+    b->block = ls.block;
+    b->lds = ls.lds;
+    b->n_work = static_cast<int64_t>(hw.size());
+    b->n_jobs = static_cast<int64_t>(n_jobs);
+    int n_cu = 0;
+    e = hipDeviceGetAttribute(&n_cu, hipDeviceAttributeMultiprocessorCount, dev);
+    if (e != hipSuccess) return batch_fail_free(b, hip_fail(e, "hipDeviceGetAttribute"));
+    const int waves_per_block = ls.block / 64;
+    b->grid = std::max(1, n_cu * tun.waves_per_cu / waves_per_block);
+    b->grid = static_cast<int>(std::min<int64_t>(b->grid, b->n_work));
+    e = hipMalloc(&b->blob, total);
+    if (e != hipSuccess) return batch_fail_free(b, fail(AMI_E_OOM, "batch workspace"));
+    unsigned char *base = static_cast<unsigned char *>(b->blob);
+    double *partial = reinterpret_cast<double *>(base + off_part);
+    for (int i = 0; i < n_items; ++i) {
+        desc[i].a.partial = items[i].out_sum ? partial + partial_off[i] : nullptr;
+        if (items[i].out_sum)
+            for (int c = 0; c < 2 * items[i].n_f; ++c) {
+                RowSumJob j;
+                j.partial = partial + partial_off[i];
+                j.dst = items[i].out_sum + c;
+                j.nblocks = tiles[i];
+                j.ncols = static_cast<int32_t>(2 * items[i].n_f);
+                j.col = c;
+                jobs.push_back(j);
+            }
+    }
+    std::vector<Work> wl(hw.size());
+    for (size_t i = 0; i < hw.size(); ++i) wl[i] = hw[i].w;
+    std::vector<unsigned char> host(off_part, 0);
+    std::memcpy(host.data(), desc.data(), sz_desc);
+    std::memcpy(host.data() + off_work, wl.data(), sz_work);
+    if (!jobs.empty()) std::memcpy(host.data() + off_jobs, jobs.data(), sizeof(RowSumJob) * jobs.size());
+    e = hipMemcpy(b->blob, host.data(), off_part, hipMemcpyHostToDevice);
+    if (e != hipSuccess) return batch_fail_free(b, hip_fail(e, "batch upload"));
+
+    // graph: reset counter -> persistent kernel -> row sums
+    const BatchDesc *d_desc = reinterpret_cast<const BatchDesc *>(base);
+    const Work *d_work = reinterpret_cast<const Work *>(base + off_work);
+    const RowSumJob *d_jobs = reinterpret_cast<const RowSumJob *>(base + off_jobs);
+    unsigned int *d_ctr = reinterpret_cast<unsigned int *>(base + off_ctr);
+    int n_work = static_cast<int>(b->n_work);
+    e = hipGraphCreate(&b->graph, 0);
+    if (e != hipSuccess) return batch_fail_free(b, hip_fail(e, "hipGraphCreate"));
+    hipGraphNode_t n_reset = nullptr, n_main = nullptr, n_sum = nullptr;
+    {
+        void *args[] = {&d_ctr};
+        hipKernelNodeParams p;
+        std::memset(&p, 0, sizeof(p));
+        p.func = reinterpret_cast<void *>(&ami_batch_reset_kernel);
+        p.gridDim = dim3(1);
+        p.blockDim = dim3(64);
+        p.kernelParams = args;
+        e = hipGraphAddKernelNode(&n_reset, b->graph, nullptr, 0, &p);
+        if (e != hipSuccess) return batch_fail_free(b, hip_fail(e, "graph reset node"));
+    }
+    {
+        void *args[] = {&d_desc, &d_work, &n_work, &d_ctr};
+        hipKernelNodeParams p;
+        std::memset(&p, 0, sizeof(p));
+        bool all = false;
+        for (int i = 0; i < n_items; ++i) all = all || desc[i].shape == kShapeGeneric || desc[i].shape > 6;
+        if (hub) p.func = all ? reinterpret_cast<void *>(&ami_batch_kernel<true, true>)
+                              : reinterpret_cast<void *>(&ami_batch_kernel<true, false>);
+        else p.func = all ? reinterpret_cast<void *>(&ami_batch_kernel<false, true>)
+                          : reinterpret_cast<void *>(&ami_batch_kernel<false, false>);
+        p.gridDim = dim3(b->grid);
+        p.blockDim = dim3(b->block);
+        p.sharedMemBytes = static_cast<unsigned>(b->lds);
+        p.kernelParams = args;
+        e = hipGraphAddKernelNode(&n_main, b->graph, &n_reset, 1, &p);
+        if (e != hipSuccess) return batch_fail_free(b, hip_fail(e, "graph batch node"));
+    }
+    if (n_jobs > 0) {
+        void *args[] = {&d_jobs};
+        hipKernelNodeParams p;
+        std::memset(&p, 0, sizeof(p));
+        p.func = reinterpret_cast<void *>(&ami_batch_rowsum_kernel);
+        p.gridDim = dim3(static_cast<unsigned>(n_jobs));
+        p.blockDim = dim3(256);
+        p.kernelParams = args;
+        e = hipGraphAddKernelNode(&n_sum, b->graph, &n_main, 1, &p);
+        if (e != hipSuccess) return batch_fail_free(b, hip_fail(e, "graph row-sum node"));
+    }
+    e = hipGraphInstantiate(&b->exec, b->graph, nullptr, nullptr, 0);
+    if (e != hipSuccess) return batch_fail_free(b, hip_fail(e, "hipGraphInstantiate"));
+    *out = b;
+    return AMI_OK;
+}
+
+AmiStatus amiBatchRun(AmiBatch *b, void *hip_stream) {
+    using namespace ami;
+    clear_error();
+    if (!b || !b->exec) return fail(AMI_E_ARG, "batch is NULL");
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return hip_fail(e, "hipGetDevice");
+    if (dev != b->device) return fail(AMI_E_ARG, "batch was created on another device");
+    e = hipGraphLaunch(b->exec, static_cast<hipStream_t>(hip_stream));
+    if (e != hipSuccess) return hip_fail(e, "hipGraphLaunch");
+    return AMI_OK;
+}
+
+AmiStatus amiBatchInfo(const AmiBatch *b, int64_t info[8]) {
+    using namespace ami;
+    clear_error();
+    if (!b || !info) return fail(AMI_E_ARG, "NULL argument");
+    info[0] = b->n_items;
+    info[1] = b->n_work;
+    info[2] = b->grid;
+    info[3] = b->block;
+    info[4] = static_cast<int64_t>(b->lds);
+    info[5] = b->n_jobs;
+    info[6] = b->hub ? 1 : 0;
+    info[7] = 0;
+    return AMI_OK;
+}
+
+void amiBatchFree(AmiBatch *b) {
+    if (!b) return;
+    int cur = 0;
+    const bool have = hipGetDevice(&cur) == hipSuccess;
+    (void)hipSetDevice(b->device);
+    if (b->exec) (void)hipGraphExecDestroy(b->exec);
+    if (b->graph) (void)hipGraphDestroy(b->graph);
+    if (b->blob) (void)hipFree(b->blob);
+    if (have) (void)hipSetDevice(cur);
+    delete b;
+}
+
+}  // extern "C"

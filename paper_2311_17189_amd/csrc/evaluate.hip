@@ -20,14 +20,15 @@
 #include "device_common.hpp"
 #include "kernel_generic.hpp"
 #include "kernels_packed.hpp"
+#include "runtime.hpp"
 
 namespace ami {
 
-namespace {
-
-inline AmiStatus hip_fail(hipError_t e, const char *what) {
+AmiStatus hip_fail(hipError_t e, const char *what) {
     return fail(AMI_E_HIP, std::string(what) + ": " + hipGetErrorString(e));
 }
+
+namespace {
 
 // out[j] = sum over b of partial[b * ncols + j], b in increasing order per thread
 // then a fixed tree over the block.  One block per column.
@@ -78,6 +79,8 @@ __global__ void ami_fill_kernel(double *p, int64_t n, double v) {
 }
 
 size_t align256(size_t x) { return (x + 255) & ~static_cast<size_t>(255); }
+
+}  // namespace
 
 AmiStatus fill(double *p, int64_t n, hipStream_t stream) {
     if (!p || n <= 0) return AMI_OK;
@@ -157,12 +160,6 @@ AmiStatus upload(AmiTerms *t, DeviceTables **out) {
     return AMI_OK;
 }
 
-struct LaunchShape {
-    int block = 256;
-    size_t lds = 0;
-    int slots = 0;
-};
-
 AmiStatus pick_shape(int slots, LaunchShape &ls) {
     int dev = 0;
     hipError_t e = hipGetDevice(&dev);
@@ -211,6 +208,8 @@ PackedTabs packed_tabs(const AmiTerms *t, const DeviceTables *dt) {
     return p;
 }
 
+namespace {
+
 template <bool ADJ, int NE, int NI, int DPT, bool EXACT, bool HUB>
 void launch_packed_one(dim3 grid, dim3 block, size_t lds, hipStream_t stream, const KArgs &a) {
     if constexpr (ADJ)
@@ -243,7 +242,11 @@ const char *launch_packed(const AmiTerms *t, dim3 grid, dim3 block, size_t lds, 
     return "bounded generic";
 }
 
+}  // namespace
+
 int fwd_slots(const Tables &tb) { return std::max(tb.L, 2 * tb.D) + tb.G; }
+
+namespace {
 int adj_slots(const Tables &tb) { return tb.L + 2 * tb.G + std::max(2 * tb.D, tb.L); }
 
 AmiStatus launch_generic_forward(AmiTerms *t, DeviceTables *dt, bool hub, const KArgs &ka, double *partial,

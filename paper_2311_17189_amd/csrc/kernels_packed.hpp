@@ -265,11 +265,14 @@ __device__ __forceinline__ void block_sum2(double vr, double vi, double *red, in
 
 // ---- forward ---------------------------------------------------------------
 
+// One tile of B = blockDim.x samples starting at tile * B; `sm` is the
+// block's dynamic LDS (a.slots columns plus the reduction area).  Shared by
+// the per-diagram kernel and the persistent batch kernel, so both compute
+// every output with the same instructions.
 template <int NE, int NI, int DPT, bool EXACT, bool HUB>
-__global__ __launch_bounds__(256) void ami_fwd_packed(KArgs a) {
-    extern __shared__ double sm[];
+__device__ __forceinline__ void fwd_tile(const KArgs &a, int64_t tile, double *sm) {
     const int tid = threadIdx.x, B = blockDim.x;
-    const int64_t s = static_cast<int64_t>(blockIdx.x) * B + tid;
+    const int64_t s = tile * B + tid;
     const bool active = s < a.n_e;
     const int64_t sc = active ? s : a.n_e - 1;
     const PackedTabs &tb = a.tb;
@@ -319,8 +322,14 @@ __global__ __launch_bounds__(256) void ami_fwd_packed(KArgs a) {
         }
         if (a.partial)
             block_sum2(active ? acc_re : 0.0, active ? acc_im : 0.0, red, tid, B,
-                       a.partial + (static_cast<int64_t>(blockIdx.x) * a.n_f + f) * 2);
+                       a.partial + (tile * a.n_f + f) * 2);
     }
+}
+
+template <int NE, int NI, int DPT, bool EXACT, bool HUB>
+__global__ __launch_bounds__(256) void ami_fwd_packed(KArgs a) {
+    extern __shared__ double sm[];
+    fwd_tile<NE, NI, DPT, EXACT, HUB>(a, blockIdx.x, sm);
 }
 
 // ---- adjoint ---------------------------------------------------------------

@@ -1,0 +1,127 @@
+"""Persistent mixed-diagram batch (one HIP graph launch over many diagrams):
+outputs bitwise equal to the per-diagram launches, stable across graph
+replays, row sums consistent, the autotuner, and host-side errors."""
+import numpy as np
+import pytest
+
+from ami_inputs import (DEFAULT_Q, k_samples, matsubara_freqs, random_self_energy,
+                        uniform_energies)
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+amd = pytest.importorskip("paper_2311_17189_amd")
+
+DEV = "cuda"
+
+
+def _mixed_items(n_per_order=2, orders=(2, 3, 4, 5, 6), n_f=4, beta=5.0, energies=False, seed=0):
+    items = []
+    for order in orders:
+        for i in range(n_per_order):
+            d = random_self_energy(order, (seed, order, i))
+            T = amd.Terms.from_diagram(d)
+            n_e = 300 + 517 * i + 131 * order            # ragged sizes
+            w = torch.from_numpy(matsubara_freqs(n_f, beta)).to(DEV)
+            it = {"terms": T, "ext_freqs": w, "beta": beta, "diagram": d,
+                  "out": torch.empty((n_f, n_e), dtype=torch.complex128, device=DEV),
+                  "out_sum": torch.empty((n_f,), dtype=torch.complex128, device=DEV)}
+            if energies:
+                it["energies"] = torch.from_numpy(uniform_energies(n_e, d.n_eps, seed=(30, order, i),
+                                                                   a=4.0)).to(DEV)
+            else:
+                it["k"] = torch.from_numpy(k_samples(n_e, d.n_int, seed=(31, order, i))).to(DEV)
+                it.update(q=list(DEFAULT_Q), t=1.0, mu=0.05)
+            items.append(it)
+    return items
+
+
+def _per_diagram(it):
+    if it.get("k") is not None:
+        return amd.evaluate_hubbard(it["terms"], it["k"], it["q"], it["t"], it["mu"], it["ext_freqs"],
+                                    it["beta"], want_sum=True)
+    return amd.evaluate(it["terms"], it["energies"], it["ext_freqs"], it["beta"], want_sum=True)
+
+
+@pytest.mark.parametrize("energies", [False, True])
+@pytest.mark.parametrize("tuning", [None, {"block": 64, "waves_per_cu": 4, "tile_factor": 1},
+                                    {"block": 128, "waves_per_cu": 16, "tile_factor": 4}])
+def test_batch_bitwise_equals_per_diagram(energies, tuning):
+    items = _mixed_items(energies=energies)
+    b = amd.Batch(items, tuning)
+    b.run()
+    torch.cuda.synchronize()
+    info = b.info()
+    assert info["items"] == len(items) and info["work_items"] >= len(items)
+    for it in items:
+        ref_out, ref_sum = _per_diagram(it)
+        torch.cuda.synchronize()
+        assert torch.equal(it["out"], ref_out)
+        # the row sum runs over the batch's tiles; it equals the per-diagram
+        # one bit for bit when the tile size matches, else to rounding
+        assert torch.allclose(it["out_sum"], ref_sum, rtol=1e-12, atol=1e-15 * float(ref_out.abs().sum()))
+
+
+def test_graph_replays_are_identical():
+    """Replay the batch graph several times with other GPU work and
+    synchronizations in between; every replay gives the same bits."""
+    items = _mixed_items(n_per_order=1)
+    b = amd.Batch(items, {"block": 64, "waves_per_cu": 8, "tile_factor": 2})
+    b.run()
+    torch.cuda.synchronize()
+    first = [(it["out"].clone(), it["out_sum"].clone()) for it in items]
+    scratch = torch.zeros(1 << 20, dtype=torch.float64, device=DEV)
+    for rep in range(4):
+        for it in items:
+            it["out"].fill_(float("nan"))
+            it["out_sum"].zero_()
+        scratch.add_(1.0)                      # eager work between replays
+        torch.cuda.synchronize()
+        b.run()
+        torch.cuda.synchronize()
+        for (o, s), it in zip(first, items):
+            assert torch.equal(it["out"], o)
+            assert torch.equal(it["out_sum"], s)
+
+
+def test_batch_outputs_only_sums():
+    items = _mixed_items(n_per_order=1)
+    for it in items:
+        it["out"] = None
+    b = amd.Batch(items)
+    b.run()
+    torch.cuda.synchronize()
+    for it in items:
+        _, ref_sum = _per_diagram(it)
+        torch.cuda.synchronize()
+        assert torch.allclose(it["out_sum"], ref_sum, rtol=1e-11)
+
+
+def test_autotuner_picks_a_working_tuning(tmp_path):
+    from paper_2311_17189_amd.autotune import autotune
+    items = _mixed_items(n_per_order=1, orders=(2, 4, 6))
+    cands = [{"block": 64, "waves_per_cu": 4, "tile_factor": 1},
+             {"block": 0, "waves_per_cu": 8, "tile_factor": 4}]
+    best, timings = autotune(items, cands, reps=2, path=str(tmp_path / "tune.json"))
+    assert best in cands and len(timings) == 2
+    again, _ = autotune(items, cands, reps=2, path=str(tmp_path / "tune.json"))
+    assert again == best                     # served from the cache
+    b = amd.Batch(items, best)
+    b.run()
+    torch.cuda.synchronize()
+    for it in items:
+        ref_out, _ = _per_diagram(it)
+        torch.cuda.synchronize()
+        assert torch.equal(it["out"], ref_out)
+
+
+def test_batch_host_errors():
+    items = _mixed_items(n_per_order=1, orders=(2, 3))
+    mixed = [items[0], dict(items[1])]
+    mixed[1].pop("k")
+    mixed[1]["energies"] = torch.zeros((10, mixed[1]["terms"].n_eps), dtype=torch.float64, device=DEV)
+    mixed[1]["out"] = torch.empty((4, 10), dtype=torch.complex128, device=DEV)
+    with pytest.raises(amd.AmiError):
+        amd.Batch(mixed)
+    with pytest.raises(amd.AmiError):
+        amd.Batch(items, {"block": 96, "waves_per_cu": 8, "tile_factor": 1})
