@@ -8,8 +8,9 @@ Workload (one step = one pass of the evaluation path over one batch):
   energies E_j = 2t(cos K_jx + cos K_jy) + mu computed in the kernel (t = 1,
   mu = 0, q = (pi/2, pi/2)); beta = 5; one external Matsubara frequency i pi/beta.
   The step evaluates out[N_F, N_E] and its Monte-Carlo row sum out_sum[N_F]
-  (forward), then the gradients of the summed integrand with respect to every
-  momentum component, mu, t, beta and the external frequency (adjoint).
+  (forward) and the gradients of the summed integrand with respect to every
+  momentum component, mu, t, beta and the external frequency (adjoint), in one
+  pass of the adjoint kernel with values.
 
 Metric: term-evaluations/s = T * N_E * N_F / (seconds per step), T the number
 of canonical flat terms; the forward alone and the plain double-table kernel
@@ -238,6 +239,12 @@ def main():
         return amd.evaluate_hubbard_adjoint(terms, k, q, hop_t, mu, w, args.beta,
                                             grad_sum=g_sum, stream=stream)
 
+    def step():
+        # the whole path in one pass: values out[N_F, N_E] and out_sum[N_F] and the
+        # gradients of Re sum_s I(s) (the row-sum cotangent is fixed in advance)
+        return amd.evaluate_hubbard_adjoint(terms, k, q, hop_t, mu, w, args.beta,
+                                            grad_sum=g_sum, out=out, out_sum=out_sum, stream=stream)
+
     if args.copy_mib > 0:
         src = torch.empty(args.copy_mib * (1 << 20) // 8, dtype=torch.float64, device=dev).fill_(1.0)
         dst = torch.empty_like(src)
@@ -247,35 +254,44 @@ def main():
         del src, dst
 
     for _ in range(args.warmup):
-        fwd()
-        adj()
+        step()
     torch.cuda.synchronize()
-    fwd_variant = amd.last_variant()
 
-    # timed region: K steps (forward + adjoint), HIP events around every launch
-    # on the launch stream
-    ev_f = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
-            for _ in range(args.steps)]
-    ev_a = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
-            for _ in range(args.steps)]
+    # timed region: K steps, HIP events around every launch on the launch stream
+    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+          for _ in range(args.steps)]
     start = torch.cuda.Event(enable_timing=True)
     stop = torch.cuda.Event(enable_timing=True)
     torch.cuda.synchronize()
     wall0 = time.perf_counter()
     start.record(stream)
     for i in range(args.steps):
-        ev_f[i][0].record(stream)
-        fwd()
-        ev_f[i][1].record(stream)
-        ev_a[i][0].record(stream)
-        adj()
-        ev_a[i][1].record(stream)
+        ev[i][0].record(stream)
+        step()
+        ev[i][1].record(stream)
     stop.record(stream)
     torch.cuda.synchronize()
     wall = time.perf_counter() - wall0
     ms_step = start.elapsed_time(stop) / args.steps
-    fwd_ms = sum(a.elapsed_time(b) for a, b in ev_f) / args.steps
-    adj_ms = sum(a.elapsed_time(b) for a, b in ev_a) / args.steps
+    step_kernel_ms = sum(a.elapsed_time(b) for a, b in ev) / args.steps
+
+    def timed(fn, reps):
+        fn()
+        torch.cuda.synchronize()
+        a0 = torch.cuda.Event(enable_timing=True)
+        a1 = torch.cuda.Event(enable_timing=True)
+        a0.record(stream)
+        for _ in range(reps):
+            fn()
+        a1.record(stream)
+        torch.cuda.synchronize()
+        return a0.elapsed_time(a1) / reps
+
+    # beside the step: forward alone and adjoint alone (separate passes)
+    reps = max(5, args.steps // 2)
+    fwd_ms = timed(fwd, reps)
+    fwd_variant = amd.last_variant()
+    adj_ms = timed(adj, reps)
 
     # the plain per-diagram kernel (double tables) on the same launch, outside the timed region
     terms.set_variant(1)
@@ -298,12 +314,10 @@ def main():
     value = te / (ms_step * 1e-3)
     fl = rl.forward_flops(st, n_e, n_f, d.alpha)
     fa = rl.adjoint_flops(st, n_e, n_f, d.alpha)
-    if adj_ms >= fwd_ms:
-        dom, dom_key, dom_ms, dom_fl = ("ami_adj_packed (+ its reduction kernel)", "ami_adj_packed",
-                                        adj_ms, fa["total"])
-    else:
-        dom, dom_key, dom_ms, dom_fl = ("ami_fwd_packed (+ its row-sum kernel)", "ami_fwd_packed",
-                                        fwd_ms, fl["total"])
+    fs = rl.adjoint_flops(st, n_e, n_f, d.alpha, with_values=True)
+    # the step is one launch of the adjoint kernel with values (+ two reductions)
+    dom, dom_key, dom_ms, dom_fl = ("ami_adj_packed with values (+ its reduction kernels)",
+                                    "ami_adj_packed", step_kernel_ms, fs["total"])
     achieved = dom_fl / (dom_ms * 1e-3)
     workload_key = f"order{args.order}-diagram{args.diagram}-ne{n_e}-nf{n_f}-beta{args.beta:g}"
     traffic = recorded_traffic(dom_key, workload_key)
@@ -333,9 +347,11 @@ def main():
             "key": workload_key,
         },
         "fwd": {"ms": fwd_ms, "term_evals_per_s": te / (fwd_ms * 1e-3), "kernel": fwd_variant,
-                "flops": fl["total"], "tflops": fl["total"] / (fwd_ms * 1e-3) / 1e12},
-        "fwd_adjoint": {"ms": fwd_ms + adj_ms, "adjoint_ms": adj_ms,
-                        "term_evals_per_s": te / ((fwd_ms + adj_ms) * 1e-3),
+                "flops": fl["total"], "tflops": fl["total"] / (fwd_ms * 1e-3) / 1e12,
+                "frac_fp64_peak": fl["total"] / (fwd_ms * 1e-3) / rl.PEAK_FP64_VECTOR},
+        "fwd_adjoint": {"one_pass_ms": step_kernel_ms,
+                        "one_pass_term_evals_per_s": te / (step_kernel_ms * 1e-3),
+                        "separate_ms": fwd_ms + adj_ms, "adjoint_ms": adj_ms,
                         "adjoint_flops": fa["total"],
                         "adjoint_tflops": fa["total"] / (adj_ms * 1e-3) / 1e12},
         "plain_kernel": {"ms": plain_ms, "term_evals_per_s": te / (plain_ms * 1e-3),

@@ -172,14 +172,18 @@ AmiStatus amiEvaluateHubbard(AmiTerms *terms,
  * of these).  Other arguments as amiEvaluate.  The sums over samples are
  * reduced in a fixed order.  Needs the packed form of the solution (every
  * energy coefficient +-1, at most 255 distinct leaves and denominators, at most
- * 8 of each per term): AMI_E_UNSUPPORTED otherwise.
+ * 8 of each per term, no leaf twice in one term): AMI_E_UNSUPPORTED otherwise.
+ * out / out_sum (device, or NULL): the forward values, as amiEvaluate would
+ * return them, computed on the way -- a value-and-gradient pass when the
+ * cotangents do not depend on the values (e.g. grad_sum for a Monte-Carlo
+ * estimate).
  */
 AmiStatus amiEvaluateAdjoint(AmiTerms *terms,
                              const double *energies, int64_t n_e, int64_t stride_s, int64_t stride_i,
                              const double *ext_freqs, int64_t n_f, double beta, double e_reg,
                              const double *grad_out, const double *grad_sum,
                              double *grad_energies, double *grad_beta, double *grad_freqs,
-                             void *hip_stream);
+                             double *out, double *out_sum, void *hip_stream);
 
 /*
  * amiEvaluateHubbardAdjoint -- the adjoint of amiEvaluateHubbard: as
@@ -195,7 +199,8 @@ AmiStatus amiEvaluateHubbardAdjoint(AmiTerms *terms,
                                     double beta, double e_reg,
                                     const double *grad_out, const double *grad_sum,
                                     double *grad_k, double *grad_mu, double *grad_t,
-                                    double *grad_beta, double *grad_freqs, void *hip_stream);
+                                    double *grad_beta, double *grad_freqs,
+                                    double *out, double *out_sum, void *hip_stream);
 
 /*
  * amiSetVariant -- choose the forward kernel of a handle: 0 (default) the

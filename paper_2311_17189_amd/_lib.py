@@ -83,10 +83,10 @@ def load_library():
                                        c_dbl, vp, vp, vp]
     lib.amiEvaluateHubbard.restype = c_i32
     lib.amiEvaluateAdjoint.argtypes = [vp, vp, c_i64, c_i64, c_i64, vp, c_i64, c_dbl, c_dbl, vp, vp,
-                                       vp, vp, vp, vp]
+                                       vp, vp, vp, vp, vp, vp]
     lib.amiEvaluateAdjoint.restype = c_i32
     lib.amiEvaluateHubbardAdjoint.argtypes = [vp, vp, c_i64, c_i64, vp, c_dbl, c_dbl, vp, c_i64, c_dbl,
-                                              c_dbl, vp, vp, vp, vp, vp, vp, vp, vp]
+                                              c_dbl, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp]
     lib.amiEvaluateHubbardAdjoint.restype = c_i32
     lib.amiSetVariant.argtypes = [vp, c_i32]
     lib.amiSetVariant.restype = c_i32
@@ -302,9 +302,10 @@ def _cot(grad_out, grad_sum, n_f, n_e, device):
 
 
 def evaluate_adjoint(terms: Terms, energies, ext_freqs, beta: float, e_reg: float = 0.0,
-                     grad_out=None, grad_sum=None, stream=None):
+                     grad_out=None, grad_sum=None, out=None, out_sum=None, stream=None):
     """``amiEvaluateAdjoint``: returns ``(grad_energies [N_E, nE], grad_beta [],
-    grad_freqs [N_F, n_ext])`` for the cotangents of ``out`` / ``out_sum``."""
+    grad_freqs [N_F, n_ext])`` for the cotangents of ``out`` / ``out_sum``;
+    ``out`` / ``out_sum`` tensors, if given, receive the forward values."""
     import torch
     if energies.dtype != torch.float64 or not energies.is_cuda or energies.dim() != 2:
         raise AmiError(-1, "energies must be a 2-D float64 CUDA tensor")
@@ -315,18 +316,22 @@ def evaluate_adjoint(terms: Terms, energies, ext_freqs, beta: float, e_reg: floa
     g_e = torch.empty((n_e, terms.n_eps), dtype=torch.float64, device=dev)
     g_b = torch.empty((), dtype=torch.float64, device=dev)
     g_w = torch.empty((n_f, w.shape[1]), dtype=torch.complex128, device=dev)
+    out, out_sum = _outputs(n_f, n_e, dev, False, False, out, out_sum)
     st_s, st_i = energies.stride()
     _check(load_library().amiEvaluateAdjoint(
         terms._h, energies.data_ptr() if n_e else None, n_e, max(st_s, 1), max(st_i, 1),
         w.data_ptr(), n_f, float(beta), float(e_reg), _ptr(go), _ptr(gs),
-        g_e.data_ptr() if n_e else None, g_b.data_ptr(), g_w.data_ptr(), _stream_ptr(stream)))
+        g_e.data_ptr() if n_e else None, g_b.data_ptr(), g_w.data_ptr(),
+        _ptr(out) if n_e else None, _ptr(out_sum), _stream_ptr(stream)))
     return g_e, g_b, g_w
 
 
 def evaluate_hubbard_adjoint(terms: Terms, k, q, t: float, mu: float, ext_freqs, beta: float,
-                             e_reg: float = 0.0, grad_out=None, grad_sum=None, stream=None):
+                             e_reg: float = 0.0, grad_out=None, grad_sum=None, out=None,
+                             out_sum=None, stream=None):
     """``amiEvaluateHubbardAdjoint``: returns ``(grad_k [N_E, 2 n_int], grad_mu [],
-    grad_t [], grad_beta [], grad_freqs [N_F, n_ext])``."""
+    grad_t [], grad_beta [], grad_freqs [N_F, n_ext])``; ``out`` / ``out_sum``
+    tensors, if given, receive the forward values."""
     import torch
     if k.dtype != torch.float64 or not k.is_cuda or k.dim() != 2:
         raise AmiError(-1, "k must be a 2-D float64 CUDA tensor")
@@ -339,13 +344,14 @@ def evaluate_hubbard_adjoint(terms: Terms, k, q, t: float, mu: float, ext_freqs,
     g_k = torch.empty((n_e, 2 * terms.n_int), dtype=torch.float64, device=dev)
     scal = torch.empty((3,), dtype=torch.float64, device=dev)
     g_w = torch.empty((n_f, w.shape[1]), dtype=torch.complex128, device=dev)
+    out, out_sum = _outputs(n_f, n_e, dev, False, False, out, out_sum)
     qa = np.ascontiguousarray(np.asarray(q, dtype=np.float64).reshape(-1))
     base = scal.data_ptr()
     _check(load_library().amiEvaluateHubbardAdjoint(
         terms._h, k.data_ptr() if n_e else None, n_e, max(k.stride(0), 2 * terms.n_int),
         qa.ctypes.data, float(t), float(mu), w.data_ptr(), n_f, float(beta), float(e_reg),
         _ptr(go), _ptr(gs), g_k.data_ptr() if n_e else None, base, base + 8, base + 16,
-        g_w.data_ptr(), _stream_ptr(stream)))
+        g_w.data_ptr(), _ptr(out) if n_e else None, _ptr(out_sum), _stream_ptr(stream)))
     return g_k, scal[0], scal[1], scal[2], g_w
 
 

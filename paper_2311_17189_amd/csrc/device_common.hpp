@@ -94,6 +94,33 @@ __device__ __forceinline__ void sincos_red(double x, double &s, double &c) {
     c = ((q + 1) & 2) ? -cc : cc;
 }
 
+// cos alone: x = k pi + r with the same three-part split (doubled: exact),
+// |r| <= pi/2, cos x = (-1)^k cos r with the Taylor series of cos to r^20
+// (truncation at pi/2 below 2e-17).  Valid for |x| < 1e5.
+__device__ __forceinline__ double cos_red(double x) {
+    constexpr double kOneOverPi = 0x1.45f306dc9c883p-2;
+    constexpr double kPiHi = 0x1.921fb54400000p+1;
+    constexpr double kPiMid = 0x1.0b4611a600000p-33;
+    constexpr double kPiLo = 0x1.3198a2e037073p-68;
+    const double kf = __builtin_rint(x * kOneOverPi);
+    double r = fma(-kf, kPiHi, x);
+    r = fma(-kf, kPiMid, r);
+    r = fma(-kf, kPiLo, r);
+    const double z = r * r;
+    double p = 1.0 / 2432902008176640000.0;      // 1/20!
+    p = fma(p, z, -1.0 / 6402373705728000.0);    // 1/18!
+    p = fma(p, z, 1.0 / 20922789888000.0);       // 1/16!
+    p = fma(p, z, -1.0 / 87178291200.0);         // 1/14!
+    p = fma(p, z, 1.0 / 479001600.0);            // 1/12!
+    p = fma(p, z, -1.0 / 3628800.0);             // 1/10!
+    p = fma(p, z, 1.0 / 40320.0);                // 1/8!
+    p = fma(p, z, -1.0 / 720.0);                 // 1/6!
+    p = fma(p, z, 1.0 / 24.0);                   // 1/4!
+    p = fma(p, z, -0.5);                         // 1/2!
+    const double c = fma(z, p, 1.0);
+    return (static_cast<int>(kf) & 1) ? -c : c;
+}
+
 // e^z and e^z - 1 from one reduction: z = k ln2 + r with ln2 split in two
 // (42 + 53 significant bits, so k * hi is exact for |k| < 2^11), |r| <= ln2/2,
 // and p = e^r - 1 by its Taylor series to r^13 (truncation below 2e-17 relative).

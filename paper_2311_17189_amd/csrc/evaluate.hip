@@ -353,6 +353,7 @@ AmiStatus launch_forward(AmiTerms *t, bool hub, KArgs &a, double *out_sum, hipSt
 
 struct AdjOut {
     double *grad_beta = nullptr, *grad_mu = nullptr, *grad_t = nullptr, *grad_freqs = nullptr;
+    double *out_sum = nullptr;   // forward row sums computed on the way (optional)
 };
 
 AmiStatus launch_adjoint(AmiTerms *t, bool hub, KArgs &a, const AdjOut &o, hipStream_t stream) {
@@ -369,6 +370,8 @@ AmiStatus launch_adjoint(AmiTerms *t, bool hub, KArgs &a, const AdjOut &o, hipSt
             st = fill(p, 1, stream);
             if (st != AMI_OK) return st;
         }
+        st = fill(o.out_sum, 2 * static_cast<int64_t>(a.n_f), stream);
+        if (st != AMI_OK) return st;
         return fill(o.grad_freqs, 2 * static_cast<int64_t>(a.n_f) * nx, stream);
     }
     LaunchShape ls;
@@ -377,12 +380,14 @@ AmiStatus launch_adjoint(AmiTerms *t, bool hub, KArgs &a, const AdjOut &o, hipSt
     const int64_t nblocks = (a.n_e + ls.block - 1) / ls.block;
     if (nblocks > 0x7fffffffLL) return fail(AMI_E_ARG, "n_e too large");
     double *partial = nullptr;
-    hipError_t e = hipMallocAsync(reinterpret_cast<void **>(&partial),
-                                  static_cast<size_t>(nblocks) * ncols * sizeof(double), stream);
+    const size_t n_grad = static_cast<size_t>(nblocks) * ncols;
+    const size_t n_val = o.out_sum ? static_cast<size_t>(nblocks) * a.n_f * 2 : 0;
+    hipError_t e = hipMallocAsync(reinterpret_cast<void **>(&partial), (n_grad + n_val) * sizeof(double), stream);
     if (e != hipSuccess) return fail(AMI_E_OOM, std::string("workspace: ") + hipGetErrorString(e));
     a.tb = packed_tabs(t, dt);
     a.slots = ls.slots;
     a.gpartial = partial;
+    a.partial = o.out_sum ? partial + n_grad : nullptr;
     const dim3 grid(static_cast<unsigned>(nblocks)), block(ls.block);
     g_last_variant = hub ? launch_packed<true, true>(t, grid, block, ls.lds, stream, a)
                          : launch_packed<true, false>(t, grid, block, ls.lds, stream, a);
@@ -394,6 +399,11 @@ AmiStatus launch_adjoint(AmiTerms *t, bool hub, KArgs &a, const AdjOut &o, hipSt
     hipLaunchKernelGGL(ami_adj_finalize_kernel, dim3(ncols), dim3(256), 0, stream, partial, nblocks, ncols,
                        o.grad_beta, o.grad_mu, o.grad_t, o.grad_freqs);
     e = hipGetLastError();
+    if (e == hipSuccess && o.out_sum) {
+        hipLaunchKernelGGL(ami_colsum_kernel, dim3(2 * a.n_f), dim3(256), 0, stream, partial + n_grad, nblocks,
+                           2 * a.n_f, o.out_sum);
+        e = hipGetLastError();
+    }
     (void)hipFreeAsync(partial, stream);
     if (e != hipSuccess) return hip_fail(e, "adjoint reduction launch");
     return AMI_OK;
@@ -510,7 +520,8 @@ AmiStatus amiEvaluateHubbard(AmiTerms *t, const double *k, int64_t n_e, int64_t 
 AmiStatus amiEvaluateAdjoint(AmiTerms *t, const double *energies, int64_t n_e, int64_t stride_s,
                              int64_t stride_i, const double *ext_freqs, int64_t n_f, double beta, double e_reg,
                              const double *grad_out, const double *grad_sum, double *grad_energies,
-                             double *grad_beta, double *grad_freqs, void *hip_stream) {
+                             double *grad_beta, double *grad_freqs, double *out, double *out_sum,
+                             void *hip_stream) {
     using namespace ami;
     clear_error();
     AmiStatus st = check_common(t, n_e, ext_freqs, n_f, beta);
@@ -526,9 +537,11 @@ AmiStatus amiEvaluateAdjoint(AmiTerms *t, const double *energies, int64_t n_e, i
     a.g_out = grad_out;
     a.g_sum = grad_sum;
     a.grad_e = grad_energies;
+    a.out = out;
     AdjOut o;
     o.grad_beta = grad_beta;
     o.grad_freqs = grad_freqs;
+    o.out_sum = out_sum;
     return launch_adjoint(t, false, a, o, static_cast<hipStream_t>(hip_stream));
 }
 
@@ -536,7 +549,7 @@ AmiStatus amiEvaluateHubbardAdjoint(AmiTerms *t, const double *k, int64_t n_e, i
                                     double hop_t, double mu, const double *ext_freqs, int64_t n_f, double beta,
                                     double e_reg, const double *grad_out, const double *grad_sum, double *grad_k,
                                     double *grad_mu, double *grad_t, double *grad_beta, double *grad_freqs,
-                                    void *hip_stream) {
+                                    double *out, double *out_sum, void *hip_stream) {
     using namespace ami;
     clear_error();
     AmiStatus st = check_common(t, n_e, ext_freqs, n_f, beta);
@@ -550,11 +563,13 @@ AmiStatus amiEvaluateHubbardAdjoint(AmiTerms *t, const double *k, int64_t n_e, i
     a.g_out = grad_out;
     a.g_sum = grad_sum;
     a.grad_k = grad_k;
+    a.out = out;
     AdjOut o;
     o.grad_beta = grad_beta;
     o.grad_mu = grad_mu;
     o.grad_t = grad_t;
     o.grad_freqs = grad_freqs;
+    o.out_sum = out_sum;
     return launch_adjoint(t, true, a, o, static_cast<hipStream_t>(hip_stream));
 }
 

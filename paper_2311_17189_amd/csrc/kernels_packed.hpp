@@ -113,20 +113,27 @@ __device__ __forceinline__ void hubbard_energies(const KArgs &a, int64_t sc, dou
                     Ky -= a.q[2 * x + 1];
                 }
             }
-            double sx, cx, sy, cy;
-            if (!slow) {
-                sincos_red(Kx, sx, cx);
-                sincos_red(Ky, sy, cy);
-            } else {
-                sincos(Kx, &sx, &cx);
-                sincos(Ky, &sy, &cy);
-            }
-            E[j] = fma(2.0 * a.hop_t, cx + cy, a.mu);
-            if (KEEP) {
+            double cx, cy;
+            if (KEEP) {            // the adjoint needs sin K as well
+                double sx, sy;
+                if (!slow) {
+                    sincos_red(Kx, sx, cx);
+                    sincos_red(Ky, sy, cy);
+                } else {
+                    sincos(Kx, &sx, &cx);
+                    sincos(Ky, &sy, &cy);
+                }
                 sKx[j] = sx;
                 sKy[j] = sy;
                 cs[j] = cx + cy;
+            } else if (!slow) {
+                cx = cos_red(Kx);
+                cy = cos_red(Ky);
+            } else {
+                cx = cos(Kx);
+                cy = cos(Ky);
             }
+            E[j] = fma(2.0 * a.hop_t, cx + cy, a.mu);
         }
     }
 }
@@ -403,6 +410,7 @@ __global__ __launch_bounds__(256) void ami_adj_packed(KArgs a) {
             gwr[x] = 0.0;
             gwi[x] = 0.0;
         }
+        double acc_re = 0.0, acc_im = 0.0;      // forward value, when asked for
         for (int g = 0; g < G; ++g) {
             const uint64_t w = grp[g];
             double xr[DPT > 0 ? DPT : 1], xi[DPT > 0 ? DPT : 1];
@@ -423,6 +431,8 @@ __global__ __launch_bounds__(256) void ami_adj_packed(KArgs a) {
             FTB[g * B + tid] += fma(cr, Rr, ci * Ri);
             // u = -FT conj(c) R
             const double ft = FT[g * B + tid];
+            acc_re = fma(ft, Rr, acc_re);
+            acc_im = fma(ft, Ri, acc_im);
             const double qr = ft * cr, qi = -ft * ci;
             const double ur = -fma(qr, Rr, -qi * Ri), ui = -fma(qr, Ri, qi * Rr);
 #pragma unroll
@@ -453,6 +463,15 @@ __global__ __launch_bounds__(256) void ami_adj_packed(KArgs a) {
         for (int x = 0; x < nx; ++x)
             block_sum2(active ? gwr[x] : 0.0, active ? -gwi[x] : 0.0, red, tid, B,
                        gp + kAdjScalars + 2 * (f * nx + x));
+        if (active && a.out) {
+            double2 v;
+            v.x = acc_re;
+            v.y = acc_im;
+            reinterpret_cast<double2 *>(a.out)[static_cast<int64_t>(f) * a.n_e + s] = v;
+        }
+        if (a.partial)
+            block_sum2(active ? acc_re : 0.0, active ? acc_im : 0.0, red, tid, B,
+                       a.partial + (static_cast<int64_t>(blockIdx.x) * a.n_f + f) * 2);
     }
 
     // leaf cotangents (the X region is free now)

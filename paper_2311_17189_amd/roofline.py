@@ -141,7 +141,7 @@ def forward_flops(st: Structure, n_e: int, n_f: int, line_alpha=None) -> dict:
             "term_evals": float(st.T) * n_e * n_f}
 
 
-def adjoint_flops(st: Structure, n_e: int, n_f: int, line_alpha=None) -> dict:
+def adjoint_flops(st: Structure, n_e: int, n_f: int, line_alpha=None, with_values=False) -> dict:
     """FLOPs of one adjoint launch: the forward recomputation of leaves,
     group sums and reciprocals, then per group and frequency the product of
     its reciprocals, the group-sum cotangent and one complex product per
@@ -164,6 +164,8 @@ def adjoint_flops(st: Structure, n_e: int, n_f: int, line_alpha=None) -> dict:
     for n_terms, dpt in st.groups:
         per_point += 6 * max(dpt - 1, 0) + 3 + 2 + 6
         per_point += dpt * (6 + 3 + 2)          # rho * u, scatter (about 3 energies, 1 frequency)
+        if with_values:
+            per_point += 4                      # FT_g R_g accumulated into the value
     total = n_e * per_sample + n_e * n_f * per_point
     return {"per_sample": per_sample, "per_point": per_point, "total": float(total),
             "term_evals": float(st.T) * n_e * n_f}

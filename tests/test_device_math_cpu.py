@@ -50,6 +50,16 @@ def test_sincos_reduced(exe):
         assert abs(c - float(mc)) <= 4 * 2.0 ** -52 * max(1.0, abs(x) * 2.0 ** -20)
 
 
+def test_cos_reduced(exe):
+    mp.mp.dps = 40
+    rng = np.random.default_rng(1)
+    xs = np.concatenate([rng.uniform(-4 * np.pi, 4 * np.pi, 400), rng.uniform(-1e4, 1e4, 200),
+                         [0.0, np.pi / 2, -np.pi / 2, np.pi, 3 * np.pi / 2, 1e-9]])
+    got = _run(exe, "c", xs)
+    for x, (c,) in zip(xs, got):
+        assert abs(c - float(mp.cos(mp.mpf(float(x))))) <= 4 * 2.0 ** -52 * max(1.0, abs(x) * 2.0 ** -20)
+
+
 def test_exp_split(exe):
     mp.mp.dps = 40
     xs = np.concatenate([-np.logspace(-12, np.log10(700.0), 300), np.logspace(-12, np.log10(700.0), 300),

@@ -218,3 +218,36 @@ def test_adjoint_empty_batch():
                                                                             device=DEV))
     torch.cuda.synchronize()
     assert g_e.shape == (0, 3) and float(g_b) == 0.0 and torch.all(g_w == 0)
+
+
+def test_value_and_gradient_in_one_pass():
+    """The adjoint entry points also return the forward values when asked: the
+    energy path bitwise equal to amiEvaluate, the momentum path within the
+    parity bar (its energies come from the sin/cos pair instead of cos alone)."""
+    d = random_self_energy(4, (0, 4, 2))
+    beta = 5.0
+    T = amd.Terms.from_diagram(d)
+    E = torch.from_numpy(uniform_energies(1500, d.n_eps, seed=27, a=4.0)).to(DEV)
+    w = torch.from_numpy(matsubara_freqs(2, beta)).to(DEV)
+    gs = torch.tensor([1.0, 0.5j], dtype=torch.complex128, device=DEV)
+    out = torch.empty((2, 1500), dtype=torch.complex128, device=DEV)
+    out_sum = torch.empty((2,), dtype=torch.complex128, device=DEV)
+    g1 = amd.evaluate_adjoint(T, E, w, beta, grad_sum=gs, out=out, out_sum=out_sum)
+    g2 = amd.evaluate_adjoint(T, E, w, beta, grad_sum=gs)
+    ref, ref_sum = amd.evaluate(T, E, w, beta, want_sum=True)
+    torch.cuda.synchronize()
+    assert torch.equal(out, ref)
+    assert torch.allclose(out_sum, ref_sum, rtol=1e-12)
+    for x, y in zip(g1, g2):
+        assert torch.equal(x, y)
+    # momentum path
+    k = k_samples(1200, d.n_int, seed=28)
+    q = np.array(DEFAULT_Q)
+    wh = np.concatenate([matsubara_freqs(1, beta), real_freqs(1, 0.3, 0.3, 0.05)])
+    out = torch.empty((2, 1200), dtype=torch.complex128, device=DEV)
+    amd.evaluate_hubbard_adjoint(T, torch.from_numpy(k).to(DEV), q, 1.0, 0.0, torch.from_numpy(wh).to(DEV),
+                                 beta, grad_sum=gs, out=out)
+    torch.cuda.synchronize()
+    from parity import reference_hubbard
+    ref, scale, dist, _ = reference_hubbard(d, k, q, 1.0, 0.0, wh, beta)
+    check(out.cpu().numpy(), ref, scale, dist, label="value and gradient")
