@@ -147,7 +147,9 @@ AmiStatus amiEvaluate(AmiTerms *terms,
  * square lattice).  Requires n_eps == n_g (one energy per propagator).
  *
  *   k        device float64 [n_e][2*n_int] row-major (k1x k1y k2x k2y ...),
- *            row stride stride_k (>= 2*n_int) in doubles
+ *            row stride stride_k (>= 2*n_int) in doubles.  Components are
+ *            reduced modulo 2 pi in the kernel (exact for |k| < 6e6; the
+ *            dispersion is 2 pi periodic)
  *   q        host float64 [2*n_ext]
  */
 AmiStatus amiEvaluateHubbard(AmiTerms *terms,

@@ -224,9 +224,8 @@ AmiStatus amiBatchCreate(const AmiBatchItem *items, int32_t n_items, const AmiBa
         d.a.k = it.k;
         d.a.stride_k = it.stride_k;
         for (int x = 0; x < t->n_ext && x < kMaxExtDev; ++x) {
-            d.a.q[2 * x] = it.q[2 * x];
-            d.a.q[2 * x + 1] = it.q[2 * x + 1];
-            if (!(std::abs(it.q[2 * x]) <= 1e4) || !(std::abs(it.q[2 * x + 1]) <= 1e4)) d.a.q_big = 1;
+            d.a.q[2 * x] = std::remainder(it.q[2 * x], 2.0 * M_PI);
+            d.a.q[2 * x + 1] = std::remainder(it.q[2 * x + 1], 2.0 * M_PI);
         }
         d.a.hop_t = it.t;
         d.a.mu = it.mu;

@@ -94,6 +94,21 @@ __device__ __forceinline__ void sincos_red(double x, double &s, double &c) {
     c = ((q + 1) & 2) ? -cc : cc;
 }
 
+// x - 2 pi n with n = rint(x / 2pi): the same three-part split scaled by 4
+// (exact), so the reduction is exact up to the last part for |x| < 6e6.  The
+// energies depend on momenta only through cos/sin of integer combinations, so
+// reducing every momentum component first keeps every later argument small.
+__device__ __forceinline__ double reduce_2pi(double x) {
+    constexpr double kOneOver2Pi = 0x1.45f306dc9c883p-3;
+    constexpr double k2PiHi = 0x1.921fb54400000p+2;
+    constexpr double k2PiMid = 0x1.0b4611a600000p-32;
+    constexpr double k2PiLo = 0x1.3198a2e037073p-67;
+    const double n = __builtin_rint(x * kOneOver2Pi);
+    double r = fma(-n, k2PiHi, x);
+    r = fma(-n, k2PiMid, r);
+    return fma(-n, k2PiLo, r);
+}
+
 // cos alone: x = k pi + r with the same three-part split (doubled: exact),
 // |r| <= pi/2, cos x = (-1)^k cos r with the Taylor series of cos to r^20
 // (truncation at pi/2 below 2e-17).  Valid for |x| < 1e5.

@@ -12,6 +12,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <cmath>
 #include <cstring>
 #include <mutex>
 #include <string>
@@ -442,9 +443,8 @@ void set_momenta(KArgs &a, const AmiTerms *t, const double *k, int64_t stride_k,
     a.stride_k = stride_k;
     a.q_big = 0;
     for (int x = 0; x < t->n_ext && x < kMaxExtDev; ++x) {
-        a.q[2 * x] = q[2 * x];
-        a.q[2 * x + 1] = q[2 * x + 1];
-        if (!(std::abs(q[2 * x]) <= 1e4) || !(std::abs(q[2 * x + 1]) <= 1e4)) a.q_big = 1;
+        a.q[2 * x] = std::remainder(q[2 * x], 2.0 * M_PI);
+        a.q[2 * x + 1] = std::remainder(q[2 * x + 1], 2.0 * M_PI);
     }
     a.hop_t = hop_t;
     a.mu = mu;

@@ -31,7 +31,7 @@ struct KArgs {
     const double *k;
     int64_t stride_k;
     double q[2 * kMaxExtDev];
-    int q_big;                  // |q| too large for the reduced sin/cos
+    int q_big;                  // unused (q is reduced modulo 2 pi on the host)
     double hop_t, mu;
     const double *ext_freqs;
     int n_f;
@@ -71,16 +71,15 @@ __device__ __forceinline__ void hubbard_energies(const KArgs &a, int64_t sc, dou
     const int ni = EXACT ? NI : a.tb.n_int;
     const int ng = EXACT ? NE : a.tb.n_g;
     const int nx = a.tb.n_ext;
+    // momenta reduced into [-pi, pi] (q is reduced on the host): every K_j then
+    // stays within the range of the reduced sin/cos
     double kx[NI > 0 ? NI : 1], ky[NI > 0 ? NI : 1];
     const double *row = a.k + sc * a.stride_k;
-    bool big = false;
 #pragma unroll
     for (int l = 0; l < NI; ++l) {
-        kx[l] = (l < ni) ? row[2 * l] : 0.0;
-        ky[l] = (l < ni) ? row[2 * l + 1] : 0.0;
-        big |= fabs(kx[l]) > 1e4 || fabs(ky[l]) > 1e4;
+        kx[l] = (l < ni) ? reduce_2pi(row[2 * l]) : 0.0;
+        ky[l] = (l < ni) ? reduce_2pi(row[2 * l + 1]) : 0.0;
     }
-    const bool slow = __any(big) || a.q_big;
     cu32 line = (cu32)(a.tb.line);
 #pragma unroll
     for (int j = 0; j < NE; ++j) {
@@ -116,22 +115,14 @@ __device__ __forceinline__ void hubbard_energies(const KArgs &a, int64_t sc, dou
             double cx, cy;
             if (KEEP) {            // the adjoint needs sin K as well
                 double sx, sy;
-                if (!slow) {
-                    sincos_red(Kx, sx, cx);
-                    sincos_red(Ky, sy, cy);
-                } else {
-                    sincos(Kx, &sx, &cx);
-                    sincos(Ky, &sy, &cy);
-                }
+                sincos_red(Kx, sx, cx);
+                sincos_red(Ky, sy, cy);
                 sKx[j] = sx;
                 sKy[j] = sy;
                 cs[j] = cx + cy;
-            } else if (!slow) {
+            } else {
                 cx = cos_red(Kx);
                 cy = cos_red(Ky);
-            } else {
-                cx = cos(Kx);
-                cy = cos(Ky);
             }
             E[j] = fma(2.0 * a.hop_t, cx + cy, a.mu);
         }

@@ -11,7 +11,9 @@ int main(int argc, char **argv) {
     const char *what = argv[1];
     double x;
     while (std::scanf("%lf", &x) == 1) {
-        if (what[0] == 'c') {
+        if (what[0] == 'r') {
+            std::printf("%.17g\n", ami::reduce_2pi(x));
+        } else if (what[0] == 'c') {
             std::printf("%.17g\n", ami::cos_red(x));
         } else if (what[0] == 's') {
             double s, c;

@@ -60,6 +60,19 @@ def test_cos_reduced(exe):
         assert abs(c - float(mp.cos(mp.mpf(float(x))))) <= 4 * 2.0 ** -52 * max(1.0, abs(x) * 2.0 ** -20)
 
 
+def test_reduce_2pi(exe):
+    """x - 2 pi rint(x / 2 pi) to a few ulp of pi for |x| up to 6e6."""
+    mp.mp.dps = 50
+    rng = np.random.default_rng(2)
+    xs = np.concatenate([rng.uniform(-10, 10, 200), rng.uniform(-6e6, 6e6, 200), [0.0, np.pi, -np.pi]])
+    got = _run(exe, "r", xs)
+    for x, (r,) in zip(xs, got):
+        X = mp.mpf(float(x))
+        n = mp.nint(X / (2 * mp.pi))
+        want = X - 2 * mp.pi * n
+        assert abs(r - float(want)) <= 8 * 2.0 ** -52 * 4, (x, r, want)
+
+
 def test_exp_split(exe):
     mp.mp.dps = 40
     xs = np.concatenate([-np.logspace(-12, np.log10(700.0), 300), np.logspace(-12, np.log10(700.0), 300),
