@@ -10,12 +10,15 @@ Workload (one step = one pass of the evaluation path over one batch):
   The step evaluates out[N_F, N_E] and its Monte-Carlo row sum out_sum[N_F]
   (forward) and the gradients of the summed integrand with respect to every
   momentum component, mu, t, beta and the external frequency (adjoint), in one
-  pass of the adjoint kernel with values.
+  pass of the adjoint kernel with values.  The kernels are the diagram's own
+  specialized ones (generated and compiled at run time, before the timed
+  region).
 
 Metric: term-evaluations/s = T * N_E * N_F / (seconds per step), T the number
-of canonical flat terms; the forward alone and the plain double-table kernel
-are reported beside it.  Also reported: the algorithmic FP64 FLOP rate of the
-dominant kernel against the FP64 vector peak, and the oracle timed on host
+of canonical flat terms; the forward alone, the table-driven (packed) kernels
+and the plain double-table kernel are reported beside it.  Also reported: the
+algorithmic FP64 FLOP rate of the dominant kernel (timed alone with HIP events
+on its stream) against the FP64 vector peak, and the oracle timed on host
 cores.  Prints one JSON line.
 """
 from __future__ import annotations
@@ -175,12 +178,14 @@ def batch_section(args, torch, dev):
             ts.append(a0.elapsed_time(a1))
         return sorted(ts)[len(ts) // 2]
 
+    for it in items:
+        it["terms"].set_variant(amd.VARIANT_PACKED)
     sep_ms = timed(separate)
     for it in items:
-        it["terms"].set_variant(1)
+        it["terms"].set_variant(amd.VARIANT_TABLES)
     plain_ms = timed(separate)
     for it in items:
-        it["terms"].set_variant(0)
+        it["terms"].set_variant(amd.VARIANT_AUTO)
     return {
         "workload": f"64 seeded self-energy diagrams, orders 2-6 (13/13/13/13/12), {n_f} Matsubara "
                     f"frequencies, {n_e} k-samples each, beta={beta}, out[N_F,N_E] + row sums",
@@ -215,6 +220,14 @@ def main():
     construct_ms = (time.perf_counter() - t0) * 1e3
     info = terms.info()
     terms.upload()
+    # generate and compile (or load from the disk cache) the specialized kernels
+    t0 = time.perf_counter()
+    try:
+        terms.specialize(momentum=True)
+        specialize_note = "ok"
+    except amd.AmiError as e:          # AUTO then runs the packed kernels; reported below
+        specialize_note = str(e)
+    specialize_ms = (time.perf_counter() - t0) * 1e3
     st = rl.structure_from_canonical(terms.canonical())
 
     hop_t, mu = 1.0, 0.0
@@ -253,27 +266,27 @@ def main():
         torch.cuda.synchronize()
         del src, dst
 
-    for _ in range(args.warmup):
+    for _ in range(max(args.warmup, 1)):
         step()
     torch.cuda.synchronize()
+    step_variant = amd.last_variant()
 
-    # timed region: K steps, HIP events around every launch on the launch stream
-    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
-          for _ in range(args.steps)]
+    # timed region: K steps; the library records HIP events on the launch
+    # stream around the main kernel of every step
     start = torch.cuda.Event(enable_timing=True)
     stop = torch.cuda.Event(enable_timing=True)
     torch.cuda.synchronize()
+    amd.kernel_timer_start(args.steps)
     wall0 = time.perf_counter()
     start.record(stream)
     for i in range(args.steps):
-        ev[i][0].record(stream)
         step()
-        ev[i][1].record(stream)
     stop.record(stream)
     torch.cuda.synchronize()
     wall = time.perf_counter() - wall0
+    kernel_ms = amd.kernel_timer_stop()
     ms_step = start.elapsed_time(stop) / args.steps
-    step_kernel_ms = sum(a.elapsed_time(b) for a, b in ev) / args.steps
+    step_kernel_ms = sum(kernel_ms) / len(kernel_ms)
 
     def timed(fn, reps):
         fn()
@@ -293,8 +306,15 @@ def main():
     fwd_variant = amd.last_variant()
     adj_ms = timed(adj, reps)
 
+    # the table-driven (packed) kernels on the same launches
+    terms.set_variant(amd.VARIANT_PACKED)
+    packed_fwd_ms = timed(fwd, reps)
+    packed_variant = amd.last_variant()
+    packed_step_ms = timed(step, reps)
+    terms.set_variant(amd.VARIANT_AUTO)
+
     # the plain per-diagram kernel (double tables) on the same launch, outside the timed region
-    terms.set_variant(1)
+    terms.set_variant(amd.VARIANT_TABLES)
     for _ in range(2):
         fwd()
     torch.cuda.synchronize()
@@ -308,16 +328,25 @@ def main():
     torch.cuda.synchronize()
     plain_ms = p0.elapsed_time(p1) / n_plain
     plain_variant = amd.last_variant()
-    terms.set_variant(0)
+    terms.set_variant(amd.VARIANT_AUTO)
 
     te = float(info["T"]) * n_e * n_f
     value = te / (ms_step * 1e-3)
-    fl = rl.forward_flops(st, n_e, n_f, d.alpha)
-    fa = rl.adjoint_flops(st, n_e, n_f, d.alpha)
-    fs = rl.adjoint_flops(st, n_e, n_f, d.alpha, with_values=True)
-    # the step is one launch of the adjoint kernel with values (+ two reductions)
-    dom, dom_key, dom_ms, dom_fl = ("ami_adj_packed with values (+ its reduction kernels)",
-                                    "ami_adj_packed", step_kernel_ms, fs["total"])
+    spec = step_variant.startswith("specialized")
+    if spec:
+        fl = rl.specialized_forward_flops(st, n_e, n_f, d.alpha)
+        fa = rl.specialized_adjoint_flops(st, n_e, n_f, d.alpha)
+        fs = rl.specialized_adjoint_flops(st, n_e, n_f, d.alpha, with_values=True)
+        dom, dom_key = "ami_jit_adj (specialized adjoint with values)", "ami_jit_adj"
+    else:
+        fl = rl.forward_flops(st, n_e, n_f, d.alpha)
+        fa = rl.adjoint_flops(st, n_e, n_f, d.alpha)
+        fs = rl.adjoint_flops(st, n_e, n_f, d.alpha, with_values=True)
+        dom, dom_key = "ami_adj_packed (packed adjoint with values)", "ami_adj_packed"
+    pfl = rl.forward_flops(st, n_e, n_f, d.alpha)
+    pfs = rl.adjoint_flops(st, n_e, n_f, d.alpha, with_values=True)
+    # the step's main kernel: the adjoint with values, timed alone
+    dom_ms, dom_fl = step_kernel_ms, fs["total"]
     achieved = dom_fl / (dom_ms * 1e-3)
     workload_key = f"order{args.order}-diagram{args.diagram}-ne{n_e}-nf{n_f}-beta{args.beta:g}"
     traffic = recorded_traffic(dom_key, workload_key)
@@ -349,11 +378,17 @@ def main():
         "fwd": {"ms": fwd_ms, "term_evals_per_s": te / (fwd_ms * 1e-3), "kernel": fwd_variant,
                 "flops": fl["total"], "tflops": fl["total"] / (fwd_ms * 1e-3) / 1e12,
                 "frac_fp64_peak": fl["total"] / (fwd_ms * 1e-3) / rl.PEAK_FP64_VECTOR},
-        "fwd_adjoint": {"one_pass_ms": step_kernel_ms,
-                        "one_pass_term_evals_per_s": te / (step_kernel_ms * 1e-3),
+        "fwd_adjoint": {"one_pass_ms": ms_step, "one_pass_kernel_ms": step_kernel_ms,
+                        "one_pass_term_evals_per_s": te / (ms_step * 1e-3), "kernel": step_variant,
                         "separate_ms": fwd_ms + adj_ms, "adjoint_ms": adj_ms,
                         "adjoint_flops": fa["total"],
                         "adjoint_tflops": fa["total"] / (adj_ms * 1e-3) / 1e12},
+        "packed_kernels": {"fwd_ms": packed_fwd_ms, "kernel": packed_variant,
+                           "fwd_tflops": pfl["total"] / (packed_fwd_ms * 1e-3) / 1e12,
+                           "step_ms": packed_step_ms,
+                           "step_term_evals_per_s": te / (packed_step_ms * 1e-3),
+                           "step_tflops": pfs["total"] / (packed_step_ms * 1e-3) / 1e12,
+                           "speedup_of_specialized_step": packed_step_ms / ms_step},
         "plain_kernel": {"ms": plain_ms, "term_evals_per_s": te / (plain_ms * 1e-3),
                          "kernel": plain_variant, "speedup_of_fwd": plain_ms / fwd_ms},
         "roofline": {
@@ -369,6 +404,7 @@ def main():
             "kernel_ms": dom_ms,
         },
         "construct_ms": construct_ms,
+        "specialize_ms": specialize_ms, "specialize": specialize_note,
         "wall_s": wall,
     }
     if not args.no_batch:

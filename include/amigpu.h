@@ -90,7 +90,9 @@ void amiFree(AmiTerms *terms);
  *   8 tree nodes of the factorized Fermi tree (0 unless built with AMI_FACTORIZE)
  *   9 raw terms before canonical merging
  *   10 leaves per term (= n_int)   11 denominators per term (= n_g - n_int)
- *   12..15 reserved (0)
+ *   12 packed form available (1/0)   13 the packed kernels build Fermi leaves
+ *      from products of exp(beta E_i) (1/0)
+ *   14..15 reserved (0)
  */
 AmiStatus amiTermsInfo(const AmiTerms *terms, int64_t info[16]);
 
@@ -205,11 +207,62 @@ AmiStatus amiEvaluateHubbardAdjoint(AmiTerms *terms,
                                     double *out, double *out_sum, void *hip_stream);
 
 /*
- * amiSetVariant -- choose the forward kernel of a handle: 0 (default) the
- * packed evaluator whenever the solution has the packed form, 1 the plain
- * double-table evaluator (any coefficients; used as the per-diagram baseline).
+ * Kernel variants of a handle (amiSetVariant).  All evaluate the same
+ * solution (Sec. 2.3); they differ in how the term tables reach the kernel:
+ *   AMI_VARIANT_AUTO         (default) specialized when the solution has at
+ *                            most 1024 flat terms (128 for the adjoint) and at
+ *                            most 16 energies and its kernels compile, else
+ *                            packed when the solution
+ *                            has the packed form (+-1 coefficients, at most 255
+ *                            leaves/denominators, 8 per term), else tables
+ *   AMI_VARIANT_TABLES       one generic kernel over double-valued tables
+ *                            (forward only, any coefficients; the per-diagram
+ *                            baseline)
+ *   AMI_VARIANT_PACKED       bit-mask tables read by kernels specialized per
+ *                            self-energy shape
+ *   AMI_VARIANT_SPECIALIZED  the diagram's own straight-line kernels, generated
+ *                            from its tables and compiled at run time (hipRTC)
+ *                            on first use -- or by amiTermsSpecialize -- and
+ *                            cached on disk (AMIGPU_CACHE_DIR, else
+ *                            $HOME/.cache/amigpu/jit)
+ * A forced variant that cannot serve a call fails it (AMI_E_UNSUPPORTED, or
+ * AMI_E_HIP when the run-time compilation fails); AUTO falls back in the order
+ * above and amiLastVariant names what ran and why.
  */
+enum { AMI_VARIANT_AUTO = 0, AMI_VARIANT_TABLES = 1, AMI_VARIANT_PACKED = 2, AMI_VARIANT_SPECIALIZED = 3 };
+
 AmiStatus amiSetVariant(AmiTerms *terms, int32_t variant);
+
+/*
+ * amiTermsSpecialize -- compile (or load from the disk cache) the specialized
+ * kernels of a handle for the energy (momentum = 0) or momentum (momentum = 1)
+ * input and load them on the current device, so that the compilation stays
+ * out of later evaluate calls.  Host-blocking.  AMI_E_UNSUPPORTED when the
+ * solution is outside the specialized form, AMI_E_HIP when compiling or loading
+ * fails (amiLastError holds the compiler log).
+ */
+AmiStatus amiTermsSpecialize(AmiTerms *terms, int32_t momentum);
+
+/*
+ * amiTermsSource -- the generated device source of the specialized kernels
+ * (energy input: momentum = 0; momentum input: 1), NUL-terminated, into buf
+ * (host, capacity cap bytes; *len receives the size including the NUL, also
+ * when buf is NULL).  The source includes the library's device headers by
+ * name (device_common.hpp, kargs.hpp, jit_kernel.hpp).  AMI_E_UNSUPPORTED when
+ * the solution is outside the specialized form, AMI_E_ARG when cap is too small.
+ */
+AmiStatus amiTermsSource(const AmiTerms *terms, int32_t momentum, char *buf, int64_t cap, int64_t *len);
+
+/*
+ * Kernel timer (measurement): after amiKernelTimerStart(capacity), every
+ * evaluate and adjoint call on this thread records a pair of HIP events on its
+ * stream around its main kernel (the first `capacity` calls; the row-sum and
+ * gradient reduction kernels stay outside).  amiKernelTimerStop waits for the
+ * recorded events, writes up to `cap` durations in milliseconds to ms (host)
+ * in call order, the number recorded to *count, and releases the events.
+ */
+AmiStatus amiKernelTimerStart(int32_t capacity);
+AmiStatus amiKernelTimerStop(float *ms, int32_t cap, int32_t *count);
 
 /* Name of the kernel variant launched by the last evaluate call on this thread. */
 const char *amiLastVariant(void);

@@ -10,10 +10,11 @@ The library must have been built (``paper_2311_17189_amd.build.build()`` or
 ``__graft_entry__.build()``); the first call into it raises ImportError
 otherwise (there is no fallback path).
 """
-from ._lib import (AmiError, Batch, Terms, evaluate, evaluate_adjoint,  # noqa: F401
-                   evaluate_hubbard, evaluate_hubbard_adjoint, last_variant,
-                   lib_path, load_library, version)
+from ._lib import (VARIANT_AUTO, VARIANT_PACKED, VARIANT_SPECIALIZED,  # noqa: F401
+                   VARIANT_TABLES, AmiError, Batch, Terms, evaluate, evaluate_adjoint,
+                   evaluate_hubbard, evaluate_hubbard_adjoint, kernel_timer_start, kernel_timer_stop,
+                   last_variant, lib_path, load_library, version)
 
-__all__ = ["AmiError", "Batch", "Terms", "evaluate", "evaluate_adjoint", "evaluate_hubbard",
-           "evaluate_hubbard_adjoint", "last_variant", "lib_path", "load_library",
+__all__ = ["VARIANT_AUTO", "VARIANT_PACKED", "VARIANT_SPECIALIZED", "VARIANT_TABLES", "AmiError", "Batch", "Terms", "evaluate", "evaluate_adjoint", "evaluate_hubbard",
+           "evaluate_hubbard_adjoint", "kernel_timer_start", "kernel_timer_stop", "last_variant", "lib_path", "load_library",
            "version"]

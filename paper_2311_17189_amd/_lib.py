@@ -90,6 +90,14 @@ def load_library():
     lib.amiEvaluateHubbardAdjoint.restype = c_i32
     lib.amiSetVariant.argtypes = [vp, c_i32]
     lib.amiSetVariant.restype = c_i32
+    lib.amiTermsSpecialize.argtypes = [vp, c_i32]
+    lib.amiTermsSpecialize.restype = c_i32
+    lib.amiTermsSource.argtypes = [vp, c_i32, ctypes.c_char_p, c_i64, ctypes.POINTER(c_i64)]
+    lib.amiTermsSource.restype = c_i32
+    lib.amiKernelTimerStart.argtypes = [c_i32]
+    lib.amiKernelTimerStart.restype = c_i32
+    lib.amiKernelTimerStop.argtypes = [vp, c_i32, ctypes.POINTER(c_i32)]
+    lib.amiKernelTimerStop.restype = c_i32
     lib.amiLastVariant.argtypes = []
     lib.amiLastVariant.restype = ctypes.c_char_p
     lib.amiBatchCreate.argtypes = [ctypes.POINTER(AmiBatchItem), c_i32, ctypes.POINTER(AmiBatchTuning),
@@ -117,6 +125,30 @@ def _check(code: int):
 
 def version() -> str:
     return load_library().amiVersion().decode()
+
+
+_timer_capacity = 0
+
+
+def kernel_timer_start(capacity: int):
+    """Record HIP events around the main kernel of the next ``capacity``
+    evaluate/adjoint calls on this thread (``amiKernelTimerStart``)."""
+    global _timer_capacity
+    _check(load_library().amiKernelTimerStart(int(capacity)))
+    _timer_capacity = int(capacity)
+
+
+def kernel_timer_stop() -> list:
+    """Durations (ms) of the recorded kernels, in call order (``amiKernelTimerStop``)."""
+    lib = load_library()
+    buf = (ctypes.c_float * max(_timer_capacity, 1))()
+    n = ctypes.c_int32()
+    _check(lib.amiKernelTimerStop(buf, max(_timer_capacity, 1), ctypes.byref(n)))
+    return [float(buf[i]) for i in range(min(n.value, _timer_capacity))]
+
+
+# kernel variants (amiSetVariant)
+VARIANT_AUTO, VARIANT_TABLES, VARIANT_PACKED, VARIANT_SPECIALIZED = 0, 1, 2, 3
 
 
 def last_variant() -> str:
@@ -165,7 +197,7 @@ class Terms:
         buf = np.zeros(16, dtype=np.int64)
         _check(load_library().amiTermsInfo(self._h, buf.ctypes.data))
         keys = ["T", "n_int", "n_eps", "n_freq", "n_ext", "L", "D", "G", "tree_nodes",
-                "raw_terms", "leaves_per_term", "dens_per_term"]
+                "raw_terms", "leaves_per_term", "dens_per_term", "packable", "products"]
         return {k: int(buf[i]) for i, k in enumerate(keys)}
 
     def canonical(self, from_tree: bool = False) -> np.ndarray:
@@ -180,8 +212,23 @@ class Terms:
         _check(load_library().amiTermsUpload(self._h))
 
     def set_variant(self, variant: int):
-        """0: packed kernels when possible (default); 1: the plain double-table kernel."""
+        """Kernel variant (``amiSetVariant``): VARIANT_AUTO (default), VARIANT_TABLES,
+        VARIANT_PACKED or VARIANT_SPECIALIZED."""
         _check(load_library().amiSetVariant(self._h, int(variant)))
+
+    def specialize(self, momentum: bool = True):
+        """Compile (or load from the disk cache) and load the specialized kernels
+        (``amiTermsSpecialize``) so later calls do not compile."""
+        _check(load_library().amiTermsSpecialize(self._h, int(bool(momentum))))
+
+    def source(self, momentum: bool = True) -> str:
+        """Generated device source of the specialized kernels (``amiTermsSource``)."""
+        lib = load_library()
+        n = ctypes.c_int64()
+        _check(lib.amiTermsSource(self._h, int(bool(momentum)), None, 0, ctypes.byref(n)))
+        buf = ctypes.create_string_buffer(n.value)
+        _check(lib.amiTermsSource(self._h, int(bool(momentum)), buf, n.value, ctypes.byref(n)))
+        return buf.value.decode()
 
     def close(self):
         if getattr(self, "_h", None) is not None and self._h.value:

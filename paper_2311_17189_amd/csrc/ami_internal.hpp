@@ -91,7 +91,7 @@ struct Tables {
 struct AmiTerms {
     int n_g = 0, n_eps = 0, n_freq = 0, n_int = 0, n_ext = 0;
     uint32_t flags = 0;
-    int variant = 0;                         // 0 packed kernels when possible, 1 double-table kernel
+    int variant = 0;                         // AMI_VARIANT_* (amigpu.h)
     std::vector<int8_t> alpha, eps;
     std::vector<uint8_t> fermionic;
     int64_t raw_terms = 0;
@@ -101,6 +101,16 @@ struct AmiTerms {
     ami::Tables tab;
     std::mutex dev_mu;
     std::vector<ami::DeviceTables> dev;      // uploaded copies
+    // run-time specialized kernels: code objects per (input, kernel) -- index
+    // 2 * momentum + adjoint -- and the modules loaded from them, one per device
+    std::mutex jit_mu;
+    std::vector<char> jit_code[4];
+    std::string jit_error[4];                // why a compilation failed (not retried)
+    struct JitModule {
+        int device = -1, kind = 0;
+        void *module = nullptr, *fn = nullptr;
+    };
+    std::vector<JitModule> jit_mods;
 };
 
 namespace ami {

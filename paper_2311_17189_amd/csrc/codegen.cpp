@@ -1,0 +1,311 @@
+// Source generator of the run-time specialized evaluator: writes the
+// diagram's evaluation tables (leaves, denominators, groups, terms and
+// momentum lines, built by build_tables) out as straight-line device code for
+// the kernels of jit_kernel.hpp.  Sums over coefficients keep the order of the
+// table-driven evaluators (index order, first term as +v or -v) and products
+// their left-to-right association; every fused multiply-add is written out
+// (the code is compiled without contraction), so the forward and adjoint
+// kernels of a diagram compute the same values bit for bit.
+#include <cstdio>
+#include <cstdlib>
+#include <cstring>
+#include <sstream>
+#include <string>
+#include <vector>
+
+#include "ami_internal.hpp"
+#include "jit.hpp"
+
+namespace ami {
+
+namespace {
+
+std::string num(double v) {
+    char b[40];
+    std::snprintf(b, sizeof(b), "%.17g", v);
+    std::string s(b);
+    if (s.find_first_of(".eEn") == std::string::npos) s += ".0";
+    return s;
+}
+
+// sum_i c_i v[i] over the non-zero coefficients, in index order: "+-v" for
+// unit coefficients, fma for others; "0.0" when every coefficient is zero.
+struct Lin {
+    std::string expr;
+    void add(double c, const std::string &v) {
+        if (c == 0.0) return;
+        if (expr.empty()) {
+            if (c == 1.0) expr = v;
+            else if (c == -1.0) expr = "(-" + v + ")";
+            else expr = "(" + num(c) + " * " + v + ")";
+        } else {
+            if (c == 1.0) expr = "(" + expr + " + " + v + ")";
+            else if (c == -1.0) expr = "(" + expr + " - " + v + ")";
+            else expr = "fma(" + num(c) + ", " + v + ", " + expr + ")";
+        }
+    }
+    std::string str() const { return expr.empty() ? "0.0" : expr; }
+};
+
+std::string idx(const char *a, int i) { return std::string(a) + "[" + std::to_string(i) + "]"; }
+
+}  // namespace
+
+bool jit_supported(const AmiTerms *t, bool hub, std::string *why) {
+    const Tables &tb = t->tab;
+    auto no = [&](const std::string &m) {
+        if (why) *why = m;
+        return false;
+    };
+    if (tb.L < 1 || tb.G < 1 || tb.D < 1) return no("solution without leaves or denominators");
+    if (t->n_eps > kMaxEpsDev) return no("more than 16 energies");
+    if (t->n_ext > kMaxExt) return no("more than 4 external slots");
+    if (hub && t->n_g != t->n_eps) return no("momentum input needs one energy per line");
+    if (tb.T > kJitMaxTerms) return no("more than " + std::to_string(kJitMaxTerms) + " terms");
+    return true;
+}
+
+namespace {
+
+// Adjoint values parked in LDS instead of registers: the momentum chain
+// rule's 3 per line, and the leaf derivatives while both fit in 40 doubles
+// per lane (two resident blocks of 256 lanes per CU).
+constexpr int kParkBudget = 40;
+int park_chain(const AmiTerms *t, bool hub) { return hub ? 3 * t->n_g : 0; }
+bool park_dv(const AmiTerms *t, bool hub) { return park_chain(t, hub) + t->tab.L <= kParkBudget; }
+int park_cols(const AmiTerms *t, bool hub) { return park_chain(t, hub) + (park_dv(t, hub) ? t->tab.L : 0); }
+
+// occupancy hint for the adjoint (waves per SIMD), AMIGPU_JIT_ADJ_WAVES
+int adj_waves() {
+    const char *e = std::getenv("AMIGPU_JIT_ADJ_WAVES");
+    if (!e) return 0;
+    const int v = std::atoi(e);
+    return (v >= 0 && v <= 8) ? v : 0;
+}
+
+}  // namespace
+
+// 256 lanes while the adjoint's parked columns fit in 80 KB per block (two
+// blocks per CU), else 128
+int jit_block(const AmiTerms *t, bool hub) { return park_cols(t, hub) * 256 * 8 <= 80 * 1024 ? 256 : 128; }
+
+std::string jit_source(const AmiTerms *t, bool hub, int kernels) {
+    const Tables &tb = t->tab;
+    const int ne = t->n_eps, ni = t->n_int, ng = t->n_g, nx = t->n_ext, nf = t->n_freq;
+    const int L = tb.L, D = tb.D, G = tb.G, dpt = tb.dpt;
+    const int nc = ne + nx;
+    std::ostringstream o;
+    o << "// generated: specialized AMI evaluator, " << tb.T << " terms, " << L << " leaves, " << D
+      << " denominators, " << G << " groups\n";
+    o << "#define AMI_JIT_HUB " << (hub ? "true" : "false") << "\n";
+    o << "#define AMI_JIT_KERNELS " << kernels << "\n";
+    o << "#define AMI_JIT_BLOCK " << jit_block(t, hub) << "\n";
+    o << "#define AMI_JIT_PARK_DV " << (park_dv(t, hub) ? "true" : "false") << "\n";
+    o << "#define AMI_JIT_ADJ_WAVES " << adj_waves() << "\n";
+    o << "#include \"kargs.hpp\"\n";
+    o << "namespace amijit {\n";
+    o << "constexpr int NE = " << ne << ", NI = " << ni << ", NG = " << ng << ", NX = " << nx << ";\n";
+    o << "constexpr int L = " << L << ", D = " << D << ", G = " << G << ";\n";
+    o << "constexpr bool kBose[L] = {";
+    for (int l = 0; l < L; ++l) o << (l ? ", " : "") << (tb.leaf_sigma[l] < 0 ? "true" : "false");
+    o << "};\n";
+    const std::string NXA = "(NX > 0 ? NX : 1)", NIA = "(NI > 0 ? NI : 1)", NGA = "(NG > 0 ? NG : 1)";
+
+    // momentum lines: K_j = sum_l alpha_jl k_l over the loops, then + q of the external slots
+    o << "__device__ __forceinline__ void lines(const double (&kx)[" << NIA << "], const double (&ky)[" << NIA
+      << "], const double *q, double (&Kx)[" << NGA << "], double (&Ky)[" << NGA << "]) {\n";
+    if (hub) {
+        for (int j = 0; j < ng; ++j) {
+            Lin ax, ay;
+            for (int l = 0; l < ni; ++l) {
+                const double a = tb.line_alpha[static_cast<size_t>(j) * nf + l];
+                ax.add(a, idx("kx", l));
+                ay.add(a, idx("ky", l));
+            }
+            for (int x = 0; x < nx; ++x) {
+                const double a = tb.line_alpha[static_cast<size_t>(j) * nf + ni + x];
+                ax.add(a, idx("q", 2 * x));
+                ay.add(a, idx("q", 2 * x + 1));
+            }
+            o << "  Kx[" << j << "] = " << ax.str() << ";\n  Ky[" << j << "] = " << ay.str() << ";\n";
+        }
+    }
+    o << "}\n";
+
+    // leaf arguments x_l = sum_i c_li E_i
+    o << "__device__ __forceinline__ void leaf_args(const double (&E)[NE], double (&x)[L]) {\n";
+    for (int l = 0; l < L; ++l) {
+        Lin s;
+        for (int i = 0; i < ne; ++i) s.add(tb.leaf_coef[static_cast<size_t>(l) * ne + i], idx("E", i));
+        o << "  x[" << l << "] = " << s.str() << ";\n";
+    }
+    o << "}\n";
+
+    // group sums FT_g = sum_t s_t prod f: the product of a term's leaves left
+    // to right, its last factor fused into the accumulation (unit s_t)
+    auto term_product = [&](int ti, int upto) {
+        std::string p;
+        for (int j = 0; j < upto; ++j) {
+            const std::string f = idx("F", tb.term_leaf[static_cast<size_t>(ti) * ni + j]);
+            p = p.empty() ? f : p + " * " + f;
+        }
+        return p.empty() ? std::string("1.0") : p;
+    };
+    o << "__device__ __forceinline__ void group_sums(const double (&F)[L], double (&FT)[G]) {\n";
+    for (int g = 0; g < G; ++g) {
+        o << "  { double ft;\n";
+        for (int ti = tb.group_start[g]; ti < tb.group_start[g + 1]; ++ti) {
+            const double s = tb.term_sign[ti];
+            if (ti == tb.group_start[g]) {
+                const std::string p = term_product(ti, ni);
+                if (s == 1.0) o << "    ft = " << p << ";\n";
+                else if (s == -1.0) o << "    ft = -(" << p << ");\n";
+                else o << "    ft = " << num(s) << " * (" << p << ");\n";
+            } else if ((s == 1.0 || s == -1.0) && ni > 1) {
+                const std::string last = idx("F", tb.term_leaf[static_cast<size_t>(ti) * ni + ni - 1]);
+                o << "    ft = fma(" << (s < 0 ? "-(" : "(") << term_product(ti, ni - 1) << "), " << last
+                  << ", ft);\n";
+            } else {
+                o << "    ft = fma(" << num(s) << ", " << term_product(ti, ni) << ", ft);\n";
+            }
+        }
+        o << "    FT[" << g << "] = ft; }\n";
+    }
+    o << "}\n";
+
+    // denominators D_k = e_k . E + a_k . w
+    o << "__device__ __forceinline__ void den_args(const double (&E)[NE], const double (&wr)[" << NXA
+      << "], const double (&wi)[" << NXA << "], double (&dr)[D], double (&di)[D]) {\n";
+    for (int k = 0; k < D; ++k) {
+        Lin re, im;
+        for (int i = 0; i < ne; ++i) re.add(tb.den_coef[static_cast<size_t>(k) * nc + i], idx("E", i));
+        for (int x = 0; x < nx; ++x) {
+            const double a = tb.den_coef[static_cast<size_t>(k) * nc + ne + x];
+            re.add(a, idx("wr", x));
+            im.add(a, idx("wi", x));
+        }
+        o << "  dr[" << k << "] = " << re.str() << ";\n  di[" << k << "] = " << im.str() << ";\n";
+    }
+    o << "}\n";
+
+    // group products R_g = prod rho_k (complex), left to right
+    o << "__device__ __forceinline__ void group_products(const double (&xr)[D], const double (&xi)[D], double (&Rr)[G], "
+         "double (&Ri)[G]) {\n";
+    for (int g = 0; g < G; ++g) {
+        o << "  { double rr = 1.0, ri = 0.0, nr = 0.0;\n";
+        for (int j = 0; j < dpt; ++j) {
+            const int k = tb.group_dens[static_cast<size_t>(g) * dpt + j];
+            if (j == 0) {
+                o << "    rr = xr[" << k << "]; ri = xi[" << k << "];\n";
+            } else {
+                o << "    nr = fma(rr, xr[" << k << "], -ri * xi[" << k << "]); ri = fma(rr, xi[" << k
+                  << "], ri * xr[" << k << "]); rr = nr;\n";
+            }
+        }
+        o << "    (void)nr; Rr[" << g << "] = rr; Ri[" << g << "] = ri; }\n";
+    }
+    o << "}\n";
+
+    // U_k = sum over the occurrences of k in the groups of u_g
+    std::vector<std::vector<int>> occ(D);
+    for (int g = 0; g < G; ++g)
+        for (int j = 0; j < dpt; ++j) occ[tb.group_dens[static_cast<size_t>(g) * dpt + j]].push_back(g);
+    o << "__device__ __forceinline__ void den_cotangents(const double (&ur)[G], const double (&ui)[G], double "
+         "(&Ur)[D], double (&Ui)[D]) {\n";
+    for (int k = 0; k < D; ++k) {
+        Lin r, i;
+        for (int g : occ[k]) {
+            r.add(1.0, idx("ur", g));
+            i.add(1.0, idx("ui", g));
+        }
+        o << "  Ur[" << k << "] = " << r.str() << ";\n  Ui[" << k << "] = " << i.str() << ";\n";
+    }
+    o << "}\n";
+
+    // dL/dE_i += e_ki dR_k ; dL/dw_x += a_kx (dR_k, dI_k)
+    auto scatter = [&](std::ostream &os, double c, const std::string &dst, const std::string &v) {
+        if (c == 0.0) return;
+        if (c == 1.0) os << "  " << dst << " += " << v << ";\n";
+        else if (c == -1.0) os << "  " << dst << " -= " << v << ";\n";
+        else os << "  " << dst << " = fma(" << num(c) << ", " << v << ", " << dst << ");\n";
+    };
+    o << "__device__ __forceinline__ void den_scatter(const double (&dR)[D], const double (&dI)[D], double (&gE)[NE], "
+         "double (&gwr)["
+      << NXA << "], double (&gwi)[" << NXA << "]) {\n";
+    for (int k = 0; k < D; ++k) {
+        for (int i = 0; i < ne; ++i) scatter(o, tb.den_coef[static_cast<size_t>(k) * nc + i], idx("gE", i), idx("dR", k));
+        for (int x = 0; x < nx; ++x) {
+            const double a = tb.den_coef[static_cast<size_t>(k) * nc + ne + x];
+            scatter(o, a, idx("gwr", x), idx("dR", k));
+            scatter(o, a, idx("gwi", x), idx("dI", k));
+        }
+    }
+    o << "}\n";
+
+    // leaf cotangents by prefix/suffix products over each term's leaves
+    o << "__device__ __forceinline__ void leaf_cotangents(const double (&F)[L], const double (&FTB)[G], double "
+         "(&FB)[L]) {\n";
+    for (int g = 0; g < G; ++g) {
+        for (int ti = tb.group_start[g]; ti < tb.group_start[g + 1]; ++ti) {
+            const double s = tb.term_sign[ti];
+            std::vector<int> lv(ni);
+            for (int j = 0; j < ni; ++j) lv[j] = tb.term_leaf[static_cast<size_t>(ti) * ni + j];
+            o << "  { const double p0 = ";
+            if (s == 1.0) o << "FTB[" << g << "]";
+            else if (s == -1.0) o << "-FTB[" << g << "]";
+            else o << "FTB[" << g << "] * " << num(s);
+            o << ";\n";
+            for (int j = 1; j < ni; ++j)
+                o << "    const double p" << j << " = p" << j - 1 << " * F[" << lv[j - 1] << "];\n";
+            o << "    double q = 1.0;\n";
+            for (int j = ni - 1; j >= 0; --j) {
+                if (j == ni - 1) o << "    FB[" << lv[j] << "] += p" << j << ";\n";
+                else o << "    FB[" << lv[j] << "] = fma(p" << j << ", q, FB[" << lv[j] << "]);\n";
+                if (j > 0) {
+                    if (j == ni - 1) o << "    q = F[" << lv[j] << "];\n";
+                    else o << "    q *= F[" << lv[j] << "];\n";
+                }
+            }
+            o << "    (void)q; }\n";
+        }
+    }
+    o << "}\n";
+
+    // dL/dE_i += sum_l c_li v_l
+    o << "__device__ __forceinline__ void leaf_scatter(const double (&v)[L], double (&gE)[NE]) {\n";
+    for (int l = 0; l < L; ++l)
+        for (int i = 0; i < ne; ++i) scatter(o, tb.leaf_coef[static_cast<size_t>(l) * ne + i], idx("gE", i), idx("v", l));
+    o << "}\n";
+
+    // dL/dk_l += sum_j alpha_jl dL/dK_j
+    o << "__device__ __forceinline__ void line_scatter(const double (&gx)[" << NGA << "], const double (&gy)[" << NGA
+      << "], double (&gkx)[" << NIA << "], double (&gky)[" << NIA << "]) {\n";
+    if (hub) {
+        for (int j = 0; j < ng; ++j)
+            for (int l = 0; l < ni; ++l) {
+                const double a = tb.line_alpha[static_cast<size_t>(j) * nf + l];
+                scatter(o, a, idx("gkx", l), idx("gx", j));
+                scatter(o, a, idx("gky", l), idx("gy", j));
+            }
+    }
+    o << "}\n";
+    o << "}  // namespace amijit\n";
+    o << "#include \"jit_kernel.hpp\"\n";
+    return o.str();
+}
+
+}  // namespace ami
+
+extern "C" AmiStatus amiTermsSource(const AmiTerms *t, int32_t momentum, char *buf, int64_t cap, int64_t *len) {
+    using namespace ami;
+    clear_error();
+    if (!t || !len) return fail(AMI_E_ARG, "NULL argument");
+    std::string why;
+    if (!jit_supported(t, momentum != 0, &why)) return fail(AMI_E_UNSUPPORTED, "no specialized kernel: " + why);
+    const std::string src = jit_source(t, momentum != 0, 3);
+    *len = static_cast<int64_t>(src.size()) + 1;
+    if (!buf) return AMI_OK;
+    if (cap < *len) return fail(AMI_E_ARG, "buffer too small");
+    std::memcpy(buf, src.c_str(), src.size() + 1);
+    return AMI_OK;
+}

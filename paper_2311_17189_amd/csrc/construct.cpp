@@ -610,6 +610,8 @@ AmiStatus amiTermsInfo(const AmiTerms *t, int64_t info[16]) {
     info[9] = t->raw_terms;
     info[10] = t->n_int;
     info[11] = t->n_g - t->n_int;
+    info[12] = t->tab.packable ? 1 : 0;
+    info[13] = t->tab.use_products ? 1 : 0;
     return AMI_OK;
 }
 

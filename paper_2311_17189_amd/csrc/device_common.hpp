@@ -5,9 +5,19 @@
 // scalar bit tests: only the non-zero coefficients cost vector instructions.
 #pragma once
 
+#ifndef __HIPCC_RTC__
 #include <hip/hip_runtime.h>
 
 #include <cstdint>
+#else
+// compiled at run time (hipRTC): no standard headers
+typedef __hip_internal::uint64_t uint64_t;
+typedef __hip_internal::int64_t int64_t;
+typedef __hip_internal::uint32_t uint32_t;
+typedef __hip_internal::int32_t int32_t;
+typedef __hip_internal::uint8_t uint8_t;
+typedef __hip_internal::int8_t int8_t;
+#endif
 
 namespace ami {
 
@@ -219,6 +229,28 @@ __device__ __forceinline__ double wave_sum(double v) {
 #pragma unroll
     for (int off = 32; off >= 1; off >>= 1) v += __shfl_xor(v, off, 64);
     return v;
+}
+
+// Block sum of (vr, vi) into dst[0..1], deterministic; every lane must call it.
+__device__ __forceinline__ void block_sum2(double vr, double vi, double *red, int tid, int B, double *dst) {
+    vr = wave_sum(vr);
+    vi = wave_sum(vi);
+    const int wave = tid >> 6, nwaves = B >> 6;
+    if ((tid & 63) == 0) {
+        red[2 * wave] = vr;
+        red[2 * wave + 1] = vi;
+    }
+    __syncthreads();
+    if (tid == 0) {
+        double sr = 0.0, si = 0.0;
+        for (int w = 0; w < nwaves; ++w) {
+            sr += red[2 * w];
+            si += red[2 * w + 1];
+        }
+        dst[0] = sr;
+        dst[1] = si;
+    }
+    __syncthreads();
 }
 
 }  // namespace ami

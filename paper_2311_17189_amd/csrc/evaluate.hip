@@ -16,10 +16,12 @@
 #include <cstring>
 #include <mutex>
 #include <string>
+#include <vector>
 
 #include "ami_internal.hpp"
 #include "device_common.hpp"
 #include "kernel_generic.hpp"
+#include "jit.hpp"
 #include "kernels_packed.hpp"
 #include "runtime.hpp"
 
@@ -304,19 +306,82 @@ AmiStatus launch_generic_forward(AmiTerms *t, DeviceTables *dt, bool hub, const 
     return AMI_OK;
 }
 
-thread_local const char *g_last_variant = "";
+thread_local std::string g_last_variant;
 
-AmiStatus launch_forward(AmiTerms *t, bool hub, KArgs &a, double *out_sum, hipStream_t stream,
-                         bool force_generic) {
+// Optional HIP-event timing of the main evaluation kernel of each call on
+// this thread (amiKernelTimerStart / amiKernelTimerStop).
+struct KernelTimer {
+    bool on = false;
+    std::vector<hipEvent_t> ev;      // start/stop pairs
+    int used = 0;
+};
+thread_local KernelTimer g_timer;
+
+void timer_mark(hipStream_t stream, bool stop) {
+    if (!g_timer.on || g_timer.used >= static_cast<int>(g_timer.ev.size()) / 2) return;
+    (void)hipEventRecord(g_timer.ev[2 * g_timer.used + (stop ? 1 : 0)], stream);
+    if (stop) ++g_timer.used;
+}
+
+enum class Path { TABLES, PACKED, SPECIALIZED };
+
+// Which kernels serve a call (AMI_VARIANT_* of the handle); for the
+// specialized path also loads them.  AUTO falls back and records why.
+AmiStatus choose_path(AmiTerms *t, bool hub, bool adjoint, Path &p, void **jit_fn, std::string &note) {
+    const int v = t->variant;
+    note.clear();
+    const bool auto_skip = v == AMI_VARIANT_AUTO && adjoint && t->tab.T > kJitAutoAdjointTerms;
+    if (auto_skip) note = " (adjoint specialized up to " + std::to_string(kJitAutoAdjointTerms) + " terms)";
+    if (v == AMI_VARIANT_SPECIALIZED || (v == AMI_VARIANT_AUTO && !auto_skip)) {
+        const AmiStatus st = jit_get(t, hub, adjoint, jit_fn);
+        if (st == AMI_OK) {
+            p = Path::SPECIALIZED;
+            return AMI_OK;
+        }
+        if (v == AMI_VARIANT_SPECIALIZED) return st;
+        note = std::string(" (not specialized: ") + amiLastError() + ")";
+        clear_error();
+    }
+    if (v == AMI_VARIANT_TABLES) {
+        if (adjoint) return fail(AMI_E_UNSUPPORTED, "the double-table variant has no adjoint");
+        p = Path::TABLES;
+        return AMI_OK;
+    }
+    if (t->tab.packable) {
+        p = Path::PACKED;
+        return AMI_OK;
+    }
+    if (v == AMI_VARIANT_PACKED || adjoint)
+        return fail(AMI_E_UNSUPPORTED,
+                    "the packed kernels need +-1 coefficients and at most 255 leaves/denominators" + note);
+    p = Path::TABLES;
+    return AMI_OK;
+}
+
+hipError_t launch_jit(void *fn, int64_t nblocks, int block, hipStream_t stream, KArgs &a) {
+    void *params[] = {&a};
+    return hipModuleLaunchKernel(static_cast<hipFunction_t>(fn), static_cast<unsigned>(nblocks), 1, 1,
+                                 static_cast<unsigned>(block), 1, 1, 0, stream, params, nullptr);
+}
+
+AmiStatus launch_forward(AmiTerms *t, bool hub, KArgs &a, double *out_sum, hipStream_t stream) {
     DeviceTables *dt = nullptr;
     AmiStatus st = upload(t, &dt);
     if (st != AMI_OK) return st;
     const Tables &tb = t->tab;
     if (a.n_e == 0) return fill(out_sum, 2 * static_cast<int64_t>(a.n_f), stream);
-    const bool packed = tb.packable && !force_generic;
-    LaunchShape ls;
-    st = pick_shape(fwd_slots(tb), ls);
+    Path path;
+    void *jit_fn = nullptr;
+    std::string note;
+    st = choose_path(t, hub, false, path, &jit_fn, note);
     if (st != AMI_OK) return st;
+    LaunchShape ls;
+    if (path == Path::SPECIALIZED) {
+        ls.block = jit_block(t, hub);
+    } else {
+        st = pick_shape(fwd_slots(tb), ls);
+        if (st != AMI_OK) return st;
+    }
     const int64_t nblocks = (a.n_e + ls.block - 1) / ls.block;
     if (nblocks > 0x7fffffffLL) return fail(AMI_E_ARG, "n_e too large");
     double *partial = nullptr;
@@ -327,17 +392,26 @@ AmiStatus launch_forward(AmiTerms *t, bool hub, KArgs &a, double *out_sum, hipSt
         if (e != hipSuccess) return fail(AMI_E_OOM, std::string("workspace: ") + hipGetErrorString(e));
     }
     const dim3 grid(static_cast<unsigned>(nblocks)), block(ls.block);
-    if (packed) {
+    timer_mark(stream, false);
+    if (path == Path::SPECIALIZED) {
+        a.partial = partial;
+        e = launch_jit(jit_fn, nblocks, ls.block, stream, a);
+        g_last_variant = "specialized";
+        if (e == hipSuccess) e = hipGetLastError();
+    } else if (path == Path::PACKED) {
         a.tb = packed_tabs(t, dt);
         a.slots = ls.slots;
         a.partial = partial;
-        g_last_variant = hub ? launch_packed<false, true>(t, grid, block, ls.lds, stream, a)
-                             : launch_packed<false, false>(t, grid, block, ls.lds, stream, a);
+        g_last_variant = std::string("packed ") +
+                         (hub ? launch_packed<false, true>(t, grid, block, ls.lds, stream, a)
+                              : launch_packed<false, false>(t, grid, block, ls.lds, stream, a)) + note;
+        e = hipGetLastError();
     } else {
         launch_generic_forward(t, dt, hub, a, partial, ls, grid, stream);
-        g_last_variant = "double tables";
+        g_last_variant = "double tables" + note;
+        e = hipGetLastError();
     }
-    e = hipGetLastError();
+    timer_mark(stream, true);
     if (e != hipSuccess) {
         if (partial) (void)hipFreeAsync(partial, stream);
         return hip_fail(e, "forward launch");
@@ -362,8 +436,6 @@ AmiStatus launch_adjoint(AmiTerms *t, bool hub, KArgs &a, const AdjOut &o, hipSt
     AmiStatus st = upload(t, &dt);
     if (st != AMI_OK) return st;
     const Tables &tb = t->tab;
-    if (!tb.packable)
-        return fail(AMI_E_UNSUPPORTED, "the adjoint needs +-1 coefficients and at most 255 leaves/denominators");
     const int nx = t->n_ext;
     const int ncols = kAdjScalars + 2 * a.n_f * nx;
     if (a.n_e == 0) {
@@ -375,9 +447,18 @@ AmiStatus launch_adjoint(AmiTerms *t, bool hub, KArgs &a, const AdjOut &o, hipSt
         if (st != AMI_OK) return st;
         return fill(o.grad_freqs, 2 * static_cast<int64_t>(a.n_f) * nx, stream);
     }
-    LaunchShape ls;
-    st = pick_shape(adj_slots(tb), ls);
+    Path path;
+    void *jit_fn = nullptr;
+    std::string note;
+    st = choose_path(t, hub, true, path, &jit_fn, note);
     if (st != AMI_OK) return st;
+    LaunchShape ls;
+    if (path == Path::SPECIALIZED) {
+        ls.block = jit_block(t, hub);
+    } else {
+        st = pick_shape(adj_slots(tb), ls);
+        if (st != AMI_OK) return st;
+    }
     const int64_t nblocks = (a.n_e + ls.block - 1) / ls.block;
     if (nblocks > 0x7fffffffLL) return fail(AMI_E_ARG, "n_e too large");
     double *partial = nullptr;
@@ -385,14 +466,23 @@ AmiStatus launch_adjoint(AmiTerms *t, bool hub, KArgs &a, const AdjOut &o, hipSt
     const size_t n_val = o.out_sum ? static_cast<size_t>(nblocks) * a.n_f * 2 : 0;
     hipError_t e = hipMallocAsync(reinterpret_cast<void **>(&partial), (n_grad + n_val) * sizeof(double), stream);
     if (e != hipSuccess) return fail(AMI_E_OOM, std::string("workspace: ") + hipGetErrorString(e));
-    a.tb = packed_tabs(t, dt);
-    a.slots = ls.slots;
     a.gpartial = partial;
     a.partial = o.out_sum ? partial + n_grad : nullptr;
     const dim3 grid(static_cast<unsigned>(nblocks)), block(ls.block);
-    g_last_variant = hub ? launch_packed<true, true>(t, grid, block, ls.lds, stream, a)
-                         : launch_packed<true, false>(t, grid, block, ls.lds, stream, a);
-    e = hipGetLastError();
+    timer_mark(stream, false);
+    if (path == Path::SPECIALIZED) {
+        e = launch_jit(jit_fn, nblocks, ls.block, stream, a);
+        g_last_variant = "specialized";
+        if (e == hipSuccess) e = hipGetLastError();
+    } else {
+        a.tb = packed_tabs(t, dt);
+        a.slots = ls.slots;
+        g_last_variant = std::string("packed ") +
+                         (hub ? launch_packed<true, true>(t, grid, block, ls.lds, stream, a)
+                              : launch_packed<true, false>(t, grid, block, ls.lds, stream, a)) + note;
+        e = hipGetLastError();
+    }
+    timer_mark(stream, true);
     if (e != hipSuccess) {
         (void)hipFreeAsync(partial, stream);
         return hip_fail(e, "adjoint launch");
@@ -478,6 +568,7 @@ void amiFree(AmiTerms *t) {
     for (auto &d : t->dev)
         if (d.blob && hipSetDevice(d.device) == hipSuccess) (void)hipFree(d.blob);
     if (have_cur) (void)hipSetDevice(cur);
+    ami::jit_release(t);
     delete t;
 }
 
@@ -497,7 +588,7 @@ AmiStatus amiEvaluate(AmiTerms *t, const double *energies, int64_t n_e, int64_t 
     a.stride_i = stride_i;
     set_common(a, ext_freqs, n_f, beta, e_reg, n_e);
     a.out = out;
-    return launch_forward(t, false, a, out_sum, static_cast<hipStream_t>(hip_stream), t->variant == 1);
+    return launch_forward(t, false, a, out_sum, static_cast<hipStream_t>(hip_stream));
 }
 
 AmiStatus amiEvaluateHubbard(AmiTerms *t, const double *k, int64_t n_e, int64_t stride_k, const double *q,
@@ -514,7 +605,7 @@ AmiStatus amiEvaluateHubbard(AmiTerms *t, const double *k, int64_t n_e, int64_t 
     set_momenta(a, t, k, stride_k, q, hop_t, mu);
     set_common(a, ext_freqs, n_f, beta, e_reg, n_e);
     a.out = out;
-    return launch_forward(t, true, a, out_sum, static_cast<hipStream_t>(hip_stream), t->variant == 1);
+    return launch_forward(t, true, a, out_sum, static_cast<hipStream_t>(hip_stream));
 }
 
 AmiStatus amiEvaluateAdjoint(AmiTerms *t, const double *energies, int64_t n_e, int64_t stride_s,
@@ -576,11 +667,65 @@ AmiStatus amiEvaluateHubbardAdjoint(AmiTerms *t, const double *k, int64_t n_e, i
 AmiStatus amiSetVariant(AmiTerms *t, int32_t variant) {
     ami::clear_error();
     if (!t) return ami::fail(AMI_E_ARG, "terms is NULL");
-    if (variant != 0 && variant != 1) return ami::fail(AMI_E_ARG, "variant must be 0 or 1");
+    if (variant < AMI_VARIANT_AUTO || variant > AMI_VARIANT_SPECIALIZED)
+        return ami::fail(AMI_E_ARG, "variant must be one of AMI_VARIANT_*");
     t->variant = variant;
     return AMI_OK;
 }
 
-const char *amiLastVariant(void) { return ami::g_last_variant; }
+AmiStatus amiTermsSpecialize(AmiTerms *t, int32_t momentum) {
+    ami::clear_error();
+    if (!t) return ami::fail(AMI_E_ARG, "terms is NULL");
+    void *fn = nullptr;
+    const AmiStatus st = ami::jit_get(t, momentum != 0, false, &fn);
+    if (st != AMI_OK) return st;
+    return ami::jit_get(t, momentum != 0, true, &fn);
+}
+
+const char *amiLastVariant(void) { return ami::g_last_variant.c_str(); }
+
+AmiStatus amiKernelTimerStart(int32_t capacity) {
+    using namespace ami;
+    clear_error();
+    if (capacity < 1 || capacity > (1 << 20)) return fail(AMI_E_ARG, "capacity must be in 1..2^20");
+    if (g_timer.on) return fail(AMI_E_ARG, "the kernel timer is already running on this thread");
+    g_timer.ev.assign(2 * static_cast<size_t>(capacity), nullptr);
+    for (size_t i = 0; i < g_timer.ev.size(); ++i) {
+        const hipError_t e = hipEventCreate(&g_timer.ev[i]);
+        if (e != hipSuccess) {
+            for (size_t j = 0; j < i; ++j) (void)hipEventDestroy(g_timer.ev[j]);
+            g_timer.ev.clear();
+            return hip_fail(e, "hipEventCreate");
+        }
+    }
+    g_timer.used = 0;
+    g_timer.on = true;
+    return AMI_OK;
+}
+
+AmiStatus amiKernelTimerStop(float *ms, int32_t cap, int32_t *count) {
+    using namespace ami;
+    clear_error();
+    if (!g_timer.on) return fail(AMI_E_ARG, "the kernel timer is not running on this thread");
+    AmiStatus st = AMI_OK;
+    int n = 0;
+    for (int i = 0; i < g_timer.used; ++i) {
+        hipError_t e = hipEventSynchronize(g_timer.ev[2 * i + 1]);
+        float v = 0.0f;
+        if (e == hipSuccess) e = hipEventElapsedTime(&v, g_timer.ev[2 * i], g_timer.ev[2 * i + 1]);
+        if (e != hipSuccess) {
+            st = hip_fail(e, "kernel timer events");
+            break;
+        }
+        if (ms && n < cap) ms[n] = v;
+        ++n;
+    }
+    for (hipEvent_t ev : g_timer.ev) (void)hipEventDestroy(ev);
+    g_timer.ev.clear();
+    g_timer.used = 0;
+    g_timer.on = false;
+    if (count) *count = n;
+    return st;
+}
 
 }  // extern "C"

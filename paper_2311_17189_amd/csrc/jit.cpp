@@ -1,0 +1,216 @@
+// Compilation, caching and loading of the run-time specialized evaluator.
+//
+// The generated source (codegen.cpp) and the embedded device headers
+// (device_common.hpp, kargs.hpp, jit_kernel.hpp, built into the library as
+// strings) are compiled for gfx950 with hipRTC under the flags the library
+// itself is built with.  Code objects are kept per handle and on disk, keyed
+// by a hash of everything that goes into the compilation, so a diagram is
+// compiled once per machine; the source is stored beside each code object and
+// compared on every hit.
+#include <hip/hip_runtime.h>
+#include <hip/hiprtc.h>
+#include <sys/stat.h>
+#include <unistd.h>
+
+#include <cerrno>
+#include <cstdio>
+#include <cstdlib>
+#include <cstring>
+#include <fstream>
+#include <iterator>
+#include <mutex>
+#include <string>
+#include <vector>
+
+#include "jit.hpp"
+#include "runtime.hpp"
+
+#include "jit_headers.inc"   // kJitHeaderCount, kJitHeaderNames[], kJitHeaderTexts[] (generated at build)
+
+namespace ami {
+
+namespace {
+
+const char *const kOptions[] = {"--offload-arch=gfx950", "-O3", "-std=c++17", "-ffp-contract=off",
+                                // keep the compiler away from packed FP32 instructions
+                                "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops"};
+constexpr int kNumOptions = static_cast<int>(sizeof(kOptions) / sizeof(kOptions[0]));
+
+uint64_t fnv1a(const std::string &s, uint64_t h) {
+    for (unsigned char c : s) {
+        h ^= c;
+        h *= 1099511628211ull;
+    }
+    return h;
+}
+
+std::string cache_key(const std::string &src) {
+    int major = 0, minor = 0;
+    (void)hiprtcVersion(&major, &minor);
+    std::string all = "amigpu-jit-1|" + std::to_string(major) + "." + std::to_string(minor) + "|";
+    for (int i = 0; i < kNumOptions; ++i) all += std::string(kOptions[i]) + "|";
+    for (int i = 0; i < kJitHeaderCount; ++i) all += std::string(kJitHeaderNames[i]) + "|" + kJitHeaderTexts[i] + "|";
+    all += src;
+    char b[40];
+    std::snprintf(b, sizeof(b), "%016llx%016llx", static_cast<unsigned long long>(fnv1a(all, 1469598103934665603ull)),
+                  static_cast<unsigned long long>(fnv1a(all, 0x9e3779b97f4a7c15ull)));
+    return b;
+}
+
+bool make_dirs(const std::string &path) {
+    std::string cur;
+    for (size_t i = 0; i <= path.size(); ++i) {
+        if (i == path.size() || path[i] == '/') {
+            if (!cur.empty() && ::mkdir(cur.c_str(), 0755) != 0 && errno != EEXIST) return false;
+        }
+        if (i < path.size()) cur += path[i];
+    }
+    return true;
+}
+
+// AMIGPU_CACHE_DIR, else $HOME/.cache/amigpu/jit; empty (no disk cache) when
+// neither can be created
+std::string cache_dir() {
+    std::string d;
+    if (const char *e = std::getenv("AMIGPU_CACHE_DIR")) {
+        d = e;
+    } else if (const char *h = std::getenv("HOME")) {
+        d = std::string(h) + "/.cache/amigpu/jit";
+    }
+    if (d.empty() || !make_dirs(d)) return std::string();
+    return d;
+}
+
+bool read_file(const std::string &path, std::vector<char> &out) {
+    std::ifstream f(path, std::ios::binary);
+    if (!f) return false;
+    out.assign(std::istreambuf_iterator<char>(f), std::istreambuf_iterator<char>());
+    return static_cast<bool>(f) || f.eof();
+}
+
+void write_file_atomic(const std::string &path, const char *data, size_t n) {
+    const std::string tmp = path + ".tmp" + std::to_string(::getpid());
+    {
+        std::ofstream f(tmp, std::ios::binary);
+        if (!f) return;
+        f.write(data, static_cast<std::streamsize>(n));
+        if (!f) {
+            std::remove(tmp.c_str());
+            return;
+        }
+    }
+    if (std::rename(tmp.c_str(), path.c_str()) != 0) std::remove(tmp.c_str());
+}
+
+AmiStatus compile(const std::string &src, std::vector<char> &code, std::string &err) {
+    hiprtcProgram prog;
+    hiprtcResult r = hiprtcCreateProgram(&prog, src.c_str(), "ami_jit.hip", kJitHeaderCount, kJitHeaderTexts,
+                                         kJitHeaderNames);
+    if (r != HIPRTC_SUCCESS) {
+        err = std::string("hiprtcCreateProgram: ") + hiprtcGetErrorString(r);
+        return AMI_E_HIP;
+    }
+    r = hiprtcCompileProgram(prog, kNumOptions, kOptions);
+    if (r != HIPRTC_SUCCESS) {
+        size_t n = 0;
+        std::string log;
+        if (hiprtcGetProgramLogSize(prog, &n) == HIPRTC_SUCCESS && n > 0) {
+            log.resize(n);
+            (void)hiprtcGetProgramLog(prog, &log[0]);
+        }
+        if (log.size() > 4000) log.resize(4000);
+        err = std::string("specialized kernel compilation failed: ") + hiprtcGetErrorString(r) + "\n" + log;
+        (void)hiprtcDestroyProgram(&prog);
+        return AMI_E_HIP;
+    }
+    size_t n = 0;
+    r = hiprtcGetCodeSize(prog, &n);
+    if (r == HIPRTC_SUCCESS) {
+        code.resize(n);
+        r = hiprtcGetCode(prog, code.data());
+    }
+    (void)hiprtcDestroyProgram(&prog);
+    if (r != HIPRTC_SUCCESS || code.empty()) {
+        err = std::string("hiprtcGetCode: ") + hiprtcGetErrorString(r);
+        code.clear();
+        return AMI_E_HIP;
+    }
+    return AMI_OK;
+}
+
+// Code object for (t, kind): from the handle, the disk cache, or a compilation.
+AmiStatus code_object(AmiTerms *t, bool hub, bool adjoint) {
+    const int kind = 2 * (hub ? 1 : 0) + (adjoint ? 1 : 0);
+    std::vector<char> &code = t->jit_code[kind];
+    if (!code.empty()) return AMI_OK;
+    std::string &err = t->jit_error[kind];
+    if (!err.empty()) return fail(AMI_E_UNSUPPORTED, err);
+    std::string why;
+    if (!jit_supported(t, hub, &why)) {
+        err = "no specialized kernel: " + why;
+        return fail(AMI_E_UNSUPPORTED, err);
+    }
+    const std::string src = jit_source(t, hub, adjoint ? 2 : 1);
+    const std::string dir = cache_dir();
+    const std::string base = dir.empty() ? std::string() : dir + "/" + cache_key(src);
+    if (!base.empty()) {
+        std::vector<char> stored_src;
+        if (read_file(base + ".hip", stored_src) && std::string(stored_src.begin(), stored_src.end()) == src &&
+            read_file(base + ".hsaco", code) && !code.empty())
+            return AMI_OK;
+        code.clear();
+    }
+    const AmiStatus st = compile(src, code, err);
+    if (st != AMI_OK) return fail(st, err);
+    if (!base.empty()) {
+        write_file_atomic(base + ".hsaco", code.data(), code.size());
+        write_file_atomic(base + ".hip", src.data(), src.size());
+    }
+    return AMI_OK;
+}
+
+}  // namespace
+
+AmiStatus jit_get(AmiTerms *t, bool hub, bool adjoint, void **fn) {
+    std::lock_guard<std::mutex> lock(t->jit_mu);
+    const int kind = 2 * (hub ? 1 : 0) + (adjoint ? 1 : 0);
+    // the compilation needs no device: do it first
+    AmiStatus st = code_object(t, hub, adjoint);
+    if (st != AMI_OK) return st;
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return hip_fail(e, "hipGetDevice");
+    for (const auto &m : t->jit_mods)
+        if (m.device == dev && m.kind == kind) {
+            *fn = m.fn;
+            return AMI_OK;
+        }
+    hipModule_t mod = nullptr;
+    e = hipModuleLoadData(&mod, t->jit_code[kind].data());
+    if (e != hipSuccess) return hip_fail(e, "hipModuleLoadData (specialized kernel)");
+    hipFunction_t f = nullptr;
+    e = hipModuleGetFunction(&f, mod, adjoint ? "ami_jit_adj" : "ami_jit_fwd");
+    if (e != hipSuccess) {
+        (void)hipModuleUnload(mod);
+        return hip_fail(e, "hipModuleGetFunction (specialized kernel)");
+    }
+    AmiTerms::JitModule m;
+    m.device = dev;
+    m.kind = kind;
+    m.module = mod;
+    m.fn = reinterpret_cast<void *>(f);
+    t->jit_mods.push_back(m);
+    *fn = m.fn;
+    return AMI_OK;
+}
+
+void jit_release(AmiTerms *t) {
+    int cur = 0;
+    const bool have_cur = hipGetDevice(&cur) == hipSuccess;
+    for (auto &m : t->jit_mods)
+        if (m.module && hipSetDevice(m.device) == hipSuccess) (void)hipModuleUnload(static_cast<hipModule_t>(m.module));
+    t->jit_mods.clear();
+    if (have_cur) (void)hipSetDevice(cur);
+}
+
+}  // namespace ami

@@ -1,0 +1,310 @@
+// Kernels of the run-time specialized evaluator (compiled with hipRTC).
+//
+// The skeleton is the one of the packed evaluators (kernels_packed.hpp), one
+// lane per energy sample, but every table walk is replaced by the diagram's own
+// straight-line code: the generated part that precedes this file defines, in
+// namespace amijit, the sizes NE (energies), NI (loops), NG (lines), NX
+// (external slots), L (distinct leaves), D (distinct denominators), G (groups),
+// the leaf kinds kBose[L], and the functions
+//   lines            K_j = sum_l alpha_jl k_l (+ external q), per component
+//   leaf_args        x_l = sum_i c_li E_i                        (Sec. 2.2)
+//   group_sums       FT_g = sum_{t in g} s_t prod_{l in t} f_l     (Sec. 2.3)
+//   den_args         D_k = e_k . E + a_k . w                        (Sec. 2.2)
+//   group_products   R_g = prod_{k in g} 1/D_k
+//   den_cotangents   U_k = sum_{g contains k} u_g
+//   den_scatter      dL/dE_i += e_ki Re(U_k rho_k), dL/dw_x += a_kx U_k rho_k
+//   leaf_cotangents  dL/df_l = sum_{t contains l} dL/dFT_g(t) s_t prod_{l' != l} f_l'
+//   leaf_scatter     dL/dE_i += sum_l c_li v_l
+//   line_scatter     dL/dk_l += sum_j alpha_jl dL/dK_j
+// With every index a constant, all per-sample state lives in registers: no
+// LDS beyond the block reduction, no table reads, no scalar bit tests.
+// Block partial sums use the packed evaluators' layouts, so the same
+// reduction kernels finish them.
+#pragma once
+
+namespace amijit {
+
+using ami::KArgs;
+
+constexpr int NXA = NX > 0 ? NX : 1;
+constexpr int NIA = NI > 0 ? NI : 1;
+constexpr int NGA = NG > 0 ? NG : 1;
+static_assert(!AMI_JIT_HUB || NG == NE, "momentum input: one energy per line");
+
+// Adjoint LDS columns per lane: the chain-rule values of the momentum input
+// (3 NG), then, with AMI_JIT_PARK_DV, the leaf derivatives f'(y_l) (L).
+constexpr int kParkChain = AMI_JIT_HUB ? 3 * NG : 0;
+constexpr bool kParkDv = AMI_JIT_PARK_DV;
+constexpr int kParkCols = kParkChain + (kParkDv ? L : 0);
+
+// E from the sample's energies or momenta.  With KEEP (adjoint, momentum
+// input) sin K_jx, sin K_jy and cos K_jx + cos K_jy, needed only by the final
+// chain rule, are parked in LDS columns (park[(c NG + j) B + tid], c = 0, 1, 2)
+// rather than held in registers through the frequency loop.
+template <bool HUB, bool KEEP>
+__device__ __forceinline__ void energies(const KArgs &a, int64_t sc, double (&E)[NE], double *park) {
+    if constexpr (HUB) {
+        // E_j = 2t(cos K_jx + cos K_jy) + mu (Sec. 5.2), momenta reduced into [-pi, pi]
+        double kx[NIA], ky[NIA];
+        const double *row = a.k + sc * a.stride_k;
+#pragma unroll
+        for (int l = 0; l < NI; ++l) {
+            kx[l] = ami::reduce_2pi(row[2 * l]);
+            ky[l] = ami::reduce_2pi(row[2 * l + 1]);
+        }
+        double Kx[NGA], Ky[NGA];
+        lines(kx, ky, a.q, Kx, Ky);
+#pragma unroll
+        for (int j = 0; j < NG; ++j) {
+            double cx, cy;
+            if constexpr (KEEP) {
+                double sx, sy;
+                ami::sincos_red(Kx[j], sx, cx);
+                ami::sincos_red(Ky[j], sy, cy);
+                const int tid = threadIdx.x, B = blockDim.x;
+                park[j * B + tid] = sx;
+                park[(NG + j) * B + tid] = sy;
+                park[(2 * NG + j) * B + tid] = cx + cy;
+            } else {
+                cx = ami::cos_red(Kx[j]);
+                cy = ami::cos_red(Ky[j]);
+            }
+            E[j] = fma(2.0 * a.hop_t, cx + cy, a.mu);
+        }
+    } else {
+        const double *row = a.energies + sc * a.stride_s;
+#pragma unroll
+        for (int i = 0; i < NE; ++i) E[i] = row[i * a.stride_i];
+    }
+}
+
+__device__ __forceinline__ void load_freq(const KArgs &a, int f, double (&wr)[NXA], double (&wi)[NXA]) {
+    ami::cdbl fr = (ami::cdbl)(a.ext_freqs);      // wave-uniform: scalar loads
+#pragma unroll
+    for (int x = 0; x < NXA; ++x) {
+        wr[x] = (x < NX) ? fr[2 * (f * NX + x)] : 0.0;
+        wi[x] = (x < NX) ? fr[2 * (f * NX + x) + 1] : 0.0;
+    }
+}
+
+// complex reciprocals rho_k = 1/D_k of every distinct denominator
+__device__ __forceinline__ void reciprocals(const double (&E)[NE], const double (&wr)[NXA], const double (&wi)[NXA],
+                                            double (&xr)[D], double (&xi)[D]) {
+    double dr[D], di[D];
+    den_args(E, wr, wi, dr, di);
+#pragma unroll
+    for (int k = 0; k < D; ++k) {
+        const double inv = ami::rcp_nr(fma(dr[k], dr[k], di[k] * di[k]));
+        xr[k] = dr[k] * inv;
+        xi[k] = -di[k] * inv;
+    }
+}
+
+template <bool HUB>
+__device__ __forceinline__ void fwd_tile(const KArgs &a, int64_t tile, double *red) {
+    const int tid = threadIdx.x, B = blockDim.x;
+    const int64_t s = tile * B + tid;
+    const bool active = s < a.n_e;
+    const int64_t sc = active ? s : a.n_e - 1;
+
+    double E[NE];
+    energies<HUB, false>(a, sc, E, nullptr);
+    double x[L], F[L];
+    leaf_args(E, x);
+#pragma unroll
+    for (int l = 0; l < L; ++l) {
+        double fm;
+        if (kBose[l]) ami::leaf_pair(true, a.beta * (x[l] + a.e_reg), F[l], fm);
+        else ami::leaf_pair(false, a.beta * x[l], F[l], fm);
+    }
+    double FT[G];
+    group_sums(F, FT);
+
+    for (int f = 0; f < a.n_f; ++f) {
+        double wr[NXA], wi[NXA], xr[D], xi[D], Rr[G], Ri[G];
+        load_freq(a, f, wr, wi);
+        reciprocals(E, wr, wi, xr, xi);
+        group_products(xr, xi, Rr, Ri);
+        double acc_re = 0.0, acc_im = 0.0;
+#pragma unroll
+        for (int g = 0; g < G; ++g) {
+            acc_re = fma(FT[g], Rr[g], acc_re);
+            acc_im = fma(FT[g], Ri[g], acc_im);
+        }
+        if (active && a.out) {
+            double2 v;
+            v.x = acc_re;
+            v.y = acc_im;
+            reinterpret_cast<double2 *>(a.out)[static_cast<int64_t>(f) * a.n_e + s] = v;
+        }
+        if (a.partial)
+            ami::block_sum2(active ? acc_re : 0.0, active ? acc_im : 0.0, red, tid, B,
+                            a.partial + (tile * a.n_f + f) * 2);
+    }
+}
+
+// Adjoint of L = Re sum_{f,s} conj(c[f,s]) I[f,s] (the packed adjoint's
+// derivation), with the denominator cotangents collected per distinct
+// denominator: dL/dD_k = -rho_k sum_{g contains k} FT_g conj(c) R_g.
+// The leaf arguments x_l are recomputed after the frequency loop instead of
+// being kept live through it.
+template <bool HUB>
+__device__ __forceinline__ void adj_tile(const KArgs &a, int64_t blk, double *red, double *park) {
+    const int tid = threadIdx.x, B = blockDim.x;
+    const int64_t s = blk * B + tid;
+    const bool active = s < a.n_e;
+    const int64_t sc = active ? s : a.n_e - 1;
+
+    double E[NE];
+    energies<HUB, HUB>(a, sc, E, park);
+    double F[L], Dv[kParkDv ? 1 : L];
+    {
+        double x[L];
+        leaf_args(E, x);
+#pragma unroll
+        for (int l = 0; l < L; ++l) {
+            if (kBose[l]) x[l] += a.e_reg;
+            double fm;
+            ami::leaf_pair(kBose[l], a.beta * x[l], F[l], fm);
+            const double dv = -(F[l] * fm);     // f'(y) = -f(y) f(-y)
+            if constexpr (kParkDv) park[(kParkChain + l) * B + tid] = dv;
+            else Dv[kParkDv ? 0 : l] = dv;
+        }
+    }
+    double FT[G], FTB[G];
+    group_sums(F, FT);
+#pragma unroll
+    for (int g = 0; g < G; ++g) FTB[g] = 0.0;
+    double gE[NE];
+#pragma unroll
+    for (int i = 0; i < NE; ++i) gE[i] = 0.0;
+    double *gp = a.gpartial + blk * (ami::kAdjScalars + 2 * a.n_f * NX);
+
+    for (int f = 0; f < a.n_f; ++f) {
+        double cr = 0.0, ci = 0.0;
+        if (active) {
+            if (a.g_out) {
+                cr = a.g_out[2 * (static_cast<int64_t>(f) * a.n_e + s)];
+                ci = a.g_out[2 * (static_cast<int64_t>(f) * a.n_e + s) + 1];
+            }
+            if (a.g_sum) {
+                cr += a.g_sum[2 * f];
+                ci += a.g_sum[2 * f + 1];
+            }
+        }
+        double wr[NXA], wi[NXA], xr[D], xi[D], Rr[G], Ri[G];
+        load_freq(a, f, wr, wi);
+        reciprocals(E, wr, wi, xr, xi);
+        group_products(xr, xi, Rr, Ri);
+        double acc_re = 0.0, acc_im = 0.0, ur[G], ui[G];
+#pragma unroll
+        for (int g = 0; g < G; ++g) {
+            FTB[g] += fma(cr, Rr[g], ci * Ri[g]);
+            acc_re = fma(FT[g], Rr[g], acc_re);
+            acc_im = fma(FT[g], Ri[g], acc_im);
+            const double qr = FT[g] * cr, qi = -FT[g] * ci;       // u = -FT conj(c) R
+            ur[g] = -fma(qr, Rr[g], -qi * Ri[g]);
+            ui[g] = -fma(qr, Ri[g], qi * Rr[g]);
+        }
+        double Ur[D], Ui[D], dR[D], dI[D];
+        den_cotangents(ur, ui, Ur, Ui);
+#pragma unroll
+        for (int k = 0; k < D; ++k) {
+            dR[k] = fma(Ur[k], xr[k], -Ui[k] * xi[k]);
+            dI[k] = fma(Ur[k], xi[k], Ui[k] * xr[k]);
+        }
+        double gwr[NXA], gwi[NXA];
+#pragma unroll
+        for (int xx = 0; xx < NXA; ++xx) {
+            gwr[xx] = 0.0;
+            gwi[xx] = 0.0;
+        }
+        den_scatter(dR, dI, gE, gwr, gwi);
+#pragma unroll
+        for (int xx = 0; xx < NX; ++xx)
+            ami::block_sum2(active ? gwr[xx] : 0.0, active ? -gwi[xx] : 0.0, red, tid, B,
+                            gp + ami::kAdjScalars + 2 * (f * NX + xx));
+        if (active && a.out) {
+            double2 v;
+            v.x = acc_re;
+            v.y = acc_im;
+            reinterpret_cast<double2 *>(a.out)[static_cast<int64_t>(f) * a.n_e + s] = v;
+        }
+        if (a.partial)
+            ami::block_sum2(active ? acc_re : 0.0, active ? acc_im : 0.0, red, tid, B,
+                            a.partial + (blk * a.n_f + f) * 2);
+    }
+
+    double FB[L];
+#pragma unroll
+    for (int l = 0; l < L; ++l) FB[l] = 0.0;
+    leaf_cotangents(F, FTB, FB);
+    double gbeta = 0.0, v[L], x[L];
+    leaf_args(E, x);
+#pragma unroll
+    for (int l = 0; l < L; ++l) {
+        if (kBose[l]) x[l] += a.e_reg;
+        const double fb = FB[l] * (kParkDv ? park[(kParkChain + l) * B + tid] : Dv[kParkDv ? 0 : l]);
+        v[l] = fb * a.beta;
+        gbeta = fma(fb, x[l], gbeta);
+    }
+    leaf_scatter(v, gE);
+
+    double gmu = 0.0, gt = 0.0;
+    if constexpr (HUB) {
+        double gx[NGA], gy[NGA], gkx[NIA], gky[NIA];
+#pragma unroll
+        for (int j = 0; j < NG; ++j) {
+            gmu += gE[j];
+            gt = fma(gE[j], 2.0 * park[(2 * NG + j) * B + tid], gt);
+            gx[j] = -2.0 * a.hop_t * gE[j] * park[j * B + tid];
+            gy[j] = -2.0 * a.hop_t * gE[j] * park[(NG + j) * B + tid];
+        }
+#pragma unroll
+        for (int l = 0; l < NIA; ++l) {
+            gkx[l] = 0.0;
+            gky[l] = 0.0;
+        }
+        line_scatter(gx, gy, gkx, gky);
+        if (active && a.grad_k) {
+            double *row = a.grad_k + s * (2 * NI);
+#pragma unroll
+            for (int l = 0; l < NI; ++l) {
+                row[2 * l] = gkx[l];
+                row[2 * l + 1] = gky[l];
+            }
+        }
+    }
+    if (active && a.grad_e) {
+        double *row = a.grad_e + s * NE;
+#pragma unroll
+        for (int i = 0; i < NE; ++i) row[i] = gE[i];
+    }
+    ami::block_sum2(active ? gbeta : 0.0, active ? gmu : 0.0, red, tid, B, gp);
+    ami::block_sum2(active ? gt : 0.0, 0.0, red, tid, B, gp + 2);
+}
+
+}  // namespace amijit
+
+// AMI_JIT_BLOCK lanes per block (the host launches with the same value);
+// AMI_JIT_KERNELS selects the forward (1), the adjoint (2) or both (3)
+#if AMI_JIT_KERNELS & 1
+extern "C" __global__ __launch_bounds__(AMI_JIT_BLOCK) void ami_jit_fwd(ami::KArgs a) {
+    __shared__ double red[2 * (AMI_JIT_BLOCK / 64)];
+    amijit::fwd_tile<AMI_JIT_HUB>(a, blockIdx.x, red);
+}
+#endif
+
+#if AMI_JIT_KERNELS & 2
+#if AMI_JIT_ADJ_WAVES > 0
+#define AMI_JIT_ADJ_ATTR __attribute__((amdgpu_waves_per_eu(AMI_JIT_ADJ_WAVES)))
+#else
+#define AMI_JIT_ADJ_ATTR
+#endif
+
+extern "C" __global__ __launch_bounds__(AMI_JIT_BLOCK) AMI_JIT_ADJ_ATTR void ami_jit_adj(ami::KArgs a) {
+    __shared__ double red[2 * (AMI_JIT_BLOCK / 64)];
+    __shared__ double park[amijit::kParkCols > 0 ? amijit::kParkCols * AMI_JIT_BLOCK : 1];
+    amijit::adj_tile<AMI_JIT_HUB>(a, blockIdx.x, red, park);
+}
+#endif

@@ -1,0 +1,40 @@
+// Argument block of the evaluator kernels (packed, batch and run-time
+// specialized): one struct passed by value, with the same layout on the host
+// and in code compiled at run time.
+#pragma once
+
+#include "device_common.hpp"
+
+namespace ami {
+
+struct KArgs {
+    PackedTabs tb;
+    int slots;                  // LDS slots per lane (before the reduction area)
+    // inputs
+    const double *energies;
+    int64_t stride_s, stride_i;
+    const double *k;
+    int64_t stride_k;
+    double q[2 * kMaxExtDev];
+    int q_big;                  // unused (q is reduced modulo 2 pi on the host)
+    double hop_t, mu;
+    const double *ext_freqs;
+    int n_f;
+    double beta, e_reg;
+    int64_t n_e;
+    // forward outputs
+    double *out;
+    double *partial;            // [grid][n_f][2]
+    // adjoint inputs/outputs
+    const double *g_out;        // complex [n_f][n_e] or NULL
+    const double *g_sum;        // complex [n_f] or NULL
+    double *grad_e;             // [n_e][n_eps] or NULL
+    double *grad_k;             // [n_e][2 n_int] or NULL
+    double *gpartial;           // [grid][kAdjScalars + 2 n_f n_ext]
+};
+
+// Per-block adjoint partial sums: dL/dbeta, dL/dmu, dL/dt, (unused), then
+// dL/dw as complex [n_f][n_ext].
+constexpr int kAdjScalars = 4;
+
+}  // namespace ami

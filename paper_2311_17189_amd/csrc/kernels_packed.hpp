@@ -19,38 +19,10 @@
 #include <cstdint>
 
 #include "device_common.hpp"
+#include "kargs.hpp"
 
 namespace ami {
 
-struct KArgs {
-    PackedTabs tb;
-    int slots;                  // LDS slots per lane (before the reduction area)
-    // inputs
-    const double *energies;
-    int64_t stride_s, stride_i;
-    const double *k;
-    int64_t stride_k;
-    double q[2 * kMaxExtDev];
-    int q_big;                  // unused (q is reduced modulo 2 pi on the host)
-    double hop_t, mu;
-    const double *ext_freqs;
-    int n_f;
-    double beta, e_reg;
-    int64_t n_e;
-    // forward outputs
-    double *out;
-    double *partial;            // [grid][n_f][2]
-    // adjoint inputs/outputs
-    const double *g_out;        // complex [n_f][n_e] or NULL
-    const double *g_sum;        // complex [n_f] or NULL
-    double *grad_e;             // [n_e][n_eps] or NULL
-    double *grad_k;             // [n_e][2 n_int] or NULL
-    double *gpartial;           // [grid][kAdjScalars + 2 n_f n_ext]
-};
-
-// Per-block adjoint partial sums: dL/dbeta, dL/dmu, dL/dt, (unused), then
-// dL/dw as complex [n_f][n_ext].
-constexpr int kAdjScalars = 4;
 
 // ---- inputs ---------------------------------------------------------------
 
@@ -237,28 +209,6 @@ __device__ __forceinline__ void load_freq(const KArgs &a, int f, double *wre, do
         wre[x] = (x < nx) ? fr[2 * (f * nx + x)] : 0.0;
         wim[x] = (x < nx) ? fr[2 * (f * nx + x) + 1] : 0.0;
     }
-}
-
-// Block sum of (vr, vi) into dst[0..1], deterministic; every lane must call it.
-__device__ __forceinline__ void block_sum2(double vr, double vi, double *red, int tid, int B, double *dst) {
-    vr = wave_sum(vr);
-    vi = wave_sum(vi);
-    const int wave = tid >> 6, nwaves = B >> 6;
-    if ((tid & 63) == 0) {
-        red[2 * wave] = vr;
-        red[2 * wave + 1] = vi;
-    }
-    __syncthreads();
-    if (tid == 0) {
-        double sr = 0.0, si = 0.0;
-        for (int w = 0; w < nwaves; ++w) {
-            sr += red[2 * w];
-            si += red[2 * w + 1];
-        }
-        dst[0] = sr;
-        dst[1] = si;
-    }
-    __syncthreads();
 }
 
 // ---- forward ---------------------------------------------------------------

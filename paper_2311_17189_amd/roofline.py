@@ -12,10 +12,18 @@ kernels compiled here (FMA 2; add, mul, min/max, ldexp, rndne, rcp 1;
 compares and conversions 0):
 
     sin and cos of one argument (both, reduced)      44
+    cos alone (reduced by pi)                        29
+    reduction of a momentum component mod 2 pi        8
     e^z and e^z - 1 of one argument (both)           37
     reciprocal (estimate + two Newton steps)          9
     leaf f(y) with its mirror f(-y), Fermi / Bose    47 / 49
     leaf derivative f'(y)                            48
+
+Two models: ``forward_flops``/``adjoint_flops`` for the table-driven (packed)
+kernels and ``specialized_forward_flops``/``specialized_adjoint_flops`` for the
+generated ones, each counting the arithmetic of its own algorithm (the
+specialized adjoint sums the cotangents of each distinct denominator before
+scattering them, and takes f'(y) = -f(y) f(-y) from the leaf pair).
 
 A term-evaluation is one canonical flat term at one (sample, frequency) point.
 """
@@ -26,6 +34,8 @@ from dataclasses import dataclass
 import numpy as np
 
 C_SINCOS = 44
+C_COS = 29
+C_RED2PI = 8
 C_EXP = 37
 C_RCP = 9
 C_LEAF_FERMI = 47
@@ -111,10 +121,14 @@ def _leaf_flops(st: Structure) -> int:
     return total
 
 
-def _momentum_flops(line_alpha) -> int:
-    total = 0
+def _momentum_flops(line_alpha, n_int: int, sincos: bool) -> int:
+    """Momenta reduced mod 2 pi, K_j per component, then E_j = 2t(cos K_jx +
+    cos K_jy) + mu (cos alone in the forward, sin and cos in the adjoint, which
+    also keeps cos K_jx + cos K_jy)."""
+    total = 2 * n_int * C_RED2PI
     for row in np.asarray(line_alpha):
-        total += 2 * max(_nnz(row) - 1, 0) + 2 * C_SINCOS + 3
+        total += 2 * max(_nnz(row) - 1, 0) + 3
+        total += 2 * C_SINCOS + 1 if sincos else 2 * C_COS
     return total
 
 
@@ -130,7 +144,7 @@ def forward_flops(st: Structure, n_e: int, n_f: int, line_alpha=None) -> dict:
     energies-from-momenta stage (Sec. 5.2) of the momentum path."""
     per_sample = _leaf_flops(st)
     if line_alpha is not None:
-        per_sample += _momentum_flops(line_alpha)
+        per_sample += _momentum_flops(line_alpha, st.n_int, sincos=False)
     for n_terms, _ in st.groups:
         per_sample += n_terms * (st.n_int + 1)              # n-1 products, sign, accumulate
     per_point = _den_flops(st)
@@ -152,7 +166,7 @@ def adjoint_flops(st: Structure, n_e: int, n_f: int, line_alpha=None, with_value
     ni = st.n_int
     per_sample = _leaf_flops(st)
     if line_alpha is not None:
-        per_sample += _momentum_flops(line_alpha)
+        per_sample += _momentum_flops(line_alpha, ni, sincos=True)
         for row in np.asarray(line_alpha)[:, :ni]:
             per_sample += 10 + 2 * _nnz(row)
     for n_terms, _ in st.groups:
@@ -166,6 +180,75 @@ def adjoint_flops(st: Structure, n_e: int, n_f: int, line_alpha=None, with_value
         per_point += dpt * (6 + 3 + 2)          # rho * u, scatter (about 3 energies, 1 frequency)
         if with_values:
             per_point += 4                      # FT_g R_g accumulated into the value
+    total = n_e * per_sample + n_e * n_f * per_point
+    return {"per_sample": per_sample, "per_point": per_point, "total": float(total),
+            "term_evals": float(st.T) * n_e * n_f}
+
+
+# ---- the specialized (generated) kernels ------------------------------------
+
+def _spec_leaves(st: Structure, adjoint: bool) -> int:
+    total = 0
+    for sigma, e in st.leaves:
+        total += max(_nnz(e) - 1, 0) + 1 + (1 if sigma == -1 else 0)    # x, beta x, + e_reg
+        total += C_LEAF_BOSE if sigma == -1 else C_LEAF_FERMI
+        if adjoint:
+            total += 1                                                   # f'(y) = -f(y) f(-y)
+    return total
+
+
+def _spec_group_sums(st: Structure) -> int:
+    n = st.n_int
+    return sum(n_terms * n - 1 for n_terms, _ in st.groups)   # n-1 products + accumulate, first term n-1
+
+
+def _spec_dens(st: Structure) -> int:
+    total = 0
+    for e, a in st.dens:
+        na = _nnz(a)
+        total += max(_nnz(e) - 1, 0) + na + max(na - 1, 0)   # real and imaginary parts
+        total += 3 + C_RCP + 2                                # |D|^2, 1/|D|^2, D* / |D|^2
+    for n_terms, dpt in st.groups:
+        total += 6 * max(dpt - 1, 0)                          # complex product of the reciprocals
+    return total
+
+
+def specialized_forward_flops(st: Structure, n_e: int, n_f: int, line_alpha=None) -> dict:
+    """FLOPs of one forward launch of the generated kernel."""
+    per_sample = _spec_leaves(st, False) + _spec_group_sums(st)
+    if line_alpha is not None:
+        per_sample += _momentum_flops(line_alpha, st.n_int, sincos=False)
+    per_point = _spec_dens(st) + 4 * len(st.groups)           # FT_g R_g accumulated
+    total = n_e * per_sample + n_e * n_f * per_point
+    return {"per_sample": per_sample, "per_point": per_point, "total": float(total),
+            "term_evals": float(st.T) * n_e * n_f}
+
+
+def specialized_adjoint_flops(st: Structure, n_e: int, n_f: int, line_alpha=None,
+                              with_values=False) -> dict:
+    """FLOPs of one adjoint launch of the generated kernel: the forward
+    recomputation, per group and frequency the group-sum cotangent and u_g,
+    per distinct denominator the sum of its u_g, one complex product and the
+    scatter to energies and frequencies; per term the prefix/suffix products
+    of its leaves; per leaf its derivative, the scatter to energies and beta;
+    on the momentum path the chain rule through -2t sin K."""
+    n = st.n_int
+    per_sample = _spec_leaves(st, True) + _spec_group_sums(st)
+    per_sample += sum(n_terms * (4 * n - 4) for n_terms, _ in st.groups)   # leaf cotangents
+    for sigma, e in st.leaves:
+        per_sample += max(_nnz(e) - 1, 0) + (1 if sigma == -1 else 0)    # x recomputed
+        per_sample += 4 + _nnz(e)                                         # f' FB, beta, d/dbeta, scatter
+    if line_alpha is not None:
+        per_sample += _momentum_flops(line_alpha, n, sincos=True)
+        for row in np.asarray(line_alpha)[:, :n]:
+            per_sample += 8 + 2 * _nnz(row)                               # mu, t, -2t sin K, d/dk
+    per_point = _spec_dens(st)
+    per_point += len(st.groups) * (4 + 8 + (4 if with_values else 0))
+    # each group holds dpt denominator occurrences; U_k sums them per distinct denominator
+    n_occ = sum(dpt for _, dpt in st.groups)
+    per_point += 2 * max(n_occ - len(st.dens), 0)
+    for e, a in st.dens:
+        per_point += 6 + _nnz(e) + 2 * _nnz(a)
     total = n_e * per_sample + n_e * n_f * per_point
     return {"per_sample": per_sample, "per_point": per_point, "total": float(total),
             "term_evals": float(st.T) * n_e * n_f}

@@ -17,6 +17,15 @@ amd = pytest.importorskip("paper_2311_17189_amd")
 
 DEV = "cuda"
 
+VARIANTS = pytest.mark.parametrize("variant", [amd.VARIANT_PACKED, amd.VARIANT_SPECIALIZED],
+                                   ids=["packed", "specialized"])
+
+
+def _terms(d, variant=amd.VARIANT_AUTO):
+    t = amd.Terms.from_diagram(d)
+    t.set_variant(variant)
+    return t
+
 
 def _cot(n_f, n_e, seed):
     rng = np.random.default_rng(seed)
@@ -31,7 +40,8 @@ def _rel(a, b):
 
 @pytest.mark.parametrize("order,i,beta", [(2, None, 5.0), (3, 1, 2.0), (4, 1, 5.0), (4, 1, 20.0),
                                           (5, 0, 3.0), (6, 0, 5.0)])
-def test_energy_adjoint_vs_oracle(order, i, beta):
+@VARIANTS
+def test_energy_adjoint_vs_oracle(order, i, beta, variant):
     """Per-sample dL/dE within 1e-10 of sum_t |dL_t/dE| (1e-6 next to a pole of
     one term); the sums over samples (dL/dbeta, dL/dw) within 1e-10 relative
     on samples away from poles."""
@@ -42,7 +52,7 @@ def test_energy_adjoint_vs_oracle(order, i, beta):
     terms = oracle_terms(d)
     cot = _cot(len(w), n_e, 1)
     cot_sum = np.array([0.5 - 0.25j, 0.1j, -0.3])
-    T = amd.Terms.from_diagram(d)
+    T = _terms(d, variant)
     g_e, _, _ = amd.evaluate_adjoint(T, torch.from_numpy(E).to(DEV), torch.from_numpy(w).to(DEV), beta,
                                      grad_out=torch.from_numpy(cot).to(DEV),
                                      grad_sum=torch.from_numpy(cot_sum).to(DEV))
@@ -69,8 +79,9 @@ def test_energy_adjoint_vs_oracle(order, i, beta):
     assert np.max(np.abs(g_w.cpu().numpy() - ref_w.astype(np.complex128))) <= 1e-10 * sc["w"]
 
 
-@pytest.mark.parametrize("order,i", [(2, None), (4, 1), (4, 3)])
-def test_hubbard_adjoint_vs_oracle(order, i):
+@pytest.mark.parametrize("order,i", [(2, None), (4, 1), (4, 3), (5, 2)])
+@VARIANTS
+def test_hubbard_adjoint_vs_oracle(order, i, variant):
     """Momentum-path adjoint: every output within 1e-10 of its rounding scale
     (the sum over terms, and over samples for reduced outputs, of the
     single-term contributions' magnitudes), on samples away from poles."""
@@ -85,7 +96,7 @@ def test_hubbard_adjoint_vs_oracle(order, i):
     k = np.ascontiguousarray(k[keep])
     n_e = len(keep)
     cot = _cot(1, n_e, 2)
-    T = amd.Terms.from_diagram(d)
+    T = _terms(d, variant)
     g_k, g_mu, g_t, g_b, g_w = amd.evaluate_hubbard_adjoint(
         T, torch.from_numpy(k).to(DEV), q, t, mu, torch.from_numpy(w).to(DEV), beta,
         grad_out=torch.from_numpy(cot).to(DEV))
@@ -101,7 +112,8 @@ def test_hubbard_adjoint_vs_oracle(order, i):
     assert np.max(np.abs(g_w.cpu().numpy() - dw.astype(np.complex128))) <= 1e-10 * sc["w"]
 
 
-def test_adjoint_matches_finite_differences_of_forward():
+@VARIANTS
+def test_adjoint_matches_finite_differences_of_forward(variant):
     """Central differences (h = 1e-6, float64) of the HIP forward row sum with
     respect to mu, t, beta and a real frequency, against the HIP adjoint."""
     d = random_self_energy(4, (0, 4, 1))
@@ -115,7 +127,7 @@ def test_adjoint_matches_finite_differences_of_forward():
                           np.array([omega + 1j * gamma]), near=1e-2)
     k = torch.from_numpy(np.ascontiguousarray(kh[keep])).to(DEV)
     n_e = len(keep)
-    T = amd.Terms.from_diagram(d)
+    T = _terms(d, variant)
 
     def loss(tt, mm, bb, om):
         w = torch.tensor([om + 1j * gamma], dtype=torch.complex128, device=DEV)
@@ -185,9 +197,10 @@ def test_adjoint_deterministic_and_sum_cotangent():
         assert torch.allclose(x, y, rtol=1e-13, atol=0)
 
 
-def test_packed_and_plain_kernels_agree():
-    """The specialized evaluator and the plain double-table one both meet the
-    parity bar against the oracle on the same inputs."""
+def test_kernel_variants_agree():
+    """Every forward variant -- double tables, packed, specialized, and the
+    automatic choice -- meets the parity bar against the oracle on the same
+    inputs, and the automatic choice names what it ran."""
     for order, i in ((3, 0), (4, 1), (5, 2), (6, 1)):
         d = random_self_energy(order, (0, order, i))
         beta = 5.0
@@ -197,16 +210,25 @@ def test_packed_and_plain_kernels_agree():
         E = torch.from_numpy(Eh).to(DEV)
         w = torch.from_numpy(wh).to(DEV)
         T = amd.Terms.from_diagram(d)
-        o1, _ = amd.evaluate(T, E, w, beta)
-        v1 = amd.last_variant()
-        T.set_variant(1)
-        o2, _ = amd.evaluate(T, E, w, beta)
-        v2 = amd.last_variant()
-        torch.cuda.synchronize()
-        assert v1.startswith("self-energy") and v2 == "double tables"
         ref, scale, dist = reference(d, Eh, wh, beta)
-        check(o1.cpu().numpy(), ref, scale, dist, label=f"packed order {order}")
-        check(o2.cpu().numpy(), ref, scale, dist, label=f"plain order {order}")
+        names = {}
+        small = T.info()["T"] <= 1024
+        variants = [amd.VARIANT_TABLES, amd.VARIANT_PACKED, amd.VARIANT_AUTO]
+        if small:
+            variants.append(amd.VARIANT_SPECIALIZED)
+        for v in variants:
+            T.set_variant(v)
+            o, _ = amd.evaluate(T, E, w, beta)
+            names[v] = amd.last_variant()
+            torch.cuda.synchronize()
+            check(o.cpu().numpy(), ref, scale, dist, label=f"variant {v} order {order}")
+        assert names[amd.VARIANT_TABLES] == "double tables"
+        assert names[amd.VARIANT_PACKED].startswith("packed self-energy")
+        if small:
+            assert names[amd.VARIANT_SPECIALIZED] == "specialized"
+            assert names[amd.VARIANT_AUTO] == "specialized"
+        else:
+            assert names[amd.VARIANT_AUTO].startswith("packed self-energy")
 
 
 def test_adjoint_empty_batch():
@@ -220,13 +242,14 @@ def test_adjoint_empty_batch():
     assert g_e.shape == (0, 3) and float(g_b) == 0.0 and torch.all(g_w == 0)
 
 
-def test_value_and_gradient_in_one_pass():
+@VARIANTS
+def test_value_and_gradient_in_one_pass(variant):
     """The adjoint entry points also return the forward values when asked: the
     energy path bitwise equal to amiEvaluate, the momentum path within the
     parity bar (its energies come from the sin/cos pair instead of cos alone)."""
     d = random_self_energy(4, (0, 4, 2))
     beta = 5.0
-    T = amd.Terms.from_diagram(d)
+    T = _terms(d, variant)
     E = torch.from_numpy(uniform_energies(1500, d.n_eps, seed=27, a=4.0)).to(DEV)
     w = torch.from_numpy(matsubara_freqs(2, beta)).to(DEV)
     gs = torch.tensor([1.0, 0.5j], dtype=torch.complex128, device=DEV)
@@ -251,3 +274,27 @@ def test_value_and_gradient_in_one_pass():
     from parity import reference_hubbard
     ref, scale, dist, _ = reference_hubbard(d, k, q, 1.0, 0.0, wh, beta)
     check(out.cpu().numpy(), ref, scale, dist, label="value and gradient")
+
+
+def test_auto_adjoint_falls_back_above_its_limit():
+    """AUTO runs the specialized adjoint up to 128 terms and the packed one
+    above; a forced variant that cannot serve the call fails it."""
+    small = amd.Terms.from_diagram(random_self_energy(4, (0, 4, 1)))
+    large = amd.Terms.from_diagram(random_self_energy(5, (0, 5, 0)))
+    huge = amd.Terms.from_diagram(random_self_energy(6, (5, 6, 0)))
+    beta = 5.0
+    w = torch.from_numpy(matsubara_freqs(1, beta)).to(DEV)
+    gs = torch.ones(1, dtype=torch.complex128, device=DEV)
+    for T, want in ((small, "specialized"), (large, "packed self-energy order 5")):
+        E = torch.from_numpy(uniform_energies(100, T.info()["n_eps"], seed=29, a=3.0)).to(DEV)
+        amd.evaluate_adjoint(T, E, w, beta, grad_sum=gs)
+        assert amd.last_variant().startswith(want), amd.last_variant()
+    E = torch.from_numpy(uniform_energies(50, huge.info()["n_eps"], seed=30, a=3.0)).to(DEV)
+    amd.evaluate(huge, E, w, beta)
+    assert amd.last_variant().startswith("packed") and "not specialized" in amd.last_variant()
+    huge.set_variant(amd.VARIANT_SPECIALIZED)
+    with pytest.raises(amd.AmiError):
+        amd.evaluate(huge, E, w, beta)
+    huge.set_variant(amd.VARIANT_TABLES)
+    with pytest.raises(amd.AmiError):
+        amd.evaluate_adjoint(huge, E, w, beta, grad_sum=gs)

@@ -21,6 +21,7 @@ def _mixed_items(n_per_order=2, orders=(2, 3, 4, 5, 6), n_f=4, beta=5.0, energie
         for i in range(n_per_order):
             d = random_self_energy(order, (seed, order, i))
             T = amd.Terms.from_diagram(d)
+            T.set_variant(amd.VARIANT_PACKED)    # the per-diagram kernels the batch shares
             n_e = 300 + 517 * i + 131 * order            # ragged sizes
             w = torch.from_numpy(matsubara_freqs(n_f, beta)).to(DEV)
             it = {"terms": T, "ext_freqs": w, "beta": beta, "diagram": d,

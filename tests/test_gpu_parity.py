@@ -16,9 +16,19 @@ amd = pytest.importorskip("paper_2311_17189_amd")
 
 DEV = "cuda"
 
+# the packed (table-driven) and the specialized (generated) kernels
+VARIANTS = pytest.mark.parametrize("variant", [amd.VARIANT_PACKED, amd.VARIANT_SPECIALIZED],
+                                   ids=["packed", "specialized"])
 
-def _gpu_eval(d, E, w, beta, e_reg=0.0, want_sum=False, terms=None):
-    t = terms if terms is not None else amd.Terms.from_diagram(d)
+
+def _terms(d, variant=amd.VARIANT_AUTO):
+    t = amd.Terms.from_diagram(d)
+    t.set_variant(variant)
+    return t
+
+
+def _gpu_eval(d, E, w, beta, e_reg=0.0, want_sum=False, terms=None, variant=amd.VARIANT_AUTO):
+    t = terms if terms is not None else _terms(d, variant)
     Et = torch.from_numpy(np.ascontiguousarray(E)).to(DEV)
     wt = torch.from_numpy(np.asarray(w, dtype=np.complex128)).to(DEV)
     out, s = amd.evaluate(t, Et, wt, beta, e_reg, want_out=True, want_sum=want_sum)
@@ -26,13 +36,14 @@ def _gpu_eval(d, E, w, beta, e_reg=0.0, want_sum=False, terms=None):
     return out.cpu().numpy(), (s.cpu().numpy() if s is not None else None)
 
 
-def test_order2_paper_example():
+@VARIANTS
+def test_order2_paper_example(variant):
     """Sec. 5.1.3: the second-order integrand at energies uniform in (-8, 8),
     100 fermionic frequencies i(2j+1)pi at beta = 1 (fewer energy rows)."""
     d = order2_example()
     E = uniform_energies(1000, 3, seed=(1, 0), a=8.0)
     w = matsubara_freqs(100, 1.0)
-    got, _ = _gpu_eval(d, E, w, 1.0)
+    got, _ = _gpu_eval(d, E, w, 1.0, variant=variant)
     ref, scale, dist = reference(d, E, w, 1.0)
     check(got, ref, scale, dist, label="order2 paper example")
 
@@ -41,23 +52,25 @@ def test_order2_paper_example():
     (3, 0, 2.0, 1500), (3, 5, 10.0, 777), (4, 1, 5.0, 2049), (4, 6, 2.0, 1000),
     (5, 2, 5.0, 700), (6, 0, 5.0, 300),
 ])
-def test_seeded_energy_path(order, i, beta, n_e):
+@VARIANTS
+def test_seeded_energy_path(order, i, beta, n_e, variant):
     d = random_self_energy(order, (0, order, i))
     E = uniform_energies(n_e, d.n_eps, seed=(2, order, i), a=4.0)
     w = np.concatenate([matsubara_freqs(2, beta), real_freqs(2, -6.0, 6.0, 0.05)])
-    got, _ = _gpu_eval(d, E, w, beta)
+    got, _ = _gpu_eval(d, E, w, beta, variant=variant)
     ref, scale, dist = reference(d, E, w, beta)
     check(got, ref, scale, dist, label=f"order {order} seed {i}")
 
 
-@pytest.mark.parametrize("order,i", [(2, None), (4, 1), (4, 3)])
-def test_hubbard_path(order, i):
+@pytest.mark.parametrize("order,i", [(2, None), (4, 1), (4, 3), (5, 2)])
+@VARIANTS
+def test_hubbard_path(order, i, variant):
     d = order2_example() if i is None else random_self_energy(order, (0, order, i))
     beta, t, mu = 5.0, 1.0, 0.1
     k = k_samples(1300, d.n_int, seed=(3, order, 0 if i is None else i))
     q = np.array(DEFAULT_Q)
     w = np.concatenate([matsubara_freqs(1, beta), real_freqs(3, -6.0, 6.0, 0.05)])
-    T = amd.Terms.from_diagram(d)
+    T = _terms(d, variant)
     kt = torch.from_numpy(k).to(DEV)
     wt = torch.from_numpy(w).to(DEV)
     out, _ = amd.evaluate_hubbard(T, kt, q, t, mu, wt, beta)
@@ -126,17 +139,19 @@ def test_small_and_empty_batches(n_e):
     check(out.cpu().numpy(), ref, scale, dist, label=f"n_e={n_e}")
 
 
-def test_regulator_on_bose_leaves():
+@VARIANTS
+def test_regulator_on_bose_leaves(variant):
     d = order2_example()
     beta, e_reg = 5.0, 0.05
     E = uniform_energies(800, 3, seed=10, a=4.0)
     w = matsubara_freqs(2, beta)
-    got, _ = _gpu_eval(d, E, w, beta, e_reg=e_reg)
+    got, _ = _gpu_eval(d, E, w, beta, e_reg=e_reg, variant=variant)
     ref, scale, dist = reference(d, E, w, beta, e_reg=e_reg)
     check(got, ref, scale, dist, label="e_reg")
 
 
-def test_bosonic_external_bubble():
+@VARIANTS
+def test_bosonic_external_bubble(variant):
     alpha = np.array([[1, 0], [1, 1]])
     eps = np.eye(2, dtype=np.int8)
     from ami_inputs import Diagram
@@ -145,7 +160,7 @@ def test_bosonic_external_bubble():
     beta = 3.0
     E = uniform_energies(600, 2, seed=11, a=3.0)
     w = 2j * np.pi * np.arange(1, 5) / beta
-    got, _ = _gpu_eval(d, E, w, beta)
+    got, _ = _gpu_eval(d, E, w, beta, variant=variant)
     ref, scale, dist = reference(d, E, w, beta)
     check(got, ref, scale, dist, label="bubble")
 
@@ -163,7 +178,8 @@ def test_host_argument_checks():
         amd.evaluate(T, E[:, :3], w, 1.0, want_out=False, want_sum=False)
 
 
-def test_full_size_sampled_order4_hubbard():
+@VARIANTS
+def test_full_size_sampled_order4_hubbard(variant):
     """The benchmark's launch: order-4 diagram, 10^6 momentum samples, one
     Matsubara frequency; 2000 sampled outputs checked one by one."""
     d = random_self_energy(4, (0, 4, 1))
@@ -172,7 +188,7 @@ def test_full_size_sampled_order4_hubbard():
     k = k_samples(n_e, d.n_int, seed=(4, 4, 1))
     q = np.array(DEFAULT_Q)
     w = matsubara_freqs(1, beta)
-    T = amd.Terms.from_diagram(d)
+    T = _terms(d, variant)
     out, s = amd.evaluate_hubbard(T, torch.from_numpy(k).to(DEV), q, t, mu,
                                   torch.from_numpy(w).to(DEV), beta, want_sum=True)
     torch.cuda.synchronize()
