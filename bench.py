@@ -57,8 +57,10 @@ def parse():
 
 
 def cpu_baseline(d, k_all, q, beta, t, mu, w, target_s):
-    """The oracle (float64 mode, as it stands) on a bounded slice of the same
-    samples, with a process pool over the host cores this process may use."""
+    """The oracle, as it stands, on the step's work for a bounded slice of the
+    same samples: values (its float64 mode) and the gradients of the summed
+    integrand (its analytic gradients, long double, with the momentum chain
+    rule), with a process pool over the host cores this process may use."""
     import numpy as np
     from concurrent.futures import ProcessPoolExecutor
 
@@ -66,7 +68,7 @@ def cpu_baseline(d, k_all, q, beta, t, mu, w, target_s):
     terms = canonical(construct(d.alpha, d.eps, d.n_int, d.fermionic))
     cores = min(len(os.sched_getaffinity(0)), 16)
     # calibrate on one chunk in this process
-    chunk = 2000
+    chunk = 1000
     t0 = time.perf_counter()
     _oracle_chunk((terms, d, k_all[:chunk], q, beta, t, mu, w))
     dt = time.perf_counter() - t0
@@ -80,17 +82,22 @@ def cpu_baseline(d, k_all, q, beta, t, mu, w, target_s):
     el = time.perf_counter() - t0
     return {"value": len(terms) * n * len(w) / el, "unit": "term-evals/s", "cores": cores,
             "kind": "oracle",
-            "sample": f"first {n} of the same momentum samples (float64 oracle, "
-                      f"{len(jobs)} chunks of {chunk} over {cores} processes), {el:.1f} s"}
+            "sample": f"first {n} of the same momentum samples: values (float64) and gradients "
+                      f"of the summed integrand w.r.t. k, mu, t, beta, w (long double), "
+                      f"{len(jobs)} chunks of {chunk} over {cores} processes, {el:.1f} s"}
 
 
 def _oracle_chunk(args):
     import numpy as np
 
-    from oracle.evaluate import energies_from_k, evaluate_terms
+    from oracle.evaluate import energies_from_k, evaluate_terms, gradients, momentum_gradients
     terms, d, k, q, beta, t, mu, w = args
     E = energies_from_k(d.alpha, k, q, t, mu, dtype=np.float64)
-    return evaluate_terms(terms, d.n_int, E, w, beta, dtype=np.float64)
+    vals = evaluate_terms(terms, d.n_int, E, w, beta, dtype=np.float64)
+    cot = np.ones((len(w), len(k)), dtype=np.complex128)          # row-sum cotangent of the step
+    dE, db, dw = gradients(terms, d.n_int, E, w, beta, cot)
+    dk, dmu, dt = momentum_gradients(d.alpha, k, q, t, mu, dE)
+    return vals.sum(axis=1), dk, dmu, dt, db, dw
 
 
 def kernel_source_hash() -> str:
@@ -252,11 +259,15 @@ def main():
         return amd.evaluate_hubbard_adjoint(terms, k, q, hop_t, mu, w, args.beta,
                                             grad_sum=g_sum, stream=stream)
 
+    grads = [None]
+
     def step():
         # the whole path in one pass: values out[N_F, N_E] and out_sum[N_F] and the
-        # gradients of Re sum_s I(s) (the row-sum cotangent is fixed in advance)
-        return amd.evaluate_hubbard_adjoint(terms, k, q, hop_t, mu, w, args.beta,
-                                            grad_sum=g_sum, out=out, out_sum=out_sum, stream=stream)
+        # gradients of Re sum_s I(s) (the row-sum cotangent is fixed in advance),
+        # written into the same output tensors every step
+        grads[0] = amd.evaluate_hubbard_adjoint(terms, k, q, hop_t, mu, w, args.beta, grad_sum=g_sum,
+                                                out=out, out_sum=out_sum, stream=stream, grads=grads[0])
+        return grads[0]
 
     if args.copy_mib > 0:
         src = torch.empty(args.copy_mib * (1 << 20) // 8, dtype=torch.float64, device=dev).fill_(1.0)
@@ -299,6 +310,43 @@ def main():
         a1.record(stream)
         torch.cuda.synchronize()
         return a0.elapsed_time(a1) / reps
+
+    # host time to issue one step (no synchronization inside the loop)
+    torch.cuda.synchronize()
+    h0 = time.perf_counter()
+    for _ in range(args.steps):
+        step()
+    host_ms = (time.perf_counter() - h0) * 1e3 / args.steps
+    torch.cuda.synchronize()
+
+    # the same step replayed as a HIP graph (captured on a side stream once the
+    # kernels are loaded and the workspace sized there): launch cost of one graph
+    graph_ms = None
+    try:
+        gs_ = torch.cuda.Stream()
+        gs_.wait_stream(stream)
+        with torch.cuda.stream(gs_):
+            gr = amd.evaluate_hubbard_adjoint(terms, k, q, hop_t, mu, w, args.beta, grad_sum=g_sum,
+                                              out=out, out_sum=out_sum, grads=grads[0])
+        torch.cuda.synchronize()
+        graph = torch.cuda.CUDAGraph()
+        with torch.cuda.graph(graph, stream=gs_):
+            amd.evaluate_hubbard_adjoint(terms, k, q, hop_t, mu, w, args.beta, grad_sum=g_sum,
+                                         out=out, out_sum=out_sum, grads=gr)
+        g0 = torch.cuda.Event(enable_timing=True)
+        g1 = torch.cuda.Event(enable_timing=True)
+        with torch.cuda.stream(gs_):         # replay() launches on the current stream
+            graph.replay()
+            torch.cuda.synchronize()
+            g0.record(gs_)
+            for _ in range(args.steps):
+                graph.replay()
+            g1.record(gs_)
+        torch.cuda.synchronize()
+        graph_ms = g0.elapsed_time(g1) / args.steps
+        del graph
+    except Exception as e:            # reported, not fatal
+        graph_ms = f"not captured: {e}"
 
     # beside the step: forward alone and adjoint alone (separate passes)
     reps = max(5, args.steps // 2)
@@ -379,6 +427,7 @@ def main():
                 "flops": fl["total"], "tflops": fl["total"] / (fwd_ms * 1e-3) / 1e12,
                 "frac_fp64_peak": fl["total"] / (fwd_ms * 1e-3) / rl.PEAK_FP64_VECTOR},
         "fwd_adjoint": {"one_pass_ms": ms_step, "one_pass_kernel_ms": step_kernel_ms,
+                        "host_ms_per_call": host_ms, "graph_ms_per_step": graph_ms,
                         "one_pass_term_evals_per_s": te / (ms_step * 1e-3), "kernel": step_variant,
                         "separate_ms": fwd_ms + adj_ms, "adjoint_ms": adj_ms,
                         "adjoint_flops": fa["total"],

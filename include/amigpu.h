@@ -133,8 +133,12 @@ AmiStatus amiTermsUpload(AmiTerms *terms);
  *   out_sum    device complex128 [n_f] = sum over s of out[f][s] (the Monte-Carlo
  *              row sum of Sec. 2.3), or NULL.  Reduced in a fixed order: repeated
  *              calls give bitwise-equal results.
- * At least one of out/out_sum must be non-NULL.  Uses an internal workspace for
- * the row sums (allocated on first need, grown on demand).
+ * At least one of out/out_sum must be non-NULL.  The per-block partial sums go
+ * to a workspace the handle keeps per device and stream (allocated on the first
+ * call on a stream, grown on demand, released by amiFree): once a call on a
+ * stream has sized it, later calls of that size allocate nothing and may be
+ * captured in a HIP graph.  Calls on different streams use different
+ * workspaces; the adjoint entry points share the same ones.
  */
 AmiStatus amiEvaluate(AmiTerms *terms,
                       const double *energies, int64_t n_e, int64_t stride_s, int64_t stride_i,
@@ -298,7 +302,7 @@ typedef struct {
 
 /* Tuning of a batch (chosen by the autotuner of the Python package):
  *   block        lanes per work-item tile: 64, 128, 256, or 0 for the choice
- *                amiEvaluate makes for the largest item
+ *                the packed amiEvaluate makes for the largest item of each class
  *   waves_per_cu resident waves per compute unit of the persistent grid, 1..32
  *   tile_factor  each work item costs about tile_factor times the most
  *                expensive single tile of the batch, 1..1024 */
@@ -310,13 +314,16 @@ typedef struct {
 } AmiBatchTuning;
 
 /*
- * amiBatchCreate -- build the work list (a diagram's sample tiles grouped into
- * items of similar cost, queued from most to least expensive), upload it with
- * the item descriptors, allocate the row-sum workspace, and instantiate the
- * graph (counter reset -> persistent kernel -> fixed-order row sums).  All
- * allocation happens here.  tuning may be NULL (defaults {0, 8, 1, 0}).
- * Every output equals the corresponding per-diagram evaluate call's bit for
- * bit when the block size matches the one that call uses.
+ * amiBatchCreate -- split the items into LDS classes (equal block size and
+ * blocks per CU of their own packed launch, at most 16 classes), build each class's
+ * work list (a diagram's sample tiles grouped into items of similar cost,
+ * queued from most to least expensive), upload them with the item
+ * descriptors, allocate the row-sum workspace, and instantiate the graph
+ * (counter reset -> one persistent kernel per class -> fixed-order row sums).
+ * All allocation happens here.  tuning may be NULL (defaults {0, 8, 1, 0}).
+ * Every out value equals the packed per-diagram evaluate call's
+ * (AMI_VARIANT_PACKED) bit for bit; out_sum does too when the class's block
+ * size matches the one that call uses.
  */
 AmiStatus amiBatchCreate(const AmiBatchItem *items, int32_t n_items, const AmiBatchTuning *tuning,
                          AmiBatch **out);
@@ -324,8 +331,10 @@ AmiStatus amiBatchCreate(const AmiBatchItem *items, int32_t n_items, const AmiBa
 /* Launch the batch graph on hip_stream (asynchronous; allocates nothing). */
 AmiStatus amiBatchRun(AmiBatch *batch, void *hip_stream);
 
-/* info[0..7]: items, work items, grid blocks, block lanes, LDS bytes per block,
- * row-sum columns, momentum path (1) or energy path (0), reserved. */
+/* info[0..7]: items, work items, grid blocks (summed over the LDS classes),
+ * block lanes (of the class with the most work items), LDS bytes per block
+ * (largest class), row-sum columns, momentum path (1) or energy path (0),
+ * LDS classes (persistent kernels in the graph). */
 AmiStatus amiBatchInfo(const AmiBatch *batch, int64_t info[8]);
 
 /* Release a batch (its device workspace and graph). */

@@ -375,10 +375,11 @@ def evaluate_adjoint(terms: Terms, energies, ext_freqs, beta: float, e_reg: floa
 
 def evaluate_hubbard_adjoint(terms: Terms, k, q, t: float, mu: float, ext_freqs, beta: float,
                              e_reg: float = 0.0, grad_out=None, grad_sum=None, out=None,
-                             out_sum=None, stream=None):
+                             out_sum=None, stream=None, grads=None):
     """``amiEvaluateHubbardAdjoint``: returns ``(grad_k [N_E, 2 n_int], grad_mu [],
     grad_t [], grad_beta [], grad_freqs [N_F, n_ext])``; ``out`` / ``out_sum``
-    tensors, if given, receive the forward values."""
+    tensors, if given, receive the forward values.  ``grads``, if given, is a
+    previous call's result whose tensors are written again instead of new ones."""
     import torch
     if k.dtype != torch.float64 or not k.is_cuda or k.dim() != 2:
         raise AmiError(-1, "k must be a 2-D float64 CUDA tensor")
@@ -388,9 +389,16 @@ def evaluate_hubbard_adjoint(terms: Terms, k, q, t: float, mu: float, ext_freqs,
     n_e, n_f = k.shape[0], w.shape[0]
     dev = k.device
     go, gs = _cot(grad_out, grad_sum, n_f, n_e, dev)
-    g_k = torch.empty((n_e, 2 * terms.n_int), dtype=torch.float64, device=dev)
-    scal = torch.empty((3,), dtype=torch.float64, device=dev)
-    g_w = torch.empty((n_f, w.shape[1]), dtype=torch.complex128, device=dev)
+    if grads is not None:
+        g_k, g_w = grads[0], grads[4]
+        scal = grads[1]._base if grads[1]._base is not None else None
+        if (scal is None or tuple(scal.shape) != (3,) or tuple(g_k.shape) != (n_e, 2 * terms.n_int)
+                or tuple(g_w.shape) != (n_f, w.shape[1]) or not g_k.is_contiguous()):
+            raise AmiError(-1, "grads must be the result of a call of the same shape")
+    else:
+        g_k = torch.empty((n_e, 2 * terms.n_int), dtype=torch.float64, device=dev)
+        scal = torch.empty((3,), dtype=torch.float64, device=dev)
+        g_w = torch.empty((n_f, w.shape[1]), dtype=torch.complex128, device=dev)
     out, out_sum = _outputs(n_f, n_e, dev, False, False, out, out_sum)
     qa = np.ascontiguousarray(np.asarray(q, dtype=np.float64).reshape(-1))
     base = scal.data_ptr()
@@ -473,7 +481,8 @@ class Batch:
     def info(self) -> dict:
         buf = np.zeros(8, dtype=np.int64)
         _check(load_library().amiBatchInfo(self._h, buf.ctypes.data))
-        keys = ["items", "work_items", "grid", "block", "lds_bytes", "rowsum_columns", "momentum_path"]
+        keys = ["items", "work_items", "grid", "block", "lds_bytes", "rowsum_columns", "momentum_path",
+                "lds_classes"]
         return {k: int(buf[i]) for i, k in enumerate(keys)}
 
     def close(self):

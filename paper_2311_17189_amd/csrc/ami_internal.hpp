@@ -7,6 +7,7 @@
 #include <map>
 #include <mutex>
 #include <string>
+#include <utility>
 #include <vector>
 
 #include "../../include/amigpu.h"
@@ -60,6 +61,16 @@ struct DeviceTables {
     const uint32_t *p_line = nullptr;
     const uint64_t *p_term = nullptr;
     const uint64_t *p_group = nullptr;
+    // workspaces of the per-block partial sums, one per stream (calls on one
+    // stream are ordered on the device, calls on different streams get
+    // different buffers); grown on demand, outgrown buffers kept until amiFree
+    struct Workspace {
+        void *stream = nullptr;
+        void *ptr = nullptr;
+        size_t bytes = 0;
+    };
+    std::vector<Workspace> ws;
+    std::vector<void *> retired;
 };
 
 // Flattened, common-subexpression-eliminated evaluation tables (host).

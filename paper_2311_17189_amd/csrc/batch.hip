@@ -4,11 +4,16 @@
 // queue, replayed as one HIP graph (reset counter -> persistent kernel ->
 // fixed-order row sums).
 //
-// Work items are built on the host: a diagram's sample tiles are grouped so
-// that every item costs about the same (a multiple, the tuning's tile factor,
-// of the most expensive single tile, estimated from the solution's table
-// sizes), and the items are queued from the most to the least expensive
-// (largest-first list scheduling).  Each item is evaluated by the same tile
+// Items are first split into LDS classes (the block size and the number of
+// blocks per CU of their own packed launch), so that no item runs below the
+// occupancy of its own launch: each class has its own block size, LDS size,
+// grid, work queue and counter, and its persistent kernel is a graph node of
+// its own between the counter reset and the row sums.  Within a class, work items are
+// built on the host: a diagram's sample tiles are grouped so that every item
+// costs about the same (a multiple, the tuning's tile factor, of the class's
+// most expensive single tile, estimated from the solution's table sizes), and
+// the items are queued from the most to the least expensive (largest-first
+// list scheduling).  Each item is evaluated by the same tile
 // function as the per-diagram kernel (fwd_tile), so every output value is
 // bitwise the one the per-diagram launch computes; the row sums are reduced
 // over the same tiles in the same order.
@@ -104,8 +109,12 @@ __global__ __launch_bounds__(256) void ami_batch_kernel(const BatchDesc *desc, c
     }
 }
 
-__global__ void ami_batch_reset_kernel(unsigned int *counter) {
-    if (threadIdx.x == 0 && blockIdx.x == 0) *counter = 0u;
+// counters are kCounterStride apart (one per class)
+constexpr int kCounterStride = 16;
+constexpr int kMaxClasses = 16;
+
+__global__ void ami_batch_reset_kernel(unsigned int *counters, int n) {
+    if (blockIdx.x == 0 && static_cast<int>(threadIdx.x) < n) counters[threadIdx.x * kCounterStride] = 0u;
 }
 
 __global__ __launch_bounds__(256) void ami_batch_rowsum_kernel(const RowSumJob *jobs) {
@@ -146,9 +155,10 @@ struct AmiBatch {
     int device = -1;
     bool hub = false;
     int n_items = 0;
-    int block = 0;
-    int grid = 0;
-    size_t lds = 0;
+    int n_classes = 0;
+    int block = 0;                         // of the class with the most work
+    int grid = 0;                          // summed over the classes
+    size_t lds = 0;                        // largest over the classes
     int64_t n_work = 0;
     int64_t n_jobs = 0;
     void *blob = nullptr;                  // descriptors, work list, jobs, counter, partial sums
@@ -192,7 +202,6 @@ AmiStatus amiBatchCreate(const AmiBatchItem *items, int32_t n_items, const AmiBa
 
     // per-item checks and descriptors
     std::vector<BatchDesc> desc(n_items);
-    int max_slots = 0;
     for (int i = 0; i < n_items; ++i) {
         const AmiBatchItem &it = items[i];
         AmiTerms *t = it.terms;
@@ -236,78 +245,123 @@ AmiStatus amiBatchCreate(const AmiBatchItem *items, int32_t n_items, const AmiBa
         d.a.n_e = it.n_e;
         d.a.out = it.out;
         d.shape = shape_of(t, hub);
-        max_slots = std::max(max_slots, fwd_slots(t->tab));
     }
-    // one block size for the whole batch (LDS sized for the largest item)
-    LaunchShape ls;
-    AmiStatus st = pick_shape(max_slots, ls);
-    if (st != AMI_OK) return st;
-    if (tun.block != 0) {
-        int max_lds = 0;
-        e = hipDeviceGetAttribute(&max_lds, hipDeviceAttributeMaxSharedMemoryPerBlock, dev);
-        if (e != hipSuccess) return hip_fail(e, "hipDeviceGetAttribute");
-        const size_t lds = static_cast<size_t>(max_slots) * sizeof(double) * tun.block +
-                           2 * sizeof(double) * (tun.block / 64);
-        if (lds > static_cast<size_t>(max_lds)) return fail(AMI_E_UNSUPPORTED, "tuning block too large for LDS");
-        ls.block = tun.block;
-        ls.lds = lds;
-    }
-    {
-        int max_lds = 0;
-        e = hipDeviceGetAttribute(&max_lds, hipDeviceAttributeMaxSharedMemoryPerBlock, dev);
-        if (e != hipSuccess) return hip_fail(e, "hipDeviceGetAttribute");
-        if (ls.lds + 64 > static_cast<size_t>(max_lds))     // the kernel's own queue slot
-            return fail(AMI_E_UNSUPPORTED, "batch items too large for the LDS of one block");
-    }
-    for (auto &d : desc) d.a.slots = max_slots;
+    int max_lds = 0, cu_lds = 0, n_cu = 0;
+    e = hipDeviceGetAttribute(&max_lds, hipDeviceAttributeMaxSharedMemoryPerBlock, dev);
+    if (e == hipSuccess) e = hipDeviceGetAttribute(&cu_lds, hipDeviceAttributeMaxSharedMemoryPerMultiprocessor, dev);
+    if (e == hipSuccess) e = hipDeviceGetAttribute(&n_cu, hipDeviceAttributeMultiprocessorCount, dev);
+    if (e != hipSuccess) return hip_fail(e, "hipDeviceGetAttribute");
+    if (cu_lds < max_lds) cu_lds = max_lds;
 
-    // work items and row-sum jobs
+    // LDS classes: items with the launch shape (block, LDS) the packed
+    // per-diagram call picks, grouped by (block, resident blocks per CU), so
+    // that every item runs at the occupancy of its own launch; classes in
+    // order of per-lane LDS need, the last one taking the rest past kMaxClasses
+    std::vector<int> order(n_items);
+    std::vector<int> slots(n_items);
+    std::vector<LaunchShape> own(n_items);
+    for (int i = 0; i < n_items; ++i) {
+        order[i] = i;
+        slots[i] = fwd_slots(items[i].terms->tab);
+        AmiStatus st = pick_shape(slots[i], own[i]);
+        if (st != AMI_OK) return st;
+        if (tun.block != 0) {
+            own[i].block = tun.block;
+            own[i].lds = static_cast<size_t>(slots[i]) * sizeof(double) * tun.block +
+                         2 * sizeof(double) * (tun.block / 64);
+        }
+    }
+    auto resident = [&](size_t lds) { return static_cast<int>(cu_lds / (lds + 64)); };
+    std::stable_sort(order.begin(), order.end(), [&](int x, int y) { return slots[x] < slots[y]; });
+    struct Class {
+        std::vector<int> items;
+        int max_slots = 0;
+        LaunchShape ls;
+        int grid = 0;
+        int64_t work0 = 0, n_work = 0;
+    };
+    std::vector<Class> cls;
+    for (int i : order) {
+        const bool same = !cls.empty() && own[cls.back().items[0]].block == own[i].block &&
+                          resident(own[cls.back().items[0]].lds) == resident(own[i].lds);
+        if (cls.empty() || (!same && static_cast<int>(cls.size()) < kMaxClasses)) cls.emplace_back();
+        cls.back().items.push_back(i);
+        cls.back().max_slots = std::max(cls.back().max_slots, slots[i]);
+    }
+    std::vector<int> cls_of(n_items);
+    for (size_t c = 0; c < cls.size(); ++c) {
+        Class &k = cls[c];
+        for (int i : k.items) cls_of[i] = static_cast<int>(c);
+        k.ls.block = own[k.items[0]].block;
+        for (int i : k.items) k.ls.block = std::min(k.ls.block, own[i].block);   // merged tail classes
+        k.ls.slots = k.max_slots;
+        k.ls.lds = static_cast<size_t>(k.max_slots) * sizeof(double) * k.ls.block +
+                   2 * sizeof(double) * (k.ls.block / 64);
+        if (k.ls.lds + 64 > static_cast<size_t>(max_lds))     // the kernel's own queue slot
+            return fail(AMI_E_UNSUPPORTED, "batch items too large for the LDS of one block");
+        for (int i : k.items) desc[i].a.slots = k.max_slots;
+    }
+
+    // work items per class and row-sum jobs
     std::vector<double> tile_cost(n_items);
     std::vector<int64_t> tiles(n_items);
-    double max_tile = 0.0;
     for (int i = 0; i < n_items; ++i) {
-        tiles[i] = (items[i].n_e + ls.block - 1) / ls.block;
-        tile_cost[i] = sample_cost(items[i].terms, items[i].n_f) * ls.block;
-        max_tile = std::max(max_tile, tile_cost[i]);
+        const int blk = cls[cls_of[i]].ls.block;
+        tiles[i] = (items[i].n_e + blk - 1) / blk;
+        tile_cost[i] = sample_cost(items[i].terms, items[i].n_f) * blk;
     }
-    const double target = max_tile * tun.tile_factor;
     struct HostWork {
         Work w;
         double cost;
     };
-    std::vector<HostWork> hw;
+    std::vector<Work> wl;
     size_t partial_total = 0;
     std::vector<size_t> partial_off(n_items, 0);
-    std::vector<RowSumJob> jobs;
-    for (int i = 0; i < n_items; ++i) {
-        const int64_t per = std::max<int64_t>(1, static_cast<int64_t>(target / tile_cost[i]));
-        for (int64_t t0 = 0; t0 < tiles[i]; t0 += per) {
-            HostWork h;
-            h.w.item = i;
-            h.w.tile0 = t0;
-            h.w.ntiles = static_cast<int32_t>(std::min<int64_t>(per, tiles[i] - t0));
-            h.cost = tile_cost[i] * h.w.ntiles;
-            hw.push_back(h);
-        }
+    for (int i = 0; i < n_items; ++i)
         if (items[i].out_sum) {
             partial_off[i] = partial_total;
             partial_total += static_cast<size_t>(tiles[i]) * items[i].n_f * 2;
         }
+    for (Class &k : cls) {
+        double max_tile = 0.0;
+        for (int i : k.items) max_tile = std::max(max_tile, tile_cost[i]);
+        const double target = max_tile * tun.tile_factor;
+        std::vector<HostWork> hw;
+        for (int i : k.items) {
+            const int64_t per = std::max<int64_t>(1, static_cast<int64_t>(target / tile_cost[i]));
+            for (int64_t t0 = 0; t0 < tiles[i]; t0 += per) {
+                HostWork h;
+                h.w.item = i;
+                h.w.tile0 = t0;
+                h.w.ntiles = static_cast<int32_t>(std::min<int64_t>(per, tiles[i] - t0));
+                h.cost = tile_cost[i] * h.w.ntiles;
+                hw.push_back(h);
+            }
+        }
+        std::stable_sort(hw.begin(), hw.end(), [](const HostWork &x, const HostWork &y) { return x.cost > y.cost; });
+        k.work0 = static_cast<int64_t>(wl.size());
+        k.n_work = static_cast<int64_t>(hw.size());
+        for (const auto &h : hw) wl.push_back(h.w);
+        // resident blocks per CU: the tuning's waves, within the CU's LDS
+        const int waves_per_block = k.ls.block / 64;
+        const int by_waves = std::max(1, tun.waves_per_cu / waves_per_block);
+        const int by_lds = std::max<int>(1, static_cast<int>(cu_lds / (k.ls.lds + 64)));
+        k.grid = static_cast<int>(std::min<int64_t>(static_cast<int64_t>(n_cu) * std::min(by_waves, by_lds),
+                                                    k.n_work));
     }
-    std::stable_sort(hw.begin(), hw.end(), [](const HostWork &x, const HostWork &y) { return x.cost > y.cost; });
-    if (hw.size() > 0x7fffffffu - 65536u) return fail(AMI_E_ARG, "too many work items");
+    if (wl.size() > 0x7fffffffu - 65536u) return fail(AMI_E_ARG, "too many work items");
 
-    // one device allocation: descriptors | work | jobs | counter | partials
+    // one device allocation: descriptors | work | jobs | counters | partials
     const size_t sz_desc = sizeof(BatchDesc) * n_items;
     const size_t off_work = (sz_desc + 255) & ~size_t(255);
-    const size_t sz_work = sizeof(Work) * hw.size();
+    const size_t sz_work = sizeof(Work) * wl.size();
     const size_t off_jobs = (off_work + sz_work + 255) & ~size_t(255);
     size_t n_jobs = 0;
     for (int i = 0; i < n_items; ++i)
         if (items[i].out_sum) n_jobs += 2 * static_cast<size_t>(items[i].n_f);
     const size_t sz_jobs = sizeof(RowSumJob) * std::max<size_t>(n_jobs, 1);
     const size_t off_ctr = (off_jobs + sz_jobs + 255) & ~size_t(255);
-    const size_t off_part = off_ctr + 256;
+    const size_t off_part = off_ctr + ((sizeof(unsigned int) * kCounterStride * kMaxClasses + 255) & ~size_t(255));
     const size_t total = off_part + sizeof(double) * std::max<size_t>(partial_total, 1);
 
     AmiBatch *b = new (std::nothrow) AmiBatch();
@@ -315,20 +369,23 @@ AmiStatus amiBatchCreate(const AmiBatchItem *items, int32_t n_items, const AmiBa
     b->device = dev;
     b->hub = hub;
     b->n_items = n_items;
-    b->block = ls.block;
-    b->lds = ls.lds;
-    b->n_work = static_cast<int64_t>(hw.size());
+    b->n_classes = static_cast<int>(cls.size());
+    b->n_work = static_cast<int64_t>(wl.size());
     b->n_jobs = static_cast<int64_t>(n_jobs);
-    int n_cu = 0;
-    e = hipDeviceGetAttribute(&n_cu, hipDeviceAttributeMultiprocessorCount, dev);
-    if (e != hipSuccess) return batch_fail_free(b, hip_fail(e, "hipDeviceGetAttribute"));
-    const int waves_per_block = ls.block / 64;
-    b->grid = std::max(1, n_cu * tun.waves_per_cu / waves_per_block);
-    b->grid = static_cast<int>(std::min<int64_t>(b->grid, b->n_work));
+    int64_t most = -1;
+    for (const Class &k : cls) {
+        b->grid += k.grid;
+        b->lds = std::max(b->lds, k.ls.lds);
+        if (k.n_work > most) {
+            most = k.n_work;
+            b->block = k.ls.block;
+        }
+    }
     e = hipMalloc(&b->blob, total);
     if (e != hipSuccess) return batch_fail_free(b, fail(AMI_E_OOM, "batch workspace"));
     unsigned char *base = static_cast<unsigned char *>(b->blob);
     double *partial = reinterpret_cast<double *>(base + off_part);
+    std::vector<RowSumJob> jobs;
     for (int i = 0; i < n_items; ++i) {
         desc[i].a.partial = items[i].out_sum ? partial + partial_off[i] : nullptr;
         if (items[i].out_sum)
@@ -342,26 +399,24 @@ AmiStatus amiBatchCreate(const AmiBatchItem *items, int32_t n_items, const AmiBa
                 jobs.push_back(j);
             }
     }
-    std::vector<Work> wl(hw.size());
-    for (size_t i = 0; i < hw.size(); ++i) wl[i] = hw[i].w;
     std::vector<unsigned char> host(off_part, 0);
     std::memcpy(host.data(), desc.data(), sz_desc);
-    std::memcpy(host.data() + off_work, wl.data(), sz_work);
+    if (sz_work) std::memcpy(host.data() + off_work, wl.data(), sz_work);
     if (!jobs.empty()) std::memcpy(host.data() + off_jobs, jobs.data(), sizeof(RowSumJob) * jobs.size());
     e = hipMemcpy(b->blob, host.data(), off_part, hipMemcpyHostToDevice);
     if (e != hipSuccess) return batch_fail_free(b, hip_fail(e, "batch upload"));
 
-    // graph: reset counter -> persistent kernel -> row sums
+    // graph: reset counters -> one persistent kernel per class -> row sums
     const BatchDesc *d_desc = reinterpret_cast<const BatchDesc *>(base);
-    const Work *d_work = reinterpret_cast<const Work *>(base + off_work);
     const RowSumJob *d_jobs = reinterpret_cast<const RowSumJob *>(base + off_jobs);
     unsigned int *d_ctr = reinterpret_cast<unsigned int *>(base + off_ctr);
-    int n_work = static_cast<int>(b->n_work);
     e = hipGraphCreate(&b->graph, 0);
     if (e != hipSuccess) return batch_fail_free(b, hip_fail(e, "hipGraphCreate"));
-    hipGraphNode_t n_reset = nullptr, n_main = nullptr, n_sum = nullptr;
+    hipGraphNode_t n_reset = nullptr, n_sum = nullptr;
+    std::vector<hipGraphNode_t> n_main;
     {
-        void *args[] = {&d_ctr};
+        int n_ctr = static_cast<int>(cls.size());
+        void *args[] = {&d_ctr, &n_ctr};
         hipKernelNodeParams p;
         std::memset(&p, 0, sizeof(p));
         p.func = reinterpret_cast<void *>(&ami_batch_reset_kernel);
@@ -371,22 +426,29 @@ AmiStatus amiBatchCreate(const AmiBatchItem *items, int32_t n_items, const AmiBa
         e = hipGraphAddKernelNode(&n_reset, b->graph, nullptr, 0, &p);
         if (e != hipSuccess) return batch_fail_free(b, hip_fail(e, "graph reset node"));
     }
-    {
-        void *args[] = {&d_desc, &d_work, &n_work, &d_ctr};
+    for (size_t c = 0; c < cls.size(); ++c) {
+        const Class &k = cls[c];
+        if (k.n_work == 0) continue;
+        const Work *d_work = reinterpret_cast<const Work *>(base + off_work) + k.work0;
+        int n_work = static_cast<int>(k.n_work);
+        unsigned int *ctr = d_ctr + c * kCounterStride;
+        void *args[] = {&d_desc, &d_work, &n_work, &ctr};
         hipKernelNodeParams p;
         std::memset(&p, 0, sizeof(p));
         bool all = false;
-        for (int i = 0; i < n_items; ++i) all = all || desc[i].shape == kShapeGeneric || desc[i].shape > 6;
+        for (int i : k.items) all = all || desc[i].shape == kShapeGeneric || desc[i].shape > 6;
         if (hub) p.func = all ? reinterpret_cast<void *>(&ami_batch_kernel<true, true>)
                               : reinterpret_cast<void *>(&ami_batch_kernel<true, false>);
         else p.func = all ? reinterpret_cast<void *>(&ami_batch_kernel<false, true>)
                           : reinterpret_cast<void *>(&ami_batch_kernel<false, false>);
-        p.gridDim = dim3(b->grid);
-        p.blockDim = dim3(b->block);
-        p.sharedMemBytes = static_cast<unsigned>(b->lds);
+        p.gridDim = dim3(static_cast<unsigned>(k.grid));
+        p.blockDim = dim3(static_cast<unsigned>(k.ls.block));
+        p.sharedMemBytes = static_cast<unsigned>(k.ls.lds);
         p.kernelParams = args;
-        e = hipGraphAddKernelNode(&n_main, b->graph, &n_reset, 1, &p);
+        hipGraphNode_t node = nullptr;
+        e = hipGraphAddKernelNode(&node, b->graph, &n_reset, 1, &p);
         if (e != hipSuccess) return batch_fail_free(b, hip_fail(e, "graph batch node"));
+        n_main.push_back(node);
     }
     if (n_jobs > 0) {
         void *args[] = {&d_jobs};
@@ -396,7 +458,7 @@ AmiStatus amiBatchCreate(const AmiBatchItem *items, int32_t n_items, const AmiBa
         p.gridDim = dim3(static_cast<unsigned>(n_jobs));
         p.blockDim = dim3(256);
         p.kernelParams = args;
-        e = hipGraphAddKernelNode(&n_sum, b->graph, &n_main, 1, &p);
+        e = hipGraphAddKernelNode(&n_sum, b->graph, n_main.data(), n_main.size(), &p);
         if (e != hipSuccess) return batch_fail_free(b, hip_fail(e, "graph row-sum node"));
     }
     e = hipGraphInstantiate(&b->exec, b->graph, nullptr, nullptr, 0);
@@ -429,7 +491,7 @@ AmiStatus amiBatchInfo(const AmiBatch *b, int64_t info[8]) {
     info[4] = static_cast<int64_t>(b->lds);
     info[5] = b->n_jobs;
     info[6] = b->hub ? 1 : 0;
-    info[7] = 0;
+    info[7] = b->n_classes;
     return AMI_OK;
 }
 

@@ -72,7 +72,10 @@ namespace {
 // per lane (two resident blocks of 256 lanes per CU).
 constexpr int kParkBudget = 40;
 int park_chain(const AmiTerms *t, bool hub) { return hub ? 3 * t->n_g : 0; }
-bool park_dv(const AmiTerms *t, bool hub) { return park_chain(t, hub) + t->tab.L <= kParkBudget; }
+bool park_dv(const AmiTerms *t, bool hub) {
+    if (const char *e = std::getenv("AMIGPU_JIT_PARK_DV")) return std::atoi(e) != 0;   // tuning override
+    return park_chain(t, hub) + t->tab.L <= kParkBudget;
+}
 int park_cols(const AmiTerms *t, bool hub) { return park_chain(t, hub) + (park_dv(t, hub) ? t->tab.L : 0); }
 
 // occupancy hint for the adjoint (waves per SIMD), AMIGPU_JIT_ADJ_WAVES

@@ -53,20 +53,30 @@ __global__ __launch_bounds__(256) void ami_colsum_kernel(const double *partial, 
 
 // Same reduction for the adjoint partials, routing each column to its output:
 // column 0 dL/dbeta, 1 dL/dmu, 2 dL/dt, 4.. dL/dw (complex [n_f][n_ext]).
+// Blocks past the gradient columns reduce the forward values' row sums
+// (partial sums [nblocks][nval] stored after the gradient ones).
 __global__ __launch_bounds__(256) void ami_adj_finalize_kernel(const double *partial, int64_t nblocks, int ncols,
                                                                double *gbeta, double *gmu, double *gt,
-                                                               double *gw) {
+                                                               double *gw, int nval, double *vsum) {
     __shared__ double sh[256];
-    const int j = blockIdx.x;
+    int j = blockIdx.x;
     const int tid = threadIdx.x;
     double *dst = nullptr;
+    const double *src = partial;
+    int stride = ncols;
     if (j == 0) dst = gbeta;
     else if (j == 1) dst = gmu;
     else if (j == 2) dst = gt;
-    else if (j >= kAdjScalars && gw) dst = gw + (j - kAdjScalars);
+    else if (j >= kAdjScalars && j < ncols && gw) dst = gw + (j - kAdjScalars);
+    else if (j >= ncols && vsum) {
+        j -= ncols;
+        dst = vsum + j;
+        src = partial + nblocks * ncols;
+        stride = nval;
+    }
     if (!dst) return;
     double acc = 0.0;
-    for (int64_t b = tid; b < nblocks; b += 256) acc += partial[b * ncols + j];
+    for (int64_t b = tid; b < nblocks; b += 256) acc += src[b * stride + j];
     sh[tid] = acc;
     __syncthreads();
     for (int w = 128; w >= 1; w >>= 1) {
@@ -358,6 +368,32 @@ AmiStatus choose_path(AmiTerms *t, bool hub, bool adjoint, Path &p, void **jit_f
     return AMI_OK;
 }
 
+// Partial-sum workspace of (handle, device, stream), at least `bytes` long:
+// steady-state calls allocate nothing (and can be captured in a graph once a
+// first call on the stream has sized it).
+AmiStatus workspace(AmiTerms *t, DeviceTables *dt, hipStream_t stream, size_t bytes, double **out) {
+    std::lock_guard<std::mutex> lk(t->dev_mu);
+    DeviceTables::Workspace *w = nullptr;
+    for (auto &x : dt->ws)
+        if (x.stream == static_cast<void *>(stream)) w = &x;
+    if (!w) {
+        dt->ws.emplace_back();
+        w = &dt->ws.back();
+        w->stream = static_cast<void *>(stream);
+    }
+    if (w->bytes < bytes) {
+        const size_t want = std::max(bytes, 2 * w->bytes);
+        void *p = nullptr;
+        const hipError_t e = hipMalloc(&p, want);
+        if (e != hipSuccess) return fail(AMI_E_OOM, std::string("workspace: ") + hipGetErrorString(e));
+        if (w->ptr) dt->retired.push_back(w->ptr);     // a launch already queued may still read it
+        w->ptr = p;
+        w->bytes = want;
+    }
+    *out = static_cast<double *>(w->ptr);
+    return AMI_OK;
+}
+
 hipError_t launch_jit(void *fn, int64_t nblocks, int block, hipStream_t stream, KArgs &a) {
     void *params[] = {&a};
     return hipModuleLaunchKernel(static_cast<hipFunction_t>(fn), static_cast<unsigned>(nblocks), 1, 1,
@@ -387,9 +423,8 @@ AmiStatus launch_forward(AmiTerms *t, bool hub, KArgs &a, double *out_sum, hipSt
     double *partial = nullptr;
     hipError_t e;
     if (out_sum) {
-        e = hipMallocAsync(reinterpret_cast<void **>(&partial),
-                           static_cast<size_t>(nblocks) * a.n_f * 2 * sizeof(double), stream);
-        if (e != hipSuccess) return fail(AMI_E_OOM, std::string("workspace: ") + hipGetErrorString(e));
+        st = workspace(t, dt, stream, static_cast<size_t>(nblocks) * a.n_f * 2 * sizeof(double), &partial);
+        if (st != AMI_OK) return st;
     }
     const dim3 grid(static_cast<unsigned>(nblocks)), block(ls.block);
     timer_mark(stream, false);
@@ -412,15 +447,11 @@ AmiStatus launch_forward(AmiTerms *t, bool hub, KArgs &a, double *out_sum, hipSt
         e = hipGetLastError();
     }
     timer_mark(stream, true);
-    if (e != hipSuccess) {
-        if (partial) (void)hipFreeAsync(partial, stream);
-        return hip_fail(e, "forward launch");
-    }
+    if (e != hipSuccess) return hip_fail(e, "forward launch");
     if (out_sum) {
         hipLaunchKernelGGL(ami_colsum_kernel, dim3(2 * a.n_f), dim3(256), 0, stream, partial, nblocks, 2 * a.n_f,
                            out_sum);
         e = hipGetLastError();
-        (void)hipFreeAsync(partial, stream);
         if (e != hipSuccess) return hip_fail(e, "row-sum launch");
     }
     return AMI_OK;
@@ -464,8 +495,9 @@ AmiStatus launch_adjoint(AmiTerms *t, bool hub, KArgs &a, const AdjOut &o, hipSt
     double *partial = nullptr;
     const size_t n_grad = static_cast<size_t>(nblocks) * ncols;
     const size_t n_val = o.out_sum ? static_cast<size_t>(nblocks) * a.n_f * 2 : 0;
-    hipError_t e = hipMallocAsync(reinterpret_cast<void **>(&partial), (n_grad + n_val) * sizeof(double), stream);
-    if (e != hipSuccess) return fail(AMI_E_OOM, std::string("workspace: ") + hipGetErrorString(e));
+    st = workspace(t, dt, stream, (n_grad + n_val) * sizeof(double), &partial);
+    if (st != AMI_OK) return st;
+    hipError_t e;
     a.gpartial = partial;
     a.partial = o.out_sum ? partial + n_grad : nullptr;
     const dim3 grid(static_cast<unsigned>(nblocks)), block(ls.block);
@@ -483,19 +515,12 @@ AmiStatus launch_adjoint(AmiTerms *t, bool hub, KArgs &a, const AdjOut &o, hipSt
         e = hipGetLastError();
     }
     timer_mark(stream, true);
-    if (e != hipSuccess) {
-        (void)hipFreeAsync(partial, stream);
-        return hip_fail(e, "adjoint launch");
-    }
-    hipLaunchKernelGGL(ami_adj_finalize_kernel, dim3(ncols), dim3(256), 0, stream, partial, nblocks, ncols,
-                       o.grad_beta, o.grad_mu, o.grad_t, o.grad_freqs);
+    if (e != hipSuccess) return hip_fail(e, "adjoint launch");
+    // one launch for every reduction: gradient columns, then the value row sums
+    const int n_red = ncols + (o.out_sum ? 2 * a.n_f : 0);
+    hipLaunchKernelGGL(ami_adj_finalize_kernel, dim3(n_red), dim3(256), 0, stream, partial, nblocks, ncols,
+                       o.grad_beta, o.grad_mu, o.grad_t, o.grad_freqs, 2 * a.n_f, o.out_sum);
     e = hipGetLastError();
-    if (e == hipSuccess && o.out_sum) {
-        hipLaunchKernelGGL(ami_colsum_kernel, dim3(2 * a.n_f), dim3(256), 0, stream, partial + n_grad, nblocks,
-                           2 * a.n_f, o.out_sum);
-        e = hipGetLastError();
-    }
-    (void)hipFreeAsync(partial, stream);
     if (e != hipSuccess) return hip_fail(e, "adjoint reduction launch");
     return AMI_OK;
 }
@@ -566,7 +591,11 @@ void amiFree(AmiTerms *t) {
     int cur = 0;
     const bool have_cur = hipGetDevice(&cur) == hipSuccess;
     for (auto &d : t->dev)
-        if (d.blob && hipSetDevice(d.device) == hipSuccess) (void)hipFree(d.blob);
+        if (hipSetDevice(d.device) == hipSuccess) {
+            if (d.blob) (void)hipFree(d.blob);
+            for (auto &w : d.ws) (void)hipFree(w.ptr);
+            for (void *p : d.retired) (void)hipFree(p);
+        }
     if (have_cur) (void)hipSetDevice(cur);
     ami::jit_release(t);
     delete t;

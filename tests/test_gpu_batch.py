@@ -54,6 +54,7 @@ def test_batch_bitwise_equals_per_diagram(energies, tuning):
     torch.cuda.synchronize()
     info = b.info()
     assert info["items"] == len(items) and info["work_items"] >= len(items)
+    assert info["lds_classes"] >= 2          # orders 2..6 span more than one LDS class
     for it in items:
         ref_out, ref_sum = _per_diagram(it)
         torch.cuda.synchronize()
