@@ -378,6 +378,34 @@ def main():
     plain_variant = amd.last_variant()
     terms.set_variant(amd.VARIANT_AUTO)
 
+    # Monte-Carlo integration of the same diagram with momenta drawn in the
+    # kernel (no sample touches HBM): forward values summed over 10 N_E samples
+    mc = None
+    try:
+        n_mc = 10 * n_e
+        sums = amd.integrate_hubbard(terms, n_mc, 1234, q, hop_t, mu, w, args.beta, stream=stream)
+        torch.cuda.synchronize()
+        amd.kernel_timer_start(5)
+        m0 = torch.cuda.Event(enable_timing=True)
+        m1 = torch.cuda.Event(enable_timing=True)
+        m0.record(stream)
+        for _ in range(5):
+            amd.integrate_hubbard(terms, n_mc, 1234, q, hop_t, mu, w, args.beta, sums=sums, stream=stream)
+        m1.record(stream)
+        torch.cuda.synchronize()
+        mk = amd.kernel_timer_stop()
+        mc_ms = m0.elapsed_time(m1) / 5
+        mean, err = amd.mc_estimate(sums, n_mc)
+        mfl = rl.mc_flops(st, n_mc, n_f, d.alpha)
+        mc = {"samples": n_mc, "ms": mc_ms, "kernel_ms": sum(mk) / len(mk),
+              "term_evals_per_s": float(info["T"]) * n_mc * n_f / (mc_ms * 1e-3),
+              "tflops": mfl["total"] / (sum(mk) / len(mk) * 1e-3) / 1e12,
+              "frac_fp64_peak": mfl["total"] / (sum(mk) / len(mk) * 1e-3) / rl.PEAK_FP64_VECTOR,
+              "estimate": [[float(z.real), float(z.imag)] for z in mean],
+              "stderr": [[float(a), float(b)] for a, b in err]}
+    except amd.AmiError as e:
+        mc = f"not run: {e}"
+
     te = float(info["T"]) * n_e * n_f
     value = te / (ms_step * 1e-3)
     spec = step_variant.startswith("specialized")
@@ -452,6 +480,7 @@ def main():
             "flops_per_launch": dom_fl,
             "kernel_ms": dom_ms,
         },
+        "monte_carlo": mc,
         "construct_ms": construct_ms,
         "specialize_ms": specialize_ms, "specialize": specialize_note,
         "wall_s": wall,

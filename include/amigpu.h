@@ -80,6 +80,43 @@ AmiStatus amiConstruct(int32_t n_g, int32_t n_eps, int32_t n_freq, int32_t n_int
 void amiFree(AmiTerms *terms);
 
 /*
+ * Feynman-graph input (Sec. 2.5).  A graph is a list of lines, 4 integers each:
+ * source vertex, target vertex, B/F (0 bosonic, 1 fermionic), spin (carried,
+ * unused).  Fermionic lines point along the fermion flow, which is also the
+ * direction of their frequency and momentum.
+ *
+ * amiReadGraph -- parse the plain-text form (one line per row, whitespace
+ * separated, '#' starts a comment) into edges (host int32 [cap][4]); *n_edges
+ * and *n_vertices (1 + the largest vertex index) are set even when edges is
+ * NULL.  AMI_E_ARG on unreadable files, malformed rows or a small buffer.
+ */
+AmiStatus amiReadGraph(const char *path, int32_t *edges, int32_t cap, int32_t *n_edges, int32_t *n_vertices);
+
+/*
+ * amiConstructGraph -- momentum-conserving labels for a graph and the
+ * construction of its integrand (amiConstruct with R0 = the labels of the
+ * fermionic lines, in edge order, and one energy per fermionic line).
+ * The external frequency enters at the vertex without an incoming fermionic
+ * line and leaves at the one without an outgoing one (self-energy legs, a
+ * fermionic external slot); with no such vertices, at the two vertices
+ * without a bosonic line (a bosonic external slot).  A spanning tree is grown
+ * from the bosonic lines first, then the fermionic ones, in edge order; each
+ * line outside it carries one summed frequency (slots in edge order) flowing
+ * source -> target on it and back through the tree; the external frequency
+ * flows along the tree path between the external vertices.  Every vertex may
+ * have at most one fermionic line in and one out.  Errors: AMI_E_ARG (sizes,
+ * ranges), AMI_E_LABEL (unbalanced or disconnected graphs, no external legs,
+ * a summed frequency on a bosonic line, and amiConstruct's), AMI_E_UNSUPPORTED
+ * (more than 15 loops or 32 propagators).  amiTermsLabels returns the labels.
+ */
+AmiStatus amiConstructGraph(int32_t n_vertices, int32_t n_edges, const int32_t *edges, uint32_t flags,
+                            AmiTerms **out);
+
+/* R0 of a handle: alpha [n_g][n_freq], eps [n_g][n_eps], fermionic [n_freq]
+ * (host buffers sized from amiTermsInfo; any may be NULL). */
+AmiStatus amiTermsLabels(const AmiTerms *terms, int8_t *alpha, int8_t *eps, uint8_t *fermionic);
+
+/*
  * amiTermsInfo -- sizes of the solution, info[0..15] (host array):
  *   0 T       flat terms after canonical merging (FACTORIZE=false form, Sec. 2.2)
  *   1 n_int   2 n_eps   3 n_freq   4 n_ext (= n_freq - n_int)
@@ -209,6 +246,32 @@ AmiStatus amiEvaluateHubbardAdjoint(AmiTerms *terms,
                                     double *grad_k, double *grad_mu, double *grad_t,
                                     double *grad_beta, double *grad_freqs,
                                     double *out, double *out_sum, void *hip_stream);
+
+/*
+ * amiIntegrateHubbard -- Monte-Carlo integration of the integrand over the
+ * internal momenta (Sec. 5.2; the row average of Sec. 2.3), sampling in the
+ * kernel: sample s (0 <= s < n_samples) draws its 2*n_int momentum
+ * components, row-major as the k rows of amiEvaluateHubbard, from Philox4x32
+ * with 10 rounds (Salmon et al., SC'11): the words of the blocks with counter
+ * (s mod 2^32, s div 2^32, b, 0), b = 0, 1, ..., and key (seed mod 2^32,
+ * seed div 2^32), component c from word c as (u - 1/2) * 2 pi with
+ * u = (word + 1/2) / 2^32, i.e. uniform on (-pi, pi).  No sample touches
+ * device memory.
+ *   q, t, mu      as amiEvaluateHubbard
+ *   ext_freqs     device complex128 [n_f][n_ext], 1 <= n_f <= 8 (split longer lists)
+ *   sums          device float64 [n_f][4]: sum over the samples of Re I, Im I,
+ *                 (Re I)^2, (Im I)^2.  The estimate of the integral with measure
+ *                 d^2k/(2 pi)^2 per loop is (sum Re I + i sum Im I) / n_samples;
+ *                 the squares give its standard error.
+ * The sums are reduced in a fixed order for a given device: repeated calls give
+ * the same bits.  Needs the specialized kernels (AMI_E_UNSUPPORTED beyond
+ * their limits, whatever the handle's variant); the kernel is compiled on first
+ * use.  Uses the handle's per-stream workspace.
+ */
+AmiStatus amiIntegrateHubbard(AmiTerms *terms, int64_t n_samples, uint64_t seed,
+                              const double *q, double t, double mu,
+                              const double *ext_freqs, int64_t n_f, double beta, double e_reg,
+                              double *sums, void *hip_stream);
 
 /*
  * Kernel variants of a handle (amiSetVariant).  All evaluate the same

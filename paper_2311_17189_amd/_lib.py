@@ -90,6 +90,15 @@ def load_library():
     lib.amiEvaluateHubbardAdjoint.restype = c_i32
     lib.amiSetVariant.argtypes = [vp, c_i32]
     lib.amiSetVariant.restype = c_i32
+    lib.amiReadGraph.argtypes = [ctypes.c_char_p, vp, c_i32, ctypes.POINTER(c_i32), ctypes.POINTER(c_i32)]
+    lib.amiReadGraph.restype = c_i32
+    lib.amiConstructGraph.argtypes = [c_i32, c_i32, vp, c_u32, ctypes.POINTER(vp)]
+    lib.amiConstructGraph.restype = c_i32
+    lib.amiTermsLabels.argtypes = [vp, vp, vp, vp]
+    lib.amiTermsLabels.restype = c_i32
+    lib.amiIntegrateHubbard.argtypes = [vp, c_i64, ctypes.c_uint64, vp, c_dbl, c_dbl, vp, c_i64, c_dbl, c_dbl,
+                                        vp, vp]
+    lib.amiIntegrateHubbard.restype = c_i32
     lib.amiTermsSpecialize.argtypes = [vp, c_i32]
     lib.amiTermsSpecialize.restype = c_i32
     lib.amiTermsSource.argtypes = [vp, c_i32, ctypes.c_char_p, c_i64, ctypes.POINTER(c_i64)]
@@ -184,6 +193,38 @@ class Terms:
         self.n_int = int(n_int)
         self.alpha = a
         self.eps = e
+
+    @classmethod
+    def from_graph(cls, edges, n_vertices: Optional[int] = None, factorize: bool = False) -> "Terms":
+        """``amiConstructGraph``: ``edges`` int [n, 4] rows (source, target, B/F, spin)
+        of a Feynman graph (Sec. 2.5), labelled and constructed by the library."""
+        e = np.ascontiguousarray(np.asarray(edges, dtype=np.int32).reshape(-1, 4))
+        nv = int(e[:, :2].max()) + 1 if n_vertices is None else int(n_vertices)
+        self = cls.__new__(cls)
+        self._h = ctypes.c_void_p()
+        _check(load_library().amiConstructGraph(nv, e.shape[0], e.ctypes.data, AMI_FACTORIZE if factorize else 0,
+                                                ctypes.byref(self._h)))
+        self.alpha, self.eps, self.fermionic = self.labels()
+        self.n_g, self.n_freq = self.alpha.shape
+        self.n_eps = self.eps.shape[1]
+        self.n_int = self.info()["n_int"]
+        return self
+
+    @classmethod
+    def from_graph_file(cls, path: str, factorize: bool = False) -> "Terms":
+        """Read a 4-column graph file (``amiReadGraph``) and construct it."""
+        return cls.from_graph(read_graph(path), factorize=factorize)
+
+    def labels(self):
+        """R0 of the handle (``amiTermsLabels``): alpha int8 [n_g, n_freq], eps int8
+        [n_g, n_eps], fermionic uint8 [n_freq]."""
+        inf = self.info()
+        n_g = inf["leaves_per_term"] + inf["dens_per_term"]
+        alpha = np.zeros((n_g, inf["n_freq"]), dtype=np.int8)
+        eps = np.zeros((n_g, inf["n_eps"]), dtype=np.int8)
+        ferm = np.zeros(inf["n_freq"], dtype=np.uint8)
+        _check(load_library().amiTermsLabels(self._h, alpha.ctypes.data, eps.ctypes.data, ferm.ctypes.data))
+        return alpha, eps, ferm
 
     @classmethod
     def from_diagram(cls, d, factorize: bool = False) -> "Terms":
@@ -408,6 +449,54 @@ def evaluate_hubbard_adjoint(terms: Terms, k, q, t: float, mu: float, ext_freqs,
         _ptr(go), _ptr(gs), g_k.data_ptr() if n_e else None, base, base + 8, base + 16,
         g_w.data_ptr(), _ptr(out) if n_e else None, _ptr(out_sum), _stream_ptr(stream)))
     return g_k, scal[0], scal[1], scal[2], g_w
+
+
+def read_graph(path: str) -> np.ndarray:
+    """``amiReadGraph``: the rows (source, target, B/F, spin) of a graph file, int32 [n, 4]."""
+    lib = load_library()
+    n = ctypes.c_int32()
+    nv = ctypes.c_int32()
+    _check(lib.amiReadGraph(path.encode(), None, 0, ctypes.byref(n), ctypes.byref(nv)))
+    buf = np.zeros((max(n.value, 1), 4), dtype=np.int32)
+    _check(lib.amiReadGraph(path.encode(), buf.ctypes.data, n.value, ctypes.byref(n), ctypes.byref(nv)))
+    return buf[:n.value]
+
+
+MC_MAX_FREQS = 8
+
+
+def integrate_hubbard(terms: Terms, n_samples: int, seed: int, q, t: float, mu: float, ext_freqs,
+                      beta: float, e_reg: float = 0.0, sums=None, stream=None):
+    """``amiIntegrateHubbard``: Monte-Carlo sums over ``n_samples`` momenta drawn
+    in the kernel (Philox4x32-10, ``seed``), as a float64 CUDA tensor [N_F, 4]
+    of (sum Re I, sum Im I, sum (Re I)^2, sum (Im I)^2); frequency lists longer
+    than 8 rows are integrated 8 rows per call (same samples for every row)."""
+    import torch
+    w = _freqs(ext_freqs, terms)
+    n_f = w.shape[0]
+    if sums is None:
+        sums = torch.empty((n_f, 4), dtype=torch.float64, device=w.device)
+    elif sums.dtype != torch.float64 or tuple(sums.shape) != (n_f, 4) or not sums.is_contiguous():
+        raise AmiError(-1, f"sums must be contiguous float64 [{n_f}, 4]")
+    qa = np.ascontiguousarray(np.asarray(q, dtype=np.float64).reshape(-1))
+    lib = load_library()
+    sp = _stream_ptr(stream)
+    for f0 in range(0, n_f, MC_MAX_FREQS):
+        f1 = min(n_f, f0 + MC_MAX_FREQS)
+        _check(lib.amiIntegrateHubbard(terms._h, int(n_samples), int(seed) & 0xFFFFFFFFFFFFFFFF, qa.ctypes.data,
+                                       float(t), float(mu), w[f0:f1].data_ptr(), f1 - f0, float(beta),
+                                       float(e_reg), sums[f0:f1].data_ptr(), sp))
+    return sums
+
+
+def mc_estimate(sums, n_samples: int):
+    """Mean (complex [N_F]) and standard error (float [N_F, 2], real and
+    imaginary parts) of the Monte-Carlo estimate from :func:`integrate_hubbard` sums."""
+    s = np.asarray(sums.cpu() if hasattr(sums, "cpu") else sums, dtype=np.float64)
+    n = float(n_samples)
+    mean = (s[:, 0] + 1j * s[:, 1]) / n
+    var = np.stack([s[:, 2] / n - (s[:, 0] / n) ** 2, s[:, 3] / n - (s[:, 1] / n) ** 2], axis=1)
+    return mean, np.sqrt(np.maximum(var, 0.0) / max(n - 1.0, 1.0))
 
 
 class Batch:

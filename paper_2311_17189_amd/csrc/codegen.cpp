@@ -305,7 +305,7 @@ extern "C" AmiStatus amiTermsSource(const AmiTerms *t, int32_t momentum, char *b
     if (!t || !len) return fail(AMI_E_ARG, "NULL argument");
     std::string why;
     if (!jit_supported(t, momentum != 0, &why)) return fail(AMI_E_UNSUPPORTED, "no specialized kernel: " + why);
-    const std::string src = jit_source(t, momentum != 0, 3);
+    const std::string src = jit_source(t, momentum != 0, momentum != 0 ? 7 : 3);
     *len = static_cast<int64_t>(src.size()) + 1;
     if (!buf) return AMI_OK;
     if (cap < *len) return fail(AMI_E_ARG, "buffer too small");

@@ -203,6 +203,35 @@ __device__ __forceinline__ double leaf_deriv(bool bose, double y) {
     return bose ? t * r * r : -t * r * r;
 }
 
+// ---- counter-based random numbers -----------------------------------------
+
+// Philox4x32 with 10 rounds (Salmon, Moraes, Dror and Shaw, SC'11): each round
+// multiplies words 0 and 2 by the two round constants (64-bit products) and
+// forms (hi1 ^ c1 ^ k0, lo1, hi0 ^ c3 ^ k1, lo0); the key grows by the Weyl
+// increments after every round.
+__device__ __forceinline__ void philox4x32_10(uint32_t (&c)[4], uint32_t k0, uint32_t k1) {
+#pragma unroll
+    for (int r = 0; r < 10; ++r) {
+        const uint64_t p0 = static_cast<uint64_t>(0xD2511F53u) * c[0];
+        const uint64_t p1 = static_cast<uint64_t>(0xCD9E8D57u) * c[2];
+        const uint32_t n0 = static_cast<uint32_t>(p1 >> 32) ^ c[1] ^ k0;
+        const uint32_t n2 = static_cast<uint32_t>(p0 >> 32) ^ c[3] ^ k1;
+        c[0] = n0;
+        c[1] = static_cast<uint32_t>(p1);
+        c[2] = n2;
+        c[3] = static_cast<uint32_t>(p0);
+        k0 += 0x9E3779B9u;
+        k1 += 0xBB67AE85u;
+    }
+}
+
+// A uniform momentum component in (-pi, pi) from one 32-bit word:
+// (u - 1/2) * 2 pi with u = (word + 1/2) / 2^32 (exact up to the last product).
+__device__ __forceinline__ double word_to_momentum(uint32_t w) {
+    const double u = (static_cast<double>(w) + 0.5) * 0x1p-32;
+    return (u - 0.5) * 0x1.921fb54442d18p+2;
+}
+
 // sum_i (+-1) E_i over the bits of two 16-bit masks (scalar bit tests).
 template <int NE>
 __device__ __forceinline__ double combo(uint32_t pos, uint32_t neg, const double (&E)[NE]) {

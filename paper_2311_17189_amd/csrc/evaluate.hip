@@ -343,7 +343,7 @@ AmiStatus choose_path(AmiTerms *t, bool hub, bool adjoint, Path &p, void **jit_f
     const bool auto_skip = v == AMI_VARIANT_AUTO && adjoint && t->tab.T > kJitAutoAdjointTerms;
     if (auto_skip) note = " (adjoint specialized up to " + std::to_string(kJitAutoAdjointTerms) + " terms)";
     if (v == AMI_VARIANT_SPECIALIZED || (v == AMI_VARIANT_AUTO && !auto_skip)) {
-        const AmiStatus st = jit_get(t, hub, adjoint, jit_fn);
+        const AmiStatus st = jit_get(t, hub, adjoint ? kJitAdjoint : kJitForward, jit_fn);
         if (st == AMI_OK) {
             p = Path::SPECIALIZED;
             return AMI_OK;
@@ -693,6 +693,54 @@ AmiStatus amiEvaluateHubbardAdjoint(AmiTerms *t, const double *k, int64_t n_e, i
     return launch_adjoint(t, true, a, o, static_cast<hipStream_t>(hip_stream));
 }
 
+AmiStatus amiIntegrateHubbard(AmiTerms *t, int64_t n_samples, uint64_t seed, const double *q, double hop_t,
+                              double mu, const double *ext_freqs, int64_t n_f, double beta, double e_reg,
+                              double *sums, void *hip_stream) {
+    using namespace ami;
+    clear_error();
+    AmiStatus st = check_common(t, n_samples, ext_freqs, n_f, beta);
+    if (st != AMI_OK) return st;
+    if (n_f > kMcMaxFreqs) return fail(AMI_E_ARG, "at most 8 frequency rows per Monte-Carlo call");
+    if (!sums) return fail(AMI_E_ARG, "sums is NULL");
+    if (t->n_eps != t->n_g) return fail(AMI_E_ARG, "the momentum path needs one energy per propagator");
+    if (t->n_ext > 0 && !q) return fail(AMI_E_ARG, "q is NULL");
+    const hipStream_t stream = static_cast<hipStream_t>(hip_stream);
+    DeviceTables *dt = nullptr;
+    st = upload(t, &dt);
+    if (st != AMI_OK) return st;
+    void *fn = nullptr;
+    st = jit_get(t, true, kJitMonteCarlo, &fn);
+    if (st != AMI_OK) return st;
+    if (n_samples == 0) return fill(sums, 4 * n_f, stream);
+    int dev = 0, n_cu = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e == hipSuccess) e = hipDeviceGetAttribute(&n_cu, hipDeviceAttributeMultiprocessorCount, dev);
+    if (e != hipSuccess) return hip_fail(e, "hipDeviceGetAttribute");
+    // a fixed grid per device (the sums are reduced in a fixed order for it):
+    // eight blocks per CU, or fewer when there are fewer samples
+    const int block = jit_block(t, true);
+    const int64_t grid = std::min<int64_t>((n_samples + block - 1) / block, 8 * static_cast<int64_t>(n_cu));
+    double *partial = nullptr;
+    st = workspace(t, dt, stream, static_cast<size_t>(grid) * n_f * 4 * sizeof(double), &partial);
+    if (st != AMI_OK) return st;
+    KArgs a;
+    std::memset(&a, 0, sizeof(a));
+    set_momenta(a, t, nullptr, 0, q, hop_t, mu);
+    set_common(a, ext_freqs, n_f, beta, e_reg, n_samples);
+    a.seed = seed;
+    a.partial = partial;
+    timer_mark(stream, false);
+    e = launch_jit(fn, grid, block, stream, a);
+    if (e == hipSuccess) e = hipGetLastError();
+    timer_mark(stream, true);
+    g_last_variant = "specialized";
+    if (e != hipSuccess) return hip_fail(e, "Monte-Carlo launch");
+    hipLaunchKernelGGL(ami_colsum_kernel, dim3(static_cast<unsigned>(4 * n_f)), dim3(256), 0, stream, partial, grid,
+                       static_cast<int>(4 * n_f), sums);
+    e = hipGetLastError();
+    return e == hipSuccess ? AMI_OK : hip_fail(e, "Monte-Carlo reduction launch");
+}
+
 AmiStatus amiSetVariant(AmiTerms *t, int32_t variant) {
     ami::clear_error();
     if (!t) return ami::fail(AMI_E_ARG, "terms is NULL");
@@ -706,9 +754,9 @@ AmiStatus amiTermsSpecialize(AmiTerms *t, int32_t momentum) {
     ami::clear_error();
     if (!t) return ami::fail(AMI_E_ARG, "terms is NULL");
     void *fn = nullptr;
-    const AmiStatus st = ami::jit_get(t, momentum != 0, false, &fn);
+    const AmiStatus st = ami::jit_get(t, momentum != 0, ami::kJitForward, &fn);
     if (st != AMI_OK) return st;
-    return ami::jit_get(t, momentum != 0, true, &fn);
+    return ami::jit_get(t, momentum != 0, ami::kJitAdjoint, &fn);
 }
 
 const char *amiLastVariant(void) { return ami::g_last_variant.c_str(); }

@@ -139,18 +139,18 @@ AmiStatus compile(const std::string &src, std::vector<char> &code, std::string &
 }
 
 // Code object for (t, kind): from the handle, the disk cache, or a compilation.
-AmiStatus code_object(AmiTerms *t, bool hub, bool adjoint) {
-    const int kind = 2 * (hub ? 1 : 0) + (adjoint ? 1 : 0);
-    std::vector<char> &code = t->jit_code[kind];
+AmiStatus code_object(AmiTerms *t, bool hub, int kind) {
+    const int slot = 3 * (hub ? 1 : 0) + kind;
+    std::vector<char> &code = t->jit_code[slot];
     if (!code.empty()) return AMI_OK;
-    std::string &err = t->jit_error[kind];
+    std::string &err = t->jit_error[slot];
     if (!err.empty()) return fail(AMI_E_UNSUPPORTED, err);
     std::string why;
     if (!jit_supported(t, hub, &why)) {
         err = "no specialized kernel: " + why;
         return fail(AMI_E_UNSUPPORTED, err);
     }
-    const std::string src = jit_source(t, hub, adjoint ? 2 : 1);
+    const std::string src = jit_source(t, hub, 1 << kind);
     const std::string dir = cache_dir();
     const std::string base = dir.empty() ? std::string() : dir + "/" + cache_key(src);
     if (!base.empty()) {
@@ -171,32 +171,35 @@ AmiStatus code_object(AmiTerms *t, bool hub, bool adjoint) {
 
 }  // namespace
 
-AmiStatus jit_get(AmiTerms *t, bool hub, bool adjoint, void **fn) {
+AmiStatus jit_get(AmiTerms *t, bool hub, int kind, void **fn) {
+    if (kind < kJitForward || kind > kJitMonteCarlo || (kind == kJitMonteCarlo && !hub))
+        return fail(AMI_E_ARG, "no such specialized kernel");
     std::lock_guard<std::mutex> lock(t->jit_mu);
-    const int kind = 2 * (hub ? 1 : 0) + (adjoint ? 1 : 0);
+    const int slot = 3 * (hub ? 1 : 0) + kind;
     // the compilation needs no device: do it first
-    AmiStatus st = code_object(t, hub, adjoint);
+    AmiStatus st = code_object(t, hub, kind);
     if (st != AMI_OK) return st;
     int dev = 0;
     hipError_t e = hipGetDevice(&dev);
     if (e != hipSuccess) return hip_fail(e, "hipGetDevice");
     for (const auto &m : t->jit_mods)
-        if (m.device == dev && m.kind == kind) {
+        if (m.device == dev && m.kind == slot) {
             *fn = m.fn;
             return AMI_OK;
         }
     hipModule_t mod = nullptr;
-    e = hipModuleLoadData(&mod, t->jit_code[kind].data());
+    e = hipModuleLoadData(&mod, t->jit_code[slot].data());
     if (e != hipSuccess) return hip_fail(e, "hipModuleLoadData (specialized kernel)");
     hipFunction_t f = nullptr;
-    e = hipModuleGetFunction(&f, mod, adjoint ? "ami_jit_adj" : "ami_jit_fwd");
+    static const char *const kNames[3] = {"ami_jit_fwd", "ami_jit_adj", "ami_jit_mc"};
+    e = hipModuleGetFunction(&f, mod, kNames[kind]);
     if (e != hipSuccess) {
         (void)hipModuleUnload(mod);
         return hip_fail(e, "hipModuleGetFunction (specialized kernel)");
     }
     AmiTerms::JitModule m;
     m.device = dev;
-    m.kind = kind;
+    m.kind = slot;
     m.module = mod;
     m.fn = reinterpret_cast<void *>(f);
     t->jit_mods.push_back(m);

@@ -22,15 +22,18 @@ bool jit_supported(const AmiTerms *t, bool hub, std::string *why);
 // Lanes per block of the specialized kernels.
 int jit_block(const AmiTerms *t, bool hub);
 
-// Device source of the specialized kernels: the forward (kernels & 1) and/or
-// the adjoint (kernels & 2).
+// Device source of the specialized kernels: the forward (kernels & 1), the
+// adjoint (kernels & 2) and/or the Monte-Carlo integrator (kernels & 4).
 std::string jit_source(const AmiTerms *t, bool hub, int kernels);
 
-// The specialized forward (adjoint = false) or adjoint kernel for the energy
-// (hub = false) or momentum input as a hipFunction_t: compiled (or fetched
-// from the code-object cache) and loaded on the current device on first use;
-// thread-safe per handle.
-AmiStatus jit_get(AmiTerms *t, bool hub, bool adjoint, void **fn);
+// Kernels of the specialized evaluator.
+enum JitKind { kJitForward = 0, kJitAdjoint = 1, kJitMonteCarlo = 2 };
+
+// The specialized kernel of `kind` for the energy (hub = false) or momentum
+// input as a hipFunction_t: compiled (or fetched from the code-object cache)
+// and loaded on the current device on first use; thread-safe per handle.
+// The Monte-Carlo kernel exists for the momentum input only.
+AmiStatus jit_get(AmiTerms *t, bool hub, int kind, void **fn);
 
 // Unload every module of the handle (amiFree).
 void jit_release(AmiTerms *t);

@@ -41,6 +41,15 @@ constexpr int kParkCols = kParkChain + (kParkDv ? L : 0);
 // input) sin K_jx, sin K_jy and cos K_jx + cos K_jy, needed only by the final
 // chain rule, are parked in LDS columns (park[(c NG + j) B + tid], c = 0, 1, 2)
 // rather than held in registers through the frequency loop.
+// E_j = 2t(cos K_jx + cos K_jy) + mu (Sec. 5.2) from momenta in [-pi, pi]
+__device__ __forceinline__ void energies_from(const KArgs &a, const double (&kx)[NIA], const double (&ky)[NIA],
+                                              double (&E)[NE]) {
+    double Kx[NGA], Ky[NGA];
+    lines(kx, ky, a.q, Kx, Ky);
+#pragma unroll
+    for (int j = 0; j < NG; ++j) E[j] = fma(2.0 * a.hop_t, ami::cos_red(Kx[j]) + ami::cos_red(Ky[j]), a.mu);
+}
+
 template <bool HUB, bool KEEP>
 __device__ __forceinline__ void energies(const KArgs &a, int64_t sc, double (&E)[NE], double *park) {
     if constexpr (HUB) {
@@ -51,6 +60,10 @@ __device__ __forceinline__ void energies(const KArgs &a, int64_t sc, double (&E)
         for (int l = 0; l < NI; ++l) {
             kx[l] = ami::reduce_2pi(row[2 * l]);
             ky[l] = ami::reduce_2pi(row[2 * l + 1]);
+        }
+        if constexpr (!KEEP) {
+            energies_from(a, kx, ky, E);
+            return;
         }
         double Kx[NGA], Ky[NGA];
         lines(kx, ky, a.q, Kx, Ky);
@@ -284,10 +297,83 @@ __device__ __forceinline__ void adj_tile(const KArgs &a, int64_t blk, double *re
     ami::block_sum2(active ? gt : 0.0, 0.0, red, tid, B, gp + 2);
 }
 
+// Monte-Carlo integration over the internal momenta (Sec. 5.2, the row
+// average of Sec. 2.3): sample s = blockIdx.x B + tid + i gridDim.x B draws
+// its 2 NI components from Philox blocks (counter (s mod 2^32, s div 2^32,
+// b, 0), key = the 64-bit seed), evaluates every frequency row, and
+// accumulates sum Re I, sum Im I, sum (Re I)^2, sum (Im I)^2 per lane; the
+// block sums go to partial[block][n_f][4].  Nothing per sample touches HBM.
+template <bool HUB>
+__device__ __forceinline__ void mc_block(const KArgs &a, double *red) {
+    static_assert(HUB, "Monte-Carlo integration samples momenta");
+    const int tid = threadIdx.x, B = blockDim.x;
+    const int64_t stride = static_cast<int64_t>(gridDim.x) * B;
+    const uint32_t k0 = static_cast<uint32_t>(a.seed), k1 = static_cast<uint32_t>(a.seed >> 32);
+    double acc[4][ami::kMcMaxFreqs];
+#pragma unroll
+    for (int f = 0; f < ami::kMcMaxFreqs; ++f) acc[0][f] = acc[1][f] = acc[2][f] = acc[3][f] = 0.0;
+    for (int64_t s = static_cast<int64_t>(blockIdx.x) * B + tid; s < a.n_e; s += stride) {
+        double kx[NIA], ky[NIA];
+#pragma unroll
+        for (int b = 0; b < (2 * NI + 3) / 4; ++b) {
+            uint32_t c[4] = {static_cast<uint32_t>(s), static_cast<uint32_t>(static_cast<uint64_t>(s) >> 32),
+                             static_cast<uint32_t>(b), 0u};
+            ami::philox4x32_10(c, k0, k1);
+#pragma unroll
+            for (int w = 0; w < 4; ++w) {
+                const int comp = 4 * b + w;
+                if (comp < 2 * NI) {
+                    const double v = ami::word_to_momentum(c[w]);
+                    if (comp % 2 == 0) kx[comp / 2] = v;
+                    else ky[comp / 2] = v;
+                }
+            }
+        }
+        double E[NE], x[L], F[L], FT[G];
+        energies_from(a, kx, ky, E);
+        leaf_args(E, x);
+#pragma unroll
+        for (int l = 0; l < L; ++l) {
+            double fm;
+            if (kBose[l]) ami::leaf_pair(true, a.beta * (x[l] + a.e_reg), F[l], fm);
+            else ami::leaf_pair(false, a.beta * x[l], F[l], fm);
+        }
+        group_sums(F, FT);
+#pragma unroll
+        for (int f = 0; f < ami::kMcMaxFreqs; ++f) {
+            if (f < a.n_f) {
+                double wr[NXA], wi[NXA], xr[D], xi[D], Rr[G], Ri[G];
+                load_freq(a, f, wr, wi);
+                reciprocals(E, wr, wi, xr, xi);
+                group_products(xr, xi, Rr, Ri);
+                double re = 0.0, im = 0.0;
+#pragma unroll
+                for (int g = 0; g < G; ++g) {
+                    re = fma(FT[g], Rr[g], re);
+                    im = fma(FT[g], Ri[g], im);
+                }
+                acc[0][f] += re;
+                acc[1][f] += im;
+                acc[2][f] = fma(re, re, acc[2][f]);
+                acc[3][f] = fma(im, im, acc[3][f]);
+            }
+        }
+    }
+#pragma unroll
+    for (int f = 0; f < ami::kMcMaxFreqs; ++f) {
+        if (f < a.n_f) {
+            double *dst = a.partial + (static_cast<int64_t>(blockIdx.x) * a.n_f + f) * 4;
+            ami::block_sum2(acc[0][f], acc[1][f], red, tid, B, dst);
+            ami::block_sum2(acc[2][f], acc[3][f], red, tid, B, dst + 2);
+        }
+    }
+}
+
 }  // namespace amijit
 
 // AMI_JIT_BLOCK lanes per block (the host launches with the same value);
-// AMI_JIT_KERNELS selects the forward (1), the adjoint (2) or both (3)
+// AMI_JIT_KERNELS selects the forward (1), the adjoint (2), the Monte-Carlo
+// integrator (4), or a sum of them
 #if AMI_JIT_KERNELS & 1
 extern "C" __global__ __launch_bounds__(AMI_JIT_BLOCK) void ami_jit_fwd(ami::KArgs a) {
     __shared__ double red[2 * (AMI_JIT_BLOCK / 64)];
@@ -306,5 +392,12 @@ extern "C" __global__ __launch_bounds__(AMI_JIT_BLOCK) AMI_JIT_ADJ_ATTR void ami
     __shared__ double red[2 * (AMI_JIT_BLOCK / 64)];
     __shared__ double park[amijit::kParkCols > 0 ? amijit::kParkCols * AMI_JIT_BLOCK : 1];
     amijit::adj_tile<AMI_JIT_HUB>(a, blockIdx.x, red, park);
+}
+#endif
+
+#if AMI_JIT_KERNELS & 4
+extern "C" __global__ __launch_bounds__(AMI_JIT_BLOCK) void ami_jit_mc(ami::KArgs a) {
+    __shared__ double red[2 * (AMI_JIT_BLOCK / 64)];
+    amijit::mc_block<AMI_JIT_HUB>(a, red);
 }
 #endif

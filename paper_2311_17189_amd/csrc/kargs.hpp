@@ -31,7 +31,12 @@ struct KArgs {
     double *grad_e;             // [n_e][n_eps] or NULL
     double *grad_k;             // [n_e][2 n_int] or NULL
     double *gpartial;           // [grid][kAdjScalars + 2 n_f n_ext]
+    // Monte-Carlo integration (momenta drawn in the kernel; n_e samples)
+    uint64_t seed;
 };
+
+// Frequency rows one Monte-Carlo launch accumulates (the caller splits longer lists).
+constexpr int kMcMaxFreqs = 8;
 
 // Per-block adjoint partial sums: dL/dbeta, dL/dmu, dL/dt, (unused), then
 // dL/dw as complex [n_f][n_ext].

@@ -252,3 +252,16 @@ def specialized_adjoint_flops(st: Structure, n_e: int, n_f: int, line_alpha=None
     total = n_e * per_sample + n_e * n_f * per_point
     return {"per_sample": per_sample, "per_point": per_point, "total": float(total),
             "term_evals": float(st.T) * n_e * n_f}
+
+
+def mc_flops(st: Structure, n_samples: int, n_f: int, line_alpha) -> dict:
+    """FLOPs of one Monte-Carlo launch: per sample the word-to-momentum
+    mapping (four per component), the specialized forward without its output,
+    and per (sample, frequency) four accumulations (two adds, two FMAs)."""
+    comps = 2 * st.n_int
+    fw = specialized_forward_flops(st, 1, 1, line_alpha)
+    per_sample = fw["per_sample"] - 2 * st.n_int * C_RED2PI + 4 * comps
+    per_point = fw["per_point"] + 6
+    total = float(n_samples) * (per_sample + n_f * per_point)
+    return {"per_sample": per_sample, "per_point": per_point, "total": total,
+            "term_evals": float(st.T) * n_samples * n_f}

@@ -9,6 +9,17 @@
 int main(int argc, char **argv) {
     if (argc < 2) return 2;
     const char *what = argv[1];
+    if (what[0] == 'p') {   // Philox4x32-10: counter[4] key[2] per line -> 4 words, and their momenta
+        unsigned long long v[6];
+        while (std::scanf("%llu %llu %llu %llu %llu %llu", &v[0], &v[1], &v[2], &v[3], &v[4], &v[5]) == 6) {
+            uint32_t c[4] = {static_cast<uint32_t>(v[0]), static_cast<uint32_t>(v[1]), static_cast<uint32_t>(v[2]),
+                             static_cast<uint32_t>(v[3])};
+            ami::philox4x32_10(c, static_cast<uint32_t>(v[4]), static_cast<uint32_t>(v[5]));
+            std::printf("%u %u %u %u %.17g %.17g %.17g %.17g\n", c[0], c[1], c[2], c[3], ami::word_to_momentum(c[0]),
+                        ami::word_to_momentum(c[1]), ami::word_to_momentum(c[2]), ami::word_to_momentum(c[3]));
+        }
+        return 0;
+    }
     double x;
     while (std::scanf("%lf", &x) == 1) {
         if (what[0] == 'r') {

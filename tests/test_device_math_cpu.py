@@ -1,6 +1,8 @@
 """The device math of the HIP evaluators (own sin/cos, exp/expm1 pair, Fermi and
 Bose leaves with their mirrors and derivatives), compiled for the host with a
-stand-in HIP header and compared with 40-digit mpmath values (CPU only)."""
+stand-in HIP header and compared with 40-digit mpmath values; the device
+Philox generator and its momentum mapping against the oracle's and the
+published known answers (CPU only)."""
 import os
 import shutil
 import subprocess
@@ -100,3 +102,26 @@ def test_leaf_pair_and_derivative(exe, kind):
         assert _ulp_err(f, ef) <= 8, (y, f, ef)
         assert _ulp_err(fm, efm) <= 8, (y, fm, efm)
         assert _ulp_err(df, -ef * efm) <= 12, (y, df)
+
+
+def test_device_philox_matches_oracle_and_known_answers(exe):
+    from oracle.mc import draw_momenta, philox4x32
+    rng = np.random.default_rng(61)
+    rows = [[0, 0, 0, 0, 0, 0], [2 ** 32 - 1] * 6,
+            [0x243f6a88, 0x85a308d3, 0x13198a2e, 0x03707344, 0xa4093822, 0x299f31d0]]
+    rows += rng.integers(0, 2 ** 32, size=(40, 6)).tolist()
+    res = subprocess.run([exe, "p"], input="\n".join(" ".join(str(int(x)) for x in r) for r in rows),
+                         capture_output=True, text=True, check=True)
+    out = [l.split() for l in res.stdout.splitlines()]
+    assert len(out) == len(rows)
+    for r, o in zip(rows, out):
+        want = philox4x32(r[:4], r[4:])
+        assert [int(x) for x in o[:4]] == want
+        assert [float(x) for x in o[4:]] == [((w + 0.5) * 2.0 ** -32 - 0.5) * 2 * np.pi for w in want]
+    assert [int(x) for x in out[0][:4]] == [0x6627e8d5, 0xe169c58d, 0xbc57ac4c, 0x9b00dbd8]
+    # the sample layout of oracle.mc: sample 5, seed 9 -> counter (5, 0, b, 0), key (9, 0)
+    k = draw_momenta(5, 1, 8, seed=9)[0]
+    res = subprocess.run([exe, "p"], input="5 0 0 0 9 0\n5 0 1 0 9 0\n", capture_output=True, text=True,
+                         check=True)
+    dev = [float(x) for l in res.stdout.splitlines() for x in l.split()[4:]]
+    assert dev == k.tolist()
