@@ -24,14 +24,26 @@ Readings taken where the paper is silent (each listed in the design notes):
   so ``f(z) = 1/(sigma exp(beta x) + 1)`` with ``x`` the pole's energy part and
   ``sigma = (-1)^(sum of the pole's fermionic frequency coefficients)``:
   ``sigma = +1`` is the Fermi function, ``sigma = -1`` is ``-n_B``;
-* a summation coefficient other than +-1, or two poles at the same place (a
-  higher-order pole, Eq. (5)), is rejected rather than handled.
+* a summation coefficient other than +-1 is rejected; two or more
+  denominators with their pole at the same place (a pole of order M, Eq. (5))
+  are rejected unless ``multipole=True``, which takes the residue of Eq. (5):
+  with ``D_r = c_r (z - z0)`` for the M denominators of the pole,
+  ``(z - z0)^M f(beta z) prod_q 1/D_q = prod_r c_r * f(beta z) prod_{other q} 1/D_q``
+  and the (M-1)-th derivative by the Leibniz rule gives, for every split
+  ``j + sum_q k_q = M - 1``, the term
+  ``prod_r c_r * T_j(x0) * prod_q (-a_q)^k_q C(m_q + k_q - 1, k_q) D_q(z0)^-(m_q + k_q)``
+  where ``a_q`` is the coefficient of ``nu_p`` in ``D_q``, ``m_q`` its
+  multiplicity, and ``T_j(x) = (1/j!) d^j/dx^j f(beta x)`` the j-th Taylor
+  coefficient of the pole's Fermi/Bose function at its energy part ``x0``
+  (the frequency part again drops out by periodicity).
 
 Data model (plain Python tuples of ints):
 
 * denominator ``(e, a)``: ``e`` energy coefficients (length nE), ``a`` frequency
-  coefficients (length nF); its value is ``sum a_l w_l + sum e_i E_i``;
-* leaf ``(sigma, e)``: the function ``f_sigma(beta * sum e_i E_i)``;
+  coefficients (length nF); its value is ``sum a_l w_l + sum e_i E_i``; a term
+  holds its denominators as a multiset (a repeated entry is a power);
+* leaf ``(code, e)``: ``code = sigma * (1 + j)``: the Taylor coefficient
+  ``T_j`` of ``f_sigma(beta * sum e_i E_i)`` (``j = 0``: the function itself);
 * term ``(s, leaves, dens)``: ``s * prod(leaves) / prod(dens)``.
 """
 from __future__ import annotations
@@ -95,21 +107,41 @@ def validate(alpha, eps, n_int: int, fermionic=None) -> np.ndarray:
     return fermionic
 
 
-def sum_one_frequency(term: Term, p: int, fermionic: Sequence[int]) -> List[Term]:
+def _splits(total: int, n: int):
+    """Every tuple of n non-negative integers summing to total."""
+    if n == 0:
+        if total == 0:
+            yield ()
+        return
+    for k in range(total + 1):
+        for rest in _splits(total - k, n - 1):
+            yield (k,) + rest
+
+
+def _binom(n: int, k: int) -> int:
+    out = 1
+    for i in range(k):
+        out = out * (n - i) // (i + 1)
+    return out
+
+
+def sum_one_frequency(term: Term, p: int, fermionic: Sequence[int], multipole: bool = False) -> List[Term]:
     """Apply the residue theorem Eq. (3) to the sum over ``nu_p`` of one term.
 
-    Every denominator with a non-zero coefficient of ``nu_p`` contributes one
-    pole (Eq. (4)); the new term takes the residue factor ``1/c = c``, the
+    Every denominator with a non-zero coefficient of ``nu_p`` has its pole
+    (Eq. (4)); the new term takes the residue factor ``1/c = c``, the
     Fermi/Bose leaf of the pole, and the other denominators evaluated at the
     pole.  The frequency part of the pole is dropped from the leaf
     (``exp(beta i nu)`` is -1 or +1) and kept in the substituted denominators.
+    Denominators sharing a pole make it a pole of higher order: rejected, or
+    with ``multipole`` taken by Eq. (5) as described in the module notes.
     """
     s, leaves, dens = term
     n_freq = len(dens[0][1]) if dens else 0
     P = [r for r, (_, a) in enumerate(dens) if a[p] != 0]
     if not P:
         raise LabelError(f"no denominator depends on summed frequency {p}")
-    poles: Dict[Den, int] = {}
+    poles: Dict[Den, List[int]] = {}
     for r in P:
         e_r, a_r = dens[r]
         c = a_r[p]
@@ -117,40 +149,54 @@ def sum_one_frequency(term: Term, p: int, fermionic: Sequence[int]) -> List[Term
             raise CoeffError(f"coefficient {c} of summed frequency {p}")
         e_z = tuple(-c * x for x in e_r)
         a_z = tuple(0 if l == p else -c * a_r[l] for l in range(n_freq))
-        if (e_z, a_z) in poles:
+        if (e_z, a_z) in poles and not multipole:
             raise MultipoleError(f"two denominators share a pole in frequency {p}")
-        poles[(e_z, a_z)] = r
+        poles.setdefault((e_z, a_z), []).append(r)
     out: List[Term] = []
-    for (e_z, a_z), r in poles.items():
-        c = dens[r][1][p]
+    for (e_z, a_z), group in poles.items():
+        M = len(group)
+        pref = s
+        for r in group:
+            pref *= dens[r][1][p]
         parity = sum(a_z[l] for l in range(n_freq) if fermionic[l]) % 2
         sigma = 1 if parity == 0 else -1
-        new_dens = []
+        # the other denominators at the pole, with their multiplicities and nu_p coefficients
+        fixed, moving = [], {}
         for q, (e_q, a_q) in enumerate(dens):
-            if q == r:
+            if q in group:
                 continue
             m = a_q[p]
             if m == 0:
-                new_dens.append((e_q, a_q))
+                fixed.append((e_q, a_q))
                 continue
             e_new = tuple(e_q[i] + m * e_z[i] for i in range(len(e_q)))
             a_new = tuple(0 if l == p else a_q[l] + m * a_z[l] for l in range(n_freq))
-            new_dens.append((e_new, a_new))
-        out.append((s * c, leaves + ((sigma, e_z),), tuple(new_dens)))
+            key = ((e_new, a_new), m)
+            moving[key] = moving.get(key, 0) + 1
+        mkeys = list(moving)
+        for split in _splits(M - 1, 1 + len(mkeys)):
+            j, ks = split[0], split[1:]
+            coef = pref
+            new_dens = list(fixed)
+            for (den, a), mult, k in zip(mkeys, (moving[x] for x in mkeys), ks):
+                coef *= (-a) ** k * _binom(mult + k - 1, k)
+                new_dens.extend([den] * (mult + k))
+            out.append((coef, leaves + ((sigma * (1 + j), e_z),), tuple(new_dens)))
     return out
 
 
-def construct(alpha, eps, n_int: int, fermionic=None) -> List[Term]:
+def construct(alpha, eps, n_int: int, fermionic=None, multipole: bool = False) -> List[Term]:
     """Flat (FACTORIZE=false) solution: repeated residues over nu_1..nu_n.
 
-    Returns the raw term list, in the order the residues produce it.
+    Returns the raw term list, in the order the residues produce it.  With
+    ``multipole``, poles of higher order are taken by Eq. (5).
     """
     fermionic = validate(alpha, eps, n_int, fermionic)
     terms: List[Term] = [(1, (), make_r0(alpha, eps))]
     for p in range(n_int):
         nxt: List[Term] = []
         for t in terms:
-            nxt.extend(sum_one_frequency(t, p, fermionic))
+            nxt.extend(sum_one_frequency(t, p, fermionic, multipole))
         terms = nxt
     for _, _, dens in terms:
         for e, a in dens:
@@ -199,11 +245,18 @@ def serialize(terms: Sequence[Term], n_int: int, n_eps: int, n_freq: int) -> Lis
     """Flat int32 stream of a canonical term list.
 
     Header ``n_int, nE, nF, T``; then per term ``s``, ``n_int`` leaves as
-    ``sigma, e[0..nE)``, and the denominators as ``e[0..nE), a[0..nF)``.
+    ``code, e[0..nE)``, and the denominators as ``e[0..nE), a[0..nF)``.
+    When the terms do not all hold the same number of denominators (poles of
+    higher order), the header's ``T`` is written as ``-T`` and every term's
+    ``s`` is followed by its number of denominators.
     """
-    out = [n_int, n_eps, n_freq, len(terms)]
+    counts = {len(d) for _, _, d in terms}
+    extended = len(counts) > 1
+    out = [n_int, n_eps, n_freq, -len(terms) if extended else len(terms)]
     for s, leaves, dens in terms:
         out.append(int(s))
+        if extended:
+            out.append(len(dens))
         for sigma, e in leaves:
             out.append(int(sigma))
             out.extend(int(x) for x in e)

@@ -18,7 +18,9 @@ vectorized over samples.
 
 Readings: a leaf ``(sigma, e)`` is ``f_sigma(y) = 1/(sigma*exp(y) + 1)`` at
 ``y = beta*(e . E)``; the regulator ``e_reg`` is added to ``e . E`` of
-``sigma = -1`` (Bose-type) leaves only.  A denominator ``(e, a)`` is
+``sigma = -1`` (Bose-type) leaves only.  A leaf code ``sigma (1 + j)`` with
+``j > 0`` (from a pole of higher order) is the j-th Taylor coefficient of that
+function in ``x = e . E`` (:func:`leaf_coefficient`).  A denominator ``(e, a)`` is
 ``e . E + a_ext . w`` -- internal frequency slots are zero after construction
 and are ignored.
 """
@@ -39,6 +41,43 @@ def leaf_value(sigma: int, y):
         if sigma == 1:
             return 1 / (np.exp(y) + 1)
         return -1 / np.expm1(y)
+
+
+def _derivative_monomials(j: int):
+    """f^(j) of a leaf as a polynomial in f and fm = f(-y) = 1 - f:
+    {(a, b): c} for c f^a fm^b, from f' = -f fm and fm' = f fm (both kinds)."""
+    poly = {(1, 0): 1}
+    for _ in range(j):
+        nxt = {}
+        for (a, b), c in poly.items():
+            if a:
+                nxt[(a, b + 1)] = nxt.get((a, b + 1), 0) - a * c
+            if b:
+                nxt[(a + 1, b)] = nxt.get((a + 1, b), 0) + b * c
+        poly = {k: v for k, v in nxt.items() if v}
+    return poly
+
+
+def leaf_coefficient(code: int, x, beta):
+    """Leaf ``(code, e)`` at ``x = e.E`` (with the regulator already added):
+    for ``code = sigma (1 + j)`` the Taylor coefficient
+    ``T_j(x) = (1/j!) d^j/dx^j f_sigma(beta x) = beta^j f_sigma^(j)(beta x) / j!``,
+    with ``f^(j)`` written through ``f`` and ``f(-y) = 1 - f`` (no cancellation
+    where f saturates)."""
+    sigma = 1 if code > 0 else -1
+    j = abs(code) - 1
+    y = beta * x
+    f = leaf_value(sigma, y)
+    if j == 0:
+        return f
+    fm = leaf_value(sigma, -y)
+    acc = 0
+    for (a, b), c in _derivative_monomials(j).items():
+        acc = acc + c * f ** a * fm ** b
+    fact = 1
+    for i in range(2, j + 1):
+        fact *= i
+    return acc * beta ** j / fact
 
 
 def _ext_slots(n_int: int, a: Sequence[int]):
@@ -65,11 +104,11 @@ def evaluate_terms(terms, n_int: int, energies, ext_freqs, beta, e_reg=0.0,
     out = np.zeros((n_f, n_e), dtype=cdt)
     for s, leaves, dens in terms:
         ft = np.full(n_e, dtype(s), dtype=dtype)
-        for sigma, e in leaves:
+        for code, e in leaves:
             x = E @ np.asarray(e, dtype=dtype)
-            if sigma == -1:
+            if code < 0:
                 x = x + e_reg
-            ft = ft * leaf_value(sigma, beta * x)
+            ft = ft * leaf_coefficient(code, x, beta)
         for f in range(n_f):
             r = np.ones(n_e, dtype=cdt)
             for e, a in dens:
@@ -223,6 +262,7 @@ def gradients(terms, n_int: int, energies, ext_freqs, beta, cot, e_reg=0.0,
         dlnft_dE = np.zeros((n_e, n_eps), dtype=LD)
         dlnft_db = np.zeros(n_e, dtype=LD)
         for sigma, e in leaves:
+            assert abs(sigma) == 1, "gradients of Taylor-coefficient leaves are not implemented"
             ev = np.asarray(e, dtype=LD)
             x = E @ ev
             if sigma == -1:

@@ -557,6 +557,7 @@ void set_momenta(KArgs &a, const AmiTerms *t, const double *k, int64_t stride_k,
     a.k = k;
     a.stride_k = stride_k;
     a.q_big = 0;
+    if (k && (reinterpret_cast<uintptr_t>(k) & 15u) == 0 && (stride_k & 1) == 0) a.vec_io |= 1;
     for (int x = 0; x < t->n_ext && x < kMaxExtDev; ++x) {
         a.q[2 * x] = std::remainder(q[2 * x], 2.0 * M_PI);
         a.q[2 * x + 1] = std::remainder(q[2 * x + 1], 2.0 * M_PI);
@@ -683,6 +684,7 @@ AmiStatus amiEvaluateHubbardAdjoint(AmiTerms *t, const double *k, int64_t n_e, i
     a.g_out = grad_out;
     a.g_sum = grad_sum;
     a.grad_k = grad_k;
+    if (grad_k && (reinterpret_cast<uintptr_t>(grad_k) & 15u) == 0) a.vec_io |= 2;
     a.out = out;
     AdjOut o;
     o.grad_beta = grad_beta;

@@ -56,10 +56,19 @@ __device__ __forceinline__ void energies(const KArgs &a, int64_t sc, double (&E)
         // E_j = 2t(cos K_jx + cos K_jy) + mu (Sec. 5.2), momenta reduced into [-pi, pi]
         double kx[NIA], ky[NIA];
         const double *row = a.k + sc * a.stride_k;
+        if (a.vec_io & 1) {              // one 16-byte load per loop
 #pragma unroll
-        for (int l = 0; l < NI; ++l) {
-            kx[l] = ami::reduce_2pi(row[2 * l]);
-            ky[l] = ami::reduce_2pi(row[2 * l + 1]);
+            for (int l = 0; l < NI; ++l) {
+                const double2 v = reinterpret_cast<const double2 *>(row)[l];
+                kx[l] = ami::reduce_2pi(v.x);
+                ky[l] = ami::reduce_2pi(v.y);
+            }
+        } else {
+#pragma unroll
+            for (int l = 0; l < NI; ++l) {
+                kx[l] = ami::reduce_2pi(row[2 * l]);
+                ky[l] = ami::reduce_2pi(row[2 * l + 1]);
+            }
         }
         if constexpr (!KEEP) {
             energies_from(a, kx, ky, E);
@@ -281,10 +290,20 @@ __device__ __forceinline__ void adj_tile(const KArgs &a, int64_t blk, double *re
         line_scatter(gx, gy, gkx, gky);
         if (active && a.grad_k) {
             double *row = a.grad_k + s * (2 * NI);
+            if (a.vec_io & 2) {
 #pragma unroll
-            for (int l = 0; l < NI; ++l) {
-                row[2 * l] = gkx[l];
-                row[2 * l + 1] = gky[l];
+                for (int l = 0; l < NI; ++l) {
+                    double2 g2;
+                    g2.x = gkx[l];
+                    g2.y = gky[l];
+                    reinterpret_cast<double2 *>(row)[l] = g2;
+                }
+            } else {
+#pragma unroll
+                for (int l = 0; l < NI; ++l) {
+                    row[2 * l] = gkx[l];
+                    row[2 * l + 1] = gky[l];
+                }
             }
         }
     }

@@ -33,6 +33,9 @@ struct KArgs {
     double *gpartial;           // [grid][kAdjScalars + 2 n_f n_ext]
     // Monte-Carlo integration (momenta drawn in the kernel; n_e samples)
     uint64_t seed;
+    // 16-byte accesses allowed: bit 0 the momentum rows (k 16-byte aligned,
+    // stride_k even), bit 1 the rows of grad_k
+    int vec_io;
 };
 
 // Frequency rows one Monte-Carlo launch accumulates (the caller splits longer lists).

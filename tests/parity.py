@@ -35,7 +35,7 @@ def pole_distance(terms, n_int, E, w, e_reg=0.0):
     dist = np.full((w.shape[0], E.shape[0]), np.inf)
     for _, leaves, dens in terms:
         for sigma, e in leaves:
-            if sigma == -1:
+            if sigma < 0:
                 x = np.abs(E @ np.asarray(e, dtype=np.float64) + e_reg)
                 dist = np.minimum(dist, x[None, :])
         for e, a in dens:
