@@ -49,6 +49,7 @@ typedef enum {
 
 /* amiConstruct flags */
 #define AMI_FACTORIZE 1u    /* also build the factorized Fermi tree (Sec. 2.1, Fig. 1) */
+#define AMI_MULTIPOLE 2u    /* take poles of higher order by Eq. (5) instead of failing */
 
 typedef struct AmiTerms AmiTerms;
 
@@ -63,7 +64,13 @@ typedef struct AmiTerms AmiTerms;
  *   eps       host int8 [n_g][n_eps],  entries in {-1,0,1}
  *   fermionic host uint8 [n_freq]: nonzero = fermionic frequency; NULL = all
  *             fermionic.  Summed slots must be fermionic (Eq. (3)).
- *   flags     0 or AMI_FACTORIZE
+ *   flags     0, AMI_FACTORIZE or AMI_MULTIPOLE (not both).  With AMI_MULTIPOLE a
+ *             pole shared by M denominators is taken by Eq. (5): the Leibniz rule
+ *             over the pole's Fermi/Bose function and the other denominators gives
+ *             terms whose leaves are Taylor coefficients T_j(x) = (1/j!) d^j/dx^j
+ *             f(beta x) (leaf code sigma*(1+j)) and whose denominators carry powers
+ *             (repeated entries); such solutions are evaluated by the specialized
+ *             forward kernels only
  *   out       receives a new handle (owned by the caller, release with amiFree)
  *
  * Host-only: no device memory is touched.  Errors: AMI_E_ARG (sizes/pointers),
@@ -126,10 +133,13 @@ AmiStatus amiTermsLabels(const AmiTerms *terms, int8_t *alpha, int8_t *eps, uint
  *             the factorized form: FT_g * R_g)
  *   8 tree nodes of the factorized Fermi tree (0 unless built with AMI_FACTORIZE)
  *   9 raw terms before canonical merging
- *   10 leaves per term (= n_int)   11 denominators per term (= n_g - n_int)
+ *   10 leaves per term (= n_int)   11 denominators per term (= n_g - n_int;
+ *      the most a term holds when info[15] is 0)
  *   12 packed form available (1/0)   13 the packed kernels build Fermi leaves
  *      from products of exp(beta E_i) (1/0)
- *   14..15 reserved (0)
+ *   14 n_g (propagators of R0)
+ *   15 uniform (1): plain leaves and n_g - n_int denominators in every term;
+ *      0 after poles of higher order (AMI_MULTIPOLE)
  */
 AmiStatus amiTermsInfo(const AmiTerms *terms, int64_t info[16]);
 
@@ -137,6 +147,10 @@ AmiStatus amiTermsInfo(const AmiTerms *terms, int64_t info[16]);
  * amiTermsCanonical -- the canonical flat term list as an int32 stream:
  *   header n_int, n_eps, n_freq, T; then per term: prefactor s; n_int leaves as
  *   (sigma, e[0..n_eps)); (n_g - n_int) denominators as (e[0..n_eps), a[0..n_freq)).
+ *   With poles of higher order (AMI_MULTIPOLE) a leaf's first entry is the code
+ *   sigma*(1+j) of its Taylor coefficient, and when the terms do not all hold the
+ *   same number of denominators the header holds -T and each term's s is
+ *   followed by its number of denominators (repeated entries are powers).
  * sigma = +1 is the Fermi function 1/(exp(y)+1), -1 is 1/(1-exp(y)) (= -n_B).
  * Canonical: each denominator's first non-zero coefficient is positive (its sign
  * moved into s), leaves sorted by (sigma, e), denominators by (e, a), equal
@@ -306,7 +320,9 @@ AmiStatus amiSetVariant(AmiTerms *terms, int32_t variant);
  * input and load them on the current device, so that the compilation stays
  * out of later evaluate calls.  Host-blocking.  AMI_E_UNSUPPORTED when the
  * solution is outside the specialized form, AMI_E_HIP when compiling or loading
- * fails (amiLastError holds the compiler log).
+ * fails (amiLastError holds the compiler log).  A solution with Taylor-
+ * coefficient leaves (AMI_MULTIPOLE) gets its forward kernels only: it has no
+ * adjoint.
  */
 AmiStatus amiTermsSpecialize(AmiTerms *terms, int32_t momentum);
 

@@ -18,6 +18,11 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 _LIB_NAME = "libamigpu.so"
 
 AMI_FACTORIZE = 1
+AMI_MULTIPOLE = 2
+
+
+def _flags(factorize: bool, multipole: bool) -> int:
+    return (AMI_FACTORIZE if factorize else 0) | (AMI_MULTIPOLE if multipole else 0)
 
 _STATUS = {0: "AMI_OK", -1: "AMI_E_ARG", -2: "AMI_E_LABEL", -3: "AMI_E_MULTIPOLE",
            -4: "AMI_E_COEFF", -5: "AMI_E_HIP", -6: "AMI_E_OOM", -7: "AMI_E_UNSUPPORTED"}
@@ -172,7 +177,7 @@ class Terms:
     [nG, nE], ``n_int`` number of sums, ``fermionic`` optional 0/1 [nF].
     """
 
-    def __init__(self, alpha, eps, n_int: int, fermionic=None, factorize: bool = False):
+    def __init__(self, alpha, eps, n_int: int, fermionic=None, factorize: bool = False, multipole: bool = False):
         lib = load_library()
         a = np.ascontiguousarray(np.asarray(alpha, dtype=np.int8))
         e = np.ascontiguousarray(np.asarray(eps, dtype=np.int8))
@@ -185,7 +190,7 @@ class Terms:
         code = lib.amiConstruct(a.shape[0], e.shape[1], a.shape[1], int(n_int),
                                 a.ctypes.data, e.ctypes.data,
                                 None if f is None else f.ctypes.data,
-                                AMI_FACTORIZE if factorize else 0, ctypes.byref(h))
+                                _flags(factorize, multipole), ctypes.byref(h))
         _check(code)
         self._h = h
         self.n_g, self.n_freq = a.shape
@@ -195,14 +200,15 @@ class Terms:
         self.eps = e
 
     @classmethod
-    def from_graph(cls, edges, n_vertices: Optional[int] = None, factorize: bool = False) -> "Terms":
+    def from_graph(cls, edges, n_vertices: Optional[int] = None, factorize: bool = False,
+                   multipole: bool = False) -> "Terms":
         """``amiConstructGraph``: ``edges`` int [n, 4] rows (source, target, B/F, spin)
         of a Feynman graph (Sec. 2.5), labelled and constructed by the library."""
         e = np.ascontiguousarray(np.asarray(edges, dtype=np.int32).reshape(-1, 4))
         nv = int(e[:, :2].max()) + 1 if n_vertices is None else int(n_vertices)
         self = cls.__new__(cls)
         self._h = ctypes.c_void_p()
-        _check(load_library().amiConstructGraph(nv, e.shape[0], e.ctypes.data, AMI_FACTORIZE if factorize else 0,
+        _check(load_library().amiConstructGraph(nv, e.shape[0], e.ctypes.data, _flags(factorize, multipole),
                                                 ctypes.byref(self._h)))
         self.alpha, self.eps, self.fermionic = self.labels()
         self.n_g, self.n_freq = self.alpha.shape
@@ -211,15 +217,15 @@ class Terms:
         return self
 
     @classmethod
-    def from_graph_file(cls, path: str, factorize: bool = False) -> "Terms":
+    def from_graph_file(cls, path: str, factorize: bool = False, multipole: bool = False) -> "Terms":
         """Read a 4-column graph file (``amiReadGraph``) and construct it."""
-        return cls.from_graph(read_graph(path), factorize=factorize)
+        return cls.from_graph(read_graph(path), factorize=factorize, multipole=multipole)
 
     def labels(self):
         """R0 of the handle (``amiTermsLabels``): alpha int8 [n_g, n_freq], eps int8
         [n_g, n_eps], fermionic uint8 [n_freq]."""
         inf = self.info()
-        n_g = inf["leaves_per_term"] + inf["dens_per_term"]
+        n_g = inf["n_g"]
         alpha = np.zeros((n_g, inf["n_freq"]), dtype=np.int8)
         eps = np.zeros((n_g, inf["n_eps"]), dtype=np.int8)
         ferm = np.zeros(inf["n_freq"], dtype=np.uint8)
@@ -227,8 +233,8 @@ class Terms:
         return alpha, eps, ferm
 
     @classmethod
-    def from_diagram(cls, d, factorize: bool = False) -> "Terms":
-        return cls(d.alpha, d.eps, d.n_int, d.fermionic, factorize)
+    def from_diagram(cls, d, factorize: bool = False, multipole: bool = False) -> "Terms":
+        return cls(d.alpha, d.eps, d.n_int, d.fermionic, factorize, multipole)
 
     @property
     def handle(self) -> int:
@@ -238,7 +244,7 @@ class Terms:
         buf = np.zeros(16, dtype=np.int64)
         _check(load_library().amiTermsInfo(self._h, buf.ctypes.data))
         keys = ["T", "n_int", "n_eps", "n_freq", "n_ext", "L", "D", "G", "tree_nodes",
-                "raw_terms", "leaves_per_term", "dens_per_term", "packable", "products"]
+                "raw_terms", "leaves_per_term", "dens_per_term", "packable", "products", "n_g", "uniform"]
         return {k: int(buf[i]) for i, k in enumerate(keys)}
 
     def canonical(self, from_tree: bool = False) -> np.ndarray:

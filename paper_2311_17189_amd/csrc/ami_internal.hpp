@@ -80,7 +80,11 @@ struct Tables {
     std::vector<double> leaf_coef;        // [L][n_eps]
     std::vector<double> leaf_sigma;       // [L]
     std::vector<double> den_coef;         // [D][n_eps + n_ext]
-    std::vector<int32_t> group_dens;      // [G][dpt]
+    std::vector<int32_t> group_dens;      // [G][dpt] (uniform solutions only)
+    std::vector<int32_t> group_den_start; // [G+1] ranges of group_den_list
+    std::vector<int32_t> group_den_list;  // every group's denominator indices (repeats = powers)
+    std::vector<int> leaf_order;          // [L] Taylor order j of each leaf (0: the function)
+    bool uniform = true;                  // plain leaves, n_g - n_int denominators per term
     std::vector<int32_t> group_start;     // [G+1]
     std::vector<double> term_sign;        // [T]
     std::vector<int32_t> term_leaf;       // [T][n_int]

@@ -6,9 +6,11 @@
 // their left-to-right association; every fused multiply-add is written out
 // (the code is compiled without contraction), so the forward and adjoint
 // kernels of a diagram compute the same values bit for bit.
+#include <algorithm>
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
+#include <map>
 #include <sstream>
 #include <string>
 #include <vector>
@@ -57,7 +59,7 @@ bool jit_supported(const AmiTerms *t, bool hub, std::string *why) {
         if (why) *why = m;
         return false;
     };
-    if (tb.L < 1 || tb.G < 1 || tb.D < 1) return no("solution without leaves or denominators");
+    if (tb.L < 1 || tb.G < 1) return no("solution without leaves");
     if (t->n_eps > kMaxEpsDev) return no("more than 16 energies");
     if (t->n_ext > kMaxExt) return no("more than 4 external slots");
     if (hub && t->n_g != t->n_eps) return no("momentum input needs one energy per line");
@@ -95,7 +97,11 @@ int jit_block(const AmiTerms *t, bool hub) { return park_cols(t, hub) * 256 * 8 
 std::string jit_source(const AmiTerms *t, bool hub, int kernels) {
     const Tables &tb = t->tab;
     const int ne = t->n_eps, ni = t->n_int, ng = t->n_g, nx = t->n_ext, nf = t->n_freq;
-    const int L = tb.L, D = tb.D, G = tb.G, dpt = tb.dpt;
+    // a solution whose terms hold no denominators gets one phantom
+    // denominator equal to 1 (no group uses it), so no array is empty
+    const int L = tb.L, D = std::max(tb.D, 1), G = tb.G;
+    auto gbegin = [&](int g) { return tb.group_den_start[g]; };
+    auto gend = [&](int g) { return tb.group_den_start[g + 1]; };
     const int nc = ne + nx;
     std::ostringstream o;
     o << "// generated: specialized AMI evaluator, " << tb.T << " terms, " << L << " leaves, " << D
@@ -176,10 +182,44 @@ std::string jit_source(const AmiTerms *t, bool hub, int kernels) {
     }
     o << "}\n";
 
+    // Taylor-coefficient leaves (poles of higher order): T_j = beta^j f^(j) / j!,
+    // f^(j) as a polynomial in f and fm = f(-y) (f' = -f fm, fm' = f fm)
+    o << "__device__ __forceinline__ void taylor_leaves(double (&F)[L], const double (&FM)[L], double beta) {\n";
+    for (int l = 0; l < L; ++l) {
+        const int jo = tb.leaf_order[l];
+        if (jo == 0) continue;
+        std::map<std::pair<int, int>, long long> poly{{{1, 0}, 1}};
+        for (int step = 0; step < jo; ++step) {
+            std::map<std::pair<int, int>, long long> nxt;
+            for (const auto &kv : poly) {
+                const int a = kv.first.first, b = kv.first.second;
+                if (a) nxt[{a, b + 1}] -= a * kv.second;
+                if (b) nxt[{a + 1, b}] += b * kv.second;
+            }
+            poly.clear();
+            for (const auto &kv : nxt)
+                if (kv.second) poly.insert(kv);
+        }
+        double fact = 1.0;
+        for (int i = 2; i <= jo; ++i) fact *= i;
+        std::string scale = "beta";
+        for (int i = 1; i < jo; ++i) scale += " * beta";
+        o << "  { const double f = F[" << l << "], m = FM[" << l << "]; double acc = 0.0;\n";
+        for (const auto &kv : poly) {
+            std::string mono;
+            for (int i = 0; i < kv.first.first; ++i) mono += (mono.empty() ? "f" : " * f");
+            for (int i = 0; i < kv.first.second; ++i) mono += (mono.empty() ? "m" : " * m");
+            o << "    acc = fma(" << num(static_cast<double>(kv.second)) << ", " << mono << ", acc);\n";
+        }
+        o << "    F[" << l << "] = acc * (" << scale << ") * " << num(1.0 / fact) << "; }\n";
+    }
+    o << "  (void)FM; (void)beta;\n}\n";
+
     // denominators D_k = e_k . E + a_k . w
     o << "__device__ __forceinline__ void den_args(const double (&E)[NE], const double (&wr)[" << NXA
       << "], const double (&wi)[" << NXA << "], double (&dr)[D], double (&di)[D]) {\n";
-    for (int k = 0; k < D; ++k) {
+    if (tb.D == 0) o << "  (void)E; (void)wr; (void)wi;\n  dr[0] = 1.0;\n  di[0] = 0.0;\n";
+    for (int k = 0; k < tb.D; ++k) {
         Lin re, im;
         for (int i = 0; i < ne; ++i) re.add(tb.den_coef[static_cast<size_t>(k) * nc + i], idx("E", i));
         for (int x = 0; x < nx; ++x) {
@@ -196,8 +236,8 @@ std::string jit_source(const AmiTerms *t, bool hub, int kernels) {
          "double (&Ri)[G]) {\n";
     for (int g = 0; g < G; ++g) {
         o << "  { double rr = 1.0, ri = 0.0, nr = 0.0;\n";
-        for (int j = 0; j < dpt; ++j) {
-            const int k = tb.group_dens[static_cast<size_t>(g) * dpt + j];
+        for (int j = 0; j < gend(g) - gbegin(g); ++j) {
+            const int k = tb.group_den_list[gbegin(g) + j];
             if (j == 0) {
                 o << "    rr = xr[" << k << "]; ri = xi[" << k << "];\n";
             } else {
@@ -212,7 +252,7 @@ std::string jit_source(const AmiTerms *t, bool hub, int kernels) {
     // U_k = sum over the occurrences of k in the groups of u_g
     std::vector<std::vector<int>> occ(D);
     for (int g = 0; g < G; ++g)
-        for (int j = 0; j < dpt; ++j) occ[tb.group_dens[static_cast<size_t>(g) * dpt + j]].push_back(g);
+        for (int j = gbegin(g); j < gend(g); ++j) occ[tb.group_den_list[j]].push_back(g);
     o << "__device__ __forceinline__ void den_cotangents(const double (&ur)[G], const double (&ui)[G], double "
          "(&Ur)[D], double (&Ui)[D]) {\n";
     for (int k = 0; k < D; ++k) {
@@ -235,7 +275,8 @@ std::string jit_source(const AmiTerms *t, bool hub, int kernels) {
     o << "__device__ __forceinline__ void den_scatter(const double (&dR)[D], const double (&dI)[D], double (&gE)[NE], "
          "double (&gwr)["
       << NXA << "], double (&gwi)[" << NXA << "]) {\n";
-    for (int k = 0; k < D; ++k) {
+    o << "  (void)dR; (void)dI; (void)gE; (void)gwr; (void)gwi;\n";
+    for (int k = 0; k < tb.D; ++k) {
         for (int i = 0; i < ne; ++i) scatter(o, tb.den_coef[static_cast<size_t>(k) * nc + i], idx("gE", i), idx("dR", k));
         for (int x = 0; x < nx; ++x) {
             const double a = tb.den_coef[static_cast<size_t>(k) * nc + ne + x];
@@ -305,7 +346,10 @@ extern "C" AmiStatus amiTermsSource(const AmiTerms *t, int32_t momentum, char *b
     if (!t || !len) return fail(AMI_E_ARG, "NULL argument");
     std::string why;
     if (!jit_supported(t, momentum != 0, &why)) return fail(AMI_E_UNSUPPORTED, "no specialized kernel: " + why);
-    const std::string src = jit_source(t, momentum != 0, momentum != 0 ? 7 : 3);
+    int kernels = momentum != 0 ? 7 : 3;
+    for (int o : t->tab.leaf_order)
+        if (o > 0) kernels &= ~2;   // Taylor-coefficient leaves: no adjoint
+    const std::string src = jit_source(t, momentum != 0, kernels);
     *len = static_cast<int64_t>(src.size()) + 1;
     if (!buf) return AMI_OK;
     if (cap < *len) return fail(AMI_E_ARG, "buffer too small");

@@ -45,8 +45,8 @@ struct Work {
 
 class Builder {
 public:
-    Builder(int n_eps, int n_freq, const std::vector<uint8_t> &fermionic)
-        : ne_(n_eps), nf_(n_freq), rec_(n_eps + n_freq), ferm_(fermionic) {}
+    Builder(int n_eps, int n_freq, const std::vector<uint8_t> &fermionic, bool multipole = false)
+        : ne_(n_eps), nf_(n_freq), rec_(n_eps + n_freq), ferm_(fermionic), multi_(multipole) {}
 
     int rec() const { return rec_; }
 
@@ -58,6 +58,14 @@ public:
         std::vector<int> dens;
     };
 
+    // Poles of slot p: each distinct pole z0 (the zero of the denominators
+    // D_r = c_r (z - z0), c_r = +-1, that share it; M of them) gives, with
+    // j + sum_q k_q = M - 1 over the other denominators q that hold nu_p
+    // (coefficient a_q, multiplicity m_q after substitution), the residue term
+    //   prod_r c_r * T_j(x0) * prod_q (-a_q)^k_q C(m_q + k_q - 1, k_q) D_q(z0)^-(m_q + k_q)
+    // (Eq. (5) by the Leibniz rule; T_j the j-th Taylor coefficient of the
+    // pole's Fermi/Bose function, leaf code sigma (1 + j)).  M = 1 is Eq. (3)
+    // with Eq. (4).  Without multipole support a shared pole is an error.
     void residues(const std::vector<int> &dens, int p, std::vector<Child> &out) const {
         const int m = static_cast<int>(dens.size()) / rec_;
         std::vector<int> P;
@@ -66,8 +74,8 @@ public:
         if (P.empty())
             throw BuildError{AMI_E_LABEL, "summed frequency " + std::to_string(p) +
                                               " appears in no denominator of a term"};
-        std::vector<std::vector<int>> poles;
-        poles.reserve(P.size());
+        std::vector<std::vector<int>> poles;       // distinct pole records, first-appearance order
+        std::vector<std::vector<int>> members;     // denominators of each pole
         for (int r : P) {
             const int c = dens[r * rec_ + ne_ + p];
             if (c != 1 && c != -1)
@@ -76,36 +84,84 @@ public:
             std::vector<int> z(rec_);
             for (int i = 0; i < rec_; ++i) z[i] = -c * dens[r * rec_ + i];
             z[ne_ + p] = 0;
-            for (const auto &other : poles)
-                if (other == z)
-                    throw BuildError{AMI_E_MULTIPOLE, "two denominators share a pole in frequency " +
-                                                          std::to_string(p)};
-            poles.push_back(std::move(z));
+            size_t k = 0;
+            while (k < poles.size() && poles[k] != z) ++k;
+            if (k < poles.size() && !multi_)
+                throw BuildError{AMI_E_MULTIPOLE, "two denominators share a pole in frequency " +
+                                                      std::to_string(p)};
+            if (k == poles.size()) {
+                poles.push_back(std::move(z));
+                members.emplace_back();
+            }
+            members[k].push_back(r);
         }
-        for (size_t k = 0; k < P.size(); ++k) {
-            const int r = P[k];
-            const int c = dens[r * rec_ + ne_ + p];
+        for (size_t k = 0; k < poles.size(); ++k) {
             const std::vector<int> &z = poles[k];
+            const std::vector<int> &grp = members[k];
+            const int M = static_cast<int>(grp.size());
+            int pref = 1;
+            for (int r : grp) pref *= dens[r * rec_ + ne_ + p];
             int parity = 0;
             for (int l = 0; l < nf_; ++l)
                 if (ferm_[l]) parity += z[ne_ + l];
-            Child ch;
-            ch.c = c;
-            ch.leaf.resize(1 + ne_);
-            ch.leaf[0] = (std::abs(parity) % 2 == 0) ? 1 : -1;
-            for (int i = 0; i < ne_; ++i) ch.leaf[1 + i] = z[i];
-            ch.dens.reserve(dens.size() - rec_);
+            const int sigma = (std::abs(parity) % 2 == 0) ? 1 : -1;
+            // the other denominators at the pole: fixed ones (no nu_p) and
+            // moving ones keyed by (substituted record, nu_p coefficient)
+            std::vector<int> fixed;
+            std::vector<std::pair<std::vector<int>, int>> mkey;   // (record, a_q)
+            std::vector<int> mult;
             for (int q = 0; q < m; ++q) {
-                if (q == r) continue;
+                if (std::find(grp.begin(), grp.end(), q) != grp.end()) continue;
                 const int mq = dens[q * rec_ + ne_ + p];
-                const size_t base = ch.dens.size();
-                ch.dens.insert(ch.dens.end(), dens.begin() + q * rec_, dens.begin() + (q + 1) * rec_);
-                if (mq != 0) {
-                    for (int i = 0; i < rec_; ++i) ch.dens[base + i] += mq * z[i];
-                    ch.dens[base + ne_ + p] = 0;
+                std::vector<int> rec(dens.begin() + q * rec_, dens.begin() + (q + 1) * rec_);
+                if (mq == 0) {
+                    fixed.insert(fixed.end(), rec.begin(), rec.end());
+                    continue;
                 }
+                for (int i = 0; i < rec_; ++i) rec[i] += mq * z[i];
+                rec[ne_ + p] = 0;
+                size_t u = 0;
+                while (u < mkey.size() && !(mkey[u].first == rec && mkey[u].second == mq)) ++u;
+                if (u == mkey.size()) {
+                    mkey.emplace_back(std::move(rec), mq);
+                    mult.push_back(0);
+                }
+                ++mult[u];
             }
-            out.push_back(std::move(ch));
+            // every split j + sum_u k_u = M - 1
+            const int nu = static_cast<int>(mkey.size());
+            std::vector<int> ks(nu, 0);
+            for (;;) {
+                int used = 0;
+                for (int x : ks) used += x;
+                if (used <= M - 1) {
+                    const int j = M - 1 - used;
+                    long long coef = pref;
+                    Child ch;
+                    ch.dens = fixed;
+                    for (int u = 0; u < nu; ++u) {
+                        const int a = mkey[u].second, kk = ks[u], mu = mult[u];
+                        long long binom = 1;
+                        for (int i = 0; i < kk; ++i) binom = binom * (mu + i) / (i + 1);
+                        for (int i = 0; i < kk; ++i) coef *= -a;
+                        coef *= binom;
+                        for (int i = 0; i < mu + kk; ++i)
+                            ch.dens.insert(ch.dens.end(), mkey[u].first.begin(), mkey[u].first.end());
+                    }
+                    if (coef > INT32_MAX || coef < INT32_MIN)
+                        throw BuildError{AMI_E_COEFF, "residue prefactor overflows int32"};
+                    ch.c = static_cast<int>(coef);
+                    ch.leaf.resize(1 + ne_);
+                    ch.leaf[0] = sigma * (1 + j);
+                    for (int i = 0; i < ne_; ++i) ch.leaf[1 + i] = z[i];
+                    out.push_back(std::move(ch));
+                }
+                // next tuple of ks (odometer over 0..M-1)
+                int u = 0;
+                while (u < nu && ks[u] == M - 1) ks[u++] = 0;
+                if (u == nu) break;
+                ++ks[u];
+            }
         }
     }
 
@@ -145,6 +201,7 @@ public:
 private:
     int ne_, nf_, rec_;
     std::vector<uint8_t> ferm_;
+    bool multi_;
 };
 
 std::vector<int> initial_dens(const AmiTerms *t) {
@@ -195,7 +252,7 @@ void check_ranges(const std::vector<FlatTerm> &terms) {
 }
 
 void construct_flat(AmiTerms *t) {
-    Builder b(t->n_eps, t->n_freq, t->fermionic);
+    Builder b(t->n_eps, t->n_freq, t->fermionic, (t->flags & AMI_MULTIPOLE) != 0);
     std::vector<Work> cur(1);
     cur[0].s = 1;
     cur[0].dens = initial_dens(t);
@@ -374,12 +431,16 @@ std::vector<FlatTerm> expand_tree(const AmiTerms *t) {
 
 void serialize(const AmiTerms *t, const std::vector<FlatTerm> &terms, std::vector<int32_t> &out) {
     out.clear();
+    const size_t drec = static_cast<size_t>(t->n_eps + t->n_freq);
+    bool extended = false;
+    for (const auto &ft : terms) extended = extended || ft.dens.size() != terms[0].dens.size();
     out.push_back(t->n_int);
     out.push_back(t->n_eps);
     out.push_back(t->n_freq);
-    out.push_back(static_cast<int32_t>(terms.size()));
+    out.push_back(extended ? -static_cast<int32_t>(terms.size()) : static_cast<int32_t>(terms.size()));
     for (const auto &ft : terms) {
         out.push_back(ft.s);
+        if (extended) out.push_back(static_cast<int32_t>(ft.dens.size() / drec));
         out.insert(out.end(), ft.leaves.begin(), ft.leaves.end());
         out.insert(out.end(), ft.dens.begin(), ft.dens.end());
     }
@@ -397,11 +458,19 @@ AmiStatus build_tables(AmiTerms *t) {
     const int ne = t->n_eps, nf = t->n_freq, ni = t->n_int, nx = t->n_ext;
     const int lrec = 1 + ne, drec = ne + nf;
     tab.dpt = t->n_g - ni;
+    // uniform: every term holds n_g - n_int denominators and plain leaves (no
+    // pole of higher order); the table-driven kernels need it
+    tab.uniform = true;
     std::map<std::vector<int>, int> leaf_id, den_id;
     for (const auto &ft : t->terms) {
-        for (int j = 0; j < ni; ++j)
+        const int nd = static_cast<int>(ft.dens.size()) / drec;
+        if (nd != tab.dpt) tab.uniform = false;
+        for (int j = 0; j < ni; ++j) {
+            const int code = ft.leaves[j * lrec];
+            if (code != 1 && code != -1) tab.uniform = false;
             leaf_id.emplace(std::vector<int>(ft.leaves.begin() + j * lrec, ft.leaves.begin() + (j + 1) * lrec), 0);
-        for (int r = 0; r < tab.dpt; ++r) {
+        }
+        for (int r = 0; r < nd; ++r) {
             std::vector<int> k(ft.dens.begin() + r * drec, ft.dens.begin() + r * drec + ne);
             k.insert(k.end(), ft.dens.begin() + r * drec + ne + ni, ft.dens.begin() + (r + 1) * drec);
             den_id.emplace(std::move(k), 0);
@@ -410,7 +479,8 @@ AmiStatus build_tables(AmiTerms *t) {
     int idx = 0;
     for (auto &kv : leaf_id) {
         kv.second = idx++;
-        tab.leaf_sigma.push_back(static_cast<double>(kv.first[0]));
+        tab.leaf_sigma.push_back(kv.first[0] > 0 ? 1.0 : -1.0);
+        tab.leaf_order.push_back(std::abs(kv.first[0]) - 1);
         for (int i = 0; i < ne; ++i) tab.leaf_coef.push_back(static_cast<double>(kv.first[1 + i]));
     }
     tab.L = idx;
@@ -427,7 +497,8 @@ AmiStatus build_tables(AmiTerms *t) {
     for (size_t ti = 0; ti < t->terms.size(); ++ti) {
         const auto &ft = t->terms[ti];
         std::vector<int> ds;
-        for (int r = 0; r < tab.dpt; ++r) {
+        const int nd = static_cast<int>(ft.dens.size()) / drec;
+        for (int r = 0; r < nd; ++r) {
             std::vector<int> k(ft.dens.begin() + r * drec, ft.dens.begin() + r * drec + ne);
             k.insert(k.end(), ft.dens.begin() + r * drec + ne + ni, ft.dens.begin() + (r + 1) * drec);
             ds.push_back(den_id.at(k));
@@ -447,8 +518,12 @@ AmiStatus build_tables(AmiTerms *t) {
     }
     tab.G = static_cast<int>(gdens.size());
     tab.group_start.push_back(0);
+    tab.group_den_start.push_back(0);
     for (int g = 0; g < tab.G; ++g) {
-        for (int d : gdens[g]) tab.group_dens.push_back(d);
+        for (int d : gdens[g]) tab.group_den_list.push_back(d);
+        tab.group_den_start.push_back(static_cast<int32_t>(tab.group_den_list.size()));
+        if (tab.uniform)
+            for (int d : gdens[g]) tab.group_dens.push_back(d);
         for (int ti : gterms[g]) {
             const auto &ft = t->terms[ti];
             tab.term_sign.push_back(static_cast<double>(ft.s));
@@ -481,6 +556,7 @@ void pack_tables(AmiTerms *t) {
     tab.p_group.clear();
     tab.fermi_used = 0;
     tab.use_products = false;
+    if (!tab.uniform) return;
     if (ne > 16 || nf > 16 || ni > 8 || tab.dpt > 8 || nx > 4 || tab.L > 255 || tab.D > 255) return;
     auto masks = [&](const double *c, int n, uint64_t &out) -> bool {
         uint32_t pos = 0, neg = 0;
@@ -558,7 +634,9 @@ AmiStatus amiConstruct(int32_t n_g, int32_t n_eps, int32_t n_freq, int32_t n_int
     if (n_eps < 1 || n_eps > kMaxEps) return fail(AMI_E_ARG, "n_eps must be in 1..32");
     if (n_freq < 1 || n_freq > kMaxFreq) return fail(AMI_E_ARG, "n_freq must be in 1..16");
     if (n_int < 0 || n_int > n_freq) return fail(AMI_E_ARG, "n_int must be in 0..n_freq");
-    if (flags & ~AMI_FACTORIZE) return fail(AMI_E_ARG, "unknown flag");
+    if (flags & ~(AMI_FACTORIZE | AMI_MULTIPOLE)) return fail(AMI_E_ARG, "unknown flag");
+    if ((flags & AMI_FACTORIZE) && (flags & AMI_MULTIPOLE))
+        return fail(AMI_E_UNSUPPORTED, "the factorized tree is built for simple poles only");
     AmiTerms *t = new (std::nothrow) AmiTerms();
     if (!t) return fail(AMI_E_OOM, "out of host memory");
     t->n_g = n_g;
@@ -612,6 +690,8 @@ AmiStatus amiTermsInfo(const AmiTerms *t, int64_t info[16]) {
     info[11] = t->n_g - t->n_int;
     info[12] = t->tab.packable ? 1 : 0;
     info[13] = t->tab.use_products ? 1 : 0;
+    info[14] = t->n_g;
+    info[15] = t->tab.uniform ? 1 : 0;
     return AMI_OK;
 }
 

@@ -352,6 +352,8 @@ AmiStatus choose_path(AmiTerms *t, bool hub, bool adjoint, Path &p, void **jit_f
         note = std::string(" (not specialized: ") + amiLastError() + ")";
         clear_error();
     }
+    if (!t->tab.uniform)
+        return fail(AMI_E_UNSUPPORTED, "poles of higher order are evaluated by the specialized kernels only" + note);
     if (v == AMI_VARIANT_TABLES) {
         if (adjoint) return fail(AMI_E_UNSUPPORTED, "the double-table variant has no adjoint");
         p = Path::TABLES;
@@ -758,6 +760,8 @@ AmiStatus amiTermsSpecialize(AmiTerms *t, int32_t momentum) {
     void *fn = nullptr;
     const AmiStatus st = ami::jit_get(t, momentum != 0, ami::kJitForward, &fn);
     if (st != AMI_OK) return st;
+    for (int o : t->tab.leaf_order)
+        if (o > 0) return AMI_OK;   // Taylor-coefficient leaves: forward only
     return ami::jit_get(t, momentum != 0, ami::kJitAdjoint, &fn);
 }
 

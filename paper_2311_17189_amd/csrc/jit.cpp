@@ -150,6 +150,12 @@ AmiStatus code_object(AmiTerms *t, bool hub, int kind) {
         err = "no specialized kernel: " + why;
         return fail(AMI_E_UNSUPPORTED, err);
     }
+    if (kind == kJitAdjoint)
+        for (int o : t->tab.leaf_order)
+            if (o > 0) {
+                err = "no specialized adjoint for Taylor-coefficient leaves (poles of higher order)";
+                return fail(AMI_E_UNSUPPORTED, err);
+            }
     const std::string src = jit_source(t, hub, 1 << kind);
     const std::string dir = cache_dir();
     const std::string base = dir.empty() ? std::string() : dir + "/" + cache_key(src);

@@ -8,6 +8,7 @@
 // the leaf kinds kBose[L], and the functions
 //   lines            K_j = sum_l alpha_jl k_l (+ external q), per component
 //   leaf_args        x_l = sum_i c_li E_i                        (Sec. 2.2)
+//   taylor_leaves    f_l -> its Taylor coefficient T_j (poles of higher order, Eq. (5))
 //   group_sums       FT_g = sum_{t in g} s_t prod_{l in t} f_l     (Sec. 2.3)
 //   den_args         D_k = e_k . E + a_k . w                        (Sec. 2.2)
 //   group_products   R_g = prod_{k in g} 1/D_k
@@ -131,14 +132,14 @@ __device__ __forceinline__ void fwd_tile(const KArgs &a, int64_t tile, double *r
 
     double E[NE];
     energies<HUB, false>(a, sc, E, nullptr);
-    double x[L], F[L];
+    double x[L], F[L], FM[L];
     leaf_args(E, x);
 #pragma unroll
     for (int l = 0; l < L; ++l) {
-        double fm;
-        if (kBose[l]) ami::leaf_pair(true, a.beta * (x[l] + a.e_reg), F[l], fm);
-        else ami::leaf_pair(false, a.beta * x[l], F[l], fm);
+        if (kBose[l]) ami::leaf_pair(true, a.beta * (x[l] + a.e_reg), F[l], FM[l]);
+        else ami::leaf_pair(false, a.beta * x[l], F[l], FM[l]);
     }
+    taylor_leaves(F, FM, a.beta);
     double FT[G];
     group_sums(F, FT);
 
@@ -348,15 +349,15 @@ __device__ __forceinline__ void mc_block(const KArgs &a, double *red) {
                 }
             }
         }
-        double E[NE], x[L], F[L], FT[G];
+        double E[NE], x[L], F[L], FM[L], FT[G];
         energies_from(a, kx, ky, E);
         leaf_args(E, x);
 #pragma unroll
         for (int l = 0; l < L; ++l) {
-            double fm;
-            if (kBose[l]) ami::leaf_pair(true, a.beta * (x[l] + a.e_reg), F[l], fm);
-            else ami::leaf_pair(false, a.beta * x[l], F[l], fm);
+            if (kBose[l]) ami::leaf_pair(true, a.beta * (x[l] + a.e_reg), F[l], FM[l]);
+            else ami::leaf_pair(false, a.beta * x[l], F[l], FM[l]);
         }
+        taylor_leaves(F, FM, a.beta);
         group_sums(F, FT);
 #pragma unroll
         for (int f = 0; f < ami::kMcMaxFreqs; ++f) {

@@ -1,7 +1,7 @@
 // Host check of the generated part of the specialized evaluator: the
 // diagram's straight-line functions (leaf_args, group_sums, den_args,
 // group_products, den_cotangents, den_scatter, leaf_cotangents, leaf_scatter,
-// lines, line_scatter) compiled with a host compiler and driven one sample at
+// lines, line_scatter, taylor_leaves) compiled with a host compiler and driven one sample at
 // a time through the same steps as the device kernels, so a test can compare
 // values and gradients with the oracle.  The generated source is included
 // through AMI_GENERATED without its two #include lines.
@@ -64,14 +64,14 @@ int main() {
         for (int f = 0; f < n_f; ++f)
             if (std::scanf("%lf %lf", &cre[f], &cim[f]) != 2) return 2;
 
-        double x[L], F[L], Dv[L];
+        double x[L], F[L], FM[L], Dv[L];
         leaf_args(E, x);
         for (int l = 0; l < L; ++l) {
             if (kBose[l]) x[l] += e_reg;
-            double fm;
-            ami::leaf_pair(kBose[l], beta * x[l], F[l], fm);
-            Dv[l] = -(F[l] * fm);
+            ami::leaf_pair(kBose[l], beta * x[l], F[l], FM[l]);
+            Dv[l] = -(F[l] * FM[l]);
         }
+        taylor_leaves(F, FM, beta);   // Taylor-coefficient leaves: values only
         double FT[G], FTB[G] = {0.0}, gE[NE] = {0.0};
         group_sums(F, FT);
         std::vector<double> gw(2 * static_cast<size_t>(n_f) * NXA, 0.0);

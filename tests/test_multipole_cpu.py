@@ -1,0 +1,105 @@
+"""Poles of higher order (Eq. (5)) in the library, on the CPU: the construction
+with AMI_MULTIPOLE against the oracle's term stream, bit for bit (including the
+extended stream of terms with unequal denominator counts), the error paths,
+and the generated straight-line functions (Taylor-coefficient leaves, groups
+with unequal denominator lists) compiled on the host and compared with the
+oracle's values."""
+import numpy as np
+import pytest
+
+from ami_inputs import matsubara_freqs, random_self_energy, real_freqs, uniform_energies
+from oracle.construct import canonical, construct, serialize
+from oracle.evaluate import evaluate_terms, term_magnitudes
+
+from parity import check, far_from_poles, pole_distance
+
+amd = pytest.importorskip("paper_2311_17189_amd")
+
+from test_specialized_cpu import _harness, _run  # noqa: E402
+
+# a double pole present from the start: (1/beta) sum_nu 1/((i nu + E1)^2 (i nu + i Omega + E2))
+DOUBLE = (np.array([[1, 0], [1, 0], [1, 1]]), np.array([[1, 0], [1, 0], [0, 1]]), 1, [1, 0])
+# a double pole that appears only after the first sum
+LATER = (np.array([[1, 0, 0], [0, 1, 1], [-1, 1, 1]]), np.array([[1, 0], [0, 1], [-1, 1]]), 2, [1, 1, 0])
+
+
+def repeated_line(order, i, line=0):
+    """A generated self-energy with one internal line taken twice (same label,
+    same energy): the diagram with a constant self-energy inserted on it,
+    whose propagator squared gives poles of second order."""
+    d = random_self_energy(order, (0, order, i))
+    j = [r for r in range(d.alpha.shape[0]) if np.any(d.alpha[r, :d.n_int])][line]
+    return (np.vstack([d.alpha, d.alpha[j:j + 1]]), np.vstack([d.eps, d.eps[j:j + 1]]), d.n_int,
+            list(d.fermionic))
+
+
+CASES = {"double": DOUBLE, "later": LATER, "o3": repeated_line(3, 0), "o4": repeated_line(4, 1),
+         "o4b": repeated_line(4, 3, 1)}
+
+
+def _oracle(case):
+    alpha, eps, n_int, ferm = case
+    return canonical(construct(alpha, eps, n_int, ferm, multipole=True))
+
+
+@pytest.mark.parametrize("name", list(CASES))
+def test_multipole_stream_matches_oracle(name):
+    alpha, eps, n_int, ferm = CASES[name]
+    T = amd.Terms(alpha, eps, n_int, ferm, multipole=True)
+    terms = _oracle(CASES[name])
+    want = np.array(serialize(terms, n_int, eps.shape[1], alpha.shape[1]), dtype=np.int32)
+    got = T.canonical()
+    assert np.array_equal(got, want)
+    inf = T.info()
+    assert inf["T"] == len(terms) and inf["n_g"] == alpha.shape[0]
+    assert inf["uniform"] == 0 and inf["packable"] == 0
+    assert any(abs(c) > 1 for _, lv, _ in terms for c, _ in lv)
+    a2, e2, f2 = T.labels()
+    assert np.array_equal(a2, alpha) and np.array_equal(e2, eps) and list(f2) == list(ferm)
+
+
+def test_multipole_errors_and_simple_poles_unchanged():
+    alpha, eps, n_int, ferm = DOUBLE
+    with pytest.raises(amd.AmiError) as e:
+        amd.Terms(alpha, eps, n_int, ferm)
+    assert e.value.code == -3
+    with pytest.raises(amd.AmiError) as e:
+        amd.Terms(alpha, eps, n_int, ferm, factorize=True, multipole=True)
+    assert e.value.code == -7
+    for order, i in ((2, 0), (3, 1), (4, 1)):
+        d = random_self_energy(order, (0, order, i))
+        a = amd.Terms.from_diagram(d)
+        b = amd.Terms.from_diagram(d, multipole=True)
+        assert np.array_equal(a.canonical(), b.canonical())
+        assert b.info()["uniform"] == 1
+
+
+@pytest.mark.parametrize("name", list(CASES))
+def test_generated_multipole_values_match_oracle(name, tmp_path):
+    alpha, eps, n_int, ferm = CASES[name]
+    T = amd.Terms(alpha, eps, n_int, ferm, multipole=True)
+    exe = _harness(T.source(momentum=False), tmp_path, name)
+    beta = 4.0
+    n_eps = eps.shape[1]
+    E = uniform_energies(200, n_eps, seed=(44, n_int, alpha.shape[0]), a=3.0)
+    w = np.concatenate([matsubara_freqs(2, beta), real_freqs(1, 0.6, 0.6, 0.05)])
+    if not ferm[-1]:
+        w = np.concatenate([2j * np.pi * np.arange(1, 3) / beta, real_freqs(1, 0.6, 0.6, 0.05)])
+    terms = _oracle(CASES[name])
+    E = np.ascontiguousarray(E[far_from_poles(terms, n_int, E, w)])
+    cot = np.zeros((len(w), len(E)), dtype=np.complex128)
+    vals = _run(exe, n_eps, len(w), beta, 0.0, 1.0, 0.0, np.zeros(2), w[:, None], E, cot)[0]
+    ref = evaluate_terms(terms, n_int, E, w, beta).astype(np.complex128)
+    scale = term_magnitudes(terms, n_int, E, w, beta).astype(np.float64)
+    check(vals, ref, scale, pole_distance(terms, n_int, E, w), label=f"{name} multipole values")
+
+
+def test_multipole_adjoint_is_refused():
+    T = amd.Terms(*DOUBLE, multipole=True)
+    src = T.source(momentum=False)
+    assert "taylor_leaves" in src
+    with pytest.raises(amd.AmiError) as e:
+        T.specialize(momentum=False)
+    # compilation of the forward kernel may succeed; the adjoint is refused
+    # before any device query
+    assert e.value.code in (-7, -5)
