@@ -13,5 +13,5 @@ exactly the same arrays from here, so the two can be compared bit for bit.
 """
 from .diagrams import (Diagram, order2_example, random_self_energy,  # noqa: F401
                        diagram_set, relabel)
-from .samples import (k_samples, uniform_energies, matsubara_freqs,  # noqa: F401
-                      real_freqs, DEFAULT_Q)
+from .samples import (k_samples, uniform_energies, complex_energies,  # noqa: F401
+                      matsubara_freqs, real_freqs, DEFAULT_Q)

@@ -31,6 +31,14 @@ def uniform_energies(n_e: int, n_eps: int, seed, a: float = 8.0) -> np.ndarray:
     return 2.0 * a * rng.random((n_e, n_eps)) - a
 
 
+def complex_energies(n_e: int, n_eps: int, seed, a: float = 3.0, eta: float = 0.1) -> np.ndarray:
+    """complex128 [n_e, n_eps]: real parts uniform on (-a, a), imaginary parts
+    uniform on (-eta, eta) (energies with a broadening; the energy vector's
+    element type is complex, Sec. 5.1.3)."""
+    rng = np.random.default_rng(seed)
+    return rng.uniform(-a, a, (n_e, n_eps)) + 1j * rng.uniform(-eta, eta, (n_e, n_eps))
+
+
 def matsubara_freqs(n_f: int, beta: float, first: int = 0) -> np.ndarray:
     """complex128 [n_f]: i*(2j+1)*pi/beta for j = first .. first+n_f-1."""
     j = np.arange(first, first + n_f, dtype=np.float64)

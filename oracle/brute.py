@@ -1,7 +1,8 @@
 """Oracle: the plain definition Eq. (1) by truncated Matsubara sums.
 
 ``I = beta^-n sum_{nu_1..nu_n} prod_j 1/(sum_l alpha_jl w_l + sum_i eps_ji E_i)``
-with ``w_l = i nu_l`` for the summed slots (Sec. 2.2, Eqs. (1)-(2)).  Nothing
+with ``w_l = i nu_l`` for the summed slots (Sec. 2.2, Eqs. (1)-(2)); the
+energies may be complex.  Nothing
 of the residue construction is used: the sums are done term by term over
 ``nu_m = (2m+1) pi / beta``, ``m = -M .. M-1`` (a range symmetric in ``nu``),
 and the truncation error is removed by Richardson extrapolation in ``1/M``
@@ -41,7 +42,8 @@ def _denominators(alpha, eps, E, w_ext, n_int):
     coefficients alpha_j[:n_int]."""
     alpha = np.asarray(alpha, dtype=np.int64)
     eps = np.asarray(eps, dtype=np.int64)
-    E = np.asarray(E, dtype=np.float64)
+    E = np.asarray(E)
+    E = E.astype(np.complex128 if np.iscomplexobj(E) else np.float64)
     w_ext = np.atleast_1d(np.asarray(w_ext, dtype=np.complex128))
     c = eps @ E + alpha[:, n_int:] @ w_ext
     return alpha[:, :n_int].astype(np.float64), c

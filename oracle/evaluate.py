@@ -18,7 +18,9 @@ vectorized over samples.
 
 Readings: a leaf ``(sigma, e)`` is ``f_sigma(y) = 1/(sigma*exp(y) + 1)`` at
 ``y = beta*(e . E)``; the regulator ``e_reg`` is added to ``e . E`` of
-``sigma = -1`` (Bose-type) leaves only.  A leaf code ``sigma (1 + j)`` with
+``sigma = -1`` (Bose-type) leaves only.  Energies may be complex (Sec. 5.1.3: the
+energy vector's element type is complex): the leaves and denominators are
+then the analytic continuations of the same expressions.  A leaf code ``sigma (1 + j)`` with
 ``j > 0`` (from a pole of higher order) is the j-th Taylor coefficient of that
 function in ``x = e . E`` (:func:`leaf_coefficient`).  A denominator ``(e, a)`` is
 ``e . E + a_ext . w`` -- internal frequency slots are zero after construction
@@ -36,11 +38,23 @@ CLD = np.clongdouble
 
 def leaf_value(sigma: int, y):
     """``f_sigma(y) = 1/(sigma e^y + 1)``; the Bose-type form is written
-    ``-1/expm1(y)`` so it keeps full relative precision near ``y = 0``."""
-    with np.errstate(over="ignore", divide="ignore"):
+    ``-1/expm1(y)`` so it keeps full relative precision near ``y = 0``.
+
+    Complex ``y`` (complex energies): with ``u = e^{-y}`` where ``Re y > 0``
+    the same function is ``u/(1 + u)`` (Fermi) and ``u/expm1(-y)`` (Bose-type),
+    which cannot overflow; elsewhere the forms above are used as they are."""
+    with np.errstate(over="ignore", divide="ignore", invalid="ignore"):
+        if not np.iscomplexobj(y):
+            if sigma == 1:
+                return 1 / (np.exp(y) + 1)
+            return -1 / np.expm1(y)
+        pos = np.real(y) > 0
+        z = np.where(pos, -y, y)          # Re z <= 0: e^z cannot overflow
         if sigma == 1:
-            return 1 / (np.exp(y) + 1)
-        return -1 / np.expm1(y)
+            u = np.exp(z)
+            return np.where(pos, u / (1 + u), 1 / (u + 1))
+        m = np.expm1(z)
+        return np.where(pos, np.exp(z) / m, -1 / m)
 
 
 def _derivative_monomials(j: int):
@@ -88,11 +102,14 @@ def evaluate_terms(terms, n_int: int, energies, ext_freqs, beta, e_reg=0.0,
                    dtype=LD):
     """Sum of flat terms at every (frequency row, energy row).
 
-    ``energies`` real [N_E, nE]; ``ext_freqs`` complex [N_F, n_ext] (or [N_F]
-    for one external slot).  Returns complex [N_F, N_E].
+    ``energies`` real or complex [N_E, nE]; ``ext_freqs`` complex [N_F, n_ext]
+    (or [N_F] for one external slot).  Returns complex [N_F, N_E].  Complex
+    energies enter the leaves and the denominators alike: every expression
+    is the same analytic function of them.
     """
     cdt = CLD if dtype is LD else np.complex128
-    E = np.asarray(energies).astype(dtype)
+    E = np.asarray(energies)
+    E = E.astype(cdt if np.iscomplexobj(E) else dtype)
     w = np.asarray(ext_freqs)
     if w.ndim == 1:
         w = w[:, None]
@@ -103,7 +120,7 @@ def evaluate_terms(terms, n_int: int, energies, ext_freqs, beta, e_reg=0.0,
     n_f = w.shape[0]
     out = np.zeros((n_f, n_e), dtype=cdt)
     for s, leaves, dens in terms:
-        ft = np.full(n_e, dtype(s), dtype=dtype)
+        ft = np.full(n_e, dtype(s), dtype=E.dtype)
         for code, e in leaves:
             x = E @ np.asarray(e, dtype=dtype)
             if code < 0:
@@ -125,7 +142,8 @@ def evaluate_terms(terms, n_int: int, energies, ext_freqs, beta, e_reg=0.0,
 def term_magnitudes(terms, n_int: int, energies, ext_freqs, beta, e_reg=0.0):
     """``sum_t |v_t|`` at every point: the natural scale of the rounding error
     of the sum over terms, used as the denominator of relative errors."""
-    E = np.asarray(energies).astype(LD)
+    E = np.asarray(energies)
+    E = E.astype(CLD if np.iscomplexobj(E) else LD)
     w = np.asarray(ext_freqs)
     if w.ndim == 1:
         w = w[:, None]
@@ -244,6 +262,7 @@ def gradients(terms, n_int: int, energies, ext_freqs, beta, cot, e_reg=0.0,
     with ``per_sample`` the last two are not summed: ``dbeta [N_E]``,
     ``dw [N_F, N_E, n_ext]``.
     """
+    assert not np.iscomplexobj(energies), "gradients are taken at real energies"
     E = np.asarray(energies).astype(LD)
     w = np.asarray(ext_freqs)
     if w.ndim == 1:

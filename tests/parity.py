@@ -28,7 +28,8 @@ def oracle_terms(d):
 def pole_distance(terms, n_int, E, w, e_reg=0.0):
     """min over Bose-type leaves of |e.E (+e_reg)| and over denominators of
     |D|, per (frequency, sample)."""
-    E = np.asarray(E, dtype=np.float64)
+    E = np.asarray(E)
+    E = E.astype(np.complex128 if np.iscomplexobj(E) else np.float64)
     w = np.asarray(w)
     if w.ndim == 1:
         w = w[:, None]
@@ -36,7 +37,7 @@ def pole_distance(terms, n_int, E, w, e_reg=0.0):
     for _, leaves, dens in terms:
         for sigma, e in leaves:
             if sigma < 0:
-                x = np.abs(E @ np.asarray(e, dtype=np.float64) + e_reg)
+                x = np.abs(E @ np.asarray(e, dtype=np.float64) + e_reg)   # |x| at complex E too
                 dist = np.minimum(dist, x[None, :])
         for e, a in dens:
             base = E @ np.asarray(e, dtype=np.float64)
