@@ -217,6 +217,30 @@ AmiStatus amiEvaluateHubbard(AmiTerms *terms,
                              double *out, double *out_sum, void *hip_stream);
 
 /*
+ * amiEvaluateComplex -- amiEvaluate at complex energies (the energy vector's
+ * element type is complex, Sec. 5.1.3; e.g. energies with a broadening):
+ *
+ *   energies  device complex128 [n_e][n_eps] as interleaved (re, im) doubles;
+ *             element (s, i) at energies[2*(s*stride_s + i*stride_i)], the
+ *             strides counted in complex elements (>= 1)
+ *
+ * Every other argument, the output layout and the ownership are those of
+ * amiEvaluate.  The leaves f(beta x) and the denominators are taken at the
+ * complex x = e . E (the analytic continuation of the real-energy result);
+ * the regulator e_reg shifts the real part of Bose-type leaf arguments.
+ * Leaves are accurate for |beta Im x| < 6e6; a Fermi leaf has poles at
+ * beta x = i pi (2n+1), which the caller keeps away from.  Served by the
+ * specialized kernels only (compiled on first use, as AMI_VARIANT_SPECIALIZED):
+ * AMI_E_UNSUPPORTED for solutions outside their form and for poles of higher
+ * order (AMI_MULTIPOLE).  No adjoint.
+ */
+AmiStatus amiEvaluateComplex(AmiTerms *terms,
+                             const double *energies, int64_t n_e, int64_t stride_s, int64_t stride_i,
+                             const double *ext_freqs, int64_t n_f,
+                             double beta, double e_reg,
+                             double *out, double *out_sum, void *hip_stream);
+
+/*
  * amiEvaluateAdjoint -- reverse-mode derivatives of the batched evaluation.
  * For the real objective L = Re sum_{f,s} conj(c[f][s]) out[f][s] with the
  * cotangent c[f][s] = grad_out[f][s] + grad_sum[f] (either may be NULL, not

@@ -12,9 +12,9 @@ otherwise (there is no fallback path).
 """
 from ._lib import (VARIANT_AUTO, VARIANT_PACKED, VARIANT_SPECIALIZED,  # noqa: F401
                    VARIANT_TABLES, AmiError, Batch, Terms, evaluate, evaluate_adjoint,
-                   evaluate_hubbard, evaluate_hubbard_adjoint, integrate_hubbard, kernel_timer_start,
+                   evaluate_complex, evaluate_hubbard, evaluate_hubbard_adjoint, integrate_hubbard, kernel_timer_start,
                    kernel_timer_stop, last_variant, lib_path, load_library, mc_estimate, read_graph, version)
 
-__all__ = ["VARIANT_AUTO", "VARIANT_PACKED", "VARIANT_SPECIALIZED", "VARIANT_TABLES", "AmiError", "Batch", "Terms", "evaluate", "evaluate_adjoint", "evaluate_hubbard",
+__all__ = ["VARIANT_AUTO", "VARIANT_PACKED", "VARIANT_SPECIALIZED", "VARIANT_TABLES", "AmiError", "Batch", "Terms", "evaluate", "evaluate_adjoint", "evaluate_complex", "evaluate_hubbard",
            "evaluate_hubbard_adjoint", "integrate_hubbard", "mc_estimate", "read_graph", "kernel_timer_start", "kernel_timer_stop", "last_variant", "lib_path", "load_library",
            "version"]

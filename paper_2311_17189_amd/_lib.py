@@ -84,6 +84,8 @@ def load_library():
     lib.amiTermsUpload.restype = c_i32
     lib.amiEvaluate.argtypes = [vp, vp, c_i64, c_i64, c_i64, vp, c_i64, c_dbl, c_dbl, vp, vp, vp]
     lib.amiEvaluate.restype = c_i32
+    lib.amiEvaluateComplex.argtypes = [vp, vp, c_i64, c_i64, c_i64, vp, c_i64, c_dbl, c_dbl, vp, vp, vp]
+    lib.amiEvaluateComplex.restype = c_i32
     lib.amiEvaluateHubbard.argtypes = [vp, vp, c_i64, c_i64, vp, c_dbl, c_dbl, vp, c_i64, c_dbl,
                                        c_dbl, vp, vp, vp]
     lib.amiEvaluateHubbard.restype = c_i32
@@ -347,6 +349,27 @@ def evaluate(terms: Terms, energies, ext_freqs, beta: float, e_reg: float = 0.0,
         out_sum.data_ptr() if out_sum is not None else None,
         _stream_ptr(stream))
     _check(code)
+    return out, out_sum
+
+
+def evaluate_complex(terms: Terms, energies, ext_freqs, beta: float, e_reg: float = 0.0,
+                     want_out: bool = True, want_sum: bool = False, out=None, out_sum=None, stream=None):
+    """``amiEvaluateComplex``: ``energies`` complex128 CUDA [N_E, nE] (any strides);
+    returns ``(out [N_F, N_E] or None, out_sum [N_F] or None)``."""
+    import torch
+    if energies.dtype != torch.complex128 or not energies.is_cuda or energies.dim() != 2:
+        raise AmiError(-1, "energies must be a complex128 CUDA tensor [N_E, nE]")
+    if energies.shape[1] != terms.n_eps:
+        raise AmiError(-1, f"energies has {energies.shape[1]} columns, terms expect {terms.n_eps}")
+    w = _freqs(ext_freqs, terms)
+    n_e, n_f = energies.shape[0], w.shape[0]
+    out, out_sum = _outputs(n_f, n_e, energies.device, want_out, want_sum, out, out_sum)
+    st_s, st_i = energies.stride()
+    _check(load_library().amiEvaluateComplex(
+        terms._h, energies.data_ptr() if n_e else None, n_e, max(st_s, 1), max(st_i, 1),
+        w.data_ptr(), n_f, float(beta), float(e_reg),
+        out.data_ptr() if out is not None else None,
+        out_sum.data_ptr() if out_sum is not None else None, _stream_ptr(stream)))
     return out, out_sum
 
 

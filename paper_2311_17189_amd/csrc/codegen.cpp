@@ -182,6 +182,36 @@ std::string jit_source(const AmiTerms *t, bool hub, int kernels) {
     }
     o << "}\n";
 
+    // complex group sums (complex energies): the same products of a term's
+    // leaves left to right, in complex arithmetic, accumulated with s_t
+    if (kernels & 8) {
+        o << "__device__ __forceinline__ void group_sums_c(const double (&Fr)[L], const double (&Fi)[L], double "
+             "(&FTr)[G], double (&FTi)[G]) {\n";
+        for (int g = 0; g < G; ++g) {
+            o << "  { double ar = 0.0, ai = 0.0, pr, pi, nr;\n";
+            for (int ti = tb.group_start[g]; ti < tb.group_start[g + 1]; ++ti) {
+                const double s = tb.term_sign[ti];
+                if (ni == 0) {
+                    o << "    pr = 1.0; pi = 0.0;\n";
+                }
+                for (int j = 0; j < ni; ++j) {
+                    const int l = tb.term_leaf[static_cast<size_t>(ti) * ni + j];
+                    if (j == 0) {
+                        o << "    pr = Fr[" << l << "]; pi = Fi[" << l << "];\n";
+                    } else {
+                        o << "    nr = fma(pr, Fr[" << l << "], -pi * Fi[" << l << "]); pi = fma(pr, Fi[" << l
+                          << "], pi * Fr[" << l << "]); pr = nr;\n";
+                    }
+                }
+                if (s == 1.0) o << "    ar += pr; ai += pi;\n";
+                else if (s == -1.0) o << "    ar -= pr; ai -= pi;\n";
+                else o << "    ar = fma(" << num(s) << ", pr, ar); ai = fma(" << num(s) << ", pi, ai);\n";
+            }
+            o << "    (void)nr; FTr[" << g << "] = ar; FTi[" << g << "] = ai; }\n";
+        }
+        o << "}\n";
+    }
+
     // Taylor-coefficient leaves (poles of higher order): T_j = beta^j f^(j) / j!,
     // f^(j) as a polynomial in f and fm = f(-y) (f' = -f fm, fm' = f fm)
     o << "__device__ __forceinline__ void taylor_leaves(double (&F)[L], const double (&FM)[L], double beta) {\n";
@@ -346,9 +376,9 @@ extern "C" AmiStatus amiTermsSource(const AmiTerms *t, int32_t momentum, char *b
     if (!t || !len) return fail(AMI_E_ARG, "NULL argument");
     std::string why;
     if (!jit_supported(t, momentum != 0, &why)) return fail(AMI_E_UNSUPPORTED, "no specialized kernel: " + why);
-    int kernels = momentum != 0 ? 7 : 3;
+    int kernels = momentum != 0 ? 7 : 11;
     for (int o : t->tab.leaf_order)
-        if (o > 0) kernels &= ~2;   // Taylor-coefficient leaves: no adjoint
+        if (o > 0) kernels &= ~10;   // Taylor-coefficient leaves: no adjoint, no complex energies
     const std::string src = jit_source(t, momentum != 0, kernels);
     *len = static_cast<int64_t>(src.size()) + 1;
     if (!buf) return AMI_OK;

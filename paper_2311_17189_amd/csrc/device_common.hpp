@@ -203,6 +203,39 @@ __device__ __forceinline__ double leaf_deriv(bool bose, double y) {
     return bose ? t * r * r : -t * r * r;
 }
 
+// A leaf at a complex argument y = yr + i yi (complex energies): with
+// z = -y where yr > 0 and z = y elsewhere (so Re z = -|yr| <= 0),
+// w = e^z = t (cos zi + i sin zi), t = e^-|yr|, and Q = sigma + w, the leaf is
+// w/Q where yr > 0 and sigma/Q elsewhere (the complex form of leaf_pair).  For
+// the Bose-type Q = w - 1, its real part is written m cos zi + (cos zi - 1)
+// with m = t - 1 (exp_split) and cos zi - 1 = -sin^2 zi/(1 + cos zi) where
+// cos zi > 0, so Q keeps full relative precision near y = 0.  The imaginary
+// part is reduced modulo 2 pi first (reduce_2pi, exact for |yi| < 6e6).
+__device__ __forceinline__ void leaf_complex(bool bose, double yr, double yi, double &fr, double &fi) {
+    const bool pos = yr > 0.0;
+    double t, m, s, c;
+    exp_split(-fmin(fabs(yr), 700.0), t, m);
+    sincos_red(reduce_2pi(pos ? -yi : yi), s, c);
+    const double wr = t * c, wi = t * s;
+    double qr;
+    if (bose) {
+        const double cm1 = c > 0.0 ? -(s * s) / (1.0 + c) : c - 1.0;
+        qr = fma(m, c, cm1);
+    } else {
+        qr = 1.0 + wr;
+    }
+    const double qi = wi;
+    const double r = rcp_nr(fma(qr, qr, qi * qi));
+    const double ir = qr * r, ii = -qi * r;                 // 1/Q
+    if (pos) {                                              // w/Q
+        fr = fma(wr, ir, -wi * ii);
+        fi = fma(wr, ii, wi * ir);
+    } else {                                                // sigma/Q
+        fr = bose ? -ir : ir;
+        fi = bose ? -ii : ii;
+    }
+}
+
 // ---- counter-based random numbers -----------------------------------------
 
 // Philox4x32 with 10 rounds (Salmon, Moraes, Dror and Shaw, SC'11): each round

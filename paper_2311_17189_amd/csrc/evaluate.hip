@@ -623,6 +623,52 @@ AmiStatus amiEvaluate(AmiTerms *t, const double *energies, int64_t n_e, int64_t 
     return launch_forward(t, false, a, out_sum, static_cast<hipStream_t>(hip_stream));
 }
 
+AmiStatus amiEvaluateComplex(AmiTerms *t, const double *energies, int64_t n_e, int64_t stride_s, int64_t stride_i,
+                             const double *ext_freqs, int64_t n_f, double beta, double e_reg, double *out,
+                             double *out_sum, void *hip_stream) {
+    using namespace ami;
+    clear_error();
+    AmiStatus st = check_common(t, n_e, ext_freqs, n_f, beta);
+    if (st == AMI_OK) st = check_energies(t, n_e, energies, stride_s, stride_i);
+    if (st != AMI_OK) return st;
+    if (!out && !out_sum) return fail(AMI_E_ARG, "out and out_sum are both NULL");
+    const hipStream_t stream = static_cast<hipStream_t>(hip_stream);
+    DeviceTables *dt = nullptr;
+    st = upload(t, &dt);
+    if (st != AMI_OK) return st;
+    void *fn = nullptr;
+    st = jit_get(t, false, kJitComplex, &fn);
+    if (st != AMI_OK) return st;
+    if (n_e == 0) return fill(out_sum, 2 * n_f, stream);
+    const int block = jit_block(t, false);
+    const int64_t nblocks = (n_e + block - 1) / block;
+    if (nblocks > 0x7fffffffLL) return fail(AMI_E_ARG, "n_e too large");
+    KArgs a;
+    std::memset(&a, 0, sizeof(a));
+    a.energies = energies;
+    a.stride_s = stride_s;
+    a.stride_i = stride_i;
+    set_common(a, ext_freqs, n_f, beta, e_reg, n_e);
+    a.out = out;
+    if (out_sum) {
+        st = workspace(t, dt, stream, static_cast<size_t>(nblocks) * n_f * 2 * sizeof(double), &a.partial);
+        if (st != AMI_OK) return st;
+    }
+    timer_mark(stream, false);
+    hipError_t e = launch_jit(fn, nblocks, block, stream, a);
+    if (e == hipSuccess) e = hipGetLastError();
+    timer_mark(stream, true);
+    g_last_variant = "specialized complex";
+    if (e != hipSuccess) return hip_fail(e, "complex-energy launch");
+    if (out_sum) {
+        hipLaunchKernelGGL(ami_colsum_kernel, dim3(static_cast<unsigned>(2 * n_f)), dim3(256), 0, stream, a.partial,
+                           nblocks, static_cast<int>(2 * n_f), out_sum);
+        e = hipGetLastError();
+        if (e != hipSuccess) return hip_fail(e, "row-sum launch");
+    }
+    return AMI_OK;
+}
+
 AmiStatus amiEvaluateHubbard(AmiTerms *t, const double *k, int64_t n_e, int64_t stride_k, const double *q,
                              double hop_t, double mu, const double *ext_freqs, int64_t n_f, double beta,
                              double e_reg, double *out, double *out_sum, void *hip_stream) {

@@ -140,7 +140,7 @@ AmiStatus compile(const std::string &src, std::vector<char> &code, std::string &
 
 // Code object for (t, kind): from the handle, the disk cache, or a compilation.
 AmiStatus code_object(AmiTerms *t, bool hub, int kind) {
-    const int slot = 3 * (hub ? 1 : 0) + kind;
+    const int slot = kJitKinds * (hub ? 1 : 0) + kind;
     std::vector<char> &code = t->jit_code[slot];
     if (!code.empty()) return AMI_OK;
     std::string &err = t->jit_error[slot];
@@ -150,10 +150,12 @@ AmiStatus code_object(AmiTerms *t, bool hub, int kind) {
         err = "no specialized kernel: " + why;
         return fail(AMI_E_UNSUPPORTED, err);
     }
-    if (kind == kJitAdjoint)
+    if (kind == kJitAdjoint || kind == kJitComplex)
         for (int o : t->tab.leaf_order)
             if (o > 0) {
-                err = "no specialized adjoint for Taylor-coefficient leaves (poles of higher order)";
+                err = kind == kJitAdjoint
+                          ? "no specialized adjoint for Taylor-coefficient leaves (poles of higher order)"
+                          : "no complex-energy kernel for Taylor-coefficient leaves (poles of higher order)";
                 return fail(AMI_E_UNSUPPORTED, err);
             }
     const std::string src = jit_source(t, hub, 1 << kind);
@@ -178,10 +180,10 @@ AmiStatus code_object(AmiTerms *t, bool hub, int kind) {
 }  // namespace
 
 AmiStatus jit_get(AmiTerms *t, bool hub, int kind, void **fn) {
-    if (kind < kJitForward || kind > kJitMonteCarlo || (kind == kJitMonteCarlo && !hub))
+    if (kind < kJitForward || kind >= kJitKinds || (kind == kJitMonteCarlo && !hub) || (kind == kJitComplex && hub))
         return fail(AMI_E_ARG, "no such specialized kernel");
     std::lock_guard<std::mutex> lock(t->jit_mu);
-    const int slot = 3 * (hub ? 1 : 0) + kind;
+    const int slot = kJitKinds * (hub ? 1 : 0) + kind;
     // the compilation needs no device: do it first
     AmiStatus st = code_object(t, hub, kind);
     if (st != AMI_OK) return st;
@@ -197,7 +199,7 @@ AmiStatus jit_get(AmiTerms *t, bool hub, int kind, void **fn) {
     e = hipModuleLoadData(&mod, t->jit_code[slot].data());
     if (e != hipSuccess) return hip_fail(e, "hipModuleLoadData (specialized kernel)");
     hipFunction_t f = nullptr;
-    static const char *const kNames[3] = {"ami_jit_fwd", "ami_jit_adj", "ami_jit_mc"};
+    static const char *const kNames[kJitKinds] = {"ami_jit_fwd", "ami_jit_adj", "ami_jit_mc", "ami_jit_cfwd"};
     e = hipModuleGetFunction(&f, mod, kNames[kind]);
     if (e != hipSuccess) {
         (void)hipModuleUnload(mod);

@@ -23,16 +23,19 @@ bool jit_supported(const AmiTerms *t, bool hub, std::string *why);
 int jit_block(const AmiTerms *t, bool hub);
 
 // Device source of the specialized kernels: the forward (kernels & 1), the
-// adjoint (kernels & 2) and/or the Monte-Carlo integrator (kernels & 4).
+// adjoint (kernels & 2), the Monte-Carlo integrator (kernels & 4) and/or the
+// forward at complex energies (kernels & 8).
 std::string jit_source(const AmiTerms *t, bool hub, int kernels);
 
 // Kernels of the specialized evaluator.
-enum JitKind { kJitForward = 0, kJitAdjoint = 1, kJitMonteCarlo = 2 };
+enum JitKind { kJitForward = 0, kJitAdjoint = 1, kJitMonteCarlo = 2, kJitComplex = 3 };
+constexpr int kJitKinds = 4;
 
 // The specialized kernel of `kind` for the energy (hub = false) or momentum
 // input as a hipFunction_t: compiled (or fetched from the code-object cache)
 // and loaded on the current device on first use; thread-safe per handle.
-// The Monte-Carlo kernel exists for the momentum input only.
+// The Monte-Carlo kernel exists for the momentum input only, the complex one
+// for the energy input only.
 AmiStatus jit_get(AmiTerms *t, bool hub, int kind, void **fn);
 
 // Unload every module of the handle (amiFree).

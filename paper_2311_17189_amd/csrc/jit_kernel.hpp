@@ -9,6 +9,7 @@
 //   lines            K_j = sum_l alpha_jl k_l (+ external q), per component
 //   leaf_args        x_l = sum_i c_li E_i                        (Sec. 2.2)
 //   taylor_leaves    f_l -> its Taylor coefficient T_j (poles of higher order, Eq. (5))
+//   group_sums_c     the group sums at complex leaves (complex energies)
 //   group_sums       FT_g = sum_{t in g} s_t prod_{l in t} f_l     (Sec. 2.3)
 //   den_args         D_k = e_k . E + a_k . w                        (Sec. 2.2)
 //   group_products   R_g = prod_{k in g} 1/D_k
@@ -389,11 +390,76 @@ __device__ __forceinline__ void mc_block(const KArgs &a, double *red) {
     }
 }
 
+#if AMI_JIT_KERNELS & 8
+// Forward at complex energies (energy input; interleaved complex128 rows,
+// strides in complex elements).  The leaf arguments and the energy part of
+// the denominators are linear in E, so leaf_args and den_args serve the real
+// and the imaginary parts alike; the leaves are complex (leaf_complex) and so
+// are the group sums FT_g, each multiplied by R_g in complex arithmetic.
+__device__ __forceinline__ void cfwd_tile(const KArgs &a, int64_t tile, double *red) {
+    const int tid = threadIdx.x, B = blockDim.x;
+    const int64_t s = tile * B + tid;
+    const bool active = s < a.n_e;
+    const int64_t sc = active ? s : a.n_e - 1;
+
+    double Er[NE], Ei[NE];
+    const double *row = a.energies + 2 * sc * a.stride_s;
+#pragma unroll
+    for (int i = 0; i < NE; ++i) {
+        Er[i] = row[2 * i * a.stride_i];
+        Ei[i] = row[2 * i * a.stride_i + 1];
+    }
+    double FTr[G], FTi[G], dEi[D];
+    {
+        double xr[L], xi[L], Fr[L], Fi[L];
+        leaf_args(Er, xr);
+        leaf_args(Ei, xi);
+#pragma unroll
+        for (int l = 0; l < L; ++l)
+            ami::leaf_complex(kBose[l], a.beta * (kBose[l] ? xr[l] + a.e_reg : xr[l]), a.beta * xi[l], Fr[l], Fi[l]);
+        group_sums_c(Fr, Fi, FTr, FTi);
+        double zr[NXA], zi[NXA], unused[D];
+#pragma unroll
+        for (int x = 0; x < NXA; ++x) zr[x] = zi[x] = 0.0;
+        den_args(Ei, zr, zi, dEi, unused);          // e_k . Im E
+    }
+
+    for (int f = 0; f < a.n_f; ++f) {
+        double wr[NXA], wi[NXA], dr[D], di[D], xr[D], xi[D], Rr[G], Ri[G];
+        load_freq(a, f, wr, wi);
+        den_args(Er, wr, wi, dr, di);
+#pragma unroll
+        for (int k = 0; k < D; ++k) {
+            const double im = di[k] + dEi[k];
+            const double inv = ami::rcp_nr(fma(dr[k], dr[k], im * im));
+            xr[k] = dr[k] * inv;
+            xi[k] = -im * inv;
+        }
+        group_products(xr, xi, Rr, Ri);
+        double acc_re = 0.0, acc_im = 0.0;
+#pragma unroll
+        for (int g = 0; g < G; ++g) {
+            acc_re = fma(FTr[g], Rr[g], fma(-FTi[g], Ri[g], acc_re));
+            acc_im = fma(FTr[g], Ri[g], fma(FTi[g], Rr[g], acc_im));
+        }
+        if (active && a.out) {
+            double2 v;
+            v.x = acc_re;
+            v.y = acc_im;
+            reinterpret_cast<double2 *>(a.out)[static_cast<int64_t>(f) * a.n_e + s] = v;
+        }
+        if (a.partial)
+            ami::block_sum2(active ? acc_re : 0.0, active ? acc_im : 0.0, red, tid, B,
+                            a.partial + (tile * a.n_f + f) * 2);
+    }
+}
+#endif
+
 }  // namespace amijit
 
 // AMI_JIT_BLOCK lanes per block (the host launches with the same value);
 // AMI_JIT_KERNELS selects the forward (1), the adjoint (2), the Monte-Carlo
-// integrator (4), or a sum of them
+// integrator (4), the forward at complex energies (8), or a sum of them
 #if AMI_JIT_KERNELS & 1
 extern "C" __global__ __launch_bounds__(AMI_JIT_BLOCK) void ami_jit_fwd(ami::KArgs a) {
     __shared__ double red[2 * (AMI_JIT_BLOCK / 64)];
@@ -419,5 +485,12 @@ extern "C" __global__ __launch_bounds__(AMI_JIT_BLOCK) AMI_JIT_ADJ_ATTR void ami
 extern "C" __global__ __launch_bounds__(AMI_JIT_BLOCK) void ami_jit_mc(ami::KArgs a) {
     __shared__ double red[2 * (AMI_JIT_BLOCK / 64)];
     amijit::mc_block<AMI_JIT_HUB>(a, red);
+}
+#endif
+
+#if AMI_JIT_KERNELS & 8
+extern "C" __global__ __launch_bounds__(AMI_JIT_BLOCK) void ami_jit_cfwd(ami::KArgs a) {
+    __shared__ double red[2 * (AMI_JIT_BLOCK / 64)];
+    amijit::cfwd_tile(a, blockIdx.x, red);
 }
 #endif

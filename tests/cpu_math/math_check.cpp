@@ -20,6 +20,14 @@ int main(int argc, char **argv) {
         }
         return 0;
     }
+    if (what[0] == 'F' || what[0] == 'B') {   // leaf at a complex argument: yr yi per line -> re im
+        double yr, yi, fr, fi;
+        while (std::scanf("%lf %lf", &yr, &yi) == 2) {
+            ami::leaf_complex(what[0] == 'B', yr, yi, fr, fi);
+            std::printf("%.17g %.17g\n", fr, fi);
+        }
+        return 0;
+    }
     double x;
     while (std::scanf("%lf", &x) == 1) {
         if (what[0] == 'r') {

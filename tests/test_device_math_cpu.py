@@ -104,6 +104,36 @@ def test_leaf_pair_and_derivative(exe, kind):
         assert _ulp_err(df, -ef * efm) <= 12, (y, df)
 
 
+@pytest.mark.parametrize("kind", ["fermi", "bose"])
+def test_leaf_at_complex_arguments(exe, kind):
+    """1/(sigma e^y + 1) at complex y to a few ulp relative: |Re y| from 1e-10
+    to 690, Im y up to 60, next to the Bose pole at 0, away from the Fermi
+    poles at i pi (2n+1)."""
+    mp.mp.dps = 40
+    rng = np.random.default_rng(62)
+    mag = np.logspace(-10, np.log10(690.0), 120)
+    yr = np.concatenate([mag, -mag, rng.uniform(-5, 5, 200), [0.0, 0.0, 1e-9, -1e-9]])
+    yi = np.concatenate([rng.uniform(-3, 3, 240), rng.uniform(-60, 60, 200), [0.3, -2.0, 1e-9, -2e-9]])
+    sig = 1 if kind == "fermi" else -1
+    if sig == 1:   # keep a distance of 0.05 from the Fermi poles
+        near = np.abs(yr) < 0.05
+        d = np.abs((yi / np.pi - 1) / 2 - np.round((yi / np.pi - 1) / 2)) * 2 * np.pi
+        keep = ~(near & (d < 0.05))
+        yr, yi = yr[keep], yi[keep]
+    res = subprocess.run([exe, "F" if sig == 1 else "B"],
+                         input="\n".join(f"{float(a)!r} {float(b)!r}" for a, b in zip(yr, yi)),
+                         capture_output=True, text=True, check=True)
+    got = np.array([[float(v) for v in l.split()] for l in res.stdout.splitlines()])
+    assert got.shape == (len(yr), 2)
+    for a, b, (fr, fi) in zip(yr, yi, got):
+        Y = mp.mpc(float(a), float(b))
+        want = 1 / (sig * mp.exp(Y) + 1)
+        err = abs(mp.mpc(fr, fi) - want)
+        # relative to |f|; the reduction of Im y modulo 2 pi costs up to |Im y| / 4 ulp
+        bound = (8 + abs(b) / 4) * 2.0 ** -52 * abs(want)
+        assert err <= bound + 1e-300, (a, b, fr, fi, complex(want))
+
+
 def test_device_philox_matches_oracle_and_known_answers(exe):
     from oracle.mc import draw_momenta, philox4x32
     rng = np.random.default_rng(61)

@@ -1,0 +1,99 @@
+"""Complex energies on the GPU (amiEvaluateComplex, the specialized
+complex-energy kernel) against the oracle, element by element on seeded
+inputs: sizes with ragged blocks, Matsubara and real frequencies, strided
+energies, the regulator, row sums, the real limit against amiEvaluate, and
+the refusals."""
+import numpy as np
+import pytest
+
+from ami_inputs import (complex_energies, matsubara_freqs, order2_example, random_self_energy, real_freqs,
+                        uniform_energies)
+
+from parity import check, oracle_terms, reference
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+amd = pytest.importorskip("paper_2311_17189_amd")
+
+DEV = "cuda"
+
+
+def _diag(order, i):
+    return order2_example() if i is None else random_self_energy(order, (0, order, i))
+
+
+@pytest.mark.parametrize("order,i,beta,n_e,e_reg", [
+    (2, None, 5.0, 1000, 0.0), (3, 0, 2.0, 1500, 0.0), (4, 1, 5.0, 2049, 0.0), (4, 6, 2.0, 777, 0.3),
+    (5, 2, 5.0, 700, 0.0), (6, 0, 5.0, 300, 0.0),
+])
+def test_complex_energy_parity(order, i, beta, n_e, e_reg):
+    d = _diag(order, i)
+    # |beta Im x| stays below pi/2 for every leaf (no Fermi pole nearby)
+    eta = 0.25 / (beta * d.n_int)
+    E = complex_energies(n_e, d.n_eps, seed=(91, order, i or 0), a=3.0, eta=eta)
+    w = np.concatenate([matsubara_freqs(2, beta), real_freqs(2, -4.0, 4.0, 0.05)])
+    T = amd.Terms.from_diagram(d)
+    out, s = amd.evaluate_complex(T, torch.from_numpy(E).to(DEV), torch.from_numpy(w).to(DEV), beta, e_reg,
+                                  want_out=True, want_sum=True)
+    torch.cuda.synchronize()
+    assert amd.last_variant() == "specialized complex"
+    ref, scale, dist = reference(d, E, w, beta, e_reg)
+    got = out.cpu().numpy()
+    check(got, ref, scale, dist, label=f"complex order {order}")
+    np.testing.assert_allclose(s.cpu().numpy(), got.sum(axis=1), rtol=1e-12, atol=1e-12 * scale.sum())
+
+
+def test_complex_strided_bosonic_and_empty():
+    # the bubble with a bosonic external frequency, energies read from a strided view
+    alpha = np.array([[1, 0], [1, 1]])
+    T = amd.Terms(alpha, np.eye(2, dtype=np.int8), 1, [1, 0])
+    beta = 2.0
+    big = complex_energies(613, 5, seed=92, a=3.0, eta=0.2)
+    Et = torch.from_numpy(big).to(DEV)[:, 1:3]
+    assert Et.stride() == (5, 1)
+    w = 2j * np.pi * np.arange(1, 4) / beta
+    out, _ = amd.evaluate_complex(T, Et, torch.from_numpy(w).to(DEV), beta)
+    torch.cuda.synchronize()
+    E = big[:, 1:3]
+    f = lambda z: 1.0 / (np.exp(beta * z) + 1.0)
+    closed = (f(-E[:, 0]) - f(-E[:, 1]))[None, :] / (w[:, None] + E[None, :, 1] - E[None, :, 0])
+    np.testing.assert_allclose(out.cpu().numpy(), closed, rtol=1e-12, atol=1e-14)
+    # the transposed layout (stride_i > stride_s)
+    Tt = torch.from_numpy(np.ascontiguousarray(E.T)).to(DEV).t()
+    out2, _ = amd.evaluate_complex(T, Tt, torch.from_numpy(w).to(DEV), beta)
+    torch.cuda.synchronize()
+    assert torch.equal(out2, out)
+    # no samples: zero row sums
+    _, s0 = amd.evaluate_complex(T, Et[:0], torch.from_numpy(w).to(DEV), beta, want_out=False, want_sum=True)
+    torch.cuda.synchronize()
+    assert torch.all(s0 == 0)
+
+
+def test_complex_real_limit_matches_the_real_path():
+    d = random_self_energy(4, (0, 4, 3))
+    T = amd.Terms.from_diagram(d)
+    beta = 5.0
+    E = uniform_energies(1024, d.n_eps, seed=93, a=3.0)
+    w = torch.from_numpy(np.concatenate([matsubara_freqs(2, beta), real_freqs(1, 0.5, 0.5, 0.05)])).to(DEV)
+    Er = torch.from_numpy(E).to(DEV)
+    a, _ = amd.evaluate(T, Er, w, beta)
+    b, _ = amd.evaluate_complex(T, Er.to(torch.complex128), w, beta)
+    torch.cuda.synchronize()
+    _, scale, _ = reference(d, E, w.cpu().numpy(), beta, terms=oracle_terms(d))
+    assert np.max(np.abs((a - b).cpu().numpy()) / scale) <= 1e-13
+
+
+def test_complex_refusals():
+    alpha = np.array([[1, 0], [1, 0], [1, 1]])
+    eps = np.array([[1, 0], [1, 0], [0, 1]])
+    T = amd.Terms(alpha, eps, 1, [1, 0], multipole=True)
+    E = torch.zeros((8, 2), dtype=torch.complex128, device=DEV)
+    w = torch.from_numpy(2j * np.pi * np.arange(1, 3) / 2.0).to(DEV)
+    with pytest.raises(amd.AmiError) as e:
+        amd.evaluate_complex(T, E, w, 2.0)
+    assert e.value.code == -7
+    T2 = amd.Terms.from_diagram(order2_example())
+    with pytest.raises(amd.AmiError) as e:
+        amd.evaluate_complex(T2, torch.zeros((8, 3), dtype=torch.float64, device=DEV), w, 2.0)
+    assert e.value.code == -1
