@@ -344,9 +344,11 @@ AmiStatus amiSetVariant(AmiTerms *terms, int32_t variant);
  * input and load them on the current device, so that the compilation stays
  * out of later evaluate calls.  Host-blocking.  AMI_E_UNSUPPORTED when the
  * solution is outside the specialized form, AMI_E_HIP when compiling or loading
- * fails (amiLastError holds the compiler log).  A solution with Taylor-
- * coefficient leaves (AMI_MULTIPOLE) gets its forward kernels only: it has no
- * adjoint.
+ * fails (amiLastError holds the compiler log).  The kernels are the forward
+ * and the adjoint, plus the complex-energy forward (amiEvaluateComplex) for
+ * the energy input; all are compiled before a device is touched.  A solution
+ * with Taylor-coefficient leaves (AMI_MULTIPOLE) gets its forward kernel
+ * only.
  */
 AmiStatus amiTermsSpecialize(AmiTerms *terms, int32_t momentum);
 

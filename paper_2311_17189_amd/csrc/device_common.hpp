@@ -287,10 +287,49 @@ __device__ __forceinline__ void combo_adj(uint32_t pos, uint32_t neg, double v, 
     }
 }
 
+// A double moved across lanes by one DPP control, as two 32-bit halves; lanes
+// whose row is outside ROW_MASK, or whose source lane is outside the row,
+// receive 0.
+template <int CTRL, int ROW_MASK>
+__device__ __forceinline__ double dpp_move(double v) {
+    const unsigned long long u = __builtin_bit_cast(unsigned long long, v);
+    const int lo = __builtin_amdgcn_update_dpp(0, static_cast<int>(static_cast<unsigned>(u)), CTRL, ROW_MASK, 0xf,
+                                               false);
+    const int hi = __builtin_amdgcn_update_dpp(0, static_cast<int>(static_cast<unsigned>(u >> 32)), CTRL, ROW_MASK,
+                                               0xf, false);
+    return __builtin_bit_cast(double, (static_cast<unsigned long long>(static_cast<unsigned>(hi)) << 32) |
+                                          static_cast<unsigned>(lo));
+}
+
+// Sum over the 64 lanes of a wave (every lane active), returned in every
+// lane: inclusive prefix sums within each row of 16 lanes (row_shr 1, 2, 4,
+// 8), then the total of row 0 added into row 1 and of row 2 into row 3
+// (row_bcast:15), then lane 31 into rows 2-3 (row_bcast:31); lane 63 then
+// holds the total, which readlane broadcasts.  Register moves only: no LDS
+// round trips and no waits.
 __device__ __forceinline__ double wave_sum(double v) {
-#pragma unroll
-    for (int off = 32; off >= 1; off >>= 1) v += __shfl_xor(v, off, 64);
-    return v;
+    v += dpp_move<0x111, 0xf>(v);   // row_shr:1
+    v += dpp_move<0x112, 0xf>(v);   // row_shr:2
+    v += dpp_move<0x114, 0xf>(v);   // row_shr:4
+    v += dpp_move<0x118, 0xf>(v);   // row_shr:8
+    v += dpp_move<0x142, 0xa>(v);   // row_bcast:15
+    v += dpp_move<0x143, 0xc>(v);   // row_bcast:31
+    const unsigned long long u = __builtin_bit_cast(unsigned long long, v);
+    const unsigned lo = static_cast<unsigned>(__builtin_amdgcn_readlane(static_cast<int>(static_cast<unsigned>(u)), 63));
+    const unsigned hi = static_cast<unsigned>(__builtin_amdgcn_readlane(static_cast<int>(static_cast<unsigned>(u >> 32)), 63));
+    return __builtin_bit_cast(double, (static_cast<unsigned long long>(hi) << 32) | lo);
+}
+
+// The wave's totals of (vr, vi), stored by its first lane at dst[0] and
+// dst[stride]: the per-wave partial sums of the specialized kernels (no LDS,
+// no barrier).
+__device__ __forceinline__ void wave_store2(double vr, double vi, int lane, double *dst, int64_t stride) {
+    vr = wave_sum(vr);
+    vi = wave_sum(vi);
+    if (lane == 0) {
+        dst[0] = vr;
+        dst[stride] = vi;
+    }
 }
 
 // Block sum of (vr, vi) into dst[0..1], deterministic; every lane must call it.

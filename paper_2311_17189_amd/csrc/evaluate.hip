@@ -10,6 +10,7 @@
 // per block with a fixed shuffle tree and then across blocks in a fixed order,
 // so repeated calls are bitwise identical.
 #include <hip/hip_runtime.h>
+#include <hip/hip_ext.h>
 
 #include <algorithm>
 #include <cmath>
@@ -33,37 +34,61 @@ AmiStatus hip_fail(hipError_t e, const char *what) {
 
 namespace {
 
-// out[j] = sum over b of partial[b * ncols + j], b in increasing order per thread
-// then a fixed tree over the block.  One block per column.
-__global__ __launch_bounds__(256) void ami_colsum_kernel(const double *partial, int64_t nblocks, int ncols,
-                                                         double *out) {
-    __shared__ double sh[256];
-    const int j = blockIdx.x;
+// Column sums of the partial-sum arrays: element (row r, column c) at
+// partial[r * rs + c * cs] (rs = ncols, cs = 1 for the per-block sums of the
+// table-driven kernels; rs = 1, cs = rows for the per-wave sums of the
+// specialized ones, so that a column is one contiguous read).  One block of
+// kRedThreads per column; thread t adds rows t, t + kRedThreads, ... in
+// order, loading 16 of them before adding (16 loads in flight per thread),
+// then the block adds the threads in a fixed order (wave sums, then the waves
+// in order): a fixed summation order for a given row count.
+constexpr int kRedThreads = 1024;
+
+__device__ __forceinline__ double column_sum(const double *col, int64_t n, int64_t rs, double *sh) {
     const int tid = threadIdx.x;
+    constexpr int kLoads = 16;                 // rows in flight per thread
     double acc = 0.0;
-    for (int64_t b = tid; b < nblocks; b += 256) acc += partial[b * ncols + j];
-    sh[tid] = acc;
-    __syncthreads();
-    for (int w = 128; w >= 1; w >>= 1) {
-        if (tid < w) sh[tid] += sh[tid + w];
-        __syncthreads();
+    for (int64_t b0 = tid; b0 < n; b0 += kLoads * kRedThreads) {
+        double v[kLoads];
+#pragma unroll
+        for (int u = 0; u < kLoads; ++u) {
+            const int64_t b = b0 + static_cast<int64_t>(u) * kRedThreads;
+            v[u] = b < n ? col[b * rs] : 0.0;
+        }
+#pragma unroll
+        for (int u = 0; u < kLoads; ++u) acc += v[u];
     }
-    if (tid == 0) out[j] = sh[0];
+    acc = wave_sum(acc);
+    if ((tid & 63) == 0) sh[tid >> 6] = acc;
+    __syncthreads();
+    double r = 0.0;
+    if (tid == 0)
+        for (int w = 0; w < kRedThreads / 64; ++w) r += sh[w];
+    return r;   // in thread 0
+}
+
+// out[j] = sum over rows of column j.  One block per column.
+__global__ __launch_bounds__(kRedThreads) void ami_colsum_kernel(const double *partial, int64_t rows, int64_t rs,
+                                                                 int64_t cs, double *out) {
+    __shared__ double sh[kRedThreads / 64];
+    const double r = column_sum(partial + blockIdx.x * cs, rows, rs, sh);
+    if (threadIdx.x == 0) out[blockIdx.x] = r;
 }
 
 // Same reduction for the adjoint partials, routing each column to its output:
 // column 0 dL/dbeta, 1 dL/dmu, 2 dL/dt, 4.. dL/dw (complex [n_f][n_ext]).
 // Blocks past the gradient columns reduce the forward values' row sums
-// (partial sums [nblocks][nval] stored after the gradient ones).
-__global__ __launch_bounds__(256) void ami_adj_finalize_kernel(const double *partial, int64_t nblocks, int ncols,
-                                                               double *gbeta, double *gmu, double *gt,
-                                                               double *gw, int nval, double *vsum) {
-    __shared__ double sh[256];
+// (partial sums of nval columns stored after the ncols gradient ones, in the
+// same layout: column-major when colmajor, else row-major).
+__global__ __launch_bounds__(kRedThreads) void ami_adj_finalize_kernel(const double *partial, int64_t rows, int ncols,
+                                                                       int colmajor, double *gbeta, double *gmu,
+                                                                       double *gt, double *gw, int nval,
+                                                                       double *vsum) {
+    __shared__ double sh[kRedThreads / 64];
     int j = blockIdx.x;
-    const int tid = threadIdx.x;
     double *dst = nullptr;
     const double *src = partial;
-    int stride = ncols;
+    int64_t width = ncols;
     if (j == 0) dst = gbeta;
     else if (j == 1) dst = gmu;
     else if (j == 2) dst = gt;
@@ -71,19 +96,12 @@ __global__ __launch_bounds__(256) void ami_adj_finalize_kernel(const double *par
     else if (j >= ncols && vsum) {
         j -= ncols;
         dst = vsum + j;
-        src = partial + nblocks * ncols;
-        stride = nval;
+        src = partial + rows * ncols;
+        width = nval;
     }
     if (!dst) return;
-    double acc = 0.0;
-    for (int64_t b = tid; b < nblocks; b += 256) acc += src[b * stride + j];
-    sh[tid] = acc;
-    __syncthreads();
-    for (int w = 128; w >= 1; w >>= 1) {
-        if (tid < w) sh[tid] += sh[tid + w];
-        __syncthreads();
-    }
-    if (tid == 0) *dst = sh[0];
+    const double r = colmajor ? column_sum(src + j * rows, rows, 1, sh) : column_sum(src + j, rows, width, sh);
+    if (threadIdx.x == 0) *dst = r;
 }
 
 __global__ void ami_fill_kernel(double *p, int64_t n, double v) {
@@ -319,7 +337,10 @@ AmiStatus launch_generic_forward(AmiTerms *t, DeviceTables *dt, bool hub, const 
 thread_local std::string g_last_variant;
 
 // Optional HIP-event timing of the main evaluation kernel of each call on
-// this thread (amiKernelTimerStart / amiKernelTimerStop).
+// this thread (amiKernelTimerStart / amiKernelTimerStop).  The specialized
+// kernels carry the events on their own dispatch (hipExtModuleLaunchKernel),
+// so the pair brackets the kernel alone; the table-driven ones are bracketed
+// by events recorded on the stream around the launch.
 struct KernelTimer {
     bool on = false;
     std::vector<hipEvent_t> ev;      // start/stop pairs
@@ -331,6 +352,15 @@ void timer_mark(hipStream_t stream, bool stop) {
     if (!g_timer.on || g_timer.used >= static_cast<int>(g_timer.ev.size()) / 2) return;
     (void)hipEventRecord(g_timer.ev[2 * g_timer.used + (stop ? 1 : 0)], stream);
     if (stop) ++g_timer.used;
+}
+
+// The next start/stop pair for a dispatch, or false when the timer is off or full.
+bool timer_pair(hipEvent_t &start, hipEvent_t &stop) {
+    if (!g_timer.on || g_timer.used >= static_cast<int>(g_timer.ev.size()) / 2) return false;
+    start = g_timer.ev[2 * g_timer.used];
+    stop = g_timer.ev[2 * g_timer.used + 1];
+    ++g_timer.used;
+    return true;
 }
 
 enum class Path { TABLES, PACKED, SPECIALIZED };
@@ -396,10 +426,16 @@ AmiStatus workspace(AmiTerms *t, DeviceTables *dt, hipStream_t stream, size_t by
     return AMI_OK;
 }
 
+// Launch of a specialized kernel (timed by the kernel timer when it runs).
 hipError_t launch_jit(void *fn, int64_t nblocks, int block, hipStream_t stream, KArgs &a) {
     void *params[] = {&a};
-    return hipModuleLaunchKernel(static_cast<hipFunction_t>(fn), static_cast<unsigned>(nblocks), 1, 1,
-                                 static_cast<unsigned>(block), 1, 1, 0, stream, params, nullptr);
+    const hipFunction_t f = static_cast<hipFunction_t>(fn);
+    hipEvent_t t0 = nullptr, t1 = nullptr;
+    if (nblocks * block <= 0xffffffffLL && timer_pair(t0, t1))
+        return hipExtModuleLaunchKernel(f, static_cast<uint32_t>(nblocks * block), 1, 1, static_cast<uint32_t>(block),
+                                        1, 1, 0, stream, params, nullptr, t0, t1, 0);
+    return hipModuleLaunchKernel(f, static_cast<unsigned>(nblocks), 1, 1, static_cast<unsigned>(block), 1, 1, 0,
+                                 stream, params, nullptr);
 }
 
 AmiStatus launch_forward(AmiTerms *t, bool hub, KArgs &a, double *out_sum, hipStream_t stream) {
@@ -422,16 +458,19 @@ AmiStatus launch_forward(AmiTerms *t, bool hub, KArgs &a, double *out_sum, hipSt
     }
     const int64_t nblocks = (a.n_e + ls.block - 1) / ls.block;
     if (nblocks > 0x7fffffffLL) return fail(AMI_E_ARG, "n_e too large");
+    // partial-sum rows: one per wave for the specialized kernels, per block otherwise
+    const int64_t rows = path == Path::SPECIALIZED ? nblocks * (ls.block / 64) : nblocks;
     double *partial = nullptr;
     hipError_t e;
     if (out_sum) {
-        st = workspace(t, dt, stream, static_cast<size_t>(nblocks) * a.n_f * 2 * sizeof(double), &partial);
+        st = workspace(t, dt, stream, static_cast<size_t>(rows) * a.n_f * 2 * sizeof(double), &partial);
         if (st != AMI_OK) return st;
     }
     const dim3 grid(static_cast<unsigned>(nblocks)), block(ls.block);
-    timer_mark(stream, false);
+    if (path != Path::SPECIALIZED) timer_mark(stream, false);
     if (path == Path::SPECIALIZED) {
         a.partial = partial;
+        a.nrows = rows;
         e = launch_jit(jit_fn, nblocks, ls.block, stream, a);
         g_last_variant = "specialized";
         if (e == hipSuccess) e = hipGetLastError();
@@ -448,11 +487,12 @@ AmiStatus launch_forward(AmiTerms *t, bool hub, KArgs &a, double *out_sum, hipSt
         g_last_variant = "double tables" + note;
         e = hipGetLastError();
     }
-    timer_mark(stream, true);
+    if (path != Path::SPECIALIZED) timer_mark(stream, true);
     if (e != hipSuccess) return hip_fail(e, "forward launch");
     if (out_sum) {
-        hipLaunchKernelGGL(ami_colsum_kernel, dim3(2 * a.n_f), dim3(256), 0, stream, partial, nblocks, 2 * a.n_f,
-                           out_sum);
+        const bool cm = path == Path::SPECIALIZED;
+        hipLaunchKernelGGL(ami_colsum_kernel, dim3(2 * a.n_f), dim3(kRedThreads), 0, stream, partial, rows,
+                           static_cast<int64_t>(cm ? 1 : 2 * a.n_f), cm ? rows : static_cast<int64_t>(1), out_sum);
         e = hipGetLastError();
         if (e != hipSuccess) return hip_fail(e, "row-sum launch");
     }
@@ -494,34 +534,38 @@ AmiStatus launch_adjoint(AmiTerms *t, bool hub, KArgs &a, const AdjOut &o, hipSt
     }
     const int64_t nblocks = (a.n_e + ls.block - 1) / ls.block;
     if (nblocks > 0x7fffffffLL) return fail(AMI_E_ARG, "n_e too large");
+    // partial-sum rows: one per wave for the specialized kernels, per block otherwise
+    const int64_t rows = path == Path::SPECIALIZED ? nblocks * (ls.block / 64) : nblocks;
     double *partial = nullptr;
-    const size_t n_grad = static_cast<size_t>(nblocks) * ncols;
-    const size_t n_val = o.out_sum ? static_cast<size_t>(nblocks) * a.n_f * 2 : 0;
+    const size_t n_grad = static_cast<size_t>(rows) * ncols;
+    const size_t n_val = o.out_sum ? static_cast<size_t>(rows) * a.n_f * 2 : 0;
     st = workspace(t, dt, stream, (n_grad + n_val) * sizeof(double), &partial);
     if (st != AMI_OK) return st;
     hipError_t e;
     a.gpartial = partial;
     a.partial = o.out_sum ? partial + n_grad : nullptr;
     const dim3 grid(static_cast<unsigned>(nblocks)), block(ls.block);
-    timer_mark(stream, false);
     if (path == Path::SPECIALIZED) {
+        a.nrows = rows;
         e = launch_jit(jit_fn, nblocks, ls.block, stream, a);
         g_last_variant = "specialized";
         if (e == hipSuccess) e = hipGetLastError();
     } else {
         a.tb = packed_tabs(t, dt);
         a.slots = ls.slots;
+        timer_mark(stream, false);
         g_last_variant = std::string("packed ") +
                          (hub ? launch_packed<true, true>(t, grid, block, ls.lds, stream, a)
                               : launch_packed<true, false>(t, grid, block, ls.lds, stream, a)) + note;
         e = hipGetLastError();
+        timer_mark(stream, true);
     }
-    timer_mark(stream, true);
     if (e != hipSuccess) return hip_fail(e, "adjoint launch");
     // one launch for every reduction: gradient columns, then the value row sums
     const int n_red = ncols + (o.out_sum ? 2 * a.n_f : 0);
-    hipLaunchKernelGGL(ami_adj_finalize_kernel, dim3(n_red), dim3(256), 0, stream, partial, nblocks, ncols,
-                       o.grad_beta, o.grad_mu, o.grad_t, o.grad_freqs, 2 * a.n_f, o.out_sum);
+    hipLaunchKernelGGL(ami_adj_finalize_kernel, dim3(n_red), dim3(kRedThreads), 0, stream, partial, rows, ncols,
+                       path == Path::SPECIALIZED ? 1 : 0, o.grad_beta, o.grad_mu, o.grad_t, o.grad_freqs, 2 * a.n_f,
+                       o.out_sum);
     e = hipGetLastError();
     if (e != hipSuccess) return hip_fail(e, "adjoint reduction launch");
     return AMI_OK;
@@ -643,6 +687,7 @@ AmiStatus amiEvaluateComplex(AmiTerms *t, const double *energies, int64_t n_e, i
     const int block = jit_block(t, false);
     const int64_t nblocks = (n_e + block - 1) / block;
     if (nblocks > 0x7fffffffLL) return fail(AMI_E_ARG, "n_e too large");
+    const int64_t rows = nblocks * (block / 64);   // partial sums per wave
     KArgs a;
     std::memset(&a, 0, sizeof(a));
     a.energies = energies;
@@ -650,19 +695,18 @@ AmiStatus amiEvaluateComplex(AmiTerms *t, const double *energies, int64_t n_e, i
     a.stride_i = stride_i;
     set_common(a, ext_freqs, n_f, beta, e_reg, n_e);
     a.out = out;
+    a.nrows = rows;
     if (out_sum) {
-        st = workspace(t, dt, stream, static_cast<size_t>(nblocks) * n_f * 2 * sizeof(double), &a.partial);
+        st = workspace(t, dt, stream, static_cast<size_t>(rows) * n_f * 2 * sizeof(double), &a.partial);
         if (st != AMI_OK) return st;
     }
-    timer_mark(stream, false);
     hipError_t e = launch_jit(fn, nblocks, block, stream, a);
     if (e == hipSuccess) e = hipGetLastError();
-    timer_mark(stream, true);
     g_last_variant = "specialized complex";
     if (e != hipSuccess) return hip_fail(e, "complex-energy launch");
     if (out_sum) {
-        hipLaunchKernelGGL(ami_colsum_kernel, dim3(static_cast<unsigned>(2 * n_f)), dim3(256), 0, stream, a.partial,
-                           nblocks, static_cast<int>(2 * n_f), out_sum);
+        hipLaunchKernelGGL(ami_colsum_kernel, dim3(static_cast<unsigned>(2 * n_f)), dim3(kRedThreads), 0, stream,
+                           a.partial, rows, static_cast<int64_t>(1), rows, out_sum);
         e = hipGetLastError();
         if (e != hipSuccess) return hip_fail(e, "row-sum launch");
     }
@@ -770,8 +814,9 @@ AmiStatus amiIntegrateHubbard(AmiTerms *t, int64_t n_samples, uint64_t seed, con
     // eight blocks per CU, or fewer when there are fewer samples
     const int block = jit_block(t, true);
     const int64_t grid = std::min<int64_t>((n_samples + block - 1) / block, 8 * static_cast<int64_t>(n_cu));
+    const int64_t rows = grid * (block / 64);   // partial sums per wave
     double *partial = nullptr;
-    st = workspace(t, dt, stream, static_cast<size_t>(grid) * n_f * 4 * sizeof(double), &partial);
+    st = workspace(t, dt, stream, static_cast<size_t>(rows) * n_f * 4 * sizeof(double), &partial);
     if (st != AMI_OK) return st;
     KArgs a;
     std::memset(&a, 0, sizeof(a));
@@ -779,14 +824,13 @@ AmiStatus amiIntegrateHubbard(AmiTerms *t, int64_t n_samples, uint64_t seed, con
     set_common(a, ext_freqs, n_f, beta, e_reg, n_samples);
     a.seed = seed;
     a.partial = partial;
-    timer_mark(stream, false);
+    a.nrows = rows;
     e = launch_jit(fn, grid, block, stream, a);
     if (e == hipSuccess) e = hipGetLastError();
-    timer_mark(stream, true);
     g_last_variant = "specialized";
     if (e != hipSuccess) return hip_fail(e, "Monte-Carlo launch");
-    hipLaunchKernelGGL(ami_colsum_kernel, dim3(static_cast<unsigned>(4 * n_f)), dim3(256), 0, stream, partial, grid,
-                       static_cast<int>(4 * n_f), sums);
+    hipLaunchKernelGGL(ami_colsum_kernel, dim3(static_cast<unsigned>(4 * n_f)), dim3(kRedThreads), 0, stream, partial,
+                       rows, static_cast<int64_t>(1), rows, sums);
     e = hipGetLastError();
     return e == hipSuccess ? AMI_OK : hip_fail(e, "Monte-Carlo reduction launch");
 }
@@ -803,12 +847,25 @@ AmiStatus amiSetVariant(AmiTerms *t, int32_t variant) {
 AmiStatus amiTermsSpecialize(AmiTerms *t, int32_t momentum) {
     ami::clear_error();
     if (!t) return ami::fail(AMI_E_ARG, "terms is NULL");
-    void *fn = nullptr;
-    const AmiStatus st = ami::jit_get(t, momentum != 0, ami::kJitForward, &fn);
-    if (st != AMI_OK) return st;
-    for (int o : t->tab.leaf_order)
-        if (o > 0) return AMI_OK;   // Taylor-coefficient leaves: forward only
-    return ami::jit_get(t, momentum != 0, ami::kJitAdjoint, &fn);
+    using namespace ami;
+    const bool hub = momentum != 0;
+    bool taylor = false;                    // Taylor-coefficient leaves: forward only
+    for (int o : t->tab.leaf_order) taylor = taylor || o > 0;
+    // the kernels for this input: forward, adjoint, and the complex-energy
+    // forward for the energy input; all compiled before any device is touched
+    std::vector<int> kinds{kJitForward};
+    if (!taylor) kinds.push_back(kJitAdjoint);
+    if (!taylor && !hub) kinds.push_back(kJitComplex);
+    for (int k : kinds) {
+        const AmiStatus st = jit_compile(t, hub, k);
+        if (st != AMI_OK) return st;
+    }
+    for (int k : kinds) {
+        void *fn = nullptr;
+        const AmiStatus st = jit_get(t, hub, k, &fn);
+        if (st != AMI_OK) return st;
+    }
+    return AMI_OK;
 }
 
 const char *amiLastVariant(void) { return ami::g_last_variant.c_str(); }

@@ -179,6 +179,13 @@ AmiStatus code_object(AmiTerms *t, bool hub, int kind) {
 
 }  // namespace
 
+AmiStatus jit_compile(AmiTerms *t, bool hub, int kind) {
+    if (kind < kJitForward || kind >= kJitKinds || (kind == kJitMonteCarlo && !hub) || (kind == kJitComplex && hub))
+        return fail(AMI_E_ARG, "no such specialized kernel");
+    std::lock_guard<std::mutex> lock(t->jit_mu);
+    return code_object(t, hub, kind);
+}
+
 AmiStatus jit_get(AmiTerms *t, bool hub, int kind, void **fn) {
     if (kind < kJitForward || kind >= kJitKinds || (kind == kJitMonteCarlo && !hub) || (kind == kJitComplex && hub))
         return fail(AMI_E_ARG, "no such specialized kernel");

@@ -38,6 +38,10 @@ constexpr int kJitKinds = 4;
 // for the energy input only.
 AmiStatus jit_get(AmiTerms *t, bool hub, int kind, void **fn);
 
+// Only the code object of `kind` (compiled or fetched from the cache): needs
+// no device.
+AmiStatus jit_compile(AmiTerms *t, bool hub, int kind);
+
 // Unload every module of the handle (amiFree).
 void jit_release(AmiTerms *t);
 

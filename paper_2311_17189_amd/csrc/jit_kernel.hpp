@@ -20,8 +20,9 @@
 //   line_scatter     dL/dk_l += sum_j alpha_jl dL/dK_j
 // With every index a constant, all per-sample state lives in registers: no
 // LDS beyond the block reduction, no table reads, no scalar bit tests.
-// Block partial sums use the packed evaluators' layouts, so the same
-// reduction kernels finish them.
+// Partial sums are written per wave (no LDS, no barrier), column by column
+// (a.nrows = blocks x waves per block rows), in the column order of the packed
+// evaluators, so the same reduction kernels finish them.
 #pragma once
 
 namespace amijit {
@@ -124,9 +125,13 @@ __device__ __forceinline__ void reciprocals(const double (&E)[NE], const double 
     }
 }
 
+// Partial sums are per wave: row r = tile * (B / 64) + wave of the partial
+// arrays (column c at [c * nrows + r]), written by the wave's first lane
+// (wave_store2).
 template <bool HUB>
-__device__ __forceinline__ void fwd_tile(const KArgs &a, int64_t tile, double *red) {
-    const int tid = threadIdx.x, B = blockDim.x;
+__device__ __forceinline__ void fwd_tile(const KArgs &a, int64_t tile) {
+    const int tid = threadIdx.x, B = blockDim.x, lane = tid & 63;
+    const int64_t row = tile * (B >> 6) + (tid >> 6);
     const int64_t s = tile * B + tid;
     const bool active = s < a.n_e;
     const int64_t sc = active ? s : a.n_e - 1;
@@ -162,8 +167,8 @@ __device__ __forceinline__ void fwd_tile(const KArgs &a, int64_t tile, double *r
             reinterpret_cast<double2 *>(a.out)[static_cast<int64_t>(f) * a.n_e + s] = v;
         }
         if (a.partial)
-            ami::block_sum2(active ? acc_re : 0.0, active ? acc_im : 0.0, red, tid, B,
-                            a.partial + (tile * a.n_f + f) * 2);
+            ami::wave_store2(active ? acc_re : 0.0, active ? acc_im : 0.0, lane, a.partial + 2 * f * a.nrows + row,
+                             a.nrows);
     }
 }
 
@@ -173,8 +178,9 @@ __device__ __forceinline__ void fwd_tile(const KArgs &a, int64_t tile, double *r
 // The leaf arguments x_l are recomputed after the frequency loop instead of
 // being kept live through it.
 template <bool HUB>
-__device__ __forceinline__ void adj_tile(const KArgs &a, int64_t blk, double *red, double *park) {
-    const int tid = threadIdx.x, B = blockDim.x;
+__device__ __forceinline__ void adj_tile(const KArgs &a, int64_t blk, double *park) {
+    const int tid = threadIdx.x, B = blockDim.x, lane = tid & 63;
+    const int64_t row = blk * (B >> 6) + (tid >> 6);
     const int64_t s = blk * B + tid;
     const bool active = s < a.n_e;
     const int64_t sc = active ? s : a.n_e - 1;
@@ -202,7 +208,7 @@ __device__ __forceinline__ void adj_tile(const KArgs &a, int64_t blk, double *re
     double gE[NE];
 #pragma unroll
     for (int i = 0; i < NE; ++i) gE[i] = 0.0;
-    double *gp = a.gpartial + blk * (ami::kAdjScalars + 2 * a.n_f * NX);
+    double *gp = a.gpartial + row;                   // column c at gp[c * nrows]
 
     for (int f = 0; f < a.n_f; ++f) {
         double cr = 0.0, ci = 0.0;
@@ -246,8 +252,8 @@ __device__ __forceinline__ void adj_tile(const KArgs &a, int64_t blk, double *re
         den_scatter(dR, dI, gE, gwr, gwi);
 #pragma unroll
         for (int xx = 0; xx < NX; ++xx)
-            ami::block_sum2(active ? gwr[xx] : 0.0, active ? -gwi[xx] : 0.0, red, tid, B,
-                            gp + ami::kAdjScalars + 2 * (f * NX + xx));
+            ami::wave_store2(active ? gwr[xx] : 0.0, active ? -gwi[xx] : 0.0, lane,
+                             gp + (ami::kAdjScalars + 2 * (f * NX + xx)) * a.nrows, a.nrows);
         if (active && a.out) {
             double2 v;
             v.x = acc_re;
@@ -255,8 +261,8 @@ __device__ __forceinline__ void adj_tile(const KArgs &a, int64_t blk, double *re
             reinterpret_cast<double2 *>(a.out)[static_cast<int64_t>(f) * a.n_e + s] = v;
         }
         if (a.partial)
-            ami::block_sum2(active ? acc_re : 0.0, active ? acc_im : 0.0, red, tid, B,
-                            a.partial + (blk * a.n_f + f) * 2);
+            ami::wave_store2(active ? acc_re : 0.0, active ? acc_im : 0.0, lane, a.partial + 2 * f * a.nrows + row,
+                             a.nrows);
     }
 
     double FB[L];
@@ -314,8 +320,8 @@ __device__ __forceinline__ void adj_tile(const KArgs &a, int64_t blk, double *re
 #pragma unroll
         for (int i = 0; i < NE; ++i) row[i] = gE[i];
     }
-    ami::block_sum2(active ? gbeta : 0.0, active ? gmu : 0.0, red, tid, B, gp);
-    ami::block_sum2(active ? gt : 0.0, 0.0, red, tid, B, gp + 2);
+    ami::wave_store2(active ? gbeta : 0.0, active ? gmu : 0.0, lane, gp, a.nrows);
+    ami::wave_store2(active ? gt : 0.0, 0.0, lane, gp + 2 * a.nrows, a.nrows);
 }
 
 // Monte-Carlo integration over the internal momenta (Sec. 5.2, the row
@@ -323,11 +329,13 @@ __device__ __forceinline__ void adj_tile(const KArgs &a, int64_t blk, double *re
 // its 2 NI components from Philox blocks (counter (s mod 2^32, s div 2^32,
 // b, 0), key = the 64-bit seed), evaluates every frequency row, and
 // accumulates sum Re I, sum Im I, sum (Re I)^2, sum (Im I)^2 per lane; the
-// block sums go to partial[block][n_f][4].  Nothing per sample touches HBM.
+// wave sums go to row block * (B / 64) + wave, columns 4 f .. 4 f + 3, of the
+// partial sums.  Nothing per sample touches HBM.
 template <bool HUB>
-__device__ __forceinline__ void mc_block(const KArgs &a, double *red) {
+__device__ __forceinline__ void mc_block(const KArgs &a) {
     static_assert(HUB, "Monte-Carlo integration samples momenta");
-    const int tid = threadIdx.x, B = blockDim.x;
+    const int tid = threadIdx.x, B = blockDim.x, lane = tid & 63;
+    const int64_t row = static_cast<int64_t>(blockIdx.x) * (B >> 6) + (tid >> 6);
     const int64_t stride = static_cast<int64_t>(gridDim.x) * B;
     const uint32_t k0 = static_cast<uint32_t>(a.seed), k1 = static_cast<uint32_t>(a.seed >> 32);
     double acc[4][ami::kMcMaxFreqs];
@@ -383,9 +391,9 @@ __device__ __forceinline__ void mc_block(const KArgs &a, double *red) {
 #pragma unroll
     for (int f = 0; f < ami::kMcMaxFreqs; ++f) {
         if (f < a.n_f) {
-            double *dst = a.partial + (static_cast<int64_t>(blockIdx.x) * a.n_f + f) * 4;
-            ami::block_sum2(acc[0][f], acc[1][f], red, tid, B, dst);
-            ami::block_sum2(acc[2][f], acc[3][f], red, tid, B, dst + 2);
+            double *dst = a.partial + 4 * f * a.nrows + row;
+            ami::wave_store2(acc[0][f], acc[1][f], lane, dst, a.nrows);
+            ami::wave_store2(acc[2][f], acc[3][f], lane, dst + 2 * a.nrows, a.nrows);
         }
     }
 }
@@ -396,18 +404,19 @@ __device__ __forceinline__ void mc_block(const KArgs &a, double *red) {
 // the denominators are linear in E, so leaf_args and den_args serve the real
 // and the imaginary parts alike; the leaves are complex (leaf_complex) and so
 // are the group sums FT_g, each multiplied by R_g in complex arithmetic.
-__device__ __forceinline__ void cfwd_tile(const KArgs &a, int64_t tile, double *red) {
-    const int tid = threadIdx.x, B = blockDim.x;
+__device__ __forceinline__ void cfwd_tile(const KArgs &a, int64_t tile) {
+    const int tid = threadIdx.x, B = blockDim.x, lane = tid & 63;
+    const int64_t row = tile * (B >> 6) + (tid >> 6);
     const int64_t s = tile * B + tid;
     const bool active = s < a.n_e;
     const int64_t sc = active ? s : a.n_e - 1;
 
     double Er[NE], Ei[NE];
-    const double *row = a.energies + 2 * sc * a.stride_s;
+    const double *erow = a.energies + 2 * sc * a.stride_s;
 #pragma unroll
     for (int i = 0; i < NE; ++i) {
-        Er[i] = row[2 * i * a.stride_i];
-        Ei[i] = row[2 * i * a.stride_i + 1];
+        Er[i] = erow[2 * i * a.stride_i];
+        Ei[i] = erow[2 * i * a.stride_i + 1];
     }
     double FTr[G], FTi[G], dEi[D];
     {
@@ -449,8 +458,8 @@ __device__ __forceinline__ void cfwd_tile(const KArgs &a, int64_t tile, double *
             reinterpret_cast<double2 *>(a.out)[static_cast<int64_t>(f) * a.n_e + s] = v;
         }
         if (a.partial)
-            ami::block_sum2(active ? acc_re : 0.0, active ? acc_im : 0.0, red, tid, B,
-                            a.partial + (tile * a.n_f + f) * 2);
+            ami::wave_store2(active ? acc_re : 0.0, active ? acc_im : 0.0, lane, a.partial + 2 * f * a.nrows + row,
+                             a.nrows);
     }
 }
 #endif
@@ -462,8 +471,7 @@ __device__ __forceinline__ void cfwd_tile(const KArgs &a, int64_t tile, double *
 // integrator (4), the forward at complex energies (8), or a sum of them
 #if AMI_JIT_KERNELS & 1
 extern "C" __global__ __launch_bounds__(AMI_JIT_BLOCK) void ami_jit_fwd(ami::KArgs a) {
-    __shared__ double red[2 * (AMI_JIT_BLOCK / 64)];
-    amijit::fwd_tile<AMI_JIT_HUB>(a, blockIdx.x, red);
+    amijit::fwd_tile<AMI_JIT_HUB>(a, blockIdx.x);
 }
 #endif
 
@@ -475,22 +483,19 @@ extern "C" __global__ __launch_bounds__(AMI_JIT_BLOCK) void ami_jit_fwd(ami::KAr
 #endif
 
 extern "C" __global__ __launch_bounds__(AMI_JIT_BLOCK) AMI_JIT_ADJ_ATTR void ami_jit_adj(ami::KArgs a) {
-    __shared__ double red[2 * (AMI_JIT_BLOCK / 64)];
     __shared__ double park[amijit::kParkCols > 0 ? amijit::kParkCols * AMI_JIT_BLOCK : 1];
-    amijit::adj_tile<AMI_JIT_HUB>(a, blockIdx.x, red, park);
+    amijit::adj_tile<AMI_JIT_HUB>(a, blockIdx.x, park);
 }
 #endif
 
 #if AMI_JIT_KERNELS & 4
 extern "C" __global__ __launch_bounds__(AMI_JIT_BLOCK) void ami_jit_mc(ami::KArgs a) {
-    __shared__ double red[2 * (AMI_JIT_BLOCK / 64)];
-    amijit::mc_block<AMI_JIT_HUB>(a, red);
+    amijit::mc_block<AMI_JIT_HUB>(a);
 }
 #endif
 
 #if AMI_JIT_KERNELS & 8
 extern "C" __global__ __launch_bounds__(AMI_JIT_BLOCK) void ami_jit_cfwd(ami::KArgs a) {
-    __shared__ double red[2 * (AMI_JIT_BLOCK / 64)];
-    amijit::cfwd_tile(a, blockIdx.x, red);
+    amijit::cfwd_tile(a, blockIdx.x);
 }
 #endif

@@ -36,6 +36,9 @@ struct KArgs {
     // 16-byte accesses allowed: bit 0 the momentum rows (k 16-byte aligned,
     // stride_k even), bit 1 the rows of grad_k
     int vec_io;
+    // rows of the specialized kernels' partial sums (one per wave), stored
+    // column by column: element (row r, column c) at [c * nrows + r]
+    int64_t nrows;
 };
 
 // Frequency rows one Monte-Carlo launch accumulates (the caller splits longer lists).

@@ -122,18 +122,25 @@ def test_source_limits_and_errors():
     assert e.value.code == -7
 
 
-def test_hiprtc_compiles_the_generated_source(tmp_path, monkeypatch):
-    """amiTermsSpecialize compiles for gfx950 before it needs a device; here
-    (no GPU) it then stops at the device query, leaving the code object and
-    its source in the disk cache.  A second handle finds them there."""
+@pytest.mark.parametrize("momentum,kernels", [(True, (1, 2)), (False, (1, 2, 8))])
+def test_hiprtc_compiles_the_generated_source(tmp_path, monkeypatch, momentum, kernels):
+    """amiTermsSpecialize compiles every kernel of the input for gfx950 before
+    it needs a device (the complex-energy forward too, for the energy input);
+    here (no GPU) it then stops at the device query, leaving the code objects
+    and their sources in the disk cache.  A second handle finds them there."""
     monkeypatch.setenv("AMIGPU_CACHE_DIR", str(tmp_path))
     d = random_self_energy(3, (0, 3, 0))
     for _ in range(2):
         T = amd.Terms.from_diagram(d)
         try:
-            T.specialize(momentum=True)
+            T.specialize(momentum=momentum)
         except amd.AmiError as e:
             assert e.code == -5 and "hipGetDevice" in str(e), str(e)
-    objs = sorted(p.name for p in tmp_path.iterdir())
-    assert len(objs) == 2 and objs[0].endswith(".hip") and objs[1].endswith(".hsaco")
-    assert (tmp_path / objs[1]).stat().st_size > 1000
+    srcs = sorted(p for p in tmp_path.iterdir() if p.name.endswith(".hip"))
+    objs = sorted(p for p in tmp_path.iterdir() if p.name.endswith(".hsaco"))
+    assert len(srcs) == len(objs) == len(kernels)
+    for p in objs:
+        assert p.stat().st_size > 1000
+    # one code object per kernel: forward 1, adjoint 2, complex-energy forward 8
+    found = sorted(k for p in srcs for k in kernels if f"#define AMI_JIT_KERNELS {k}\n" in p.read_text())
+    assert found == sorted(kernels)
