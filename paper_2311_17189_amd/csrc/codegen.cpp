@@ -141,6 +141,49 @@ std::string jit_source(const AmiTerms *t, bool hub, int kernels) {
     }
     o << "}\n";
 
+    // sin and cos of the line momenta from those of the loop momenta and of
+    // q (adjoint): K_j = sum of +-k_l (+-q), folded term by term with
+    // sin(A +- b) = sin A cos b +- cos A sin b, cos(A +- b) = cos A cos b -+ sin A sin b
+    o << "__device__ __forceinline__ void line_trig(const double (&sx)[" << NIA << "], const double (&cx)[" << NIA
+      << "], const double (&sy)[" << NIA << "], const double (&cy)[" << NIA
+      << "], const double *qs, const double *qc, double (&Sx)[" << NGA << "], double (&Cx)[" << NGA
+      << "], double (&Sy)[" << NGA << "], double (&Cy)[" << NGA << "]) {\n";
+    if (hub) {
+        o << "  double nS;\n";
+        for (int j = 0; j < ng; ++j)
+            for (int comp = 0; comp < 2; ++comp) {
+                std::vector<std::pair<int, std::pair<std::string, std::string>>> terms;
+                for (int l = 0; l < ni; ++l) {
+                    const int a = static_cast<int>(tb.line_alpha[static_cast<size_t>(j) * nf + l]);
+                    if (a) terms.push_back({a, {idx(comp ? "sy" : "sx", l), idx(comp ? "cy" : "cx", l)}});
+                }
+                for (int x = 0; x < nx; ++x) {
+                    const int a = static_cast<int>(tb.line_alpha[static_cast<size_t>(j) * nf + ni + x]);
+                    if (a) terms.push_back({a, {idx("qs", 2 * x + comp), idx("qc", 2 * x + comp)}});
+                }
+                const std::string S = idx(comp ? "Sy" : "Sx", j), C = idx(comp ? "Cy" : "Cx", j);
+                if (terms.empty()) {
+                    o << "  " << S << " = 0.0; " << C << " = 1.0;\n";
+                    continue;
+                }
+                for (size_t k = 0; k < terms.size(); ++k) {
+                    const int sg = terms[k].first;
+                    const std::string &sb = terms[k].second.first, &cb = terms[k].second.second;
+                    if (k == 0) {
+                        o << "  " << S << " = " << (sg > 0 ? "" : "-") << sb << "; " << C << " = " << cb << ";\n";
+                    } else if (sg > 0) {
+                        o << "  nS = fma(" << S << ", " << cb << ", " << C << " * " << sb << "); " << C << " = fma("
+                          << C << ", " << cb << ", -(" << S << " * " << sb << ")); " << S << " = nS;\n";
+                    } else {
+                        o << "  nS = fma(" << S << ", " << cb << ", -(" << C << " * " << sb << ")); " << C
+                          << " = fma(" << C << ", " << cb << ", " << S << " * " << sb << "); " << S << " = nS;\n";
+                    }
+                }
+            }
+        o << "  (void)nS;\n";
+    }
+    o << "  (void)sx; (void)cx; (void)sy; (void)cy; (void)qs; (void)qc; (void)Sx; (void)Cx; (void)Sy; (void)Cy;\n}\n";
+
     // leaf arguments x_l = sum_i c_li E_i
     o << "__device__ __forceinline__ void leaf_args(const double (&E)[NE], double (&x)[L]) {\n";
     for (int l = 0; l < L; ++l) {

@@ -604,10 +604,13 @@ void set_momenta(KArgs &a, const AmiTerms *t, const double *k, int64_t stride_k,
     a.stride_k = stride_k;
     a.q_big = 0;
     if (k && (reinterpret_cast<uintptr_t>(k) & 15u) == 0 && (stride_k & 1) == 0) a.vec_io |= 1;
-    for (int x = 0; x < t->n_ext && x < kMaxExtDev; ++x) {
-        a.q[2 * x] = std::remainder(q[2 * x], 2.0 * M_PI);
-        a.q[2 * x + 1] = std::remainder(q[2 * x + 1], 2.0 * M_PI);
-    }
+    for (int x = 0; x < t->n_ext && x < kMaxExtDev; ++x)
+        for (int c = 0; c < 2; ++c) {
+            const double r = std::remainder(q[2 * x + c], 2.0 * M_PI);
+            a.q[2 * x + c] = r;
+            a.qs[2 * x + c] = std::sin(r);
+            a.qc[2 * x + c] = std::cos(r);
+        }
     a.hop_t = hop_t;
     a.mu = mu;
 }

@@ -7,6 +7,7 @@
 // (external slots), L (distinct leaves), D (distinct denominators), G (groups),
 // the leaf kinds kBose[L], and the functions
 //   lines            K_j = sum_l alpha_jl k_l (+ external q), per component
+//   line_trig        sin K_j, cos K_j from those of the k_l and q by angle addition
 //   leaf_args        x_l = sum_i c_li E_i                        (Sec. 2.2)
 //   taylor_leaves    f_l -> its Taylor coefficient T_j (poles of higher order, Eq. (5))
 //   group_sums_c     the group sums at complex leaves (complex energies)
@@ -43,7 +44,9 @@ constexpr int kParkCols = kParkChain + (kParkDv ? L : 0);
 // E from the sample's energies or momenta.  With KEEP (adjoint, momentum
 // input) sin K_jx, sin K_jy and cos K_jx + cos K_jy, needed only by the final
 // chain rule, are parked in LDS columns (park[(c NG + j) B + tid], c = 0, 1, 2)
-// rather than held in registers through the frequency loop.
+// rather than held in registers through the frequency loop; they come from
+// sin and cos of the loop momenta by angle addition (line_trig), 2 NI
+// reduced sin/cos pairs instead of 2 NG.
 // E_j = 2t(cos K_jx + cos K_jy) + mu (Sec. 5.2) from momenta in [-pi, pi]
 __device__ __forceinline__ void energies_from(const KArgs &a, const double (&kx)[NIA], const double (&ky)[NIA],
                                               double (&E)[NE]) {
@@ -77,24 +80,22 @@ __device__ __forceinline__ void energies(const KArgs &a, int64_t sc, double (&E)
             energies_from(a, kx, ky, E);
             return;
         }
-        double Kx[NGA], Ky[NGA];
-        lines(kx, ky, a.q, Kx, Ky);
+        // sin and cos of the loop momenta, then of the lines by angle addition
+        double sx[NIA], cx[NIA], sy[NIA], cy[NIA], Sx[NGA], Cx[NGA], Sy[NGA], Cy[NGA];
+#pragma unroll
+        for (int l = 0; l < NI; ++l) {
+            ami::sincos_red(kx[l], sx[l], cx[l]);
+            ami::sincos_red(ky[l], sy[l], cy[l]);
+        }
+        line_trig(sx, cx, sy, cy, a.qs, a.qc, Sx, Cx, Sy, Cy);
+        const int tid = threadIdx.x, B = blockDim.x;
 #pragma unroll
         for (int j = 0; j < NG; ++j) {
-            double cx, cy;
-            if constexpr (KEEP) {
-                double sx, sy;
-                ami::sincos_red(Kx[j], sx, cx);
-                ami::sincos_red(Ky[j], sy, cy);
-                const int tid = threadIdx.x, B = blockDim.x;
-                park[j * B + tid] = sx;
-                park[(NG + j) * B + tid] = sy;
-                park[(2 * NG + j) * B + tid] = cx + cy;
-            } else {
-                cx = ami::cos_red(Kx[j]);
-                cy = ami::cos_red(Ky[j]);
-            }
-            E[j] = fma(2.0 * a.hop_t, cx + cy, a.mu);
+            const double cs = Cx[j] + Cy[j];
+            park[j * B + tid] = Sx[j];
+            park[(NG + j) * B + tid] = Sy[j];
+            park[(2 * NG + j) * B + tid] = cs;
+            E[j] = fma(2.0 * a.hop_t, cs, a.mu);
         }
     } else {
         const double *row = a.energies + sc * a.stride_s;

@@ -16,6 +16,7 @@ struct KArgs {
     const double *k;
     int64_t stride_k;
     double q[2 * kMaxExtDev];
+    double qs[2 * kMaxExtDev], qc[2 * kMaxExtDev];   // sin q, cos q (set on the host)
     int q_big;                  // unused (q is reduced modulo 2 pi on the host)
     double hop_t, mu;
     const double *ext_freqs;

@@ -132,6 +132,18 @@ def _momentum_flops(line_alpha, n_int: int, sincos: bool) -> int:
     return total
 
 
+def _momentum_flops_added(line_alpha, n_int: int) -> int:
+    """The specialized adjoint's energies from momenta: the loop momenta
+    reduced mod 2 pi, sin and cos of each loop component, then sin and cos of
+    every line component by angle addition (each further term: two products
+    and two FMAs, 6 FLOPs; sin and cos of q come from the host), and
+    E_j = 2t(cos K_jx + cos K_jy) + mu."""
+    total = 2 * n_int * (C_RED2PI + C_SINCOS)
+    for row in np.asarray(line_alpha):
+        total += 2 * 6 * max(_nnz(row) - 1, 0) + 3
+    return total
+
+
 def _den_flops(st: Structure) -> int:
     total = 0
     for e, a in st.dens:
@@ -231,7 +243,8 @@ def specialized_adjoint_flops(st: Structure, n_e: int, n_f: int, line_alpha=None
     per distinct denominator the sum of its u_g, one complex product and the
     scatter to energies and frequencies; per term the prefix/suffix products
     of its leaves; per leaf its derivative, the scatter to energies and beta;
-    on the momentum path the chain rule through -2t sin K."""
+    on the momentum path sin and cos of the lines by angle addition and the
+    chain rule through -2t sin K."""
     n = st.n_int
     per_sample = _spec_leaves(st, True) + _spec_group_sums(st)
     per_sample += sum(n_terms * (4 * n - 4) for n_terms, _ in st.groups)   # leaf cotangents
@@ -239,7 +252,7 @@ def specialized_adjoint_flops(st: Structure, n_e: int, n_f: int, line_alpha=None
         per_sample += max(_nnz(e) - 1, 0) + (1 if sigma == -1 else 0)    # x recomputed
         per_sample += 4 + _nnz(e)                                         # f' FB, beta, d/dbeta, scatter
     if line_alpha is not None:
-        per_sample += _momentum_flops(line_alpha, n, sincos=True)
+        per_sample += _momentum_flops_added(line_alpha, n)
         for row in np.asarray(line_alpha)[:, :n]:
             per_sample += 8 + 2 * _nnz(row)                               # mu, t, -2t sin K, d/dk
     per_point = _spec_dens(st)

@@ -1,7 +1,7 @@
 // Host check of the generated part of the specialized evaluator: the
 // diagram's straight-line functions (leaf_args, group_sums, den_args,
 // group_products, den_cotangents, den_scatter, leaf_cotangents, leaf_scatter,
-// lines, line_scatter, taylor_leaves) compiled with a host compiler and driven one sample at
+// line_trig, line_scatter, taylor_leaves) compiled with a host compiler and driven one sample at
 // a time through the same steps as the device kernels, so a test can compare
 // values and gradients with the oracle.  The generated source is included
 // through AMI_GENERATED without its two #include lines.
@@ -46,15 +46,24 @@ int main() {
                 kx[l] = ami::reduce_2pi(a);
                 ky[l] = ami::reduce_2pi(b);
             }
-            double qr[2 * NXA];
-            for (int x = 0; x < 2 * NXA; ++x) qr[x] = ami::reduce_2pi(q[x]);
-            lines(kx, ky, qr, Kx, Ky);
+            double qr[2 * NXA], qs[2 * NXA], qc[2 * NXA];
+            for (int x = 0; x < 2 * NXA; ++x) {
+                qr[x] = ami::reduce_2pi(q[x]);
+                qs[x] = std::sin(qr[x]);
+                qc[x] = std::cos(qr[x]);
+            }
+            (void)Kx;
+            (void)Ky;
+            // as the adjoint kernel: sin/cos of the loop momenta, lines by angle addition
+            double lsx[NIA], lcx[NIA], lsy[NIA], lcy[NIA], Cx[NGA], Cy[NGA];
+            for (int l = 0; l < NI; ++l) {
+                ami::sincos_red(kx[l], lsx[l], lcx[l]);
+                ami::sincos_red(ky[l], lsy[l], lcy[l]);
+            }
+            line_trig(lsx, lcx, lsy, lcy, qs, qc, sx, Cx, sy, Cy);
             for (int j = 0; j < NG; ++j) {
-                double cx, cy;
-                ami::sincos_red(Kx[j], sx[j], cx);
-                ami::sincos_red(Ky[j], sy[j], cy);
-                cs[j] = cx + cy;
-                E[j] = std::fma(2.0 * t, cx + cy, mu);
+                cs[j] = Cx[j] + Cy[j];
+                E[j] = std::fma(2.0 * t, cs[j], mu);
             }
         } else {
             for (int i = 0; i < NE; ++i)
