@@ -287,52 +287,53 @@ __device__ __forceinline__ void combo_adj(uint32_t pos, uint32_t neg, double v, 
     }
 }
 
-// A double moved across lanes by one DPP control, as two 32-bit halves; lanes
-// whose row is outside ROW_MASK, or whose source lane is outside the row,
-// receive 0.
-template <int CTRL, int ROW_MASK>
+// A double moved across lanes by one DPP control (all rows and banks, bound
+// control on: a lane whose source lane falls outside the wave or the row
+// receives 0), as two 32-bit halves.
+template <int CTRL>
 __device__ __forceinline__ double dpp_move(double v) {
     const unsigned long long u = __builtin_bit_cast(unsigned long long, v);
-    const int lo = __builtin_amdgcn_update_dpp(0, static_cast<int>(static_cast<unsigned>(u)), CTRL, ROW_MASK, 0xf,
-                                               false);
-    const int hi = __builtin_amdgcn_update_dpp(0, static_cast<int>(static_cast<unsigned>(u >> 32)), CTRL, ROW_MASK,
-                                               0xf, false);
+    const int lo = __builtin_amdgcn_mov_dpp(static_cast<int>(static_cast<unsigned>(u)), CTRL, 0xf, 0xf, true);
+    const int hi = __builtin_amdgcn_mov_dpp(static_cast<int>(static_cast<unsigned>(u >> 32)), CTRL, 0xf, 0xf, true);
     return __builtin_bit_cast(double, (static_cast<unsigned long long>(static_cast<unsigned>(hi)) << 32) |
                                           static_cast<unsigned>(lo));
 }
 
-// Sum over the 64 lanes of a wave (every lane active), returned in every
-// lane: inclusive prefix sums within each row of 16 lanes (row_shr 1, 2, 4,
-// 8), then the total of row 0 added into row 1 and of row 2 into row 3
-// (row_bcast:15), then lane 31 into rows 2-3 (row_bcast:31); lane 63 then
-// holds the total, which readlane broadcasts.  Register moves only: no LDS
-// round trips and no waits.
+// Sum over the 64 lanes of a wave (every lane active), left in lane 63:
+// inclusive prefix sums within each row of 16 lanes (row_shr 1, 2, 4, 8), so
+// lane 15 of row r holds the row's sum S_r; row_bcast:15 then adds lane 15 of
+// the previous row (lane 63: S_3 + S_2), and row_bcast:31 adds lane 31 (by then
+// S_1 + S_0) into rows 2-3.  Register moves only: no LDS round trips, no waits.
+__device__ __forceinline__ double wave_sum_lane63(double v) {
+    v += dpp_move<0x111>(v);   // row_shr:1
+    v += dpp_move<0x112>(v);   // row_shr:2
+    v += dpp_move<0x114>(v);   // row_shr:4
+    v += dpp_move<0x118>(v);   // row_shr:8
+    v += dpp_move<0x142>(v);   // row_bcast:15
+    v += dpp_move<0x143>(v);   // row_bcast:31
+    return v;
+}
+
+// The same sum broadcast to every lane (readlane of lane 63).
 __device__ __forceinline__ double wave_sum(double v) {
-    v += dpp_move<0x111, 0xf>(v);   // row_shr:1
-    v += dpp_move<0x112, 0xf>(v);   // row_shr:2
-    v += dpp_move<0x114, 0xf>(v);   // row_shr:4
-    v += dpp_move<0x118, 0xf>(v);   // row_shr:8
-    v += dpp_move<0x142, 0xa>(v);   // row_bcast:15
-    v += dpp_move<0x143, 0xc>(v);   // row_bcast:31
-    const unsigned long long u = __builtin_bit_cast(unsigned long long, v);
+    const unsigned long long u = __builtin_bit_cast(unsigned long long, wave_sum_lane63(v));
     const unsigned lo = static_cast<unsigned>(__builtin_amdgcn_readlane(static_cast<int>(static_cast<unsigned>(u)), 63));
     const unsigned hi = static_cast<unsigned>(__builtin_amdgcn_readlane(static_cast<int>(static_cast<unsigned>(u >> 32)), 63));
     return __builtin_bit_cast(double, (static_cast<unsigned long long>(hi) << 32) | lo);
 }
 
-// The wave's totals of (vr, vi), stored by its first lane at dst[0] and
+// The wave's totals of (vr, vi), stored by its last lane at dst[0] and
 // dst[stride]: the per-wave partial sums of the specialized kernels (no LDS,
 // no barrier).
 __device__ __forceinline__ void wave_store2(double vr, double vi, int lane, double *dst, int64_t stride) {
-    vr = wave_sum(vr);
-    vi = wave_sum(vi);
-    if (lane == 0) {
+    vr = wave_sum_lane63(vr);
+    vi = wave_sum_lane63(vi);
+    if (lane == 63) {
         dst[0] = vr;
         dst[stride] = vi;
     }
 }
 
-// Block sum of (vr, vi) into dst[0..1], deterministic; every lane must call it.
 __device__ __forceinline__ void block_sum2(double vr, double vi, double *red, int tid, int B, double *dst) {
     vr = wave_sum(vr);
     vi = wave_sum(vi);

@@ -56,25 +56,42 @@ __device__ __forceinline__ void energies_from(const KArgs &a, const double (&kx)
     for (int j = 0; j < NG; ++j) E[j] = fma(2.0 * a.hop_t, ami::cos_red(Kx[j]) + ami::cos_red(Ky[j]), a.mu);
 }
 
-template <bool HUB, bool KEEP>
-__device__ __forceinline__ void energies(const KArgs &a, int64_t sc, double (&E)[NE], double *park) {
+// The sample's raw inputs: its 2 NI momentum components (momentum input) or
+// its NE energies.  Loaded apart from their use so that a kernel can issue
+// the loads of a later tile before the arithmetic of the current one.
+constexpr int NIN = AMI_JIT_HUB ? 2 * NIA : NE;
+
+template <bool HUB>
+__device__ __forceinline__ void load_inputs(const KArgs &a, int64_t sc, double (&in)[NIN]) {
     if constexpr (HUB) {
-        // E_j = 2t(cos K_jx + cos K_jy) + mu (Sec. 5.2), momenta reduced into [-pi, pi]
-        double kx[NIA], ky[NIA];
         const double *row = a.k + sc * a.stride_k;
         if (a.vec_io & 1) {              // one 16-byte load per loop
 #pragma unroll
             for (int l = 0; l < NI; ++l) {
                 const double2 v = reinterpret_cast<const double2 *>(row)[l];
-                kx[l] = ami::reduce_2pi(v.x);
-                ky[l] = ami::reduce_2pi(v.y);
+                in[2 * l] = v.x;
+                in[2 * l + 1] = v.y;
             }
         } else {
 #pragma unroll
-            for (int l = 0; l < NI; ++l) {
-                kx[l] = ami::reduce_2pi(row[2 * l]);
-                ky[l] = ami::reduce_2pi(row[2 * l + 1]);
-            }
+            for (int l = 0; l < 2 * NI; ++l) in[l] = row[l];
+        }
+    } else {
+        const double *row = a.energies + sc * a.stride_s;
+#pragma unroll
+        for (int i = 0; i < NE; ++i) in[i] = row[i * a.stride_i];
+    }
+}
+
+template <bool HUB, bool KEEP>
+__device__ __forceinline__ void energies(const KArgs &a, const double (&in)[NIN], double (&E)[NE], double *park) {
+    if constexpr (HUB) {
+        // E_j = 2t(cos K_jx + cos K_jy) + mu (Sec. 5.2), momenta reduced into [-pi, pi]
+        double kx[NIA], ky[NIA];
+#pragma unroll
+        for (int l = 0; l < NI; ++l) {
+            kx[l] = ami::reduce_2pi(in[2 * l]);
+            ky[l] = ami::reduce_2pi(in[2 * l + 1]);
         }
         if constexpr (!KEEP) {
             energies_from(a, kx, ky, E);
@@ -98,10 +115,16 @@ __device__ __forceinline__ void energies(const KArgs &a, int64_t sc, double (&E)
             E[j] = fma(2.0 * a.hop_t, cs, a.mu);
         }
     } else {
-        const double *row = a.energies + sc * a.stride_s;
 #pragma unroll
-        for (int i = 0; i < NE; ++i) E[i] = row[i * a.stride_i];
+        for (int i = 0; i < NE; ++i) E[i] = in[i];
     }
+}
+
+template <bool HUB, bool KEEP>
+__device__ __forceinline__ void energies(const KArgs &a, int64_t sc, double (&E)[NE], double *park) {
+    double in[NIN];
+    load_inputs<HUB>(a, sc, in);
+    energies<HUB, KEEP>(a, in, E, park);
 }
 
 __device__ __forceinline__ void load_freq(const KArgs &a, int f, double (&wr)[NXA], double (&wi)[NXA]) {
@@ -179,15 +202,14 @@ __device__ __forceinline__ void fwd_tile(const KArgs &a, int64_t tile) {
 // The leaf arguments x_l are recomputed after the frequency loop instead of
 // being kept live through it.
 template <bool HUB>
-__device__ __forceinline__ void adj_tile(const KArgs &a, int64_t blk, double *park) {
+__device__ __forceinline__ void adj_tile(const KArgs &a, int64_t blk, double *park, const double (&in)[NIN]) {
     const int tid = threadIdx.x, B = blockDim.x, lane = tid & 63;
     const int64_t row = blk * (B >> 6) + (tid >> 6);
     const int64_t s = blk * B + tid;
     const bool active = s < a.n_e;
-    const int64_t sc = active ? s : a.n_e - 1;
 
     double E[NE];
-    energies<HUB, HUB>(a, sc, E, park);
+    energies<HUB, HUB>(a, in, E, park);
     double F[L], Dv[kParkDv ? 1 : L];
     {
         double x[L];
@@ -485,7 +507,10 @@ extern "C" __global__ __launch_bounds__(AMI_JIT_BLOCK) void ami_jit_fwd(ami::KAr
 
 extern "C" __global__ __launch_bounds__(AMI_JIT_BLOCK) AMI_JIT_ADJ_ATTR void ami_jit_adj(ami::KArgs a) {
     __shared__ double park[amijit::kParkCols > 0 ? amijit::kParkCols * AMI_JIT_BLOCK : 1];
-    amijit::adj_tile<AMI_JIT_HUB>(a, blockIdx.x, park);
+    const int64_t s = static_cast<int64_t>(blockIdx.x) * AMI_JIT_BLOCK + threadIdx.x;
+    double in[amijit::NIN];
+    amijit::load_inputs<AMI_JIT_HUB>(a, s < a.n_e ? s : a.n_e - 1, in);
+    amijit::adj_tile<AMI_JIT_HUB>(a, blockIdx.x, park, in);
 }
 #endif
 

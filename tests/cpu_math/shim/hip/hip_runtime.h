@@ -14,6 +14,6 @@ using std::fmax;
 using std::fmin;
 inline double __shfl_xor(double v, int, int) { return v; }
 // one lane per "wave" on the host: cross-lane moves return the lane's own value
-inline int __builtin_amdgcn_update_dpp(int, int src, int, int, int, bool) { return src; }
+inline int __builtin_amdgcn_mov_dpp(int src, int, int, int, bool) { return src; }
 inline int __builtin_amdgcn_readlane(int v, int) { return v; }
 inline void __syncthreads() {}
