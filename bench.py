@@ -205,6 +205,99 @@ def batch_section(args, torch, dev):
     }
 
 
+def _timed_kernel(torch, amd, stream, fn, reps):
+    """(ms per call between stream events, mean kernel ms from the library's
+    dispatch events) over `reps` calls after one warm call."""
+    fn()
+    torch.cuda.synchronize()
+    amd.kernel_timer_start(reps)
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    for _ in range(reps):
+        fn()
+    e1.record(stream)
+    torch.cuda.synchronize()
+    ks = amd.kernel_timer_stop()
+    return e0.elapsed_time(e1) / reps, sum(ks) / len(ks)
+
+
+def next_rows_section(args, torch, dev, stream):
+    """The rows built beyond the main path, each measured on the order-4
+    workload: complex energies (forward, energy input), poles of higher order
+    (the order-4 topology with one internal line taken twice, momentum input,
+    forward) and graph input (label + construct from the 4-column form)."""
+    import numpy as np
+
+    import paper_2311_17189_amd as amd
+    from ami_inputs import DEFAULT_Q, complex_energies, k_samples, matsubara_freqs, random_self_energy
+    from paper_2311_17189_amd import roofline as rl
+
+    res = {}
+    d = random_self_energy(args.order, (0, args.order, args.diagram))
+    n_e, reps = args.n_e, max(5, args.steps // 2)
+    w = torch.from_numpy(matsubara_freqs(1, args.beta)).to(dev)
+    # complex energies: |beta Im x| below pi/2 for every leaf
+    try:
+        T = amd.Terms.from_diagram(d)
+        st = rl.structure_from_canonical(T.canonical())
+        eta = 0.25 / (args.beta * d.n_int)
+        E = torch.from_numpy(complex_energies(n_e, d.n_eps, seed=(101, args.order, args.diagram),
+                                              a=3.0, eta=eta)).to(dev)
+        out = torch.empty((1, n_e), dtype=torch.complex128, device=dev)
+        osum = torch.empty((1,), dtype=torch.complex128, device=dev)
+        ms, kms = _timed_kernel(torch, amd, stream, lambda: amd.evaluate_complex(
+            T, E, w, args.beta, out=out, out_sum=osum, want_sum=True, stream=stream), reps)
+        fl = rl.specialized_complex_forward_flops(st, n_e, 1)
+        res["complex_energies"] = {
+            "workload": f"order-{args.order} topology {args.diagram}, {n_e} complex energy rows "
+                        f"(Re uniform in (-3, 3), |Im| < {eta:.3g}), 1 Matsubara frequency, out + row sum",
+            "kernel": amd.last_variant(), "ms": ms, "kernel_ms": kms,
+            "term_evals_per_s": float(st.T) * n_e / (ms * 1e-3),
+            "flops_per_launch": fl["total"], "frac_fp64_peak": fl["total"] / (kms * 1e-3) / rl.PEAK_FP64_VECTOR}
+    except amd.AmiError as e:
+        res["complex_energies"] = f"not run: {e}"
+    # poles of higher order: one internal line repeated, its energy slot unused
+    try:
+        j = [r for r in range(d.alpha.shape[0]) if np.any(d.alpha[r, :d.n_int])][0]
+        ng = d.alpha.shape[0]
+        alpha = np.vstack([d.alpha, d.alpha[j:j + 1]])
+        eps = np.eye(ng + 1, dtype=np.int8)
+        eps[ng] = 0
+        eps[ng, j] = 1
+        T = amd.Terms(alpha, eps, d.n_int, d.fermionic, multipole=True)
+        T.specialize(momentum=True)
+        st = rl.structure_from_canonical(T.canonical())
+        k = torch.from_numpy(k_samples(n_e, d.n_int, seed=(102, args.order, args.diagram))).to(dev)
+        q = np.array(DEFAULT_Q)
+        out = torch.empty((1, n_e), dtype=torch.complex128, device=dev)
+        osum = torch.empty((1,), dtype=torch.complex128, device=dev)
+        ms, kms = _timed_kernel(torch, amd, stream, lambda: amd.evaluate_hubbard(
+            T, k, q, 1.0, 0.0, w, args.beta, out=out, out_sum=osum, want_sum=True, stream=stream), reps)
+        fl = rl.specialized_forward_flops(st, n_e, 1, alpha)
+        orders = sorted({abs(c) - 1 for c, _ in st.leaves})
+        res["multipole"] = {
+            "workload": f"order-{args.order} topology {args.diagram} with line {j} taken twice (double poles), "
+                        f"{n_e} k-samples, 1 Matsubara frequency, out + row sum",
+            "terms": st.T, "leaf_orders": orders, "kernel": amd.last_variant(), "ms": ms, "kernel_ms": kms,
+            "term_evals_per_s": float(st.T) * n_e / (ms * 1e-3),
+            "flops_per_launch": fl["total"], "frac_fp64_peak": fl["total"] / (kms * 1e-3) / rl.PEAK_FP64_VECTOR}
+    except amd.AmiError as e:
+        res["multipole"] = f"not run: {e}"
+    # graph input: label and construct, host only
+    g = {}
+    for order, i in ((args.order, args.diagram), (6, 0)):
+        dd = random_self_energy(order, (0, order, i))
+        n = 20
+        t0 = time.perf_counter()
+        for _ in range(n):
+            amd.Terms.from_graph(dd.graph).close()
+        g[f"order{order}"] = {"construct_ms": (time.perf_counter() - t0) * 1e3 / n,
+                              "terms": amd.Terms.from_graph(dd.graph).info()["T"]}
+    res["graph_construct"] = g
+    return res
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -485,6 +578,7 @@ def main():
         "specialize_ms": specialize_ms, "specialize": specialize_note,
         "wall_s": wall,
     }
+    res["next_rows"] = next_rows_section(args, torch, dev, stream)
     if not args.no_batch:
         res["batch"] = batch_section(args, torch, dev)
     if args.cpu_seconds > 0:

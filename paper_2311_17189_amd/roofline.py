@@ -18,6 +18,7 @@ compares and conversions 0):
     reciprocal (estimate + two Newton steps)          9
     leaf f(y) with its mirror f(-y), Fermi / Bose    47 / 49
     leaf derivative f'(y)                            48
+    leaf at a complex argument, Fermi / Bose        112 / 135
 
 Two models: ``forward_flops``/``adjoint_flops`` for the table-driven (packed)
 kernels and ``specialized_forward_flops``/``specialized_adjoint_flops`` for the
@@ -41,6 +42,8 @@ C_RCP = 9
 C_LEAF_FERMI = 47
 C_LEAF_BOSE = 49
 C_LEAF_DERIV = 48
+C_LEAF_C_FERMI = 112    # leaf at a complex argument (leaf_complex), Fermi / Bose-type
+C_LEAF_C_BOSE = 135
 
 PEAK_FP64_VECTOR = 78.6e12     # 256 CUs x 2.4 GHz x 128 FP64 FLOP/clk
 PEAK_HBM = 8.0e12              # bytes/s
@@ -59,22 +62,31 @@ class Structure:
 
 def structure_from_canonical(stream) -> Structure:
     """Distinct leaves, distinct denominators and denominator groups of the
-    canonical term stream (layout of ``amiTermsCanonical``)."""
+    canonical term stream (layout of ``amiTermsCanonical``; with T written as
+    -T every term's denominator count follows its prefactor).  Leaves keep
+    their codes (sigma (1 + j) for Taylor coefficients)."""
     s = [int(x) for x in np.asarray(stream).reshape(-1)]
     n_int, n_eps, n_freq, T = s[:4]
+    extended = T < 0
+    T = abs(T)
     per_den = n_eps + n_freq
     per_leaf = 1 + n_eps
-    per_term = (len(s) - 4) // T if T else 0
-    dpt = (per_term - 1 - n_int * per_leaf) // per_den if T else 0
+    dpt = 0
+    if T and not extended:
+        dpt = ((len(s) - 4) // T - 1 - n_int * per_leaf) // per_den
     pos = 4
     leaves, dens, groups = {}, {}, {}
     for _ in range(T):
         pos += 1
+        nd = dpt
+        if extended:
+            nd = s[pos]
+            pos += 1
         for _ in range(n_int):
             leaves[(s[pos], tuple(s[pos + 1:pos + per_leaf]))] = True
             pos += per_leaf
         gk = []
-        for _ in range(dpt):
+        for _ in range(nd):
             e = tuple(s[pos:pos + n_eps])
             a = tuple(s[pos + n_eps + n_int:pos + per_den])
             dens[(e, a)] = True
@@ -84,7 +96,7 @@ def structure_from_canonical(stream) -> Structure:
         groups[gk] = groups.get(gk, 0) + 1
     return Structure(n_int=n_int, n_eps=n_eps, n_freq=n_freq, T=T,
                      leaves=list(leaves), dens=list(dens),
-                     groups=[(c, dpt) for c in groups.values()])
+                     groups=[(c, len(gk)) for gk, c in groups.items()])
 
 
 def _nnz(v) -> int:
@@ -199,11 +211,19 @@ def adjoint_flops(st: Structure, n_e: int, n_f: int, line_alpha=None, with_value
 
 # ---- the specialized (generated) kernels ------------------------------------
 
+def _taylor_flops(j: int) -> int:
+    """A Taylor-coefficient leaf of order j from f and f(-y): j monomials of
+    degree j + 1 (j products and one FMA each), then beta^j / j!."""
+    return j * (j + 2) + j + 1 if j > 0 else 0
+
+
 def _spec_leaves(st: Structure, adjoint: bool) -> int:
     total = 0
-    for sigma, e in st.leaves:
+    for code, e in st.leaves:
+        sigma = 1 if code > 0 else -1
         total += max(_nnz(e) - 1, 0) + 1 + (1 if sigma == -1 else 0)    # x, beta x, + e_reg
         total += C_LEAF_BOSE if sigma == -1 else C_LEAF_FERMI
+        total += _taylor_flops(abs(code) - 1)
         if adjoint:
             total += 1                                                   # f'(y) = -f(y) f(-y)
     return total
@@ -231,6 +251,29 @@ def specialized_forward_flops(st: Structure, n_e: int, n_f: int, line_alpha=None
     if line_alpha is not None:
         per_sample += _momentum_flops(line_alpha, st.n_int, sincos=False)
     per_point = _spec_dens(st) + 4 * len(st.groups)           # FT_g R_g accumulated
+    total = n_e * per_sample + n_e * n_f * per_point
+    return {"per_sample": per_sample, "per_point": per_point, "total": float(total),
+            "term_evals": float(st.T) * n_e * n_f}
+
+
+def specialized_complex_forward_flops(st: Structure, n_e: int, n_f: int) -> dict:
+    """FLOPs of one launch of the complex-energy forward kernel: per sample the
+    leaf arguments of the real and imaginary parts, the complex leaf, the
+    complex group sums (6 FLOPs per complex product, 2 per accumulation) and
+    the imaginary energy part of every denominator; per (sample, frequency)
+    the denominators as in the real kernel plus that part, and every group's
+    complex FT_g R_g accumulation (8)."""
+    n = st.n_int
+    per_sample = 0
+    for code, e in st.leaves:
+        sigma = 1 if code > 0 else -1
+        per_sample += 2 * max(_nnz(e) - 1, 0) + 2 + (1 if sigma == -1 else 0)
+        per_sample += C_LEAF_C_BOSE if sigma == -1 else C_LEAF_C_FERMI
+    per_sample += sum(n_terms * (6 * max(n - 1, 0) + 2) for n_terms, _ in st.groups)
+    for e, a in st.dens:
+        na = _nnz(a)
+        per_sample += max(_nnz(e) + na - 1, 0) + max(na - 1, 0)      # den_args at Im E (w = 0)
+    per_point = _spec_dens(st) + len(st.dens) + 8 * len(st.groups)
     total = n_e * per_sample + n_e * n_f * per_point
     return {"per_sample": per_sample, "per_point": per_point, "total": float(total),
             "term_evals": float(st.T) * n_e * n_f}

@@ -94,12 +94,30 @@ def test_generated_multipole_values_match_oracle(name, tmp_path):
     check(vals, ref, scale, pole_distance(terms, n_int, E, w), label=f"{name} multipole values")
 
 
-def test_multipole_adjoint_is_refused():
+def test_multipole_source_has_no_adjoint(tmp_path, monkeypatch):
+    """The generated source of a multipole solution holds the forward kernel
+    and the Taylor-coefficient leaves, not the adjoint; amiTermsSpecialize
+    compiles that forward kernel alone (here, with no device, it then stops
+    at the device query)."""
+    monkeypatch.setenv("AMIGPU_CACHE_DIR", str(tmp_path))
     T = amd.Terms(*DOUBLE, multipole=True)
     src = T.source(momentum=False)
-    assert "taylor_leaves" in src
+    assert "taylor_leaves" in src and "#define AMI_JIT_KERNELS 1\n" in src
     with pytest.raises(amd.AmiError) as e:
         T.specialize(momentum=False)
-    # compilation of the forward kernel may succeed; the adjoint is refused
-    # before any device query
-    assert e.value.code in (-7, -5)
+    assert e.value.code == -5 and "hipGetDevice" in str(e.value)
+    assert len([p for p in tmp_path.iterdir() if p.name.endswith(".hsaco")]) == 1
+
+
+@pytest.mark.parametrize("name", list(CASES))
+def test_structure_of_the_extended_stream(name):
+    """The measurement code reads the extended stream (unequal denominator
+    counts) into the same distinct leaves, denominators and groups as the
+    library's tables."""
+    from paper_2311_17189_amd import roofline as rl
+    T = amd.Terms(*CASES[name], multipole=True)
+    st = rl.structure_from_canonical(T.canonical())
+    inf = T.info()
+    assert (st.T, len(st.leaves), len(st.dens), len(st.groups)) == (inf["T"], inf["L"], inf["D"], inf["G"])
+    assert sum(c for c, _ in st.groups) == st.T
+    assert any(abs(c) > 1 for c, _ in st.leaves)
