@@ -367,17 +367,20 @@ std::string jit_source(const AmiTerms *t, bool hub, int kernels) {
             const double s = tb.term_sign[ti];
             std::vector<int> lv(ni);
             for (int j = 0; j < ni; ++j) lv[j] = tb.term_leaf[static_cast<size_t>(ti) * ni + j];
+            // a unit sign goes into the update (a free negation), so that terms
+            // sharing leading leaves share their prefix products
+            const bool unit = s == 1.0 || s == -1.0;
+            const char *sg = s == -1.0 ? "-" : "";
             o << "  { const double p0 = ";
-            if (s == 1.0) o << "FTB[" << g << "]";
-            else if (s == -1.0) o << "-FTB[" << g << "]";
+            if (unit) o << "FTB[" << g << "]";
             else o << "FTB[" << g << "] * " << num(s);
             o << ";\n";
             for (int j = 1; j < ni; ++j)
                 o << "    const double p" << j << " = p" << j - 1 << " * F[" << lv[j - 1] << "];\n";
             o << "    double q = 1.0;\n";
             for (int j = ni - 1; j >= 0; --j) {
-                if (j == ni - 1) o << "    FB[" << lv[j] << "] += p" << j << ";\n";
-                else o << "    FB[" << lv[j] << "] = fma(p" << j << ", q, FB[" << lv[j] << "]);\n";
+                if (j == ni - 1) o << "    FB[" << lv[j] << "] " << (s == -1.0 ? "-=" : "+=") << " p" << j << ";\n";
+                else o << "    FB[" << lv[j] << "] = fma(" << sg << "p" << j << ", q, FB[" << lv[j] << "]);\n";
                 if (j > 0) {
                     if (j == ni - 1) o << "    q = F[" << lv[j] << "];\n";
                     else o << "    q *= F[" << lv[j] << "];\n";

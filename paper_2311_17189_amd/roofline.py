@@ -58,6 +58,7 @@ class Structure:
     leaves: list      # distinct (sigma, e-tuple)
     dens: list        # distinct (e-tuple, a_ext-tuple)
     groups: list      # per group: (n_terms, n_dens)
+    terms: list = None    # per term in stream order: (group index, prefactor, leaf keys)
 
 
 def structure_from_canonical(stream) -> Structure:
@@ -76,14 +77,19 @@ def structure_from_canonical(stream) -> Structure:
         dpt = ((len(s) - 4) // T - 1 - n_int * per_leaf) // per_den
     pos = 4
     leaves, dens, groups = {}, {}, {}
+    gindex, tlist = {}, []
     for _ in range(T):
+        pref = s[pos]
         pos += 1
         nd = dpt
         if extended:
             nd = s[pos]
             pos += 1
+        lv = []
         for _ in range(n_int):
-            leaves[(s[pos], tuple(s[pos + 1:pos + per_leaf]))] = True
+            key = (s[pos], tuple(s[pos + 1:pos + per_leaf]))
+            leaves[key] = True
+            lv.append(key)
             pos += per_leaf
         gk = []
         for _ in range(nd):
@@ -94,9 +100,10 @@ def structure_from_canonical(stream) -> Structure:
             pos += per_den
         gk = tuple(sorted(gk))
         groups[gk] = groups.get(gk, 0) + 1
+        tlist.append((gindex.setdefault(gk, len(gindex)), pref, tuple(lv)))
     return Structure(n_int=n_int, n_eps=n_eps, n_freq=n_freq, T=T,
                      leaves=list(leaves), dens=list(dens),
-                     groups=[(c, len(gk)) for gk, c in groups.items()])
+                     groups=[(c, len(gk)) for gk, c in groups.items()], terms=tlist)
 
 
 def _nnz(v) -> int:
@@ -230,8 +237,48 @@ def _spec_leaves(st: Structure, adjoint: bool) -> int:
 
 
 def _spec_group_sums(st: Structure) -> int:
+    """Group sums as generated: each term's leaves multiplied left to right,
+    the last factor of every term but a group's first fused into the
+    accumulation (FMA; a unit prefactor's sign is a free negation).  Equal
+    leading products of the terms of one group are computed once (the
+    compiler merges the identical expressions), so a product counts once per
+    distinct prefix."""
     n = st.n_int
-    return sum(n_terms * n - 1 for n_terms, _ in st.groups)   # n-1 products + accumulate, first term n-1
+    if st.terms is None:
+        return sum(n_terms * n - 1 for n_terms, _ in st.groups)
+    total, prefixes, seen = 0, set(), set()
+    for g, pref, lv in st.terms:
+        first = g not in seen
+        seen.add(g)
+        unit = abs(pref) == 1
+        upto = n if (first or not unit) else n - 1       # factors multiplied before the accumulation
+        for k in range(2, upto + 1):
+            prefixes.add((g, lv[:k]))
+        if not first:
+            total += 2                                     # fma into the group sum
+        if not unit:
+            total += 0 if first else 0                     # the prefactor enters the FMA
+    return total + len(prefixes)
+
+
+def _spec_leaf_cotangents(st: Structure) -> int:
+    """Leaf cotangents as generated: per term the products FTB_g f_1 ... f_j
+    (shared by the terms of a group with the same leading leaves, a unit sign
+    being applied in the update), the suffix products (n - 2 multiplies), one
+    update per leaf (n - 1 FMAs and an add)."""
+    n = st.n_int
+    if st.terms is None or n == 0:
+        return sum(n_terms * (4 * n - 4) for n_terms, _ in st.groups)
+    prefixes, total = set(), 0
+    for g, pref, lv in st.terms:
+        unit = abs(pref) == 1
+        if not unit:
+            total += 1 + (n - 1)                           # FTB s, its own prefix chain
+        else:
+            for k in range(1, n):
+                prefixes.add((g, lv[:k]))
+        total += max(n - 2, 0) + 2 * (n - 1) + 1
+    return total + len(prefixes)
 
 
 def _spec_dens(st: Structure) -> int:
@@ -290,7 +337,7 @@ def specialized_adjoint_flops(st: Structure, n_e: int, n_f: int, line_alpha=None
     chain rule through -2t sin K."""
     n = st.n_int
     per_sample = _spec_leaves(st, True) + _spec_group_sums(st)
-    per_sample += sum(n_terms * (4 * n - 4) for n_terms, _ in st.groups)   # leaf cotangents
+    per_sample += _spec_leaf_cotangents(st)
     for sigma, e in st.leaves:
         per_sample += max(_nnz(e) - 1, 0) + (1 if sigma == -1 else 0)    # x recomputed
         per_sample += 4 + _nnz(e)                                         # f' FB, beta, d/dbeta, scatter
