@@ -194,6 +194,19 @@ __device__ __forceinline__ void leaf_pair(bool bose, double y, double &f, double
     fm = y > 0.0 ? large : small;
 }
 
+// f_sigma(y) and f_sigma'(y) = -f_sigma(y) f_sigma(-y) together: the product of
+// the pair is the same whichever value is f, so it needs no select (the same
+// bits as -(f * fm) from leaf_pair).
+__device__ __forceinline__ void leaf_and_slope(bool bose, double y, double &f, double &dv) {
+    double t, m;
+    exp_split(-fmin(fabs(y), 700.0), t, m);
+    const double r = rcp_nr(bose ? m : 1.0 + t);
+    const double small = t * r;
+    const double large = bose ? -r : r;
+    f = y > 0.0 ? small : large;
+    dv = -(small * large);
+}
+
 // f_sigma'(y) = -f_sigma(y) f_sigma(-y) in closed form: -t/(1+t)^2 (Fermi) and
 // t/m^2 (Bose-type).
 __device__ __forceinline__ double leaf_deriv(bool bose, double y) {

@@ -217,9 +217,8 @@ __device__ __forceinline__ void adj_tile(const KArgs &a, int64_t blk, double *pa
 #pragma unroll
         for (int l = 0; l < L; ++l) {
             if (kBose[l]) x[l] += a.e_reg;
-            double fm;
-            ami::leaf_pair(kBose[l], a.beta * x[l], F[l], fm);
-            const double dv = -(F[l] * fm);     // f'(y) = -f(y) f(-y)
+            double dv;                          // f'(y) = -f(y) f(-y)
+            ami::leaf_and_slope(kBose[l], a.beta * x[l], F[l], dv);
             if constexpr (kParkDv) park[(kParkChain + l) * B + tid] = dv;
             else Dv[kParkDv ? 0 : l] = dv;
         }

@@ -42,6 +42,10 @@ int main(int argc, char **argv) {
             double t, m;
             ami::exp_split(x, t, m);
             std::printf("%.17g %.17g\n", t, m);
+        } else if (what[0] == 'u' || what[0] == 'v') {   // leaf_and_slope: Fermi (u) / Bose-type (v)
+            double f, dv;
+            ami::leaf_and_slope(what[0] == 'v', x, f, dv);
+            std::printf("%.17g %.17g\n", f, dv);
         } else {
             double f, fm;
             const bool bose = what[0] == 'b';

@@ -105,6 +105,17 @@ def test_leaf_pair_and_derivative(exe, kind):
 
 
 @pytest.mark.parametrize("kind", ["fermi", "bose"])
+def test_leaf_and_slope_equal_the_pair(exe, kind):
+    """leaf_and_slope gives the leaf_pair value and exactly -f(y) f(-y)."""
+    mag = np.logspace(-10, np.log10(690.0), 200)
+    ys = np.concatenate([mag, -mag, [0.0]] if kind == "fermi" else [mag, -mag])   # the Bose pole at 0 aside
+    pair = _run(exe, kind[0], ys)
+    slope = _run(exe, "u" if kind == "fermi" else "v", ys)
+    for (f, fm, _), (f2, dv) in zip(pair, slope):
+        assert f2 == f and dv == -(f * fm)
+
+
+@pytest.mark.parametrize("kind", ["fermi", "bose"])
 def test_leaf_at_complex_arguments(exe, kind):
     """1/(sigma e^y + 1) at complex y to a few ulp relative: |Re y| from 1e-10
     to 690, Im y up to 60, next to the Bose pole at 0, away from the Fermi
