@@ -316,7 +316,11 @@ AmiStatus amiIntegrateHubbard(AmiTerms *terms, int64_t n_samples, uint64_t seed,
  * solution (Sec. 2.3); they differ in how the term tables reach the kernel:
  *   AMI_VARIANT_AUTO         (default) specialized when the solution has at
  *                            most 1024 flat terms (128 for the adjoint) and at
- *                            most 16 energies and its kernels compile, else
+ *                            most 16 energies and its kernels compile -- the
+ *                            forward in two passes (below) when the solution
+ *                            has more than 1024 terms (up to 4096) or when its
+ *                            groups and denominators would not fit the one-pass
+ *                            kernel's registers (2 G + 4 D > 128) -- else
  *                            packed when the solution
  *                            has the packed form (+-1 coefficients, at most 255
  *                            leaves/denominators, 8 per term), else tables
@@ -329,14 +333,32 @@ AmiStatus amiIntegrateHubbard(AmiTerms *terms, int64_t n_samples, uint64_t seed,
  *                            from its tables and compiled at run time (hipRTC)
  *                            on first use -- or by amiTermsSpecialize -- and
  *                            cached on disk (AMIGPU_CACHE_DIR, else
- *                            $HOME/.cache/amigpu/jit)
+ *                            $HOME/.cache/amigpu/jit); the forward in two
+ *                            passes where AUTO would take them
+ *   AMI_VARIANT_TWO_PASS     the specialized forward in two passes: a first
+ *                            kernel stores every sample's group sums and
+ *                            energies in a workspace (in chunks of at most
+ *                            256 MB), a second evaluates, per frequency row,
+ *                            the denominators and the group products against
+ *                            them; register use independent of the number of
+ *                            groups.  Forward only, at most 65535 frequency
+ *                            rows per call
  * A forced variant that cannot serve a call fails it (AMI_E_UNSUPPORTED, or
  * AMI_E_HIP when the run-time compilation fails); AUTO falls back in the order
  * above and amiLastVariant names what ran and why.
  */
-enum { AMI_VARIANT_AUTO = 0, AMI_VARIANT_TABLES = 1, AMI_VARIANT_PACKED = 2, AMI_VARIANT_SPECIALIZED = 3 };
+enum { AMI_VARIANT_AUTO = 0, AMI_VARIANT_TABLES = 1, AMI_VARIANT_PACKED = 2, AMI_VARIANT_SPECIALIZED = 3,
+       AMI_VARIANT_TWO_PASS = 4 };
 
 AmiStatus amiSetVariant(AmiTerms *terms, int32_t variant);
+
+/*
+ * amiSetTwoPassChunkBytes -- bound (bytes, >= 64 KiB; default 256 MB) on the
+ * workspace of one chunk of samples of the two-pass forward, for every handle
+ * of the process: a call with more samples than fit runs chunk after chunk.
+ * Takes effect at the next call; the workspace never shrinks.
+ */
+AmiStatus amiSetTwoPassChunkBytes(int64_t bytes);
 
 /*
  * amiTermsSpecialize -- compile (or load from the disk cache) the specialized
@@ -345,16 +367,17 @@ AmiStatus amiSetVariant(AmiTerms *terms, int32_t variant);
  * out of later evaluate calls.  Host-blocking.  AMI_E_UNSUPPORTED when the
  * solution is outside the specialized form, AMI_E_HIP when compiling or loading
  * fails (amiLastError holds the compiler log).  The kernels are the forward
- * and the adjoint, plus the complex-energy forward (amiEvaluateComplex) for
- * the energy input; all are compiled before a device is touched.  A solution
- * with Taylor-coefficient leaves (AMI_MULTIPOLE) gets its forward kernel
- * only.
+ * (its two passes where AUTO takes them), the adjoint where AUTO uses it (at
+ * most 128 terms), and for solutions of at most 1024 terms the complex-energy
+ * forward (amiEvaluateComplex) for the energy input; all are compiled before a device is touched.  A solution
+ * with Taylor-coefficient leaves (AMI_MULTIPOLE) gets its forward only.
  */
 AmiStatus amiTermsSpecialize(AmiTerms *terms, int32_t momentum);
 
 /*
  * amiTermsSource -- the generated device source of the specialized kernels
- * (energy input: momentum = 0; momentum input: 1), NUL-terminated, into buf
+ * (energy input: momentum = 0; momentum input: 1; plus 2 for the source of the
+ * two-pass forward, up to 4096 terms), NUL-terminated, into buf
  * (host, capacity cap bytes; *len receives the size including the NUL, also
  * when buf is NULL).  The source includes the library's device headers by
  * name (device_common.hpp, kargs.hpp, jit_kernel.hpp).  AMI_E_UNSUPPORTED when

@@ -86,6 +86,8 @@ def load_library():
     lib.amiEvaluate.restype = c_i32
     lib.amiEvaluateComplex.argtypes = [vp, vp, c_i64, c_i64, c_i64, vp, c_i64, c_dbl, c_dbl, vp, vp, vp]
     lib.amiEvaluateComplex.restype = c_i32
+    lib.amiSetTwoPassChunkBytes.argtypes = [c_i64]
+    lib.amiSetTwoPassChunkBytes.restype = c_i32
     lib.amiEvaluateHubbard.argtypes = [vp, vp, c_i64, c_i64, vp, c_dbl, c_dbl, vp, c_i64, c_dbl,
                                        c_dbl, vp, vp, vp]
     lib.amiEvaluateHubbard.restype = c_i32
@@ -164,7 +166,12 @@ def kernel_timer_stop() -> list:
 
 
 # kernel variants (amiSetVariant)
-VARIANT_AUTO, VARIANT_TABLES, VARIANT_PACKED, VARIANT_SPECIALIZED = 0, 1, 2, 3
+VARIANT_AUTO, VARIANT_TABLES, VARIANT_PACKED, VARIANT_SPECIALIZED, VARIANT_TWO_PASS = 0, 1, 2, 3, 4
+
+
+def set_two_pass_chunk_bytes(nbytes: int):
+    """``amiSetTwoPassChunkBytes``: bound on one chunk of the two-pass workspace."""
+    _check(load_library().amiSetTwoPassChunkBytes(int(nbytes)))
 
 
 def last_variant() -> str:
@@ -262,7 +269,7 @@ class Terms:
 
     def set_variant(self, variant: int):
         """Kernel variant (``amiSetVariant``): VARIANT_AUTO (default), VARIANT_TABLES,
-        VARIANT_PACKED or VARIANT_SPECIALIZED."""
+        VARIANT_PACKED, VARIANT_SPECIALIZED or VARIANT_TWO_PASS (forward only)."""
         _check(load_library().amiSetVariant(self._h, int(variant)))
 
     def specialize(self, momentum: bool = True):
@@ -270,13 +277,15 @@ class Terms:
         (``amiTermsSpecialize``) so later calls do not compile."""
         _check(load_library().amiTermsSpecialize(self._h, int(bool(momentum))))
 
-    def source(self, momentum: bool = True) -> str:
-        """Generated device source of the specialized kernels (``amiTermsSource``)."""
+    def source(self, momentum: bool = True, two_pass: bool = False) -> str:
+        """Generated device source of the specialized kernels (``amiTermsSource``);
+        ``two_pass`` for the two-pass forward's."""
         lib = load_library()
         n = ctypes.c_int64()
-        _check(lib.amiTermsSource(self._h, int(bool(momentum)), None, 0, ctypes.byref(n)))
+        sel = int(bool(momentum)) | (2 if two_pass else 0)
+        _check(lib.amiTermsSource(self._h, sel, None, 0, ctypes.byref(n)))
         buf = ctypes.create_string_buffer(n.value)
-        _check(lib.amiTermsSource(self._h, int(bool(momentum)), buf, n.value, ctypes.byref(n)))
+        _check(lib.amiTermsSource(self._h, sel, buf, n.value, ctypes.byref(n)))
         return buf.value.decode()
 
     def close(self):

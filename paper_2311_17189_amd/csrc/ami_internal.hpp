@@ -117,11 +117,12 @@ struct AmiTerms {
     std::mutex dev_mu;
     std::vector<ami::DeviceTables> dev;      // uploaded copies
     // run-time specialized kernels: code objects per (input, kernel) -- index
-    // 4 * momentum + kernel (0 forward, 1 adjoint, 2 Monte-Carlo, 3 forward at
-    // complex energies) -- and the modules loaded from them, one per device
+    // 6 * momentum + kernel (0 forward, 1 adjoint, 2 Monte-Carlo, 3 forward at
+    // complex energies, 4 and 5 the two passes of the two-pass forward) -- and
+    // the modules loaded from them, one per device
     std::mutex jit_mu;
-    std::vector<char> jit_code[8];
-    std::string jit_error[8];                // why a compilation failed (not retried)
+    std::vector<char> jit_code[12];
+    std::string jit_error[12];                // why a compilation failed (not retried)
     struct JitModule {
         int device = -1, kind = 0;
         void *module = nullptr, *fn = nullptr;

@@ -53,7 +53,12 @@ std::string idx(const char *a, int i) { return std::string(a) + "[" + std::to_st
 
 }  // namespace
 
-bool jit_supported(const AmiTerms *t, bool hub, std::string *why) {
+bool jit_prefers_two_pass(const AmiTerms *t) {
+    const Tables &tb = t->tab;
+    return tb.T > kJitMaxTerms || 2 * tb.G + 4 * tb.D > 128;
+}
+
+bool jit_supported(const AmiTerms *t, bool hub, std::string *why, bool two_pass) {
     const Tables &tb = t->tab;
     auto no = [&](const std::string &m) {
         if (why) *why = m;
@@ -63,7 +68,8 @@ bool jit_supported(const AmiTerms *t, bool hub, std::string *why) {
     if (t->n_eps > kMaxEpsDev) return no("more than 16 energies");
     if (t->n_ext > kMaxExt) return no("more than 4 external slots");
     if (hub && t->n_g != t->n_eps) return no("momentum input needs one energy per line");
-    if (tb.T > kJitMaxTerms) return no("more than " + std::to_string(kJitMaxTerms) + " terms");
+    const int max_terms = two_pass ? kJitTwoPassMaxTerms : kJitMaxTerms;
+    if (tb.T > max_terms) return no("more than " + std::to_string(max_terms) + " terms");
     return true;
 }
 
@@ -195,17 +201,43 @@ std::string jit_source(const AmiTerms *t, bool hub, int kernels) {
 
     // group sums FT_g = sum_t s_t prod f: the product of a term's leaves left
     // to right, its last factor fused into the accumulation (unit s_t)
+    // leaf names: F[l], or a group's own copy f<l> (opaque copies)
+    std::string leaf_prefix = "F[", leaf_suffix = "]";
+    auto leaf_name = [&](int l) { return leaf_prefix + std::to_string(l) + leaf_suffix; };
     auto term_product = [&](int ti, int upto) {
         std::string p;
         for (int j = 0; j < upto; ++j) {
-            const std::string f = idx("F", tb.term_leaf[static_cast<size_t>(ti) * ni + j]);
+            const std::string f = leaf_name(tb.term_leaf[static_cast<size_t>(ti) * ni + j]);
             p = p.empty() ? f : p + " * " + f;
         }
         return p.empty() ? std::string("1.0") : p;
     };
-    o << "__device__ __forceinline__ void group_sums(const double (&F)[L], double (&FT)[G]) {\n";
+    // the one-pass kernels' functions (and the adjoint's) are emitted when one
+    // of those kernels is asked for, or for any solution small enough for them
+    // (the host checks compile them); a two-pass source of a large solution
+    // holds only what its two kernels use
+    const bool small = tb.T <= kJitMaxTerms;
+    const bool one_pass = (kernels & 15) != 0;
+    const bool adj_fns = (kernels & 2) || ((kernels & 1) && small);
+    // With `opaque`, every group first takes copies of the leaves it reads
+    // through an empty asm (no instruction): the compiler then cannot merge
+    // equal products of different groups, which for large solutions would
+    // keep hundreds of shared products live across the whole function; equal
+    // products within a group are still merged.
+    auto group_sums_body = [&](const std::string &sink_prefix, const std::string &sink_suffix, bool opaque) {
     for (int g = 0; g < G; ++g) {
         o << "  { double ft;\n";
+        leaf_prefix = opaque ? "f" : "F[";
+        leaf_suffix = opaque ? "" : "]";
+        if (opaque) {
+            std::vector<int> used;
+            for (int ti = tb.group_start[g]; ti < tb.group_start[g + 1]; ++ti)
+                for (int j = 0; j < ni; ++j) used.push_back(tb.term_leaf[static_cast<size_t>(ti) * ni + j]);
+            std::sort(used.begin(), used.end());
+            used.erase(std::unique(used.begin(), used.end()), used.end());
+            for (int l : used)
+                o << "    double f" << l << " = F[" << l << "]; AMI_OPAQUE(f" << l << ");\n";
+        }
         for (int ti = tb.group_start[g]; ti < tb.group_start[g + 1]; ++ti) {
             const double s = tb.term_sign[ti];
             if (ti == tb.group_start[g]) {
@@ -214,16 +246,27 @@ std::string jit_source(const AmiTerms *t, bool hub, int kernels) {
                 else if (s == -1.0) o << "    ft = -(" << p << ");\n";
                 else o << "    ft = " << num(s) << " * (" << p << ");\n";
             } else if ((s == 1.0 || s == -1.0) && ni > 1) {
-                const std::string last = idx("F", tb.term_leaf[static_cast<size_t>(ti) * ni + ni - 1]);
+                const std::string last = leaf_name(tb.term_leaf[static_cast<size_t>(ti) * ni + ni - 1]);
                 o << "    ft = fma(" << (s < 0 ? "-(" : "(") << term_product(ti, ni - 1) << "), " << last
                   << ", ft);\n";
             } else {
                 o << "    ft = fma(" << num(s) << ", " << term_product(ti, ni) << ", ft);\n";
             }
         }
-        o << "    FT[" << g << "] = ft; }\n";
+        o << "    " << sink_prefix << g << sink_suffix << " = ft; }\n";
     }
-    o << "}\n";
+    };
+    if (one_pass) {
+        o << "__device__ __forceinline__ void group_sums(const double (&F)[L], double (&FT)[G]) {\n";
+        group_sums_body("FT[", "]", false);
+        o << "}\n";
+    }
+    // two-pass forward, first pass: each group sum stored as soon as it is formed
+    if (kernels & 16) {
+        o << "__device__ __forceinline__ void group_sums_store(const double (&F)[L], double *dst, int64_t ld) {\n";
+        group_sums_body("dst[(int64_t)", " * ld]", true);
+        o << "}\n";
+    }
 
     // complex group sums (complex energies): the same products of a term's
     // leaves left to right, in complex arithmetic, accumulated with s_t
@@ -304,24 +347,55 @@ std::string jit_source(const AmiTerms *t, bool hub, int kernels) {
     }
     o << "}\n";
 
-    // group products R_g = prod rho_k (complex), left to right
-    o << "__device__ __forceinline__ void group_products(const double (&xr)[D], const double (&xi)[D], double (&Rr)[G], "
-         "double (&Ri)[G]) {\n";
-    for (int g = 0; g < G; ++g) {
+    // group products R_g = prod rho_k (complex), left to right; with `opaque`
+    // from the group's own copies of its reciprocals (as for the group sums)
+    auto group_product = [&](int g, bool opaque) {
         o << "  { double rr = 1.0, ri = 0.0, nr = 0.0;\n";
+        std::string pr = "xr[", pi = "xi[", sf = "]";
+        if (opaque) {
+            std::vector<int> used(tb.group_den_list.begin() + gbegin(g), tb.group_den_list.begin() + gend(g));
+            std::sort(used.begin(), used.end());
+            used.erase(std::unique(used.begin(), used.end()), used.end());
+            for (int k : used)
+                o << "    double yr" << k << " = xr[" << k << "], yi" << k << " = xi[" << k << "]; AMI_OPAQUE(yr" << k
+                  << "); AMI_OPAQUE(yi" << k << ");\n";
+            pr = "yr";
+            pi = "yi";
+            sf = "";
+        }
         for (int j = 0; j < gend(g) - gbegin(g); ++j) {
-            const int k = tb.group_den_list[gbegin(g) + j];
+            const std::string k = std::to_string(tb.group_den_list[gbegin(g) + j]);
             if (j == 0) {
-                o << "    rr = xr[" << k << "]; ri = xi[" << k << "];\n";
+                o << "    rr = " << pr << k << sf << "; ri = " << pi << k << sf << ";\n";
             } else {
-                o << "    nr = fma(rr, xr[" << k << "], -ri * xi[" << k << "]); ri = fma(rr, xi[" << k
-                  << "], ri * xr[" << k << "]); rr = nr;\n";
+                o << "    nr = fma(rr, " << pr << k << sf << ", -ri * " << pi << k << sf << "); ri = fma(rr, " << pi
+                  << k << sf << ", ri * " << pr << k << sf << "); rr = nr;\n";
             }
         }
-        o << "    (void)nr; Rr[" << g << "] = rr; Ri[" << g << "] = ri; }\n";
+    };
+    if (one_pass) {
+        o << "__device__ __forceinline__ void group_products(const double (&xr)[D], const double (&xi)[D], "
+             "double (&Rr)[G], double (&Ri)[G]) {\n";
+        for (int g = 0; g < G; ++g) {
+            group_product(g, false);
+            o << "    (void)nr; Rr[" << g << "] = rr; Ri[" << g << "] = ri; }\n";
+        }
+        o << "}\n";
     }
-    o << "}\n";
+    // two-pass forward, second pass: each R_g times its stored group sum,
+    // accumulated group by group
+    if (kernels & 32) {
+        o << "__device__ __forceinline__ void group_accumulate(const double (&xr)[D], const double (&xi)[D], "
+             "const double *ft, int64_t ld, double &acc_re, double &acc_im) {\n";
+        for (int g = 0; g < G; ++g) {
+            group_product(g, true);
+            o << "    const double v = ft[(int64_t)" << g << " * ld];\n";
+            o << "    (void)nr; acc_re = fma(v, rr, acc_re); acc_im = fma(v, ri, acc_im); }\n";
+        }
+        o << "}\n";
+    }
 
+    if (adj_fns) {
     // U_k = sum over the occurrences of k in the groups of u_g
     std::vector<std::vector<int>> occ(D);
     for (int g = 0; g < G; ++g)
@@ -409,6 +483,7 @@ std::string jit_source(const AmiTerms *t, bool hub, int kernels) {
             }
     }
     o << "}\n";
+    }  // adj_fns
     o << "}  // namespace amijit\n";
     o << "#include \"jit_kernel.hpp\"\n";
     return o.str();
@@ -420,12 +495,14 @@ extern "C" AmiStatus amiTermsSource(const AmiTerms *t, int32_t momentum, char *b
     using namespace ami;
     clear_error();
     if (!t || !len) return fail(AMI_E_ARG, "NULL argument");
+    if (momentum < 0 || momentum > 3) return fail(AMI_E_ARG, "momentum must be 0..3");
+    const bool hub = (momentum & 1) != 0, two_pass = (momentum & 2) != 0;
     std::string why;
-    if (!jit_supported(t, momentum != 0, &why)) return fail(AMI_E_UNSUPPORTED, "no specialized kernel: " + why);
-    int kernels = momentum != 0 ? 7 : 11;
+    if (!jit_supported(t, hub, &why, two_pass)) return fail(AMI_E_UNSUPPORTED, "no specialized kernel: " + why);
+    int kernels = two_pass ? 48 : hub ? 7 : 11;
     for (int o : t->tab.leaf_order)
         if (o > 0) kernels &= ~10;   // Taylor-coefficient leaves: no adjoint, no complex energies
-    const std::string src = jit_source(t, momentum != 0, kernels);
+    const std::string src = jit_source(t, hub, kernels);
     *len = static_cast<int64_t>(src.size()) + 1;
     if (!buf) return AMI_OK;
     if (cap < *len) return fail(AMI_E_ARG, "buffer too small");

@@ -19,6 +19,13 @@ typedef __hip_internal::uint8_t uint8_t;
 typedef __hip_internal::int8_t int8_t;
 #endif
 
+// A value made opaque to the optimizer (an empty asm that may change it; no
+// instruction): generated code copies a group's operands through it so that
+// equal products of different groups are not merged into long-lived values.
+#ifndef AMI_OPAQUE
+#define AMI_OPAQUE(x) asm volatile("" : "+v"(x))
+#endif
+
 namespace ami {
 
 typedef const __attribute__((address_space(4))) uint64_t *cu64;

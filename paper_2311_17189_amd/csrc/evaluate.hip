@@ -13,6 +13,7 @@
 #include <hip/hip_ext.h>
 
 #include <algorithm>
+#include <atomic>
 #include <cmath>
 #include <cstring>
 #include <mutex>
@@ -363,16 +364,42 @@ bool timer_pair(hipEvent_t &start, hipEvent_t &stop) {
     return true;
 }
 
-enum class Path { TABLES, PACKED, SPECIALIZED };
+enum class Path { TABLES, PACKED, SPECIALIZED, TWO_PASS };
+
+// Workspace of one chunk of the two-pass forward (group sums and energies):
+// 256 MB unless amiSetTwoPassChunkBytes set another bound.
+std::atomic<int64_t> g_two_pass_chunk_bytes{int64_t(256) << 20};
+// Frequency rows of one two-pass launch (its second kernel's grid height).
+constexpr int kTwoPassMaxFreqs = 65535;
 
 // Which kernels serve a call (AMI_VARIANT_* of the handle); for the
 // specialized path also loads them.  AUTO falls back and records why.
-AmiStatus choose_path(AmiTerms *t, bool hub, bool adjoint, Path &p, void **jit_fn, std::string &note) {
+AmiStatus choose_path(AmiTerms *t, bool hub, bool adjoint, Path &p, void **jit_fn, std::string &note,
+                      void **jit_fn2 = nullptr, int n_f = 1) {
     const int v = t->variant;
     note.clear();
+    // the forward of a large solution: two passes (AUTO and SPECIALIZED when the
+    // one-pass kernel would not fit its registers; TWO_PASS always)
+    const bool two = !adjoint && jit_fn2 && n_f <= kTwoPassMaxFreqs &&
+                     (v == AMI_VARIANT_TWO_PASS ||
+                      ((v == AMI_VARIANT_AUTO || v == AMI_VARIANT_SPECIALIZED) && jit_prefers_two_pass(t)));
+    if (v == AMI_VARIANT_TWO_PASS && !two)
+        return fail(AMI_E_UNSUPPORTED, adjoint ? "the two-pass variant has no adjoint"
+                                               : "the two-pass variant takes at most 65535 frequency rows");
+    if (two) {
+        AmiStatus st = jit_get(t, hub, kJitSumsPass, jit_fn);
+        if (st == AMI_OK) st = jit_get(t, hub, kJitFreqPass, jit_fn2);
+        if (st == AMI_OK) {
+            p = Path::TWO_PASS;
+            return AMI_OK;
+        }
+        if (v != AMI_VARIANT_AUTO) return st;
+        note = std::string(" (not two-pass: ") + amiLastError() + ")";
+        clear_error();
+    }
     const bool auto_skip = v == AMI_VARIANT_AUTO && adjoint && t->tab.T > kJitAutoAdjointTerms;
     if (auto_skip) note = " (adjoint specialized up to " + std::to_string(kJitAutoAdjointTerms) + " terms)";
-    if (v == AMI_VARIANT_SPECIALIZED || (v == AMI_VARIANT_AUTO && !auto_skip)) {
+    if (v == AMI_VARIANT_SPECIALIZED || (v == AMI_VARIANT_AUTO && !auto_skip && !two)) {
         const AmiStatus st = jit_get(t, hub, adjoint ? kJitAdjoint : kJitForward, jit_fn);
         if (st == AMI_OK) {
             p = Path::SPECIALIZED;
@@ -426,16 +453,59 @@ AmiStatus workspace(AmiTerms *t, DeviceTables *dt, hipStream_t stream, size_t by
     return AMI_OK;
 }
 
-// Launch of a specialized kernel (timed by the kernel timer when it runs).
-hipError_t launch_jit(void *fn, int64_t nblocks, int block, hipStream_t stream, KArgs &a) {
+// Launch of a specialized kernel on a grid of nblocks x gy blocks (timed by
+// the kernel timer when it runs).
+hipError_t launch_jit(void *fn, int64_t nblocks, int block, hipStream_t stream, KArgs &a, int gy = 1) {
     void *params[] = {&a};
     const hipFunction_t f = static_cast<hipFunction_t>(fn);
     hipEvent_t t0 = nullptr, t1 = nullptr;
     if (nblocks * block <= 0xffffffffLL && timer_pair(t0, t1))
-        return hipExtModuleLaunchKernel(f, static_cast<uint32_t>(nblocks * block), 1, 1, static_cast<uint32_t>(block),
-                                        1, 1, 0, stream, params, nullptr, t0, t1, 0);
-    return hipModuleLaunchKernel(f, static_cast<unsigned>(nblocks), 1, 1, static_cast<unsigned>(block), 1, 1, 0,
-                                 stream, params, nullptr);
+        return hipExtModuleLaunchKernel(f, static_cast<uint32_t>(nblocks * block), static_cast<uint32_t>(gy), 1,
+                                        static_cast<uint32_t>(block), 1, 1, 0, stream, params, nullptr, t0, t1, 0);
+    return hipModuleLaunchKernel(f, static_cast<unsigned>(nblocks), static_cast<unsigned>(gy), 1,
+                                 static_cast<unsigned>(block), 1, 1, 0, stream, params, nullptr);
+}
+
+// The two-pass forward: the samples in chunks whose group sums and energies
+// fit the chunk workspace; per chunk the sums pass (one lane per sample) and
+// the frequency pass (a grid row per frequency), then one column reduction
+// of the per-wave partial sums for the row sums.
+AmiStatus launch_two_pass(AmiTerms *t, DeviceTables *dt, bool hub, KArgs &a, double *out_sum, void *fn_sums,
+                          void *fn_freq, hipStream_t stream) {
+    const int B = jit_block(t, hub);
+    const int64_t tiles = (a.n_e + B - 1) / B;
+    if (tiles > 0x7fffffffLL) return fail(AMI_E_ARG, "n_e too large");
+    const int64_t rows = tiles * (B / 64);
+    const int64_t cols = static_cast<int64_t>(t->tab.G) + t->n_eps;
+    const int64_t chunk_bytes = g_two_pass_chunk_bytes.load();
+    int64_t ld = chunk_bytes / (cols * static_cast<int64_t>(sizeof(double))) / B * B;
+    ld = std::max<int64_t>(B, std::min<int64_t>(ld, tiles * B));
+    double *ws = nullptr;
+    const size_t n_part = out_sum ? static_cast<size_t>(rows) * a.n_f * 2 : 0;
+    AmiStatus st = workspace(t, dt, stream, (static_cast<size_t>(cols) * ld + n_part) * sizeof(double), &ws);
+    if (st != AMI_OK) return st;
+    a.work = ws;
+    a.ld = ld;
+    a.partial = out_sum ? ws + static_cast<size_t>(cols) * ld : nullptr;
+    a.nrows = rows;
+    hipError_t e = hipSuccess;
+    for (int64_t s0 = 0; s0 < a.n_e && e == hipSuccess; s0 += ld) {
+        a.s0 = s0;
+        a.n_chunk = std::min<int64_t>(ld, a.n_e - s0);
+        const int64_t nb = (a.n_chunk + B - 1) / B;
+        e = launch_jit(fn_sums, nb, B, stream, a);
+        if (e == hipSuccess) e = launch_jit(fn_freq, nb, B, stream, a, a.n_f);
+    }
+    if (e == hipSuccess) e = hipGetLastError();
+    g_last_variant = "specialized two-pass";
+    if (e != hipSuccess) return hip_fail(e, "two-pass launch");
+    if (out_sum) {
+        hipLaunchKernelGGL(ami_colsum_kernel, dim3(2 * a.n_f), dim3(kRedThreads), 0, stream, a.partial, rows,
+                           static_cast<int64_t>(1), rows, out_sum);
+        e = hipGetLastError();
+        if (e != hipSuccess) return hip_fail(e, "row-sum launch");
+    }
+    return AMI_OK;
 }
 
 AmiStatus launch_forward(AmiTerms *t, bool hub, KArgs &a, double *out_sum, hipStream_t stream) {
@@ -445,10 +515,11 @@ AmiStatus launch_forward(AmiTerms *t, bool hub, KArgs &a, double *out_sum, hipSt
     const Tables &tb = t->tab;
     if (a.n_e == 0) return fill(out_sum, 2 * static_cast<int64_t>(a.n_f), stream);
     Path path;
-    void *jit_fn = nullptr;
+    void *jit_fn = nullptr, *jit_fn2 = nullptr;
     std::string note;
-    st = choose_path(t, hub, false, path, &jit_fn, note);
+    st = choose_path(t, hub, false, path, &jit_fn, note, &jit_fn2, a.n_f);
     if (st != AMI_OK) return st;
+    if (path == Path::TWO_PASS) return launch_two_pass(t, dt, hub, a, out_sum, jit_fn, jit_fn2, stream);
     LaunchShape ls;
     if (path == Path::SPECIALIZED) {
         ls.block = jit_block(t, hub);
@@ -838,10 +909,17 @@ AmiStatus amiIntegrateHubbard(AmiTerms *t, int64_t n_samples, uint64_t seed, con
     return e == hipSuccess ? AMI_OK : hip_fail(e, "Monte-Carlo reduction launch");
 }
 
+AmiStatus amiSetTwoPassChunkBytes(int64_t bytes) {
+    ami::clear_error();
+    if (bytes < (int64_t(1) << 16)) return ami::fail(AMI_E_ARG, "the chunk bound must be at least 64 KiB");
+    ami::g_two_pass_chunk_bytes.store(bytes);
+    return AMI_OK;
+}
+
 AmiStatus amiSetVariant(AmiTerms *t, int32_t variant) {
     ami::clear_error();
     if (!t) return ami::fail(AMI_E_ARG, "terms is NULL");
-    if (variant < AMI_VARIANT_AUTO || variant > AMI_VARIANT_SPECIALIZED)
+    if (variant < AMI_VARIANT_AUTO || variant > AMI_VARIANT_TWO_PASS)
         return ami::fail(AMI_E_ARG, "variant must be one of AMI_VARIANT_*");
     t->variant = variant;
     return AMI_OK;
@@ -856,9 +934,16 @@ AmiStatus amiTermsSpecialize(AmiTerms *t, int32_t momentum) {
     for (int o : t->tab.leaf_order) taylor = taylor || o > 0;
     // the kernels for this input: forward, adjoint, and the complex-energy
     // forward for the energy input; all compiled before any device is touched
-    std::vector<int> kinds{kJitForward};
-    if (!taylor) kinds.push_back(kJitAdjoint);
-    if (!taylor && !hub) kinds.push_back(kJitComplex);
+    const bool small = t->tab.T <= kJitMaxTerms;
+    std::vector<int> kinds;
+    if (jit_prefers_two_pass(t)) {
+        kinds.push_back(kJitSumsPass);
+        kinds.push_back(kJitFreqPass);
+    } else {
+        kinds.push_back(kJitForward);
+    }
+    if (!taylor && t->tab.T <= kJitAutoAdjointTerms) kinds.push_back(kJitAdjoint);
+    if (!taylor && small && !hub) kinds.push_back(kJitComplex);
     for (int k : kinds) {
         const AmiStatus st = jit_compile(t, hub, k);
         if (st != AMI_OK) return st;

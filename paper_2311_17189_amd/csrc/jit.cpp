@@ -146,7 +146,7 @@ AmiStatus code_object(AmiTerms *t, bool hub, int kind) {
     std::string &err = t->jit_error[slot];
     if (!err.empty()) return fail(AMI_E_UNSUPPORTED, err);
     std::string why;
-    if (!jit_supported(t, hub, &why)) {
+    if (!jit_supported(t, hub, &why, kind == kJitSumsPass || kind == kJitFreqPass)) {
         err = "no specialized kernel: " + why;
         return fail(AMI_E_UNSUPPORTED, err);
     }
@@ -206,7 +206,8 @@ AmiStatus jit_get(AmiTerms *t, bool hub, int kind, void **fn) {
     e = hipModuleLoadData(&mod, t->jit_code[slot].data());
     if (e != hipSuccess) return hip_fail(e, "hipModuleLoadData (specialized kernel)");
     hipFunction_t f = nullptr;
-    static const char *const kNames[kJitKinds] = {"ami_jit_fwd", "ami_jit_adj", "ami_jit_mc", "ami_jit_cfwd"};
+    static const char *const kNames[kJitKinds] = {"ami_jit_fwd", "ami_jit_adj", "ami_jit_mc", "ami_jit_cfwd",
+                                                  "ami_jit_sums", "ami_jit_freq"};
     e = hipModuleGetFunction(&f, mod, kNames[kind]);
     if (e != hipSuccess) {
         (void)hipModuleUnload(mod);

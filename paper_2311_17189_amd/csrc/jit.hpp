@@ -11,25 +11,36 @@ namespace ami {
 // Largest solution (flat terms) specialized; larger ones stay on the
 // table-driven kernels, whose code size does not grow with the diagram.
 constexpr int kJitMaxTerms = 1024;
+// Largest solution evaluated by the two-pass specialized forward (group sums
+// stored per sample by a first kernel, read back per frequency by a second):
+// its register use does not grow with the number of groups.
+constexpr int kJitTwoPassMaxTerms = 4096;
 // AMI_VARIANT_AUTO uses the specialized adjoint up to this many terms: beyond
 // it the straight-line reverse sweep outgrows the register file.
 constexpr int kJitAutoAdjointTerms = 128;
 
 // Whether the diagram can be specialized for the energy (hub = false) or
 // momentum (hub = true) input; *why says why not.
-bool jit_supported(const AmiTerms *t, bool hub, std::string *why);
+bool jit_supported(const AmiTerms *t, bool hub, std::string *why, bool two_pass = false);
+
+// Whether AUTO evaluates the forward in two passes: the group sums and the
+// reciprocals the one-pass kernel holds in registers across its frequency
+// loop would exceed about half of a wave's registers.
+bool jit_prefers_two_pass(const AmiTerms *t);
 
 // Lanes per block of the specialized kernels.
 int jit_block(const AmiTerms *t, bool hub);
 
 // Device source of the specialized kernels: the forward (kernels & 1), the
-// adjoint (kernels & 2), the Monte-Carlo integrator (kernels & 4) and/or the
-// forward at complex energies (kernels & 8).
+// adjoint (kernels & 2), the Monte-Carlo integrator (kernels & 4), the
+// forward at complex energies (kernels & 8), and the two passes of the
+// two-pass forward (kernels & 16: group sums and energies stored per sample;
+// kernels & 32: per frequency, reciprocals and group products against them).
 std::string jit_source(const AmiTerms *t, bool hub, int kernels);
 
 // Kernels of the specialized evaluator.
-enum JitKind { kJitForward = 0, kJitAdjoint = 1, kJitMonteCarlo = 2, kJitComplex = 3 };
-constexpr int kJitKinds = 4;
+enum JitKind { kJitForward = 0, kJitAdjoint = 1, kJitMonteCarlo = 2, kJitComplex = 3, kJitSumsPass = 4, kJitFreqPass = 5 };
+constexpr int kJitKinds = 6;
 
 // The specialized kernel of `kind` for the energy (hub = false) or momentum
 // input as a hipFunction_t: compiled (or fetched from the code-object cache)

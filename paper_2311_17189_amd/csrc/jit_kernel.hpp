@@ -149,8 +149,9 @@ __device__ __forceinline__ void reciprocals(const double (&E)[NE], const double 
     }
 }
 
+#if AMI_JIT_KERNELS & 1
 // Partial sums are per wave: row r = tile * (B / 64) + wave of the partial
-// arrays (column c at [c * nrows + r]), written by the wave's first lane
+// arrays (column c at [c * nrows + r]), written by the wave's last lane
 // (wave_store2).
 template <bool HUB>
 __device__ __forceinline__ void fwd_tile(const KArgs &a, int64_t tile) {
@@ -196,6 +197,9 @@ __device__ __forceinline__ void fwd_tile(const KArgs &a, int64_t tile) {
     }
 }
 
+#endif
+
+#if AMI_JIT_KERNELS & 2
 // Adjoint of L = Re sum_{f,s} conj(c[f,s]) I[f,s] (the packed adjoint's
 // derivation), with the denominator cotangents collected per distinct
 // denominator: dL/dD_k = -rho_k sum_{g contains k} FT_g conj(c) R_g.
@@ -345,7 +349,9 @@ __device__ __forceinline__ void adj_tile(const KArgs &a, int64_t blk, double *pa
     ami::wave_store2(active ? gbeta : 0.0, active ? gmu : 0.0, lane, gp, a.nrows);
     ami::wave_store2(active ? gt : 0.0, 0.0, lane, gp + 2 * a.nrows, a.nrows);
 }
+#endif
 
+#if AMI_JIT_KERNELS & 4
 // Monte-Carlo integration over the internal momenta (Sec. 5.2, the row
 // average of Sec. 2.3): sample s = blockIdx.x B + tid + i gridDim.x B draws
 // its 2 NI components from Philox blocks (counter (s mod 2^32, s div 2^32,
@@ -420,6 +426,66 @@ __device__ __forceinline__ void mc_block(const KArgs &a) {
     }
 }
 
+#endif
+
+#if AMI_JIT_KERNELS & 16
+// Two-pass forward, first pass (large solutions: their group sums do not fit
+// in registers through a frequency loop): one lane per sample of the chunk,
+// energies, leaves and group sums, each group sum stored to the workspace as
+// soon as it is formed, the energies beside them.  Lanes past the chunk write
+// rows of the workspace that nothing reads (ld is a multiple of the block).
+template <bool HUB>
+__device__ __forceinline__ void sums_tile(const KArgs &a, int64_t tile) {
+    const int tid = threadIdx.x, B = blockDim.x;
+    const int64_t i = tile * B + tid;
+    const int64_t sc = a.s0 + (i < a.n_chunk ? i : a.n_chunk - 1);
+    double E[NE];
+    energies<HUB, false>(a, sc, E, nullptr);
+    double x[L], F[L], FM[L];
+    leaf_args(E, x);
+#pragma unroll
+    for (int l = 0; l < L; ++l) {
+        if (kBose[l]) ami::leaf_pair(true, a.beta * (x[l] + a.e_reg), F[l], FM[l]);
+        else ami::leaf_pair(false, a.beta * x[l], F[l], FM[l]);
+    }
+    taylor_leaves(F, FM, a.beta);
+    group_sums_store(F, a.work + i, a.ld);
+#pragma unroll
+    for (int j = 0; j < NE; ++j) a.work[(G + j) * a.ld + i] = E[j];
+}
+#endif
+
+#if AMI_JIT_KERNELS & 32
+// Two-pass forward, second pass: block (tile, f) evaluates frequency row
+// f = blockIdx.y for the samples of one tile of the chunk: the reciprocals of
+// every distinct denominator from the stored energies, then group by group
+// R_g times the stored FT_g, accumulated.  Values go to out[f][s0 + i]; the
+// wave sums to row (s0 / B + tile) * (B / 64) + wave, columns 2 f, 2 f + 1.
+__device__ __forceinline__ void freq_tile(const KArgs &a, int64_t tile, int f) {
+    const int tid = threadIdx.x, B = blockDim.x, lane = tid & 63;
+    const int64_t i = tile * B + tid;
+    const bool active = i < a.n_chunk;
+    const int64_t row = (a.s0 / B + tile) * (B >> 6) + (tid >> 6);
+    double E[NE];
+#pragma unroll
+    for (int j = 0; j < NE; ++j) E[j] = a.work[(G + j) * a.ld + i];
+    double wr[NXA], wi[NXA], xr[D], xi[D];
+    load_freq(a, f, wr, wi);
+    reciprocals(E, wr, wi, xr, xi);
+    double acc_re = 0.0, acc_im = 0.0;
+    group_accumulate(xr, xi, a.work + i, a.ld, acc_re, acc_im);
+    if (active && a.out) {
+        double2 v;
+        v.x = acc_re;
+        v.y = acc_im;
+        reinterpret_cast<double2 *>(a.out)[static_cast<int64_t>(f) * a.n_e + a.s0 + i] = v;
+    }
+    if (a.partial)
+        ami::wave_store2(active ? acc_re : 0.0, active ? acc_im : 0.0, lane, a.partial + 2 * f * a.nrows + row,
+                         a.nrows);
+}
+#endif
+
 #if AMI_JIT_KERNELS & 8
 // Forward at complex energies (energy input; interleaved complex128 rows,
 // strides in complex elements).  The leaf arguments and the energy part of
@@ -490,7 +556,8 @@ __device__ __forceinline__ void cfwd_tile(const KArgs &a, int64_t tile) {
 
 // AMI_JIT_BLOCK lanes per block (the host launches with the same value);
 // AMI_JIT_KERNELS selects the forward (1), the adjoint (2), the Monte-Carlo
-// integrator (4), the forward at complex energies (8), or a sum of them
+// integrator (4), the forward at complex energies (8), the two passes of the
+// two-pass forward (16, 32), or a sum of them
 #if AMI_JIT_KERNELS & 1
 extern "C" __global__ __launch_bounds__(AMI_JIT_BLOCK) void ami_jit_fwd(ami::KArgs a) {
     amijit::fwd_tile<AMI_JIT_HUB>(a, blockIdx.x);
@@ -522,5 +589,23 @@ extern "C" __global__ __launch_bounds__(AMI_JIT_BLOCK) void ami_jit_mc(ami::KArg
 #if AMI_JIT_KERNELS & 8
 extern "C" __global__ __launch_bounds__(AMI_JIT_BLOCK) void ami_jit_cfwd(ami::KArgs a) {
     amijit::cfwd_tile(a, blockIdx.x);
+}
+#endif
+
+#ifndef AMI_JIT_SUMS_WAVES
+#define AMI_JIT_SUMS_WAVES 0
+#endif
+#if AMI_JIT_KERNELS & 16
+#if AMI_JIT_SUMS_WAVES > 0
+__attribute__((amdgpu_waves_per_eu(AMI_JIT_SUMS_WAVES)))
+#endif
+extern "C" __global__ __launch_bounds__(AMI_JIT_BLOCK) void ami_jit_sums(ami::KArgs a) {
+    amijit::sums_tile<AMI_JIT_HUB>(a, blockIdx.x);
+}
+#endif
+
+#if AMI_JIT_KERNELS & 32
+extern "C" __global__ __launch_bounds__(AMI_JIT_BLOCK) void ami_jit_freq(ami::KArgs a) {
+    amijit::freq_tile(a, blockIdx.x, blockIdx.y);
 }
 #endif

@@ -40,6 +40,11 @@ struct KArgs {
     // rows of the specialized kernels' partial sums (one per wave), stored
     // column by column: element (row r, column c) at [c * nrows + r]
     int64_t nrows;
+    // two-pass forward: a chunk of n_chunk samples starting at sample s0;
+    // work holds its group sums FT_g at [g * ld + i] and energies E_j at
+    // [(G + j) * ld + i] (ld a multiple of the block)
+    double *work;
+    int64_t ld, s0, n_chunk;
 };
 
 // Frequency rows one Monte-Carlo launch accumulates (the caller splits longer lists).

@@ -198,9 +198,9 @@ def test_adjoint_deterministic_and_sum_cotangent():
 
 
 def test_kernel_variants_agree():
-    """Every forward variant -- double tables, packed, specialized, and the
-    automatic choice -- meets the parity bar against the oracle on the same
-    inputs, and the automatic choice names what it ran."""
+    """Every forward variant -- double tables, packed, specialized (one or two
+    passes), and the automatic choice -- meets the parity bar against the
+    oracle on the same inputs, and the automatic choice names what it ran."""
     for order, i in ((3, 0), (4, 1), (5, 2), (6, 1)):
         d = random_self_energy(order, (0, order, i))
         beta = 5.0
@@ -212,8 +212,12 @@ def test_kernel_variants_agree():
         T = amd.Terms.from_diagram(d)
         ref, scale, dist = reference(d, Eh, wh, beta)
         names = {}
-        small = T.info()["T"] <= 1024
-        variants = [amd.VARIANT_TABLES, amd.VARIANT_PACKED, amd.VARIANT_AUTO]
+        inf = T.info()
+        small = inf["T"] <= 1024
+        # the specialized forward runs in two passes where the one-pass kernel
+        # would not hold its groups and reciprocals in registers
+        two = inf["T"] > 1024 or 2 * inf["G"] + 4 * inf["D"] > 128
+        variants = [amd.VARIANT_TABLES, amd.VARIANT_PACKED, amd.VARIANT_AUTO, amd.VARIANT_TWO_PASS]
         if small:
             variants.append(amd.VARIANT_SPECIALIZED)
         for v in variants:
@@ -224,11 +228,11 @@ def test_kernel_variants_agree():
             check(o.cpu().numpy(), ref, scale, dist, label=f"variant {v} order {order}")
         assert names[amd.VARIANT_TABLES] == "double tables"
         assert names[amd.VARIANT_PACKED].startswith("packed self-energy")
+        assert names[amd.VARIANT_TWO_PASS] == "specialized two-pass"
+        want = "specialized two-pass" if two else "specialized"
+        assert names[amd.VARIANT_AUTO] == want
         if small:
-            assert names[amd.VARIANT_SPECIALIZED] == "specialized"
-            assert names[amd.VARIANT_AUTO] == "specialized"
-        else:
-            assert names[amd.VARIANT_AUTO].startswith("packed self-energy")
+            assert names[amd.VARIANT_SPECIALIZED] == want
 
 
 def test_adjoint_empty_batch():
@@ -278,7 +282,8 @@ def test_value_and_gradient_in_one_pass(variant):
 
 def test_auto_adjoint_falls_back_above_its_limit():
     """AUTO runs the specialized adjoint up to 128 terms and the packed one
-    above; a forced variant that cannot serve the call fails it."""
+    above (the forward of a solution above 1024 terms in two passes); a forced
+    variant that cannot serve the call fails it."""
     small = amd.Terms.from_diagram(random_self_energy(4, (0, 4, 1)))
     large = amd.Terms.from_diagram(random_self_energy(5, (0, 5, 0)))
     huge = amd.Terms.from_diagram(random_self_energy(6, (5, 6, 0)))
@@ -290,11 +295,14 @@ def test_auto_adjoint_falls_back_above_its_limit():
         amd.evaluate_adjoint(T, E, w, beta, grad_sum=gs)
         assert amd.last_variant().startswith(want), amd.last_variant()
     E = torch.from_numpy(uniform_energies(50, huge.info()["n_eps"], seed=30, a=3.0)).to(DEV)
+    # above 1024 terms the forward runs in two passes; the adjoint falls back
     amd.evaluate(huge, E, w, beta)
-    assert amd.last_variant().startswith("packed") and "not specialized" in amd.last_variant()
+    assert amd.last_variant() == "specialized two-pass"
+    amd.evaluate_adjoint(huge, E, w, beta, grad_sum=gs)
+    assert amd.last_variant().startswith("packed")
     huge.set_variant(amd.VARIANT_SPECIALIZED)
     with pytest.raises(amd.AmiError):
-        amd.evaluate(huge, E, w, beta)
+        amd.evaluate_adjoint(huge, E, w, beta, grad_sum=gs)
     huge.set_variant(amd.VARIANT_TABLES)
     with pytest.raises(amd.AmiError):
         amd.evaluate_adjoint(huge, E, w, beta, grad_sum=gs)
