@@ -132,10 +132,11 @@ def recorded_traffic(kernel: str, workload: str):
 
 
 def batch_section(args, torch, dev):
-    """Persistent mixed batch: 64 seeded diagrams of orders 2-6 (13/13/13/13/12),
-    16 external Matsubara frequencies and N samples each, one graph launch with
-    an autotuned tiling, against 64 separate launches of the packed and of the
-    plain kernel."""
+    """Mixed batch: 64 seeded diagrams of orders 2-6 (13/13/13/13/12), 16
+    external Matsubara frequencies and N samples each, one graph launch with
+    the autotuned choice (the specialized kernels, or the persistent packed
+    kernels with a tiling), against the best packed batch and 64 separate
+    launches of the specialized, the packed and the plain kernels."""
     import numpy as np
 
     import paper_2311_17189_amd as amd
@@ -158,6 +159,19 @@ def batch_section(args, torch, dev):
                       "out_sum": torch.empty((n_f,), dtype=torch.complex128, device=dev)})
     term_counts = [it["terms"].info()["T"] for it in items]
     te = float(sum(term_counts)) * n_e * n_f
+    # compile (or load from the disk cache) every diagram's specialized
+    # kernels, several at a time, before tuning
+    from concurrent.futures import ThreadPoolExecutor
+
+    def _spec(it):
+        try:
+            it["terms"].specialize(momentum=True)
+        except amd.AmiError:
+            pass                               # that item stays on the packed kernels
+    t0 = time.perf_counter()
+    with ThreadPoolExecutor(max_workers=8) as pool:
+        list(pool.map(_spec, items))
+    specialize_s = time.perf_counter() - t0
     t0 = time.perf_counter()
     best, timings = autotune(items, reps=3)
     tune_s = time.perf_counter() - t0
@@ -185,9 +199,13 @@ def batch_section(args, torch, dev):
             ts.append(a0.elapsed_time(a1))
         return sorted(ts)[len(ts) // 2]
 
+    auto_ms = timed(separate)               # AUTO: the specialized kernels, one launch after another
     for it in items:
         it["terms"].set_variant(amd.VARIANT_PACKED)
     sep_ms = timed(separate)
+    # the persistent packed batch (the kernels every item had before the
+    # specialized ones), best of the packed tilings the autotuner timed
+    packed_best = min(((v, k) for k, v in timings.items() if '"kernels": 1' in k), default=(None, None))
     for it in items:
         it["terms"].set_variant(amd.VARIANT_TABLES)
     plain_ms = timed(separate)
@@ -199,9 +217,12 @@ def batch_section(args, torch, dev):
         "terms_min": min(term_counts), "terms_max": max(term_counts), "terms_total": sum(term_counts),
         "term_evals": te,
         "batch_ms": batch_ms, "batch_term_evals_per_s": te / (batch_ms * 1e-3),
+        "separate_auto_ms": auto_ms, "separate_auto_term_evals_per_s": te / (auto_ms * 1e-3),
+        "packed_batch_ms": packed_best[0], "packed_batch_tuning": packed_best[1],
         "separate_packed_ms": sep_ms, "separate_packed_term_evals_per_s": te / (sep_ms * 1e-3),
         "separate_plain_ms": plain_ms, "separate_plain_term_evals_per_s": te / (plain_ms * 1e-3),
         "tuning": best, "tuning_candidates": len(timings), "tuning_s": tune_s, "info": info,
+        "specialize_s": specialize_s,
     }
 
 

@@ -433,25 +433,34 @@ typedef struct {
  *                the packed amiEvaluate makes for the largest item of each class
  *   waves_per_cu resident waves per compute unit of the persistent grid, 1..32
  *   tile_factor  each work item costs about tile_factor times the most
- *                expensive single tile of the batch, 1..1024 */
+ *                expensive single tile of the batch, 1..1024
+ *   kernels      0: every item whose specialized forward an AUTO evaluate call
+ *                would run (one or two passes) runs it, the others the packed
+ *                persistent kernels; 1: every item on the packed kernels
+ *                (block, waves_per_cu and tile_factor tune those only) */
 typedef struct {
     int32_t block;
     int32_t waves_per_cu;
     int32_t tile_factor;
-    int32_t reserved;
+    int32_t kernels;
 } AmiBatchTuning;
 
 /*
- * amiBatchCreate -- split the items into LDS classes (equal block size and
- * blocks per CU of their own packed launch, at most 16 classes), build each class's
- * work list (a diagram's sample tiles grouped into items of similar cost,
- * queued from most to least expensive), upload them with the item
- * descriptors, allocate the row-sum workspace, and instantiate the graph
- * (counter reset -> one persistent kernel per class -> fixed-order row sums).
- * All allocation happens here.  tuning may be NULL (defaults {0, 8, 1, 0}).
- * Every out value equals the packed per-diagram evaluate call's
- * (AMI_VARIANT_PACKED) bit for bit; out_sum does too when the class's block
- * size matches the one that call uses.
+ * amiBatchCreate -- with tuning.kernels = 0, compile and load the specialized
+ * forward of every item that has one (as AUTO would choose it); run those
+ * items once, then record their launches from up to four streams (largest
+ * first onto the least loaded stream) into a child graph.  Split the other
+ * items into LDS classes (equal block size and blocks per CU of their own
+ * packed launch, at most 16 classes), build each class's work list (a
+ * diagram's sample tiles grouped into items of similar cost, queued from most
+ * to least expensive), upload them with the item descriptors, allocate the
+ * row-sum workspace, and instantiate the graph (the child graph beside
+ * counter reset -> one persistent kernel per class -> fixed-order row sums).
+ * All allocation and compilation happens here.  tuning may be NULL (defaults
+ * {0, 8, 1, 0}).  An item on its specialized kernels gets out and out_sum
+ * equal to an AUTO evaluate call's bit for bit; an item on the packed kernels
+ * gets out equal to the packed per-diagram call's (AMI_VARIANT_PACKED) bit for
+ * bit, and out_sum too when the class's block size matches that call's.
  */
 AmiStatus amiBatchCreate(const AmiBatchItem *items, int32_t n_items, const AmiBatchTuning *tuning,
                          AmiBatch **out);
@@ -459,11 +468,12 @@ AmiStatus amiBatchCreate(const AmiBatchItem *items, int32_t n_items, const AmiBa
 /* Launch the batch graph on hip_stream (asynchronous; allocates nothing). */
 AmiStatus amiBatchRun(AmiBatch *batch, void *hip_stream);
 
-/* info[0..7]: items, work items, grid blocks (summed over the LDS classes),
+/* info[0..9]: items, work items, grid blocks (summed over the LDS classes),
  * block lanes (of the class with the most work items), LDS bytes per block
  * (largest class), row-sum columns, momentum path (1) or energy path (0),
- * LDS classes (persistent kernels in the graph). */
-AmiStatus amiBatchInfo(const AmiBatch *batch, int64_t info[8]);
+ * LDS classes (persistent kernels in the graph), items on their specialized
+ * kernels, streams their launches were recorded from. */
+AmiStatus amiBatchInfo(const AmiBatch *batch, int64_t info[10]);
 
 /* Release a batch (its device workspace and graph). */
 void amiBatchFree(AmiBatch *batch);

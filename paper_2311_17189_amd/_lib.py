@@ -54,7 +54,7 @@ class AmiBatchItem(ctypes.Structure):
 class AmiBatchTuning(ctypes.Structure):
     """Mirror of the C struct AmiBatchTuning."""
     _fields_ = [("block", ctypes.c_int32), ("waves_per_cu", ctypes.c_int32),
-                ("tile_factor", ctypes.c_int32), ("reserved", ctypes.c_int32)]
+                ("tile_factor", ctypes.c_int32), ("kernels", ctypes.c_int32)]
 
 
 def lib_path() -> str:
@@ -547,7 +547,8 @@ class Batch:
     and the outputs ``out`` (complex128 [N_F, N_E]) and/or ``out_sum``
     (complex128 [N_F]).  The tensors are referenced by the batch; every
     :meth:`run` evaluates what they hold.  ``tuning`` is a dict with ``block``,
-    ``waves_per_cu`` and ``tile_factor`` (see :mod:`.autotune`).
+    ``waves_per_cu``, ``tile_factor`` and ``kernels`` (0: specialized kernels
+    where AUTO would use them, 1: packed only; see :mod:`.autotune`).
     """
 
     def __init__(self, items, tuning=None):
@@ -595,7 +596,7 @@ class Batch:
         tun = None
         if tuning is not None:
             tun = AmiBatchTuning(int(tuning.get("block", 0)), int(tuning.get("waves_per_cu", 8)),
-                                 int(tuning.get("tile_factor", 1)), 0)
+                                 int(tuning.get("tile_factor", 1)), int(tuning.get("kernels", 0)))
         h = ctypes.c_void_p()
         _check(lib.amiBatchCreate(arr, len(items), ctypes.byref(tun) if tun is not None else None,
                                   ctypes.byref(h)))
@@ -606,10 +607,10 @@ class Batch:
         _check(load_library().amiBatchRun(self._h, _stream_ptr(stream)))
 
     def info(self) -> dict:
-        buf = np.zeros(8, dtype=np.int64)
+        buf = np.zeros(10, dtype=np.int64)
         _check(load_library().amiBatchInfo(self._h, buf.ctypes.data))
         keys = ["items", "work_items", "grid", "block", "lds_bytes", "rowsum_columns", "momentum_path",
-                "lds_classes"]
+                "lds_classes", "specialized_items", "capture_streams"]
         return {k: int(buf[i]) for i, k in enumerate(keys)}
 
     def close(self):

@@ -161,6 +161,9 @@ struct AmiBatch {
     size_t lds = 0;                        // largest over the classes
     int64_t n_work = 0;
     int64_t n_jobs = 0;
+    int n_spec = 0;                        // items on their specialized kernels
+    int n_streams = 0;                     // streams their launches were captured from
+    hipStream_t streams[4] = {};           // kept until the batch is freed (their workspaces)
     void *blob = nullptr;                  // descriptors, work list, jobs, counter, partial sums
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
@@ -169,10 +172,93 @@ struct AmiBatch {
 namespace ami {
 namespace {
 
+AmiStatus batch_fail_free(AmiBatch *b, AmiStatus st);
+
+// The items on their specialized kernels: each item's forward (as an AUTO
+// evaluate call launches it, row sums included) recorded from up to four
+// streams -- items assigned largest first to the least loaded stream, so
+// small diagrams run side by side -- into a graph added to the batch graph as
+// a child node beside the persistent kernels.  One eager run first sizes the
+// items' per-stream workspaces and loads their kernels, so the recorded
+// launches allocate nothing; the streams stay with the batch (its items'
+// workspaces are keyed by them).
+AmiStatus capture_specialized(AmiBatch *b, const AmiBatchItem *items, const std::vector<char> &spec, bool hub) {
+    std::vector<int> ids;
+    for (size_t i = 0; i < spec.size(); ++i)
+        if (spec[i]) ids.push_back(static_cast<int>(i));
+    std::vector<double> cost(spec.size(), 0.0);
+    for (int i : ids) cost[i] = sample_cost(items[i].terms, items[i].n_f) * static_cast<double>(items[i].n_e);
+    std::stable_sort(ids.begin(), ids.end(), [&](int x, int y) { return cost[x] > cost[y]; });
+    b->n_streams = std::min<int>(4, static_cast<int>(ids.size()));
+    for (int k = 0; k < b->n_streams; ++k) {
+        const hipError_t e = hipStreamCreateWithFlags(&b->streams[k], hipStreamNonBlocking);
+        if (e != hipSuccess) return hip_fail(e, "hipStreamCreateWithFlags");
+    }
+    std::vector<int> stream_of(spec.size(), 0);
+    std::vector<double> load(b->n_streams, 0.0);
+    for (int i : ids) {
+        const int k = static_cast<int>(std::min_element(load.begin(), load.end()) - load.begin());
+        stream_of[i] = k;
+        load[k] += cost[i];
+    }
+    auto launch_all = [&]() -> AmiStatus {
+        for (int i : ids) {
+            const AmiBatchItem &it = items[i];
+            KArgs a;
+            std::memset(&a, 0, sizeof(a));
+            set_inputs(a, it.terms, it.k, it.stride_k, it.q, it.t, it.mu, it.energies, it.stride_s, it.stride_i,
+                       it.ext_freqs, it.n_f, it.beta, it.e_reg, it.n_e);
+            a.out = it.out;
+            const AmiStatus st = launch_forward_as(it.terms, hub, a, it.out_sum, b->streams[stream_of[i]],
+                                                   AMI_VARIANT_AUTO);
+            if (st != AMI_OK) return st;
+        }
+        return AMI_OK;
+    };
+    AmiStatus st = launch_all();   // eager: workspaces sized, kernels loaded
+    for (int k = 0; k < b->n_streams && st == AMI_OK; ++k) {
+        const hipError_t e = hipStreamSynchronize(b->streams[k]);
+        if (e != hipSuccess) st = hip_fail(e, "hipStreamSynchronize");
+    }
+    if (st != AMI_OK) return st;
+    hipEvent_t ev[5] = {};
+    for (int k = 0; k <= b->n_streams; ++k) {
+        const hipError_t e = hipEventCreateWithFlags(&ev[k], hipEventDisableTiming);
+        if (e != hipSuccess) {
+            for (int j = 0; j < k; ++j) (void)hipEventDestroy(ev[j]);
+            return hip_fail(e, "hipEventCreateWithFlags");
+        }
+    }
+    hipStream_t s0 = b->streams[0];
+    hipGraph_t g = nullptr;
+    hipError_t e = hipStreamBeginCapture(s0, hipStreamCaptureModeRelaxed);
+    if (e == hipSuccess) {
+        e = hipEventRecord(ev[0], s0);                                  // fork
+        for (int k = 1; k < b->n_streams && e == hipSuccess; ++k) e = hipStreamWaitEvent(b->streams[k], ev[0], 0);
+        if (e == hipSuccess) st = launch_all();
+        for (int k = 1; k < b->n_streams && e == hipSuccess; ++k) {   // join
+            e = hipEventRecord(ev[k], b->streams[k]);
+            if (e == hipSuccess) e = hipStreamWaitEvent(s0, ev[k], 0);
+        }
+        const hipError_t e2 = hipStreamEndCapture(s0, &g);                // always ends the capture
+        if (e == hipSuccess) e = e2;
+    }
+    for (int k = 0; k <= b->n_streams; ++k) (void)hipEventDestroy(ev[k]);
+    if (e == hipSuccess && st == AMI_OK) {
+        hipGraphNode_t node = nullptr;
+        e = hipGraphAddChildGraphNode(&node, b->graph, nullptr, 0, g);
+    }
+    if (g) (void)hipGraphDestroy(g);
+    if (st != AMI_OK) return st;
+    return e == hipSuccess ? AMI_OK : hip_fail(e, "capture of the specialized items");
+}
+
 AmiStatus batch_fail_free(AmiBatch *b, AmiStatus st) {
     if (b->exec) (void)hipGraphExecDestroy(b->exec);
     if (b->graph) (void)hipGraphDestroy(b->graph);
     if (b->blob) (void)hipFree(b->blob);
+    for (int k = 0; k < b->n_streams; ++k)
+        if (b->streams[k]) (void)hipStreamDestroy(b->streams[k]);
     delete b;
     return st;
 }
@@ -195,20 +281,22 @@ AmiStatus amiBatchCreate(const AmiBatchItem *items, int32_t n_items, const AmiBa
     if (tun.tile_factor < 1 || tun.tile_factor > 1024) return fail(AMI_E_ARG, "tile_factor must be in 1..1024");
     if (tun.block != 0 && tun.block != 64 && tun.block != 128 && tun.block != 256)
         return fail(AMI_E_ARG, "block must be 0 (automatic), 64, 128 or 256");
+    if (tun.kernels != 0 && tun.kernels != 1) return fail(AMI_E_ARG, "kernels must be 0 or 1");
     const bool hub = items[0].k != nullptr;
     int dev = 0;
     hipError_t e = hipGetDevice(&dev);
     if (e != hipSuccess) return hip_fail(e, "hipGetDevice");
 
-    // per-item checks and descriptors
+    // per-item checks and descriptors; with kernels = 0 an item whose
+    // specialized forward AUTO would run takes it (compiled and loaded here)
     std::vector<BatchDesc> desc(n_items);
+    std::vector<char> spec(n_items, 0);
     for (int i = 0; i < n_items; ++i) {
         const AmiBatchItem &it = items[i];
         AmiTerms *t = it.terms;
         if (!t) return fail(AMI_E_ARG, "item " + std::to_string(i) + ": terms is NULL");
         if ((it.k != nullptr) != hub)
             return fail(AMI_E_ARG, "all items must use the same path (momenta or energies)");
-        if (!t->tab.packable) return fail(AMI_E_UNSUPPORTED, "item " + std::to_string(i) + ": not in packed form");
         if (t->n_eps > kMaxEpsDev || t->n_ext > kMaxExt) return fail(AMI_E_UNSUPPORTED, "item shape too large");
         if (it.n_e < 1) return fail(AMI_E_ARG, "item " + std::to_string(i) + ": n_e must be >= 1");
         if (it.n_f < 1 || it.n_f > (1 << 24)) return fail(AMI_E_ARG, "n_f must be in 1..2^24");
@@ -224,6 +312,9 @@ AmiStatus amiBatchCreate(const AmiBatchItem *items, int32_t n_items, const AmiBa
         DeviceTables *dt = nullptr;
         AmiStatus st = upload(t, &dt);
         if (st != AMI_OK) return st;
+        spec[i] = tun.kernels == 0 && specialized_forward_ready(t, hub, static_cast<int>(it.n_f));
+        if (!spec[i] && !t->tab.packable)
+            return fail(AMI_E_UNSUPPORTED, "item " + std::to_string(i) + ": no specialized kernel and not in packed form");
         BatchDesc &d = desc[i];
         std::memset(&d, 0, sizeof(d));
         d.a.tb = packed_tabs(t, dt);
@@ -257,11 +348,12 @@ AmiStatus amiBatchCreate(const AmiBatchItem *items, int32_t n_items, const AmiBa
     // per-diagram call picks, grouped by (block, resident blocks per CU), so
     // that every item runs at the occupancy of its own launch; classes in
     // order of per-lane LDS need, the last one taking the rest past kMaxClasses
-    std::vector<int> order(n_items);
-    std::vector<int> slots(n_items);
+    std::vector<int> order;
+    std::vector<int> slots(n_items, 0);
     std::vector<LaunchShape> own(n_items);
     for (int i = 0; i < n_items; ++i) {
-        order[i] = i;
+        if (spec[i]) continue;
+        order.push_back(i);
         slots[i] = fwd_slots(items[i].terms->tab);
         AmiStatus st = pick_shape(slots[i], own[i]);
         if (st != AMI_OK) return st;
@@ -288,7 +380,7 @@ AmiStatus amiBatchCreate(const AmiBatchItem *items, int32_t n_items, const AmiBa
         cls.back().items.push_back(i);
         cls.back().max_slots = std::max(cls.back().max_slots, slots[i]);
     }
-    std::vector<int> cls_of(n_items);
+    std::vector<int> cls_of(n_items, -1);
     for (size_t c = 0; c < cls.size(); ++c) {
         Class &k = cls[c];
         for (int i : k.items) cls_of[i] = static_cast<int>(c);
@@ -303,9 +395,10 @@ AmiStatus amiBatchCreate(const AmiBatchItem *items, int32_t n_items, const AmiBa
     }
 
     // work items per class and row-sum jobs
-    std::vector<double> tile_cost(n_items);
-    std::vector<int64_t> tiles(n_items);
+    std::vector<double> tile_cost(n_items, 0.0);
+    std::vector<int64_t> tiles(n_items, 0);
     for (int i = 0; i < n_items; ++i) {
+        if (spec[i]) continue;
         const int blk = cls[cls_of[i]].ls.block;
         tiles[i] = (items[i].n_e + blk - 1) / blk;
         tile_cost[i] = sample_cost(items[i].terms, items[i].n_f) * blk;
@@ -318,7 +411,7 @@ AmiStatus amiBatchCreate(const AmiBatchItem *items, int32_t n_items, const AmiBa
     size_t partial_total = 0;
     std::vector<size_t> partial_off(n_items, 0);
     for (int i = 0; i < n_items; ++i)
-        if (items[i].out_sum) {
+        if (items[i].out_sum && !spec[i]) {
             partial_off[i] = partial_total;
             partial_total += static_cast<size_t>(tiles[i]) * items[i].n_f * 2;
         }
@@ -358,7 +451,7 @@ AmiStatus amiBatchCreate(const AmiBatchItem *items, int32_t n_items, const AmiBa
     const size_t off_jobs = (off_work + sz_work + 255) & ~size_t(255);
     size_t n_jobs = 0;
     for (int i = 0; i < n_items; ++i)
-        if (items[i].out_sum) n_jobs += 2 * static_cast<size_t>(items[i].n_f);
+        if (items[i].out_sum && !spec[i]) n_jobs += 2 * static_cast<size_t>(items[i].n_f);
     const size_t sz_jobs = sizeof(RowSumJob) * std::max<size_t>(n_jobs, 1);
     const size_t off_ctr = (off_jobs + sz_jobs + 255) & ~size_t(255);
     const size_t off_part = off_ctr + ((sizeof(unsigned int) * kCounterStride * kMaxClasses + 255) & ~size_t(255));
@@ -372,6 +465,9 @@ AmiStatus amiBatchCreate(const AmiBatchItem *items, int32_t n_items, const AmiBa
     b->n_classes = static_cast<int>(cls.size());
     b->n_work = static_cast<int64_t>(wl.size());
     b->n_jobs = static_cast<int64_t>(n_jobs);
+    int n_spec = 0;
+    for (int i = 0; i < n_items; ++i) n_spec += spec[i] ? 1 : 0;
+    b->n_spec = n_spec;
     int64_t most = -1;
     for (const Class &k : cls) {
         b->grid += k.grid;
@@ -387,8 +483,8 @@ AmiStatus amiBatchCreate(const AmiBatchItem *items, int32_t n_items, const AmiBa
     double *partial = reinterpret_cast<double *>(base + off_part);
     std::vector<RowSumJob> jobs;
     for (int i = 0; i < n_items; ++i) {
-        desc[i].a.partial = items[i].out_sum ? partial + partial_off[i] : nullptr;
-        if (items[i].out_sum)
+        desc[i].a.partial = items[i].out_sum && !spec[i] ? partial + partial_off[i] : nullptr;
+        if (items[i].out_sum && !spec[i])
             for (int c = 0; c < 2 * items[i].n_f; ++c) {
                 RowSumJob j;
                 j.partial = partial + partial_off[i];
@@ -461,6 +557,10 @@ AmiStatus amiBatchCreate(const AmiBatchItem *items, int32_t n_items, const AmiBa
         e = hipGraphAddKernelNode(&n_sum, b->graph, n_main.data(), n_main.size(), &p);
         if (e != hipSuccess) return batch_fail_free(b, hip_fail(e, "graph row-sum node"));
     }
+    if (n_spec > 0) {
+        const AmiStatus st = capture_specialized(b, items, spec, hub);
+        if (st != AMI_OK) return batch_fail_free(b, st);
+    }
     e = hipGraphInstantiate(&b->exec, b->graph, nullptr, nullptr, 0);
     if (e != hipSuccess) return batch_fail_free(b, hip_fail(e, "hipGraphInstantiate"));
     *out = b;
@@ -480,7 +580,7 @@ AmiStatus amiBatchRun(AmiBatch *b, void *hip_stream) {
     return AMI_OK;
 }
 
-AmiStatus amiBatchInfo(const AmiBatch *b, int64_t info[8]) {
+AmiStatus amiBatchInfo(const AmiBatch *b, int64_t info[10]) {
     using namespace ami;
     clear_error();
     if (!b || !info) return fail(AMI_E_ARG, "NULL argument");
@@ -492,6 +592,8 @@ AmiStatus amiBatchInfo(const AmiBatch *b, int64_t info[8]) {
     info[5] = b->n_jobs;
     info[6] = b->hub ? 1 : 0;
     info[7] = b->n_classes;
+    info[8] = b->n_spec;
+    info[9] = b->n_streams;
     return AMI_OK;
 }
 
@@ -503,6 +605,8 @@ void amiBatchFree(AmiBatch *b) {
     if (b->exec) (void)hipGraphExecDestroy(b->exec);
     if (b->graph) (void)hipGraphDestroy(b->graph);
     if (b->blob) (void)hipFree(b->blob);
+    for (int k = 0; k < b->n_streams; ++k)
+        if (b->streams[k]) (void)hipStreamDestroy(b->streams[k]);
     if (have) (void)hipSetDevice(cur);
     delete b;
 }

@@ -375,8 +375,8 @@ constexpr int kTwoPassMaxFreqs = 65535;
 // Which kernels serve a call (AMI_VARIANT_* of the handle); for the
 // specialized path also loads them.  AUTO falls back and records why.
 AmiStatus choose_path(AmiTerms *t, bool hub, bool adjoint, Path &p, void **jit_fn, std::string &note,
-                      void **jit_fn2 = nullptr, int n_f = 1) {
-    const int v = t->variant;
+                      void **jit_fn2 = nullptr, int n_f = 1, int variant = -1) {
+    const int v = variant >= 0 ? variant : t->variant;
     note.clear();
     // the forward of a large solution: two passes (AUTO and SPECIALIZED when the
     // one-pass kernel would not fit its registers; TWO_PASS always)
@@ -459,7 +459,9 @@ hipError_t launch_jit(void *fn, int64_t nblocks, int block, hipStream_t stream, 
     void *params[] = {&a};
     const hipFunction_t f = static_cast<hipFunction_t>(fn);
     hipEvent_t t0 = nullptr, t1 = nullptr;
-    if (nblocks * block <= 0xffffffffLL && timer_pair(t0, t1))
+    hipStreamCaptureStatus cap = hipStreamCaptureStatusNone;
+    if (g_timer.on) (void)hipStreamIsCapturing(stream, &cap);   // no timer events inside a capture
+    if (nblocks * block <= 0xffffffffLL && cap == hipStreamCaptureStatusNone && timer_pair(t0, t1))
         return hipExtModuleLaunchKernel(f, static_cast<uint32_t>(nblocks * block), static_cast<uint32_t>(gy), 1,
                                         static_cast<uint32_t>(block), 1, 1, 0, stream, params, nullptr, t0, t1, 0);
     return hipModuleLaunchKernel(f, static_cast<unsigned>(nblocks), static_cast<unsigned>(gy), 1,
@@ -508,7 +510,7 @@ AmiStatus launch_two_pass(AmiTerms *t, DeviceTables *dt, bool hub, KArgs &a, dou
     return AMI_OK;
 }
 
-AmiStatus launch_forward(AmiTerms *t, bool hub, KArgs &a, double *out_sum, hipStream_t stream) {
+AmiStatus launch_forward(AmiTerms *t, bool hub, KArgs &a, double *out_sum, hipStream_t stream, int variant = -1) {
     DeviceTables *dt = nullptr;
     AmiStatus st = upload(t, &dt);
     if (st != AMI_OK) return st;
@@ -517,7 +519,7 @@ AmiStatus launch_forward(AmiTerms *t, bool hub, KArgs &a, double *out_sum, hipSt
     Path path;
     void *jit_fn = nullptr, *jit_fn2 = nullptr;
     std::string note;
-    st = choose_path(t, hub, false, path, &jit_fn, note, &jit_fn2, a.n_f);
+    st = choose_path(t, hub, false, path, &jit_fn, note, &jit_fn2, a.n_f, variant);
     if (st != AMI_OK) return st;
     if (path == Path::TWO_PASS) return launch_two_pass(t, dt, hub, a, out_sum, jit_fn, jit_fn2, stream);
     LaunchShape ls;
@@ -695,6 +697,29 @@ void set_common(KArgs &a, const double *ext_freqs, int64_t n_f, double beta, dou
 }
 
 }  // namespace
+
+AmiStatus launch_forward_as(AmiTerms *t, bool hub, KArgs &a, double *out_sum, hipStream_t stream, int variant) {
+    return launch_forward(t, hub, a, out_sum, stream, variant);
+}
+
+bool specialized_forward_ready(AmiTerms *t, bool hub, int n_f) {
+    Path p;
+    void *f1 = nullptr, *f2 = nullptr;
+    std::string note;
+    const AmiStatus st = choose_path(t, hub, false, p, &f1, note, &f2, n_f, AMI_VARIANT_AUTO);
+    clear_error();
+    return st == AMI_OK && (p == Path::SPECIALIZED || p == Path::TWO_PASS);
+}
+
+void set_inputs(KArgs &a, const AmiTerms *t, const double *k, int64_t stride_k, const double *q, double hop_t,
+                double mu, const double *energies, int64_t stride_s, int64_t stride_i, const double *ext_freqs,
+                int64_t n_f, double beta, double e_reg, int64_t n_e) {
+    if (k) set_momenta(a, t, k, stride_k, q, hop_t, mu);
+    a.energies = energies;
+    a.stride_s = stride_s;
+    a.stride_i = stride_i;
+    set_common(a, ext_freqs, n_f, beta, e_reg, n_e);
+}
 
 }  // namespace ami
 

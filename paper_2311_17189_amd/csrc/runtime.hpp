@@ -8,6 +8,7 @@
 
 #include "ami_internal.hpp"
 #include "device_common.hpp"
+#include "kargs.hpp"
 
 namespace ami {
 
@@ -23,5 +24,17 @@ AmiStatus upload(AmiTerms *t, DeviceTables **out);
 AmiStatus pick_shape(int slots, LaunchShape &ls);
 PackedTabs packed_tabs(const AmiTerms *t, const DeviceTables *dt);
 int fwd_slots(const Tables &tb);
+
+// The forward of one handle as an evaluate call with the given variant
+// (AMI_VARIANT_*) would launch it on `stream`, row sums included.
+AmiStatus launch_forward_as(AmiTerms *t, bool hub, KArgs &a, double *out_sum, hipStream_t stream, int variant);
+// Whether AUTO would run the specialized (one- or two-pass) forward of t for
+// n_f frequency rows; compiles and loads its kernels on the current device.
+bool specialized_forward_ready(AmiTerms *t, bool hub, int n_f);
+// The argument block of an evaluate call: momenta (k non-NULL; q reduced
+// modulo 2 pi, its sin and cos) or energies, frequencies, beta, regulator.
+void set_inputs(KArgs &a, const AmiTerms *t, const double *k, int64_t stride_k, const double *q, double hop_t,
+                double mu, const double *energies, int64_t stride_s, int64_t stride_i, const double *ext_freqs,
+                int64_t n_f, double beta, double e_reg, int64_t n_e);
 
 }  // namespace ami

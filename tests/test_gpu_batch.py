@@ -1,6 +1,9 @@
-"""Persistent mixed-diagram batch (one HIP graph launch over many diagrams):
-outputs bitwise equal to the per-diagram launches, stable across graph
-replays, row sums consistent, the autotuner, and host-side errors."""
+"""Mixed-diagram batch (one HIP graph launch over many diagrams), in both
+modes -- every item on its specialized kernels where AUTO would run them
+(recorded launches in a child graph), or every item on the persistent packed
+kernels: outputs bitwise equal to the per-diagram launches of the same
+kernels, stable across graph replays, row sums consistent, the autotuner,
+and host-side errors."""
 import numpy as np
 import pytest
 
@@ -15,13 +18,14 @@ amd = pytest.importorskip("paper_2311_17189_amd")
 DEV = "cuda"
 
 
-def _mixed_items(n_per_order=2, orders=(2, 3, 4, 5, 6), n_f=4, beta=5.0, energies=False, seed=0):
+def _mixed_items(n_per_order=2, orders=(2, 3, 4, 5, 6), n_f=4, beta=5.0, energies=False, seed=0, kernels=1):
     items = []
     for order in orders:
         for i in range(n_per_order):
             d = random_self_energy(order, (seed, order, i))
             T = amd.Terms.from_diagram(d)
-            T.set_variant(amd.VARIANT_PACKED)    # the per-diagram kernels the batch shares
+            # the per-diagram kernels the batch shares
+            T.set_variant(amd.VARIANT_PACKED if kernels == 1 else amd.VARIANT_AUTO)
             n_e = 300 + 517 * i + 131 * order            # ragged sizes
             w = torch.from_numpy(matsubara_freqs(n_f, beta)).to(DEV)
             it = {"terms": T, "ext_freqs": w, "beta": beta, "diagram": d,
@@ -45,30 +49,40 @@ def _per_diagram(it):
 
 
 @pytest.mark.parametrize("energies", [False, True])
-@pytest.mark.parametrize("tuning", [None, {"block": 64, "waves_per_cu": 4, "tile_factor": 1},
-                                    {"block": 128, "waves_per_cu": 16, "tile_factor": 4}])
+@pytest.mark.parametrize("tuning", [None, {"block": 64, "waves_per_cu": 4, "tile_factor": 1, "kernels": 1},
+                                    {"block": 128, "waves_per_cu": 16, "tile_factor": 4, "kernels": 1}])
 def test_batch_bitwise_equals_per_diagram(energies, tuning):
-    items = _mixed_items(energies=energies)
+    kernels = 0 if tuning is None else tuning["kernels"]
+    items = _mixed_items(energies=energies, kernels=kernels)
     b = amd.Batch(items, tuning)
     b.run()
     torch.cuda.synchronize()
     info = b.info()
-    assert info["items"] == len(items) and info["work_items"] >= len(items)
-    assert info["lds_classes"] >= 2          # orders 2..6 span more than one LDS class
+    assert info["items"] == len(items)
+    if kernels == 1:
+        assert info["work_items"] >= len(items) and info["specialized_items"] == 0
+        assert info["lds_classes"] >= 2          # orders 2..6 span more than one LDS class
+    else:
+        assert info["specialized_items"] == len(items) and info["lds_classes"] == 0
+        assert info["capture_streams"] == 4
     for it in items:
         ref_out, ref_sum = _per_diagram(it)
         torch.cuda.synchronize()
         assert torch.equal(it["out"], ref_out)
-        # the row sum runs over the batch's tiles; it equals the per-diagram
-        # one bit for bit when the tile size matches, else to rounding
-        assert torch.allclose(it["out_sum"], ref_sum, rtol=1e-12, atol=1e-15 * float(ref_out.abs().sum()))
+        if kernels == 0:
+            assert torch.equal(it["out_sum"], ref_sum)       # the same kernels and reduction
+        else:
+            # the row sum runs over the batch's tiles; it equals the per-diagram
+            # one bit for bit when the tile size matches, else to rounding
+            assert torch.allclose(it["out_sum"], ref_sum, rtol=1e-12, atol=1e-15 * float(ref_out.abs().sum()))
 
 
-def test_graph_replays_are_identical():
+@pytest.mark.parametrize("kernels", [0, 1])
+def test_graph_replays_are_identical(kernels):
     """Replay the batch graph several times with other GPU work and
     synchronizations in between; every replay gives the same bits."""
-    items = _mixed_items(n_per_order=1)
-    b = amd.Batch(items, {"block": 64, "waves_per_cu": 8, "tile_factor": 2})
+    items = _mixed_items(n_per_order=1, kernels=kernels)
+    b = amd.Batch(items, {"block": 64, "waves_per_cu": 8, "tile_factor": 2, "kernels": kernels})
     b.run()
     torch.cuda.synchronize()
     first = [(it["out"].clone(), it["out_sum"].clone()) for it in items]
@@ -86,11 +100,12 @@ def test_graph_replays_are_identical():
             assert torch.equal(it["out_sum"], s)
 
 
-def test_batch_outputs_only_sums():
-    items = _mixed_items(n_per_order=1)
+@pytest.mark.parametrize("kernels", [0, 1])
+def test_batch_outputs_only_sums(kernels):
+    items = _mixed_items(n_per_order=1, kernels=kernels)
     for it in items:
         it["out"] = None
-    b = amd.Batch(items)
+    b = amd.Batch(items, {"kernels": kernels})
     b.run()
     torch.cuda.synchronize()
     for it in items:
@@ -102,8 +117,8 @@ def test_batch_outputs_only_sums():
 def test_autotuner_picks_a_working_tuning(tmp_path):
     from paper_2311_17189_amd.autotune import autotune
     items = _mixed_items(n_per_order=1, orders=(2, 4, 6))
-    cands = [{"block": 64, "waves_per_cu": 4, "tile_factor": 1},
-             {"block": 0, "waves_per_cu": 8, "tile_factor": 4}]
+    cands = [{"block": 64, "waves_per_cu": 4, "tile_factor": 1, "kernels": 1},
+             {"block": 0, "waves_per_cu": 8, "tile_factor": 4, "kernels": 1}]
     best, timings = autotune(items, cands, reps=2, path=str(tmp_path / "tune.json"))
     assert best in cands and len(timings) == 2
     again, _ = autotune(items, cands, reps=2, path=str(tmp_path / "tune.json"))
@@ -127,3 +142,5 @@ def test_batch_host_errors():
         amd.Batch(mixed)
     with pytest.raises(amd.AmiError):
         amd.Batch(items, {"block": 96, "waves_per_cu": 8, "tile_factor": 1})
+    with pytest.raises(amd.AmiError):
+        amd.Batch(items, {"kernels": 2})
