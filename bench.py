@@ -247,7 +247,8 @@ def next_rows_section(args, torch, dev, stream):
     """The rows built beyond the main path, each measured on the order-4
     workload: complex energies (forward, energy input), poles of higher order
     (the order-4 topology with one internal line taken twice, momentum input,
-    forward) and graph input (label + construct from the 4-column form)."""
+    forward) and graph input (label + construct from the 4-column form); and a
+    large order-6 solution through the two-pass forward."""
     import numpy as np
 
     import paper_2311_17189_amd as amd
@@ -305,6 +306,30 @@ def next_rows_section(args, torch, dev, stream):
             "flops_per_launch": fl["total"], "frac_fp64_peak": fl["total"] / (kms * 1e-3) / rl.PEAK_FP64_VECTOR}
     except amd.AmiError as e:
         res["multipole"] = f"not run: {e}"
+    # a large solution through the two-pass forward: order 6, 2804 terms, the
+    # batch's frequency count
+    try:
+        dl = random_self_energy(6, (5, 6, 2))
+        T = amd.Terms.from_diagram(dl)
+        T.specialize(momentum=True)
+        st = rl.structure_from_canonical(T.canonical())
+        n_l, n_fl = 200_000, 16
+        wl = torch.from_numpy(matsubara_freqs(n_fl, args.beta)).to(dev)
+        k = torch.from_numpy(k_samples(n_l, dl.n_int, seed=(103, 6, 2))).to(dev)
+        q = np.array(DEFAULT_Q)
+        out = torch.empty((n_fl, n_l), dtype=torch.complex128, device=dev)
+        osum = torch.empty((n_fl,), dtype=torch.complex128, device=dev)
+        ms, _ = _timed_kernel(torch, amd, stream, lambda: amd.evaluate_hubbard(
+            T, k, q, 1.0, 0.0, wl, args.beta, out=out, out_sum=osum, want_sum=True, stream=stream), 5)
+        fl = rl.specialized_forward_flops(st, n_l, n_fl, dl.alpha)
+        res["large_two_pass"] = {
+            "workload": f"order-6 topology (5, 6, 2), {st.T} terms, {n_l} k-samples, {n_fl} Matsubara frequencies, "
+                        "out + row sums",
+            "kernel": amd.last_variant(), "ms": ms,
+            "term_evals_per_s": float(st.T) * n_l * n_fl / (ms * 1e-3),
+            "flops_per_call": fl["total"], "frac_fp64_peak": fl["total"] / (ms * 1e-3) / rl.PEAK_FP64_VECTOR}
+    except amd.AmiError as e:
+        res["large_two_pass"] = f"not run: {e}"
     # graph input: label and construct, host only
     g = {}
     for order, i in ((args.order, args.diagram), (6, 0)):

@@ -294,7 +294,10 @@ AmiStatus amiEvaluateHubbardAdjoint(AmiTerms *terms,
  * (s mod 2^32, s div 2^32, b, 0), b = 0, 1, ..., and key (seed mod 2^32,
  * seed div 2^32), component c from word c as (u - 1/2) * 2 pi with
  * u = (word + 1/2) / 2^32, i.e. uniform on (-pi, pi).  No sample touches
- * device memory.
+ * device memory -- except for solutions AUTO evaluates in two passes (more
+ * than 1024 terms, up to 4096, or 2 G + 4 D > 128): the first pass draws the
+ * momenta and stores each sample's group sums and energies in the chunked
+ * workspace, the second accumulates the sums per frequency row.
  *   q, t, mu      as amiEvaluateHubbard
  *   ext_freqs     device complex128 [n_f][n_ext], 1 <= n_f <= 8 (split longer lists)
  *   sums          device float64 [n_f][4]: sum over the samples of Re I, Im I,
@@ -303,8 +306,8 @@ AmiStatus amiEvaluateHubbardAdjoint(AmiTerms *terms,
  *                 the squares give its standard error.
  * The sums are reduced in a fixed order for a given device: repeated calls give
  * the same bits.  Needs the specialized kernels (AMI_E_UNSUPPORTED beyond
- * their limits, whatever the handle's variant); the kernel is compiled on first
- * use.  Uses the handle's per-stream workspace.
+ * their limits, whatever the handle's variant); the kernels are compiled on
+ * first use.  Uses the handle's per-stream workspace.
  */
 AmiStatus amiIntegrateHubbard(AmiTerms *terms, int64_t n_samples, uint64_t seed,
                               const double *q, double t, double mu,

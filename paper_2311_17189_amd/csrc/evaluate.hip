@@ -483,7 +483,8 @@ AmiStatus launch_two_pass(AmiTerms *t, DeviceTables *dt, bool hub, KArgs &a, dou
     int64_t ld = chunk_bytes / (cols * static_cast<int64_t>(sizeof(double))) / B * B;
     ld = std::max<int64_t>(B, std::min<int64_t>(ld, tiles * B));
     double *ws = nullptr;
-    const size_t n_part = out_sum ? static_cast<size_t>(rows) * a.n_f * 2 : 0;
+    const int ncols = a.mc ? 4 * a.n_f : 2 * a.n_f;   // per-wave sums (Monte Carlo: with squares)
+    const size_t n_part = out_sum ? static_cast<size_t>(rows) * ncols : 0;
     AmiStatus st = workspace(t, dt, stream, (static_cast<size_t>(cols) * ld + n_part) * sizeof(double), &ws);
     if (st != AMI_OK) return st;
     a.work = ws;
@@ -502,7 +503,7 @@ AmiStatus launch_two_pass(AmiTerms *t, DeviceTables *dt, bool hub, KArgs &a, dou
     g_last_variant = "specialized two-pass";
     if (e != hipSuccess) return hip_fail(e, "two-pass launch");
     if (out_sum) {
-        hipLaunchKernelGGL(ami_colsum_kernel, dim3(2 * a.n_f), dim3(kRedThreads), 0, stream, a.partial, rows,
+        hipLaunchKernelGGL(ami_colsum_kernel, dim3(ncols), dim3(kRedThreads), 0, stream, a.partial, rows,
                            static_cast<int64_t>(1), rows, out_sum);
         e = hipGetLastError();
         if (e != hipSuccess) return hip_fail(e, "row-sum launch");
@@ -901,6 +902,21 @@ AmiStatus amiIntegrateHubbard(AmiTerms *t, int64_t n_samples, uint64_t seed, con
     DeviceTables *dt = nullptr;
     st = upload(t, &dt);
     if (st != AMI_OK) return st;
+    if (jit_prefers_two_pass(t)) {
+        // large solutions: the two-pass kernels, momenta drawn in the first
+        void *f1 = nullptr, *f2 = nullptr;
+        st = jit_get(t, true, kJitSumsPass, &f1);
+        if (st == AMI_OK) st = jit_get(t, true, kJitFreqPass, &f2);
+        if (st != AMI_OK) return st;
+        if (n_samples == 0) return fill(sums, 4 * n_f, stream);
+        KArgs a;
+        std::memset(&a, 0, sizeof(a));
+        set_momenta(a, t, nullptr, 0, q, hop_t, mu);
+        set_common(a, ext_freqs, n_f, beta, e_reg, n_samples);
+        a.seed = seed;
+        a.mc = 1;
+        return launch_two_pass(t, dt, true, a, sums, f1, f2, stream);
+    }
     void *fn = nullptr;
     st = jit_get(t, true, kJitMonteCarlo, &fn);
     if (st != AMI_OK) return st;

@@ -41,6 +41,29 @@ constexpr int kParkChain = AMI_JIT_HUB ? 3 * NG : 0;
 constexpr bool kParkDv = AMI_JIT_PARK_DV;
 constexpr int kParkCols = kParkChain + (kParkDv ? L : 0);
 
+// The momenta of Monte-Carlo sample s: the words of Philox4x32-10 blocks
+// b = 0, 1, ... with counter (s mod 2^32, s div 2^32, b, 0) and key = the
+// 64-bit seed, component c = 2 l + (0: x, 1: y) from word c, each mapped to
+// (-pi, pi) (word_to_momentum).
+__device__ __forceinline__ void draw_momenta(const KArgs &a, int64_t s, double (&kx)[NIA], double (&ky)[NIA]) {
+    const uint32_t k0 = static_cast<uint32_t>(a.seed), k1 = static_cast<uint32_t>(a.seed >> 32);
+#pragma unroll
+    for (int b = 0; b < (2 * NI + 3) / 4; ++b) {
+        uint32_t c[4] = {static_cast<uint32_t>(s), static_cast<uint32_t>(static_cast<uint64_t>(s) >> 32),
+                         static_cast<uint32_t>(b), 0u};
+        ami::philox4x32_10(c, k0, k1);
+#pragma unroll
+        for (int w = 0; w < 4; ++w) {
+            const int comp = 4 * b + w;
+            if (comp < 2 * NI) {
+                const double v = ami::word_to_momentum(c[w]);
+                if (comp % 2 == 0) kx[comp / 2] = v;
+                else ky[comp / 2] = v;
+            }
+        }
+    }
+}
+
 // E from the sample's energies or momenta.  With KEEP (adjoint, momentum
 // input) sin K_jx, sin K_jy and cos K_jx + cos K_jy, needed only by the final
 // chain rule, are parked in LDS columns (park[(c NG + j) B + tid], c = 0, 1, 2)
@@ -365,27 +388,12 @@ __device__ __forceinline__ void mc_block(const KArgs &a) {
     const int tid = threadIdx.x, B = blockDim.x, lane = tid & 63;
     const int64_t row = static_cast<int64_t>(blockIdx.x) * (B >> 6) + (tid >> 6);
     const int64_t stride = static_cast<int64_t>(gridDim.x) * B;
-    const uint32_t k0 = static_cast<uint32_t>(a.seed), k1 = static_cast<uint32_t>(a.seed >> 32);
     double acc[4][ami::kMcMaxFreqs];
 #pragma unroll
     for (int f = 0; f < ami::kMcMaxFreqs; ++f) acc[0][f] = acc[1][f] = acc[2][f] = acc[3][f] = 0.0;
     for (int64_t s = static_cast<int64_t>(blockIdx.x) * B + tid; s < a.n_e; s += stride) {
         double kx[NIA], ky[NIA];
-#pragma unroll
-        for (int b = 0; b < (2 * NI + 3) / 4; ++b) {
-            uint32_t c[4] = {static_cast<uint32_t>(s), static_cast<uint32_t>(static_cast<uint64_t>(s) >> 32),
-                             static_cast<uint32_t>(b), 0u};
-            ami::philox4x32_10(c, k0, k1);
-#pragma unroll
-            for (int w = 0; w < 4; ++w) {
-                const int comp = 4 * b + w;
-                if (comp < 2 * NI) {
-                    const double v = ami::word_to_momentum(c[w]);
-                    if (comp % 2 == 0) kx[comp / 2] = v;
-                    else ky[comp / 2] = v;
-                }
-            }
-        }
+        draw_momenta(a, s, kx, ky);
         double E[NE], x[L], F[L], FM[L], FT[G];
         energies_from(a, kx, ky, E);
         leaf_args(E, x);
@@ -440,7 +448,13 @@ __device__ __forceinline__ void sums_tile(const KArgs &a, int64_t tile) {
     const int64_t i = tile * B + tid;
     const int64_t sc = a.s0 + (i < a.n_chunk ? i : a.n_chunk - 1);
     double E[NE];
-    energies<HUB, false>(a, sc, E, nullptr);
+    if (HUB && a.mc) {                  // Monte Carlo: the momenta of sample sc drawn here
+        double kx[NIA], ky[NIA];
+        draw_momenta(a, sc, kx, ky);
+        energies_from(a, kx, ky, E);
+    } else {
+        energies<HUB, false>(a, sc, E, nullptr);
+    }
     double x[L], F[L], FM[L];
     leaf_args(E, x);
 #pragma unroll
@@ -474,6 +488,13 @@ __device__ __forceinline__ void freq_tile(const KArgs &a, int64_t tile, int f) {
     reciprocals(E, wr, wi, xr, xi);
     double acc_re = 0.0, acc_im = 0.0;
     group_accumulate(xr, xi, a.work + i, a.ld, acc_re, acc_im);
+    if (a.mc) {                         // Monte Carlo: sums and sums of squares per frequency row
+        const double re = active ? acc_re : 0.0, im = active ? acc_im : 0.0;
+        double *dst = a.partial + 4 * f * a.nrows + row;
+        ami::wave_store2(re, im, lane, dst, a.nrows);
+        ami::wave_store2(re * re, im * im, lane, dst + 2 * a.nrows, a.nrows);
+        return;
+    }
     if (active && a.out) {
         double2 v;
         v.x = acc_re;

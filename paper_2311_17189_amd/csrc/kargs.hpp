@@ -45,6 +45,10 @@ struct KArgs {
     // [(G + j) * ld + i] (ld a multiple of the block)
     double *work;
     int64_t ld, s0, n_chunk;
+    // two-pass Monte-Carlo sums: the first pass draws sample s's momenta from
+    // the counter-based generator (seed), the second accumulates per frequency
+    // row sum Re I, sum Im I, sum (Re I)^2, sum (Im I)^2 (columns 4 f .. 4 f + 3)
+    int mc;
 };
 
 // Frequency rows one Monte-Carlo launch accumulates (the caller splits longer lists).

@@ -39,6 +39,37 @@ def test_mc_sums_match_oracle_on_the_same_draws(order, i, n, seed):
     assert np.all(np.abs(got - want) <= bound + 1e-300), (got, want, bound)
 
 
+@pytest.mark.parametrize("i,n,chunk", [(0, 600, 1 << 16), (9, 1500, 256 << 20)])
+def test_mc_two_pass_for_large_solutions(i, n, chunk):
+    """A solution evaluated in two passes (order 6): the first pass draws the
+    momenta, the sums match the oracle on the same draws; several chunks."""
+    d = random_self_energy(6, (5, 6, i))
+    T = amd.Terms.from_diagram(d)
+    inf = T.info()
+    assert inf["T"] > 1024 or 2 * inf["G"] + 4 * inf["D"] > 128
+    beta, t, mu = 5.0, 1.0, 0.1
+    q = np.array(DEFAULT_Q)
+    w = np.concatenate([matsubara_freqs(1, beta), real_freqs(1, 0.5, 0.5, 0.05)])
+    amd.set_two_pass_chunk_bytes(chunk)
+    try:
+        sums = amd.integrate_hubbard(T, n, 9, q, t, mu, torch.from_numpy(w).to(DEV), beta)
+        torch.cuda.synchronize()
+        assert amd.last_variant() == "specialized two-pass"
+        again = amd.integrate_hubbard(T, n, 9, q, t, mu, torch.from_numpy(w).to(DEV), beta)
+        torch.cuda.synchronize()
+    finally:
+        amd.set_two_pass_chunk_bytes(256 << 20)
+    assert torch.equal(sums, again)
+    got = sums.cpu().numpy()
+    k = draw_momenta(0, n, 2 * d.n_int, 9)
+    ref, scale, dist, _ = reference_hubbard(d, k, q, t, mu, w, beta)
+    tol = np.where(dist >= NEAR, TOL, TOL_NEAR) * scale
+    want = np.stack([ref.real.sum(1), ref.imag.sum(1), (ref.real ** 2).sum(1), (ref.imag ** 2).sum(1)], axis=1)
+    bound = np.stack([tol.sum(1), tol.sum(1), (2 * np.abs(ref) * tol).sum(1), (2 * np.abs(ref) * tol).sum(1)],
+                     axis=1)
+    assert np.all(np.abs(got - want) <= bound + 1e-300), (got, want, bound)
+
+
 def test_mc_deterministic_chunked_and_edge_sizes():
     d = random_self_energy(3, (0, 3, 0))
     T = amd.Terms.from_diagram(d)

@@ -2,7 +2,7 @@
 with Taylor-coefficient leaves and groups of unequal denominator lists, on the
 energy input, the momentum input and the in-kernel Monte-Carlo sums, against
 the oracle's multipole solution; the paths that do not take such solutions
-refuse them."""
+refuse them; the batch takes them on the specialized kernels."""
 import types
 
 import numpy as np
@@ -107,7 +107,13 @@ def test_multipole_refusals():
     with pytest.raises(amd.AmiError) as e:
         amd.evaluate_adjoint(T, E, w, 2.0, grad_out=cot)
     assert e.value.code == -7
+    # a batch takes the item on its specialized kernels (equal to the call
+    # above bit for bit); the packed-only batch refuses it
     o = torch.empty((2, 64), dtype=torch.complex128, device=DEV)
+    b = amd.Batch([{"terms": T, "energies": E, "ext_freqs": w, "beta": 2.0, "out": o}])
+    b.run()
+    torch.cuda.synchronize()
+    assert b.info()["specialized_items"] == 1 and torch.equal(o, out)
     with pytest.raises(amd.AmiError) as e:
-        amd.Batch([{"terms": T, "energies": E, "ext_freqs": w, "beta": 2.0, "out": o}])
+        amd.Batch([{"terms": T, "energies": E, "ext_freqs": w, "beta": 2.0, "out": o}], {"kernels": 1})
     assert e.value.code == -7
