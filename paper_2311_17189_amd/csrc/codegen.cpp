@@ -3,9 +3,10 @@
 // momentum lines, built by build_tables) out as straight-line device code for
 // the kernels of jit_kernel.hpp.  Sums over coefficients keep the order of the
 // table-driven evaluators (index order, first term as +v or -v) and products
-// their left-to-right association; every fused multiply-add is written out
-// (the code is compiled without contraction), so the forward and adjoint
-// kernels of a diagram compute the same values bit for bit.
+// their left-to-right association; every fused multiply-add of the values
+// is written out (the code is compiled without contraction, which only the
+// reverse sweep's functions turn on), so the forward and adjoint kernels of a
+// diagram compute the same values bit for bit.
 #include <algorithm>
 #include <cstdio>
 #include <cstdlib>
@@ -21,6 +22,11 @@
 namespace ami {
 
 namespace {
+
+// The reverse sweep (cotangents and their scatters) lets the compiler fuse
+// its multiply-add pairs; the forward values are computed outside it, with
+// every fused multiply-add written out, so they do not change.
+const char *const kReverseContract = "#pragma clang fp contract(fast)\n";
 
 std::string num(double v) {
     char b[40];
@@ -402,6 +408,7 @@ std::string jit_source(const AmiTerms *t, bool hub, int kernels) {
         for (int j = gbegin(g); j < gend(g); ++j) occ[tb.group_den_list[j]].push_back(g);
     o << "__device__ __forceinline__ void den_cotangents(const double (&ur)[G], const double (&ui)[G], double "
          "(&Ur)[D], double (&Ui)[D]) {\n";
+    o << kReverseContract;
     for (int k = 0; k < D; ++k) {
         Lin r, i;
         for (int g : occ[k]) {
@@ -422,6 +429,7 @@ std::string jit_source(const AmiTerms *t, bool hub, int kernels) {
     o << "__device__ __forceinline__ void den_scatter(const double (&dR)[D], const double (&dI)[D], double (&gE)[NE], "
          "double (&gwr)["
       << NXA << "], double (&gwi)[" << NXA << "]) {\n";
+    o << kReverseContract;
     o << "  (void)dR; (void)dI; (void)gE; (void)gwr; (void)gwi;\n";
     for (int k = 0; k < tb.D; ++k) {
         for (int i = 0; i < ne; ++i) scatter(o, tb.den_coef[static_cast<size_t>(k) * nc + i], idx("gE", i), idx("dR", k));
@@ -436,6 +444,7 @@ std::string jit_source(const AmiTerms *t, bool hub, int kernels) {
     // leaf cotangents by prefix/suffix products over each term's leaves
     o << "__device__ __forceinline__ void leaf_cotangents(const double (&F)[L], const double (&FTB)[G], double "
          "(&FB)[L]) {\n";
+    o << kReverseContract;
     for (int g = 0; g < G; ++g) {
         for (int ti = tb.group_start[g]; ti < tb.group_start[g + 1]; ++ti) {
             const double s = tb.term_sign[ti];
@@ -467,6 +476,7 @@ std::string jit_source(const AmiTerms *t, bool hub, int kernels) {
 
     // dL/dE_i += sum_l c_li v_l
     o << "__device__ __forceinline__ void leaf_scatter(const double (&v)[L], double (&gE)[NE]) {\n";
+    o << kReverseContract;
     for (int l = 0; l < L; ++l)
         for (int i = 0; i < ne; ++i) scatter(o, tb.leaf_coef[static_cast<size_t>(l) * ne + i], idx("gE", i), idx("v", l));
     o << "}\n";
@@ -474,6 +484,7 @@ std::string jit_source(const AmiTerms *t, bool hub, int kernels) {
     // dL/dk_l += sum_j alpha_jl dL/dK_j
     o << "__device__ __forceinline__ void line_scatter(const double (&gx)[" << NGA << "], const double (&gy)[" << NGA
       << "], double (&gkx)[" << NIA << "], double (&gky)[" << NIA << "]) {\n";
+    o << kReverseContract;
     if (hub) {
         for (int j = 0; j < ng; ++j)
             for (int l = 0; l < ni; ++l) {

@@ -342,16 +342,73 @@ __device__ __forceinline__ double wave_sum(double v) {
     return __builtin_bit_cast(double, (static_cast<unsigned long long>(hi) << 32) | lo);
 }
 
-// The wave's totals of (vr, vi), stored by its last lane at dst[0] and
-// dst[stride]: the per-wave partial sums of the specialized kernels (no LDS,
-// no barrier).
+// gfx950 lane exchanges of a double, as two 32-bit halves: swap32 exchanges
+// lanes 32-63 of x with lanes 0-31 of y (afterwards x holds the lower halves
+// of both, y the upper halves); swap16 exchanges rows 1 and 3 of x with rows 0
+// and 2 of y (x then holds the even rows of both, y the odd ones).  Every lane
+// of the wave takes part.
+__device__ __forceinline__ void swap32(double &x, double &y) {
+    const unsigned long long ux = __builtin_bit_cast(unsigned long long, x);
+    const unsigned long long uy = __builtin_bit_cast(unsigned long long, y);
+    const auto lo = __builtin_amdgcn_permlane32_swap(static_cast<unsigned>(ux), static_cast<unsigned>(uy), false,
+                                                     false);
+    const auto hi = __builtin_amdgcn_permlane32_swap(static_cast<unsigned>(ux >> 32), static_cast<unsigned>(uy >> 32),
+                                                     false, false);
+    x = __builtin_bit_cast(double, (static_cast<unsigned long long>(static_cast<unsigned>(hi[0])) << 32) |
+                                       static_cast<unsigned>(lo[0]));
+    y = __builtin_bit_cast(double, (static_cast<unsigned long long>(static_cast<unsigned>(hi[1])) << 32) |
+                                       static_cast<unsigned>(lo[1]));
+}
+
+__device__ __forceinline__ void swap16(double &x, double &y) {
+    const unsigned long long ux = __builtin_bit_cast(unsigned long long, x);
+    const unsigned long long uy = __builtin_bit_cast(unsigned long long, y);
+    const auto lo = __builtin_amdgcn_permlane16_swap(static_cast<unsigned>(ux), static_cast<unsigned>(uy), false,
+                                                     false);
+    const auto hi = __builtin_amdgcn_permlane16_swap(static_cast<unsigned>(ux >> 32), static_cast<unsigned>(uy >> 32),
+                                                     false, false);
+    x = __builtin_bit_cast(double, (static_cast<unsigned long long>(static_cast<unsigned>(hi[0])) << 32) |
+                                       static_cast<unsigned>(lo[0]));
+    y = __builtin_bit_cast(double, (static_cast<unsigned long long>(static_cast<unsigned>(hi[1])) << 32) |
+                                       static_cast<unsigned>(lo[1]));
+}
+
+// Inclusive prefix sums within each row of 16 lanes: lane 15 of a row holds
+// the row's sum.
+__device__ __forceinline__ double row_sums(double v) {
+    v += dpp_move<0x111>(v);   // row_shr:1
+    v += dpp_move<0x112>(v);   // row_shr:2
+    v += dpp_move<0x114>(v);   // row_shr:4
+    v += dpp_move<0x118>(v);   // row_shr:8
+    return v;
+}
+
+// The wave's totals of (vr, vi), stored at dst[0] and dst[stride]: one swap32
+// folds the two halves of the wave, leaving vr's 32 partial sums in rows 0-1
+// and vi's in rows 2-3; after the row sums, row_bcast:15 adds row 0 into lane
+// 31 (vr's total) and row 2 into lane 63 (vi's total).  Register moves only:
+// no LDS, no barrier.
 __device__ __forceinline__ void wave_store2(double vr, double vi, int lane, double *dst, int64_t stride) {
-    vr = wave_sum_lane63(vr);
-    vi = wave_sum_lane63(vi);
-    if (lane == 63) {
-        dst[0] = vr;
-        dst[stride] = vi;
-    }
+    swap32(vr, vi);
+    double v = row_sums(vr + vi);
+    v += dpp_move<0x142>(v);   // row_bcast:15
+    if (lane == 31) dst[0] = v;
+    if (lane == 63) dst[stride] = v;
+}
+
+// The wave's totals of four values, v_k stored at *p_k (a null p_k: not
+// stored).  swap32 on the pairs (v0, v1) and (v2, v3) folds the halves of the
+// wave; swap16 on the two results folds row pairs, leaving one value per row
+// (rows 0-3: v0, v2, v1, v3), whose row sums end in lanes 15, 31, 47 and 63.
+__device__ __forceinline__ void wave_store4(double v0, double v1, double v2, double v3, int lane, double *p0,
+                                            double *p1, double *p2, double *p3) {
+    swap32(v0, v1);
+    swap32(v2, v3);
+    double x = v0 + v1, y = v2 + v3;
+    swap16(x, y);
+    const double v = row_sums(x + y);
+    double *const p = lane == 15 ? p0 : lane == 31 ? p2 : lane == 47 ? p1 : lane == 63 ? p3 : nullptr;
+    if (p) *p = v;
 }
 
 __device__ __forceinline__ void block_sum2(double vr, double vi, double *red, int tid, int B, double *dst) {

@@ -174,8 +174,8 @@ __device__ __forceinline__ void reciprocals(const double (&E)[NE], const double 
 
 #if AMI_JIT_KERNELS & 1
 // Partial sums are per wave: row r = tile * (B / 64) + wave of the partial
-// arrays (column c at [c * nrows + r]), written by the wave's last lane
-// (wave_store2).
+// arrays (column c at [c * nrows + r]), each total written by the one lane
+// of the wave that holds it (wave_store2, wave_store4).
 template <bool HUB>
 __device__ __forceinline__ void fwd_tile(const KArgs &a, int64_t tile) {
     const int tid = threadIdx.x, B = blockDim.x, lane = tid & 63;
@@ -230,6 +230,10 @@ __device__ __forceinline__ void fwd_tile(const KArgs &a, int64_t tile) {
 // being kept live through it.
 template <bool HUB>
 __device__ __forceinline__ void adj_tile(const KArgs &a, int64_t blk, double *park, const double (&in)[NIN]) {
+    // multiply-add pairs written here fuse with those of the reverse-sweep
+    // functions; the values come from functions compiled without contraction
+    // and from explicit fma, so they match the forward kernel bit for bit
+#pragma clang fp contract(fast)
     const int tid = threadIdx.x, B = blockDim.x, lane = tid & 63;
     const int64_t row = blk * (B >> 6) + (tid >> 6);
     const int64_t s = blk * B + tid;
@@ -299,19 +303,37 @@ __device__ __forceinline__ void adj_tile(const KArgs &a, int64_t blk, double *pa
             gwi[xx] = 0.0;
         }
         den_scatter(dR, dI, gE, gwr, gwi);
-#pragma unroll
-        for (int xx = 0; xx < NX; ++xx)
-            ami::wave_store2(active ? gwr[xx] : 0.0, active ? -gwi[xx] : 0.0, lane,
-                             gp + (ami::kAdjScalars + 2 * (f * NX + xx)) * a.nrows, a.nrows);
         if (active && a.out) {
             double2 v;
             v.x = acc_re;
             v.y = acc_im;
             reinterpret_cast<double2 *>(a.out)[static_cast<int64_t>(f) * a.n_e + s] = v;
         }
-        if (a.partial)
-            ami::wave_store2(active ? acc_re : 0.0, active ? acc_im : 0.0, lane, a.partial + 2 * f * a.nrows + row,
-                             a.nrows);
+        // this row's per-wave sums, four values per reduction: the frequency
+        // cotangents (columns kAdjScalars + 2 (f NX + x) and the next), then
+        // the forward values' row sums (when asked for)
+        constexpr int NV = 2 * NX + 2, NV4 = (NV + 3) / 4 * 4;
+        double vv[NV4];
+        double *pp[NV4];
+#pragma unroll
+        for (int xx = 0; xx < NX; ++xx) {
+            vv[2 * xx] = active ? gwr[xx] : 0.0;
+            vv[2 * xx + 1] = active ? -gwi[xx] : 0.0;
+            pp[2 * xx] = gp + (ami::kAdjScalars + 2 * (f * NX + xx)) * a.nrows;
+            pp[2 * xx + 1] = pp[2 * xx] + a.nrows;
+        }
+        vv[2 * NX] = active ? acc_re : 0.0;
+        vv[2 * NX + 1] = active ? acc_im : 0.0;
+        pp[2 * NX] = a.partial ? a.partial + 2 * f * a.nrows + row : nullptr;
+        pp[2 * NX + 1] = a.partial ? pp[2 * NX] + a.nrows : nullptr;
+#pragma unroll
+        for (int c = NV; c < NV4; ++c) {
+            vv[c] = 0.0;
+            pp[c] = nullptr;
+        }
+#pragma unroll
+        for (int c = 0; c < NV4; c += 4)
+            ami::wave_store4(vv[c], vv[c + 1], vv[c + 2], vv[c + 3], lane, pp[c], pp[c + 1], pp[c + 2], pp[c + 3]);
     }
 
     double FB[L];
@@ -369,8 +391,8 @@ __device__ __forceinline__ void adj_tile(const KArgs &a, int64_t blk, double *pa
 #pragma unroll
         for (int i = 0; i < NE; ++i) row[i] = gE[i];
     }
-    ami::wave_store2(active ? gbeta : 0.0, active ? gmu : 0.0, lane, gp, a.nrows);
-    ami::wave_store2(active ? gt : 0.0, 0.0, lane, gp + 2 * a.nrows, a.nrows);
+    ami::wave_store4(active ? gbeta : 0.0, active ? gmu : 0.0, active ? gt : 0.0, 0.0, lane, gp, gp + a.nrows,
+                     gp + 2 * a.nrows, nullptr);
 }
 #endif
 
@@ -428,8 +450,8 @@ __device__ __forceinline__ void mc_block(const KArgs &a) {
     for (int f = 0; f < ami::kMcMaxFreqs; ++f) {
         if (f < a.n_f) {
             double *dst = a.partial + 4 * f * a.nrows + row;
-            ami::wave_store2(acc[0][f], acc[1][f], lane, dst, a.nrows);
-            ami::wave_store2(acc[2][f], acc[3][f], lane, dst + 2 * a.nrows, a.nrows);
+            ami::wave_store4(acc[0][f], acc[1][f], acc[2][f], acc[3][f], lane, dst, dst + a.nrows,
+                             dst + 2 * a.nrows, dst + 3 * a.nrows);
         }
     }
 }
@@ -491,8 +513,7 @@ __device__ __forceinline__ void freq_tile(const KArgs &a, int64_t tile, int f) {
     if (a.mc) {                         // Monte Carlo: sums and sums of squares per frequency row
         const double re = active ? acc_re : 0.0, im = active ? acc_im : 0.0;
         double *dst = a.partial + 4 * f * a.nrows + row;
-        ami::wave_store2(re, im, lane, dst, a.nrows);
-        ami::wave_store2(re * re, im * im, lane, dst + 2 * a.nrows, a.nrows);
+        ami::wave_store4(re, im, re * re, im * im, lane, dst, dst + a.nrows, dst + 2 * a.nrows, dst + 3 * a.nrows);
         return;
     }
     if (active && a.out) {

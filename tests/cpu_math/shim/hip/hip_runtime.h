@@ -17,4 +17,10 @@ inline double __shfl_xor(double v, int, int) { return v; }
 // one lane per "wave" on the host: cross-lane moves return the lane's own value
 inline int __builtin_amdgcn_mov_dpp(int src, int, int, int, bool) { return src; }
 inline int __builtin_amdgcn_readlane(int v, int) { return v; }
+struct AmiLanePair {
+    unsigned v[2];
+    unsigned operator[](int i) const { return v[i]; }
+};
+inline AmiLanePair __builtin_amdgcn_permlane32_swap(unsigned x, unsigned y, bool, bool) { return {{x, y}}; }
+inline AmiLanePair __builtin_amdgcn_permlane16_swap(unsigned x, unsigned y, bool, bool) { return {{x, y}}; }
 inline void __syncthreads() {}
