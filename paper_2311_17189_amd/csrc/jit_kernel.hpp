@@ -41,6 +41,45 @@ constexpr int kParkChain = AMI_JIT_HUB ? 3 * NG : 0;
 constexpr bool kParkDv = AMI_JIT_PARK_DV;
 constexpr int kParkCols = kParkChain + (kParkDv ? L : 0);
 
+// Gradient rows (W doubles per sample, row-major, the wave's 64 consecutive
+// samples contiguous in memory) leave through LDS, so that each store
+// instruction writes 64 consecutive doubles instead of one row piece per lane
+// at a W-double stride: lane i puts its row at elements i W .. i W + W - 1 of
+// the wave's staging area, then takes back elements 64 j + i.  Element e sits
+// at stage[e + e / 64] (one pad double per 64, which keeps both passes free of
+// bank conflicts).  The staging areas (65 W doubles per wave) reuse the park
+// area once every wave of the block has read its parked values.
+template <int W>
+constexpr bool kStageFits = kParkCols * AMI_JIT_BLOCK >= (AMI_JIT_BLOCK / 64) * 65 * W;
+
+template <int W>
+__device__ __forceinline__ void store_rows_staged(double *stage, int lane, const double (&v)[W], double *dst,
+                                                  int64_t n_valid) {
+    if constexpr (64 % W == 0) {       // a lane's row does not cross a pad
+        double *row = stage + lane * W + ((lane * W) >> 6);
+#pragma unroll
+        for (int c = 0; c < W; ++c) row[c] = v[c];
+    } else {
+#pragma unroll
+        for (int c = 0; c < W; ++c) {
+            const int e = lane * W + c;
+            stage[e + (e >> 6)] = v[c];
+        }
+    }
+    __builtin_amdgcn_wave_barrier();
+    double x[W];
+#pragma unroll
+    for (int j = 0; j < W; ++j) x[j] = stage[65 * j + lane];
+    if (n_valid >= 64 * W) {           // the whole wave (uniform)
+#pragma unroll
+        for (int j = 0; j < W; ++j) dst[64 * j + lane] = x[j];
+    } else {
+#pragma unroll
+        for (int j = 0; j < W; ++j)
+            if (64 * j + lane < n_valid) dst[64 * j + lane] = x[j];
+    }
+}
+
 // The momenta of Monte-Carlo sample s: the words of Philox4x32-10 blocks
 // b = 0, 1, ... with counter (s mod 2^32, s div 2^32, b, 0) and key = the
 // 64-bit seed, component c = 2 l + (0: x, 1: y) from word c, each mapped to
@@ -367,7 +406,21 @@ __device__ __forceinline__ void adj_tile(const KArgs &a, int64_t blk, double *pa
             gky[l] = 0.0;
         }
         line_scatter(gx, gy, gkx, gky);
-        if (active && a.grad_k) {
+        if constexpr (kStageFits<2 * NI>) {
+            if (a.grad_k) {
+                double g[2 * NI];
+#pragma unroll
+                for (int l = 0; l < NI; ++l) {
+                    g[2 * l] = gkx[l];
+                    g[2 * l + 1] = gky[l];
+                }
+                __syncthreads();                    // every wave has read its parked values
+                const int wave = tid >> 6;
+                const int64_t s0 = blk * B + (wave << 6);
+                store_rows_staged<2 * NI>(park + wave * 65 * (2 * NI), lane, g, a.grad_k + s0 * (2 * NI),
+                                          (a.n_e - s0) * (2 * NI));
+            }
+        } else if (active && a.grad_k) {
             double *row = a.grad_k + s * (2 * NI);
             if (a.vec_io & 2) {
 #pragma unroll
@@ -386,7 +439,14 @@ __device__ __forceinline__ void adj_tile(const KArgs &a, int64_t blk, double *pa
             }
         }
     }
-    if (active && a.grad_e) {
+    if constexpr (kStageFits<NE>) {
+        if (a.grad_e) {
+            __syncthreads();                        // every wave is done with the park area
+            const int wave = tid >> 6;
+            const int64_t s0 = blk * B + (wave << 6);
+            store_rows_staged<NE>(park + wave * 65 * NE, lane, gE, a.grad_e + s0 * NE, (a.n_e - s0) * NE);
+        }
+    } else if (active && a.grad_e) {
         double *row = a.grad_e + s * NE;
 #pragma unroll
         for (int i = 0; i < NE; ++i) row[i] = gE[i];
