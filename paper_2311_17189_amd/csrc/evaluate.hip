@@ -369,7 +369,8 @@ enum class Path { TABLES, PACKED, SPECIALIZED, TWO_PASS };
 // Workspace of one chunk of the two-pass forward (group sums and energies):
 // 256 MB unless amiSetTwoPassChunkBytes set another bound.
 std::atomic<int64_t> g_two_pass_chunk_bytes{int64_t(256) << 20};
-// Frequency rows of one two-pass launch (its second kernel's grid height).
+// Frequency rows of one two-pass launch (its second kernel runs a block per
+// tile and frequency row; the bound keeps that grid below 2^31 blocks).
 constexpr int kTwoPassMaxFreqs = 65535;
 
 // Which kernels serve a call (AMI_VARIANT_* of the handle); for the
@@ -470,7 +471,7 @@ hipError_t launch_jit(void *fn, int64_t nblocks, int block, hipStream_t stream, 
 
 // The two-pass forward: the samples in chunks whose group sums and energies
 // fit the chunk workspace; per chunk the sums pass (one lane per sample) and
-// the frequency pass (a grid row per frequency), then one column reduction
+// the frequency pass (a block per tile and frequency row), then one column reduction
 // of the per-wave partial sums for the row sums.
 AmiStatus launch_two_pass(AmiTerms *t, DeviceTables *dt, bool hub, KArgs &a, double *out_sum, void *fn_sums,
                           void *fn_freq, hipStream_t stream) {
@@ -491,13 +492,17 @@ AmiStatus launch_two_pass(AmiTerms *t, DeviceTables *dt, bool hub, KArgs &a, dou
     a.ld = ld;
     a.partial = out_sum ? ws + static_cast<size_t>(cols) * ld : nullptr;
     a.nrows = rows;
+    // the largest chunk's frequency pass: a block per tile and frequency row
+    if ((std::min<int64_t>(ld, a.n_e) + B - 1) / B * a.n_f + 7 * a.n_f > 0x7fffffffLL)
+        return fail(AMI_E_ARG, "two-pass chunk too large for its frequency rows");
     hipError_t e = hipSuccess;
     for (int64_t s0 = 0; s0 < a.n_e && e == hipSuccess; s0 += ld) {
         a.s0 = s0;
         a.n_chunk = std::min<int64_t>(ld, a.n_e - s0);
         const int64_t nb = (a.n_chunk + B - 1) / B;
         e = launch_jit(fn_sums, nb, B, stream, a);
-        if (e == hipSuccess) e = launch_jit(fn_freq, nb, B, stream, a, a.n_f);
+        // (tile, frequency) blocks, tiles rounded up to a multiple of the 8 XCDs
+        if (e == hipSuccess) e = launch_jit(fn_freq, (nb + 7) / 8 * 8 * a.n_f, B, stream, a);
     }
     if (e == hipSuccess) e = hipGetLastError();
     g_last_variant = "specialized two-pass";

@@ -707,7 +707,17 @@ extern "C" __global__ __launch_bounds__(AMI_JIT_BLOCK) void ami_jit_sums(ami::KA
 #endif
 
 #if AMI_JIT_KERNELS & 32
+// One block per (tile, frequency row) in a one-dimensional grid: block b runs
+// on the XCD b mod 8 (the dispatcher deals blocks round-robin over the eight
+// XCDs), and the n_f blocks of a tile are consecutive on that XCD, so a
+// tile's stored group sums come from HBM once and from the XCD's L2 for the
+// other frequency rows.  Blocks past the last tile (the tile count rounded up
+// to a multiple of 8) return at once.
 extern "C" __global__ __launch_bounds__(AMI_JIT_BLOCK) void ami_jit_freq(ami::KArgs a) {
-    amijit::freq_tile(a, blockIdx.x, blockIdx.y);
+    const int64_t b = blockIdx.x, local = b >> 3;
+    const int f = static_cast<int>(local % a.n_f);
+    const int64_t tile = 8 * (local / a.n_f) + (b & 7);
+    if (tile * AMI_JIT_BLOCK >= a.n_chunk) return;
+    amijit::freq_tile(a, tile, f);
 }
 #endif
