@@ -36,6 +36,134 @@ std::string num(double v) {
     return s;
 }
 
+// A sum of signed products of leaves, sum_t c_t prod_{l in t} F_l, written as
+// nested multiply-adds (a greedy multivariate Horner scheme): the leaf a that
+// occurs in the most terms (the lowest index among equals) is factored out,
+// F_a * (the terms holding a, one a removed) + (the other terms), and both
+// parts are nested the same way.  Each step is one fma (a mul or an add where
+// a part is zero or a unit constant); terms with equal leaf multisets merge,
+// and a sub-sum met again (or its negative) reuses the temporary that holds
+// it.  Every temporary is a const double h<k> of the enclosing block.
+struct HornerTerm {
+    double c;
+    std::vector<int> leaves;   // a multiset (a leaf may repeat)
+};
+
+struct HornerValue {
+    bool zero = true;          // the empty sum
+    bool constant = false;     // a plain number c
+    double c = 0.0;
+    std::string name;          // else the temporary (or leaf) holding it
+    bool negate = false;       // the value is -name
+    std::string expr() const {
+        if (zero) return "0.0";
+        if (constant) return num(c);
+        return negate ? "(-" + name + ")" : name;
+    }
+};
+
+template <typename LeafName>
+HornerValue horner_split(std::vector<HornerTerm> merged, const LeafName &leaf_name, std::ostream &o, int &temps,
+                         std::map<std::string, HornerValue> &memo);
+
+HornerValue negated(HornerValue v) {
+    if (v.constant) v.c = -v.c;
+    else if (!v.zero) v.negate = !v.negate;
+    return v;
+}
+
+// Sub-sums already written (up to sign) within the enclosing block.
+using HornerMemo = std::map<std::string, HornerValue>;
+
+template <typename LeafName>
+HornerValue horner(std::vector<HornerTerm> ts, const LeafName &leaf_name, std::ostream &o, int &temps,
+                   HornerMemo &memo) {
+    for (HornerTerm &t : ts) std::sort(t.leaves.begin(), t.leaves.end());
+    std::sort(ts.begin(), ts.end(), [](const HornerTerm &x, const HornerTerm &y) { return x.leaves < y.leaves; });
+    std::vector<HornerTerm> merged;
+    for (HornerTerm &t : ts) {
+        if (!merged.empty() && merged.back().leaves == t.leaves) merged.back().c += t.c;
+        else merged.push_back(std::move(t));
+    }
+    merged.erase(std::remove_if(merged.begin(), merged.end(), [](const HornerTerm &t) { return t.c == 0.0; }),
+                 merged.end());
+    HornerValue r;
+    if (merged.empty()) return r;
+    r.zero = false;
+    if (merged.size() == 1 && merged[0].leaves.empty()) {
+        r.constant = true;
+        r.c = merged[0].c;
+        return r;
+    }
+    // the sum's key with its first coefficient made positive
+    const bool flip = merged[0].c < 0.0;
+    std::string key;
+    for (const HornerTerm &t : merged) {
+        key += num(flip ? -t.c : t.c) + ":";
+        for (int l : t.leaves) key += std::to_string(l) + ",";
+        key += ";";
+    }
+    if (const auto it = memo.find(key); it != memo.end()) return flip ? negated(it->second) : it->second;
+    const HornerValue v = horner_split(std::move(merged), leaf_name, o, temps, memo);
+    memo[key] = flip ? negated(v) : v;
+    return v;
+}
+
+// One Horner step on a merged, non-constant sum: factor out the most shared
+// leaf and nest both parts.
+template <typename LeafName>
+HornerValue horner_split(std::vector<HornerTerm> merged, const LeafName &leaf_name, std::ostream &o, int &temps,
+                         HornerMemo &memo) {
+    HornerValue r;
+    r.zero = false;
+    std::map<int, int> count;   // terms holding each leaf
+    for (const HornerTerm &t : merged)
+        for (size_t j = 0; j < t.leaves.size(); ++j)
+            if (j == 0 || t.leaves[j] != t.leaves[j - 1]) ++count[t.leaves[j]];
+    int a = -1, best = 0;
+    for (const auto &kv : count)
+        if (kv.second > best) {
+            a = kv.first;
+            best = kv.second;
+        }
+    std::vector<HornerTerm> with, without;
+    for (HornerTerm &t : merged) {
+        auto it = std::find(t.leaves.begin(), t.leaves.end(), a);
+        if (it == t.leaves.end()) {
+            without.push_back(std::move(t));
+        } else {
+            t.leaves.erase(it);
+            with.push_back(std::move(t));
+        }
+    }
+    const HornerValue vw = horner(with, leaf_name, o, temps, memo);
+    const HornerValue vo = horner(without, leaf_name, o, temps, memo);
+    if (vw.zero) return vo;
+    const std::string fa = leaf_name(a);
+    // F_a * vw + vo
+    std::string rhs;
+    bool neg = false;
+    if (vw.constant && (vw.c == 1.0 || vw.c == -1.0)) {
+        if (vo.zero) {                       // +-F_a itself
+            r.name = fa;
+            r.negate = vw.c < 0.0;
+            return r;
+        }
+        rhs = vo.expr() + (vw.c < 0.0 ? " - " : " + ") + fa;
+    } else if (vw.constant) {
+        rhs = vo.zero ? num(vw.c) + " * " + fa : "fma(" + num(vw.c) + ", " + fa + ", " + vo.expr() + ")";
+    } else if (vo.zero) {
+        rhs = fa + " * " + vw.name;          // the sign of vw carries over
+        neg = vw.negate;
+    } else {
+        rhs = "fma(" + (vw.negate ? "-" + fa : fa) + ", " + vw.name + ", " + vo.expr() + ")";
+    }
+    r.name = "h" + std::to_string(temps++);
+    r.negate = neg;
+    o << "    const double " << r.name << " = " << rhs << ";\n";
+    return r;
+}
+
 // sum_i c_i v[i] over the non-zero coefficients, in index order: "+-v" for
 // unit coefficients, fma for others; "0.0" when every coefficient is zero.
 struct Lin {
@@ -205,19 +333,11 @@ std::string jit_source(const AmiTerms *t, bool hub, int kernels) {
     }
     o << "}\n";
 
-    // group sums FT_g = sum_t s_t prod f: the product of a term's leaves left
-    // to right, its last factor fused into the accumulation (unit s_t)
+    // group sums FT_g = sum_t s_t prod f, each group in the nested form of
+    // horner()
     // leaf names: F[l], or a group's own copy f<l> (opaque copies)
     std::string leaf_prefix = "F[", leaf_suffix = "]";
     auto leaf_name = [&](int l) { return leaf_prefix + std::to_string(l) + leaf_suffix; };
-    auto term_product = [&](int ti, int upto) {
-        std::string p;
-        for (int j = 0; j < upto; ++j) {
-            const std::string f = leaf_name(tb.term_leaf[static_cast<size_t>(ti) * ni + j]);
-            p = p.empty() ? f : p + " * " + f;
-        }
-        return p.empty() ? std::string("1.0") : p;
-    };
     // the one-pass kernels' functions (and the adjoint's) are emitted when one
     // of those kernels is asked for, or for any solution small enough for them
     // (the host checks compile them); a two-pass source of a large solution
@@ -244,21 +364,16 @@ std::string jit_source(const AmiTerms *t, bool hub, int kernels) {
             for (int l : used)
                 o << "    double f" << l << " = F[" << l << "]; AMI_OPAQUE(f" << l << ");\n";
         }
+        std::vector<HornerTerm> ts;
         for (int ti = tb.group_start[g]; ti < tb.group_start[g + 1]; ++ti) {
-            const double s = tb.term_sign[ti];
-            if (ti == tb.group_start[g]) {
-                const std::string p = term_product(ti, ni);
-                if (s == 1.0) o << "    ft = " << p << ";\n";
-                else if (s == -1.0) o << "    ft = -(" << p << ");\n";
-                else o << "    ft = " << num(s) << " * (" << p << ");\n";
-            } else if ((s == 1.0 || s == -1.0) && ni > 1) {
-                const std::string last = leaf_name(tb.term_leaf[static_cast<size_t>(ti) * ni + ni - 1]);
-                o << "    ft = fma(" << (s < 0 ? "-(" : "(") << term_product(ti, ni - 1) << "), " << last
-                  << ", ft);\n";
-            } else {
-                o << "    ft = fma(" << num(s) << ", " << term_product(ti, ni) << ", ft);\n";
-            }
+            HornerTerm h{tb.term_sign[ti], {}};
+            for (int j = 0; j < ni; ++j) h.leaves.push_back(tb.term_leaf[static_cast<size_t>(ti) * ni + j]);
+            ts.push_back(std::move(h));
         }
+        int temps = 0;
+        HornerMemo memo;
+        const HornerValue v = horner(ts, leaf_name, o, temps, memo);
+        o << "    ft = " << v.expr() << ";\n";
         o << "    " << sink_prefix << g << sink_suffix << " = ft; }\n";
     }
     };
