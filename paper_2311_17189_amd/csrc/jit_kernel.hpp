@@ -215,7 +215,9 @@ __device__ __forceinline__ void reciprocals(const double (&E)[NE], const double 
 // Partial sums are per wave: row r = tile * (B / 64) + wave of the partial
 // arrays (column c at [c * nrows + r]), each total written by the one lane
 // of the wave that holds it (wave_store2, wave_store4).
-template <bool HUB>
+// NF1: one frequency row (n_f = 1 known at compile time, so the tile is
+// straight-line code the compiler schedules as a whole).
+template <bool HUB, bool NF1>
 __device__ __forceinline__ void fwd_tile(const KArgs &a, int64_t tile) {
     const int tid = threadIdx.x, B = blockDim.x, lane = tid & 63;
     const int64_t row = tile * (B >> 6) + (tid >> 6);
@@ -236,7 +238,8 @@ __device__ __forceinline__ void fwd_tile(const KArgs &a, int64_t tile) {
     double FT[G];
     group_sums(F, FT);
 
-    for (int f = 0; f < a.n_f; ++f) {
+    const int nf = NF1 ? 1 : a.n_f;
+    for (int f = 0; f < nf; ++f) {
         double wr[NXA], wi[NXA], xr[D], xi[D], Rr[G], Ri[G];
         load_freq(a, f, wr, wi);
         reciprocals(E, wr, wi, xr, xi);
@@ -267,7 +270,7 @@ __device__ __forceinline__ void fwd_tile(const KArgs &a, int64_t tile) {
 // denominator: dL/dD_k = -rho_k sum_{g contains k} FT_g conj(c) R_g.
 // The leaf arguments x_l are recomputed after the frequency loop instead of
 // being kept live through it.
-template <bool HUB>
+template <bool HUB, bool NF1>
 __device__ __forceinline__ void adj_tile(const KArgs &a, int64_t blk, double *park, const double (&in)[NIN]) {
     // multiply-add pairs written here fuse with those of the reverse-sweep
     // functions; the values come from functions compiled without contraction
@@ -302,7 +305,8 @@ __device__ __forceinline__ void adj_tile(const KArgs &a, int64_t blk, double *pa
     for (int i = 0; i < NE; ++i) gE[i] = 0.0;
     double *gp = a.gpartial + row;                   // column c at gp[c * nrows]
 
-    for (int f = 0; f < a.n_f; ++f) {
+    const int nf = NF1 ? 1 : a.n_f;       // NF1: straight-line code for one frequency row
+    for (int f = 0; f < nf; ++f) {
         double cr = 0.0, ci = 0.0;
         if (active) {
             if (a.g_out) {
@@ -662,7 +666,8 @@ __device__ __forceinline__ void cfwd_tile(const KArgs &a, int64_t tile) {
 // two-pass forward (16, 32), or a sum of them
 #if AMI_JIT_KERNELS & 1
 extern "C" __global__ __launch_bounds__(AMI_JIT_BLOCK) void ami_jit_fwd(ami::KArgs a) {
-    amijit::fwd_tile<AMI_JIT_HUB>(a, blockIdx.x);
+    if (a.n_f == 1) amijit::fwd_tile<AMI_JIT_HUB, true>(a, blockIdx.x);
+    else amijit::fwd_tile<AMI_JIT_HUB, false>(a, blockIdx.x);
 }
 #endif
 
@@ -678,7 +683,8 @@ extern "C" __global__ __launch_bounds__(AMI_JIT_BLOCK) AMI_JIT_ADJ_ATTR void ami
     const int64_t s = static_cast<int64_t>(blockIdx.x) * AMI_JIT_BLOCK + threadIdx.x;
     double in[amijit::NIN];
     amijit::load_inputs<AMI_JIT_HUB>(a, s < a.n_e ? s : a.n_e - 1, in);
-    amijit::adj_tile<AMI_JIT_HUB>(a, blockIdx.x, park, in);
+    if (a.n_f == 1) amijit::adj_tile<AMI_JIT_HUB, true>(a, blockIdx.x, park, in);
+    else amijit::adj_tile<AMI_JIT_HUB, false>(a, blockIdx.x, park, in);
 }
 #endif
 
