@@ -14,6 +14,7 @@
 #include <map>
 #include <sstream>
 #include <string>
+#include <tuple>
 #include <vector>
 
 #include "ami_internal.hpp"
@@ -161,6 +162,155 @@ HornerValue horner_split(std::vector<HornerTerm> merged, const LeafName &leaf_na
     r.name = "h" + std::to_string(temps++);
     r.negate = neg;
     o << "    const double " << r.name << " = " << rhs << ";\n";
+    return r;
+}
+
+// The same greedy nesting for a sum of products whose factors may be complex:
+// sum_g prod_{k in g} z_k with complex reciprocals z_k and one real factor
+// per product (its group sum, read from memory).  Values are zero, a number,
+// a real or a complex pair of expressions; each step L * W + U is written out
+// with fma and the kinds of its operands (a complex product fused into the
+// addend: re = fma(lr, wr, fma(-li, wi, ur))).
+struct CVal {
+    enum Kind { ZERO, CONST, REAL, CPLX } kind = ZERO;
+    double c = 0.0;
+    std::string re, im;   // expressions: a name, "(-name)" or a number
+};
+
+std::string neg_expr(const std::string &e) {
+    if (e.size() > 3 && e.compare(0, 2, "(-") == 0 && e.back() == ')') return e.substr(2, e.size() - 3);
+    return "(-" + e + ")";
+}
+
+CVal cnegated(CVal v) {
+    if (v.kind == CVal::CONST) v.c = -v.c;
+    if (v.kind == CVal::REAL || v.kind == CVal::CPLX) v.re = neg_expr(v.re);
+    if (v.kind == CVal::CPLX) v.im = neg_expr(v.im);
+    return v;
+}
+
+// products (sign, x, y) added to an addend: nested fma, or a product alone
+std::string fused(const std::vector<std::tuple<bool, std::string, std::string>> &prods, const std::string &addend) {
+    std::string acc = addend;
+    for (auto it = prods.rbegin(); it != prods.rend(); ++it) {
+        const auto &[negp, x, y] = *it;
+        const std::string xs = negp ? neg_expr(x) : x;
+        acc = acc.empty() ? xs + " * " + y : "fma(" + xs + ", " + y + ", " + acc + ")";
+    }
+    return acc;
+}
+
+using CMemo = std::map<std::string, CVal>;
+
+// leaf(a) gives the value of factor a (a REAL or CPLX CVal of names)
+template <typename Leaf>
+CVal horner_c(std::vector<HornerTerm> ts, const Leaf &leaf, std::ostream &o, int &temps, CMemo &memo) {
+    for (HornerTerm &t : ts) std::sort(t.leaves.begin(), t.leaves.end());
+    std::sort(ts.begin(), ts.end(), [](const HornerTerm &x, const HornerTerm &y) { return x.leaves < y.leaves; });
+    std::vector<HornerTerm> m;
+    for (HornerTerm &t : ts) {
+        if (!m.empty() && m.back().leaves == t.leaves) m.back().c += t.c;
+        else m.push_back(std::move(t));
+    }
+    m.erase(std::remove_if(m.begin(), m.end(), [](const HornerTerm &t) { return t.c == 0.0; }), m.end());
+    CVal r;
+    if (m.empty()) return r;
+    if (m.size() == 1 && m[0].leaves.empty()) {
+        r.kind = CVal::CONST;
+        r.c = m[0].c;
+        return r;
+    }
+    const bool flip = m[0].c < 0.0;
+    std::string key;
+    for (const HornerTerm &t : m) {
+        key += num(flip ? -t.c : t.c) + ":";
+        for (int l : t.leaves) key += std::to_string(l) + ",";
+        key += ";";
+    }
+    if (const auto it = memo.find(key); it != memo.end()) return flip ? cnegated(it->second) : it->second;
+    std::map<int, int> count;
+    for (const HornerTerm &t : m)
+        for (size_t j = 0; j < t.leaves.size(); ++j)
+            if (j == 0 || t.leaves[j] != t.leaves[j - 1]) ++count[t.leaves[j]];
+    int a = -1, best = 0;
+    for (const auto &kv : count)
+        if (kv.second > best) {
+            a = kv.first;
+            best = kv.second;
+        }
+    std::vector<HornerTerm> with, without;
+    for (HornerTerm &t : m) {
+        auto it = std::find(t.leaves.begin(), t.leaves.end(), a);
+        if (it == t.leaves.end()) {
+            without.push_back(std::move(t));
+        } else {
+            t.leaves.erase(it);
+            with.push_back(std::move(t));
+        }
+    }
+    const CVal w = horner_c(with, leaf, o, temps, memo);
+    const CVal u = horner_c(without, leaf, o, temps, memo);
+    const CVal L = leaf(a);
+    if (w.kind == CVal::ZERO) {
+        r = u;
+    } else {
+        // the product L * w as real and imaginary lists of (sign, x, y), or a
+        // plain (signed) expression where w is a unit
+        using Prods = std::vector<std::tuple<bool, std::string, std::string>>;
+        Prods pre, pim;
+        std::string plain_re, plain_im;
+        const bool lc = L.kind == CVal::CPLX;
+        bool cplx = lc;
+        if (w.kind == CVal::CONST) {
+            if (w.c == 1.0 || w.c == -1.0) {
+                plain_re = w.c < 0 ? neg_expr(L.re) : L.re;
+                if (lc) plain_im = w.c < 0 ? neg_expr(L.im) : L.im;
+            } else {
+                pre.emplace_back(false, num(w.c), L.re);
+                if (lc) pim.emplace_back(false, num(w.c), L.im);
+            }
+        } else if (w.kind == CVal::REAL) {
+            pre.emplace_back(false, L.re, w.re);
+            if (lc) pim.emplace_back(false, L.im, w.re);
+        } else {
+            cplx = true;
+            if (lc) {
+                pre.emplace_back(false, L.re, w.re);
+                pre.emplace_back(true, L.im, w.im);
+                pim.emplace_back(false, L.re, w.im);
+                pim.emplace_back(false, L.im, w.re);
+            } else {
+                pre.emplace_back(false, L.re, w.re);
+                pim.emplace_back(false, L.re, w.im);
+            }
+        }
+        cplx = cplx || u.kind == CVal::CPLX;
+        std::string ure, uim;
+        if (u.kind == CVal::CONST) ure = num(u.c);
+        if (u.kind == CVal::REAL || u.kind == CVal::CPLX) ure = u.re;
+        if (u.kind == CVal::CPLX) uim = u.im;
+        auto part = [&](const Prods &pr, const std::string &plain, const std::string &add) -> std::string {
+            if (!pr.empty()) return fused(pr, add);
+            if (plain.empty()) return add;                    // nothing of L * w here
+            if (add.empty()) return plain;
+            return add + " + " + plain;
+        };
+        const std::string ere = part(pre, plain_re, ure);
+        const std::string eim = cplx ? part(pim, plain_im, uim) : std::string();
+        auto temp = [&](const std::string &e) {
+            if (e.empty()) return std::string("0.0");
+            const bool simple = e.find_first_of(" (") == std::string::npos || (e.compare(0, 2, "(-") == 0 &&
+                                                                               e.find(' ') == std::string::npos);
+            if (simple) return e;                              // a name or a negated name
+            const std::string n = "c" + std::to_string(temps++);
+            o << "    const double " << n << " = " << e << ";\n";
+            return n;
+        };
+        r.kind = cplx ? CVal::CPLX : CVal::REAL;
+        r.re = temp(ere);
+        if (cplx) r.im = temp(eim);
+    }
+    memo[key] = flip ? cnegated(r) : r;
     return r;
 }
 
@@ -508,11 +658,43 @@ std::string jit_source(const AmiTerms *t, bool hub, int kernels) {
     if (kernels & 32) {
         o << "__device__ __forceinline__ void group_accumulate(const double (&xr)[D], const double (&xi)[D], "
              "const double *ft, int64_t ld, double &acc_re, double &acc_im) {\n";
+        // sum_g FT_g R_g nested over the reciprocals (factor k < D: z_k; factor
+        // D + g: the stored FT_g, read where the nesting first needs it)
+        std::vector<HornerTerm> ts;
         for (int g = 0; g < G; ++g) {
-            group_product(g, true);
-            o << "    const double v = ft[(int64_t)" << g << " * ld];\n";
-            o << "    (void)nr; acc_re = fma(v, rr, acc_re); acc_im = fma(v, ri, acc_im); }\n";
+            HornerTerm h{1.0, {}};
+            for (int j = gbegin(g); j < gend(g); ++j) h.leaves.push_back(tb.group_den_list[j]);
+            h.leaves.push_back(D + g);
+            ts.push_back(std::move(h));
         }
+        std::vector<bool> loaded(static_cast<size_t>(G), false);
+        auto leaf = [&](int k) {
+            CVal v;
+            if (k < D) {
+                v.kind = CVal::CPLX;
+                v.re = "xr[" + std::to_string(k) + "]";
+                v.im = "xi[" + std::to_string(k) + "]";
+            } else {
+                const int g = k - D;
+                if (!loaded[static_cast<size_t>(g)]) {
+                    o << "    const double ft" << g << " = ft[(int64_t)" << g << " * ld];\n";
+                    loaded[static_cast<size_t>(g)] = true;
+                }
+                v.kind = CVal::REAL;
+                v.re = "ft" + std::to_string(g);
+            }
+            return v;
+        };
+        int temps = 0;
+        CMemo memo;
+        const CVal v = horner_c(ts, leaf, o, temps, memo);
+        auto comp = [&](bool imag) {
+            if (v.kind == CVal::ZERO) return std::string("0.0");
+            if (v.kind == CVal::CONST) return imag ? std::string("0.0") : num(v.c);
+            if (v.kind == CVal::REAL) return imag ? std::string("0.0") : v.re;
+            return imag ? v.im : v.re;
+        };
+        o << "    acc_re += " << comp(false) << ";\n    acc_im += " << comp(true) << ";\n";
         o << "}\n";
     }
 
