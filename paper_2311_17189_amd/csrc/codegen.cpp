@@ -405,6 +405,10 @@ std::string jit_source(const AmiTerms *t, bool hub, int kernels) {
     o << "namespace amijit {\n";
     o << "constexpr int NE = " << ne << ", NI = " << ni << ", NG = " << ng << ", NX = " << nx << ";\n";
     o << "constexpr int L = " << L << ", D = " << D << ", G = " << G << ";\n";
+    // the forward values from sum_g FT_g R_g nested over the reciprocals
+    // (groups_combine) above the adjoint's automatic size, group by group below
+    const bool nested_groups = tb.T > kJitAutoAdjointTerms;
+    o << "constexpr bool kNestedGroups = " << (nested_groups ? "true" : "false") << ";\n";
     o << "constexpr bool kBose[L] = {";
     for (int l = 0; l < L; ++l) o << (l ? ", " : "") << (tb.leaf_sigma[l] < 0 ? "true" : "false");
     o << "};\n";
@@ -653,8 +657,49 @@ std::string jit_source(const AmiTerms *t, bool hub, int kernels) {
         }
         o << "}\n";
     }
-    // two-pass forward, second pass: each R_g times its stored group sum,
-    // accumulated group by group
+    // the one-pass kernels' values sum_g FT_g R_g: nested over the reciprocals
+    // (as the two-pass frequency pass) for solutions above the adjoint's
+    // automatic size, else group by group from the products R_g (the
+    // adjoint's own accumulation, so both kernels give the same bits)
+    if (one_pass) {
+        o << "__device__ __forceinline__ void groups_combine(const double (&xr)[D], const double (&xi)[D], "
+             "const double (&FT)[G], double &acc_re, double &acc_im) {\n";
+        if (nested_groups) {
+            std::vector<HornerTerm> ts;
+            for (int g = 0; g < G; ++g) {
+                HornerTerm h{1.0, {}};
+                for (int j = gbegin(g); j < gend(g); ++j) h.leaves.push_back(tb.group_den_list[j]);
+                h.leaves.push_back(D + g);
+                ts.push_back(std::move(h));
+            }
+            auto leaf = [&](int k) {
+                CVal v;
+                if (k < D) {
+                    v.kind = CVal::CPLX;
+                    v.re = "xr[" + std::to_string(k) + "]";
+                    v.im = "xi[" + std::to_string(k) + "]";
+                } else {
+                    v.kind = CVal::REAL;
+                    v.re = "FT[" + std::to_string(k - D) + "]";
+                }
+                return v;
+            };
+            int temps = 0;
+            CMemo memo;
+            const CVal v = horner_c(ts, leaf, o, temps, memo);
+            const bool z = v.kind == CVal::ZERO;
+            o << "    acc_re = " << (z ? "0.0" : v.kind == CVal::CONST ? num(v.c) : v.re) << ";\n";
+            o << "    acc_im = " << (v.kind == CVal::CPLX ? v.im : "0.0") << ";\n";
+        } else {
+            o << "  double Rr[G], Ri[G];\n  group_products(xr, xi, Rr, Ri);\n  acc_re = 0.0;\n  acc_im = 0.0;\n";
+            for (int g = 0; g < G; ++g)
+                o << "  acc_re = fma(FT[" << g << "], Rr[" << g << "], acc_re);\n  acc_im = fma(FT[" << g << "], Ri[" << g
+                  << "], acc_im);\n";
+        }
+        o << "}\n";
+    }
+    // two-pass forward, second pass: sum_g FT_g R_g nested over the
+    // reciprocals, each stored group sum read where the nesting needs it
     if (kernels & 32) {
         o << "__device__ __forceinline__ void group_accumulate(const double (&xr)[D], const double (&xi)[D], "
              "const double *ft, int64_t ld, double &acc_re, double &acc_im) {\n";

@@ -240,16 +240,11 @@ __device__ __forceinline__ void fwd_tile(const KArgs &a, int64_t tile) {
 
     const int nf = NF1 ? 1 : a.n_f;
     for (int f = 0; f < nf; ++f) {
-        double wr[NXA], wi[NXA], xr[D], xi[D], Rr[G], Ri[G];
+        double wr[NXA], wi[NXA], xr[D], xi[D];
         load_freq(a, f, wr, wi);
         reciprocals(E, wr, wi, xr, xi);
-        group_products(xr, xi, Rr, Ri);
-        double acc_re = 0.0, acc_im = 0.0;
-#pragma unroll
-        for (int g = 0; g < G; ++g) {
-            acc_re = fma(FT[g], Rr[g], acc_re);
-            acc_im = fma(FT[g], Ri[g], acc_im);
-        }
+        double acc_re, acc_im;
+        groups_combine(xr, xi, FT, acc_re, acc_im);
         if (active && a.out) {
             double2 v;
             v.x = acc_re;
@@ -323,11 +318,14 @@ __device__ __forceinline__ void adj_tile(const KArgs &a, int64_t blk, double *pa
         reciprocals(E, wr, wi, xr, xi);
         group_products(xr, xi, Rr, Ri);
         double acc_re = 0.0, acc_im = 0.0, ur[G], ui[G];
+        if constexpr (kNestedGroups) groups_combine(xr, xi, FT, acc_re, acc_im);   // the forward's values
 #pragma unroll
         for (int g = 0; g < G; ++g) {
             FTB[g] += fma(cr, Rr[g], ci * Ri[g]);
-            acc_re = fma(FT[g], Rr[g], acc_re);
-            acc_im = fma(FT[g], Ri[g], acc_im);
+            if constexpr (!kNestedGroups) {
+                acc_re = fma(FT[g], Rr[g], acc_re);
+                acc_im = fma(FT[g], Ri[g], acc_im);
+            }
             const double qr = FT[g] * cr, qi = -FT[g] * ci;       // u = -FT conj(c) R
             ur[g] = -fma(qr, Rr[g], -qi * Ri[g]);
             ui[g] = -fma(qr, Ri[g], qi * Rr[g]);
@@ -493,16 +491,11 @@ __device__ __forceinline__ void mc_block(const KArgs &a) {
 #pragma unroll
         for (int f = 0; f < ami::kMcMaxFreqs; ++f) {
             if (f < a.n_f) {
-                double wr[NXA], wi[NXA], xr[D], xi[D], Rr[G], Ri[G];
+                double wr[NXA], wi[NXA], xr[D], xi[D];
                 load_freq(a, f, wr, wi);
                 reciprocals(E, wr, wi, xr, xi);
-                group_products(xr, xi, Rr, Ri);
-                double re = 0.0, im = 0.0;
-#pragma unroll
-                for (int g = 0; g < G; ++g) {
-                    re = fma(FT[g], Rr[g], re);
-                    im = fma(FT[g], Ri[g], im);
-                }
+                double re, im;
+                groups_combine(xr, xi, FT, re, im);
                 acc[0][f] += re;
                 acc[1][f] += im;
                 acc[2][f] = fma(re, re, acc[2][f]);

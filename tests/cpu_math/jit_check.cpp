@@ -1,6 +1,6 @@
 // Host check of the generated part of the specialized evaluator: the
 // diagram's straight-line functions (leaf_args, group_sums, den_args,
-// group_products, den_cotangents, den_scatter, leaf_cotangents, leaf_scatter,
+// group_products, groups_combine, den_cotangents, den_scatter, leaf_cotangents, leaf_scatter,
 // line_trig, line_scatter, taylor_leaves) compiled with a host compiler and driven one sample at
 // a time through the same steps as the device kernels, so a test can compare
 // values and gradients with the oracle.  The generated source is included
@@ -97,12 +97,11 @@ int main() {
                 xi[k] = -di[k] * inv;
             }
             group_products(xr, xi, Rr, Ri);
-            double acc_re = 0.0, acc_im = 0.0, ur[G], ui[G];
+            double acc_re, acc_im, ur[G], ui[G];
+            groups_combine(xr, xi, FT, acc_re, acc_im);     // the kernels' values
             const double cr = cre[f], ci = cim[f];
             for (int g = 0; g < G; ++g) {
                 FTB[g] += std::fma(cr, Rr[g], ci * Ri[g]);
-                acc_re = std::fma(FT[g], Rr[g], acc_re);
-                acc_im = std::fma(FT[g], Ri[g], acc_im);
                 const double qr = FT[g] * cr, qi = -FT[g] * ci;
                 ur[g] = -std::fma(qr, Rr[g], -qi * Ri[g]);
                 ui[g] = -std::fma(qr, Ri[g], qi * Rr[g]);

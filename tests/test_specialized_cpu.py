@@ -56,7 +56,9 @@ def _run(exe, rows, n_f, beta, e_reg, t, mu, q, w, inputs, cot):
     return vals.T, g_in, rest[:, 0].sum(), rest[:, 1].sum(), rest[:, 2].sum(), gw.sum(axis=0).reshape(n_f, n_ext)
 
 
-CASES = [("o2", None), ("o3", (0, 3, 0)), ("o4", (0, 4, 1)), ("o4b", (0, 4, 3))]
+# o5: 196 terms, above the adjoint's automatic size, so the values come from
+# the nested sum over groups (groups_combine)
+CASES = [("o2", None), ("o3", (0, 3, 0)), ("o4", (0, 4, 1)), ("o4b", (0, 4, 3)), ("o5", (0, 5, 2))]
 
 
 @pytest.mark.parametrize("name,seed", CASES)
