@@ -543,32 +543,32 @@ std::string jit_source(const AmiTerms *t, bool hub, int kernels) {
         o << "}\n";
     }
 
-    // complex group sums (complex energies): the same products of a term's
-    // leaves left to right, in complex arithmetic, accumulated with s_t
+    // complex group sums (complex energies): each group's sum nested as the
+    // real group sums, in complex arithmetic
     if (kernels & 8) {
         o << "__device__ __forceinline__ void group_sums_c(const double (&Fr)[L], const double (&Fi)[L], double "
              "(&FTr)[G], double (&FTi)[G]) {\n";
+        auto leaf = [&](int l) {
+            CVal v;
+            v.kind = CVal::CPLX;
+            v.re = "Fr[" + std::to_string(l) + "]";
+            v.im = "Fi[" + std::to_string(l) + "]";
+            return v;
+        };
         for (int g = 0; g < G; ++g) {
-            o << "  { double ar = 0.0, ai = 0.0, pr, pi, nr;\n";
+            o << "  {\n";
+            std::vector<HornerTerm> ts;
             for (int ti = tb.group_start[g]; ti < tb.group_start[g + 1]; ++ti) {
-                const double s = tb.term_sign[ti];
-                if (ni == 0) {
-                    o << "    pr = 1.0; pi = 0.0;\n";
-                }
-                for (int j = 0; j < ni; ++j) {
-                    const int l = tb.term_leaf[static_cast<size_t>(ti) * ni + j];
-                    if (j == 0) {
-                        o << "    pr = Fr[" << l << "]; pi = Fi[" << l << "];\n";
-                    } else {
-                        o << "    nr = fma(pr, Fr[" << l << "], -pi * Fi[" << l << "]); pi = fma(pr, Fi[" << l
-                          << "], pi * Fr[" << l << "]); pr = nr;\n";
-                    }
-                }
-                if (s == 1.0) o << "    ar += pr; ai += pi;\n";
-                else if (s == -1.0) o << "    ar -= pr; ai -= pi;\n";
-                else o << "    ar = fma(" << num(s) << ", pr, ar); ai = fma(" << num(s) << ", pi, ai);\n";
+                HornerTerm h{tb.term_sign[ti], {}};
+                for (int j = 0; j < ni; ++j) h.leaves.push_back(tb.term_leaf[static_cast<size_t>(ti) * ni + j]);
+                ts.push_back(std::move(h));
             }
-            o << "    (void)nr; FTr[" << g << "] = ar; FTi[" << g << "] = ai; }\n";
+            int temps = 0;
+            CMemo memo;
+            const CVal v = horner_c(ts, leaf, o, temps, memo);
+            const std::string re = v.kind == CVal::ZERO ? "0.0" : v.kind == CVal::CONST ? num(v.c) : v.re;
+            const std::string im = v.kind == CVal::CPLX ? v.im : "0.0";
+            o << "    FTr[" << g << "] = " << re << "; FTi[" << g << "] = " << im << "; }\n";
         }
         o << "}\n";
     }
