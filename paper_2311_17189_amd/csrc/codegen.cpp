@@ -43,82 +43,64 @@ std::string num(double v) {
 // F_a * (the terms holding a, one a removed) + (the other terms), and both
 // parts are nested the same way.  Each step is one fma (a mul or an add where
 // a part is zero or a unit constant); terms with equal leaf multisets merge,
-// and a sub-sum met again (or its negative) reuses the temporary that holds
-// it.  Every temporary is a const double h<k> of the enclosing block.
+// and a sub-sum met again (or its negative) reuses the node that holds it.
+// The nodes are built first (horner_build), then written out (horner_emit:
+// const double h<k> of the enclosing block).
 struct HornerTerm {
     double c;
     std::vector<int> leaves;   // a multiset (a leaf may repeat)
 };
 
-struct HornerValue {
-    bool zero = true;          // the empty sum
-    bool constant = false;     // a plain number c
-    double c = 0.0;
-    std::string name;          // else the temporary (or leaf) holding it
-    bool negate = false;       // the value is -name
-    std::string expr() const {
-        if (zero) return "0.0";
-        if (constant) return num(c);
-        return negate ? "(-" + name + ")" : name;
-    }
+// A value of the nesting: zero, a number, a leaf or a node, with a sign.
+struct HRef {
+    enum Kind { ZERO, CONST, LEAF, NODE } kind = ZERO;
+    double c = 0.0;   // CONST
+    int idx = -1;     // LEAF: the leaf; NODE: the node
+    bool neg = false;
 };
 
-template <typename LeafName>
-HornerValue horner_split(std::vector<HornerTerm> merged, const LeafName &leaf_name, std::ostream &o, int &temps,
-                         std::map<std::string, HornerValue> &memo);
+// Node k holds F_a * w + u (w not zero).
+struct HNode {
+    int a;
+    HRef w, u;
+};
 
-HornerValue negated(HornerValue v) {
-    if (v.constant) v.c = -v.c;
-    else if (!v.zero) v.negate = !v.negate;
-    return v;
+HRef href_negated(HRef r) {
+    if (r.kind == HRef::CONST) r.c = -r.c;
+    else if (r.kind != HRef::ZERO) r.neg = !r.neg;
+    return r;
 }
 
-// Sub-sums already written (up to sign) within the enclosing block.
-using HornerMemo = std::map<std::string, HornerValue>;
+// Sub-sums already built (up to sign) for the current nesting.
+using HMemo = std::map<std::string, HRef>;
 
-template <typename LeafName>
-HornerValue horner(std::vector<HornerTerm> ts, const LeafName &leaf_name, std::ostream &o, int &temps,
-                   HornerMemo &memo) {
+HRef horner_nodes(std::vector<HornerTerm> ts, std::vector<HNode> &nodes, HMemo &memo) {
     for (HornerTerm &t : ts) std::sort(t.leaves.begin(), t.leaves.end());
     std::sort(ts.begin(), ts.end(), [](const HornerTerm &x, const HornerTerm &y) { return x.leaves < y.leaves; });
-    std::vector<HornerTerm> merged;
+    std::vector<HornerTerm> m;
     for (HornerTerm &t : ts) {
-        if (!merged.empty() && merged.back().leaves == t.leaves) merged.back().c += t.c;
-        else merged.push_back(std::move(t));
+        if (!m.empty() && m.back().leaves == t.leaves) m.back().c += t.c;
+        else m.push_back(std::move(t));
     }
-    merged.erase(std::remove_if(merged.begin(), merged.end(), [](const HornerTerm &t) { return t.c == 0.0; }),
-                 merged.end());
-    HornerValue r;
-    if (merged.empty()) return r;
-    r.zero = false;
-    if (merged.size() == 1 && merged[0].leaves.empty()) {
-        r.constant = true;
-        r.c = merged[0].c;
+    m.erase(std::remove_if(m.begin(), m.end(), [](const HornerTerm &t) { return t.c == 0.0; }), m.end());
+    HRef r;
+    if (m.empty()) return r;
+    if (m.size() == 1 && m[0].leaves.empty()) {
+        r.kind = HRef::CONST;
+        r.c = m[0].c;
         return r;
     }
     // the sum's key with its first coefficient made positive
-    const bool flip = merged[0].c < 0.0;
+    const bool flip = m[0].c < 0.0;
     std::string key;
-    for (const HornerTerm &t : merged) {
+    for (const HornerTerm &t : m) {
         key += num(flip ? -t.c : t.c) + ":";
         for (int l : t.leaves) key += std::to_string(l) + ",";
         key += ";";
     }
-    if (const auto it = memo.find(key); it != memo.end()) return flip ? negated(it->second) : it->second;
-    const HornerValue v = horner_split(std::move(merged), leaf_name, o, temps, memo);
-    memo[key] = flip ? negated(v) : v;
-    return v;
-}
-
-// One Horner step on a merged, non-constant sum: factor out the most shared
-// leaf and nest both parts.
-template <typename LeafName>
-HornerValue horner_split(std::vector<HornerTerm> merged, const LeafName &leaf_name, std::ostream &o, int &temps,
-                         HornerMemo &memo) {
-    HornerValue r;
-    r.zero = false;
+    if (const auto it = memo.find(key); it != memo.end()) return flip ? href_negated(it->second) : it->second;
     std::map<int, int> count;   // terms holding each leaf
-    for (const HornerTerm &t : merged)
+    for (const HornerTerm &t : m)
         for (size_t j = 0; j < t.leaves.size(); ++j)
             if (j == 0 || t.leaves[j] != t.leaves[j - 1]) ++count[t.leaves[j]];
     int a = -1, best = 0;
@@ -128,7 +110,7 @@ HornerValue horner_split(std::vector<HornerTerm> merged, const LeafName &leaf_na
             best = kv.second;
         }
     std::vector<HornerTerm> with, without;
-    for (HornerTerm &t : merged) {
+    for (HornerTerm &t : m) {
         auto it = std::find(t.leaves.begin(), t.leaves.end(), a);
         if (it == t.leaves.end()) {
             without.push_back(std::move(t));
@@ -137,32 +119,61 @@ HornerValue horner_split(std::vector<HornerTerm> merged, const LeafName &leaf_na
             with.push_back(std::move(t));
         }
     }
-    const HornerValue vw = horner(with, leaf_name, o, temps, memo);
-    const HornerValue vo = horner(without, leaf_name, o, temps, memo);
-    if (vw.zero) return vo;
-    const std::string fa = leaf_name(a);
-    // F_a * vw + vo
-    std::string rhs;
-    bool neg = false;
-    if (vw.constant && (vw.c == 1.0 || vw.c == -1.0)) {
-        if (vo.zero) {                       // +-F_a itself
-            r.name = fa;
-            r.negate = vw.c < 0.0;
-            return r;
-        }
-        rhs = vo.expr() + (vw.c < 0.0 ? " - " : " + ") + fa;
-    } else if (vw.constant) {
-        rhs = vo.zero ? num(vw.c) + " * " + fa : "fma(" + num(vw.c) + ", " + fa + ", " + vo.expr() + ")";
-    } else if (vo.zero) {
-        rhs = fa + " * " + vw.name;          // the sign of vw carries over
-        neg = vw.negate;
+    const HRef w = horner_nodes(with, nodes, memo);
+    const HRef u = horner_nodes(without, nodes, memo);
+    if (w.kind == HRef::ZERO) {
+        r = u;
+    } else if (w.kind == HRef::CONST && (w.c == 1.0 || w.c == -1.0) && u.kind == HRef::ZERO) {
+        r.kind = HRef::LEAF;           // +-F_a itself
+        r.idx = a;
+        r.neg = w.c < 0.0;
     } else {
-        rhs = "fma(" + (vw.negate ? "-" + fa : fa) + ", " + vw.name + ", " + vo.expr() + ")";
+        nodes.push_back(HNode{a, w, u});
+        r.kind = HRef::NODE;
+        r.idx = static_cast<int>(nodes.size()) - 1;
     }
-    r.name = "h" + std::to_string(temps++);
-    r.negate = neg;
-    o << "    const double " << r.name << " = " << rhs << ";\n";
+    memo[key] = flip ? href_negated(r) : r;
     return r;
+}
+
+// The nesting of sum_t c_t prod F over the given terms: its nodes and value.
+HRef horner_build(std::vector<HornerTerm> ts, std::vector<HNode> &nodes) {
+    HMemo memo;
+    return horner_nodes(std::move(ts), nodes, memo);
+}
+
+template <typename LeafName>
+std::string href_name(const HRef &r, const LeafName &leaf_name) {   // without its sign
+    if (r.kind == HRef::LEAF) return leaf_name(r.idx);
+    if (r.kind == HRef::NODE) return "h" + std::to_string(r.idx);
+    return r.kind == HRef::CONST ? num(r.c) : std::string("0.0");
+}
+
+template <typename LeafName>
+std::string href_expr(const HRef &r, const LeafName &leaf_name) {
+    if (r.kind == HRef::CONST || r.kind == HRef::ZERO) return href_name(r, leaf_name);
+    return r.neg ? "(-" + href_name(r, leaf_name) + ")" : href_name(r, leaf_name);
+}
+
+// The nodes as "const double h<k> = ...;" (one fma, mul or add each).
+template <typename LeafName>
+void horner_emit(const std::vector<HNode> &nodes, const LeafName &leaf_name, std::ostream &o) {
+    for (size_t k = 0; k < nodes.size(); ++k) {
+        const HNode &n = nodes[k];
+        const std::string fa = leaf_name(n.a);
+        std::string rhs;
+        if (n.w.kind == HRef::CONST) {
+            if (n.w.c == 1.0 || n.w.c == -1.0) rhs = href_expr(n.u, leaf_name) + (n.w.c < 0 ? " - " : " + ") + fa;
+            else if (n.u.kind == HRef::ZERO) rhs = num(n.w.c) + " * " + fa;
+            else rhs = "fma(" + num(n.w.c) + ", " + fa + ", " + href_expr(n.u, leaf_name) + ")";
+        } else {
+            const std::string sfa = n.w.neg ? "-" + fa : fa;
+            const std::string wn = href_name(n.w, leaf_name);
+            if (n.u.kind == HRef::ZERO) rhs = (n.w.neg ? "(-" + fa + ")" : fa) + " * " + wn;
+            else rhs = "fma(" + sfa + ", " + wn + ", " + href_expr(n.u, leaf_name) + ")";
+        }
+        o << "    const double h" << k << " = " << rhs << ";\n";
+    }
 }
 
 // The same greedy nesting for a sum of products whose factors may be complex:
@@ -524,10 +535,10 @@ std::string jit_source(const AmiTerms *t, bool hub, int kernels) {
             for (int j = 0; j < ni; ++j) h.leaves.push_back(tb.term_leaf[static_cast<size_t>(ti) * ni + j]);
             ts.push_back(std::move(h));
         }
-        int temps = 0;
-        HornerMemo memo;
-        const HornerValue v = horner(ts, leaf_name, o, temps, memo);
-        o << "    ft = " << v.expr() << ";\n";
+        std::vector<HNode> nodes;
+        const HRef v = horner_build(std::move(ts), nodes);
+        horner_emit(nodes, leaf_name, o);
+        o << "    ft = " << href_expr(v, leaf_name) << ";\n";
         o << "    " << sink_prefix << g << sink_suffix << " = ft; }\n";
     }
     };
