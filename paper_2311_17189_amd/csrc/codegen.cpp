@@ -539,7 +539,8 @@ std::string jit_source(const AmiTerms *t, bool hub, int kernels) {
         const HRef v = horner_build(std::move(ts), nodes);
         horner_emit(nodes, leaf_name, o);
         o << "    ft = " << href_expr(v, leaf_name) << ";\n";
-        o << "    " << sink_prefix << g << sink_suffix << " = ft; }\n";
+        if (sink_suffix.find("ft)") != std::string::npos) o << "    " << sink_prefix << g << sink_suffix << "; }\n";
+        else o << "    " << sink_prefix << g << sink_suffix << " = ft; }\n";
     }
     };
     if (one_pass) {
@@ -549,8 +550,9 @@ std::string jit_source(const AmiTerms *t, bool hub, int kernels) {
     }
     // two-pass forward, first pass: each group sum stored as soon as it is formed
     if (kernels & 16) {
-        o << "__device__ __forceinline__ void group_sums_store(const double (&F)[L], double *dst, int64_t ld) {\n";
-        group_sums_body("dst[(int64_t)", " * ld]", true);
+        o << "__device__ __forceinline__ void group_sums_store(const double (&F)[L], double *ws, int64_t ld, "
+             "uint32_t off) {\n";
+        group_sums_body("ami::ws_store(ws, ld, ", ", off, ft)", true);
         o << "}\n";
     }
 
@@ -713,7 +715,7 @@ std::string jit_source(const AmiTerms *t, bool hub, int kernels) {
     // reciprocals, each stored group sum read where the nesting needs it
     if (kernels & 32) {
         o << "__device__ __forceinline__ void group_accumulate(const double (&xr)[D], const double (&xi)[D], "
-             "const double *ft, int64_t ld, double &acc_re, double &acc_im) {\n";
+             "const double *ws, int64_t ld, uint32_t off, double &acc_re, double &acc_im) {\n";
         // sum_g FT_g R_g nested over the reciprocals (factor k < D: z_k; factor
         // D + g: the stored FT_g, read where the nesting first needs it)
         std::vector<HornerTerm> ts;
@@ -733,7 +735,7 @@ std::string jit_source(const AmiTerms *t, bool hub, int kernels) {
             } else {
                 const int g = k - D;
                 if (!loaded[static_cast<size_t>(g)]) {
-                    o << "    const double ft" << g << " = ft[(int64_t)" << g << " * ld];\n";
+                    o << "    const double ft" << g << " = ami::ws_load(ws, ld, " << g << ", off);\n";
                     loaded[static_cast<size_t>(g)] = true;
                 }
                 v.kind = CVal::REAL;

@@ -342,6 +342,18 @@ __device__ __forceinline__ double wave_sum(double v) {
     return __builtin_bit_cast(double, (static_cast<unsigned long long>(hi) << 32) | lo);
 }
 
+// Element (column c, sample at byte offset off) of a [column][sample]
+// workspace with leading dimension ld: the column's base is wave-uniform and
+// the offset a 32-bit lane value, which the compiler turns into a load or store
+// with a scalar base and no vector address arithmetic.
+__device__ __forceinline__ double ws_load(const double *ws, int64_t ld, int c, uint32_t off) {
+    return *reinterpret_cast<const double *>(reinterpret_cast<const char *>(ws + c * ld) + off);
+}
+
+__device__ __forceinline__ void ws_store(double *ws, int64_t ld, int c, uint32_t off, double v) {
+    *reinterpret_cast<double *>(reinterpret_cast<char *>(ws + c * ld) + off) = v;
+}
+
 // gfx950 lane exchanges of a double, as two 32-bit halves: swap32 exchanges
 // lanes 32-63 of x with lanes 0-31 of y (afterwards x holds the lower halves
 // of both, y the upper halves); swap16 exchanges rows 1 and 3 of x with rows 0

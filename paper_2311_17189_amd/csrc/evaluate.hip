@@ -483,6 +483,7 @@ AmiStatus launch_two_pass(AmiTerms *t, DeviceTables *dt, bool hub, KArgs &a, dou
     const int64_t chunk_bytes = g_two_pass_chunk_bytes.load();
     int64_t ld = chunk_bytes / (cols * static_cast<int64_t>(sizeof(double))) / B * B;
     ld = std::max<int64_t>(B, std::min<int64_t>(ld, tiles * B));
+    ld = std::min<int64_t>(ld, int64_t(1) << 28);   // the kernels address a chunk with 32-bit byte offsets
     double *ws = nullptr;
     const int ncols = a.mc ? 4 * a.n_f : 2 * a.n_f;   // per-wave sums (Monte Carlo: with squares)
     const size_t n_part = out_sum ? static_cast<size_t>(rows) * ncols : 0;

@@ -542,17 +542,18 @@ __device__ __forceinline__ void sums_tile(const KArgs &a, int64_t tile) {
         else ami::leaf_pair(false, a.beta * x[l], F[l], FM[l]);
     }
     taylor_leaves(F, FM, a.beta);
-    group_sums_store(F, a.work + i, a.ld);
+    const uint32_t off = static_cast<uint32_t>(i) * 8u;   // i < ld <= 2^28 (host bound)
+    group_sums_store(F, a.work, a.ld, off);
 #pragma unroll
-    for (int j = 0; j < NE; ++j) a.work[(G + j) * a.ld + i] = E[j];
+    for (int j = 0; j < NE; ++j) ami::ws_store(a.work, a.ld, G + j, off, E[j]);
 }
 #endif
 
 #if AMI_JIT_KERNELS & 32
-// Two-pass forward, second pass: block (tile, f) evaluates frequency row
-// f = blockIdx.y for the samples of one tile of the chunk: the reciprocals of
-// every distinct denominator from the stored energies, then group by group
-// R_g times the stored FT_g, accumulated.  Values go to out[f][s0 + i]; the
+// Two-pass forward, second pass: block (tile, f) evaluates frequency row f
+// for the samples of one tile of the chunk: the reciprocals of every distinct
+// denominator from the stored energies, then sum_g FT_g R_g nested over the
+// reciprocals, each stored FT_g read where the nesting needs it.  Values go to out[f][s0 + i]; the
 // wave sums to row (s0 / B + tile) * (B / 64) + wave, columns 2 f, 2 f + 1.
 __device__ __forceinline__ void freq_tile(const KArgs &a, int64_t tile, int f) {
     const int tid = threadIdx.x, B = blockDim.x, lane = tid & 63;
@@ -560,13 +561,14 @@ __device__ __forceinline__ void freq_tile(const KArgs &a, int64_t tile, int f) {
     const bool active = i < a.n_chunk;
     const int64_t row = (a.s0 / B + tile) * (B >> 6) + (tid >> 6);
     double E[NE];
+    const uint32_t off = static_cast<uint32_t>(i) * 8u;   // i < ld <= 2^28 (host bound)
 #pragma unroll
-    for (int j = 0; j < NE; ++j) E[j] = a.work[(G + j) * a.ld + i];
+    for (int j = 0; j < NE; ++j) E[j] = ami::ws_load(a.work, a.ld, G + j, off);
     double wr[NXA], wi[NXA], xr[D], xi[D];
     load_freq(a, f, wr, wi);
     reciprocals(E, wr, wi, xr, xi);
     double acc_re = 0.0, acc_im = 0.0;
-    group_accumulate(xr, xi, a.work + i, a.ld, acc_re, acc_im);
+    group_accumulate(xr, xi, a.work, a.ld, off, acc_re, acc_im);
     if (a.mc) {                         // Monte Carlo: sums and sums of squares per frequency row
         const double re = active ? acc_re : 0.0, im = active ? acc_im : 0.0;
         double *dst = a.partial + 4 * f * a.nrows + row;

@@ -61,7 +61,7 @@ int main() {
             ami::leaf_pair(kBose[l], beta * x[l], F[l], FM[l]);
         }
         taylor_leaves(F, FM, beta);
-        group_sums_store(F, ft, 1);
+        group_sums_store(F, ft, 1, 0u);
         // second pass, frequency by frequency
         for (int f = 0; f < n_f; ++f) {
             double wr[NXA], wi[NXA], dr[D], di[D], xr[D], xi[D];
@@ -76,7 +76,7 @@ int main() {
                 xi[k] = -di[k] * inv;
             }
             double acc_re = 0.0, acc_im = 0.0;
-            group_accumulate(xr, xi, ft, 1, acc_re, acc_im);
+            group_accumulate(xr, xi, ft, 1, 0u, acc_re, acc_im);
             std::printf("%.17g %.17g ", acc_re, acc_im);
         }
         std::printf("\n");
