@@ -12,7 +12,9 @@ Workload (one step = one pass of the evaluation path over one batch):
   momentum component, mu, t, beta and the external frequency (adjoint), in one
   pass of the adjoint kernel with values.  The kernels are the diagram's own
   specialized ones (generated and compiled at run time, before the timed
-  region).
+  region).  Each timed step is one replay of a HIP graph holding the step's
+  launches (captured once after the warm-up; --no-graph times plain
+  launches); the same steps as plain launches are reported beside it.
 
 Metric: term-evaluations/s = T * N_E * N_F / (seconds per step), T the number
 of canonical flat terms; the forward alone, the table-driven (packed) kernels
@@ -47,6 +49,8 @@ def parse():
     ap.add_argument("--beta", type=float, default=5.0)
     ap.add_argument("--cpu-seconds", type=float, default=15.0,
                     help="target duration of the oracle CPU baseline (0 disables it)")
+    ap.add_argument("--no-graph", action="store_true",
+                    help="time the steps as plain launches instead of HIP graph replays")
     ap.add_argument("--no-batch", action="store_true",
                     help="skip the persistent mixed-diagram batch section")
     ap.add_argument("--batch-n-e", type=int, default=200_000)
@@ -186,8 +190,7 @@ def batch_section(args, torch, dev):
                                  want_sum=True, out=it["out"], out_sum=it["out_sum"], stream=stream)
 
     def timed(fn, reps=3):
-        fn()
-        torch.cuda.synchronize()
+        _warm(torch, fn)
         ts = []
         for _ in range(reps):
             a0 = torch.cuda.Event(enable_timing=True)
@@ -226,11 +229,23 @@ def batch_section(args, torch, dev):
     }
 
 
+def _warm(torch, fn, calls=1, seconds=0.1):
+    """Untimed calls right before a timed loop: at least `calls` of them and
+    at least `seconds` of work, so that timing does not start on a clock still
+    ramping up after idle set-up."""
+    n, t_end = 0, time.perf_counter() + seconds
+    while n < calls or time.perf_counter() < t_end:
+        fn()
+        n += 1
+        if n % 10 == 0:
+            torch.cuda.synchronize()
+    torch.cuda.synchronize()
+
+
 def _timed_kernel(torch, amd, stream, fn, reps):
     """(ms per call between stream events, mean kernel ms from the library's
-    dispatch events) over `reps` calls after one warm call."""
-    fn()
-    torch.cuda.synchronize()
+    dispatch events) over `reps` calls after the warm-up of _warm."""
+    _warm(torch, fn)
     amd.kernel_timer_start(reps)
     e0 = torch.cuda.Event(enable_timing=True)
     e1 = torch.cuda.Event(enable_timing=True)
@@ -421,26 +436,66 @@ def main():
     torch.cuda.synchronize()
     step_variant = amd.last_variant()
 
-    # timed region: K steps; the library records HIP events on the launch
-    # stream around the main kernel of every step
-    start = torch.cuda.Event(enable_timing=True)
-    stop = torch.cuda.Event(enable_timing=True)
-    torch.cuda.synchronize()
-    amd.kernel_timer_start(args.steps)
+    # the step as a HIP graph: captured once on a side stream (after the
+    # kernels are loaded and the workspace sized there), replayed per step
+    graph, gstream, graph_note = None, None, None
+    if not args.no_graph:
+        try:
+            gstream = torch.cuda.Stream()
+            gstream.wait_stream(stream)
+            with torch.cuda.stream(gstream):
+                amd.evaluate_hubbard_adjoint(terms, k, q, hop_t, mu, w, args.beta, grad_sum=g_sum,
+                                             out=out, out_sum=out_sum, grads=grads[0])
+            torch.cuda.synchronize()
+            graph = torch.cuda.CUDAGraph()
+            with torch.cuda.graph(graph, stream=gstream):
+                amd.evaluate_hubbard_adjoint(terms, k, q, hop_t, mu, w, args.beta, grad_sum=g_sum,
+                                             out=out, out_sum=out_sum, grads=grads[0])
+        except Exception as e:            # reported, not fatal: the steps are then plain launches
+            graph, graph_note = None, f"not captured: {e}"
+
+    def warm(replay):
+        # untimed steps right before the timed loop (at least W of them)
+        with torch.cuda.stream(gstream if replay else stream):
+            _warm(torch, graph.replay if replay else step, calls=max(args.warmup, 1))
+
+    def timed_steps(replay):
+        s_ = gstream if replay else stream
+        t0 = torch.cuda.Event(enable_timing=True)
+        t1 = torch.cuda.Event(enable_timing=True)
+        torch.cuda.synchronize()
+        with torch.cuda.stream(s_):       # replay() launches on the current stream
+            t0.record(s_)
+            for _ in range(args.steps):
+                if replay:
+                    graph.replay()
+                else:
+                    step()
+            t1.record(s_)
+        torch.cuda.synchronize()
+        return t0.elapsed_time(t1) / args.steps
+
+    # timed region: K steps, each one graph replay of the whole step (plain
+    # launches with --no-graph or when the capture failed)
+    warm(graph is not None)
     wall0 = time.perf_counter()
-    start.record(stream)
-    for i in range(args.steps):
-        step()
-    stop.record(stream)
-    torch.cuda.synchronize()
+    ms_step = timed_steps(graph is not None)
     wall = time.perf_counter() - wall0
+    step_mode = "graph replay" if graph is not None else "launches"
+
+    # the same K steps as plain launches; the library records HIP events on
+    # the launch stream around the main kernel of every step (the roofline's
+    # kernel duration)
+    warm(False)
+    amd.kernel_timer_start(args.steps)
+    launch_ms = timed_steps(False)
     kernel_ms = amd.kernel_timer_stop()
-    ms_step = start.elapsed_time(stop) / args.steps
     step_kernel_ms = sum(kernel_ms) / len(kernel_ms)
+    graph_ms = ms_step if graph is not None else graph_note
+    del graph
 
     def timed(fn, reps):
-        fn()
-        torch.cuda.synchronize()
+        _warm(torch, fn)
         a0 = torch.cuda.Event(enable_timing=True)
         a1 = torch.cuda.Event(enable_timing=True)
         a0.record(stream)
@@ -458,35 +513,6 @@ def main():
     host_ms = (time.perf_counter() - h0) * 1e3 / args.steps
     torch.cuda.synchronize()
 
-    # the same step replayed as a HIP graph (captured on a side stream once the
-    # kernels are loaded and the workspace sized there): launch cost of one graph
-    graph_ms = None
-    try:
-        gs_ = torch.cuda.Stream()
-        gs_.wait_stream(stream)
-        with torch.cuda.stream(gs_):
-            gr = amd.evaluate_hubbard_adjoint(terms, k, q, hop_t, mu, w, args.beta, grad_sum=g_sum,
-                                              out=out, out_sum=out_sum, grads=grads[0])
-        torch.cuda.synchronize()
-        graph = torch.cuda.CUDAGraph()
-        with torch.cuda.graph(graph, stream=gs_):
-            amd.evaluate_hubbard_adjoint(terms, k, q, hop_t, mu, w, args.beta, grad_sum=g_sum,
-                                         out=out, out_sum=out_sum, grads=gr)
-        g0 = torch.cuda.Event(enable_timing=True)
-        g1 = torch.cuda.Event(enable_timing=True)
-        with torch.cuda.stream(gs_):         # replay() launches on the current stream
-            graph.replay()
-            torch.cuda.synchronize()
-            g0.record(gs_)
-            for _ in range(args.steps):
-                graph.replay()
-            g1.record(gs_)
-        torch.cuda.synchronize()
-        graph_ms = g0.elapsed_time(g1) / args.steps
-        del graph
-    except Exception as e:            # reported, not fatal
-        graph_ms = f"not captured: {e}"
-
     # beside the step: forward alone and adjoint alone (separate passes)
     reps = max(5, args.steps // 2)
     fwd_ms = timed(fwd, reps)
@@ -502,9 +528,7 @@ def main():
 
     # the plain per-diagram kernel (double tables) on the same launch, outside the timed region
     terms.set_variant(amd.VARIANT_TABLES)
-    for _ in range(2):
-        fwd()
-    torch.cuda.synchronize()
+    _warm(torch, fwd, calls=2)
     p0 = torch.cuda.Event(enable_timing=True)
     p1 = torch.cuda.Event(enable_timing=True)
     n_plain = max(5, args.steps // 2)
@@ -523,7 +547,8 @@ def main():
     try:
         n_mc = 10 * n_e
         sums = amd.integrate_hubbard(terms, n_mc, 1234, q, hop_t, mu, w, args.beta, stream=stream)
-        torch.cuda.synchronize()
+        _warm(torch, lambda: amd.integrate_hubbard(terms, n_mc, 1234, q, hop_t, mu, w, args.beta, sums=sums,
+                                                   stream=stream))
         amd.kernel_timer_start(5)
         m0 = torch.cuda.Event(enable_timing=True)
         m1 = torch.cuda.Event(enable_timing=True)
@@ -593,9 +618,9 @@ def main():
         "fwd": {"ms": fwd_ms, "term_evals_per_s": te / (fwd_ms * 1e-3), "kernel": fwd_variant,
                 "flops": fl["total"], "tflops": fl["total"] / (fwd_ms * 1e-3) / 1e12,
                 "frac_fp64_peak": fl["total"] / (fwd_ms * 1e-3) / rl.PEAK_FP64_VECTOR},
-        "fwd_adjoint": {"one_pass_ms": ms_step, "one_pass_kernel_ms": step_kernel_ms,
+        "fwd_adjoint": {"step_mode": step_mode, "one_pass_ms": launch_ms, "one_pass_kernel_ms": step_kernel_ms,
                         "host_ms_per_call": host_ms, "graph_ms_per_step": graph_ms,
-                        "one_pass_term_evals_per_s": te / (ms_step * 1e-3), "kernel": step_variant,
+                        "one_pass_term_evals_per_s": te / (launch_ms * 1e-3), "kernel": step_variant,
                         "separate_ms": fwd_ms + adj_ms, "adjoint_ms": adj_ms,
                         "adjoint_flops": fa["total"],
                         "adjoint_tflops": fa["total"] / (adj_ms * 1e-3) / 1e12},
@@ -604,7 +629,7 @@ def main():
                            "step_ms": packed_step_ms,
                            "step_term_evals_per_s": te / (packed_step_ms * 1e-3),
                            "step_tflops": pfs["total"] / (packed_step_ms * 1e-3) / 1e12,
-                           "speedup_of_specialized_step": packed_step_ms / ms_step},
+                           "speedup_of_specialized_step": packed_step_ms / launch_ms},
         "plain_kernel": {"ms": plain_ms, "term_evals_per_s": te / (plain_ms * 1e-3),
                          "kernel": plain_variant, "speedup_of_fwd": plain_ms / fwd_ms},
         "roofline": {

@@ -58,12 +58,20 @@ def _store_cache(path, data):
         pass
 
 
-def time_batch(batch, reps: int = 3, stream=None) -> float:
-    """Median milliseconds of one batch graph launch (after one warm-up)."""
+def time_batch(batch, reps: int = 3, stream=None, warm_s: float = 0.05) -> float:
+    """Median milliseconds of one batch graph launch, after launches for at
+    least `warm_s` seconds (so timing does not start on a clock still ramping
+    up) and at least one."""
+    import time
+
     import torch
     s = stream if stream is not None else torch.cuda.current_stream()
+    t_end = time.perf_counter() + warm_s
     batch.run(s)
     torch.cuda.synchronize()
+    while time.perf_counter() < t_end:
+        batch.run(s)
+        torch.cuda.synchronize()
     times = []
     for _ in range(reps):
         a = torch.cuda.Event(enable_timing=True)
