@@ -51,6 +51,59 @@ struct HornerTerm {
     std::vector<int> leaves;   // a multiset (a leaf may repeat)
 };
 
+// The terms with their leaf multisets sorted, equal multisets merged and
+// zero coefficients dropped.
+std::vector<HornerTerm> merged_terms(std::vector<HornerTerm> ts) {
+    for (HornerTerm &t : ts) std::sort(t.leaves.begin(), t.leaves.end());
+    std::sort(ts.begin(), ts.end(), [](const HornerTerm &x, const HornerTerm &y) { return x.leaves < y.leaves; });
+    std::vector<HornerTerm> m;
+    for (HornerTerm &t : ts) {
+        if (!m.empty() && m.back().leaves == t.leaves) m.back().c += t.c;
+        else m.push_back(std::move(t));
+    }
+    m.erase(std::remove_if(m.begin(), m.end(), [](const HornerTerm &t) { return t.c == 0.0; }), m.end());
+    return m;
+}
+
+// The merged sum's key up to sign (`flip`: its first coefficient is negative
+// and the key is that of the negated sum).
+std::string sum_key(const std::vector<HornerTerm> &m, bool &flip) {
+    flip = m[0].c < 0.0;
+    std::string key;
+    for (const HornerTerm &t : m) {
+        key += num(flip ? -t.c : t.c) + ":";
+        for (int l : t.leaves) key += std::to_string(l) + ",";
+        key += ";";
+    }
+    return key;
+}
+
+// One step of the nesting: the leaf in the most terms (the lowest index among
+// equals) and the terms split into those holding it (one occurrence removed)
+// and the others.
+int split_on_shared_leaf(std::vector<HornerTerm> m, std::vector<HornerTerm> &with, std::vector<HornerTerm> &without) {
+    std::map<int, int> count;   // terms holding each leaf
+    for (const HornerTerm &t : m)
+        for (size_t j = 0; j < t.leaves.size(); ++j)
+            if (j == 0 || t.leaves[j] != t.leaves[j - 1]) ++count[t.leaves[j]];
+    int a = -1, best = 0;
+    for (const auto &kv : count)
+        if (kv.second > best) {
+            a = kv.first;
+            best = kv.second;
+        }
+    for (HornerTerm &t : m) {
+        auto it = std::find(t.leaves.begin(), t.leaves.end(), a);
+        if (it == t.leaves.end()) {
+            without.push_back(std::move(t));
+        } else {
+            t.leaves.erase(it);
+            with.push_back(std::move(t));
+        }
+    }
+    return a;
+}
+
 // A value of the nesting: zero, a number, a leaf or a node, with a sign.
 struct HRef {
     enum Kind { ZERO, CONST, LEAF, NODE } kind = ZERO;
@@ -75,14 +128,7 @@ HRef href_negated(HRef r) {
 using HMemo = std::map<std::string, HRef>;
 
 HRef horner_nodes(std::vector<HornerTerm> ts, std::vector<HNode> &nodes, HMemo &memo) {
-    for (HornerTerm &t : ts) std::sort(t.leaves.begin(), t.leaves.end());
-    std::sort(ts.begin(), ts.end(), [](const HornerTerm &x, const HornerTerm &y) { return x.leaves < y.leaves; });
-    std::vector<HornerTerm> m;
-    for (HornerTerm &t : ts) {
-        if (!m.empty() && m.back().leaves == t.leaves) m.back().c += t.c;
-        else m.push_back(std::move(t));
-    }
-    m.erase(std::remove_if(m.begin(), m.end(), [](const HornerTerm &t) { return t.c == 0.0; }), m.end());
+    std::vector<HornerTerm> m = merged_terms(std::move(ts));
     HRef r;
     if (m.empty()) return r;
     if (m.size() == 1 && m[0].leaves.empty()) {
@@ -90,35 +136,11 @@ HRef horner_nodes(std::vector<HornerTerm> ts, std::vector<HNode> &nodes, HMemo &
         r.c = m[0].c;
         return r;
     }
-    // the sum's key with its first coefficient made positive
-    const bool flip = m[0].c < 0.0;
-    std::string key;
-    for (const HornerTerm &t : m) {
-        key += num(flip ? -t.c : t.c) + ":";
-        for (int l : t.leaves) key += std::to_string(l) + ",";
-        key += ";";
-    }
+    bool flip;
+    const std::string key = sum_key(m, flip);
     if (const auto it = memo.find(key); it != memo.end()) return flip ? href_negated(it->second) : it->second;
-    std::map<int, int> count;   // terms holding each leaf
-    for (const HornerTerm &t : m)
-        for (size_t j = 0; j < t.leaves.size(); ++j)
-            if (j == 0 || t.leaves[j] != t.leaves[j - 1]) ++count[t.leaves[j]];
-    int a = -1, best = 0;
-    for (const auto &kv : count)
-        if (kv.second > best) {
-            a = kv.first;
-            best = kv.second;
-        }
     std::vector<HornerTerm> with, without;
-    for (HornerTerm &t : m) {
-        auto it = std::find(t.leaves.begin(), t.leaves.end(), a);
-        if (it == t.leaves.end()) {
-            without.push_back(std::move(t));
-        } else {
-            t.leaves.erase(it);
-            with.push_back(std::move(t));
-        }
-    }
+    const int a = split_on_shared_leaf(std::move(m), with, without);
     const HRef w = horner_nodes(with, nodes, memo);
     const HRef u = horner_nodes(without, nodes, memo);
     if (w.kind == HRef::ZERO) {
@@ -216,14 +238,7 @@ using CMemo = std::map<std::string, CVal>;
 // leaf(a) gives the value of factor a (a REAL or CPLX CVal of names)
 template <typename Leaf>
 CVal horner_c(std::vector<HornerTerm> ts, const Leaf &leaf, std::ostream &o, int &temps, CMemo &memo) {
-    for (HornerTerm &t : ts) std::sort(t.leaves.begin(), t.leaves.end());
-    std::sort(ts.begin(), ts.end(), [](const HornerTerm &x, const HornerTerm &y) { return x.leaves < y.leaves; });
-    std::vector<HornerTerm> m;
-    for (HornerTerm &t : ts) {
-        if (!m.empty() && m.back().leaves == t.leaves) m.back().c += t.c;
-        else m.push_back(std::move(t));
-    }
-    m.erase(std::remove_if(m.begin(), m.end(), [](const HornerTerm &t) { return t.c == 0.0; }), m.end());
+    std::vector<HornerTerm> m = merged_terms(std::move(ts));
     CVal r;
     if (m.empty()) return r;
     if (m.size() == 1 && m[0].leaves.empty()) {
@@ -231,34 +246,11 @@ CVal horner_c(std::vector<HornerTerm> ts, const Leaf &leaf, std::ostream &o, int
         r.c = m[0].c;
         return r;
     }
-    const bool flip = m[0].c < 0.0;
-    std::string key;
-    for (const HornerTerm &t : m) {
-        key += num(flip ? -t.c : t.c) + ":";
-        for (int l : t.leaves) key += std::to_string(l) + ",";
-        key += ";";
-    }
+    bool flip;
+    const std::string key = sum_key(m, flip);
     if (const auto it = memo.find(key); it != memo.end()) return flip ? cnegated(it->second) : it->second;
-    std::map<int, int> count;
-    for (const HornerTerm &t : m)
-        for (size_t j = 0; j < t.leaves.size(); ++j)
-            if (j == 0 || t.leaves[j] != t.leaves[j - 1]) ++count[t.leaves[j]];
-    int a = -1, best = 0;
-    for (const auto &kv : count)
-        if (kv.second > best) {
-            a = kv.first;
-            best = kv.second;
-        }
     std::vector<HornerTerm> with, without;
-    for (HornerTerm &t : m) {
-        auto it = std::find(t.leaves.begin(), t.leaves.end(), a);
-        if (it == t.leaves.end()) {
-            without.push_back(std::move(t));
-        } else {
-            t.leaves.erase(it);
-            with.push_back(std::move(t));
-        }
-    }
+    const int a = split_on_shared_leaf(std::move(m), with, without);
     const CVal w = horner_c(with, leaf, o, temps, memo);
     const CVal u = horner_c(without, leaf, o, temps, memo);
     const CVal L = leaf(a);
