@@ -493,6 +493,11 @@ def main():
     step_kernel_ms = sum(kernel_ms) / len(kernel_ms)
     graph_ms = ms_step if graph is not None else graph_note
     del graph
+    # FP64 FMA throughput of this GPU right after the timed steps (clock warm)
+    try:
+        fma_peak = amd.measure_fp64_peak(1 << 16, stream=stream)
+    except amd.AmiError:
+        fma_peak = None
 
     def timed(fn, reps):
         _warm(torch, fn)
@@ -643,6 +648,10 @@ def main():
             "kernel": dom,
             "flops_per_launch": dom_fl,
             "kernel_ms": dom_ms,
+            # FP64 FMA throughput measured on this GPU (eight independent FMA
+            # chains per lane, eight waves per SIMD), beside the vendor peak
+            "measured_fma_peak": fma_peak,
+            "frac_of_measured_fma_peak": (achieved / 1e12 / fma_peak) if fma_peak else None,
         },
         "monte_carlo": mc,
         "construct_ms": construct_ms,

@@ -399,6 +399,17 @@ AmiStatus amiTermsSource(const AmiTerms *terms, int32_t momentum, char *buf, int
 AmiStatus amiKernelTimerStart(int32_t capacity);
 AmiStatus amiKernelTimerStop(float *ms, int32_t cap, int32_t *count);
 
+/*
+ * FP64 fused multiply-add throughput of the current device (measurement, not
+ * part of the evaluation): a kernel of eight independent FMA chains per lane
+ * for `iters` steps (1..2^24) on 8 blocks of 256 lanes per compute unit,
+ * launched twice on `hip_stream`; the second launch is timed with HIP events
+ * and *tflops (host) receives 2 * 8 * iters * lanes / seconds / 1e12.  Blocks
+ * until done; allocates and frees a small sink buffer.  AMI_E_ARG for a bad
+ * iters or NULL tflops, AMI_E_HIP on a HIP error.
+ */
+AmiStatus amiMeasureFp64Peak(int64_t iters, double *tflops, void *hip_stream);
+
 /* Name of the kernel variant launched by the last evaluate call on this thread. */
 const char *amiLastVariant(void);
 

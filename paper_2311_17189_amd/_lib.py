@@ -112,6 +112,8 @@ def load_library():
     lib.amiTermsSpecialize.restype = c_i32
     lib.amiTermsSource.argtypes = [vp, c_i32, ctypes.c_char_p, c_i64, ctypes.POINTER(c_i64)]
     lib.amiTermsSource.restype = c_i32
+    lib.amiMeasureFp64Peak.argtypes = [c_i64, ctypes.POINTER(ctypes.c_double), vp]
+    lib.amiMeasureFp64Peak.restype = c_i32
     lib.amiKernelTimerStart.argtypes = [c_i32]
     lib.amiKernelTimerStart.restype = c_i32
     lib.amiKernelTimerStop.argtypes = [vp, c_i32, ctypes.POINTER(c_i32)]
@@ -146,6 +148,14 @@ def version() -> str:
 
 
 _timer_capacity = 0
+
+
+def measure_fp64_peak(iters: int = 1 << 16, stream=None) -> float:
+    """FP64 FMA throughput of the current device in TFLOP/s
+    (``amiMeasureFp64Peak``; blocks until done)."""
+    v = ctypes.c_double()
+    _check(load_library().amiMeasureFp64Peak(int(iters), ctypes.byref(v), _stream_ptr(stream)))
+    return v.value
 
 
 def kernel_timer_start(capacity: int):
