@@ -627,29 +627,16 @@ std::string jit_source(const AmiTerms *t, bool hub, int kernels) {
     }
     o << "}\n";
 
-    // group products R_g = prod rho_k (complex), left to right; with `opaque`
-    // from the group's own copies of its reciprocals (as for the group sums)
-    auto group_product = [&](int g, bool opaque) {
+    // group products R_g = prod rho_k (complex), left to right
+    auto group_product = [&](int g) {
         o << "  { double rr = 1.0, ri = 0.0, nr = 0.0;\n";
-        std::string pr = "xr[", pi = "xi[", sf = "]";
-        if (opaque) {
-            std::vector<int> used(tb.group_den_list.begin() + gbegin(g), tb.group_den_list.begin() + gend(g));
-            std::sort(used.begin(), used.end());
-            used.erase(std::unique(used.begin(), used.end()), used.end());
-            for (int k : used)
-                o << "    double yr" << k << " = xr[" << k << "], yi" << k << " = xi[" << k << "]; AMI_OPAQUE(yr" << k
-                  << "); AMI_OPAQUE(yi" << k << ");\n";
-            pr = "yr";
-            pi = "yi";
-            sf = "";
-        }
         for (int j = 0; j < gend(g) - gbegin(g); ++j) {
             const std::string k = std::to_string(tb.group_den_list[gbegin(g) + j]);
             if (j == 0) {
-                o << "    rr = " << pr << k << sf << "; ri = " << pi << k << sf << ";\n";
+                o << "    rr = xr[" << k << "]; ri = xi[" << k << "];\n";
             } else {
-                o << "    nr = fma(rr, " << pr << k << sf << ", -ri * " << pi << k << sf << "); ri = fma(rr, " << pi
-                  << k << sf << ", ri * " << pr << k << sf << "); rr = nr;\n";
+                o << "    nr = fma(rr, xr[" << k << "], -ri * xi[" << k << "]); ri = fma(rr, xi[" << k
+                  << "], ri * xr[" << k << "]); rr = nr;\n";
             }
         }
     };
@@ -657,7 +644,7 @@ std::string jit_source(const AmiTerms *t, bool hub, int kernels) {
         o << "__device__ __forceinline__ void group_products(const double (&xr)[D], const double (&xi)[D], "
              "double (&Rr)[G], double (&Ri)[G]) {\n";
         for (int g = 0; g < G; ++g) {
-            group_product(g, false);
+            group_product(g);
             o << "    (void)nr; Rr[" << g << "] = rr; Ri[" << g << "] = ri; }\n";
         }
         o << "}\n";
