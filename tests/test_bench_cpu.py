@@ -1,0 +1,31 @@
+"""The benchmark's host-side contract, on the CPU: more than one GPU is
+refused with a message before any device work, and the recorded HBM byte
+counters belong to the kernel sources they were taken on."""
+import json
+import os
+import subprocess
+import sys
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+ROOT = os.path.dirname(HERE)
+
+
+def test_more_than_one_gpu_is_refused_with_a_message():
+    r = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--gpus", "2"], capture_output=True,
+                       text=True, timeout=300, cwd=ROOT)
+    assert "one GPU only" in r.stdout + r.stderr
+    assert not any(l.startswith("{") for l in r.stdout.splitlines())    # no result line
+
+
+def test_traffic_record_names_its_sources():
+    sys.path.insert(0, ROOT)
+    import bench
+    with open(os.path.join(ROOT, "profiles", "traffic.json")) as fh:
+        rec = json.load(fh)
+    assert set(rec) >= {"source_sha256", "note", "kernels"}
+    assert len(rec["source_sha256"]) == 64
+    for per_key in rec["kernels"].values():
+        for v in per_key.values():
+            assert v["fetch_bytes"] > 0 and v["write_bytes"] > 0
+    # bench reports these bytes only while the sources hash the same
+    assert isinstance(bench.kernel_source_hash(), str)
