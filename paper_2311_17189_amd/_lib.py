@@ -316,6 +316,31 @@ def _stream_ptr(stream) -> Optional[int]:
     return s.cuda_stream
 
 
+def _energy_strides(energies):
+    """``(tensor, stride_s, stride_i)`` of an energies tensor [N_E, nE] for the C
+    ABI, whose strides must be >= 1.  A dimension of size 1 is read at index 0
+    only, so its stride is irrelevant and passed as 1; a broadcast dimension
+    (stride 0, e.g. ``E0.expand(N, nE)``) of size > 1 would make the kernels
+    read N rows out of a buffer holding one, so such a tensor is copied to a
+    contiguous one first."""
+    n, m = energies.shape
+    st_s, st_i = energies.stride()
+    if (n > 1 and st_s < 1) or (m > 1 and st_i < 1):
+        energies = energies.contiguous()
+        st_s, st_i = energies.stride()
+    return energies, (st_s if n > 1 else 1), (st_i if m > 1 else 1)
+
+
+def _momentum_rows(k, n_int: int):
+    """``(tensor, stride_k)`` of a momentum tensor [N_E, 2 n_int] (unit column
+    stride) for the C ABI, which needs a row stride >= 2 n_int: rows that
+    overlap or repeat (a broadcast row, stride 0) are copied to a contiguous
+    tensor first; a single row's stride is irrelevant."""
+    if k.shape[0] > 1 and k.stride(0) < 2 * n_int:
+        k = k.contiguous()
+    return k, (k.stride(0) if k.shape[0] > 1 else 2 * n_int)
+
+
 def _freqs(ext_freqs, terms: Terms):
     import torch
     w = ext_freqs
@@ -360,9 +385,9 @@ def evaluate(terms: Terms, energies, ext_freqs, beta: float, e_reg: float = 0.0,
     w = _freqs(ext_freqs, terms)
     n_e, n_f = energies.shape[0], w.shape[0]
     out, out_sum = _outputs(n_f, n_e, energies.device, want_out, want_sum, out, out_sum)
-    st_s, st_i = energies.stride()
+    energies, st_s, st_i = _energy_strides(energies)
     code = load_library().amiEvaluate(
-        terms._h, energies.data_ptr() if n_e else None, n_e, max(st_s, 1), max(st_i, 1),
+        terms._h, energies.data_ptr() if n_e else None, n_e, st_s, st_i,
         w.data_ptr(), n_f, float(beta), float(e_reg),
         out.data_ptr() if out is not None else None,
         out_sum.data_ptr() if out_sum is not None else None,
@@ -383,9 +408,9 @@ def evaluate_complex(terms: Terms, energies, ext_freqs, beta: float, e_reg: floa
     w = _freqs(ext_freqs, terms)
     n_e, n_f = energies.shape[0], w.shape[0]
     out, out_sum = _outputs(n_f, n_e, energies.device, want_out, want_sum, out, out_sum)
-    st_s, st_i = energies.stride()
+    energies, st_s, st_i = _energy_strides(energies)
     _check(load_library().amiEvaluateComplex(
-        terms._h, energies.data_ptr() if n_e else None, n_e, max(st_s, 1), max(st_i, 1),
+        terms._h, energies.data_ptr() if n_e else None, n_e, st_s, st_i,
         w.data_ptr(), n_f, float(beta), float(e_reg),
         out.data_ptr() if out is not None else None,
         out_sum.data_ptr() if out_sum is not None else None, _stream_ptr(stream)))
@@ -407,8 +432,9 @@ def evaluate_hubbard(terms: Terms, k, q: Sequence[float], t: float, mu: float, e
     n_e, n_f = k.shape[0], w.shape[0]
     out, out_sum = _outputs(n_f, n_e, k.device, want_out, want_sum, out, out_sum)
     qa = np.ascontiguousarray(np.asarray(q, dtype=np.float64).reshape(-1))
+    k, st_k = _momentum_rows(k, terms.n_int)
     code = load_library().amiEvaluateHubbard(
-        terms._h, k.data_ptr() if n_e else None, n_e, max(k.stride(0), 2 * terms.n_int),
+        terms._h, k.data_ptr() if n_e else None, n_e, st_k,
         qa.ctypes.data, float(t), float(mu), w.data_ptr(), n_f, float(beta), float(e_reg),
         out.data_ptr() if out is not None else None,
         out_sum.data_ptr() if out_sum is not None else None,
@@ -453,9 +479,9 @@ def evaluate_adjoint(terms: Terms, energies, ext_freqs, beta: float, e_reg: floa
     g_b = torch.empty((), dtype=torch.float64, device=dev)
     g_w = torch.empty((n_f, w.shape[1]), dtype=torch.complex128, device=dev)
     out, out_sum = _outputs(n_f, n_e, dev, False, False, out, out_sum)
-    st_s, st_i = energies.stride()
+    energies, st_s, st_i = _energy_strides(energies)
     _check(load_library().amiEvaluateAdjoint(
-        terms._h, energies.data_ptr() if n_e else None, n_e, max(st_s, 1), max(st_i, 1),
+        terms._h, energies.data_ptr() if n_e else None, n_e, st_s, st_i,
         w.data_ptr(), n_f, float(beta), float(e_reg), _ptr(go), _ptr(gs),
         g_e.data_ptr() if n_e else None, g_b.data_ptr(), g_w.data_ptr(),
         _ptr(out) if n_e else None, _ptr(out_sum), _stream_ptr(stream)))
@@ -490,9 +516,10 @@ def evaluate_hubbard_adjoint(terms: Terms, k, q, t: float, mu: float, ext_freqs,
         g_w = torch.empty((n_f, w.shape[1]), dtype=torch.complex128, device=dev)
     out, out_sum = _outputs(n_f, n_e, dev, False, False, out, out_sum)
     qa = np.ascontiguousarray(np.asarray(q, dtype=np.float64).reshape(-1))
+    k, st_k = _momentum_rows(k, terms.n_int)
     base = scal.data_ptr()
     _check(load_library().amiEvaluateHubbardAdjoint(
-        terms._h, k.data_ptr() if n_e else None, n_e, max(k.stride(0), 2 * terms.n_int),
+        terms._h, k.data_ptr() if n_e else None, n_e, st_k,
         qa.ctypes.data, float(t), float(mu), w.data_ptr(), n_f, float(beta), float(e_reg),
         _ptr(go), _ptr(gs), g_k.data_ptr() if n_e else None, base, base + 8, base + 16,
         g_w.data_ptr(), _ptr(out) if n_e else None, _ptr(out_sum), _stream_ptr(stream)))
@@ -556,7 +583,8 @@ class Batch:
     ``ext_freqs`` (complex128 CUDA [N_F, n_ext]), ``beta``, optional ``e_reg``,
     and the outputs ``out`` (complex128 [N_F, N_E]) and/or ``out_sum``
     (complex128 [N_F]).  The tensors are referenced by the batch; every
-    :meth:`run` evaluates what they hold.  ``tuning`` is a dict with ``block``,
+    :meth:`run` evaluates what they hold (an input with broadcast rows is
+    copied once, here, and the batch reads the copy).  ``tuning`` is a dict with ``block``,
     ``waves_per_cu``, ``tile_factor`` and ``kernels`` (0: specialized kernels
     where AUTO would use them, 1: packed only; see :mod:`.autotune`).
     """
@@ -577,8 +605,8 @@ class Batch:
                 if k.dtype != torch.float64 or not k.is_cuda or k.dim() != 2 or k.shape[1] != 2 * t.n_int \
                         or k.stride(1) != 1:
                     raise AmiError(-1, f"item {i}: k must be float64 CUDA [N_E, 2*n_int]")
+                k, c.stride_k = _momentum_rows(k, t.n_int)
                 c.k = k.data_ptr()
-                c.stride_k = k.stride(0)
                 n_e = k.shape[0]
                 qa = np.asarray(it.get("q", ()), dtype=np.float64).reshape(-1)
                 for j, v in enumerate(qa[:8]):
@@ -590,8 +618,8 @@ class Batch:
                 e = it["energies"]
                 if e.dtype != torch.float64 or not e.is_cuda or e.dim() != 2 or e.shape[1] != t.n_eps:
                     raise AmiError(-1, f"item {i}: energies must be float64 CUDA [N_E, nE]")
+                e, c.stride_s, c.stride_i = _energy_strides(e)
                 c.energies = e.data_ptr()
-                c.stride_s, c.stride_i = e.stride()
                 n_e = e.shape[0]
                 self._keep.append(e)
             c.n_e = n_e

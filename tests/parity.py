@@ -8,6 +8,13 @@ Points within ``near`` of a pole of one term -- a Bose-type leaf argument
 ``|e.E| < near`` or a denominator ``|D| < near`` -- lose digits to the
 rounding of their arguments in float64 on both sides of the comparison and are
 held to the looser ``tol_near``.
+
+The plain relative error ``|got - ref| / |ref|`` is held to the same ``tol``
+wherever it is attainable: away from poles, at points whose cancellation ratio
+``sum_t |v_t| / |ref|`` is at most ``COND_MAX``.  Beyond that ratio the terms
+cancel to a total far below their own size (exponentially small totals, where
+no float64 sum over terms is relatively accurate), and only the
+condition-aware bound applies.
 """
 from __future__ import annotations
 
@@ -19,6 +26,7 @@ from oracle.evaluate import evaluate_terms, energies_from_k, term_magnitudes
 TOL = 1e-10        # relative to sum_t |v_t|, away from poles
 TOL_NEAR = 1e-6    # within NEAR of a pole of one term
 NEAR = 1e-4
+COND_MAX = 1e4     # the plain relative bar applies up to this cancellation ratio
 
 
 def oracle_terms(d):
@@ -61,9 +69,16 @@ def reference_hubbard(d, k, q, t, mu, w, beta, e_reg=0.0, terms=None):
     return ref, scale, dist, E.astype(np.float64)
 
 
-def check(got, ref, scale, dist, tol=TOL, tol_near=TOL_NEAR, near=NEAR, label=""):
+def check(got, ref, scale, dist, tol=TOL, tol_near=TOL_NEAR, near=NEAR, label="", cond_max=COND_MAX,
+          stats=None):
+    """Assert the bars above; returns the worst condition-aware error away from
+    poles.  ``stats``, a dict if given, receives the worst plain relative error
+    where it is asserted, the number of such points, and percentiles of the
+    cancellation ratio."""
     got = np.asarray(got)
-    err = np.abs(got - ref) / np.maximum(scale, 1e-300)
+    ref = np.asarray(ref)
+    diff = np.abs(got - ref)
+    err = diff / np.maximum(scale, 1e-300)
     far = dist >= near
     assert np.all(np.isfinite(got[far])), f"{label}: non-finite output away from poles"
     worst = float(err[far].max()) if far.any() else 0.0
@@ -71,6 +86,18 @@ def check(got, ref, scale, dist, tol=TOL, tol_near=TOL_NEAR, near=NEAR, label=""
     if (~far).any():
         worst_near = float(np.nanmax(err[~far]))
         assert worst_near <= tol_near, f"{label}: max error {worst_near:.3e} near poles"
+    absref = np.abs(ref)
+    ratio = scale / np.maximum(absref, 1e-300)
+    plain = far & (ratio <= cond_max) & (absref > 0)
+    worst_plain = float((diff[plain] / absref[plain]).max()) if plain.any() else 0.0
+    assert worst_plain <= tol, (f"{label}: max plain relative error {worst_plain:.3e} > {tol:.1e} "
+                                f"(away from poles, cancellation ratio <= {cond_max:.0e})")
+    if stats is not None:
+        r = ratio[far] if far.any() else np.zeros(1)
+        stats.update({"worst_plain_rel": worst_plain, "plain_points": int(plain.sum()),
+                      "far_points": int(far.sum()), "ratio_p50": float(np.percentile(r, 50)),
+                      "ratio_p90": float(np.percentile(r, 90)), "ratio_p99": float(np.percentile(r, 99)),
+                      "worst_scaled": worst})
     return worst
 
 

@@ -6,7 +6,7 @@ import pytest
 
 from ami_inputs import (DEFAULT_Q, k_samples, matsubara_freqs, order2_example,
                         random_self_energy, real_freqs, uniform_energies)
-from oracle.evaluate import (energies_from_k, gradients, momentum_gradients)
+from oracle.evaluate import (energies_from_k, gradients, momentum_gradients, term_magnitudes)
 
 from parity import check, far_from_poles, gradient_scale, gradient_scales, oracle_terms, reference
 
@@ -144,8 +144,63 @@ def test_adjoint_matches_finite_differences_of_forward(variant):
         (float(g_b), (loss(t, mu, beta + h, omega) - loss(t, mu, beta - h, omega)) / (2 * h)),
         (float(g_w[0, 0].real), (loss(t, mu, beta, omega + h) - loss(t, mu, beta, omega - h)) / (2 * h)),
     ]
+    # the difference quotient's own rounding: each loss carries an error of a
+    # few ulp of sum_s sum_t |v_t| (the scale of the sum it rounds), divided by 2h
+    E = energies_from_k(d.alpha, kh[keep], q, t, mu)
+    mag = float(np.sum(term_magnitudes(oracle_terms(d), d.n_int, E, np.array([omega + 1j * gamma]), beta)))
+    floor = 8 * 2.0 ** -52 * mag / (2 * h)
     for got, fd in checks:
-        assert abs(got - fd) <= 1e-7 * max(abs(fd), 1e-3 * n_e), (got, fd)
+        assert abs(got - fd) <= 1e-7 * abs(fd) + floor, (got, fd, floor)
+
+
+@VARIANTS
+def test_momentum_gradient_matches_finite_differences(variant):
+    """Every momentum component of the order-4 adjoint step (8 per sample)
+    against central differences (h = 1e-6, float64) of the HIP forward: each
+    component is moved in every sample at once (samples are independent), so
+    16 forward calls give the difference quotient of every (sample, component).
+    The bar is 1e-7 relative plus the quotient's own rounding (a few ulp of
+    sum_t |v_t| over 2h); samples within 0.05 of a pole of one term are left
+    out (the third derivative there outgrows the step)."""
+    d = random_self_energy(4, (0, 4, 1))
+    beta, t, mu = 5.0, 1.0, 0.0
+    q = np.array(DEFAULT_Q)
+    wv = matsubara_freqs(1, beta)
+    kh = k_samples(6000, d.n_int, seed=(27, 4))
+    terms = oracle_terms(d)
+    keep = far_from_poles(terms, d.n_int, energies_from_k(d.alpha, kh, q, t, mu), wv, near=0.05)
+    kk = np.ascontiguousarray(kh[keep])
+    n_e = len(kk)
+    assert n_e > 2000
+    cot = _cot(1, n_e, 28)
+    T = _terms(d, variant)
+    w = torch.from_numpy(wv).to(DEV)
+    kt = torch.from_numpy(kk).to(DEV)
+    g_k, *_ = amd.evaluate_hubbard_adjoint(T, kt, q, t, mu, w, beta, grad_out=torch.from_numpy(cot).to(DEV))
+    g_k = g_k.cpu().numpy()
+    h = 1e-6
+    fd = np.zeros_like(kk)
+    for c in range(2 * d.n_int):
+        plus, minus = kk.copy(), kk.copy()
+        plus[:, c] += h
+        minus[:, c] -= h
+        op, _ = amd.evaluate_hubbard(T, torch.from_numpy(plus).to(DEV), q, t, mu, w, beta)
+        om, _ = amd.evaluate_hubbard(T, torch.from_numpy(minus).to(DEV), q, t, mu, w, beta)
+        dq = (op.cpu().numpy() - om.cpu().numpy()) / (2 * h)
+        fd[:, c] = np.real(np.conj(cot) * dq).sum(axis=0)
+    E = energies_from_k(d.alpha, kk, q, t, mu)
+    mag = (np.abs(cot) * term_magnitudes(terms, d.n_int, E, wv, beta).astype(np.float64)).sum(axis=0)
+    floor = 8 * 2.0 ** -52 * mag / (2 * h)
+    err = np.abs(g_k - fd)
+    bound = 1e-7 * np.abs(fd) + floor[:, None]
+    assert np.all(err <= bound), float(np.max(err / bound))
+    # where the quotient's rounding is below a tenth of the bar, the plain
+    # relative error is within 1e-7 itself
+    clean = floor[:, None] <= 1e-8 * np.abs(fd)
+    worst = float(np.max(err[clean] / np.abs(fd[clean]))) if clean.any() else 0.0
+    print(f"k-gradient vs FD: {int(clean.sum())} of {fd.size} entries under the plain bar, worst {worst:.2e}")
+    assert clean.sum() > n_e // 2
+    assert worst <= 1e-7
 
 
 def test_autograd_function_gradcheck():
@@ -154,9 +209,10 @@ def test_autograd_function_gradcheck():
     T = amd.Terms.from_diagram(d)
     k = torch.from_numpy(k_samples(5, 2, seed=23)).to(DEV).requires_grad_(True)
     q = np.array(DEFAULT_Q)
-    t = torch.tensor(1.0, dtype=torch.float64, device=DEV, requires_grad=True)
-    mu = torch.tensor(0.2, dtype=torch.float64, device=DEV, requires_grad=True)
-    beta = torch.tensor(3.0, dtype=torch.float64, device=DEV, requires_grad=True)
+    # the scalars as host tensors (read without a device synchronization)
+    t = torch.tensor(1.0, dtype=torch.float64, requires_grad=True)
+    mu = torch.tensor(0.2, dtype=torch.float64, requires_grad=True)
+    beta = torch.tensor(3.0, dtype=torch.float64, requires_grad=True)
     w = torch.tensor([[0.4 + 0.3j], [1j * np.pi / 3.0]], dtype=torch.complex128, device=DEV,
                      requires_grad=True)
 
@@ -165,6 +221,26 @@ def test_autograd_function_gradcheck():
         return out, s
 
     assert torch.autograd.gradcheck(f, (k, t, mu, w, beta), eps=1e-6, atol=1e-6, rtol=1e-5)
+
+
+def test_autograd_with_number_scalars_and_device_scalars():
+    """t and mu as plain numbers get no gradient and break nothing; beta as a
+    CUDA tensor gets its gradient on the device; k's gradient equals the
+    adjoint call's."""
+    from paper_2311_17189_amd.autograd import AmiHubbard
+    d = random_self_energy(3, (0, 3, 1))
+    T = amd.Terms.from_diagram(d)
+    q = np.array(DEFAULT_Q)
+    k = torch.from_numpy(k_samples(300, d.n_int, seed=26)).to(DEV).requires_grad_(True)
+    w = torch.from_numpy(matsubara_freqs(2, 4.0)).to(DEV)
+    beta = torch.tensor(4.0, dtype=torch.float64, device=DEV, requires_grad=True)
+    out, s = AmiHubbard.apply(T, k, q, 1.0, 0.1, w, beta)
+    s.real.sum().backward()
+    gs = torch.ones(2, dtype=torch.complex128, device=DEV)
+    g_k, _, _, g_b, _ = amd.evaluate_hubbard_adjoint(T, k.detach(), q, 1.0, 0.1, w, 4.0, grad_sum=gs)
+    torch.cuda.synchronize()
+    assert torch.equal(k.grad, g_k)
+    assert beta.grad.device == beta.device and torch.equal(beta.grad, g_b)
 
 
 def test_autograd_energy_function():

@@ -1,14 +1,17 @@
 """Mixed-diagram batch (one HIP graph launch over many diagrams), in both
 modes -- every item on its specialized kernels where AUTO would run them
 (recorded launches in a child graph), or every item on the persistent packed
-kernels: outputs bitwise equal to the per-diagram launches of the same
-kernels, stable across graph replays, row sums consistent, the autotuner,
-and host-side errors."""
+kernels: outputs against the oracle, bitwise equal to the per-diagram
+launches of the same kernels, stable across graph replays, row sums
+consistent, the autotuner, host-side errors, and the 64-diagram workload at
+full size (sampled outputs against the oracle)."""
 import numpy as np
 import pytest
 
 from ami_inputs import (DEFAULT_Q, k_samples, matsubara_freqs, random_self_energy,
                         uniform_energies)
+
+from parity import NEAR, TOL, TOL_NEAR, check, oracle_terms, reference, reference_hubbard
 
 pytestmark = pytest.mark.gpu
 
@@ -41,6 +44,39 @@ def _mixed_items(n_per_order=2, orders=(2, 3, 4, 5, 6), n_f=4, beta=5.0, energie
     return items
 
 
+_ORACLE = {}
+
+
+def _oracle_check(it, idx=None, label=""):
+    """The item's out (all samples, or the columns idx) and out_sum against
+    the oracle: values by the parity bar, the row sum within the bar summed
+    over the samples (only when every sample is compared)."""
+    import hashlib
+    d = it["diagram"]
+    w = it["ext_freqs"].cpu().numpy()
+    hub = it.get("k") is not None
+    x = (it["k"] if hub else it["energies"]).cpu().numpy()
+    x = x if idx is None else x[idx]
+    # the cache key is the whole input: labels, samples, frequencies, scalars
+    h = hashlib.sha256()
+    for a in (d.alpha, d.eps, x, w, np.array([it["beta"], it.get("t", 0.0), it.get("mu", 0.0)])):
+        h.update(np.ascontiguousarray(a).tobytes())
+    key = (hub, h.hexdigest())
+    if key not in _ORACLE:
+        terms = oracle_terms(d)
+        if hub:
+            ref, scale, dist, _ = reference_hubbard(d, x, it["q"], it["t"], it["mu"], w, it["beta"], terms=terms)
+        else:
+            ref, scale, dist = reference(d, x, w, it["beta"], terms=terms)
+        _ORACLE[key] = (ref, scale, dist)
+    ref, scale, dist = _ORACLE[key]
+    out = it["out"] if idx is None else it["out"][:, torch.from_numpy(np.asarray(idx)).to(DEV)]
+    check(out.cpu().numpy(), ref, scale, dist, label=label)
+    if idx is None and it.get("out_sum") is not None:
+        bound = (np.where(dist >= NEAR, TOL, TOL_NEAR) * scale).sum(axis=1)
+        assert np.all(np.abs(it["out_sum"].cpu().numpy() - ref.sum(axis=1)) <= bound), label
+
+
 def _per_diagram(it):
     if it.get("k") is not None:
         return amd.evaluate_hubbard(it["terms"], it["k"], it["q"], it["t"], it["mu"], it["ext_freqs"],
@@ -65,7 +101,8 @@ def test_batch_bitwise_equals_per_diagram(energies, tuning):
     else:
         assert info["specialized_items"] == len(items) and info["lds_classes"] == 0
         assert info["capture_streams"] == 4
-    for it in items:
+    for j, it in enumerate(items):
+        _oracle_check(it, label=f"batch item {j}")
         ref_out, ref_sum = _per_diagram(it)
         torch.cuda.synchronize()
         assert torch.equal(it["out"], ref_out)
@@ -144,3 +181,49 @@ def test_batch_host_errors():
         amd.Batch(items, {"block": 96, "waves_per_cu": 8, "tile_factor": 1})
     with pytest.raises(amd.AmiError):
         amd.Batch(items, {"kernels": 2})
+
+
+@pytest.mark.timeout(900)
+def test_full_size_mixed_batch_against_oracle():
+    """The 64-diagram workload the benchmark times (orders 2-6, 13/13/13/13/12
+    seeded topologies, 16 Matsubara frequencies, 2*10^5 k-samples each), one
+    graph launch with the default tuning: 12 sampled samples of every diagram
+    (the last one included) at all 16 rows against the oracle, and the row
+    sums against sums of the returned rows."""
+    from concurrent.futures import ThreadPoolExecutor
+    orders = [2] * 13 + [3] * 13 + [4] * 13 + [5] * 13 + [6] * 12
+    beta, n_f, n_e = 5.0, 16, 200_000
+    w = torch.from_numpy(matsubara_freqs(n_f, beta)).to(DEV)
+    items, seen = [], {}
+    for order in orders:
+        i = seen.get(order, 0)
+        seen[order] = i + 1
+        d = random_self_energy(order, (5, order, i))
+        T = amd.Terms.from_diagram(d)
+        k = torch.from_numpy(k_samples(n_e, d.n_int, seed=(200, order, i))).to(DEV)
+        items.append({"terms": T, "k": k, "q": list(DEFAULT_Q), "t": 1.0, "mu": 0.0, "ext_freqs": w,
+                      "beta": beta, "diagram": d,
+                      "out": torch.empty((n_f, n_e), dtype=torch.complex128, device=DEV),
+                      "out_sum": torch.empty((n_f,), dtype=torch.complex128, device=DEV)})
+
+    def spec(it):
+        try:
+            it["terms"].specialize(momentum=True)
+        except amd.AmiError:
+            pass
+    with ThreadPoolExecutor(max_workers=8) as pool:
+        list(pool.map(spec, items))
+    b = amd.Batch(items)
+    for it in items:
+        it["out"].fill_(float("nan"))
+    b.run()
+    torch.cuda.synchronize()
+    print(f"batch: {b.info()}", flush=True)
+    rng = np.random.default_rng(7)
+    for j, it in enumerate(items):
+        idx = np.sort(rng.choice(n_e - 1, 11, replace=False)).tolist() + [n_e - 1]
+        _oracle_check(it, idx=idx, label=f"full-size batch item {j} (order {orders[j]})")
+        rows = it["out"].sum(dim=1)
+        torch.cuda.synchronize()
+        np.testing.assert_allclose(it["out_sum"].cpu().numpy(), rows.cpu().numpy(), rtol=1e-9,
+                                   atol=1e-12 * float(torch.abs(it["out"]).sum()))

@@ -44,7 +44,9 @@ def test_full_size_real_frequency_grid():
     idx = _sampled(N_E, 200, 5)
     sub = out[:, torch.from_numpy(idx).to(DEV)].cpu().numpy()
     ref, scale, dist, _ = reference_hubbard(d, k[idx], q, t, mu, w, beta, terms=oracle_terms(d))
-    check(sub, ref, scale, dist, label="full-size real-frequency grid")
+    st = {}
+    check(sub, ref, scale, dist, label="full-size real-frequency grid", stats=st)
+    print(f"real-frequency grid: {st}", flush=True)
     rows = out.sum(dim=1)
     torch.cuda.synchronize()
     np.testing.assert_allclose(s.cpu().numpy(), rows.cpu().numpy(), rtol=1e-9,
@@ -96,7 +98,10 @@ def test_full_size_adjoint_step():
     keep = far_from_poles(terms, d.n_int, E, w)
     idx, E = idx[keep], E[keep]
     ref, scale, dist, _ = reference_hubbard(d, k[idx], q, t, mu, w, beta, terms=terms)
-    check(out[:, torch.from_numpy(idx).to(DEV)].cpu().numpy(), ref, scale, dist, label="full-size adjoint values")
+    st = {}
+    check(out[:, torch.from_numpy(idx).to(DEV)].cpu().numpy(), ref, scale, dist, label="full-size adjoint values",
+          stats=st)
+    print(f"adjoint step values: {st}", flush=True)
     cot = np.full((1, len(idx)), c)
     dE, _, _ = gradients(terms, d.n_int, E, w, beta, cot)
     dk, _, _ = momentum_gradients(d.alpha, k[idx], q, t, mu, dE)

@@ -12,7 +12,8 @@ from ami_inputs import DEFAULT_Q, k_samples, matsubara_freqs, real_freqs, unifor
 from oracle.mc import draw_momenta
 
 from parity import NEAR, TOL, TOL_NEAR, check, reference, reference_hubbard
-from test_multipole_cpu import CASES, _oracle, repeated_line
+from multipole_cases import CASES, repeated_line
+from test_multipole_cpu import _oracle
 
 pytestmark = pytest.mark.gpu
 

@@ -12,30 +12,11 @@ from oracle.construct import canonical, construct, serialize
 from oracle.evaluate import evaluate_terms, term_magnitudes
 
 from parity import check, far_from_poles, pole_distance
+from multipole_cases import CASES, DOUBLE, repeated_line  # noqa: F401
 
 amd = pytest.importorskip("paper_2311_17189_amd")
 
 from test_specialized_cpu import _harness, _run  # noqa: E402
-
-# a double pole present from the start: (1/beta) sum_nu 1/((i nu + E1)^2 (i nu + i Omega + E2))
-DOUBLE = (np.array([[1, 0], [1, 0], [1, 1]]), np.array([[1, 0], [1, 0], [0, 1]]), 1, [1, 0])
-# a double pole that appears only after the first sum
-LATER = (np.array([[1, 0, 0], [0, 1, 1], [-1, 1, 1]]), np.array([[1, 0], [0, 1], [-1, 1]]), 2, [1, 1, 0])
-
-
-def repeated_line(order, i, line=0):
-    """A generated self-energy with one internal line taken twice (same label,
-    same energy): the diagram with a constant self-energy inserted on it,
-    whose propagator squared gives poles of second order."""
-    d = random_self_energy(order, (0, order, i))
-    j = [r for r in range(d.alpha.shape[0]) if np.any(d.alpha[r, :d.n_int])][line]
-    return (np.vstack([d.alpha, d.alpha[j:j + 1]]), np.vstack([d.eps, d.eps[j:j + 1]]), d.n_int,
-            list(d.fermionic))
-
-
-CASES = {"double": DOUBLE, "later": LATER, "o3": repeated_line(3, 0), "o4": repeated_line(4, 1),
-         "o4b": repeated_line(4, 3, 1)}
-
 
 def _oracle(case):
     alpha, eps, n_int, ferm = case

@@ -12,6 +12,8 @@ from oracle.brute import brute_force
 from oracle.construct import MultipoleError, canonical, construct, serialize
 from oracle.evaluate import evaluate_terms, leaf_coefficient
 
+from multipole_cases import CASES, SINGLE_SUM_CASES
+
 
 @pytest.mark.parametrize("sigma", [1, -1])
 @pytest.mark.parametrize("j", [1, 2, 3])
@@ -78,3 +80,112 @@ def test_simple_poles_unchanged_by_the_option(order, i):
     a = canonical(construct(d.alpha, d.eps, d.n_int, d.fermionic))
     b = canonical(construct(d.alpha, d.eps, d.n_int, d.fermionic, multipole=True))
     assert a == b
+
+
+def _residue_sum_mpmath(alpha, eps, E, w, beta):
+    """The residue theorem for one sum written out directly: the poles of
+    prod_j 1/(a_j z + c_j) (z = i nu), each of order M, contribute
+    (1/(M-1)!) d^(M-1)/dz^(M-1) [f(beta z) (z - z0)^M prod_j 1/(a_j z + c_j)]
+    at z0, with f(y) = 1/(exp(y) + 1) taken at the complex pole itself (no
+    periodicity argument) and the derivative by 40-digit numerical
+    differentiation."""
+    mp.mp.dps = 40
+    a = [int(r[0]) for r in alpha]
+    c = [sum(int(eps[j][i]) * mp.mpf(E[i]) for i in range(len(E))) + int(alpha[j][1]) * mp.mpc(w)
+         for j in range(len(a))]
+    poles = {}
+    for j in range(len(a)):
+        z0 = -c[j] / a[j]
+        key = (mp.nstr(mp.re(z0), 25), mp.nstr(mp.im(z0), 25))
+        poles.setdefault(key, (z0, []))[1].append(j)
+    total = mp.mpc(0)
+    for z0, members in poles.values():
+        M = len(members)
+        rest = [j for j in range(len(a)) if j not in members]
+
+        def h(z, members=members, rest=rest):
+            v = 1 / (mp.exp(beta * z) + 1)
+            for j in members:
+                v /= a[j]            # (z - z0) / (a_j z + c_j) = 1 / a_j
+            for j in rest:
+                v /= a[j] * z + c[j]
+            return v
+        total += mp.diff(h, z0, M - 1) / mp.factorial(M - 1)
+    return complex(total)
+
+
+@pytest.mark.parametrize("name", list(SINGLE_SUM_CASES))
+def test_higher_order_single_sums(name):
+    import oracle.construct as oc
+    alpha, eps, n_int, fermionic = SINGLE_SUM_CASES[name]
+    beta = 2.0
+    with pytest.raises(MultipoleError):
+        construct(alpha, eps, 1, fermionic)
+    # record which Leibniz factors (m, k) the construction takes
+    seen = set()
+    binom = oc._binom
+
+    def spy(n, k):
+        seen.add((n - k + 1, k))
+        return binom(n, k)
+    oc._binom = spy
+    try:
+        terms = canonical(construct(alpha, eps, n_int, fermionic, multipole=True))
+    finally:
+        oc._binom = binom
+    want_codes = {"triple": 3, "quadruple": 4, "square_square": 2, "square_negsquare": 2, "triple_square": 3}[name]
+    assert max(abs(code) for _, leaves, _ in terms for code, _ in leaves) == want_codes
+    if name != "triple" and name != "quadruple":
+        assert any(m >= 2 and k >= 1 for m, k in seen), seen
+    for E, Om in (((0.37, -1.21), 2 * np.pi / beta), ((-0.8, 0.45), 4 * np.pi / beta)):
+        w = 1j * Om
+        got = complex(evaluate_terms(terms, n_int, np.array([E]), np.array([[w]]), beta)[0, 0])
+        ref = brute_force(alpha, eps, 1, E, [w], beta)
+        assert abs(got - ref) <= 1e-10 * abs(ref), (got, ref)
+        res = _residue_sum_mpmath(alpha, eps, E, w, beta)
+        assert abs(got - res) <= 1e-13 * abs(res), (got, res)
+
+
+def test_double_poles_at_three_sums_against_brute_force():
+    """The order-3 self-energy with one line taken twice (a constant
+    self-energy inserted on it): double poles over three nested sums, against
+    the truncated triple sum of Eq. (1)."""
+    alpha, eps, n_int, ferm = CASES["o3"]
+    assert n_int == 3
+    beta = 2.0
+    terms = canonical(construct(alpha, eps, n_int, ferm, multipole=True))
+    assert any(abs(code) == 2 for _, leaves, _ in terms for code, _ in leaves)
+    for E in ((0.41, -0.93, 0.77, -0.35, 1.12), (-0.62, 0.31, -1.37, 0.93, 0.19)):
+        w = 1j * np.pi / beta
+        got = complex(evaluate_terms(terms, n_int, np.array([E]), np.array([[w]]), beta)[0, 0])
+        ref = brute_force(alpha, eps, n_int, E, [w], beta)
+        assert abs(got - ref) <= 3e-6 * abs(ref), (got, ref)
+
+
+def test_double_pole_values_invariant_under_relabelling():
+    """Reordering and negating the summed frequencies of the order-4 solution
+    with a repeated line changes its term list, not its value."""
+    from oracle.construct import CoeffError
+    alpha, eps, n_int, ferm = CASES["o4"]
+    beta = 3.0
+    E = np.array([[0.41, -0.93, 0.77, -0.35, 1.12, -0.58, 0.26][:eps.shape[1]],
+                  [-0.3, 0.65, -1.1, 0.2, 0.85, 0.44, -0.71][:eps.shape[1]]])
+    w = np.array([[1j * np.pi / beta], [0.4 + 0.05j]])
+    base = evaluate_terms(canonical(construct(alpha, eps, n_int, ferm, multipole=True)), n_int, E, w, beta)
+    rng = np.random.default_rng(5)
+    checked = 0
+    for _ in range(12):
+        perm = list(rng.permutation(n_int))
+        signs = list(rng.choice([-1, 1], size=n_int))
+        cols = perm + list(range(n_int, alpha.shape[1]))
+        a2 = alpha[:, cols].astype(np.int64)
+        a2[:, :n_int] *= np.asarray(signs)[None, :]
+        rows = list(reversed(range(alpha.shape[0])))
+        try:
+            t2 = canonical(construct(a2[rows], eps[rows], n_int, [ferm[c] for c in cols], multipole=True))
+        except CoeffError:
+            continue
+        other = evaluate_terms(t2, n_int, E, w, beta)
+        np.testing.assert_allclose(other.astype(np.complex128), base.astype(np.complex128), rtol=1e-11, atol=1e-14)
+        checked += 1
+    assert checked >= 3
