@@ -88,7 +88,7 @@ def check(got, ref, scale, dist, tol=TOL, tol_near=TOL_NEAR, near=NEAR, label=""
         assert worst_near <= tol_near, f"{label}: max error {worst_near:.3e} near poles"
     absref = np.abs(ref)
     ratio = scale / np.maximum(absref, 1e-300)
-    plain = far & (ratio <= cond_max) & (absref > 0)
+    plain = far & (ratio <= cond_max) & (absref > 0)   # cond_max = 0 turns the plain bar off
     worst_plain = float((diff[plain] / absref[plain]).max()) if plain.any() else 0.0
     assert worst_plain <= tol, (f"{label}: max plain relative error {worst_plain:.3e} > {tol:.1e} "
                                 f"(away from poles, cancellation ratio <= {cond_max:.0e})")

@@ -36,11 +36,20 @@ def test_graph_file_energy_path_matches_generator_labels(order, i, tmp_path):
     w = np.concatenate([matsubara_freqs(2, beta), real_freqs(2, -2.0, 2.0, 0.05)])
     out, s = amd.evaluate(T, torch.from_numpy(E).to(DEV), torch.from_numpy(w).to(DEV), beta, want_sum=True)
     torch.cuda.synchronize()
-    # the oracle's own construction from the generator's labels of the same graph
-    ref, scale, dist = reference(d, E, w, beta)
-    check(out.cpu().numpy(), ref, scale, dist, label=f"graph file, order {order}")
-    np.testing.assert_allclose(s.cpu().numpy(), out.cpu().numpy().sum(axis=1), rtol=1e-11,
-                               atol=1e-12 * scale.sum())
+    got = out.cpu().numpy()
+    # the oracle's construction of the library's labels: the same term list,
+    # so the full parity bar (plain relative error included) applies
+    alpha, eps, ferm = T.labels()
+    lab = type(d)(alpha=alpha, eps=eps, n_int=T.info()["n_int"], fermionic=ferm)
+    ref, scale, dist = reference(lab, E, w, beta)
+    check(got, ref, scale, dist, label=f"graph file, order {order}")
+    # the oracle's construction from the generator's own labels of the same
+    # graph: another term list of the same integrand, whose rounding differs,
+    # so the bar is relative to the larger of the two term-magnitude sums
+    ref2, scale2, dist2 = reference(d, E, w, beta)
+    check(got, ref2, np.maximum(scale, scale2), np.minimum(dist, dist2), cond_max=0.0,
+          label=f"graph file vs generator labels, order {order}")
+    np.testing.assert_allclose(s.cpu().numpy(), got.sum(axis=1), rtol=1e-11, atol=1e-12 * scale.sum())
 
 
 @pytest.mark.parametrize("order,i", [(3, 1), (4, 5)])
