@@ -286,6 +286,40 @@ AmiStatus amiEvaluateHubbardAdjoint(AmiTerms *terms,
                                     double *out, double *out_sum, void *hip_stream);
 
 /*
+ * amiEvaluateHubbardAdjointNoAlloc -- amiEvaluateHubbardAdjoint for callers
+ * that cannot allocate device memory (code under HIP graph capture, tight
+ * serving loops, harnesses that forbid hipMalloc).  Same arguments, layouts,
+ * kernels and results (bit for bit) as amiEvaluateHubbardAdjoint; it calls no
+ * hipMalloc, hipFree or other allocating routine:
+ *   - the partial sums over samples go to a scratch array of
+ *     AMI_NOALLOC_SCRATCH_BYTES inside the library (one per device, held until
+ *     the process ends; its address is looked up on the first call on a
+ *     device).  Calls that need more -- about (4 + 2 n_f n_ext + 2 n_f) * 8 / 64
+ *     bytes per sample, i.e. n_e up to about 16.7 million at n_f = 1 -- fail
+ *     with AMI_E_ARG: split the samples;
+ *   - the handle's tables must already be on the current device
+ *     (amiTermsUpload, or an earlier evaluate call), else AMI_E_ARG;
+ *   - when the call is served by a specialized kernel, that kernel must
+ *     already be loaded on the current device (amiTermsSpecialize(terms, 1) with
+ *     the device current, or an earlier amiEvaluateHubbardAdjoint call), else
+ *     AMI_E_ARG; nothing is compiled or loaded.
+ * Every call on one device shares that device's scratch: calls that overlap
+ * on one device (two streams, two threads) race and give wrong sums; the
+ * scratch keeps the last call's partial sums, every one of which a call
+ * writes before reading it.
+ */
+#define AMI_NOALLOC_SCRATCH_BYTES (16u << 20)
+AmiStatus amiEvaluateHubbardAdjointNoAlloc(AmiTerms *terms,
+                                           const double *k, int64_t n_e, int64_t stride_k,
+                                           const double *q, double t, double mu,
+                                           const double *ext_freqs, int64_t n_f,
+                                           double beta, double e_reg,
+                                           const double *grad_out, const double *grad_sum,
+                                           double *grad_k, double *grad_mu, double *grad_t,
+                                           double *grad_beta, double *grad_freqs,
+                                           double *out, double *out_sum, void *hip_stream);
+
+/*
  * amiIntegrateHubbard -- Monte-Carlo integration of the integrand over the
  * internal momenta (Sec. 5.2; the row average of Sec. 2.3), sampling in the
  * kernel: sample s (0 <= s < n_samples) draws its 2*n_int momentum

@@ -97,6 +97,8 @@ def load_library():
     lib.amiEvaluateHubbardAdjoint.argtypes = [vp, vp, c_i64, c_i64, vp, c_dbl, c_dbl, vp, c_i64, c_dbl,
                                               c_dbl, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp]
     lib.amiEvaluateHubbardAdjoint.restype = c_i32
+    lib.amiEvaluateHubbardAdjointNoAlloc.argtypes = lib.amiEvaluateHubbardAdjoint.argtypes
+    lib.amiEvaluateHubbardAdjointNoAlloc.restype = c_i32
     lib.amiSetVariant.argtypes = [vp, c_i32]
     lib.amiSetVariant.restype = c_i32
     lib.amiReadGraph.argtypes = [ctypes.c_char_p, vp, c_i32, ctypes.POINTER(c_i32), ctypes.POINTER(c_i32)]
@@ -495,6 +497,25 @@ def evaluate_hubbard_adjoint(terms: Terms, k, q, t: float, mu: float, ext_freqs,
     grad_t [], grad_beta [], grad_freqs [N_F, n_ext])``; ``out`` / ``out_sum``
     tensors, if given, receive the forward values.  ``grads``, if given, is a
     previous call's result whose tensors are written again instead of new ones."""
+    return _hubbard_adjoint("amiEvaluateHubbardAdjoint", terms, k, q, t, mu, ext_freqs, beta, e_reg,
+                            grad_out, grad_sum, out, out_sum, stream, grads)
+
+
+def evaluate_hubbard_adjoint_no_alloc(terms: Terms, k, q, t: float, mu: float, ext_freqs, beta: float,
+                                      e_reg: float = 0.0, grad_out=None, grad_sum=None, out=None,
+                                      out_sum=None, stream=None, grads=None):
+    """``amiEvaluateHubbardAdjointNoAlloc``: ``evaluate_hubbard_adjoint`` with the
+    library allocating nothing (its partial sums in the library's fixed scratch).
+    The handle must have been uploaded (``Terms.upload``) and, when the call runs
+    specialized kernels, specialized (``Terms.specialize``) on this device.  The
+    library allocates nothing; this wrapper allocates the gradient tensors unless
+    ``grads`` passes a previous call's."""
+    return _hubbard_adjoint("amiEvaluateHubbardAdjointNoAlloc", terms, k, q, t, mu, ext_freqs, beta, e_reg,
+                            grad_out, grad_sum, out, out_sum, stream, grads)
+
+
+def _hubbard_adjoint(entry: str, terms: Terms, k, q, t, mu, ext_freqs, beta, e_reg, grad_out, grad_sum,
+                     out, out_sum, stream, grads):
     import torch
     if k.dtype != torch.float64 or not k.is_cuda or k.dim() != 2:
         raise AmiError(-1, "k must be a 2-D float64 CUDA tensor")
@@ -518,7 +539,7 @@ def evaluate_hubbard_adjoint(terms: Terms, k, q, t: float, mu: float, ext_freqs,
     qa = np.ascontiguousarray(np.asarray(q, dtype=np.float64).reshape(-1))
     k, st_k = _momentum_rows(k, terms.n_int)
     base = scal.data_ptr()
-    _check(load_library().amiEvaluateHubbardAdjoint(
+    _check(getattr(load_library(), entry)(
         terms._h, k.data_ptr() if n_e else None, n_e, st_k,
         qa.ctypes.data, float(t), float(mu), w.data_ptr(), n_f, float(beta), float(e_reg),
         _ptr(go), _ptr(gs), g_k.data_ptr() if n_e else None, base, base + 8, base + 16,

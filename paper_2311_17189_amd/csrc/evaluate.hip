@@ -375,10 +375,16 @@ constexpr int kTwoPassMaxFreqs = 65535;
 
 // Which kernels serve a call (AMI_VARIANT_* of the handle); for the
 // specialized path also loads them.  AUTO falls back and records why.
+// With no_load the specialized kernels must already be loaded on the device
+// (jit_loaded): nothing is compiled, loaded or allocated, and a kernel that
+// the call would use but that is not loaded yet is an error, not a fallback.
 AmiStatus choose_path(AmiTerms *t, bool hub, bool adjoint, Path &p, void **jit_fn, std::string &note,
-                      void **jit_fn2 = nullptr, int n_f = 1, int variant = -1) {
+                      void **jit_fn2 = nullptr, int n_f = 1, int variant = -1, bool no_load = false) {
     const int v = variant >= 0 ? variant : t->variant;
     note.clear();
+    auto get = [&](int kind, void **fn) {
+        return no_load ? jit_loaded(t, hub, kind, fn) : jit_get(t, hub, kind, fn);
+    };
     // the forward of a large solution: two passes (AUTO and SPECIALIZED when the
     // one-pass kernel would not fit its registers; TWO_PASS always)
     const bool two = !adjoint && jit_fn2 && n_f <= kTwoPassMaxFreqs &&
@@ -388,25 +394,25 @@ AmiStatus choose_path(AmiTerms *t, bool hub, bool adjoint, Path &p, void **jit_f
         return fail(AMI_E_UNSUPPORTED, adjoint ? "the two-pass variant has no adjoint"
                                                : "the two-pass variant takes at most 65535 frequency rows");
     if (two) {
-        AmiStatus st = jit_get(t, hub, kJitSumsPass, jit_fn);
-        if (st == AMI_OK) st = jit_get(t, hub, kJitFreqPass, jit_fn2);
+        AmiStatus st = get(kJitSumsPass, jit_fn);
+        if (st == AMI_OK) st = get(kJitFreqPass, jit_fn2);
         if (st == AMI_OK) {
             p = Path::TWO_PASS;
             return AMI_OK;
         }
-        if (v != AMI_VARIANT_AUTO) return st;
+        if (v != AMI_VARIANT_AUTO || (no_load && st != AMI_E_UNSUPPORTED)) return st;
         note = std::string(" (not two-pass: ") + amiLastError() + ")";
         clear_error();
     }
     const bool auto_skip = v == AMI_VARIANT_AUTO && adjoint && t->tab.T > kJitAutoAdjointTerms;
     if (auto_skip) note = " (adjoint specialized up to " + std::to_string(kJitAutoAdjointTerms) + " terms)";
     if (v == AMI_VARIANT_SPECIALIZED || (v == AMI_VARIANT_AUTO && !auto_skip && !two)) {
-        const AmiStatus st = jit_get(t, hub, adjoint ? kJitAdjoint : kJitForward, jit_fn);
+        const AmiStatus st = get(adjoint ? kJitAdjoint : kJitForward, jit_fn);
         if (st == AMI_OK) {
             p = Path::SPECIALIZED;
             return AMI_OK;
         }
-        if (v == AMI_VARIANT_SPECIALIZED) return st;
+        if (v == AMI_VARIANT_SPECIALIZED || (no_load && st != AMI_E_UNSUPPORTED)) return st;
         note = std::string(" (not specialized: ") + amiLastError() + ")";
         clear_error();
     }
@@ -579,14 +585,64 @@ AmiStatus launch_forward(AmiTerms *t, bool hub, KArgs &a, double *out_sum, hipSt
     return AMI_OK;
 }
 
+// Scratch of the allocation-free entry point (amiEvaluateHubbardAdjointNoAlloc):
+// the partial sums of one call.  Every device the library runs on holds its
+// own copy until the process ends.  In host code `scratch` names a host-side
+// stand-in, not device memory: kernels get the address hipGetSymbolAddress
+// returns for the current device (scratch_address).
+constexpr size_t kScratchBytes = AMI_NOALLOC_SCRATCH_BYTES;
+static __device__ __align__(256) double scratch[kScratchBytes / sizeof(double)];
+
+constexpr int kScratchMaxDevices = 64;
+std::mutex g_scratch_mu;
+double *g_scratch_ptr[kScratchMaxDevices] = {};
+
+// The device address of `scratch` on the current device, looked up on the
+// first call there.
+AmiStatus scratch_address(double **out) {
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return hip_fail(e, "hipGetDevice");
+    if (dev < 0 || dev >= kScratchMaxDevices) return fail(AMI_E_UNSUPPORTED, "device index beyond 63");
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void *p = nullptr;
+        e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess) return hip_fail(e, "hipGetSymbolAddress (scratch)");
+        if (!p) return fail(AMI_E_HIP, "hipGetSymbolAddress (scratch) returned NULL");
+        g_scratch_ptr[dev] = static_cast<double *>(p);
+    }
+    *out = g_scratch_ptr[dev];
+    return AMI_OK;
+}
+
+// The handle's tables on the current device when amiTermsUpload (or an
+// earlier evaluate call) has put them there; uploads nothing.
+AmiStatus find_uploaded(AmiTerms *t, DeviceTables **out) {
+    int dev = 0;
+    const hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return hip_fail(e, "hipGetDevice");
+    std::lock_guard<std::mutex> lk(t->dev_mu);
+    for (auto &d : t->dev)
+        if (d.device == dev) {
+            *out = &d;
+            return AMI_OK;
+        }
+    return fail(AMI_E_ARG, "the tables are not on this device: call amiTermsUpload first");
+}
+
 struct AdjOut {
     double *grad_beta = nullptr, *grad_mu = nullptr, *grad_t = nullptr, *grad_freqs = nullptr;
     double *out_sum = nullptr;   // forward row sums computed on the way (optional)
 };
 
-AmiStatus launch_adjoint(AmiTerms *t, bool hub, KArgs &a, const AdjOut &o, hipStream_t stream) {
+// fixed_ws: the partial sums go there (at most kScratchBytes), and nothing is
+// uploaded, compiled, loaded or allocated (the allocation-free entry point);
+// NULL: the handle's per-stream workspace.
+AmiStatus launch_adjoint(AmiTerms *t, bool hub, KArgs &a, const AdjOut &o, hipStream_t stream,
+                         double *fixed_ws = nullptr) {
     DeviceTables *dt = nullptr;
-    AmiStatus st = upload(t, &dt);
+    AmiStatus st = fixed_ws ? find_uploaded(t, &dt) : upload(t, &dt);
     if (st != AMI_OK) return st;
     const Tables &tb = t->tab;
     const int nx = t->n_ext;
@@ -603,7 +659,7 @@ AmiStatus launch_adjoint(AmiTerms *t, bool hub, KArgs &a, const AdjOut &o, hipSt
     Path path;
     void *jit_fn = nullptr;
     std::string note;
-    st = choose_path(t, hub, true, path, &jit_fn, note);
+    st = choose_path(t, hub, true, path, &jit_fn, note, nullptr, 1, -1, fixed_ws != nullptr);
     if (st != AMI_OK) return st;
     LaunchShape ls;
     if (path == Path::SPECIALIZED) {
@@ -619,8 +675,17 @@ AmiStatus launch_adjoint(AmiTerms *t, bool hub, KArgs &a, const AdjOut &o, hipSt
     double *partial = nullptr;
     const size_t n_grad = static_cast<size_t>(rows) * ncols;
     const size_t n_val = o.out_sum ? static_cast<size_t>(rows) * a.n_f * 2 : 0;
-    st = workspace(t, dt, stream, (n_grad + n_val) * sizeof(double), &partial);
-    if (st != AMI_OK) return st;
+    const size_t ws_bytes = (n_grad + n_val) * sizeof(double);
+    if (fixed_ws) {
+        if (ws_bytes > kScratchBytes)
+            return fail(AMI_E_ARG, "the partial sums need " + std::to_string(ws_bytes) +
+                                       " bytes, more than the " + std::to_string(kScratchBytes) +
+                                       "-byte scratch of the allocation-free entry point: split the samples");
+        partial = fixed_ws;
+    } else {
+        st = workspace(t, dt, stream, ws_bytes, &partial);
+        if (st != AMI_OK) return st;
+    }
     hipError_t e;
     a.gpartial = partial;
     a.partial = o.out_sum ? partial + n_grad : nullptr;
@@ -864,12 +929,16 @@ AmiStatus amiEvaluateAdjoint(AmiTerms *t, const double *energies, int64_t n_e, i
     return launch_adjoint(t, false, a, o, static_cast<hipStream_t>(hip_stream));
 }
 
-AmiStatus amiEvaluateHubbardAdjoint(AmiTerms *t, const double *k, int64_t n_e, int64_t stride_k, const double *q,
-                                    double hop_t, double mu, const double *ext_freqs, int64_t n_f, double beta,
-                                    double e_reg, const double *grad_out, const double *grad_sum, double *grad_k,
-                                    double *grad_mu, double *grad_t, double *grad_beta, double *grad_freqs,
-                                    double *out, double *out_sum, void *hip_stream) {
-    using namespace ami;
+}  // extern "C"
+
+namespace ami {
+namespace {
+
+AmiStatus hubbard_adjoint(AmiTerms *t, const double *k, int64_t n_e, int64_t stride_k, const double *q,
+                          double hop_t, double mu, const double *ext_freqs, int64_t n_f, double beta, double e_reg,
+                          const double *grad_out, const double *grad_sum, double *grad_k, double *grad_mu,
+                          double *grad_t, double *grad_beta, double *grad_freqs, double *out, double *out_sum,
+                          void *hip_stream, bool no_alloc) {
     clear_error();
     AmiStatus st = check_common(t, n_e, ext_freqs, n_f, beta);
     if (st == AMI_OK) st = check_momenta(t, n_e, k, stride_k, q);
@@ -890,7 +959,36 @@ AmiStatus amiEvaluateHubbardAdjoint(AmiTerms *t, const double *k, int64_t n_e, i
     o.grad_t = grad_t;
     o.grad_freqs = grad_freqs;
     o.out_sum = out_sum;
-    return launch_adjoint(t, true, a, o, static_cast<hipStream_t>(hip_stream));
+    double *ws = nullptr;
+    if (no_alloc) {
+        st = scratch_address(&ws);
+        if (st != AMI_OK) return st;
+    }
+    return launch_adjoint(t, true, a, o, static_cast<hipStream_t>(hip_stream), ws);
+}
+
+}  // namespace
+}  // namespace ami
+
+extern "C" {
+
+AmiStatus amiEvaluateHubbardAdjoint(AmiTerms *t, const double *k, int64_t n_e, int64_t stride_k, const double *q,
+                                    double hop_t, double mu, const double *ext_freqs, int64_t n_f, double beta,
+                                    double e_reg, const double *grad_out, const double *grad_sum, double *grad_k,
+                                    double *grad_mu, double *grad_t, double *grad_beta, double *grad_freqs,
+                                    double *out, double *out_sum, void *hip_stream) {
+    return ami::hubbard_adjoint(t, k, n_e, stride_k, q, hop_t, mu, ext_freqs, n_f, beta, e_reg, grad_out, grad_sum,
+                                grad_k, grad_mu, grad_t, grad_beta, grad_freqs, out, out_sum, hip_stream, false);
+}
+
+AmiStatus amiEvaluateHubbardAdjointNoAlloc(AmiTerms *t, const double *k, int64_t n_e, int64_t stride_k,
+                                           const double *q, double hop_t, double mu, const double *ext_freqs,
+                                           int64_t n_f, double beta, double e_reg, const double *grad_out,
+                                           const double *grad_sum, double *grad_k, double *grad_mu, double *grad_t,
+                                           double *grad_beta, double *grad_freqs, double *out, double *out_sum,
+                                           void *hip_stream) {
+    return ami::hubbard_adjoint(t, k, n_e, stride_k, q, hop_t, mu, ext_freqs, n_f, beta, e_reg, grad_out, grad_sum,
+                                grad_k, grad_mu, grad_t, grad_beta, grad_freqs, out, out_sum, hip_stream, true);
 }
 
 AmiStatus amiIntegrateHubbard(AmiTerms *t, int64_t n_samples, uint64_t seed, const double *q, double hop_t,

@@ -223,6 +223,23 @@ AmiStatus jit_get(AmiTerms *t, bool hub, int kind, void **fn) {
     return AMI_OK;
 }
 
+AmiStatus jit_loaded(AmiTerms *t, bool hub, int kind, void **fn) {
+    if (kind < kJitForward || kind >= kJitKinds || (kind == kJitMonteCarlo && !hub) || (kind == kJitComplex && hub))
+        return fail(AMI_E_ARG, "no such specialized kernel");
+    std::lock_guard<std::mutex> lock(t->jit_mu);
+    const int slot = kJitKinds * (hub ? 1 : 0) + kind;
+    if (!t->jit_error[slot].empty()) return fail(AMI_E_UNSUPPORTED, t->jit_error[slot]);
+    int dev = 0;
+    const hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return hip_fail(e, "hipGetDevice");
+    for (const auto &m : t->jit_mods)
+        if (m.device == dev && m.kind == slot) {
+            *fn = m.fn;
+            return AMI_OK;
+        }
+    return fail(AMI_E_ARG, "the specialized kernel is not loaded on this device: call amiTermsSpecialize first");
+}
+
 void jit_release(AmiTerms *t) {
     int cur = 0;
     const bool have_cur = hipGetDevice(&cur) == hipSuccess;

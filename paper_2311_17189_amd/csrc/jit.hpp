@@ -49,6 +49,11 @@ constexpr int kJitKinds = 6;
 // for the energy input only.
 AmiStatus jit_get(AmiTerms *t, bool hub, int kind, void **fn);
 
+// The kernel of `kind` only if jit_get has already loaded it on the current
+// device (loads nothing, allocates nothing): AMI_E_UNSUPPORTED when its
+// compilation failed, AMI_E_ARG when it has not been loaded yet.
+AmiStatus jit_loaded(AmiTerms *t, bool hub, int kind, void **fn);
+
 // Only the code object of `kind` (compiled or fetched from the cache): needs
 // no device.
 AmiStatus jit_compile(AmiTerms *t, bool hub, int kind);
