@@ -253,13 +253,15 @@ AmiStatus amiEvaluateComplex(AmiTerms *terms,
  * using d f_sigma/dy = -f_sigma (1 - f_sigma) for every leaf and
  * d(1/D)/dD = -1/D^2 for every denominator (the terms of Eq. (6) are products
  * of these).  Other arguments as amiEvaluate.  The sums over samples are
- * reduced in a fixed order.  Needs the packed form of the solution (every
- * energy coefficient +-1, at most 255 distinct leaves and denominators, at most
- * 8 of each per term, no leaf twice in one term): AMI_E_UNSUPPORTED otherwise.
+ * reduced in a fixed order.  Served by the specialized kernels (in one pass
+ * up to 128 terms, in passes up to 4096; see the variants below) or by the
+ * packed ones (every energy coefficient +-1, at most 255 distinct leaves and
+ * denominators, at most 8 of each per term, no leaf twice in one term):
+ * AMI_E_UNSUPPORTED when none applies (e.g. poles of higher order).
  * out / out_sum (device, or NULL): the forward values, as amiEvaluate would
- * return them, computed on the way -- a value-and-gradient pass when the
- * cotangents do not depend on the values (e.g. grad_sum for a Monte-Carlo
- * estimate).
+ * return them (up to rounding when the adjoint runs in passes), computed on
+ * the way -- a value-and-gradient pass when the cotangents do not depend on
+ * the values (e.g. grad_sum for a Monte-Carlo estimate).
  */
 AmiStatus amiEvaluateAdjoint(AmiTerms *terms,
                              const double *energies, int64_t n_e, int64_t stride_s, int64_t stride_i,
@@ -352,12 +354,13 @@ AmiStatus amiIntegrateHubbard(AmiTerms *terms, int64_t n_samples, uint64_t seed,
  * Kernel variants of a handle (amiSetVariant).  All evaluate the same
  * solution (Sec. 2.3); they differ in how the term tables reach the kernel:
  *   AMI_VARIANT_AUTO         (default) specialized when the solution has at
- *                            most 1024 flat terms (128 for the adjoint) and at
+ *                            most 1024 flat terms (4096 in passes) and at
  *                            most 16 energies and its kernels compile -- the
  *                            forward in two passes (below) when the solution
  *                            has more than 1024 terms (up to 4096) or when its
  *                            groups and denominators would not fit the one-pass
- *                            kernel's registers (2 G + 4 D > 128) -- else
+ *                            kernel's registers (2 G + 4 D > 128), the adjoint
+ *                            in passes (below) above 128 terms -- else
  *                            packed when the solution
  *                            has the packed form (+-1 coefficients, at most 255
  *                            leaves/denominators, 8 per term), else tables
@@ -378,8 +381,16 @@ AmiStatus amiIntegrateHubbard(AmiTerms *terms, int64_t n_samples, uint64_t seed,
  *                            256 MB), a second evaluates, per frequency row,
  *                            the denominators and the group products against
  *                            them; register use independent of the number of
- *                            groups.  Forward only, at most 65535 frequency
- *                            rows per call
+ *                            groups; at most 65535 frequency rows per call.
+ *                            The adjoint in passes over the same workspace
+ *                            (per chunk of samples): that first kernel, then
+ *                            one that per frequency row forms the values, the
+ *                            group sums' cotangents and the denominators'
+ *                            (stored), then one that forms the leaves'
+ *                            cotangents by a reverse sweep of each group's
+ *                            nested sum and finishes the gradients; its values
+ *                            equal the forward's up to rounding.  No poles of
+ *                            higher order
  * A forced variant that cannot serve a call fails it (AMI_E_UNSUPPORTED, or
  * AMI_E_HIP when the run-time compilation fails); AUTO falls back in the order
  * above and amiLastVariant names what ran and why.

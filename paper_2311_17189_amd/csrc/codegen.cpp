@@ -338,6 +338,12 @@ struct Lin {
 
 std::string idx(const char *a, int i) { return std::string(a) + "[" + std::to_string(i) + "]"; }
 
+// Groups per chunk of the adjoint's frequency pass for large solutions (the
+// cotangents of a chunk's denominators are gathered in registers).
+constexpr int kAdjChunkGroups = 4;
+// Groups of the leaf pass's reverse sweep between scheduling fences.
+constexpr int kAdjLeafFenceGroups = 4;
+
 }  // namespace
 
 bool jit_prefers_two_pass(const AmiTerms *t) {
@@ -357,6 +363,16 @@ bool jit_supported(const AmiTerms *t, bool hub, std::string *why, bool two_pass)
     if (hub && t->n_g != t->n_eps) return no("momentum input needs one energy per line");
     const int max_terms = two_pass ? kJitTwoPassMaxTerms : kJitMaxTerms;
     if (tb.T > max_terms) return no("more than " + std::to_string(max_terms) + " terms");
+    return true;
+}
+
+bool jit_adjoint_passes_supported(const AmiTerms *t, bool hub, std::string *why) {
+    if (!jit_supported(t, hub, why, true)) return false;
+    for (int o : t->tab.leaf_order)
+        if (o > 0) {
+            if (why) *why = "Taylor-coefficient leaves (poles of higher order)";
+            return false;
+        }
     return true;
 }
 
@@ -735,6 +751,135 @@ std::string jit_source(const AmiTerms *t, bool hub, int kernels) {
         o << "}\n";
     }
 
+    // The adjoint of large solutions in passes (after the two-pass forward's
+    // first pass has stored every FT_g and E_j in the workspace [column][sample]:
+    // columns 0..G-1 FT_g, G..G+NE-1 E_j, then NE columns of the energy
+    // cotangents gathered from the denominators, then G columns of the group-sum
+    // cotangents FTB_g).
+    const std::string ftb0 = "(G + 2 * NE)";
+    if (kernels & 64) {
+        // frequency pass, one frequency row: every reciprocal, then per chunk
+        // of groups (scheduled apart, so that only one chunk's values are live
+        // at a time) each group's R_g, the value FT_g R_g, FTB_g +=
+        // Re(conj(c) R_g) (stored; added to the stored value after the first
+        // row) and u_g = -FT_g conj(c) R_g summed per denominator of the
+        // chunk, then per such denominator the scatter of U_k rho_k
+        o << "__device__ __forceinline__ void adj_freq_row(const double (&E)[NE], const double (&wr)[" << NXA
+          << "], const double (&wi)[" << NXA << "], double cr, double ci, double *ws, int64_t ld, uint32_t off, "
+             "bool first, double &acc_re, double &acc_im, double (&gE)[NE], double (&gwr)["
+          << NXA << "], double (&gwi)[" << NXA << "]) {\n";
+        o << "  double xr[D], xi[D];\n  { double dr[D], di[D];\n    den_args(E, wr, wi, dr, di);\n"
+             "#pragma unroll\n    for (int k = 0; k < D; ++k) {\n"
+             "      const double inv = ami::rcp_nr(fma(dr[k], dr[k], di[k] * di[k]));\n"
+             "      xr[k] = dr[k] * inv;\n      xi[k] = -di[k] * inv;\n    } }\n";
+        for (int g0 = 0; g0 < G; g0 += kAdjChunkGroups) {
+            const int g1 = std::min(G, g0 + kAdjChunkGroups);
+            std::vector<int> ks;
+            for (int g = g0; g < g1; ++g)
+                for (int j = gbegin(g); j < gend(g); ++j) ks.push_back(tb.group_den_list[j]);
+            std::sort(ks.begin(), ks.end());
+            ks.erase(std::unique(ks.begin(), ks.end()), ks.end());
+            o << "  {\n";
+            for (int k : ks) o << "    double Ur" << k << " = 0.0, Ui" << k << " = 0.0;\n";
+            for (int g = g0; g < g1; ++g) {
+                o << "    { const double ft = ami::ws_load(ws, ld, " << g << ", off);\n";
+                o << "      double rr = 1.0, ri = 0.0, nr = 0.0;\n";
+                for (int j = gbegin(g); j < gend(g); ++j) {
+                    const std::string k = std::to_string(tb.group_den_list[j]);
+                    if (j == gbegin(g)) o << "      rr = xr[" << k << "]; ri = xi[" << k << "];\n";
+                    else
+                        o << "      nr = fma(rr, xr[" << k << "], -ri * xi[" << k << "]); ri = fma(rr, xi[" << k
+                          << "], ri * xr[" << k << "]); rr = nr;\n";
+                }
+                o << "      (void)nr;\n";
+                o << "      acc_re = fma(ft, rr, acc_re);\n      acc_im = fma(ft, ri, acc_im);\n";
+                o << "      const double tb = fma(cr, rr, ci * ri);\n";
+                o << "      ami::ws_store(ws, ld, " << ftb0 << " + " << g << ", off, first ? tb : ami::ws_load(ws, ld, "
+                  << ftb0 << " + " << g << ", off) + tb);\n";
+                o << "      const double qr = ft * cr, qi = -ft * ci;\n";
+                o << "      const double ur = -fma(qr, rr, -qi * ri), ui = -fma(qr, ri, qi * rr);\n";
+                for (int j = gbegin(g); j < gend(g); ++j) {
+                    const std::string k = std::to_string(tb.group_den_list[j]);
+                    o << "      Ur" << k << " += ur; Ui" << k << " += ui;\n";
+                }
+                o << "    }\n";
+            }
+            for (int k : ks) {
+                o << "    { const double dR = fma(Ur" << k << ", xr[" << k << "], -Ui" << k << " * xi[" << k
+                  << "]), dI = fma(Ur" << k << ", xi[" << k << "], Ui" << k << " * xr[" << k << "]);\n";
+                for (int i = 0; i < ne; ++i) {
+                    const double c = tb.den_coef[static_cast<size_t>(k) * nc + i];
+                    if (c == 1.0) o << "      gE[" << i << "] += dR;\n";
+                    else if (c == -1.0) o << "      gE[" << i << "] -= dR;\n";
+                    else if (c != 0.0) o << "      gE[" << i << "] = fma(" << num(c) << ", dR, gE[" << i << "]);\n";
+                }
+                for (int x = 0; x < nx; ++x) {
+                    const double a = tb.den_coef[static_cast<size_t>(k) * nc + ne + x];
+                    if (a == 0.0) continue;
+                    o << "      gwr[" << x << "] = fma(" << num(a) << ", dR, gwr[" << x << "]);\n";
+                    o << "      gwi[" << x << "] = fma(" << num(a) << ", dI, gwi[" << x << "]);\n";
+                }
+                o << "    }\n";
+            }
+            o << "  }\n";
+            if (g1 < G) o << "  AMI_SCHED_FENCE();\n";
+        }
+        o << "}\n";
+    }
+    if (kernels & 128) {
+        // leaf pass: FB_l = sum_g FTB_g dFT_g/dF_l by a reverse sweep of each
+        // group's nested sum (the nodes recomputed, then their cotangents in
+        // reverse order: node h = F_a w + u passes h' w to F_a, h' F_a to w and
+        // h' to u)
+        o << "__device__ __forceinline__ void leaf_cotangents_ws(const double (&F)[L], const double *ws, int64_t ld, "
+             "uint32_t off, double (&FB)[L]) {\n";
+        o << kReverseContract;
+        leaf_prefix = "F[";
+        leaf_suffix = "]";
+        for (int g = 0; g < G; ++g) {
+            std::vector<HornerTerm> ts;
+            for (int ti = tb.group_start[g]; ti < tb.group_start[g + 1]; ++ti) {
+                HornerTerm h{tb.term_sign[ti], {}};
+                for (int j = 0; j < ni; ++j) h.leaves.push_back(tb.term_leaf[static_cast<size_t>(ti) * ni + j]);
+                ts.push_back(std::move(h));
+            }
+            std::vector<HNode> nodes;
+            const HRef v = horner_build(std::move(ts), nodes);
+            o << "  { const double tb = ami::ws_load(ws, ld, " << ftb0 << " + " << g << ", off);\n";
+            horner_emit(nodes, leaf_name, o);
+            const size_t nn = nodes.size();
+            for (size_t k = 0; k < nn; ++k) o << "    double hb" << k << " = 0.0;\n";
+            // a cotangent c passed to reference r: hb += c (node) or FB += c (leaf)
+            auto pass = [&](const HRef &r, const std::string &c) {
+                if (r.kind == HRef::NODE) {
+                    o << "    hb" << r.idx << (r.neg ? " -= " : " += ") << c << ";\n";
+                } else if (r.kind == HRef::LEAF) {
+                    o << "    FB[" << r.idx << "]" << (r.neg ? " -= " : " += ") << c << ";\n";
+                }
+            };
+            pass(v, "tb");
+            for (size_t kk = nn; kk-- > 0;) {
+                const HNode &n = nodes[kk];
+                const std::string hb = "hb" + std::to_string(kk), fa = "F[" + std::to_string(n.a) + "]";
+                // to F_a: hb * w
+                if (n.w.kind == HRef::CONST) {
+                    if (n.w.c == 1.0) o << "    FB[" << n.a << "] += " << hb << ";\n";
+                    else if (n.w.c == -1.0) o << "    FB[" << n.a << "] -= " << hb << ";\n";
+                    else o << "    FB[" << n.a << "] = fma(" << num(n.w.c) << ", " << hb << ", FB[" << n.a << "]);\n";
+                } else {
+                    const std::string wn = href_name(n.w, leaf_name);
+                    o << "    FB[" << n.a << "] = fma(" << (n.w.neg ? "-" : "") << wn << ", " << hb << ", FB[" << n.a
+                      << "]);\n";
+                    pass(n.w, fa + " * " + hb);
+                }
+                pass(n.u, hb);
+            }
+            o << "  }\n";
+            if ((g + 1) % kAdjLeafFenceGroups == 0 && g + 1 < G) o << "  AMI_SCHED_FENCE();\n";
+        }
+        o << "}\n";
+    }
+
     if (adj_fns) {
     // U_k = sum over the occurrences of k in the groups of u_g
     std::vector<std::vector<int>> occ(D);
@@ -807,7 +952,17 @@ std::string jit_source(const AmiTerms *t, bool hub, int kernels) {
         }
     }
     o << "}\n";
+    }  // adj_fns
 
+    // the leaves' and lines' scatters: every adjoint kernel (one pass, or the
+    // leaf pass of large solutions)
+    if (adj_fns || (kernels & 128)) {
+    auto scatter = [&](std::ostream &os, double c, const std::string &dst, const std::string &v) {
+        if (c == 0.0) return;
+        if (c == 1.0) os << "  " << dst << " += " << v << ";\n";
+        else if (c == -1.0) os << "  " << dst << " -= " << v << ";\n";
+        else os << "  " << dst << " = fma(" << num(c) << ", " << v << ", " << dst << ");\n";
+    };
     // dL/dE_i += sum_l c_li v_l
     o << "__device__ __forceinline__ void leaf_scatter(const double (&v)[L], double (&gE)[NE]) {\n";
     o << kReverseContract;
@@ -828,7 +983,7 @@ std::string jit_source(const AmiTerms *t, bool hub, int kernels) {
             }
     }
     o << "}\n";
-    }  // adj_fns
+    }  // adjoint scatters
     o << "}  // namespace amijit\n";
     o << "#include \"jit_kernel.hpp\"\n";
     return o.str();
@@ -844,9 +999,9 @@ extern "C" AmiStatus amiTermsSource(const AmiTerms *t, int32_t momentum, char *b
     const bool hub = (momentum & 1) != 0, two_pass = (momentum & 2) != 0;
     std::string why;
     if (!jit_supported(t, hub, &why, two_pass)) return fail(AMI_E_UNSUPPORTED, "no specialized kernel: " + why);
-    int kernels = two_pass ? 48 : hub ? 7 : 11;
+    int kernels = two_pass ? 48 | 64 | 128 : hub ? 7 : 11;
     for (int o : t->tab.leaf_order)
-        if (o > 0) kernels &= ~10;   // Taylor-coefficient leaves: no adjoint, no complex energies
+        if (o > 0) kernels &= ~(2 | 8 | 64 | 128);   // Taylor-coefficient leaves: no adjoint, no complex energies
     const std::string src = jit_source(t, hub, kernels);
     *len = static_cast<int64_t>(src.size()) + 1;
     if (!buf) return AMI_OK;

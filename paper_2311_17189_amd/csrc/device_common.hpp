@@ -26,6 +26,13 @@ typedef __hip_internal::int8_t int8_t;
 #define AMI_OPAQUE(x) asm volatile("" : "+v"(x))
 #endif
 
+// A scheduling fence: the compiler moves no instruction across it.  Generated
+// code puts one between chunks of independent work, so that the loads and
+// values of a later chunk do not stay live through an earlier one.
+#ifndef AMI_SCHED_FENCE
+#define AMI_SCHED_FENCE() __builtin_amdgcn_sched_barrier(0)
+#endif
+
 namespace ami {
 
 typedef const __attribute__((address_space(4))) uint64_t *cu64;

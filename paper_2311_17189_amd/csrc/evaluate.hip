@@ -364,7 +364,7 @@ bool timer_pair(hipEvent_t &start, hipEvent_t &stop) {
     return true;
 }
 
-enum class Path { TABLES, PACKED, SPECIALIZED, TWO_PASS };
+enum class Path { TABLES, PACKED, SPECIALIZED, TWO_PASS, ADJ_PASSES };
 
 // Workspace of one chunk of the two-pass forward (group sums and energies):
 // 256 MB unless amiSetTwoPassChunkBytes set another bound.
@@ -378,8 +378,11 @@ constexpr int kTwoPassMaxFreqs = 65535;
 // With no_load the specialized kernels must already be loaded on the device
 // (jit_loaded): nothing is compiled, loaded or allocated, and a kernel that
 // the call would use but that is not loaded yet is an error, not a fallback.
+// The adjoint of a large solution in passes (Path::ADJ_PASSES) takes three
+// kernels: jit_fn (sums pass), jit_fn2 (frequency pass), jit_fn3 (leaf pass).
 AmiStatus choose_path(AmiTerms *t, bool hub, bool adjoint, Path &p, void **jit_fn, std::string &note,
-                      void **jit_fn2 = nullptr, int n_f = 1, int variant = -1, bool no_load = false) {
+                      void **jit_fn2 = nullptr, int n_f = 1, int variant = -1, bool no_load = false,
+                      void **jit_fn3 = nullptr) {
     const int v = variant >= 0 ? variant : t->variant;
     note.clear();
     auto get = [&](int kind, void **fn) {
@@ -390,9 +393,26 @@ AmiStatus choose_path(AmiTerms *t, bool hub, bool adjoint, Path &p, void **jit_f
     const bool two = !adjoint && jit_fn2 && n_f <= kTwoPassMaxFreqs &&
                      (v == AMI_VARIANT_TWO_PASS ||
                       ((v == AMI_VARIANT_AUTO || v == AMI_VARIANT_SPECIALIZED) && jit_prefers_two_pass(t)));
-    if (v == AMI_VARIANT_TWO_PASS && !two)
-        return fail(AMI_E_UNSUPPORTED, adjoint ? "the two-pass variant has no adjoint"
+    const bool passes = adjoint && jit_fn2 && jit_fn3 &&
+                        (v == AMI_VARIANT_TWO_PASS || (v == AMI_VARIANT_AUTO && t->tab.T > kJitAutoAdjointTerms));
+    if (v == AMI_VARIANT_TWO_PASS && !two && !passes)
+        return fail(AMI_E_UNSUPPORTED, adjoint ? "the two-pass variant of the adjoint runs in passes only"
                                                : "the two-pass variant takes at most 65535 frequency rows");
+    if (passes) {
+        std::string why;
+        AmiStatus st = AMI_OK;
+        if (!jit_adjoint_passes_supported(t, hub, &why)) st = fail(AMI_E_UNSUPPORTED, "no adjoint in passes: " + why);
+        if (st == AMI_OK) st = get(kJitSumsPass, jit_fn);
+        if (st == AMI_OK) st = get(kJitAdjFreq, jit_fn2);
+        if (st == AMI_OK) st = get(kJitAdjLeaf, jit_fn3);
+        if (st == AMI_OK) {
+            p = Path::ADJ_PASSES;
+            return AMI_OK;
+        }
+        if (v != AMI_VARIANT_AUTO || (no_load && st != AMI_E_UNSUPPORTED)) return st;
+        note = std::string(" (not in passes: ") + amiLastError() + ")";
+        clear_error();
+    }
     if (two) {
         AmiStatus st = get(kJitSumsPass, jit_fn);
         if (st == AMI_OK) st = get(kJitFreqPass, jit_fn2);
@@ -405,7 +425,8 @@ AmiStatus choose_path(AmiTerms *t, bool hub, bool adjoint, Path &p, void **jit_f
         clear_error();
     }
     const bool auto_skip = v == AMI_VARIANT_AUTO && adjoint && t->tab.T > kJitAutoAdjointTerms;
-    if (auto_skip) note = " (adjoint specialized up to " + std::to_string(kJitAutoAdjointTerms) + " terms)";
+    if (auto_skip && note.empty())
+        note = " (adjoint specialized in one pass up to " + std::to_string(kJitAutoAdjointTerms) + " terms)";
     if (v == AMI_VARIANT_SPECIALIZED || (v == AMI_VARIANT_AUTO && !auto_skip && !two)) {
         const AmiStatus st = get(adjoint ? kJitAdjoint : kJitForward, jit_fn);
         if (st == AMI_OK) {
@@ -636,6 +657,69 @@ struct AdjOut {
     double *out_sum = nullptr;   // forward row sums computed on the way (optional)
 };
 
+// The adjoint of a large solution in passes, per chunk of samples: the
+// two-pass forward's sums pass (FT_g and E_j into the workspace), the
+// frequency pass (values, FTB_g and the denominators' energy cotangents into
+// the workspace, wave sums of dL/dw and of the values), the leaf pass (leaf
+// cotangents, per-sample gradients, wave sums of dL/dbeta, dL/dmu, dL/dt);
+// then one reduction of the wave sums.  Workspace: the partial sums (rows x
+// columns), then the chunk's 2 G + 2 NE columns of ld samples each.
+// fixed_ws: both in the allocation-free scratch (the chunk sized to what is
+// left), nothing allocated.
+AmiStatus launch_adjoint_passes(AmiTerms *t, DeviceTables *dt, bool hub, KArgs &a, const AdjOut &o, void *fn_sums,
+                                void *fn_freq, void *fn_leaf, hipStream_t stream, double *fixed_ws) {
+    const int B = jit_block(t, hub);
+    const int64_t tiles = (a.n_e + B - 1) / B;
+    if (tiles > 0x7fffffffLL) return fail(AMI_E_ARG, "n_e too large");
+    const int64_t rows = tiles * (B / 64);
+    const int ncols = kAdjScalars + 2 * a.n_f * t->n_ext;
+    const int nval = o.out_sum ? 2 * a.n_f : 0;
+    const int64_t cols = 2 * static_cast<int64_t>(t->tab.G) + 2 * t->n_eps;
+    const size_t n_part = static_cast<size_t>(rows) * (ncols + nval);
+    int64_t ld = 0;
+    double *ws = nullptr;
+    if (fixed_ws) {
+        const int64_t left = static_cast<int64_t>(kScratchBytes / sizeof(double)) - static_cast<int64_t>(n_part);
+        ld = left > 0 ? left / cols / B * B : 0;
+        if (ld < B)
+            return fail(AMI_E_ARG, "the partial sums and one chunk of samples do not fit the " +
+                                       std::to_string(kScratchBytes) +
+                                       "-byte scratch of the allocation-free entry point: split the samples");
+        ld = std::min<int64_t>(ld, tiles * B);
+        ws = fixed_ws;
+    } else {
+        ld = g_two_pass_chunk_bytes.load() / (cols * static_cast<int64_t>(sizeof(double))) / B * B;
+        ld = std::max<int64_t>(B, std::min<int64_t>(ld, tiles * B));
+    }
+    ld = std::min<int64_t>(ld, int64_t(1) << 28);   // the kernels address a chunk with 32-bit byte offsets
+    if (!fixed_ws) {
+        const AmiStatus st = workspace(t, dt, stream, (n_part + static_cast<size_t>(cols) * ld) * sizeof(double), &ws);
+        if (st != AMI_OK) return st;
+    }
+    a.gpartial = ws;
+    a.partial = o.out_sum ? ws + static_cast<size_t>(rows) * ncols : nullptr;
+    a.nrows = rows;
+    a.work = ws + n_part;
+    a.ld = ld;
+    a.mc = 0;
+    hipError_t e = hipSuccess;
+    for (int64_t s0 = 0; s0 < a.n_e && e == hipSuccess; s0 += ld) {
+        a.s0 = s0;
+        a.n_chunk = std::min<int64_t>(ld, a.n_e - s0);
+        const int64_t nb = (a.n_chunk + B - 1) / B;
+        e = launch_jit(fn_sums, nb, B, stream, a);
+        if (e == hipSuccess) e = launch_jit(fn_freq, nb, B, stream, a);
+        if (e == hipSuccess) e = launch_jit(fn_leaf, nb, B, stream, a);
+    }
+    if (e == hipSuccess) e = hipGetLastError();
+    g_last_variant = "specialized passes";
+    if (e != hipSuccess) return hip_fail(e, "adjoint passes launch");
+    hipLaunchKernelGGL(ami_adj_finalize_kernel, dim3(ncols + nval), dim3(kRedThreads), 0, stream, a.gpartial, rows,
+                       ncols, 1, o.grad_beta, o.grad_mu, o.grad_t, o.grad_freqs, 2 * a.n_f, o.out_sum);
+    e = hipGetLastError();
+    return e == hipSuccess ? AMI_OK : hip_fail(e, "adjoint reduction launch");
+}
+
 // fixed_ws: the partial sums go there (at most kScratchBytes), and nothing is
 // uploaded, compiled, loaded or allocated (the allocation-free entry point);
 // NULL: the handle's per-stream workspace.
@@ -657,10 +741,12 @@ AmiStatus launch_adjoint(AmiTerms *t, bool hub, KArgs &a, const AdjOut &o, hipSt
         return fill(o.grad_freqs, 2 * static_cast<int64_t>(a.n_f) * nx, stream);
     }
     Path path;
-    void *jit_fn = nullptr;
+    void *jit_fn = nullptr, *jit_fn2 = nullptr, *jit_fn3 = nullptr;
     std::string note;
-    st = choose_path(t, hub, true, path, &jit_fn, note, nullptr, 1, -1, fixed_ws != nullptr);
+    st = choose_path(t, hub, true, path, &jit_fn, note, &jit_fn2, a.n_f, -1, fixed_ws != nullptr, &jit_fn3);
     if (st != AMI_OK) return st;
+    if (path == Path::ADJ_PASSES)
+        return launch_adjoint_passes(t, dt, hub, a, o, jit_fn, jit_fn2, jit_fn3, stream, fixed_ws);
     LaunchShape ls;
     if (path == Path::SPECIALIZED) {
         ls.block = jit_block(t, hub);
@@ -1088,6 +1174,11 @@ AmiStatus amiTermsSpecialize(AmiTerms *t, int32_t momentum) {
         kinds.push_back(kJitForward);
     }
     if (!taylor && t->tab.T <= kJitAutoAdjointTerms) kinds.push_back(kJitAdjoint);
+    if (!taylor && t->tab.T > kJitAutoAdjointTerms && jit_adjoint_passes_supported(t, hub, nullptr)) {
+        if (!jit_prefers_two_pass(t)) kinds.push_back(kJitSumsPass);
+        kinds.push_back(kJitAdjFreq);
+        kinds.push_back(kJitAdjLeaf);
+    }
     if (!taylor && small && !hub) kinds.push_back(kJitComplex);
     for (int k : kinds) {
         const AmiStatus st = jit_compile(t, hub, k);

@@ -146,14 +146,15 @@ AmiStatus code_object(AmiTerms *t, bool hub, int kind) {
     std::string &err = t->jit_error[slot];
     if (!err.empty()) return fail(AMI_E_UNSUPPORTED, err);
     std::string why;
-    if (!jit_supported(t, hub, &why, kind == kJitSumsPass || kind == kJitFreqPass)) {
+    const bool passes = kind == kJitSumsPass || kind == kJitFreqPass || kind == kJitAdjFreq || kind == kJitAdjLeaf;
+    if (!jit_supported(t, hub, &why, passes)) {
         err = "no specialized kernel: " + why;
         return fail(AMI_E_UNSUPPORTED, err);
     }
-    if (kind == kJitAdjoint || kind == kJitComplex)
+    if (kind == kJitAdjoint || kind == kJitComplex || kind == kJitAdjFreq || kind == kJitAdjLeaf)
         for (int o : t->tab.leaf_order)
             if (o > 0) {
-                err = kind == kJitAdjoint
+                err = kind != kJitComplex
                           ? "no specialized adjoint for Taylor-coefficient leaves (poles of higher order)"
                           : "no complex-energy kernel for Taylor-coefficient leaves (poles of higher order)";
                 return fail(AMI_E_UNSUPPORTED, err);
@@ -206,8 +207,8 @@ AmiStatus jit_get(AmiTerms *t, bool hub, int kind, void **fn) {
     e = hipModuleLoadData(&mod, t->jit_code[slot].data());
     if (e != hipSuccess) return hip_fail(e, "hipModuleLoadData (specialized kernel)");
     hipFunction_t f = nullptr;
-    static const char *const kNames[kJitKinds] = {"ami_jit_fwd", "ami_jit_adj", "ami_jit_mc", "ami_jit_cfwd",
-                                                  "ami_jit_sums", "ami_jit_freq"};
+    static const char *const kNames[kJitKinds] = {"ami_jit_fwd",  "ami_jit_adj",  "ami_jit_mc",   "ami_jit_cfwd",
+                                                  "ami_jit_sums", "ami_jit_freq", "ami_jit_adjf", "ami_jit_adjl"};
     e = hipModuleGetFunction(&f, mod, kNames[kind]);
     if (e != hipSuccess) {
         (void)hipModuleUnload(mod);

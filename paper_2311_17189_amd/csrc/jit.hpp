@@ -15,9 +15,14 @@ constexpr int kJitMaxTerms = 1024;
 // stored per sample by a first kernel, read back per frequency by a second):
 // its register use does not grow with the number of groups.
 constexpr int kJitTwoPassMaxTerms = 4096;
-// AMI_VARIANT_AUTO uses the specialized adjoint up to this many terms: beyond
-// it the straight-line reverse sweep outgrows the register file.
+// AMI_VARIANT_AUTO uses the one-pass specialized adjoint up to this many
+// terms: beyond it the straight-line reverse sweep outgrows the register file,
+// and the adjoint runs in passes over a workspace (up to kJitTwoPassMaxTerms).
 constexpr int kJitAutoAdjointTerms = 128;
+
+// Whether the adjoint of a solution above kJitAutoAdjointTerms can run in
+// passes (the two-pass form, no Taylor-coefficient leaves).
+bool jit_adjoint_passes_supported(const AmiTerms *t, bool hub, std::string *why);
 
 // Whether the diagram can be specialized for the energy (hub = false) or
 // momentum (hub = true) input; *why says why not.
@@ -33,14 +38,28 @@ int jit_block(const AmiTerms *t, bool hub);
 
 // Device source of the specialized kernels: the forward (kernels & 1), the
 // adjoint (kernels & 2), the Monte-Carlo integrator (kernels & 4), the
-// forward at complex energies (kernels & 8), and the two passes of the
+// forward at complex energies (kernels & 8), the two passes of the
 // two-pass forward (kernels & 16: group sums and energies stored per sample;
-// kernels & 32: per frequency, reciprocals and group products against them).
+// kernels & 32: per frequency, reciprocals and group products against them),
+// and the passes of the adjoint of large solutions that follow the first of
+// those (kernels & 64: per frequency, the group-sum and denominator
+// cotangents; kernels & 128: the leaf cotangents and the gradients).
 std::string jit_source(const AmiTerms *t, bool hub, int kernels);
 
 // Kernels of the specialized evaluator.
-enum JitKind { kJitForward = 0, kJitAdjoint = 1, kJitMonteCarlo = 2, kJitComplex = 3, kJitSumsPass = 4, kJitFreqPass = 5 };
-constexpr int kJitKinds = 6;
+// kJitAdjFreq and kJitAdjLeaf are the frequency and leaf passes of the
+// adjoint of large solutions (after kJitSumsPass).
+enum JitKind {
+    kJitForward = 0,
+    kJitAdjoint = 1,
+    kJitMonteCarlo = 2,
+    kJitComplex = 3,
+    kJitSumsPass = 4,
+    kJitFreqPass = 5,
+    kJitAdjFreq = 6,
+    kJitAdjLeaf = 7
+};
+constexpr int kJitKinds = 8;
 
 // The specialized kernel of `kind` for the energy (hub = false) or momentum
 // input as a hipFunction_t: compiled (or fetched from the code-object cache)

@@ -259,6 +259,99 @@ __device__ __forceinline__ void fwd_tile(const KArgs &a, int64_t tile) {
 
 #endif
 
+#if AMI_JIT_KERNELS & (2 | 128)
+// The end of the adjoint of one sample once its leaf cotangents FB are known:
+// the leaves' derivatives (f'(y) from Dv or the park area) scattered to the
+// energies and to beta, on the momentum input the chain rule through
+// dE_j/dK_j = -2t sin K_j to the momenta (the trig values parked by
+// energies<HUB, true>), the per-sample gradient rows (staged through the park
+// area when they fit), and the wave sums of dL/dbeta, dL/dmu, dL/dt at the
+// partial-sum row gp.  s_blk: the block's first sample; s_end: one past the
+// last sample the launch writes; gE holds the energies' cotangent so far.
+template <bool HUB>
+__device__ __forceinline__ void adj_leaf_end(const KArgs &a, int64_t s_blk, int64_t s_end, bool active, double *gp,
+                                             double *park, const double (&E)[NE], const double (&Dv)[kParkDv ? 1 : L],
+                                             const double (&FB)[L], double (&gE)[NE]) {
+#pragma clang fp contract(fast)
+    const int tid = threadIdx.x, B = blockDim.x, lane = tid & 63;
+    const int64_t s = s_blk + tid;
+    double gbeta = 0.0, v[L], x[L];
+    leaf_args(E, x);
+#pragma unroll
+    for (int l = 0; l < L; ++l) {
+        if (kBose[l]) x[l] += a.e_reg;
+        const double fb = FB[l] * (kParkDv ? park[(kParkChain + l) * B + tid] : Dv[kParkDv ? 0 : l]);
+        v[l] = fb * a.beta;
+        gbeta = fma(fb, x[l], gbeta);
+    }
+    leaf_scatter(v, gE);
+
+    double gmu = 0.0, gt = 0.0;
+    if constexpr (HUB) {
+        double gx[NGA], gy[NGA], gkx[NIA], gky[NIA];
+#pragma unroll
+        for (int j = 0; j < NG; ++j) {
+            gmu += gE[j];
+            gt = fma(gE[j], 2.0 * park[(2 * NG + j) * B + tid], gt);
+            gx[j] = -2.0 * a.hop_t * gE[j] * park[j * B + tid];
+            gy[j] = -2.0 * a.hop_t * gE[j] * park[(NG + j) * B + tid];
+        }
+#pragma unroll
+        for (int l = 0; l < NIA; ++l) {
+            gkx[l] = 0.0;
+            gky[l] = 0.0;
+        }
+        line_scatter(gx, gy, gkx, gky);
+        if constexpr (kStageFits<2 * NI>) {
+            if (a.grad_k) {
+                double g[2 * NI];
+#pragma unroll
+                for (int l = 0; l < NI; ++l) {
+                    g[2 * l] = gkx[l];
+                    g[2 * l + 1] = gky[l];
+                }
+                __syncthreads();                    // every wave has read its parked values
+                const int wave = tid >> 6;
+                const int64_t s0 = s_blk + (wave << 6);
+                store_rows_staged<2 * NI>(park + wave * 65 * (2 * NI), lane, g, a.grad_k + s0 * (2 * NI),
+                                          (s_end - s0) * (2 * NI));
+            }
+        } else if (active && a.grad_k) {
+            double *row = a.grad_k + s * (2 * NI);
+            if (a.vec_io & 2) {
+#pragma unroll
+                for (int l = 0; l < NI; ++l) {
+                    double2 g2;
+                    g2.x = gkx[l];
+                    g2.y = gky[l];
+                    reinterpret_cast<double2 *>(row)[l] = g2;
+                }
+            } else {
+#pragma unroll
+                for (int l = 0; l < NI; ++l) {
+                    row[2 * l] = gkx[l];
+                    row[2 * l + 1] = gky[l];
+                }
+            }
+        }
+    }
+    if constexpr (kStageFits<NE>) {
+        if (a.grad_e) {
+            __syncthreads();                        // every wave is done with the park area
+            const int wave = tid >> 6;
+            const int64_t s0 = s_blk + (wave << 6);
+            store_rows_staged<NE>(park + wave * 65 * NE, lane, gE, a.grad_e + s0 * NE, (s_end - s0) * NE);
+        }
+    } else if (active && a.grad_e) {
+        double *row = a.grad_e + s * NE;
+#pragma unroll
+        for (int i = 0; i < NE; ++i) row[i] = gE[i];
+    }
+    ami::wave_store4(active ? gbeta : 0.0, active ? gmu : 0.0, active ? gt : 0.0, 0.0, lane, gp, gp + a.nrows,
+                     gp + 2 * a.nrows, nullptr);
+}
+#endif
+
 #if AMI_JIT_KERNELS & 2
 // Adjoint of L = Re sum_{f,s} conj(c[f,s]) I[f,s] (the packed adjoint's
 // derivation), with the denominator cotangents collected per distinct
@@ -381,80 +474,7 @@ __device__ __forceinline__ void adj_tile(const KArgs &a, int64_t blk, double *pa
 #pragma unroll
     for (int l = 0; l < L; ++l) FB[l] = 0.0;
     leaf_cotangents(F, FTB, FB);
-    double gbeta = 0.0, v[L], x[L];
-    leaf_args(E, x);
-#pragma unroll
-    for (int l = 0; l < L; ++l) {
-        if (kBose[l]) x[l] += a.e_reg;
-        const double fb = FB[l] * (kParkDv ? park[(kParkChain + l) * B + tid] : Dv[kParkDv ? 0 : l]);
-        v[l] = fb * a.beta;
-        gbeta = fma(fb, x[l], gbeta);
-    }
-    leaf_scatter(v, gE);
-
-    double gmu = 0.0, gt = 0.0;
-    if constexpr (HUB) {
-        double gx[NGA], gy[NGA], gkx[NIA], gky[NIA];
-#pragma unroll
-        for (int j = 0; j < NG; ++j) {
-            gmu += gE[j];
-            gt = fma(gE[j], 2.0 * park[(2 * NG + j) * B + tid], gt);
-            gx[j] = -2.0 * a.hop_t * gE[j] * park[j * B + tid];
-            gy[j] = -2.0 * a.hop_t * gE[j] * park[(NG + j) * B + tid];
-        }
-#pragma unroll
-        for (int l = 0; l < NIA; ++l) {
-            gkx[l] = 0.0;
-            gky[l] = 0.0;
-        }
-        line_scatter(gx, gy, gkx, gky);
-        if constexpr (kStageFits<2 * NI>) {
-            if (a.grad_k) {
-                double g[2 * NI];
-#pragma unroll
-                for (int l = 0; l < NI; ++l) {
-                    g[2 * l] = gkx[l];
-                    g[2 * l + 1] = gky[l];
-                }
-                __syncthreads();                    // every wave has read its parked values
-                const int wave = tid >> 6;
-                const int64_t s0 = blk * B + (wave << 6);
-                store_rows_staged<2 * NI>(park + wave * 65 * (2 * NI), lane, g, a.grad_k + s0 * (2 * NI),
-                                          (a.n_e - s0) * (2 * NI));
-            }
-        } else if (active && a.grad_k) {
-            double *row = a.grad_k + s * (2 * NI);
-            if (a.vec_io & 2) {
-#pragma unroll
-                for (int l = 0; l < NI; ++l) {
-                    double2 g2;
-                    g2.x = gkx[l];
-                    g2.y = gky[l];
-                    reinterpret_cast<double2 *>(row)[l] = g2;
-                }
-            } else {
-#pragma unroll
-                for (int l = 0; l < NI; ++l) {
-                    row[2 * l] = gkx[l];
-                    row[2 * l + 1] = gky[l];
-                }
-            }
-        }
-    }
-    if constexpr (kStageFits<NE>) {
-        if (a.grad_e) {
-            __syncthreads();                        // every wave is done with the park area
-            const int wave = tid >> 6;
-            const int64_t s0 = blk * B + (wave << 6);
-            store_rows_staged<NE>(park + wave * 65 * NE, lane, gE, a.grad_e + s0 * NE, (a.n_e - s0) * NE);
-        }
-    } else if (active && a.grad_e) {
-        double *row = a.grad_e + s * NE;
-#pragma unroll
-        for (int i = 0; i < NE; ++i) row[i] = gE[i];
-    }
-    ami::wave_store4(active ? gbeta : 0.0, active ? gmu : 0.0, active ? gt : 0.0, 0.0, lane, gp, gp + a.nrows,
-                     gp + 2 * a.nrows, nullptr);
+    adj_leaf_end<HUB>(a, blk * B, a.n_e, active, gp, park, E, Dv, FB, gE);
 }
 #endif
 
@@ -587,6 +607,131 @@ __device__ __forceinline__ void freq_tile(const KArgs &a, int64_t tile, int f) {
 }
 #endif
 
+#if AMI_JIT_KERNELS & 64
+// Adjoint of a large solution, frequency pass (after the two-pass forward's
+// first pass stored FT_g and E_j): one lane per sample of the chunk, every
+// frequency row in turn.  Per row the generated adj_freq_row forms, chunk of
+// groups by chunk, the reciprocals, each group's R_g, the value sum_g FT_g R_g,
+// FTB_g += Re(conj(c) R_g) (stored in the workspace) and the denominators'
+// cotangents scattered to the energies (gE, stored after the last row) and to
+// the frequencies.  Values go to out[f][s]; the wave sums of dL/dw and of the
+// values to row (s0 / B + tile) * (B / 64) + wave of the partial sums, in the
+// columns of the one-pass adjoint.
+__device__ __forceinline__ void adjf_tile(const KArgs &a, int64_t tile) {
+    const int tid = threadIdx.x, B = blockDim.x, lane = tid & 63;
+    const int64_t i = tile * B + tid;
+    const bool active = i < a.n_chunk;
+    const int64_t s = a.s0 + i;
+    const int64_t row = (a.s0 / B + tile) * (B >> 6) + (tid >> 6);
+    const uint32_t off = static_cast<uint32_t>(i) * 8u;   // i < ld <= 2^28 (host bound)
+    double E[NE], gE[NE];
+#pragma unroll
+    for (int j = 0; j < NE; ++j) {
+        E[j] = ami::ws_load(a.work, a.ld, G + j, off);
+        gE[j] = 0.0;
+    }
+    double *gp = a.gpartial + row;
+    for (int f = 0; f < a.n_f; ++f) {
+        double cr = 0.0, ci = 0.0;
+        if (active) {
+            if (a.g_out) {
+                cr = a.g_out[2 * (static_cast<int64_t>(f) * a.n_e + s)];
+                ci = a.g_out[2 * (static_cast<int64_t>(f) * a.n_e + s) + 1];
+            }
+            if (a.g_sum) {
+                cr += a.g_sum[2 * f];
+                ci += a.g_sum[2 * f + 1];
+            }
+        }
+        double wr[NXA], wi[NXA], gwr[NXA], gwi[NXA];
+        load_freq(a, f, wr, wi);
+#pragma unroll
+        for (int xx = 0; xx < NXA; ++xx) {
+            gwr[xx] = 0.0;
+            gwi[xx] = 0.0;
+        }
+        double acc_re = 0.0, acc_im = 0.0;
+        // the offset made opaque per row: the workspace addresses of every
+        // column are then formed where they are used, not hoisted out of the
+        // loop and held (64-bit per lane and column) through it
+        uint32_t off_f = off;
+        AMI_OPAQUE(off_f);
+        adj_freq_row(E, wr, wi, cr, ci, a.work, a.ld, off_f, f == 0, acc_re, acc_im, gE, gwr, gwi);
+        if (active && a.out) {
+            double2 v;
+            v.x = acc_re;
+            v.y = acc_im;
+            reinterpret_cast<double2 *>(a.out)[static_cast<int64_t>(f) * a.n_e + s] = v;
+        }
+        constexpr int NV = 2 * NX + 2, NV4 = (NV + 3) / 4 * 4;
+        double vv[NV4];
+        double *pp[NV4];
+#pragma unroll
+        for (int xx = 0; xx < NX; ++xx) {
+            vv[2 * xx] = active ? gwr[xx] : 0.0;
+            vv[2 * xx + 1] = active ? -gwi[xx] : 0.0;
+            pp[2 * xx] = gp + (ami::kAdjScalars + 2 * (f * NX + xx)) * a.nrows;
+            pp[2 * xx + 1] = pp[2 * xx] + a.nrows;
+        }
+        vv[2 * NX] = active ? acc_re : 0.0;
+        vv[2 * NX + 1] = active ? acc_im : 0.0;
+        pp[2 * NX] = a.partial ? a.partial + 2 * f * a.nrows + row : nullptr;
+        pp[2 * NX + 1] = a.partial ? pp[2 * NX] + a.nrows : nullptr;
+#pragma unroll
+        for (int c = NV; c < NV4; ++c) {
+            vv[c] = 0.0;
+            pp[c] = nullptr;
+        }
+#pragma unroll
+        for (int c = 0; c < NV4; c += 4)
+            ami::wave_store4(vv[c], vv[c + 1], vv[c + 2], vv[c + 3], lane, pp[c], pp[c + 1], pp[c + 2], pp[c + 3]);
+    }
+#pragma unroll
+    for (int j = 0; j < NE; ++j) ami::ws_store(a.work, a.ld, G + NE + j, off, gE[j]);
+}
+#endif
+
+#if AMI_JIT_KERNELS & 128
+// Adjoint of a large solution, leaf pass (after the frequency pass): one lane
+// per sample of the chunk.  The energies again from the sample's inputs (on
+// the momentum input with the chain rule's trig values parked), the leaves
+// and their derivatives, the leaf cotangents by the reverse sweep of every
+// group's nested sum against the stored FTB_g, then the end of the one-pass
+// adjoint (adj_leaf_end) on the stored energy cotangents of the denominators.
+template <bool HUB>
+__device__ __forceinline__ void adjl_tile(const KArgs &a, int64_t tile, double *park) {
+    const int tid = threadIdx.x, B = blockDim.x;
+    const int64_t i = tile * B + tid;
+    const bool active = i < a.n_chunk;
+    const int64_t row = (a.s0 / B + tile) * (B >> 6) + (tid >> 6);
+    const uint32_t off = static_cast<uint32_t>(i) * 8u;
+    double in[NIN];
+    load_inputs<HUB>(a, a.s0 + (active ? i : a.n_chunk - 1), in);
+    double E[NE];
+    energies<HUB, HUB>(a, in, E, park);
+    double F[L], Dv[kParkDv ? 1 : L];
+    {
+        double x[L];
+        leaf_args(E, x);
+#pragma unroll
+        for (int l = 0; l < L; ++l) {
+            if (kBose[l]) x[l] += a.e_reg;
+            double dv;                          // f'(y) = -f(y) f(-y)
+            ami::leaf_and_slope(kBose[l], a.beta * x[l], F[l], dv);
+            if constexpr (kParkDv) park[(kParkChain + l) * B + tid] = dv;
+            else Dv[kParkDv ? 0 : l] = dv;
+        }
+    }
+    double FB[L], gE[NE];
+#pragma unroll
+    for (int l = 0; l < L; ++l) FB[l] = 0.0;
+    leaf_cotangents_ws(F, a.work, a.ld, off, FB);
+#pragma unroll
+    for (int j = 0; j < NE; ++j) gE[j] = ami::ws_load(a.work, a.ld, G + NE + j, off);
+    adj_leaf_end<HUB>(a, a.s0 + tile * B, a.s0 + a.n_chunk, active, a.gpartial + row, park, E, Dv, FB, gE);
+}
+#endif
+
 #if AMI_JIT_KERNELS & 8
 // Forward at complex energies (energy input; interleaved complex128 rows,
 // strides in complex elements).  The leaf arguments and the energy part of
@@ -692,6 +837,32 @@ extern "C" __global__ __launch_bounds__(AMI_JIT_BLOCK) void ami_jit_mc(ami::KArg
 #if AMI_JIT_KERNELS & 8
 extern "C" __global__ __launch_bounds__(AMI_JIT_BLOCK) void ami_jit_cfwd(ami::KArgs a) {
     amijit::cfwd_tile(a, blockIdx.x);
+}
+#endif
+
+// occupancy floors of the large adjoint's passes (waves per SIMD; 0: none)
+#ifndef AMI_JIT_ADJF_WAVES
+#define AMI_JIT_ADJF_WAVES 2
+#endif
+#ifndef AMI_JIT_ADJL_WAVES
+#define AMI_JIT_ADJL_WAVES 2
+#endif
+#if AMI_JIT_KERNELS & 64
+#if AMI_JIT_ADJF_WAVES > 0
+__attribute__((amdgpu_waves_per_eu(AMI_JIT_ADJF_WAVES)))
+#endif
+extern "C" __global__ __launch_bounds__(AMI_JIT_BLOCK) void ami_jit_adjf(ami::KArgs a) {
+    amijit::adjf_tile(a, blockIdx.x);
+}
+#endif
+
+#if AMI_JIT_KERNELS & 128
+#if AMI_JIT_ADJL_WAVES > 0
+__attribute__((amdgpu_waves_per_eu(AMI_JIT_ADJL_WAVES)))
+#endif
+extern "C" __global__ __launch_bounds__(AMI_JIT_BLOCK) void ami_jit_adjl(ami::KArgs a) {
+    __shared__ double park[amijit::kParkCols > 0 ? amijit::kParkCols * AMI_JIT_BLOCK : 1];
+    amijit::adjl_tile<AMI_JIT_HUB>(a, blockIdx.x, park);
 }
 #endif
 

@@ -7,6 +7,7 @@
 #define __forceinline__ inline
 #define __launch_bounds__(x)
 #define AMI_OPAQUE(x) asm volatile("" : "+m"(x))
+#define AMI_SCHED_FENCE()
 #define __builtin_amdgcn_rcp(x) (1.0 / (x))
 using std::expm1;
 using std::fabs;

@@ -19,6 +19,11 @@ DEV = "cuda"
 
 VARIANTS = pytest.mark.parametrize("variant", [amd.VARIANT_PACKED, amd.VARIANT_SPECIALIZED],
                                    ids=["packed", "specialized"])
+# the adjoint's kernels: table-driven, specialized in one pass, specialized in
+# passes over a workspace (VARIANT_TWO_PASS; AUTO above 128 terms)
+ADJ_VARIANTS = pytest.mark.parametrize("variant", [amd.VARIANT_PACKED, amd.VARIANT_SPECIALIZED,
+                                                   amd.VARIANT_TWO_PASS],
+                                       ids=["packed", "specialized", "passes"])
 
 
 def _terms(d, variant=amd.VARIANT_AUTO):
@@ -40,7 +45,7 @@ def _rel(a, b):
 
 @pytest.mark.parametrize("order,i,beta", [(2, None, 5.0), (3, 1, 2.0), (4, 1, 5.0), (4, 1, 20.0),
                                           (5, 0, 3.0), (6, 0, 5.0)])
-@VARIANTS
+@ADJ_VARIANTS
 def test_energy_adjoint_vs_oracle(order, i, beta, variant):
     """Per-sample dL/dE within 1e-10 of sum_t |dL_t/dE| (1e-6 next to a pole of
     one term); the sums over samples (dL/dbeta, dL/dw) within 1e-10 relative
@@ -80,7 +85,7 @@ def test_energy_adjoint_vs_oracle(order, i, beta, variant):
 
 
 @pytest.mark.parametrize("order,i", [(2, None), (4, 1), (4, 3), (5, 2)])
-@VARIANTS
+@ADJ_VARIANTS
 def test_hubbard_adjoint_vs_oracle(order, i, variant):
     """Momentum-path adjoint: every output within 1e-10 of its rounding scale
     (the sum over terms, and over samples for reduced outputs, of the
@@ -153,7 +158,7 @@ def test_adjoint_matches_finite_differences_of_forward(variant):
         assert abs(got - fd) <= 1e-7 * abs(fd) + floor, (got, fd, floor)
 
 
-@VARIANTS
+@ADJ_VARIANTS
 def test_momentum_gradient_matches_finite_differences(variant):
     """Every momentum component of the order-4 adjoint step (8 per sample)
     against central differences (h = 1e-6, float64) of the HIP forward: each
@@ -356,29 +361,81 @@ def test_value_and_gradient_in_one_pass(variant):
     check(out.cpu().numpy(), ref, scale, dist, label="value and gradient")
 
 
-def test_auto_adjoint_falls_back_above_its_limit():
-    """AUTO runs the specialized adjoint up to 128 terms and the packed one
-    above (the forward of a solution above 1024 terms in two passes); a forced
-    variant that cannot serve the call fails it."""
+def test_auto_adjoint_above_its_one_pass_limit():
+    """AUTO runs the specialized adjoint in one pass up to 128 terms and in
+    passes over a workspace above (the forward of a solution above 1024 terms
+    in two passes); a forced variant that cannot serve the call fails it."""
     small = amd.Terms.from_diagram(random_self_energy(4, (0, 4, 1)))
     large = amd.Terms.from_diagram(random_self_energy(5, (0, 5, 0)))
     huge = amd.Terms.from_diagram(random_self_energy(6, (5, 6, 0)))
     beta = 5.0
     w = torch.from_numpy(matsubara_freqs(1, beta)).to(DEV)
     gs = torch.ones(1, dtype=torch.complex128, device=DEV)
-    for T, want in ((small, "specialized"), (large, "packed self-energy order 5")):
+    for T, want in ((small, "specialized"), (large, "specialized passes")):
         E = torch.from_numpy(uniform_energies(100, T.info()["n_eps"], seed=29, a=3.0)).to(DEV)
         amd.evaluate_adjoint(T, E, w, beta, grad_sum=gs)
-        assert amd.last_variant().startswith(want), amd.last_variant()
+        assert amd.last_variant() == want, amd.last_variant()
     E = torch.from_numpy(uniform_energies(50, huge.info()["n_eps"], seed=30, a=3.0)).to(DEV)
-    # above 1024 terms the forward runs in two passes; the adjoint falls back
     amd.evaluate(huge, E, w, beta)
     assert amd.last_variant() == "specialized two-pass"
     amd.evaluate_adjoint(huge, E, w, beta, grad_sum=gs)
-    assert amd.last_variant().startswith("packed")
+    assert amd.last_variant() == "specialized passes"
     huge.set_variant(amd.VARIANT_SPECIALIZED)
     with pytest.raises(amd.AmiError):
         amd.evaluate_adjoint(huge, E, w, beta, grad_sum=gs)
     huge.set_variant(amd.VARIANT_TABLES)
     with pytest.raises(amd.AmiError):
         amd.evaluate_adjoint(huge, E, w, beta, grad_sum=gs)
+
+
+@pytest.mark.parametrize("order,seed", [(5, (0, 5, 0)), (6, (5, 6, 2))])
+def test_adjoint_passes_chunks_rows_and_values(order, seed):
+    """The adjoint in passes with the samples in several workspace chunks (a
+    ragged last one) and three frequency rows (the group-sum cotangents added
+    to the stored ones after the first row): gradients and the values it
+    returns on the way against the oracle, the same bits as one chunk, and
+    the same bits on a repeat."""
+    d = random_self_energy(order, seed)
+    beta = 5.0
+    n_e = 1100 if order == 5 else 300
+    Eh = uniform_energies(n_e, d.n_eps, seed=(31, order), a=3.0)
+    wh = np.concatenate([matsubara_freqs(2, beta), real_freqs(1, 0.9, 0.9, 0.05)])
+    terms = oracle_terms(d)
+    keep = far_from_poles(terms, d.n_int, Eh, wh)
+    Eh = np.ascontiguousarray(Eh[keep])
+    n_e = len(Eh)
+    cot = _cot(len(wh), n_e, 32)
+    cot_sum = np.array([0.2 - 0.1j, 0.3j, -0.4])
+    T = amd.Terms.from_diagram(d)
+    E = torch.from_numpy(Eh).to(DEV)
+    w = torch.from_numpy(wh).to(DEV)
+
+    def run():
+        out = torch.empty((len(wh), n_e), dtype=torch.complex128, device=DEV)
+        out_sum = torch.empty((len(wh),), dtype=torch.complex128, device=DEV)
+        g = amd.evaluate_adjoint(T, E, w, beta, grad_out=torch.from_numpy(cot).to(DEV),
+                                 grad_sum=torch.from_numpy(cot_sum).to(DEV), out=out, out_sum=out_sum)
+        torch.cuda.synchronize()
+        assert amd.last_variant() == "specialized passes"
+        return [x.cpu().numpy() for x in g] + [out.cpu().numpy(), out_sum.cpu().numpy()]
+
+    one = run()
+    cols = 2 * T.info()["G"] + 2 * d.n_eps
+    try:
+        amd.set_two_pass_chunk_bytes(max(1 << 16, 256 * 8 * cols * 2))   # chunks of 512 samples
+        many = run()
+        again = run()
+    finally:
+        amd.set_two_pass_chunk_bytes(256 << 20)
+    for a, b, c in zip(one, many, again):
+        assert np.array_equal(a, b) and np.array_equal(b, c)
+    g_e, g_b, g_w, out, out_sum = many
+    full = cot + cot_sum[:, None]
+    ref_e, ref_b, ref_w = gradients(terms, d.n_int, Eh, wh, beta, full)
+    sc = gradient_scales(terms, d.n_int, Eh, wh, beta, full)
+    assert np.max(np.abs(g_e - ref_e.astype(np.float64)) / np.maximum(sc["E"], 1e-300)) <= 1e-10
+    assert abs(float(g_b) - float(ref_b)) <= 1e-10 * sc["beta"]
+    assert np.max(np.abs(g_w - ref_w.astype(np.complex128))) <= 1e-10 * sc["w"]
+    ref, scale, dist = reference(d, Eh, wh, beta, terms=terms)
+    check(out, ref, scale, dist, label=f"passes values order {order}")
+    assert np.allclose(out_sum, out.sum(axis=1), rtol=1e-12, atol=1e-14 * float(scale.sum()))

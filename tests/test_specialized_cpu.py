@@ -22,7 +22,7 @@ amd = pytest.importorskip("paper_2311_17189_amd")
 HERE = os.path.dirname(os.path.abspath(__file__))
 
 
-def _harness(src: str, tmp_path, name: str) -> str:
+def _harness(src: str, tmp_path, name: str, driver: str = "jit_check.cpp") -> str:
     cxx = shutil.which("g++")
     if cxx is None:
         pytest.skip("no host C++ compiler")
@@ -33,7 +33,7 @@ def _harness(src: str, tmp_path, name: str) -> str:
     exe = str(tmp_path / name)
     subprocess.run([cxx, "-O1", "-std=c++17", "-ffp-contract=off",
                     "-I", os.path.join(HERE, "cpu_math", "shim"),
-                    f'-DAMI_GENERATED="{gen}"', os.path.join(HERE, "cpu_math", "jit_check.cpp"),
+                    f'-DAMI_GENERATED="{gen}"', os.path.join(HERE, "cpu_math", driver),
                     "-o", exe], check=True, capture_output=True, text=True)
     return exe
 
@@ -103,6 +103,62 @@ def test_generated_momentum_kernels_match_oracle(name, seed, tmp_path):
     E = energies_from_k(d.alpha, k, q, t, mu)
     ref, scale, dist = reference(d, E, w, beta)
     check(vals, ref, scale, dist, label=f"{name} momentum values")
+    dE, db, dw = gradients(terms, d.n_int, E, w, beta, cot)
+    dk, dmu, dt = momentum_gradients(d.alpha, k, q, t, mu, dE)
+    sc = gradient_scales(terms, d.n_int, E, w, beta, cot, hubbard=(d.alpha, k, q, t, mu))
+    assert np.max(np.abs(gk - dk.astype(np.float64)) / np.maximum(sc["k"], 1e-300)) <= 1e-10
+    for got, ref_, key in ((gb, db, "beta"), (gmu, dmu, "mu"), (gt, dt, "t")):
+        assert abs(got - float(ref_)) <= 1e-10 * sc[key], key
+    assert np.max(np.abs(gw - dw.astype(np.complex128))) <= 1e-10 * sc["w"]
+
+
+# the adjoint of large solutions in passes (its functions are in the two-pass
+# source of any solution): o4 52 terms, o5 196, o6 560
+PASS_CASES = [("o4", (0, 4, 1), 120), ("o5", (0, 5, 2), 80), ("o6", (0, 6, 0), 30)]
+
+
+@pytest.mark.parametrize("name,seed,n", PASS_CASES)
+def test_adjoint_passes_energy_input_match_oracle(name, seed, n, tmp_path):
+    d = random_self_energy(seed[1], seed)
+    T = amd.Terms.from_diagram(d)
+    src = T.source(momentum=False, two_pass=True)
+    assert "adj_freq_row" in src and "leaf_cotangents_ws" in src
+    exe = _harness(src, tmp_path, name + "p", "jit_check_adj_passes.cpp")
+    beta = 5.0
+    E = uniform_energies(n, d.n_eps, seed=(44, d.n_int), a=3.0)
+    w = np.concatenate([matsubara_freqs(2, beta), real_freqs(1, -0.3, -0.3, 0.05)])
+    terms = oracle_terms(d)
+    E = np.ascontiguousarray(E[far_from_poles(terms, d.n_int, E, w)])
+    rng = np.random.default_rng(45)
+    cot = rng.standard_normal((len(w), len(E))) + 1j * rng.standard_normal((len(w), len(E)))
+    vals, gE, gb, _, _, gw = _run(exe, d.n_eps, len(w), beta, 0.0, 1.0, 0.0, np.zeros(2), w[:, None], E, cot)
+    ref, scale, dist = reference(d, E, w, beta)
+    check(vals, ref, scale, dist, label=f"{name} values (passes)")
+    dE, db, dw = gradients(terms, d.n_int, E, w, beta, cot)
+    sc = gradient_scales(terms, d.n_int, E, w, beta, cot)
+    assert np.max(np.abs(gE - dE.astype(np.float64)) / np.maximum(sc["E"], 1e-300)) <= 1e-10
+    assert abs(gb - float(db)) <= 1e-10 * sc["beta"]
+    assert np.max(np.abs(gw - dw.astype(np.complex128))) <= 1e-10 * sc["w"]
+
+
+@pytest.mark.parametrize("name,seed,n", PASS_CASES)
+def test_adjoint_passes_momentum_input_match_oracle(name, seed, n, tmp_path):
+    d = random_self_energy(seed[1], seed)
+    T = amd.Terms.from_diagram(d)
+    exe = _harness(T.source(momentum=True, two_pass=True), tmp_path, name + "pk", "jit_check_adj_passes.cpp")
+    beta, t, mu = 5.0, 1.0, 0.1
+    q = np.array(DEFAULT_Q)
+    w = matsubara_freqs(1, beta)
+    k = k_samples(2 * n, d.n_int, seed=(46, d.n_int))
+    terms = oracle_terms(d)
+    keep = far_from_poles(terms, d.n_int, energies_from_k(d.alpha, k, q, t, mu), w)
+    k = np.ascontiguousarray(k[keep][:n])
+    rng = np.random.default_rng(47)
+    cot = rng.standard_normal((1, len(k))) + 1j * rng.standard_normal((1, len(k)))
+    vals, gk, gb, gmu, gt, gw = _run(exe, 2 * d.n_int, 1, beta, 0.0, t, mu, q, w[:, None], k, cot)
+    E = energies_from_k(d.alpha, k, q, t, mu)
+    ref, scale, dist = reference(d, E, w, beta)
+    check(vals, ref, scale, dist, label=f"{name} momentum values (passes)")
     dE, db, dw = gradients(terms, d.n_int, E, w, beta, cot)
     dk, dmu, dt = momentum_gradients(d.alpha, k, q, t, mu, dE)
     sc = gradient_scales(terms, d.n_int, E, w, beta, cot, hubbard=(d.alpha, k, q, t, mu))
