@@ -340,9 +340,14 @@ std::string idx(const char *a, int i) { return std::string(a) + "[" + std::to_st
 
 // Groups per chunk of the adjoint's frequency pass for large solutions (the
 // cotangents of a chunk's denominators are gathered in registers).
-constexpr int kAdjChunkGroups = 4;
-// Groups of the leaf pass's reverse sweep between scheduling fences.
-constexpr int kAdjLeafFenceGroups = 4;
+constexpr int kAdjChunkGroups = 2;
+// Whether each chunk forms the reciprocals of its own denominators (else all
+// of them are formed once per frequency row and held through the chunks).
+constexpr bool kAdjChunkOwnDens = true;
+// Terms per nested part of a group in the adjoint's leaf pass, and parts
+// between scheduling fences.
+constexpr int kAdjLeafPartTerms = 32;
+constexpr int kAdjLeafFenceParts = 1;
 
 }  // namespace
 
@@ -764,14 +769,17 @@ std::string jit_source(const AmiTerms *t, bool hub, int kernels) {
         // Re(conj(c) R_g) (stored; added to the stored value after the first
         // row) and u_g = -FT_g conj(c) R_g summed per denominator of the
         // chunk, then per such denominator the scatter of U_k rho_k
-        o << "__device__ __forceinline__ void adj_freq_row(const double (&E)[NE], const double (&wr)[" << NXA
-          << "], const double (&wi)[" << NXA << "], double cr, double ci, double *ws, int64_t ld, uint32_t off, "
-             "bool first, double &acc_re, double &acc_im, double (&gE)[NE], double (&gwr)["
+        // FIRST: the first frequency row (FTB_g stored, not added to the stored value)
+        o << "template <bool FIRST>\n__device__ __forceinline__ void adj_freq_row(const double (&E)[NE], const double (&wr)["
+          << NXA << "], const double (&wi)[" << NXA << "], double cr, double ci, double *ws, int64_t ld, uint32_t off, "
+             "double &acc_re, double &acc_im, double (&gE)[NE], double (&gwr)["
           << NXA << "], double (&gwi)[" << NXA << "]) {\n";
-        o << "  double xr[D], xi[D];\n  { double dr[D], di[D];\n    den_args(E, wr, wi, dr, di);\n"
-             "#pragma unroll\n    for (int k = 0; k < D; ++k) {\n"
-             "      const double inv = ami::rcp_nr(fma(dr[k], dr[k], di[k] * di[k]));\n"
-             "      xr[k] = dr[k] * inv;\n      xi[k] = -di[k] * inv;\n    } }\n";
+        const bool own = kAdjChunkOwnDens;
+        if (!own)
+            o << "  double xr[D], xi[D];\n  { double dr[D], di[D];\n    den_args(E, wr, wi, dr, di);\n"
+                 "#pragma unroll\n    for (int k = 0; k < D; ++k) {\n"
+                 "      const double inv = ami::rcp_nr(fma(dr[k], dr[k], di[k] * di[k]));\n"
+                 "      xr[k] = dr[k] * inv;\n      xi[k] = -di[k] * inv;\n    } }\n";
         for (int g0 = 0; g0 < G; g0 += kAdjChunkGroups) {
             const int g1 = std::min(G, g0 + kAdjChunkGroups);
             std::vector<int> ks;
@@ -780,6 +788,22 @@ std::string jit_source(const AmiTerms *t, bool hub, int kernels) {
             std::sort(ks.begin(), ks.end());
             ks.erase(std::unique(ks.begin(), ks.end()), ks.end());
             o << "  {\n";
+            if (own) {
+                // the chunk's own reciprocals
+                o << "    double xr[D], xi[D];\n";
+                for (int k : ks) {
+                    Lin re, im;
+                    for (int i = 0; i < ne; ++i) re.add(tb.den_coef[static_cast<size_t>(k) * nc + i], idx("E", i));
+                    for (int x = 0; x < nx; ++x) {
+                        const double a = tb.den_coef[static_cast<size_t>(k) * nc + ne + x];
+                        re.add(a, idx("wr", x));
+                        im.add(a, idx("wi", x));
+                    }
+                    o << "    { const double dr = " << re.str() << ", di = " << im.str()
+                      << ";\n      const double inv = ami::rcp_nr(fma(dr, dr, di * di));\n      xr[" << k
+                      << "] = dr * inv;\n      xi[" << k << "] = -di * inv; }\n";
+                }
+            }
             for (int k : ks) o << "    double Ur" << k << " = 0.0, Ui" << k << " = 0.0;\n";
             for (int g = g0; g < g1; ++g) {
                 o << "    { const double ft = ami::ws_load(ws, ld, " << g << ", off);\n";
@@ -794,8 +818,9 @@ std::string jit_source(const AmiTerms *t, bool hub, int kernels) {
                 o << "      (void)nr;\n";
                 o << "      acc_re = fma(ft, rr, acc_re);\n      acc_im = fma(ft, ri, acc_im);\n";
                 o << "      const double tb = fma(cr, rr, ci * ri);\n";
-                o << "      ami::ws_store(ws, ld, " << ftb0 << " + " << g << ", off, first ? tb : ami::ws_load(ws, ld, "
-                  << ftb0 << " + " << g << ", off) + tb);\n";
+                o << "      if constexpr (FIRST) ami::ws_store(ws, ld, " << ftb0 << " + " << g << ", off, tb);\n"
+                  << "      else ami::ws_store(ws, ld, " << ftb0 << " + " << g << ", off, ami::ws_load(ws, ld, " << ftb0
+                  << " + " << g << ", off) + tb);\n";
                 o << "      const double qr = ft * cr, qi = -ft * ci;\n";
                 o << "      const double ur = -fma(qr, rr, -qi * ri), ui = -fma(qr, ri, qi * rr);\n";
                 for (int j = gbegin(g); j < gend(g); ++j) {
@@ -830,52 +855,108 @@ std::string jit_source(const AmiTerms *t, bool hub, int kernels) {
         // leaf pass: FB_l = sum_g FTB_g dFT_g/dF_l by a reverse sweep of each
         // group's nested sum (the nodes recomputed, then their cotangents in
         // reverse order: node h = F_a w + u passes h' w to F_a, h' F_a to w and
-        // h' to u)
-        o << "__device__ __forceinline__ void leaf_cotangents_ws(const double (&F)[L], const double *ws, int64_t ld, "
-             "uint32_t off, double (&FB)[L]) {\n";
-        o << kReverseContract;
-        leaf_prefix = "F[";
-        leaf_suffix = "]";
-        for (int g = 0; g < G; ++g) {
-            std::vector<HornerTerm> ts;
-            for (int ti = tb.group_start[g]; ti < tb.group_start[g + 1]; ++ti) {
-                HornerTerm h{tb.term_sign[ti], {}};
-                for (int j = 0; j < ni; ++j) h.leaves.push_back(tb.term_leaf[static_cast<size_t>(ti) * ni + j]);
-                ts.push_back(std::move(h));
-            }
+        // h' to u).  A group's terms are nested in parts of at most
+        // kAdjLeafPartTerms (consecutive in canonical order), which bounds the
+        // node values live in a sweep; each leaf is formed just before the
+        // first part that reads it and its cotangent is scattered to the
+        // energies and to beta just after the last one.
+        struct Part {
+            int g;
             std::vector<HNode> nodes;
-            const HRef v = horner_build(std::move(ts), nodes);
-            o << "  { const double tb = ami::ws_load(ws, ld, " << ftb0 << " + " << g << ", off);\n";
-            horner_emit(nodes, leaf_name, o);
-            const size_t nn = nodes.size();
+            HRef root;
+            std::vector<int> leaves;
+        };
+        std::vector<Part> parts;
+        for (int g = 0; g < G; ++g) {
+            for (int t0 = tb.group_start[g]; t0 < tb.group_start[g + 1]; t0 += kAdjLeafPartTerms) {
+                const int t1 = std::min(tb.group_start[g + 1], t0 + kAdjLeafPartTerms);
+                std::vector<HornerTerm> ts;
+                for (int ti = t0; ti < t1; ++ti) {
+                    HornerTerm h{tb.term_sign[ti], {}};
+                    for (int j = 0; j < ni; ++j) h.leaves.push_back(tb.term_leaf[static_cast<size_t>(ti) * ni + j]);
+                    ts.push_back(std::move(h));
+                }
+                Part pt;
+                pt.g = g;
+                pt.root = horner_build(std::move(ts), pt.nodes);
+                std::vector<int> used;
+                auto note = [&](const HRef &r) {
+                    if (r.kind == HRef::LEAF) used.push_back(r.idx);
+                };
+                note(pt.root);
+                for (const HNode &n : pt.nodes) {
+                    used.push_back(n.a);
+                    note(n.w);
+                    note(n.u);
+                }
+                std::sort(used.begin(), used.end());
+                used.erase(std::unique(used.begin(), used.end()), used.end());
+                pt.leaves = used;
+                parts.push_back(std::move(pt));
+            }
+        }
+        std::vector<int> first_use(static_cast<size_t>(L), -1), last_use(static_cast<size_t>(L), -1);
+        for (size_t p = 0; p < parts.size(); ++p)
+            for (int l : parts[p].leaves) {
+                if (first_use[l] < 0) first_use[l] = static_cast<int>(p);
+                last_use[l] = static_cast<int>(p);
+            }
+        o << "__device__ __forceinline__ void leaf_pass(const double (&E)[NE], double beta, double e_reg, const double "
+             "*ws, int64_t ld, uint32_t off, double (&gE)[NE], double &gbeta) {\n";
+        o << kReverseContract;
+        o << "  (void)e_reg;\n";
+        for (int l = 0; l < L; ++l) o << "  double F" << l << ", FB" << l << ", DV" << l << ";\n";
+        auto leaf_arg = [&](int l) {
+            Lin x;
+            for (int i = 0; i < ne; ++i) x.add(tb.leaf_coef[static_cast<size_t>(l) * ne + i], idx("E", i));
+            return x.str() + (tb.leaf_sigma[l] < 0 ? " + e_reg" : "");
+        };
+        auto fname = [](int l) { return "F" + std::to_string(l); };
+        for (size_t p = 0; p < parts.size(); ++p) {
+            const Part &pt = parts[p];
+            for (int l : pt.leaves) {
+                if (first_use[l] != static_cast<int>(p)) continue;
+                o << "  ami::leaf_and_slope(" << (tb.leaf_sigma[l] < 0 ? "true" : "false") << ", beta * ("
+                  << leaf_arg(l) << "), F" << l << ", DV" << l << ");\n  FB" << l << " = 0.0;\n";
+            }
+            o << "  { const double tb = ami::ws_load(ws, ld, " << ftb0 << " + " << pt.g << ", off);\n";
+            horner_emit(pt.nodes, fname, o);
+            const size_t nn = pt.nodes.size();
             for (size_t k = 0; k < nn; ++k) o << "    double hb" << k << " = 0.0;\n";
             // a cotangent c passed to reference r: hb += c (node) or FB += c (leaf)
             auto pass = [&](const HRef &r, const std::string &c) {
-                if (r.kind == HRef::NODE) {
-                    o << "    hb" << r.idx << (r.neg ? " -= " : " += ") << c << ";\n";
-                } else if (r.kind == HRef::LEAF) {
-                    o << "    FB[" << r.idx << "]" << (r.neg ? " -= " : " += ") << c << ";\n";
-                }
+                if (r.kind == HRef::NODE) o << "    hb" << r.idx << (r.neg ? " -= " : " += ") << c << ";\n";
+                else if (r.kind == HRef::LEAF) o << "    FB" << r.idx << (r.neg ? " -= " : " += ") << c << ";\n";
             };
-            pass(v, "tb");
+            pass(pt.root, "tb");
             for (size_t kk = nn; kk-- > 0;) {
-                const HNode &n = nodes[kk];
-                const std::string hb = "hb" + std::to_string(kk), fa = "F[" + std::to_string(n.a) + "]";
-                // to F_a: hb * w
+                const HNode &n = pt.nodes[kk];
+                const std::string hb = "hb" + std::to_string(kk), fa = fname(n.a), fb = "FB" + std::to_string(n.a);
                 if (n.w.kind == HRef::CONST) {
-                    if (n.w.c == 1.0) o << "    FB[" << n.a << "] += " << hb << ";\n";
-                    else if (n.w.c == -1.0) o << "    FB[" << n.a << "] -= " << hb << ";\n";
-                    else o << "    FB[" << n.a << "] = fma(" << num(n.w.c) << ", " << hb << ", FB[" << n.a << "]);\n";
+                    if (n.w.c == 1.0) o << "    " << fb << " += " << hb << ";\n";
+                    else if (n.w.c == -1.0) o << "    " << fb << " -= " << hb << ";\n";
+                    else o << "    " << fb << " = fma(" << num(n.w.c) << ", " << hb << ", " << fb << ");\n";
                 } else {
-                    const std::string wn = href_name(n.w, leaf_name);
-                    o << "    FB[" << n.a << "] = fma(" << (n.w.neg ? "-" : "") << wn << ", " << hb << ", FB[" << n.a
-                      << "]);\n";
+                    const std::string wn = href_name(n.w, fname);
+                    o << "    " << fb << " = fma(" << (n.w.neg ? "-" : "") << wn << ", " << hb << ", " << fb << ");\n";
                     pass(n.w, fa + " * " + hb);
                 }
                 pass(n.u, hb);
             }
             o << "  }\n";
-            if ((g + 1) % kAdjLeafFenceGroups == 0 && g + 1 < G) o << "  AMI_SCHED_FENCE();\n";
+            for (int l : pt.leaves) {
+                if (last_use[l] != static_cast<int>(p)) continue;
+                o << "  { const double fb = FB" << l << " * DV" << l << ";\n    gbeta = fma(fb, " << leaf_arg(l)
+                  << ", gbeta);\n    const double v = fb * beta;\n";
+                for (int i = 0; i < ne; ++i) {
+                    const double c = tb.leaf_coef[static_cast<size_t>(l) * ne + i];
+                    if (c == 1.0) o << "    gE[" << i << "] += v;\n";
+                    else if (c == -1.0) o << "    gE[" << i << "] -= v;\n";
+                    else if (c != 0.0) o << "    gE[" << i << "] = fma(" << num(c) << ", v, gE[" << i << "]);\n";
+                }
+                o << "  }\n";
+            }
+            if ((p + 1) % kAdjLeafFenceParts == 0 && p + 1 < parts.size()) o << "  AMI_SCHED_FENCE();\n";
         }
         o << "}\n";
     }

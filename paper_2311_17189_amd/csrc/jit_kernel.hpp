@@ -260,31 +260,19 @@ __device__ __forceinline__ void fwd_tile(const KArgs &a, int64_t tile) {
 #endif
 
 #if AMI_JIT_KERNELS & (2 | 128)
-// The end of the adjoint of one sample once its leaf cotangents FB are known:
-// the leaves' derivatives (f'(y) from Dv or the park area) scattered to the
-// energies and to beta, on the momentum input the chain rule through
+// The gradients of one sample once its energies' cotangent gE and its dL/dbeta
+// contribution are complete: on the momentum input the chain rule through
 // dE_j/dK_j = -2t sin K_j to the momenta (the trig values parked by
 // energies<HUB, true>), the per-sample gradient rows (staged through the park
 // area when they fit), and the wave sums of dL/dbeta, dL/dmu, dL/dt at the
 // partial-sum row gp.  s_blk: the block's first sample; s_end: one past the
-// last sample the launch writes; gE holds the energies' cotangent so far.
+// last sample the launch writes.
 template <bool HUB>
-__device__ __forceinline__ void adj_leaf_end(const KArgs &a, int64_t s_blk, int64_t s_end, bool active, double *gp,
-                                             double *park, const double (&E)[NE], const double (&Dv)[kParkDv ? 1 : L],
-                                             const double (&FB)[L], double (&gE)[NE]) {
+__device__ __forceinline__ void adj_grad_end(const KArgs &a, int64_t s_blk, int64_t s_end, bool active, double *gp,
+                                             double *park, double (&gE)[NE], double gbeta) {
 #pragma clang fp contract(fast)
     const int tid = threadIdx.x, B = blockDim.x, lane = tid & 63;
     const int64_t s = s_blk + tid;
-    double gbeta = 0.0, v[L], x[L];
-    leaf_args(E, x);
-#pragma unroll
-    for (int l = 0; l < L; ++l) {
-        if (kBose[l]) x[l] += a.e_reg;
-        const double fb = FB[l] * (kParkDv ? park[(kParkChain + l) * B + tid] : Dv[kParkDv ? 0 : l]);
-        v[l] = fb * a.beta;
-        gbeta = fma(fb, x[l], gbeta);
-    }
-    leaf_scatter(v, gE);
 
     double gmu = 0.0, gt = 0.0;
     if constexpr (HUB) {
@@ -349,6 +337,29 @@ __device__ __forceinline__ void adj_leaf_end(const KArgs &a, int64_t s_blk, int6
     }
     ami::wave_store4(active ? gbeta : 0.0, active ? gmu : 0.0, active ? gt : 0.0, 0.0, lane, gp, gp + a.nrows,
                      gp + 2 * a.nrows, nullptr);
+}
+
+// The end of the adjoint of one sample once its leaf cotangents FB are known:
+// the leaves' derivatives (f'(y) from Dv or the park area) scattered to the
+// energies and to beta, then adj_grad_end.  gE holds the energies' cotangent
+// so far.
+template <bool HUB>
+__device__ __forceinline__ void adj_leaf_end(const KArgs &a, int64_t s_blk, int64_t s_end, bool active, double *gp,
+                                             double *park, const double (&E)[NE], const double (&Dv)[kParkDv ? 1 : L],
+                                             const double (&FB)[L], double (&gE)[NE]) {
+#pragma clang fp contract(fast)
+    const int tid = threadIdx.x, B = blockDim.x;
+    double gbeta = 0.0, v[L], x[L];
+    leaf_args(E, x);
+#pragma unroll
+    for (int l = 0; l < L; ++l) {
+        if (kBose[l]) x[l] += a.e_reg;
+        const double fb = FB[l] * (kParkDv ? park[(kParkChain + l) * B + tid] : Dv[kParkDv ? 0 : l]);
+        v[l] = fb * a.beta;
+        gbeta = fma(fb, x[l], gbeta);
+    }
+    leaf_scatter(v, gE);
+    adj_grad_end<HUB>(a, s_blk, s_end, active, gp, park, gE, gbeta);
 }
 #endif
 
@@ -656,7 +667,8 @@ __device__ __forceinline__ void adjf_tile(const KArgs &a, int64_t tile) {
         // loop and held (64-bit per lane and column) through it
         uint32_t off_f = off;
         AMI_OPAQUE(off_f);
-        adj_freq_row(E, wr, wi, cr, ci, a.work, a.ld, off_f, f == 0, acc_re, acc_im, gE, gwr, gwi);
+        if (f == 0) adj_freq_row<true>(E, wr, wi, cr, ci, a.work, a.ld, off_f, acc_re, acc_im, gE, gwr, gwi);
+        else adj_freq_row<false>(E, wr, wi, cr, ci, a.work, a.ld, off_f, acc_re, acc_im, gE, gwr, gwi);
         if (active && a.out) {
             double2 v;
             v.x = acc_re;
@@ -694,10 +706,11 @@ __device__ __forceinline__ void adjf_tile(const KArgs &a, int64_t tile) {
 #if AMI_JIT_KERNELS & 128
 // Adjoint of a large solution, leaf pass (after the frequency pass): one lane
 // per sample of the chunk.  The energies again from the sample's inputs (on
-// the momentum input with the chain rule's trig values parked), the leaves
-// and their derivatives, the leaf cotangents by the reverse sweep of every
-// group's nested sum against the stored FTB_g, then the end of the one-pass
-// adjoint (adj_leaf_end) on the stored energy cotangents of the denominators.
+// the momentum input with the chain rule's trig values parked), then the
+// generated leaf_pass (leaves, their cotangents by the reverse sweep of every
+// group's nested sum against the stored FTB_g, their scatter to the energies
+// and beta) on the stored energy cotangents of the denominators, then the end
+// of the one-pass adjoint (adj_grad_end).
 template <bool HUB>
 __device__ __forceinline__ void adjl_tile(const KArgs &a, int64_t tile, double *park) {
     const int tid = threadIdx.x, B = blockDim.x;
@@ -709,26 +722,11 @@ __device__ __forceinline__ void adjl_tile(const KArgs &a, int64_t tile, double *
     load_inputs<HUB>(a, a.s0 + (active ? i : a.n_chunk - 1), in);
     double E[NE];
     energies<HUB, HUB>(a, in, E, park);
-    double F[L], Dv[kParkDv ? 1 : L];
-    {
-        double x[L];
-        leaf_args(E, x);
-#pragma unroll
-        for (int l = 0; l < L; ++l) {
-            if (kBose[l]) x[l] += a.e_reg;
-            double dv;                          // f'(y) = -f(y) f(-y)
-            ami::leaf_and_slope(kBose[l], a.beta * x[l], F[l], dv);
-            if constexpr (kParkDv) park[(kParkChain + l) * B + tid] = dv;
-            else Dv[kParkDv ? 0 : l] = dv;
-        }
-    }
-    double FB[L], gE[NE];
-#pragma unroll
-    for (int l = 0; l < L; ++l) FB[l] = 0.0;
-    leaf_cotangents_ws(F, a.work, a.ld, off, FB);
+    double gE[NE], gbeta = 0.0;
 #pragma unroll
     for (int j = 0; j < NE; ++j) gE[j] = ami::ws_load(a.work, a.ld, G + NE + j, off);
-    adj_leaf_end<HUB>(a, a.s0 + tile * B, a.s0 + a.n_chunk, active, a.gpartial + row, park, E, Dv, FB, gE);
+    leaf_pass(E, a.beta, a.e_reg, a.work, a.ld, off, gE, gbeta);
+    adj_grad_end<HUB>(a, a.s0 + tile * B, a.s0 + a.n_chunk, active, a.gpartial + row, park, gE, gbeta);
 }
 #endif
 

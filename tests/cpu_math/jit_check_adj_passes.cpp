@@ -1,8 +1,8 @@
 // Host check of the generated part of the adjoint of large solutions in
 // passes: the two-pass forward's group_sums_store (first pass), then per
 // frequency row adj_freq_row (values, group-sum cotangents, the
-// denominators' scatter; second pass), then leaf_cotangents_ws and the
-// leaves' and lines' scatters (third pass), compiled with a host compiler and
+// denominators' scatter; second pass), then leaf_pass and the lines' scatter
+// (third pass), compiled with a host compiler and
 // driven one sample at a time through the kernels' steps with a one-sample
 // workspace (ld = 1), so a test can compare values and gradients with the
 // oracle.  The generated source is included through AMI_GENERATED without its
@@ -93,7 +93,8 @@ int main() {
                 wi[xx] = wim[f * NXA + xx];
             }
             double acc_re = 0.0, acc_im = 0.0;
-            adj_freq_row(E, wr, wi, cre[f], cim[f], ws.data(), 1, 0u, f == 0, acc_re, acc_im, gE, gwr, gwi);
+            if (f == 0) adj_freq_row<true>(E, wr, wi, cre[f], cim[f], ws.data(), 1, 0u, acc_re, acc_im, gE, gwr, gwi);
+            else adj_freq_row<false>(E, wr, wi, cre[f], cim[f], ws.data(), 1, 0u, acc_re, acc_im, gE, gwr, gwi);
             std::printf("%.17g %.17g ", acc_re, acc_im);
             for (int xx = 0; xx < NX; ++xx) {
                 gw[2 * (f * NXA + xx)] = gwr[xx];
@@ -101,15 +102,9 @@ int main() {
             }
         }
         for (int j = 0; j < NE; ++j) ws[G + NE + j] = gE[j];
-        double FB[L] = {0.0}, v[L], gbeta = 0.0;
-        leaf_cotangents_ws(F, ws.data(), 1, 0u, FB);
+        double gbeta = 0.0;
         for (int j = 0; j < NE; ++j) gE[j] = ws[G + NE + j];
-        for (int l = 0; l < L; ++l) {
-            const double fb = FB[l] * Dv[l];
-            v[l] = fb * beta;
-            gbeta = std::fma(fb, x[l], gbeta);
-        }
-        leaf_scatter(v, gE);
+        leaf_pass(E, beta, e_reg, ws.data(), 1, 0u, gE, gbeta);
         double gmu = 0.0, gt = 0.0;
         if (AMI_JIT_HUB) {
             double gx[NGA], gy[NGA], gkx[NIA] = {0.0}, gky[NIA] = {0.0};
