@@ -54,6 +54,8 @@ def parse():
     ap.add_argument("--no-batch", action="store_true",
                     help="skip the persistent mixed-diagram batch section")
     ap.add_argument("--batch-n-e", type=int, default=200_000)
+    ap.add_argument("--no-configs", action="store_true",
+                    help="skip the other workloads (C1-C3, large solutions)")
     ap.add_argument("--copy-mib", type=int, default=0,
                     help="first copy a buffer of this many MiB device to device (a plain copy "
                          "kernel of known size, to scale hardware byte counters)")
@@ -61,37 +63,58 @@ def parse():
 
 
 def cpu_baseline(d, k_all, q, beta, t, mu, w, target_s):
-    """The oracle, as it stands, on the step's work for a bounded slice of the
-    same samples: values (its float64 mode) and the gradients of the summed
-    integrand (its analytic gradients, long double, with the momentum chain
-    rule), with a process pool over the host cores this process may use."""
-    import numpy as np
-    from concurrent.futures import ProcessPoolExecutor
-
+    """The oracle, as it stands, on bounded slices of the same samples, over
+    the host cores this process may use (a process pool, capped at 16):
+    float64 values (its plain evaluation of the flat terms, energies from
+    momenta) on all cores -- the reported value -- and on one core, and the
+    whole step (float64 values and the analytic gradients of the summed
+    integrand with the momentum chain rule, in long double) on all cores.
+    Each timing takes about target_s / 3 seconds."""
     from oracle.construct import canonical, construct
     terms = canonical(construct(d.alpha, d.eps, d.n_int, d.fermionic))
     cores = min(len(os.sched_getaffinity(0)), 16)
-    # calibrate on one chunk in this process
+    each = target_s / 3.0
     chunk = 1000
-    t0 = time.perf_counter()
-    _oracle_chunk((terms, d, k_all[:chunk], q, beta, t, mu, w))
-    dt = time.perf_counter() - t0
-    per_sample = dt / chunk
-    n = int(min(len(k_all), max(chunk, target_s * cores / per_sample)))
-    n = (n // chunk) * chunk
-    jobs = [(terms, d, k_all[i:i + chunk], q, beta, t, mu, w) for i in range(0, n, chunk)]
-    t0 = time.perf_counter()
-    with ProcessPoolExecutor(max_workers=cores) as ex:
-        list(ex.map(_oracle_chunk, jobs))
-    el = time.perf_counter() - t0
-    return {"value": len(terms) * n * len(w) / el, "unit": "term-evals/s", "cores": cores,
-            "kind": "oracle",
-            "sample": f"first {n} of the same momentum samples: values (float64) and gradients "
-                      f"of the summed integrand w.r.t. k, mu, t, beta, w (long double), "
-                      f"{len(jobs)} chunks of {chunk} over {cores} processes, {el:.1f} s"}
+    out = {}
+    for key, fn, n_proc in (("values_f64", _oracle_values, cores), ("values_f64_1core", _oracle_values, 1),
+                            ("step", _oracle_step, cores)):
+        t0 = time.perf_counter()                     # calibrate on one chunk in this process
+        fn((terms, d, k_all[:chunk], q, beta, t, mu, w))
+        per_sample = (time.perf_counter() - t0) / chunk
+        n = int(min(len(k_all), max(chunk, each * n_proc / per_sample)))
+        n = (n // chunk) * chunk
+        jobs = [(terms, d, k_all[i:i + chunk], q, beta, t, mu, w) for i in range(0, n, chunk)]
+        t0 = time.perf_counter()
+        if n_proc > 1:
+            from concurrent.futures import ProcessPoolExecutor
+            with ProcessPoolExecutor(max_workers=n_proc) as ex:
+                list(ex.map(fn, jobs))
+        else:
+            for j in jobs:
+                fn(j)
+        el = time.perf_counter() - t0
+        out[key] = {"term_evals_per_s": len(terms) * n * len(w) / el, "samples": n, "processes": n_proc,
+                    "seconds": el}
+    v = out["values_f64"]
+    return {"value": v["term_evals_per_s"], "unit": "term-evals/s", "cores": cores, "kind": "oracle",
+            "sample": f"first {v['samples']} of the same momentum samples, float64 values of the flat terms "
+                      f"(energies from momenta), {v['samples'] // chunk} chunks of {chunk} over {cores} "
+                      f"processes, {v['seconds']:.1f} s",
+            "values_f64_1core": out["values_f64_1core"],
+            "step_values_and_gradients": dict(out["step"], note="float64 values and long-double analytic "
+                                                                "gradients w.r.t. k, mu, t, beta, w")}
 
 
-def _oracle_chunk(args):
+def _oracle_values(args):
+    import numpy as np
+
+    from oracle.evaluate import energies_from_k, evaluate_terms
+    terms, d, k, q, beta, t, mu, w = args
+    E = energies_from_k(d.alpha, k, q, t, mu, dtype=np.float64)
+    return evaluate_terms(terms, d.n_int, E, w, beta, dtype=np.float64).sum(axis=1)
+
+
+def _oracle_step(args):
     import numpy as np
 
     from oracle.evaluate import energies_from_k, evaluate_terms, gradients, momentum_gradients
@@ -256,6 +279,136 @@ def _timed_kernel(torch, amd, stream, fn, reps):
     torch.cuda.synchronize()
     ks = amd.kernel_timer_stop()
     return e0.elapsed_time(e1) / reps, sum(ks) / len(ks)
+
+
+def _median_ms(torch, stream, fn, reps=25):
+    """Median over `reps` calls, each bracketed by its own pair of stream
+    events, after the warm-up of _warm; also the minimum."""
+    _warm(torch, fn)
+    ts = []
+    for _ in range(reps):
+        a0 = torch.cuda.Event(enable_timing=True)
+        a1 = torch.cuda.Event(enable_timing=True)
+        a0.record(stream)
+        fn()
+        a1.record(stream)
+        a1.synchronize()
+        ts.append(a0.elapsed_time(a1))
+    ts.sort()
+    return ts[len(ts) // 2], ts[0]
+
+
+def configs_section(args, torch, dev, stream):
+    """The workloads beside the headline one, each timed as the median of 25
+    individually timed calls: C1, the order-2 self-energy of Sec. 5.1.1 at
+    10^4 k-samples (a latency); C2, seeded order-3 and order-4 topologies at
+    beta = 2, 5, 10 and 10^6 k-samples (forward, and the value-and-gradient
+    step); C3, an order-4 topology on the 256-point real-frequency grid
+    omega + 0.05i, omega in [-6, 6], at 10^6 k-samples (out is 4.1 GB: HBM
+    rate and FP64 fraction); and the adjoint of large solutions in passes
+    (order 5 and order 6 at 2 10^5 k-samples, one Matsubara frequency)."""
+    import numpy as np
+
+    import paper_2311_17189_amd as amd
+    from ami_inputs import DEFAULT_Q, k_samples, matsubara_freqs, order2_example, random_self_energy, real_freqs
+    from paper_2311_17189_amd import roofline as rl
+
+    q = np.array(DEFAULT_Q)
+    res = {}
+
+    def prepare(d, n_e, seed, freqs):
+        T = amd.Terms.from_diagram(d)
+        T.upload()
+        T.specialize(momentum=True)
+        st = rl.structure_from_canonical(T.canonical())
+        k = torch.from_numpy(k_samples(n_e, d.n_int, seed=seed)).to(dev)
+        w = torch.from_numpy(freqs).to(dev)
+        n_f = w.shape[0]
+        out = torch.empty((n_f, n_e), dtype=torch.complex128, device=dev)
+        osum = torch.empty((n_f,), dtype=torch.complex128, device=dev)
+        gs = torch.ones((n_f,), dtype=torch.complex128, device=dev)
+        return T, st, k, w, out, osum, gs
+
+    def fwd_and_step(d, n_e, seed, beta, freqs, with_step=True):
+        T, st, k, w, out, osum, gs = prepare(d, n_e, seed, freqs)
+        n_f = w.shape[0]
+        te = float(st.T) * n_e * n_f
+        fwd = lambda: amd.evaluate_hubbard(T, k, q, 1.0, 0.0, w, beta, want_sum=True, out=out, out_sum=osum,
+                                           stream=stream)
+        f_med, f_min = _median_ms(torch, stream, fwd)
+        fv = amd.last_variant()
+        ffl = rl.specialized_forward_flops(st, n_e, n_f, d.alpha)["total"]
+        row = {"terms": st.T, "n_e": n_e, "n_f": n_f, "beta": beta,
+               "fwd_ms_median": f_med, "fwd_ms_min": f_min, "fwd_kernel": fv,
+               "fwd_term_evals_per_s": te / (f_med * 1e-3),
+               "fwd_frac_fp64_peak": ffl / (f_med * 1e-3) / rl.PEAK_FP64_VECTOR}
+        if with_step:
+            g = [None]
+
+            def step():
+                g[0] = amd.evaluate_hubbard_adjoint(T, k, q, 1.0, 0.0, w, beta, grad_sum=gs, out=out,
+                                                    out_sum=osum, stream=stream, grads=g[0])
+            s_med, s_min = _median_ms(torch, stream, step)
+            sfl = rl.specialized_adjoint_flops(st, n_e, n_f, d.alpha, with_values=True)["total"]
+            row.update({"step_ms_median": s_med, "step_ms_min": s_min, "step_kernel": amd.last_variant(),
+                        "step_term_evals_per_s": te / (s_med * 1e-3),
+                        "step_frac_fp64_peak": sfl / (s_med * 1e-3) / rl.PEAK_FP64_VECTOR})
+        return row
+
+    # C1: latency of the order-2 example
+    try:
+        d = order2_example()
+        res["C1_order2_latency"] = fwd_and_step(d, 10_000, (110, 2, 0), 5.0, matsubara_freqs(1, 5.0))
+        res["C1_order2_latency"]["workload"] = ("order-2 self-energy (R0 of Sec. 5.1.1), 10^4 k-samples, beta=5, "
+                                                "i pi/beta; times are latencies (launch-bound)")
+    except amd.AmiError as e:
+        res["C1_order2_latency"] = f"not run: {e}"
+    # C2: orders 3 and 4, two topologies each, three temperatures
+    c2 = []
+    for order, i in ((3, 0), (3, 1), (4, 1), (4, 3)):
+        d = random_self_energy(order, (0, order, i))
+        for beta in (2.0, 5.0, 10.0):
+            try:
+                row = fwd_and_step(d, 1_000_000, (111, order, i), beta, matsubara_freqs(1, beta))
+                row.update({"order": order, "topology": [0, order, i]})
+                c2.append(row)
+            except amd.AmiError as e:
+                c2.append({"order": order, "topology": [0, order, i], "beta": beta, "error": str(e)})
+    res["C2_orders3_4_betas"] = c2
+    # C3: the real-frequency grid, forward (out is 256 x 10^6 complex128)
+    try:
+        d = random_self_energy(4, (0, 4, 1))
+        n_e, beta = 1_000_000, 5.0
+        wr = real_freqs(256, -6.0, 6.0, 0.05)
+        T, st, k, w, out, osum, _ = prepare(d, n_e, (112, 4, 1), wr)
+        fwd = lambda: amd.evaluate_hubbard(T, k, q, 1.0, 0.0, w, beta, want_sum=True, out=out, out_sum=osum,
+                                           stream=stream)
+        f_med, f_min = _median_ms(torch, stream, fwd, reps=21)
+        nbytes = n_e * 2 * d.n_int * 8 + 256 * n_e * 16 + 256 * 16
+        fl = rl.specialized_forward_flops(st, n_e, 256, d.alpha)["total"]
+        res["C3_real_frequency_grid"] = {
+            "workload": "order-4 topology (0, 4, 1), 10^6 k-samples, 256 real frequencies omega + 0.05i, "
+                        "omega in [-6, 6], beta=5, out [256, 10^6] complex128 (4.1 GB) + row sums",
+            "kernel": amd.last_variant(), "ms_median": f_med, "ms_min": f_min,
+            "term_evals_per_s": float(st.T) * n_e * 256 / (f_med * 1e-3),
+            "algorithmic_bytes": nbytes, "hbm_gb_per_s": nbytes / (f_med * 1e-3) / 1e9,
+            "frac_hbm_peak": nbytes / (f_med * 1e-3) / rl.PEAK_HBM,
+            "flops": fl, "frac_fp64_peak": fl / (f_med * 1e-3) / rl.PEAK_FP64_VECTOR}
+        del out
+    except amd.AmiError as e:
+        res["C3_real_frequency_grid"] = f"not run: {e}"
+    # the adjoint of large solutions in passes: forward and value-and-gradient step
+    large = []
+    for order, seed in ((5, (0, 5, 0)), (6, (0, 6, 0)), (6, (5, 6, 2))):
+        try:
+            d = random_self_energy(order, seed)
+            row = fwd_and_step(d, 200_000, (113,) + seed, 5.0, matsubara_freqs(1, 5.0))
+            row.update({"order": order, "topology": list(seed)})
+            large.append(row)
+        except amd.AmiError as e:
+            large.append({"order": order, "topology": list(seed), "error": str(e)})
+    res["large_adjoint_passes"] = large
+    return res
 
 
 def next_rows_section(args, torch, dev, stream):
@@ -482,6 +635,10 @@ def main():
     ms_step = timed_steps(graph is not None)
     wall = time.perf_counter() - wall0
     step_mode = "graph replay" if graph is not None else "launches"
+    # the same steps again, each timed alone (max(K, 20) of them): median and minimum
+    with torch.cuda.stream(gstream if graph is not None else stream):
+        step_median = _median_ms(torch, gstream if graph is not None else stream,
+                                 graph.replay if graph is not None else step, reps=max(args.steps, 20))
 
     # the same K steps as plain launches; the library records HIP events on
     # the launch stream around the main kernel of every step (the roofline's
@@ -658,7 +815,10 @@ def main():
         "specialize_ms": specialize_ms, "specialize": specialize_note,
         "wall_s": wall,
     }
+    res["ms_per_step_median"], res["ms_per_step_min"] = step_median
     res["next_rows"] = next_rows_section(args, torch, dev, stream)
+    if not args.no_configs:
+        res["configs"] = configs_section(args, torch, dev, stream)
     if not args.no_batch:
         res["batch"] = batch_section(args, torch, dev)
     if args.cpu_seconds > 0:
