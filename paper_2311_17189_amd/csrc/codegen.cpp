@@ -394,12 +394,16 @@ bool park_dv(const AmiTerms *t, bool hub) {
 }
 int park_cols(const AmiTerms *t, bool hub) { return park_chain(t, hub) + (park_dv(t, hub) ? t->tab.L : 0); }
 
-// occupancy hint for the adjoint (waves per SIMD), AMIGPU_JIT_ADJ_WAVES
+// occupancy floor of the one-pass adjoint (waves per SIMD; 0: none),
+// AMIGPU_JIT_ADJ_WAVES overriding the default of two: an adjoint that would
+// take more than 256 VGPRs runs at two waves with a few spills rather than at
+// one (order-4 topologies of 40-52 terms: 0.099-0.105 -> 0.081-0.086 ms per
+// 10^6-sample step)
 int adj_waves() {
     const char *e = std::getenv("AMIGPU_JIT_ADJ_WAVES");
-    if (!e) return 0;
+    if (!e) return 2;
     const int v = std::atoi(e);
-    return (v >= 0 && v <= 8) ? v : 0;
+    return (v >= 0 && v <= 8) ? v : 2;
 }
 
 }  // namespace
