@@ -161,9 +161,10 @@ def recorded_traffic(kernel: str, workload: str):
 def batch_section(args, torch, dev):
     """Mixed batch: 64 seeded diagrams of orders 2-6 (13/13/13/13/12), 16
     external Matsubara frequencies and N samples each, one graph launch with
-    the autotuned choice (the specialized kernels, or the persistent packed
-    kernels with a tiling), against the best packed batch and 64 separate
-    launches of the specialized, the packed and the plain kernels."""
+    the autotuned choice (the specialized kernels as recorded launches or in
+    persistent kernels, or the persistent packed kernels, each with its
+    tilings), against the best persistent batches of either kind and 64
+    separate launches of the specialized, the packed and the plain kernels."""
     import numpy as np
 
     import paper_2311_17189_amd as amd
@@ -232,6 +233,8 @@ def batch_section(args, torch, dev):
     # the persistent packed batch (the kernels every item had before the
     # specialized ones), best of the packed tilings the autotuner timed
     packed_best = min(((v, k) for k, v in timings.items() if '"kernels": 1' in k), default=(None, None))
+    # the specialized tile functions inside persistent kernels, best of the tilings timed
+    pspec_best = min(((v, k) for k, v in timings.items() if '"kernels": 2' in k), default=(None, None))
     for it in items:
         it["terms"].set_variant(amd.VARIANT_TABLES)
     plain_ms = timed(separate)
@@ -245,6 +248,7 @@ def batch_section(args, torch, dev):
         "batch_ms": batch_ms, "batch_term_evals_per_s": te / (batch_ms * 1e-3),
         "separate_auto_ms": auto_ms, "separate_auto_term_evals_per_s": te / (auto_ms * 1e-3),
         "packed_batch_ms": packed_best[0], "packed_batch_tuning": packed_best[1],
+        "persistent_specialized_ms": pspec_best[0], "persistent_specialized_tuning": pspec_best[1],
         "separate_packed_ms": sep_ms, "separate_packed_term_evals_per_s": te / (sep_ms * 1e-3),
         "separate_plain_ms": plain_ms, "separate_plain_term_evals_per_s": te / (plain_ms * 1e-3),
         "tuning": best, "tuning_candidates": len(timings), "tuning_s": tune_s, "info": info,

@@ -434,6 +434,19 @@ AmiStatus amiTermsSpecialize(AmiTerms *terms, int32_t momentum);
 AmiStatus amiTermsSource(const AmiTerms *terms, int32_t momentum, char *buf, int64_t cap, int64_t *len);
 
 /*
+ * amiBatchSource -- the generated device source of one module of the
+ * persistent specialized batch (amiBatchCreate with tuning.kernels = 2) for
+ * the n handles terms[0..n) with n_f[i] frequency rows each (host arrays;
+ * momentum as in amiTermsSource), NUL-terminated into buf as amiTermsSource
+ * does.  With compile nonzero it is also compiled for gfx950 with hipRTC (into
+ * the disk cache; no device is needed): AMI_E_HIP with the compiler's log
+ * when that fails.  AMI_E_UNSUPPORTED when an item is outside the
+ * specialized form.
+ */
+AmiStatus amiBatchSource(AmiTerms *const *terms, int32_t n, const int64_t *n_f, int32_t momentum, int32_t compile,
+                         char *buf, int64_t cap, int64_t *len);
+
+/*
  * Kernel timer (measurement): after amiKernelTimerStart(capacity), every
  * evaluate and adjoint call on this thread records a pair of HIP events on its
  * stream around its main kernel (the first `capacity` calls; the row-sum and
@@ -496,7 +509,11 @@ typedef struct {
  *   kernels      0: every item whose specialized forward an AUTO evaluate call
  *                would run (one or two passes) runs it, the others the packed
  *                persistent kernels; 1: every item on the packed kernels
- *                (block, waves_per_cu and tile_factor tune those only) */
+ *                (block, waves_per_cu and tile_factor tune those only);
+ *                2: every item's specialized tile functions inside persistent
+ *                kernels (every item needs a specialized forward; block is
+ *                ignored, 256 lanes; waves_per_cu caps the resident waves and
+ *                tile_factor sizes the work items) */
 typedef struct {
     int32_t block;
     int32_t waves_per_cu;
@@ -520,6 +537,15 @@ typedef struct {
  * equal to an AUTO evaluate call's bit for bit; an item on the packed kernels
  * gets out equal to the packed per-diagram call's (AMI_VARIANT_PACKED) bit for
  * bit, and out_sum too when the class's block size matches that call's.
+ * With tuning.kernels = 2: generate, compile (side by side, into the disk
+ * cache) and load one module per group of items -- per pass (the one-pass
+ * tiles with the two-pass items' first pass, then their frequency pass), the
+ * items grouped by the occupancy of their own kernel of that pass -- holding
+ * every item's generated tile functions and a persistent kernel that pulls
+ * (item, tile range, frequency row) work items from its own counter; the graph
+ * runs counter reset -> the first-pass kernels side by side -> the
+ * frequency-pass kernels -> fixed-order row sums; out and out_sum equal an
+ * AUTO evaluate call's bit for bit.
  */
 AmiStatus amiBatchCreate(const AmiBatchItem *items, int32_t n_items, const AmiBatchTuning *tuning,
                          AmiBatch **out);

@@ -114,6 +114,8 @@ def load_library():
     lib.amiTermsSpecialize.restype = c_i32
     lib.amiTermsSource.argtypes = [vp, c_i32, ctypes.c_char_p, c_i64, ctypes.POINTER(c_i64)]
     lib.amiTermsSource.restype = c_i32
+    lib.amiBatchSource.argtypes = [vp, c_i32, vp, c_i32, c_i32, ctypes.c_char_p, c_i64, ctypes.POINTER(c_i64)]
+    lib.amiBatchSource.restype = c_i32
     lib.amiMeasureFp64Peak.argtypes = [c_i64, ctypes.POINTER(ctypes.c_double), vp]
     lib.amiMeasureFp64Peak.restype = c_i32
     lib.amiKernelTimerStart.argtypes = [c_i32]
@@ -547,6 +549,22 @@ def _hubbard_adjoint(entry: str, terms: Terms, k, q, t, mu, ext_freqs, beta, e_r
     return g_k, scal[0], scal[1], scal[2], g_w
 
 
+def batch_source(terms_list, n_f, momentum: bool = True, compile: bool = False) -> str:
+    """``amiBatchSource``: the generated source of one module of the persistent
+    specialized batch for these handles (``n_f`` frequency rows each); with
+    ``compile`` it is also compiled with hipRTC (no device needed)."""
+    lib = load_library()
+    hs = (ctypes.c_void_p * len(terms_list))(*[t._h.value for t in terms_list])
+    nf = np.ascontiguousarray(np.broadcast_to(np.asarray(n_f, dtype=np.int64), (len(terms_list),)))
+    n = ctypes.c_int64()
+    _check(lib.amiBatchSource(hs, len(terms_list), nf.ctypes.data, int(bool(momentum)), int(bool(compile)),
+                              None, 0, ctypes.byref(n)))
+    buf = ctypes.create_string_buffer(n.value)
+    _check(lib.amiBatchSource(hs, len(terms_list), nf.ctypes.data, int(bool(momentum)), 0, buf, n.value,
+                              ctypes.byref(n)))
+    return buf.value.decode()
+
+
 def read_graph(path: str) -> np.ndarray:
     """``amiReadGraph``: the rows (source, target, B/F, spin) of a graph file, int32 [n, 4]."""
     lib = load_library()
@@ -607,7 +625,8 @@ class Batch:
     :meth:`run` evaluates what they hold (an input with broadcast rows is
     copied once, here, and the batch reads the copy).  ``tuning`` is a dict with ``block``,
     ``waves_per_cu``, ``tile_factor`` and ``kernels`` (0: specialized kernels
-    where AUTO would use them, 1: packed only; see :mod:`.autotune`).
+    where AUTO would use them, as recorded launches; 1: packed only; 2: every
+    item's specialized tile functions in persistent kernels; see :mod:`.autotune`).
     """
 
     def __init__(self, items, tuning=None):

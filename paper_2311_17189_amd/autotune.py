@@ -1,10 +1,12 @@
 """Autotuner of the persistent mixed-diagram batch.
 
-Tries batch tunings -- the specialized kernels where available, or the packed
-persistent kernels with a block size (lanes per tile), resident waves per CU
-of the persistent grid, and the tile factor that sets how many sample tiles
-one work item of a cheap diagram holds -- times each with HIP events on the
-batch graph, and keeps the fastest.  Results are cached in a JSON file keyed by a
+Tries batch tunings -- the specialized kernels where available as recorded
+per-diagram launches (kernels 0), the specialized tile functions inside
+persistent kernels (kernels 2), or the packed persistent kernels (kernels 1);
+for the persistent ones a block size (lanes per tile, packed only), resident
+waves per CU of the persistent grid, and the tile factor that sets how many
+sample tiles one work item of a cheap diagram holds -- times each with HIP
+events on the batch graph, and keeps the fastest.  Results are cached in a JSON file keyed by a
 signature of the batch (every diagram's canonical term list, sample and
 frequency counts, path), so a repeated workload is tuned once.
 """
@@ -15,9 +17,12 @@ import json
 import os
 from typing import Dict, List, Optional
 
-# the specialized kernels (no tiling to tune), then the packed persistent
-# kernels over a grid of tilings
+# the specialized kernels as recorded launches (no tiling to tune), the
+# specialized tile functions in persistent kernels over a few tilings, then the
+# packed persistent kernels over a grid of tilings
 DEFAULT_CANDIDATES: List[Dict[str, int]] = [{"block": 0, "waves_per_cu": 8, "tile_factor": 1, "kernels": 0}] + [
+    {"block": 0, "waves_per_cu": w, "tile_factor": f, "kernels": 2} for w, f in ((32, 4), (16, 2), (32, 1))
+] + [
     {"block": b, "waves_per_cu": w, "tile_factor": f, "kernels": 1}
     for b in (0, 64, 128) for w in (4, 8, 16) for f in (1, 4)
 ]

@@ -20,13 +20,17 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <atomic>
 #include <cmath>
 #include <cstring>
 #include <string>
 #include <vector>
 
+#include <thread>
+
 #include "ami_internal.hpp"
 #include "device_common.hpp"
+#include "jit.hpp"
 #include "kernels_packed.hpp"
 #include "runtime.hpp"
 
@@ -167,6 +171,7 @@ struct AmiBatch {
     void *blob = nullptr;                  // descriptors, work list, jobs, counter, partial sums
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
+    std::vector<hipModule_t> modules;      // persistent specialized batch: its compiled groups
 };
 
 namespace ami {
@@ -257,10 +262,332 @@ AmiStatus batch_fail_free(AmiBatch *b, AmiStatus st) {
     if (b->exec) (void)hipGraphExecDestroy(b->exec);
     if (b->graph) (void)hipGraphDestroy(b->graph);
     if (b->blob) (void)hipFree(b->blob);
+    for (hipModule_t m : b->modules) (void)hipModuleUnload(m);
     for (int k = 0; k < b->n_streams; ++k)
         if (b->streams[k]) (void)hipStreamDestroy(b->streams[k]);
     delete b;
     return st;
+}
+
+// Row sums of the persistent specialized batch: per item and column, the
+// column's per-wave partial sums reduced by column_sum, the routine (and
+// block size) of the per-diagram row-sum kernel, so out_sum is bitwise the
+// per-diagram call's.
+struct ColJob {
+    const double *col;
+    double *dst;
+    int64_t rows;
+};
+
+__global__ __launch_bounds__(kRedThreads) void ami_batch_colsum_kernel(const ColJob *jobs) {
+    __shared__ double sh[kRedThreads / 64];
+    const ColJob j = jobs[blockIdx.x];
+    const double r = column_sum(j.col, j.rows, 1, sh);
+    if (threadIdx.x == 0) *j.dst = r;
+}
+
+// Work item of the persistent specialized kernels (the layout of
+// amibatch::Work in the generated source).
+struct SpecWork {
+    int32_t item, ntiles;
+    int64_t tile0;
+    int32_t f, pad;
+};
+
+// Terms per compiled group of the persistent specialized batch (groups are
+// compiled side by side; one group per occupancy class below this bound).
+constexpr int64_t kSpecGroupTerms = 16000;
+constexpr int kSpecBlock = 256;
+
+// The persistent specialized batch (tuning.kernels = 2): every item runs its
+// own generated tile functions inside persistent kernels.  Per pass (the
+// one-pass tiles with the two-pass items' first pass, then the two-pass
+// items' frequency pass) the items are grouped by the occupancy (VGPRs) of
+// their own kernel of that pass, groups cut at about kSpecGroupTerms terms;
+// each group is one module compiled at run time whose kernel pulls work items
+// from its own counter.  The graph: counter reset -> every first-pass kernel
+// (side by side) -> every frequency-pass kernel -> row sums.
+AmiStatus create_spec_persistent(const AmiBatchItem *items, int n_items, const AmiBatchTuning &tun, bool hub,
+                                 int dev, AmiBatch **out) {
+    int n_cu = 0;
+    hipError_t e = hipDeviceGetAttribute(&n_cu, hipDeviceAttributeMultiprocessorCount, dev);
+    if (e != hipSuccess) return hip_fail(e, "hipDeviceGetAttribute");
+    const int B = kSpecBlock;
+    // per item: one or two passes (as AUTO), and the occupancy (waves per
+    // SIMD) of its own kernel of each pass: the forward, or the first and the
+    // frequency pass
+    std::vector<int> two(n_items, 0), waves1(n_items, 8), waves2(n_items, 8);
+    std::vector<int64_t> tiles(n_items, 0);
+    auto waves_of = [&](AmiTerms *t, int kind, int &w) -> AmiStatus {
+        void *fn = nullptr;
+        AmiStatus st = jit_get(t, hub, kind, &fn);
+        if (st != AMI_OK) return st;
+        int r = 0;
+        const hipError_t e2 = hipFuncGetAttribute(&r, HIP_FUNC_ATTRIBUTE_NUM_REGS, static_cast<hipFunction_t>(fn));
+        if (e2 != hipSuccess) return hip_fail(e2, "hipFuncGetAttribute");
+        w = std::max(1, std::min(8, 512 / std::max(8, (r + 7) / 8 * 8)));
+        return AMI_OK;
+    };
+    for (int i = 0; i < n_items; ++i) {
+        AmiTerms *t = items[i].terms;
+        if (!specialized_forward_ready(t, hub, static_cast<int>(items[i].n_f)))
+            return fail(AMI_E_UNSUPPORTED, "item " + std::to_string(i) + ": no specialized forward");
+        two[i] = jit_prefers_two_pass(t) ? 1 : 0;
+        if (two[i] && items[i].n_f > 65535) return fail(AMI_E_UNSUPPORTED, "more than 65535 frequency rows");
+        AmiStatus st = waves_of(t, two[i] ? kJitSumsPass : kJitForward, waves1[i]);
+        if (st == AMI_OK && two[i]) st = waves_of(t, kJitFreqPass, waves2[i]);
+        if (st != AMI_OK) return st;
+        tiles[i] = (items[i].n_e + B - 1) / B;
+    }
+    std::vector<double> cost(n_items);
+    for (int i = 0; i < n_items; ++i) cost[i] = sample_cost(items[i].terms, items[i].n_f) * items[i].n_e;
+    // kernel groups: per pass, the items by the occupancy of their own kernel
+    // of that pass (most waves first, then by cost), cut at kSpecGroupTerms
+    // terms; a group's kernel runs at the occupancy its own code allows
+    struct KGroup {
+        int pass;
+        std::vector<int> items;
+    };
+    std::vector<KGroup> groups;
+    for (int pass = 1; pass <= 2; ++pass) {
+        const std::vector<int> &wv = pass == 1 ? waves1 : waves2;
+        std::vector<int> order;
+        for (int i = 0; i < n_items; ++i)
+            if (pass == 1 || two[i]) order.push_back(i);
+        std::stable_sort(order.begin(), order.end(),
+                         [&](int x, int y) { return wv[x] != wv[y] ? wv[x] > wv[y] : cost[x] > cost[y]; });
+        int64_t terms_in = 0;
+        bool fresh = true;
+        for (int i : order) {
+            const int64_t T = items[i].terms->tab.T;
+            if (fresh || wv[groups.back().items[0]] != wv[i] || terms_in + T > kSpecGroupTerms) {
+                groups.push_back(KGroup{pass, {}});
+                terms_in = 0;
+                fresh = false;
+            }
+            groups.back().items.push_back(i);
+            terms_in += T;
+        }
+    }
+    // generated sources, compiled side by side (no device needed), then loaded
+    const size_t G = groups.size();
+    std::vector<std::string> srcs(G), errs(G);
+    std::vector<std::vector<char>> codes(G);
+    std::vector<AmiStatus> sts(G, AMI_OK);
+    for (size_t g = 0; g < G; ++g) {
+        std::vector<const AmiTerms *> ts;
+        std::vector<int> tp, one, labels;
+        for (int i : groups[g].items) {
+            ts.push_back(items[i].terms);
+            tp.push_back(two[i]);
+            one.push_back(items[i].n_f == 1 ? 1 : 0);
+            labels.push_back(i);
+        }
+        srcs[g] = jit_batch_source(ts, tp, one, hub, B, groups[g].pass, labels);
+    }
+    {
+        std::vector<std::thread> pool;
+        std::atomic<size_t> next{0};
+        const unsigned n_thr = std::max(1u, std::min<unsigned>(8u, static_cast<unsigned>(G)));
+        for (unsigned k = 0; k < n_thr; ++k)
+            pool.emplace_back([&]() {
+                for (size_t g = next++; g < G; g = next++) sts[g] = code_from_source(srcs[g], codes[g], errs[g]);
+            });
+        for (auto &th : pool) th.join();
+    }
+    for (size_t g = 0; g < G; ++g)
+        if (sts[g] != AMI_OK) return fail(sts[g], "persistent batch group " + std::to_string(g) + ": " + errs[g]);
+
+    AmiBatch *b = new (std::nothrow) AmiBatch();
+    if (!b) return fail(AMI_E_OOM, "out of host memory");
+    b->device = dev;
+    b->hub = hub;
+    b->n_items = n_items;
+    b->n_spec = n_items;
+    b->block = B;
+    std::vector<hipFunction_t> kfn(G, nullptr);
+    for (size_t g = 0; g < G; ++g) {
+        hipModule_t m = nullptr;
+        e = hipModuleLoadData(&m, codes[g].data());
+        if (e != hipSuccess) return batch_fail_free(b, hip_fail(e, "hipModuleLoadData (persistent batch)"));
+        b->modules.push_back(m);
+        const char *name = groups[g].pass == 1 ? "ami_batch_p1" : "ami_batch_p2";
+        e = hipModuleGetFunction(&kfn[g], m, name);
+        if (e != hipSuccess) return batch_fail_free(b, fail(AMI_E_HIP, std::string("hipModuleGetFunction ") + name));
+    }
+
+    // work lists: per group, each item's tiles in work items of about
+    // tile_factor times the group's most expensive tile, the items from the
+    // most to the least expensive with their work items together (a CU then
+    // mostly runs one item's code at a time); in the frequency pass a work
+    // item is a tile range at one frequency row, the rows of a range queued
+    // one after another
+    std::vector<double> tile_cost(n_items);
+    for (int i = 0; i < n_items; ++i) tile_cost[i] = sample_cost(items[i].terms, items[i].n_f) * B;
+    std::vector<SpecWork> wl;
+    std::vector<int64_t> w0(G, 0), nw(G, 0);
+    for (size_t g = 0; g < G; ++g) {
+        const int pass = groups[g].pass;
+        // pass 1 of a two-pass item: leaves and group sums only (about a
+        // fifth of its tile's cost); pass 2: one frequency row
+        auto unit = [&](int i) {
+            return !two[i] ? tile_cost[i] : pass == 1 ? tile_cost[i] / 5 : tile_cost[i] / items[i].n_f;
+        };
+        double max_tile = 0.0;
+        for (int i : groups[g].items) max_tile = std::max(max_tile, unit(i));
+        const double target = max_tile * tun.tile_factor;
+        std::vector<int> by_cost = groups[g].items;
+        std::stable_sort(by_cost.begin(), by_cost.end(), [&](int x, int y) { return cost[x] > cost[y]; });
+        w0[g] = static_cast<int64_t>(wl.size());
+        for (int i : by_cost) {
+            const int64_t per = std::max<int64_t>(1, static_cast<int64_t>(target / unit(i)));
+            const int rows_per = pass == 2 ? static_cast<int>(items[i].n_f) : 1;
+            for (int64_t t0 = 0; t0 < tiles[i]; t0 += per)
+                for (int f = 0; f < rows_per; ++f) {
+                    SpecWork w;
+                    std::memset(&w, 0, sizeof(w));
+                    w.item = i;
+                    w.tile0 = t0;
+                    w.ntiles = static_cast<int32_t>(std::min<int64_t>(per, tiles[i] - t0));
+                    w.f = pass == 2 ? f : -1;
+                    wl.push_back(w);
+                }
+        }
+        nw[g] = static_cast<int64_t>(wl.size()) - w0[g];
+    }
+    if (wl.size() > 0x7fffffffu - 65536u) return batch_fail_free(b, fail(AMI_E_ARG, "too many work items"));
+
+    // one allocation: argument blocks (item order) | work |
+    // column jobs | counters | per-wave partial sums | two-pass workspaces
+    std::vector<int64_t> rows(n_items), part_off(n_items, -1), ws_off(n_items, -1), ld(n_items, 0);
+    int64_t part_total = 0, ws_total = 0, n_jobs = 0;
+    for (int i = 0; i < n_items; ++i) {
+        rows[i] = tiles[i] * (B / 64);
+        if (items[i].out_sum) {
+            part_off[i] = part_total;
+            part_total += rows[i] * 2 * items[i].n_f;
+            n_jobs += 2 * items[i].n_f;
+        }
+        if (two[i]) {
+            ld[i] = tiles[i] * B;
+            ws_off[i] = ws_total;
+            ws_total += (static_cast<int64_t>(items[i].terms->tab.G) + items[i].terms->n_eps) * ld[i];
+        }
+    }
+    auto al = [](size_t x) { return (x + 255) & ~size_t(255); };
+    const size_t sz_args = sizeof(KArgs) * n_items;
+    const size_t off_work = al(sz_args);
+    const size_t off_jobs = al(off_work + sizeof(SpecWork) * std::max<size_t>(wl.size(), 1));
+    const size_t off_ctr = al(off_jobs + sizeof(ColJob) * std::max<int64_t>(n_jobs, 1));
+    const size_t off_part = al(off_ctr + sizeof(unsigned int) * kCounterStride * G);
+    const size_t off_ws = al(off_part + sizeof(double) * std::max<int64_t>(part_total, 1));
+    const size_t total = off_ws + sizeof(double) * std::max<int64_t>(ws_total, 1);
+    e = hipMalloc(&b->blob, total);
+    if (e != hipSuccess) return batch_fail_free(b, fail(AMI_E_OOM, "persistent batch workspace"));
+    unsigned char *base = static_cast<unsigned char *>(b->blob);
+    double *partial = reinterpret_cast<double *>(base + off_part);
+    double *wsp = reinterpret_cast<double *>(base + off_ws);
+    std::vector<KArgs> args(n_items);
+    std::vector<ColJob> jobs;
+    for (int i = 0; i < n_items; ++i) {
+        const AmiBatchItem &it = items[i];
+        KArgs &a = args[i];
+        std::memset(&a, 0, sizeof(a));
+        set_inputs(a, it.terms, it.k, it.stride_k, it.q, it.t, it.mu, it.energies, it.stride_s, it.stride_i,
+                   it.ext_freqs, it.n_f, it.beta, it.e_reg, it.n_e);
+        a.out = it.out;
+        a.nrows = rows[i];
+        a.partial = it.out_sum ? partial + part_off[i] : nullptr;
+        if (two[i]) {
+            a.work = wsp + ws_off[i];
+            a.ld = ld[i];
+            a.s0 = 0;
+            a.n_chunk = it.n_e;
+        }
+        if (it.out_sum)
+            for (int c = 0; c < 2 * it.n_f; ++c) jobs.push_back(ColJob{partial + part_off[i] + c * rows[i], it.out_sum + c, rows[i]});
+        if (two[i] && ld[i] > (int64_t(1) << 28))
+            return batch_fail_free(b, fail(AMI_E_ARG, "item " + std::to_string(i) + ": more than 2^28 samples in two passes"));
+    }
+    // work items name their item; the kernels index the argument blocks by it
+    std::vector<unsigned char> host(off_part, 0);
+    std::memcpy(host.data(), args.data(), sz_args);
+    if (!wl.empty()) std::memcpy(host.data() + off_work, wl.data(), sizeof(SpecWork) * wl.size());
+    if (!jobs.empty()) std::memcpy(host.data() + off_jobs, jobs.data(), sizeof(ColJob) * jobs.size());
+    e = hipMemcpy(b->blob, host.data(), off_part, hipMemcpyHostToDevice);
+    if (e != hipSuccess) return batch_fail_free(b, hip_fail(e, "persistent batch upload"));
+    b->n_work = static_cast<int64_t>(wl.size());
+    b->n_jobs = n_jobs;
+    b->n_classes = static_cast<int>(G);
+
+    // graph
+    e = hipGraphCreate(&b->graph, 0);
+    if (e != hipSuccess) return batch_fail_free(b, hip_fail(e, "hipGraphCreate"));
+    unsigned int *d_ctr = reinterpret_cast<unsigned int *>(base + off_ctr);
+    hipGraphNode_t n_reset = nullptr;
+    {
+        if (G > 1024) return batch_fail_free(b, fail(AMI_E_ARG, "too many groups"));
+        int n_ctr = static_cast<int>(G);
+        void *kp[] = {&d_ctr, &n_ctr};
+        hipKernelNodeParams p;
+        std::memset(&p, 0, sizeof(p));
+        p.func = reinterpret_cast<void *>(&ami_batch_reset_kernel);
+        p.gridDim = dim3(1);
+        p.blockDim = dim3(static_cast<unsigned>(std::max<size_t>(64, (G + 63) / 64 * 64)));
+        p.kernelParams = kp;
+        e = hipGraphAddKernelNode(&n_reset, b->graph, nullptr, 0, &p);
+        if (e != hipSuccess) return batch_fail_free(b, hip_fail(e, "graph reset node"));
+    }
+    // every first-pass kernel after the reset, side by side; every frequency-
+    // pass kernel after all of them; the row sums after everything
+    std::vector<hipGraphNode_t> first, all;
+    for (int pass = 1; pass <= 2; ++pass)
+        for (size_t g = 0; g < G; ++g) {
+            if (groups[g].pass != pass || nw[g] == 0) continue;
+            // resident blocks per CU from the kernel's own VGPRs (one wave of
+            // each block per SIMD), capped by the tuning
+            int regs = 0;
+            e = hipFuncGetAttribute(&regs, HIP_FUNC_ATTRIBUTE_NUM_REGS, kfn[g]);
+            if (e != hipSuccess) return batch_fail_free(b, hip_fail(e, "hipFuncGetAttribute"));
+            const int gw = std::max(1, std::min(8, 512 / std::max(8, (regs + 7) / 8 * 8)));
+            const int per_cu = std::max(1, std::min(gw, tun.waves_per_cu / (B / 64)));
+            const KArgs *d_args = reinterpret_cast<const KArgs *>(base);
+            const SpecWork *d_work = reinterpret_cast<const SpecWork *>(base + off_work) + w0[g];
+            int n_work = static_cast<int>(nw[g]);
+            unsigned int *ctr = d_ctr + g * kCounterStride;
+            void *kp[] = {&d_args, &d_work, &n_work, &ctr};
+            hipKernelNodeParams p;
+            std::memset(&p, 0, sizeof(p));
+            p.func = reinterpret_cast<void *>(kfn[g]);
+            p.gridDim = dim3(static_cast<unsigned>(std::min<int64_t>(static_cast<int64_t>(n_cu) * per_cu, nw[g])));
+            p.blockDim = dim3(B);
+            p.kernelParams = kp;
+            hipGraphNode_t node = nullptr;
+            const std::vector<hipGraphNode_t> &deps = pass == 1 ? std::vector<hipGraphNode_t>{n_reset} : first;
+            e = hipGraphAddKernelNode(&node, b->graph, deps.data(), deps.size(), &p);
+            if (e != hipSuccess) return batch_fail_free(b, hip_fail(e, "graph persistent node"));
+            if (pass == 1) first.push_back(node);
+            all.push_back(node);
+            b->grid += static_cast<int>(p.gridDim.x);
+        }
+    std::vector<hipGraphNode_t> &last = all;
+    if (n_jobs > 0) {
+        const ColJob *d_jobs = reinterpret_cast<const ColJob *>(base + off_jobs);
+        void *kp[] = {&d_jobs};
+        hipKernelNodeParams p;
+        std::memset(&p, 0, sizeof(p));
+        p.func = reinterpret_cast<void *>(&ami_batch_colsum_kernel);
+        p.gridDim = dim3(static_cast<unsigned>(n_jobs));
+        p.blockDim = dim3(kRedThreads);
+        p.kernelParams = kp;
+        hipGraphNode_t node = nullptr;
+        e = hipGraphAddKernelNode(&node, b->graph, last.data(), last.size(), &p);
+        if (e != hipSuccess) return batch_fail_free(b, hip_fail(e, "graph row-sum node"));
+    }
+    e = hipGraphInstantiate(&b->exec, b->graph, nullptr, nullptr, 0);
+    if (e != hipSuccess) return batch_fail_free(b, hip_fail(e, "hipGraphInstantiate"));
+    *out = b;
+    return AMI_OK;
 }
 
 }  // namespace
@@ -281,7 +608,7 @@ AmiStatus amiBatchCreate(const AmiBatchItem *items, int32_t n_items, const AmiBa
     if (tun.tile_factor < 1 || tun.tile_factor > 1024) return fail(AMI_E_ARG, "tile_factor must be in 1..1024");
     if (tun.block != 0 && tun.block != 64 && tun.block != 128 && tun.block != 256)
         return fail(AMI_E_ARG, "block must be 0 (automatic), 64, 128 or 256");
-    if (tun.kernels != 0 && tun.kernels != 1) return fail(AMI_E_ARG, "kernels must be 0 or 1");
+    if (tun.kernels < 0 || tun.kernels > 2) return fail(AMI_E_ARG, "kernels must be 0, 1 or 2");
     const bool hub = items[0].k != nullptr;
     int dev = 0;
     hipError_t e = hipGetDevice(&dev);
@@ -312,6 +639,7 @@ AmiStatus amiBatchCreate(const AmiBatchItem *items, int32_t n_items, const AmiBa
         DeviceTables *dt = nullptr;
         AmiStatus st = upload(t, &dt);
         if (st != AMI_OK) return st;
+        if (tun.kernels == 2) continue;
         spec[i] = tun.kernels == 0 && specialized_forward_ready(t, hub, static_cast<int>(it.n_f));
         if (!spec[i] && !t->tab.packable)
             return fail(AMI_E_UNSUPPORTED, "item " + std::to_string(i) + ": no specialized kernel and not in packed form");
@@ -337,6 +665,7 @@ AmiStatus amiBatchCreate(const AmiBatchItem *items, int32_t n_items, const AmiBa
         d.a.out = it.out;
         d.shape = shape_of(t, hub);
     }
+    if (tun.kernels == 2) return create_spec_persistent(items, n_items, tun, hub, dev, out);
     int max_lds = 0, cu_lds = 0, n_cu = 0;
     e = hipDeviceGetAttribute(&max_lds, hipDeviceAttributeMaxSharedMemoryPerBlock, dev);
     if (e == hipSuccess) e = hipDeviceGetAttribute(&cu_lds, hipDeviceAttributeMaxSharedMemoryPerMultiprocessor, dev);
@@ -605,6 +934,7 @@ void amiBatchFree(AmiBatch *b) {
     if (b->exec) (void)hipGraphExecDestroy(b->exec);
     if (b->graph) (void)hipGraphDestroy(b->graph);
     if (b->blob) (void)hipFree(b->blob);
+    for (hipModule_t m : b->modules) (void)hipModuleUnload(m);
     for (int k = 0; k < b->n_streams; ++k)
         if (b->streams[k]) (void)hipStreamDestroy(b->streams[k]);
     if (have) (void)hipSetDevice(cur);

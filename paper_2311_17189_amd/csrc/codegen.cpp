@@ -1074,7 +1074,112 @@ std::string jit_source(const AmiTerms *t, bool hub, int kernels) {
     return o.str();
 }
 
+std::string jit_batch_source(const std::vector<const AmiTerms *> &items, const std::vector<int> &two_pass,
+                             const std::vector<int> &one_row, bool hub, int block, int phases,
+                             const std::vector<int> &labels) {
+    std::ostringstream o;
+    o << "// generated: persistent batch of " << items.size() << " specialized evaluators\n";
+    o << "#include \"kargs.hpp\"\n";
+    // the tile functions read the argument blocks through the constant address space
+    o << "#define AMI_JIT_ARGS const __attribute__((address_space(4))) ami::KArgs\n";
+    const char *const kSettings[] = {"AMI_JIT_HUB", "AMI_JIT_KERNELS", "AMI_JIT_BLOCK", "AMI_JIT_PARK_DV",
+                                     "AMI_JIT_ADJ_WAVES"};
+    bool any_two = false;
+    for (size_t j = 0; j < items.size(); ++j) {
+        any_two = any_two || two_pass[j];
+        std::string src = jit_source(items[j], hub, two_pass[j] ? (16 | 32) : 1);
+        // the diagram's functions in a namespace of its own, with its settings
+        // and the block of the batch, followed by the tile functions
+        std::istringstream in(src);
+        std::string line;
+        for (const char *m : kSettings) o << "#undef " << m << "\n";
+        o << "#define amijit amijit_b" << j << "\n";
+        while (std::getline(in, line)) {
+            if (line == "#include \"kargs.hpp\"" || line == "#include \"jit_kernel.hpp\"") continue;
+            if (line.rfind("#define AMI_JIT_BLOCK ", 0) == 0) line = "#define AMI_JIT_BLOCK " + std::to_string(block);
+            o << line << "\n";
+        }
+        o << "#include \"jit_tiles.hpp\"\n#undef amijit\n";
+    }
+    // the persistent kernels: every block takes work items (item, first tile,
+    // tile count, frequency row) from its counter until the list is done (every
+    // wave sees the counter pass n_work and exits) and runs the item's own tile
+    // function on each tile; the first kernel runs the one-pass forward tiles
+    // and the two-pass items' first pass, the second their frequency pass
+    o << "namespace amibatch {\n"
+         "struct Work {\n  int32_t item, ntiles;\n  int64_t tile0;\n  int32_t f, pad;\n};\n"
+         "typedef const __attribute__((address_space(4))) Work *cwork;\n"
+         "typedef const __attribute__((address_space(4))) ami::KArgs *cargs;\n"
+         "}  // namespace amibatch\n";
+    for (int phase = 1; phase <= 2; ++phase) {
+        if (!(phases & phase) || (phase == 2 && !any_two)) continue;
+        o << "extern \"C\" __global__ __launch_bounds__(" << block << ") void ami_batch_p" << phase
+          << "(const ami::KArgs *args, const amibatch::Work *work, int n_work, unsigned int *counter) {\n"
+             "  __shared__ int next;\n"
+             "  const amibatch::cwork cw = (amibatch::cwork)(work);\n"
+             "  const amibatch::cargs ca = (amibatch::cargs)(args);\n"
+             "  for (;;) {\n"
+             "    if (threadIdx.x == 0) next = static_cast<int>(atomicAdd(counter, 1u));\n"
+             "    __syncthreads();\n"
+             "    const int wi = __builtin_amdgcn_readfirstlane(next);\n"
+             "    __syncthreads();\n"
+             "    if (wi >= n_work) break;\n"
+             "    const int item = cw[wi].item, ntiles = cw[wi].ntiles, f = cw[wi].f;\n"
+             "    const int64_t tile0 = cw[wi].tile0;\n"
+             "    const __attribute__((address_space(4))) ami::KArgs &a = ca[item];\n"
+             "    (void)f;\n"
+             "    switch (item) {\n";
+        for (size_t j = 0; j < items.size(); ++j) {
+            const std::string ns = "amijit_b" + std::to_string(j);
+            const std::string h = hub ? "true" : "false";
+            const int label = labels.empty() ? static_cast<int>(j) : labels[j];
+            if (phase == 1) {
+                o << "    case " << label << ":\n      for (int64_t t = tile0; t < tile0 + ntiles; ++t) ";
+                if (two_pass[j]) o << ns << "::sums_tile<" << h << ">(a, t);\n";
+                else o << ns << "::fwd_tile<" << h << ", " << (one_row[j] ? "true" : "false") << ">(a, t);\n";
+                o << "      break;\n";
+            } else if (two_pass[j]) {
+                o << "    case " << label << ":\n      for (int64_t t = tile0; t < tile0 + ntiles; ++t) " << ns
+                  << "::freq_tile(a, t, f);\n      break;\n";
+            }
+        }
+        o << "    default: break;\n    }\n  }\n}\n";
+    }
+    return o.str();
+}
+
 }  // namespace ami
+
+extern "C" AmiStatus amiBatchSource(AmiTerms *const *terms, int32_t n, const int64_t *n_f, int32_t momentum,
+                                    int32_t compile, char *buf, int64_t cap, int64_t *len) {
+    using namespace ami;
+    clear_error();
+    if (!terms || !n_f || !len || n < 1) return fail(AMI_E_ARG, "NULL argument or no items");
+    const bool hub = momentum != 0;
+    std::vector<const AmiTerms *> ts;
+    std::vector<int> two, one;
+    for (int i = 0; i < n; ++i) {
+        if (!terms[i]) return fail(AMI_E_ARG, "terms[" + std::to_string(i) + "] is NULL");
+        two.push_back(jit_prefers_two_pass(terms[i]) ? 1 : 0);
+        std::string why;
+        if (!jit_supported(terms[i], hub, &why, two.back() != 0))
+            return fail(AMI_E_UNSUPPORTED, "item " + std::to_string(i) + ": no specialized kernel: " + why);
+        ts.push_back(terms[i]);
+        one.push_back(n_f[i] == 1 ? 1 : 0);
+    }
+    const std::string src = jit_batch_source(ts, two, one, hub, 256, 3, {});
+    if (compile) {
+        std::vector<char> code;
+        std::string err;
+        const AmiStatus st = code_from_source(src, code, err);
+        if (st != AMI_OK) return fail(st, err);
+    }
+    *len = static_cast<int64_t>(src.size()) + 1;
+    if (!buf) return AMI_OK;
+    if (cap < *len) return fail(AMI_E_ARG, "buffer too small");
+    std::memcpy(buf, src.c_str(), src.size() + 1);
+    return AMI_OK;
+}
 
 extern "C" AmiStatus amiTermsSource(const AmiTerms *t, int32_t momentum, char *buf, int64_t cap, int64_t *len) {
     using namespace ami;

@@ -35,39 +35,6 @@ AmiStatus hip_fail(hipError_t e, const char *what) {
 
 namespace {
 
-// Column sums of the partial-sum arrays: element (row r, column c) at
-// partial[r * rs + c * cs] (rs = ncols, cs = 1 for the per-block sums of the
-// table-driven kernels; rs = 1, cs = rows for the per-wave sums of the
-// specialized ones, so that a column is one contiguous read).  One block of
-// kRedThreads per column; thread t adds rows t, t + kRedThreads, ... in
-// order, loading 16 of them before adding (16 loads in flight per thread),
-// then the block adds the threads in a fixed order (wave sums, then the waves
-// in order): a fixed summation order for a given row count.
-constexpr int kRedThreads = 1024;
-
-__device__ __forceinline__ double column_sum(const double *col, int64_t n, int64_t rs, double *sh) {
-    const int tid = threadIdx.x;
-    constexpr int kLoads = 16;                 // rows in flight per thread
-    double acc = 0.0;
-    for (int64_t b0 = tid; b0 < n; b0 += kLoads * kRedThreads) {
-        double v[kLoads];
-#pragma unroll
-        for (int u = 0; u < kLoads; ++u) {
-            const int64_t b = b0 + static_cast<int64_t>(u) * kRedThreads;
-            v[u] = b < n ? col[b * rs] : 0.0;
-        }
-#pragma unroll
-        for (int u = 0; u < kLoads; ++u) acc += v[u];
-    }
-    acc = wave_sum(acc);
-    if ((tid & 63) == 0) sh[tid >> 6] = acc;
-    __syncthreads();
-    double r = 0.0;
-    if (tid == 0)
-        for (int w = 0; w < kRedThreads / 64; ++w) r += sh[w];
-    return r;   // in thread 0
-}
-
 // out[j] = sum over rows of column j.  One block per column.
 __global__ __launch_bounds__(kRedThreads) void ami_colsum_kernel(const double *partial, int64_t rows, int64_t rs,
                                                                  int64_t cs, double *out) {

@@ -1,7 +1,7 @@
 // Compilation, caching and loading of the run-time specialized evaluator.
 //
 // The generated source (codegen.cpp) and the embedded device headers
-// (device_common.hpp, kargs.hpp, jit_kernel.hpp, built into the library as
+// (device_common.hpp, kargs.hpp, jit_tiles.hpp, jit_kernel.hpp, built into the library as
 // strings) are compiled for gfx950 with hipRTC under the flags the library
 // itself is built with.  Code objects are kept per handle and on disk, keyed
 // by a hash of everything that goes into the compilation, so a diagram is
@@ -159,7 +159,13 @@ AmiStatus code_object(AmiTerms *t, bool hub, int kind) {
                           : "no complex-energy kernel for Taylor-coefficient leaves (poles of higher order)";
                 return fail(AMI_E_UNSUPPORTED, err);
             }
-    const std::string src = jit_source(t, hub, 1 << kind);
+    const AmiStatus st = code_from_source(jit_source(t, hub, 1 << kind), code, err);
+    return st == AMI_OK ? AMI_OK : fail(st, err);
+}
+
+}  // namespace
+
+AmiStatus code_from_source(const std::string &src, std::vector<char> &code, std::string &err) {
     const std::string dir = cache_dir();
     const std::string base = dir.empty() ? std::string() : dir + "/" + cache_key(src);
     if (!base.empty()) {
@@ -170,15 +176,13 @@ AmiStatus code_object(AmiTerms *t, bool hub, int kind) {
         code.clear();
     }
     const AmiStatus st = compile(src, code, err);
-    if (st != AMI_OK) return fail(st, err);
+    if (st != AMI_OK) return st;
     if (!base.empty()) {
         write_file_atomic(base + ".hsaco", code.data(), code.size());
         write_file_atomic(base + ".hip", src.data(), src.size());
     }
     return AMI_OK;
 }
-
-}  // namespace
 
 AmiStatus jit_compile(AmiTerms *t, bool hub, int kind) {
     if (kind < kJitForward || kind >= kJitKinds || (kind == kJitMonteCarlo && !hub) || (kind == kJitComplex && hub))

@@ -3,6 +3,7 @@
 #pragma once
 
 #include <string>
+#include <vector>
 
 #include "ami_internal.hpp"
 
@@ -46,6 +47,19 @@ int jit_block(const AmiTerms *t, bool hub);
 // cotangents; kernels & 128: the leaf cotangents and the gradients).
 std::string jit_source(const AmiTerms *t, bool hub, int kernels);
 
+// Source of one module of the persistent specialized batch: the generated
+// functions of every item (forward in one pass, or the two-pass forward where
+// two_pass[j] is set; one_row[j]: the one-pass tile for exactly one frequency
+// row) in a namespace of its own with the tile functions, all at `block`
+// lanes per block, and the persistent kernels selected by `phases`:
+// ami_batch_p1 (phases & 1: one-pass tiles and the two-pass items' first
+// pass) and ami_batch_p2 (phases & 2, with any two-pass item: their frequency
+// pass, a work item being a tile range at one row).
+// A work item names its item by labels[j] (by j when labels is empty).
+std::string jit_batch_source(const std::vector<const AmiTerms *> &items, const std::vector<int> &two_pass,
+                             const std::vector<int> &one_row, bool hub, int block, int phases,
+                             const std::vector<int> &labels);
+
 // Kernels of the specialized evaluator.
 // kJitAdjFreq and kJitAdjLeaf are the frequency and leaf passes of the
 // adjoint of large solutions (after kJitSumsPass).
@@ -76,6 +90,11 @@ AmiStatus jit_loaded(AmiTerms *t, bool hub, int kind, void **fn);
 // Only the code object of `kind` (compiled or fetched from the cache): needs
 // no device.
 AmiStatus jit_compile(AmiTerms *t, bool hub, int kind);
+
+// The code object of a generated source: from the disk cache, else compiled
+// with hipRTC under the library's flags and stored there.  Needs no device;
+// thread-safe.  On failure err says why (the status is AMI_E_HIP).
+AmiStatus code_from_source(const std::string &src, std::vector<char> &code, std::string &err);
 
 // Unload every module of the handle (amiFree).
 void jit_release(AmiTerms *t);

@@ -1,7 +1,8 @@
-"""Mixed-diagram batch (one HIP graph launch over many diagrams), in both
-modes -- every item on its specialized kernels where AUTO would run them
-(recorded launches in a child graph), or every item on the persistent packed
-kernels: outputs against the oracle, bitwise equal to the per-diagram
+"""Mixed-diagram batch (one HIP graph launch over many diagrams), in its
+three modes -- every item on its specialized kernels where AUTO would run them
+(recorded launches in a child graph), every item's specialized tile functions
+in persistent kernels, or every item on the persistent packed kernels:
+outputs against the oracle, bitwise equal to the per-diagram
 launches of the same kernels, stable across graph replays, row sums
 consistent, the autotuner, host-side errors, and the 64-diagram workload at
 full size (sampled outputs against the oracle)."""
@@ -86,7 +87,9 @@ def _per_diagram(it):
 
 @pytest.mark.parametrize("energies", [False, True])
 @pytest.mark.parametrize("tuning", [None, {"block": 64, "waves_per_cu": 4, "tile_factor": 1, "kernels": 1},
-                                    {"block": 128, "waves_per_cu": 16, "tile_factor": 4, "kernels": 1}])
+                                    {"block": 128, "waves_per_cu": 16, "tile_factor": 4, "kernels": 1},
+                                    {"block": 0, "waves_per_cu": 32, "tile_factor": 2, "kernels": 2},
+                                    {"block": 0, "waves_per_cu": 8, "tile_factor": 1, "kernels": 2}])
 def test_batch_bitwise_equals_per_diagram(energies, tuning):
     kernels = 0 if tuning is None else tuning["kernels"]
     items = _mixed_items(energies=energies, kernels=kernels)
@@ -98,6 +101,10 @@ def test_batch_bitwise_equals_per_diagram(energies, tuning):
     if kernels == 1:
         assert info["work_items"] >= len(items) and info["specialized_items"] == 0
         assert info["lds_classes"] >= 2          # orders 2..6 span more than one LDS class
+    elif kernels == 2:
+        # persistent kernels running every item's own tile functions
+        assert info["specialized_items"] == len(items) and info["capture_streams"] == 0
+        assert info["lds_classes"] >= 1 and info["work_items"] >= len(items)
     else:
         assert info["specialized_items"] == len(items) and info["lds_classes"] == 0
         assert info["capture_streams"] == 4
@@ -106,15 +113,15 @@ def test_batch_bitwise_equals_per_diagram(energies, tuning):
         ref_out, ref_sum = _per_diagram(it)
         torch.cuda.synchronize()
         assert torch.equal(it["out"], ref_out)
-        if kernels == 0:
-            assert torch.equal(it["out_sum"], ref_sum)       # the same kernels and reduction
+        if kernels in (0, 2):
+            assert torch.equal(it["out_sum"], ref_sum)       # the same tile functions and reduction
         else:
             # the row sum runs over the batch's tiles; it equals the per-diagram
             # one bit for bit when the tile size matches, else to rounding
             assert torch.allclose(it["out_sum"], ref_sum, rtol=1e-12, atol=1e-15 * float(ref_out.abs().sum()))
 
 
-@pytest.mark.parametrize("kernels", [0, 1])
+@pytest.mark.parametrize("kernels", [0, 1, 2])
 def test_graph_replays_are_identical(kernels):
     """Replay the batch graph several times with other GPU work and
     synchronizations in between; every replay gives the same bits."""
@@ -137,7 +144,7 @@ def test_graph_replays_are_identical(kernels):
             assert torch.equal(it["out_sum"], s)
 
 
-@pytest.mark.parametrize("kernels", [0, 1])
+@pytest.mark.parametrize("kernels", [0, 1, 2])
 def test_batch_outputs_only_sums(kernels):
     items = _mixed_items(n_per_order=1, kernels=kernels)
     for it in items:
@@ -180,7 +187,7 @@ def test_batch_host_errors():
     with pytest.raises(amd.AmiError):
         amd.Batch(items, {"block": 96, "waves_per_cu": 8, "tile_factor": 1})
     with pytest.raises(amd.AmiError):
-        amd.Batch(items, {"kernels": 2})
+        amd.Batch(items, {"kernels": 3})
 
 
 @pytest.mark.timeout(900)

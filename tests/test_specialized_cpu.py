@@ -202,3 +202,22 @@ def test_hiprtc_compiles_the_generated_source(tmp_path, monkeypatch, momentum, k
     # one code object per kernel: forward 1, adjoint 2, complex-energy forward 8
     found = sorted(k for p in srcs for k in kernels if f"#define AMI_JIT_KERNELS {k}\n" in p.read_text())
     assert found == sorted(kernels)
+
+
+def test_persistent_batch_module_compiles(tmp_path, monkeypatch):
+    """The source of one persistent batch module -- several diagrams' generated
+    functions, each in a namespace of its own with the tile functions, one
+    solution in two passes, and the persistent kernels -- compiles for gfx950
+    with hipRTC (no device needed)."""
+    monkeypatch.setenv("AMIGPU_CACHE_DIR", str(tmp_path))
+    ds = [random_self_energy(6, (0, 6, 0)), order2_example(), random_self_energy(3, (0, 3, 1)),
+          random_self_energy(4, (0, 4, 1))]
+    ts = [amd.Terms.from_diagram(d) for d in ds]
+    src = amd.batch_source(ts, [16, 16, 16, 1], momentum=True, compile=True)
+    for j in range(len(ds)):
+        assert f"#define amijit amijit_b{j}" in src
+    assert "ami_batch_p1" in src and "ami_batch_p2" in src         # order 6 (first): two passes
+    assert "amijit_b3::fwd_tile<true, true>" in src                 # one frequency row
+    assert "amijit_b1::fwd_tile<true, false>" in src
+    objs = [p for p in tmp_path.iterdir() if p.name.endswith(".hsaco")]
+    assert len(objs) == 1 and objs[0].stat().st_size > 10000
