@@ -115,7 +115,7 @@ AmiStatus amiReadGraph(const char *path, int32_t *edges, int32_t cap, int32_t *n
     *n_vertices = nv;
     if (!edges) return AMI_OK;
     if (cap < *n_edges) return fail(AMI_E_ARG, "edge buffer too small");
-    std::memcpy(edges, rows.data(), rows.size() * sizeof(int32_t));
+    if (!rows.empty()) std::memcpy(edges, rows.data(), rows.size() * sizeof(int32_t));   // an empty file has no rows
     return AMI_OK;
 }
 
