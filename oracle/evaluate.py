@@ -277,22 +277,26 @@ def gradients(terms, n_int: int, energies, ext_freqs, beta, cot, e_reg=0.0,
     dbeta = np.zeros(n_e, dtype=LD)
     dw = np.zeros((n_f, n_e, n_ext), dtype=CLD)
     for s, leaves, dens in terms:
-        ft = np.full(n_e, LD(s), dtype=LD)
-        dlnft_dE = np.zeros((n_e, n_eps), dtype=LD)
-        dlnft_db = np.zeros(n_e, dtype=LD)
-        for sigma, e in leaves:
-            assert abs(sigma) == 1, "gradients of Taylor-coefficient leaves are not implemented"
-            ev = np.asarray(e, dtype=LD)
-            x = E @ ev
-            if sigma == -1:
-                x = x + e_reg
-            f = leaf_value(sigma, beta * x)
-            ft = ft * f
-            # 1 - f_sigma(y) = f_sigma(-y) for both statistics; written this way
-            # it keeps full relative precision where f saturates at 1
-            one_minus = leaf_value(sigma, -beta * x)
-            dlnft_dE -= beta * one_minus[:, None] * ev[None, :]
-            dlnft_db -= x * one_minus
+        if any(abs(code) > 1 for code, _ in leaves):
+            ft, dft_dE, dft_db = _taylor_term_leaves(s, leaves, E, beta, e_reg)
+        else:
+            ft = np.full(n_e, LD(s), dtype=LD)
+            dlnft_dE = np.zeros((n_e, n_eps), dtype=LD)
+            dlnft_db = np.zeros(n_e, dtype=LD)
+            for sigma, e in leaves:
+                ev = np.asarray(e, dtype=LD)
+                x = E @ ev
+                if sigma == -1:
+                    x = x + e_reg
+                f = leaf_value(sigma, beta * x)
+                ft = ft * f
+                # 1 - f_sigma(y) = f_sigma(-y) for both statistics; written this way
+                # it keeps full relative precision where f saturates at 1
+                one_minus = leaf_value(sigma, -beta * x)
+                dlnft_dE -= beta * one_minus[:, None] * ev[None, :]
+                dlnft_db -= x * one_minus
+            dft_dE = ft[:, None] * dlnft_dE
+            dft_db = ft * dlnft_db
         for fi in range(n_f):
             r = np.ones(n_e, dtype=CLD)
             dlnr_dE = np.zeros((n_e, n_eps), dtype=CLD)
@@ -311,14 +315,52 @@ def gradients(terms, n_int: int, energies, ext_freqs, beta, cot, e_reg=0.0,
                         dlnr_dw[:, j] -= aj / d
             v = ft * r
             gf = g[fi]
-            dv_dE = v[:, None] * (dlnft_dE + dlnr_dE)
+            dv_dE = dft_dE * r[:, None] + v[:, None] * dlnr_dE
             dE += np.real(np.conj(gf)[:, None] * dv_dE)
-            dbeta += np.real(np.conj(gf) * v * dlnft_db)
+            dbeta += np.real(np.conj(gf) * r * dft_db)
             dv_dw = v[:, None] * dlnr_dw
             dw[fi] += gf[:, None] * np.conj(dv_dw)
     if per_sample:
         return dE, dbeta, dw
     return dE, np.sum(dbeta), np.sum(dw, axis=1)
+
+
+def _taylor_term_leaves(s, leaves, E, beta, e_reg):
+    """The Fermi-tree product ``s prod_l T_l`` of a term holding
+    Taylor-coefficient leaves (poles of higher order, Eq. (5)) and its
+    derivatives by the product rule, since a ``T_j`` can vanish.  With
+    ``T_j(x) = beta^j f^(j)(beta x) / j!`` (``leaf_coefficient``):
+    ``dT_j/dx = (j + 1) T_(j+1)`` and ``dT_j/dbeta = (j T_j + x (j + 1) T_(j+1)) / beta``
+    (the code of ``T_(j+1)`` is ``sigma (j + 2)``); x holds the regulator of a
+    Bose-type leaf.  Returns ``(ft [N_E], dft/dE [N_E, nE], dft/dbeta [N_E])``."""
+    n_e, n_eps = E.shape
+    vals, dx, db, evs = [], [], [], []
+    for code, e in leaves:
+        sigma = 1 if code > 0 else -1
+        j = abs(code) - 1
+        ev = np.asarray(e, dtype=LD)
+        x = E @ ev
+        if sigma == -1:
+            x = x + e_reg
+        t = leaf_coefficient(code, x, beta)
+        slope = (j + 1) * leaf_coefficient(sigma * (j + 2), x, beta)
+        vals.append(t)
+        dx.append(slope)
+        db.append((j * t + x * slope) / beta)
+        evs.append(ev)
+    ft = np.full(n_e, LD(s), dtype=LD)
+    for t in vals:
+        ft = ft * t
+    dft_dE = np.zeros((n_e, n_eps), dtype=LD)
+    dft_db = np.zeros(n_e, dtype=LD)
+    for i in range(len(vals)):
+        rest = np.full(n_e, LD(s), dtype=LD)
+        for m, t in enumerate(vals):
+            if m != i:
+                rest = rest * t
+        dft_dE += (rest * dx[i])[:, None] * evs[i][None, :]
+        dft_db += rest * db[i]
+    return ft, dft_dE, dft_db
 
 
 def momentum_gradients(alpha, k_int, q, t, mu, dE, dim: int = 2):

@@ -189,3 +189,61 @@ def test_double_pole_values_invariant_under_relabelling():
         np.testing.assert_allclose(other.astype(np.complex128), base.astype(np.complex128), rtol=1e-11, atol=1e-14)
         checked += 1
     assert checked >= 3
+
+
+@pytest.mark.parametrize("sigma", [1, -1])
+@pytest.mark.parametrize("j", [0, 1, 2])
+def test_taylor_leaf_slopes_against_mpmath(sigma, j):
+    """The derivatives the gradients take of a Taylor-coefficient leaf:
+    dT_j/dx = (j + 1) T_(j+1) and dT_j/dbeta = (j T_j + x (j + 1) T_(j+1)) / beta,
+    against 40-digit differentiation of T_j(x; beta) = (1/j!) d^j/dx^j f(beta x)."""
+    mp.mp.dps = 40
+
+    def T(x, b):
+        return mp.diff(lambda u: 1 / (sigma * mp.exp(b * u) + 1), x, j) / mp.factorial(j)
+    for x, beta in ((-1.3, 2.5), (0.42, 2.5), (2.2, 1.3)):
+        X, B = mp.mpf(x), mp.mpf(beta)
+        want_x = mp.diff(lambda u: T(u, B), X)
+        want_b = mp.diff(lambda b: T(X, b), B)
+        lx, lb = np.longdouble(x), np.longdouble(beta)
+        tj = leaf_coefficient(sigma * (j + 1), lx, lb)
+        slope = (j + 1) * leaf_coefficient(sigma * (j + 2), lx, lb)
+        got_b = (j * tj + lx * slope) / lb
+        assert abs(float(slope) - float(want_x)) <= 1e-14 * abs(float(want_x)) + 1e-300
+        assert abs(float(got_b) - float(want_b)) <= 1e-14 * abs(float(want_b)) + 1e-300
+
+
+@pytest.mark.parametrize("name", ["double", "later", "o3", "o4", "triple", "square_square", "triple_square"])
+def test_multipole_gradients_against_finite_differences(name):
+    """The oracle's analytic gradients of solutions with poles of higher order
+    (Taylor-coefficient leaves, powers of denominators) against central
+    differences of its own long-double values (step 1e-6: truncation and
+    rounding both below 1e-10 of the gradient's scale)."""
+    from oracle.evaluate import gradients
+    from parity import gradient_scales
+    alpha, eps, n_int, ferm = (CASES if name in CASES else SINGLE_SUM_CASES)[name]
+    terms = canonical(construct(alpha, eps, n_int, ferm, multipole=True))
+    assert any(abs(code) > 1 for _, leaves, _ in terms for code, _ in leaves)
+    beta = 2.0
+    rng = np.random.default_rng(11)
+    E = rng.uniform(-1.5, 1.5, size=(3, eps.shape[1])).astype(np.longdouble)
+    n_ext = alpha.shape[1] - n_int
+    w = np.array([[1j * np.pi / beta] * n_ext, [0.35 + 0.05j] * n_ext]) if n_ext else np.zeros((2, 0))
+    if name in SINGLE_SUM_CASES:     # bosonic external: an even Matsubara frequency
+        w = np.array([[2j * np.pi / beta] * n_ext, [0.35 + 0.05j] * n_ext])
+    cot = rng.standard_normal((2, 3)) + 1j * rng.standard_normal((2, 3))
+
+    def loss(Ev, b):
+        v = evaluate_terms(terms, n_int, Ev, w, b)
+        return np.real(np.sum(np.conj(cot) * v, axis=0))            # per sample
+    dE, db, _ = gradients(terms, n_int, E, w, beta, cot, per_sample=True)
+    sc = gradient_scales(terms, n_int, E, w, beta, cot)
+    h = np.longdouble(1e-6)
+    for i in range(E.shape[1]):
+        ep, em = E.copy(), E.copy()
+        ep[:, i] += h
+        em[:, i] -= h
+        fd = (loss(ep, beta) - loss(em, beta)) / (2 * h)
+        assert np.all(np.abs(dE[:, i] - fd) <= 1e-9 * np.maximum(sc["E"][:, i], 1e-300)), (i, dE[:, i], fd)
+    fd_b = (loss(E, np.longdouble(beta) + h) - loss(E, np.longdouble(beta) - h)) / (2 * h)
+    assert abs(float(np.sum(db)) - float(np.sum(fd_b))) <= 1e-9 * sc["beta"]
