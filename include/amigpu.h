@@ -252,12 +252,15 @@ AmiStatus amiEvaluateComplex(AmiTerms *terms,
  *                 (d/dRe w + i d/dIm w) (device, or NULL)
  * using d f_sigma/dy = -f_sigma (1 - f_sigma) for every leaf and
  * d(1/D)/dD = -1/D^2 for every denominator (the terms of Eq. (6) are products
- * of these).  Other arguments as amiEvaluate.  The sums over samples are
- * reduced in a fixed order.  Served by the specialized kernels (in one pass
- * up to 128 terms, in passes up to 4096; see the variants below) or by the
- * packed ones (every energy coefficient +-1, at most 255 distinct leaves and
+ * of these); a Taylor-coefficient leaf of a pole of higher order (Eq. (5)),
+ * T_j(x) = beta^j f^(j)(beta x) / j!, has dT_j/dx = (j + 1) T_(j+1) and
+ * dT_j/dbeta = (j T_j + x dT_j/dx) / beta.  Other arguments as amiEvaluate.
+ * The sums over samples are reduced in a fixed order.  Served by the
+ * specialized kernels (in one pass up to 128 terms, in passes up to 4096; see
+ * the variants below; poles of higher order only there) or by the packed ones
+ * (every energy coefficient +-1, at most 255 distinct leaves and
  * denominators, at most 8 of each per term, no leaf twice in one term):
- * AMI_E_UNSUPPORTED when none applies (e.g. poles of higher order).
+ * AMI_E_UNSUPPORTED when none applies.
  * out / out_sum (device, or NULL): the forward values, as amiEvaluate would
  * return them (up to rounding when the adjoint runs in passes), computed on
  * the way -- a value-and-gradient pass when the cotangents do not depend on
@@ -389,8 +392,7 @@ AmiStatus amiIntegrateHubbard(AmiTerms *terms, int64_t n_samples, uint64_t seed,
  *                            (stored), then one that forms the leaves'
  *                            cotangents by a reverse sweep of each group's
  *                            nested sum and finishes the gradients; its values
- *                            equal the forward's up to rounding.  No poles of
- *                            higher order
+ *                            equal the forward's up to rounding
  * A forced variant that cannot serve a call fails it (AMI_E_UNSUPPORTED, or
  * AMI_E_HIP when the run-time compilation fails); AUTO falls back in the order
  * above and amiLastVariant names what ran and why.
@@ -415,10 +417,11 @@ AmiStatus amiSetTwoPassChunkBytes(int64_t bytes);
  * out of later evaluate calls.  Host-blocking.  AMI_E_UNSUPPORTED when the
  * solution is outside the specialized form, AMI_E_HIP when compiling or loading
  * fails (amiLastError holds the compiler log).  The kernels are the forward
- * (its two passes where AUTO takes them), the adjoint where AUTO uses it (at
- * most 128 terms), and for solutions of at most 1024 terms the complex-energy
- * forward (amiEvaluateComplex) for the energy input; all are compiled before a device is touched.  A solution
- * with Taylor-coefficient leaves (AMI_MULTIPOLE) gets its forward only.
+ * (its two passes where AUTO takes them), the adjoint AUTO uses (one pass up
+ * to 128 terms, its passes above), and for solutions of at most 1024 terms the complex-energy
+ * forward (amiEvaluateComplex) for the energy input; all are compiled before a
+ * device is touched.  A solution with Taylor-coefficient leaves (AMI_MULTIPOLE)
+ * gets no complex-energy forward.
  */
 AmiStatus amiTermsSpecialize(AmiTerms *terms, int32_t momentum);
 

@@ -372,13 +372,7 @@ bool jit_supported(const AmiTerms *t, bool hub, std::string *why, bool two_pass)
 }
 
 bool jit_adjoint_passes_supported(const AmiTerms *t, bool hub, std::string *why) {
-    if (!jit_supported(t, hub, why, true)) return false;
-    for (int o : t->tab.leaf_order)
-        if (o > 0) {
-            if (why) *why = "Taylor-coefficient leaves (poles of higher order)";
-            return false;
-        }
-    return true;
+    return jit_supported(t, hub, why, true);
 }
 
 namespace {
@@ -390,6 +384,8 @@ constexpr int kParkBudget = 40;
 int park_chain(const AmiTerms *t, bool hub) { return hub ? 3 * t->n_g : 0; }
 bool park_dv(const AmiTerms *t, bool hub) {
     if (const char *e = std::getenv("AMIGPU_JIT_PARK_DV")) return std::atoi(e) != 0;   // tuning override
+    for (int o : t->tab.leaf_order)
+        if (o > 0) return false;              // Taylor-coefficient leaves: their slopes stay in registers
     return park_chain(t, hub) + t->tab.L <= kParkBudget;
 }
 int park_cols(const AmiTerms *t, bool hub) { return park_chain(t, hub) + (park_dv(t, hub) ? t->tab.L : 0); }
@@ -604,11 +600,11 @@ std::string jit_source(const AmiTerms *t, bool hub, int kernels) {
     }
 
     // Taylor-coefficient leaves (poles of higher order): T_j = beta^j f^(j) / j!,
-    // f^(j) as a polynomial in f and fm = f(-y) (f' = -f fm, fm' = f fm)
-    o << "__device__ __forceinline__ void taylor_leaves(double (&F)[L], const double (&FM)[L], double beta) {\n";
-    for (int l = 0; l < L; ++l) {
-        const int jo = tb.leaf_order[l];
-        if (jo == 0) continue;
+    // f^(j) as a polynomial in f and fm = f(-y) (f' = -f fm, fm' = f fm);
+    // taylor_expr writes statements that leave T_j of the values named f and m
+    // in `dst` (j = 0: f itself)
+    auto taylor_expr = [&](int jo, const std::string &dst, const std::string &pad) {
+        if (jo == 0) return pad + dst + " = f;\n";
         std::map<std::pair<int, int>, long long> poly{{{1, 0}, 1}};
         for (int step = 0; step < jo; ++step) {
             std::map<std::pair<int, int>, long long> nxt;
@@ -625,16 +621,43 @@ std::string jit_source(const AmiTerms *t, bool hub, int kernels) {
         for (int i = 2; i <= jo; ++i) fact *= i;
         std::string scale = "beta";
         for (int i = 1; i < jo; ++i) scale += " * beta";
-        o << "  { const double f = F[" << l << "], m = FM[" << l << "]; double acc = 0.0;\n";
+        std::string out = pad + "{ double acc = 0.0;\n";
         for (const auto &kv : poly) {
             std::string mono;
             for (int i = 0; i < kv.first.first; ++i) mono += (mono.empty() ? "f" : " * f");
             for (int i = 0; i < kv.first.second; ++i) mono += (mono.empty() ? "m" : " * m");
-            o << "    acc = fma(" << num(static_cast<double>(kv.second)) << ", " << mono << ", acc);\n";
+            out += pad + "  acc = fma(" + num(static_cast<double>(kv.second)) + ", " + mono + ", acc);\n";
         }
-        o << "    F[" << l << "] = acc * (" << scale << ") * " << num(1.0 / fact) << "; }\n";
+        out += pad + "  " + dst + " = acc * (" + scale + ") * " + num(1.0 / fact) + "; }\n";
+        return out;
+    };
+    bool taylor = false;
+    for (int l = 0; l < L; ++l) taylor = taylor || tb.leaf_order[l] > 0;
+    o << "constexpr bool kTaylor = " << (taylor ? "true" : "false") << ";\n";
+    o << "__device__ __forceinline__ void taylor_leaves(double (&F)[L], const double (&FM)[L], double beta) {\n";
+    for (int l = 0; l < L; ++l) {
+        const int jo = tb.leaf_order[l];
+        if (jo == 0) continue;
+        o << "  { const double f = F[" << l << "], m = FM[" << l << "];\n";
+        o << taylor_expr(jo, "F[" + std::to_string(l) + "]", "    ");
+        o << "  }\n";
     }
     o << "  (void)FM; (void)beta;\n}\n";
+    // the adjoint's derivatives of the leaves of a solution with Taylor
+    // coefficients: DX = dT_j/dx = (j + 1) T_(j+1), DB = dT_j/dbeta =
+    // (j T_j + x DX) / beta, from the plain leaf pair (f, fm) at x
+    o << "__device__ __forceinline__ void taylor_slopes(const double (&F)[L], const double (&FM)[L], const double "
+         "(&X)[L], double beta, double (&DX)[L], double (&DB)[L]) {\n";
+    if (taylor)
+        for (int l = 0; l < L; ++l) {
+            const int jo = tb.leaf_order[l];
+            o << "  { const double f = F[" << l << "], m = FM[" << l << "]; double tj = 0.0, tn = 0.0;\n";
+            o << taylor_expr(jo, "tj", "    ") << taylor_expr(jo + 1, "tn", "    ");
+            o << "    DX[" << l << "] = " << num(static_cast<double>(jo + 1)) << " * tn;\n";
+            o << "    DB[" << l << "] = fma(" << num(static_cast<double>(jo)) << ", tj, X[" << l << "] * DX[" << l
+              << "]) / beta; }\n";
+        }
+    o << "  (void)F; (void)FM; (void)X; (void)beta; (void)DX; (void)DB;\n}\n";
 
     // denominators D_k = e_k . E + a_k . w
     o << "__device__ __forceinline__ void den_args(const double (&E)[NE], const double (&wr)[" << NXA
@@ -909,7 +932,9 @@ std::string jit_source(const AmiTerms *t, bool hub, int kernels) {
              "*ws, int64_t ld, uint32_t off, double (&gE)[NE], double &gbeta) {\n";
         o << kReverseContract;
         o << "  (void)e_reg;\n";
-        for (int l = 0; l < L; ++l) o << "  double F" << l << ", FB" << l << ", DV" << l << ";\n";
+        // with Taylor-coefficient leaves DV holds dT/dx and DB dT/dbeta
+        for (int l = 0; l < L; ++l)
+            o << "  double F" << l << ", FB" << l << ", DV" << l << (taylor ? ", DB" + std::to_string(l) : "") << ";\n";
         auto leaf_arg = [&](int l) {
             Lin x;
             for (int i = 0; i < ne; ++i) x.add(tb.leaf_coef[static_cast<size_t>(l) * ne + i], idx("E", i));
@@ -920,8 +945,18 @@ std::string jit_source(const AmiTerms *t, bool hub, int kernels) {
             const Part &pt = parts[p];
             for (int l : pt.leaves) {
                 if (first_use[l] != static_cast<int>(p)) continue;
-                o << "  ami::leaf_and_slope(" << (tb.leaf_sigma[l] < 0 ? "true" : "false") << ", beta * ("
-                  << leaf_arg(l) << "), F" << l << ", DV" << l << ");\n  FB" << l << " = 0.0;\n";
+                if (taylor) {
+                    const int jo = tb.leaf_order[l];
+                    o << "  { const double x = " << leaf_arg(l) << ";\n    double f, m, tn = 0.0;\n    ami::leaf_pair("
+                      << (tb.leaf_sigma[l] < 0 ? "true" : "false") << ", beta * x, f, m);\n";
+                    o << taylor_expr(jo, "F" + std::to_string(l), "    ") << taylor_expr(jo + 1, "tn", "    ");
+                    o << "    DV" << l << " = " << num(static_cast<double>(jo + 1)) << " * tn;\n    DB" << l << " = fma("
+                      << num(static_cast<double>(jo)) << ", F" << l << ", x * DV" << l << ") / beta; }\n  FB" << l
+                      << " = 0.0;\n";
+                } else {
+                    o << "  ami::leaf_and_slope(" << (tb.leaf_sigma[l] < 0 ? "true" : "false") << ", beta * ("
+                      << leaf_arg(l) << "), F" << l << ", DV" << l << ");\n  FB" << l << " = 0.0;\n";
+                }
             }
             o << "  { const double tb = ami::ws_load(ws, ld, " << ftb0 << " + " << pt.g << ", off);\n";
             horner_emit(pt.nodes, fname, o);
@@ -950,8 +985,12 @@ std::string jit_source(const AmiTerms *t, bool hub, int kernels) {
             o << "  }\n";
             for (int l : pt.leaves) {
                 if (last_use[l] != static_cast<int>(p)) continue;
-                o << "  { const double fb = FB" << l << " * DV" << l << ";\n    gbeta = fma(fb, " << leaf_arg(l)
-                  << ", gbeta);\n    const double v = fb * beta;\n";
+                if (taylor)
+                    o << "  { gbeta = fma(FB" << l << ", DB" << l << ", gbeta);\n    const double v = FB" << l << " * DV"
+                      << l << ";\n";
+                else
+                    o << "  { const double fb = FB" << l << " * DV" << l << ";\n    gbeta = fma(fb, " << leaf_arg(l)
+                      << ", gbeta);\n    const double v = fb * beta;\n";
                 for (int i = 0; i < ne; ++i) {
                     const double c = tb.leaf_coef[static_cast<size_t>(l) * ne + i];
                     if (c == 1.0) o << "    gE[" << i << "] += v;\n";
@@ -1191,7 +1230,7 @@ extern "C" AmiStatus amiTermsSource(const AmiTerms *t, int32_t momentum, char *b
     if (!jit_supported(t, hub, &why, two_pass)) return fail(AMI_E_UNSUPPORTED, "no specialized kernel: " + why);
     int kernels = two_pass ? 48 | 64 | 128 : hub ? 7 : 11;
     for (int o : t->tab.leaf_order)
-        if (o > 0) kernels &= ~(2 | 8 | 64 | 128);   // Taylor-coefficient leaves: no adjoint, no complex energies
+        if (o > 0) kernels &= ~8;   // Taylor-coefficient leaves: no complex energies
     const std::string src = jit_source(t, hub, kernels);
     *len = static_cast<int64_t>(src.size()) + 1;
     if (!buf) return AMI_OK;

@@ -1128,7 +1128,7 @@ AmiStatus amiTermsSpecialize(AmiTerms *t, int32_t momentum) {
     if (!t) return ami::fail(AMI_E_ARG, "terms is NULL");
     using namespace ami;
     const bool hub = momentum != 0;
-    bool taylor = false;                    // Taylor-coefficient leaves: forward only
+    bool taylor = false;                    // Taylor-coefficient leaves: no complex energies
     for (int o : t->tab.leaf_order) taylor = taylor || o > 0;
     // the kernels for this input: forward, adjoint, and the complex-energy
     // forward for the energy input; all compiled before any device is touched
@@ -1140,8 +1140,8 @@ AmiStatus amiTermsSpecialize(AmiTerms *t, int32_t momentum) {
     } else {
         kinds.push_back(kJitForward);
     }
-    if (!taylor && t->tab.T <= kJitAutoAdjointTerms) kinds.push_back(kJitAdjoint);
-    if (!taylor && t->tab.T > kJitAutoAdjointTerms && jit_adjoint_passes_supported(t, hub, nullptr)) {
+    if (t->tab.T <= kJitAutoAdjointTerms) kinds.push_back(kJitAdjoint);
+    if (t->tab.T > kJitAutoAdjointTerms && jit_adjoint_passes_supported(t, hub, nullptr)) {
         if (!jit_prefers_two_pass(t)) kinds.push_back(kJitSumsPass);
         kinds.push_back(kJitAdjFreq);
         kinds.push_back(kJitAdjLeaf);

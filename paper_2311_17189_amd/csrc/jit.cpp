@@ -151,12 +151,10 @@ AmiStatus code_object(AmiTerms *t, bool hub, int kind) {
         err = "no specialized kernel: " + why;
         return fail(AMI_E_UNSUPPORTED, err);
     }
-    if (kind == kJitAdjoint || kind == kJitComplex || kind == kJitAdjFreq || kind == kJitAdjLeaf)
+    if (kind == kJitComplex)
         for (int o : t->tab.leaf_order)
             if (o > 0) {
-                err = kind != kJitComplex
-                          ? "no specialized adjoint for Taylor-coefficient leaves (poles of higher order)"
-                          : "no complex-energy kernel for Taylor-coefficient leaves (poles of higher order)";
+                err = "no complex-energy kernel for Taylor-coefficient leaves (poles of higher order)";
                 return fail(AMI_E_UNSUPPORTED, err);
             }
     const AmiStatus st = code_from_source(jit_source(t, hub, 1 << kind), code, err);

@@ -28,6 +28,7 @@ static_assert(!AMI_JIT_HUB || NG == NE, "momentum input: one energy per line");
 // (3 NG), then, with AMI_JIT_PARK_DV, the leaf derivatives f'(y_l) (L).
 constexpr int kParkChain = AMI_JIT_HUB ? 3 * NG : 0;
 constexpr bool kParkDv = AMI_JIT_PARK_DV;
+static_assert(!(kParkDv && kTaylor), "Taylor-coefficient leaves keep their slopes out of the park area");
 constexpr int kParkCols = kParkChain + (kParkDv ? L : 0);
 
 // Gradient rows (W doubles per sample, row-major, the wave's 64 consecutive
@@ -331,7 +332,8 @@ __device__ __forceinline__ void adj_grad_end(const KArgs &a, int64_t s_blk, int6
 // The end of the adjoint of one sample once its leaf cotangents FB are known:
 // the leaves' derivatives (f'(y) from Dv or the park area) scattered to the
 // energies and to beta, then adj_grad_end.  gE holds the energies' cotangent
-// so far.
+// so far.  A solution with Taylor-coefficient leaves recomputes the plain
+// leaf pairs here and takes dT/dx and dT/dbeta from taylor_slopes.
 template <bool HUB>
 __device__ __forceinline__ void adj_leaf_end(const KArgs &a, int64_t s_blk, int64_t s_end, bool active, double *gp,
                                              double *park, const double (&E)[NE], const double (&Dv)[kParkDv ? 1 : L],
@@ -340,12 +342,30 @@ __device__ __forceinline__ void adj_leaf_end(const KArgs &a, int64_t s_blk, int6
     const int tid = threadIdx.x, B = blockDim.x;
     double gbeta = 0.0, v[L], x[L];
     leaf_args(E, x);
+    if constexpr (kTaylor) {
+        double F[L], FM[L], DX[L], DB[L];
 #pragma unroll
-    for (int l = 0; l < L; ++l) {
-        if (kBose[l]) x[l] += a.e_reg;
-        const double fb = FB[l] * (kParkDv ? park[(kParkChain + l) * B + tid] : Dv[kParkDv ? 0 : l]);
-        v[l] = fb * a.beta;
-        gbeta = fma(fb, x[l], gbeta);
+        for (int l = 0; l < L; ++l) {
+            if (kBose[l]) x[l] += a.e_reg;
+            ami::leaf_pair(kBose[l], a.beta * x[l], F[l], FM[l]);
+        }
+        taylor_slopes(F, FM, x, a.beta, DX, DB);
+#pragma unroll
+        for (int l = 0; l < L; ++l) {
+            v[l] = FB[l] * DX[l];
+            gbeta = fma(FB[l], DB[l], gbeta);
+        }
+        (void)Dv;
+        (void)tid;
+        (void)B;
+    } else {
+#pragma unroll
+        for (int l = 0; l < L; ++l) {
+            if (kBose[l]) x[l] += a.e_reg;
+            const double fb = FB[l] * (kParkDv ? park[(kParkChain + l) * B + tid] : Dv[kParkDv ? 0 : l]);
+            v[l] = fb * a.beta;
+            gbeta = fma(fb, x[l], gbeta);
+        }
     }
     leaf_scatter(v, gE);
     adj_grad_end<HUB>(a, s_blk, s_end, active, gp, park, gE, gbeta);
@@ -375,13 +395,23 @@ __device__ __forceinline__ void adj_tile(const KArgs &a, int64_t blk, double *pa
     {
         double x[L];
         leaf_args(E, x);
+        if constexpr (kTaylor) {                // the forward's leaves; slopes at the end
+            double FM[L];
 #pragma unroll
-        for (int l = 0; l < L; ++l) {
-            if (kBose[l]) x[l] += a.e_reg;
-            double dv;                          // f'(y) = -f(y) f(-y)
-            ami::leaf_and_slope(kBose[l], a.beta * x[l], F[l], dv);
-            if constexpr (kParkDv) park[(kParkChain + l) * B + tid] = dv;
-            else Dv[kParkDv ? 0 : l] = dv;
+            for (int l = 0; l < L; ++l) {
+                if (kBose[l]) x[l] += a.e_reg;
+                ami::leaf_pair(kBose[l], a.beta * x[l], F[l], FM[l]);
+            }
+            taylor_leaves(F, FM, a.beta);
+        } else {
+#pragma unroll
+            for (int l = 0; l < L; ++l) {
+                if (kBose[l]) x[l] += a.e_reg;
+                double dv;                      // f'(y) = -f(y) f(-y)
+                ami::leaf_and_slope(kBose[l], a.beta * x[l], F[l], dv);
+                if constexpr (kParkDv) park[(kParkChain + l) * B + tid] = dv;
+                else Dv[kParkDv ? 0 : l] = dv;
+            }
         }
     }
     double FT[G], FTB[G];

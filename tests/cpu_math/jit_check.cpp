@@ -1,7 +1,7 @@
 // Host check of the generated part of the specialized evaluator: the
 // diagram's straight-line functions (leaf_args, group_sums, den_args,
 // group_products, groups_combine, den_cotangents, den_scatter, leaf_cotangents, leaf_scatter,
-// line_trig, line_scatter, taylor_leaves) compiled with a host compiler and driven one sample at
+// line_trig, line_scatter, taylor_leaves, taylor_slopes) compiled with a host compiler and driven one sample at
 // a time through the same steps as the device kernels, so a test can compare
 // values and gradients with the oracle.  The generated source is included
 // through AMI_GENERATED without its two #include lines.
@@ -80,7 +80,9 @@ int main() {
             ami::leaf_pair(kBose[l], beta * x[l], F[l], FM[l]);
             Dv[l] = -(F[l] * FM[l]);
         }
-        taylor_leaves(F, FM, beta);   // Taylor-coefficient leaves: values only
+        double DX[L], DB[L];          // Taylor-coefficient leaves: dT/dx, dT/dbeta
+        taylor_slopes(F, FM, x, beta, DX, DB);
+        taylor_leaves(F, FM, beta);
         double FT[G], FTB[G] = {0.0}, gE[NE] = {0.0};
         group_sums(F, FT);
         std::vector<double> gw(2 * static_cast<size_t>(n_f) * NXA, 0.0);
@@ -122,9 +124,14 @@ int main() {
         double FB[L] = {0.0}, v[L], gbeta = 0.0;
         leaf_cotangents(F, FTB, FB);
         for (int l = 0; l < L; ++l) {
-            const double fb = FB[l] * Dv[l];
-            v[l] = fb * beta;
-            gbeta = std::fma(fb, x[l], gbeta);
+            if (kTaylor) {
+                v[l] = FB[l] * DX[l];
+                gbeta = std::fma(FB[l], DB[l], gbeta);
+            } else {
+                const double fb = FB[l] * Dv[l];
+                v[l] = fb * beta;
+                gbeta = std::fma(fb, x[l], gbeta);
+            }
         }
         leaf_scatter(v, gE);
         double gmu = 0.0, gt = 0.0;

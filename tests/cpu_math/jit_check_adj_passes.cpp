@@ -79,6 +79,7 @@ int main() {
             ami::leaf_pair(kBose[l], beta * x[l], F[l], FM[l]);
             Dv[l] = -(F[l] * FM[l]);
         }
+        taylor_leaves(F, FM, beta);   // as the sums pass (Taylor-coefficient leaves)
         // workspace of one sample: FT_g, E_j, the denominators' energy
         // cotangents, FTB_g
         std::vector<double> ws(2 * static_cast<size_t>(G) + 2 * NE, 0.0);

@@ -1,17 +1,17 @@
 """Poles of higher order (Eq. (5)) in the library, on the CPU: the construction
 with AMI_MULTIPOLE against the oracle's term stream, bit for bit (including the
 extended stream of terms with unequal denominator counts), the error paths,
-and the generated straight-line functions (Taylor-coefficient leaves, groups
-with unequal denominator lists) compiled on the host and compared with the
-oracle's values."""
+and the generated straight-line functions (Taylor-coefficient leaves and their
+slopes, groups with unequal denominator lists) compiled on the host and
+compared with the oracle's values and analytic gradients."""
 import numpy as np
 import pytest
 
 from ami_inputs import matsubara_freqs, random_self_energy, real_freqs, uniform_energies
 from oracle.construct import canonical, construct, serialize
-from oracle.evaluate import evaluate_terms, term_magnitudes
+from oracle.evaluate import evaluate_terms, gradients, term_magnitudes
 
-from parity import check, far_from_poles, pole_distance
+from parity import check, far_from_poles, gradient_scales, pole_distance
 from multipole_cases import CASES, DOUBLE, repeated_line  # noqa: F401
 
 amd = pytest.importorskip("paper_2311_17189_amd")
@@ -55,39 +55,66 @@ def test_multipole_errors_and_simple_poles_unchanged():
         assert b.info()["uniform"] == 1
 
 
-@pytest.mark.parametrize("name", list(CASES))
-def test_generated_multipole_values_match_oracle(name, tmp_path):
+def _multipole_inputs(name, n=200):
     alpha, eps, n_int, ferm = CASES[name]
-    T = amd.Terms(alpha, eps, n_int, ferm, multipole=True)
-    exe = _harness(T.source(momentum=False), tmp_path, name)
     beta = 4.0
-    n_eps = eps.shape[1]
-    E = uniform_energies(200, n_eps, seed=(44, n_int, alpha.shape[0]), a=3.0)
+    E = uniform_energies(n, eps.shape[1], seed=(44, n_int, alpha.shape[0]), a=3.0)
     w = np.concatenate([matsubara_freqs(2, beta), real_freqs(1, 0.6, 0.6, 0.05)])
     if not ferm[-1]:
         w = np.concatenate([2j * np.pi * np.arange(1, 3) / beta, real_freqs(1, 0.6, 0.6, 0.05)])
     terms = _oracle(CASES[name])
     E = np.ascontiguousarray(E[far_from_poles(terms, n_int, E, w)])
-    cot = np.zeros((len(w), len(E)), dtype=np.complex128)
-    vals = _run(exe, n_eps, len(w), beta, 0.0, 1.0, 0.0, np.zeros(2), w[:, None], E, cot)[0]
+    rng = np.random.default_rng(48)
+    cot = rng.standard_normal((len(w), len(E))) + 1j * rng.standard_normal((len(w), len(E)))
+    return terms, beta, E, w, cot
+
+
+def _check_multipole(name, exe, label):
+    alpha, eps, n_int, ferm = CASES[name]
+    terms, beta, E, w, cot = _multipole_inputs(name)
+    vals, gE, gb, _, _, gw = _run(exe, eps.shape[1], len(w), beta, 0.0, 1.0, 0.0, np.zeros(2), w[:, None], E, cot)
     ref = evaluate_terms(terms, n_int, E, w, beta).astype(np.complex128)
     scale = term_magnitudes(terms, n_int, E, w, beta).astype(np.float64)
-    check(vals, ref, scale, pole_distance(terms, n_int, E, w), label=f"{name} multipole values")
+    check(vals, ref, scale, pole_distance(terms, n_int, E, w), label=f"{name} multipole values ({label})")
+    # the adjoint: dT_j/dx = (j + 1) T_(j+1) and dT_j/dbeta = (j T_j + x dT_j/dx) / beta
+    # for the Taylor-coefficient leaves, powers of denominators as repeated factors
+    dE, db, dw = gradients(terms, n_int, E, w, beta, cot)
+    sc = gradient_scales(terms, n_int, E, w, beta, cot)
+    assert np.max(np.abs(gE - dE.astype(np.float64)) / np.maximum(sc["E"], 1e-300)) <= 1e-10
+    assert abs(gb - float(db)) <= 1e-10 * sc["beta"]
+    if alpha.shape[1] > n_int:
+        assert np.max(np.abs(gw - dw.astype(np.complex128))) <= 1e-10 * sc["w"]
 
 
-def test_multipole_source_has_no_adjoint(tmp_path, monkeypatch):
+@pytest.mark.parametrize("name", list(CASES))
+def test_generated_multipole_values_and_gradients_match_oracle(name, tmp_path):
+    T = amd.Terms(*CASES[name], multipole=True)
+    src = T.source(momentum=False)
+    assert "taylor_slopes" in src and "constexpr bool kTaylor = true;" in src
+    _check_multipole(name, _harness(src, tmp_path, name), "one pass")
+
+
+@pytest.mark.parametrize("name", list(CASES))
+def test_generated_multipole_adjoint_passes_match_oracle(name, tmp_path):
+    T = amd.Terms(*CASES[name], multipole=True)
+    src = T.source(momentum=False, two_pass=True)
+    assert "void leaf_pass(" in src and "DB0" in src
+    _check_multipole(name, _harness(src, tmp_path, name + "p", "jit_check_adj_passes.cpp"), "passes")
+
+
+def test_multipole_source_has_adjoint_not_complex(tmp_path, monkeypatch):
     """The generated source of a multipole solution holds the forward kernel
-    and the Taylor-coefficient leaves, not the adjoint; amiTermsSpecialize
-    compiles that forward kernel alone (here, with no device, it then stops
-    at the device query)."""
+    and the adjoint (Taylor-coefficient leaves with their slopes), not the
+    complex-energy kernel; amiTermsSpecialize compiles those two (here, with
+    no device, it then stops at the device query)."""
     monkeypatch.setenv("AMIGPU_CACHE_DIR", str(tmp_path))
     T = amd.Terms(*DOUBLE, multipole=True)
     src = T.source(momentum=False)
-    assert "taylor_leaves" in src and "#define AMI_JIT_KERNELS 1\n" in src
+    assert "taylor_leaves" in src and "#define AMI_JIT_KERNELS 3\n" in src
     with pytest.raises(amd.AmiError) as e:
         T.specialize(momentum=False)
     assert e.value.code == -5 and "hipGetDevice" in str(e.value)
-    assert len([p for p in tmp_path.iterdir() if p.name.endswith(".hsaco")]) == 1
+    assert len([p for p in tmp_path.iterdir() if p.name.endswith(".hsaco")]) == 2
 
 
 @pytest.mark.parametrize("name", list(CASES))
