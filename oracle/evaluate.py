@@ -9,7 +9,8 @@
   columns) with the 2D Hubbard dispersion ``eps(k) = -2t(cos kx + cos ky) - mu``;
   energies are ``E = -eps`` (Sec. 2.2, below Eq. (2)).
 * :func:`gradients` -- analytic derivatives of a cotangent-weighted sum of the
-  result with respect to energies, beta, external frequencies, and through
+  result with respect to energies (real or complex), beta, external
+  frequencies, and through
   :func:`energies_from_k` with respect to momenta and ``mu``.
 
 Arithmetic is numpy ``longdouble`` (x87 80-bit on x86-64) unless a dtype is
@@ -261,9 +262,16 @@ def gradients(terms, n_int: int, energies, ext_freqs, beta, cot, e_reg=0.0,
     complex one in the convention ``conj(dI/dw) * cot`` summed over samples;
     with ``per_sample`` the last two are not summed: ``dbeta [N_E]``,
     ``dw [N_F, N_E, n_ext]``.
+
+    Complex energies (Sec. 5.1.3): every expression above is the same analytic
+    function of ``E`` (the leaf's ``d ln f/dy = -f(-y)`` holds at complex
+    ``y``), so ``dI/dE`` is complex and ``dE`` is returned complex in the
+    convention of ``dw``: ``sum_f cot * conj(dI/dE)``, which is
+    ``dL/dRe E + i dL/dIm E`` of the real ``L`` (its real part is the formula
+    for real energies).  ``dbeta`` stays real (beta is).
     """
-    assert not np.iscomplexobj(energies), "gradients are taken at real energies"
-    E = np.asarray(energies).astype(LD)
+    cplx = np.iscomplexobj(energies)
+    E = np.asarray(energies).astype(CLD if cplx else LD)
     w = np.asarray(ext_freqs)
     if w.ndim == 1:
         w = w[:, None]
@@ -273,16 +281,17 @@ def gradients(terms, n_int: int, energies, ext_freqs, beta, cot, e_reg=0.0,
     e_reg = LD(e_reg)
     n_e, n_eps = E.shape
     n_f, n_ext = w.shape
-    dE = np.zeros((n_e, n_eps), dtype=LD)
+    dE = np.zeros((n_e, n_eps), dtype=E.dtype)
     dbeta = np.zeros(n_e, dtype=LD)
     dw = np.zeros((n_f, n_e, n_ext), dtype=CLD)
     for s, leaves, dens in terms:
         if any(abs(code) > 1 for code, _ in leaves):
+            assert not cplx, "Taylor-coefficient leaves are taken at real energies"
             ft, dft_dE, dft_db = _taylor_term_leaves(s, leaves, E, beta, e_reg)
         else:
-            ft = np.full(n_e, LD(s), dtype=LD)
-            dlnft_dE = np.zeros((n_e, n_eps), dtype=LD)
-            dlnft_db = np.zeros(n_e, dtype=LD)
+            ft = np.full(n_e, LD(s), dtype=E.dtype)
+            dlnft_dE = np.zeros((n_e, n_eps), dtype=E.dtype)
+            dlnft_db = np.zeros(n_e, dtype=E.dtype)
             for sigma, e in leaves:
                 ev = np.asarray(e, dtype=LD)
                 x = E @ ev
@@ -316,7 +325,10 @@ def gradients(terms, n_int: int, energies, ext_freqs, beta, cot, e_reg=0.0,
             v = ft * r
             gf = g[fi]
             dv_dE = dft_dE * r[:, None] + v[:, None] * dlnr_dE
-            dE += np.real(np.conj(gf)[:, None] * dv_dE)
+            if cplx:
+                dE += gf[:, None] * np.conj(dv_dE)
+            else:
+                dE += np.real(np.conj(gf)[:, None] * dv_dE)
             dbeta += np.real(np.conj(gf) * r * dft_db)
             dv_dw = v[:, None] * dlnr_dw
             dw[fi] += gf[:, None] * np.conj(dv_dw)

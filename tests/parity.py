@@ -119,7 +119,7 @@ def gradient_scales(terms, n_int, E, w, beta, cot, e_reg=0.0, hubbard=None):
     contributions.  ``hubbard = (alpha, k, q, t, mu)`` adds the momentum path."""
     from oracle.evaluate import gradients, line_momenta
     E = np.asarray(E)
-    out = {"E": np.zeros(E.shape), "beta": 0.0, "w": 0.0}
+    out = {"E": np.zeros(E.shape, dtype=np.float64), "beta": 0.0, "w": 0.0}
     if hubbard is not None:
         alpha, k, q, t, mu = hubbard
         K = line_momenta(alpha, k, q).astype(np.float64)
@@ -130,7 +130,7 @@ def gradient_scales(terms, n_int, E, w, beta, cot, e_reg=0.0, hubbard=None):
         A = np.kron(np.asarray(alpha, dtype=np.float64), np.eye(2))
     for term in terms:
         de, db, dw = gradients([term], n_int, E, w, beta, cot, e_reg, per_sample=True)
-        de = de.astype(np.float64)
+        de = de.astype(np.complex128 if np.iscomplexobj(de) else np.float64)
         out["E"] += np.abs(de)
         out["beta"] += float(np.sum(np.abs(db.astype(np.float64))))
         out["w"] += float(np.sum(np.abs(dw.astype(np.complex128))))

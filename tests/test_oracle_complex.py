@@ -2,14 +2,16 @@
 complex, Sec. 5.1.3): the textbook second-order form continued to complex
 energies, the plain definition Eq. (1) by truncated Matsubara sums, the
 Cauchy-Riemann relations of an analytic function of the energies, conjugation
-symmetry, the real limit, and leaves far out on both sides (CPU only)."""
+symmetry, the real limit, leaves far out on both sides, and the analytic
+gradients at complex energies against central differences of the values in
+the real and the imaginary direction of every energy (CPU only)."""
 import numpy as np
 import pytest
 
 from ami_inputs import complex_energies, matsubara_freqs, order2_example, random_self_energy, uniform_energies
 from oracle.brute import brute_force
 from oracle.construct import canonical, construct
-from oracle.evaluate import CLD, LD, evaluate_terms, leaf_value, term_magnitudes
+from oracle.evaluate import CLD, LD, evaluate_terms, gradients, leaf_value, term_magnitudes
 
 
 def _terms(d, multipole=False):
@@ -113,3 +115,54 @@ def test_complex_leaves_far_out(sigma):
     # at moderate arguments the leaf equals the plain formula
     np.testing.assert_allclose(f[2:].astype(np.complex128),
                                (1 / (sigma * np.exp(y[2:]) + 1)).astype(np.complex128), rtol=1e-15)
+
+
+@pytest.mark.parametrize("order,i,e_reg", [(2, None, 0.0), (3, 0, 0.0), (4, 1, 0.0), (4, 3, 0.02)])
+def test_complex_gradients_against_central_differences(order, i, e_reg):
+    """dL/dRe E_j + i dL/dIm E_j of L = Re sum conj(c) I at complex energies,
+    dL/dbeta and dL/dw, against long-double central differences of the
+    oracle's values (step 1e-6: truncation and rounding below 1e-9 of each
+    gradient's scale); at real energies the real part is the real-energy
+    gradient.  A missing conjugate, a sign of the imaginary direction or a
+    leaf slope continued wrongly fails one of them."""
+    from parity import gradient_scales
+    d = order2_example() if i is None else random_self_energy(order, (0, order, i))
+    terms = _terms(d)
+    beta = 2.0
+    E = complex_energies(4, d.n_eps, seed=(85, order), eta=0.1).astype(CLD)
+    w = np.concatenate([matsubara_freqs(1, beta), [0.4 + 0.06j]])[:, None].astype(CLD)
+    rng = np.random.default_rng(86)
+    cot = rng.standard_normal((2, 4)) + 1j * rng.standard_normal((2, 4))
+
+    def loss(Ev, b, wv=w):
+        v = evaluate_terms(terms, d.n_int, Ev, wv, b, e_reg)
+        return np.real(np.sum(np.conj(cot) * v, axis=0))            # per sample
+
+    dE, db, dw = gradients(terms, d.n_int, E, w, beta, cot, e_reg, per_sample=True)
+    assert np.iscomplexobj(dE)
+    sc = gradient_scales(terms, d.n_int, E, w, beta, cot, e_reg)
+    h = LD(1e-6)
+    for j in range(d.n_eps):
+        ej = np.zeros(d.n_eps, dtype=CLD)
+        ej[j] = 1
+        fre = (loss(E + h * ej, beta) - loss(E - h * ej, beta)) / (2 * h)
+        fim = (loss(E + 1j * h * ej, beta) - loss(E - 1j * h * ej, beta)) / (2 * h)
+        err = np.abs(dE[:, j] - (fre + 1j * fim))
+        assert np.all(err <= 1e-9 * np.maximum(sc["E"][:, j], 1e-300)), (j, dE[:, j], fre + 1j * fim)
+    fb = (loss(E, LD(beta) + h) - loss(E, LD(beta) - h)) / (2 * h)
+    assert abs(float(np.sum(db)) - float(np.sum(fb))) <= 1e-9 * sc["beta"]
+    for f in range(2):
+        df = np.zeros_like(w)
+        df[f, 0] = 1
+        fre = np.sum(loss(E, beta, w + h * df) - loss(E, beta, w - h * df)) / (2 * h)
+        fim = np.sum(loss(E, beta, w + 1j * h * df) - loss(E, beta, w - 1j * h * df)) / (2 * h)
+        assert abs(complex(np.sum(dw[f, :, 0])) - complex(fre + 1j * fim)) <= 1e-9 * sc["w"], f
+    # the real limit: real energies given as complex numbers
+    Er = uniform_energies(5, d.n_eps, seed=87, a=3.0)
+    c5 = rng.standard_normal((2, 5)) + 1j * rng.standard_normal((2, 5))
+    gr, br, wr = gradients(terms, d.n_int, Er, w, beta, c5, e_reg)
+    gc, bc, wc = gradients(terms, d.n_int, Er.astype(np.complex128), w, beta, c5, e_reg)
+    scr = gradient_scales(terms, d.n_int, Er, w, beta, c5, e_reg)
+    assert np.max(np.abs(np.real(gc) - gr) / np.maximum(scr["E"], 1e-300)) <= 1e-17
+    assert abs(float(bc) - float(br)) <= 1e-17 * scr["beta"]
+    assert np.max(np.abs(wc - wr)) <= 1e-17 * scr["w"]
