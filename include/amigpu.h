@@ -232,13 +232,41 @@ AmiStatus amiEvaluateHubbard(AmiTerms *terms,
  * beta x = i pi (2n+1), which the caller keeps away from.  Served by the
  * specialized kernels only (compiled on first use, as AMI_VARIANT_SPECIALIZED):
  * AMI_E_UNSUPPORTED for solutions outside their form and for poles of higher
- * order (AMI_MULTIPOLE).  No adjoint.
+ * order (AMI_MULTIPOLE).  Its adjoint is amiEvaluateComplexAdjoint.
  */
 AmiStatus amiEvaluateComplex(AmiTerms *terms,
                              const double *energies, int64_t n_e, int64_t stride_s, int64_t stride_i,
                              const double *ext_freqs, int64_t n_f,
                              double beta, double e_reg,
                              double *out, double *out_sum, void *hip_stream);
+
+/*
+ * amiEvaluateComplexAdjoint -- reverse-mode derivatives of amiEvaluateComplex
+ * (Sec. 5.1.3: complex energies).  The result is analytic in every energy, so
+ * for the real objective L = Re sum_{f,s} conj(c[f][s]) out[f][s], with
+ * c[f][s] = grad_out[f][s] + grad_sum[f] (either may be NULL, not both), it
+ * returns
+ *   grad_energies complex [n_e][n_eps] row-major, interleaved (device, or
+ *                 NULL): dL/dRe E + i dL/dIm E = sum_f c[f][s] conj(dI/dE),
+ *                 the convention of grad_freqs; at real energies its real
+ *                 part is amiEvaluateAdjoint's grad_energies
+ *   grad_beta     [1]: dL/dbeta (real; device, or NULL)
+ *   grad_freqs    complex [n_f][n_ext]: as amiEvaluateAdjoint (device, or NULL)
+ * using f_sigma'(y) = -f_sigma(y) f_sigma(-y) at complex y and
+ * d(1/D)/dD = -1/D^2.  energies, strides, ext_freqs, beta, e_reg: as
+ * amiEvaluateComplex; out / out_sum (device, or NULL) receive the forward
+ * values on the way.  The sums over samples are reduced in a fixed order.
+ * Served by one specialized kernel (compiled on first use; at most 1024
+ * terms): AMI_E_UNSUPPORTED for solutions outside its form and for poles of
+ * higher order.
+ */
+AmiStatus amiEvaluateComplexAdjoint(AmiTerms *terms,
+                                    const double *energies, int64_t n_e, int64_t stride_s, int64_t stride_i,
+                                    const double *ext_freqs, int64_t n_f,
+                                    double beta, double e_reg,
+                                    const double *grad_out, const double *grad_sum,
+                                    double *grad_energies, double *grad_beta, double *grad_freqs,
+                                    double *out, double *out_sum, void *hip_stream);
 
 /*
  * amiEvaluateAdjoint -- reverse-mode derivatives of the batched evaluation.
@@ -418,10 +446,11 @@ AmiStatus amiSetTwoPassChunkBytes(int64_t bytes);
  * solution is outside the specialized form, AMI_E_HIP when compiling or loading
  * fails (amiLastError holds the compiler log).  The kernels are the forward
  * (its two passes where AUTO takes them), the adjoint AUTO uses (one pass up
- * to 128 terms, its passes above), and for solutions of at most 1024 terms the complex-energy
- * forward (amiEvaluateComplex) for the energy input; all are compiled before a
+ * to 128 terms, its passes above), and for solutions of at most 1024 terms
+ * the complex-energy forward and its adjoint (amiEvaluateComplex,
+ * amiEvaluateComplexAdjoint) for the energy input; all are compiled before a
  * device is touched.  A solution with Taylor-coefficient leaves (AMI_MULTIPOLE)
- * gets no complex-energy forward.
+ * gets no complex-energy kernels.
  */
 AmiStatus amiTermsSpecialize(AmiTerms *terms, int32_t momentum);
 

@@ -94,6 +94,8 @@ def load_library():
     lib.amiEvaluateAdjoint.argtypes = [vp, vp, c_i64, c_i64, c_i64, vp, c_i64, c_dbl, c_dbl, vp, vp,
                                        vp, vp, vp, vp, vp, vp]
     lib.amiEvaluateAdjoint.restype = c_i32
+    lib.amiEvaluateComplexAdjoint.argtypes = lib.amiEvaluateAdjoint.argtypes
+    lib.amiEvaluateComplexAdjoint.restype = c_i32
     lib.amiEvaluateHubbardAdjoint.argtypes = [vp, vp, c_i64, c_i64, vp, c_dbl, c_dbl, vp, c_i64, c_dbl,
                                               c_dbl, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp]
     lib.amiEvaluateHubbardAdjoint.restype = c_i32
@@ -485,6 +487,35 @@ def evaluate_adjoint(terms: Terms, energies, ext_freqs, beta: float, e_reg: floa
     out, out_sum = _outputs(n_f, n_e, dev, False, False, out, out_sum)
     energies, st_s, st_i = _energy_strides(energies)
     _check(load_library().amiEvaluateAdjoint(
+        terms._h, energies.data_ptr() if n_e else None, n_e, st_s, st_i,
+        w.data_ptr(), n_f, float(beta), float(e_reg), _ptr(go), _ptr(gs),
+        g_e.data_ptr() if n_e else None, g_b.data_ptr(), g_w.data_ptr(),
+        _ptr(out) if n_e else None, _ptr(out_sum), _stream_ptr(stream)))
+    return g_e, g_b, g_w
+
+
+def evaluate_complex_adjoint(terms: Terms, energies, ext_freqs, beta: float, e_reg: float = 0.0,
+                             grad_out=None, grad_sum=None, out=None, out_sum=None, stream=None):
+    """``amiEvaluateComplexAdjoint``: ``energies`` complex128 CUDA [N_E, nE]
+    (any strides); returns ``(grad_energies [N_E, nE] complex128 (dL/dRe E +
+    i dL/dIm E), grad_beta [], grad_freqs [N_F, n_ext])`` for the cotangents of
+    ``out`` / ``out_sum``; ``out`` / ``out_sum`` tensors, if given, receive the
+    forward values."""
+    import torch
+    if energies.dtype != torch.complex128 or not energies.is_cuda or energies.dim() != 2:
+        raise AmiError(-1, "energies must be a complex128 CUDA tensor [N_E, nE]")
+    if energies.shape[1] != terms.n_eps:
+        raise AmiError(-1, f"energies has {energies.shape[1]} columns, terms expect {terms.n_eps}")
+    w = _freqs(ext_freqs, terms)
+    n_e, n_f = energies.shape[0], w.shape[0]
+    dev = energies.device
+    go, gs = _cot(grad_out, grad_sum, n_f, n_e, dev)
+    g_e = torch.empty((n_e, terms.n_eps), dtype=torch.complex128, device=dev)
+    g_b = torch.empty((), dtype=torch.float64, device=dev)
+    g_w = torch.empty((n_f, w.shape[1]), dtype=torch.complex128, device=dev)
+    out, out_sum = _outputs(n_f, n_e, dev, False, False, out, out_sum)
+    energies, st_s, st_i = _energy_strides(energies)
+    _check(load_library().amiEvaluateComplexAdjoint(
         terms._h, energies.data_ptr() if n_e else None, n_e, st_s, st_i,
         w.data_ptr(), n_f, float(beta), float(e_reg), _ptr(go), _ptr(gs),
         g_e.data_ptr() if n_e else None, g_b.data_ptr(), g_w.data_ptr(),

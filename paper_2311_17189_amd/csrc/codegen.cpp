@@ -521,8 +521,8 @@ std::string jit_source(const AmiTerms *t, bool hub, int kernels) {
     // (the host checks compile them); a two-pass source of a large solution
     // holds only what its two kernels use
     const bool small = tb.T <= kJitMaxTerms;
-    const bool one_pass = (kernels & 15) != 0;
-    const bool adj_fns = (kernels & 2) || ((kernels & 1) && small);
+    const bool one_pass = (kernels & (15 | 256)) != 0;
+    const bool adj_fns = (kernels & (2 | 256)) || ((kernels & 1) && small);
     // With `opaque`, every group first takes copies of the leaves it reads
     // through an empty asm (no instruction): the compiler then cannot merge
     // equal products of different groups, which for large solutions would
@@ -571,7 +571,7 @@ std::string jit_source(const AmiTerms *t, bool hub, int kernels) {
 
     // complex group sums (complex energies): each group's sum nested as the
     // real group sums, in complex arithmetic
-    if (kernels & 8) {
+    if (kernels & (8 | 256)) {
         o << "__device__ __forceinline__ void group_sums_c(const double (&Fr)[L], const double (&Fi)[L], double "
              "(&FTr)[G], double (&FTi)[G]) {\n";
         auto leaf = [&](int l) {
@@ -1076,6 +1076,57 @@ std::string jit_source(const AmiTerms *t, bool hub, int kernels) {
         }
     }
     o << "}\n";
+
+    // the same at complex energies: FB_l += sum over the terms holding l of
+    // s FTB_g prod_(others) F, in complex arithmetic (the caller passes
+    // conj(F), which makes the update FTB_g conj(dFT_g/dF_l))
+    if (kernels & 256) {
+    o << "__device__ __forceinline__ void leaf_cotangents_c(const double (&Fr)[L], const double (&Fi)[L], const double "
+         "(&FTBr)[G], const double (&FTBi)[G], double (&FBr)[L], double (&FBi)[L]) {\n";
+    o << kReverseContract;
+    for (int g = 0; g < G; ++g) {
+        for (int ti = tb.group_start[g]; ti < tb.group_start[g + 1]; ++ti) {
+            const double s = tb.term_sign[ti];
+            std::vector<int> lv(ni);
+            for (int j = 0; j < ni; ++j) lv[j] = tb.term_leaf[static_cast<size_t>(ti) * ni + j];
+            const bool unit = s == 1.0 || s == -1.0;
+            const std::string sg = s == -1.0 ? "-" : "";
+            auto F = [&](const char *part, int j) { return std::string(part) + "[" + std::to_string(lv[j]) + "]"; };
+            o << "  { const double p0r = FTBr[" << g << "]" << (unit ? "" : " * " + num(s)) << ", p0i = FTBi[" << g
+              << "]" << (unit ? "" : " * " + num(s)) << ";\n";
+            for (int j = 1; j < ni; ++j) {
+                const std::string pr = "p" + std::to_string(j - 1) + "r", pi = "p" + std::to_string(j - 1) + "i";
+                o << "    const double p" << j << "r = fma(" << pr << ", " << F("Fr", j - 1) << ", -" << pi << " * "
+                  << F("Fi", j - 1) << "), p" << j << "i = fma(" << pr << ", " << F("Fi", j - 1) << ", " << pi
+                  << " * " << F("Fr", j - 1) << ");\n";
+            }
+            o << "    double qr = 1.0, qi = 0.0;\n";
+            for (int j = ni - 1; j >= 0; --j) {
+                const std::string pr = "p" + std::to_string(j) + "r", pi = "p" + std::to_string(j) + "i";
+                const std::string fbr = F("FBr", j), fbi = F("FBi", j);
+                if (j == ni - 1) {
+                    o << "    " << fbr << (s == -1.0 ? " -= " : " += ") << pr << ";\n";
+                    o << "    " << fbi << (s == -1.0 ? " -= " : " += ") << pi << ";\n";
+                } else {
+                    o << "    " << fbr << " = fma(" << sg << pr << ", qr, fma(" << (s == -1.0 ? "" : "-") << pi
+                      << ", qi, " << fbr << "));\n";
+                    o << "    " << fbi << " = fma(" << sg << pr << ", qi, fma(" << sg << pi << ", qr, " << fbi
+                      << "));\n";
+                }
+                if (j > 0) {
+                    if (j == ni - 1) {
+                        o << "    qr = " << F("Fr", j) << "; qi = " << F("Fi", j) << ";\n";
+                    } else {
+                        o << "    { const double tr = fma(qr, " << F("Fr", j) << ", -qi * " << F("Fi", j)
+                          << "); qi = fma(qr, " << F("Fi", j) << ", qi * " << F("Fr", j) << "); qr = tr; }\n";
+                    }
+                }
+            }
+            o << "    (void)qr; (void)qi; }\n";
+        }
+    }
+    o << "}\n";
+    }
     }  // adj_fns
 
     // the leaves' and lines' scatters: every adjoint kernel (one pass, or the
@@ -1228,9 +1279,9 @@ extern "C" AmiStatus amiTermsSource(const AmiTerms *t, int32_t momentum, char *b
     const bool hub = (momentum & 1) != 0, two_pass = (momentum & 2) != 0;
     std::string why;
     if (!jit_supported(t, hub, &why, two_pass)) return fail(AMI_E_UNSUPPORTED, "no specialized kernel: " + why);
-    int kernels = two_pass ? 48 | 64 | 128 : hub ? 7 : 11;
+    int kernels = two_pass ? 48 | 64 | 128 : hub ? 7 : 11 | 256;
     for (int o : t->tab.leaf_order)
-        if (o > 0) kernels &= ~8;   // Taylor-coefficient leaves: no complex energies
+        if (o > 0) kernels &= ~(8 | 256);   // Taylor-coefficient leaves: no complex energies
     const std::string src = jit_source(t, hub, kernels);
     *len = static_cast<int64_t>(src.size()) + 1;
     if (!buf) return AMI_OK;

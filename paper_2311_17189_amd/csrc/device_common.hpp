@@ -238,7 +238,12 @@ __device__ __forceinline__ double leaf_deriv(bool bose, double y) {
 // with m = t - 1 (exp_split) and cos zi - 1 = -sin^2 zi/(1 + cos zi) where
 // cos zi > 0, so Q keeps full relative precision near y = 0.  The imaginary
 // part is reduced modulo 2 pi first (reduce_2pi, exact for |yi| < 6e6).
-__device__ __forceinline__ void leaf_complex(bool bose, double yr, double yi, double &fr, double &fi) {
+// leaf_complex_pair also gives f(-y): for -y the same z, w and Q arise (where
+// yr = 0, w/Q equals f(-y) at z = y), with the two quotients exchanged:
+// f(y) = w/Q and f(-y) = sigma/Q where yr > 0, the other way round elsewhere.
+// The adjoint's slope is f'(y) = -f(y) f(-y).
+__device__ __forceinline__ void leaf_complex_pair(bool bose, double yr, double yi, double &fr, double &fi,
+                                                  double &mr, double &mi) {
     const bool pos = yr > 0.0;
     double t, m, s, c;
     exp_split(-fmin(fabs(yr), 700.0), t, m);
@@ -254,13 +259,19 @@ __device__ __forceinline__ void leaf_complex(bool bose, double yr, double yi, do
     const double qi = wi;
     const double r = rcp_nr(fma(qr, qr, qi * qi));
     const double ir = qr * r, ii = -qi * r;                 // 1/Q
-    if (pos) {                                              // w/Q
-        fr = fma(wr, ir, -wi * ii);
-        fi = fma(wr, ii, wi * ir);
-    } else {                                                // sigma/Q
-        fr = bose ? -ir : ir;
-        fi = bose ? -ii : ii;
-    }
+    const double ar = fma(wr, ir, -wi * ii), ai = fma(wr, ii, wi * ir);   // w/Q
+    const double br = bose ? -ir : ir, bi = bose ? -ii : ii;             // sigma/Q
+    fr = pos ? ar : br;
+    fi = pos ? ai : bi;
+    mr = pos ? br : ar;
+    mi = pos ? bi : ai;
+}
+
+__device__ __forceinline__ void leaf_complex(bool bose, double yr, double yi, double &fr, double &fi) {
+    double mr, mi;
+    leaf_complex_pair(bose, yr, yi, fr, fi, mr, mi);
+    (void)mr;
+    (void)mi;
 }
 
 // ---- counter-based random numbers -----------------------------------------

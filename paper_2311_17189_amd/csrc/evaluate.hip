@@ -937,6 +937,66 @@ AmiStatus amiEvaluateComplex(AmiTerms *t, const double *energies, int64_t n_e, i
     return AMI_OK;
 }
 
+AmiStatus amiEvaluateComplexAdjoint(AmiTerms *t, const double *energies, int64_t n_e, int64_t stride_s,
+                                    int64_t stride_i, const double *ext_freqs, int64_t n_f, double beta, double e_reg,
+                                    const double *grad_out, const double *grad_sum, double *grad_energies,
+                                    double *grad_beta, double *grad_freqs, double *out, double *out_sum,
+                                    void *hip_stream) {
+    using namespace ami;
+    clear_error();
+    AmiStatus st = check_common(t, n_e, ext_freqs, n_f, beta);
+    if (st == AMI_OK) st = check_energies(t, n_e, energies, stride_s, stride_i);
+    if (st != AMI_OK) return st;
+    if (!grad_out && !grad_sum) return fail(AMI_E_ARG, "grad_out and grad_sum are both NULL");
+    const hipStream_t stream = static_cast<hipStream_t>(hip_stream);
+    DeviceTables *dt = nullptr;
+    st = upload(t, &dt);
+    if (st != AMI_OK) return st;
+    void *fn = nullptr;
+    st = jit_get(t, false, kJitComplexAdj, &fn);
+    if (st != AMI_OK) return st;
+    const int nx = t->n_ext;
+    const int ncols = kAdjScalars + 2 * static_cast<int>(n_f) * nx;
+    if (n_e == 0) {
+        st = fill(grad_beta, 1, stream);
+        if (st == AMI_OK) st = fill(out_sum, 2 * n_f, stream);
+        if (st == AMI_OK) st = fill(grad_freqs, 2 * n_f * nx, stream);
+        return st;
+    }
+    const int block = jit_block(t, false);
+    const int64_t nblocks = (n_e + block - 1) / block;
+    if (nblocks > 0x7fffffffLL) return fail(AMI_E_ARG, "n_e too large");
+    const int64_t rows = nblocks * (block / 64);   // partial sums per wave
+    const size_t n_grad = static_cast<size_t>(rows) * ncols;
+    const size_t n_val = out_sum ? static_cast<size_t>(rows) * n_f * 2 : 0;
+    double *partial = nullptr;
+    st = workspace(t, dt, stream, (n_grad + n_val) * sizeof(double), &partial);
+    if (st != AMI_OK) return st;
+    KArgs a;
+    std::memset(&a, 0, sizeof(a));
+    a.energies = energies;
+    a.stride_s = stride_s;
+    a.stride_i = stride_i;
+    set_common(a, ext_freqs, n_f, beta, e_reg, n_e);
+    a.g_out = grad_out;
+    a.g_sum = grad_sum;
+    a.grad_e = grad_energies;
+    a.out = out;
+    a.nrows = rows;
+    a.gpartial = partial;
+    a.partial = out_sum ? partial + n_grad : nullptr;
+    hipError_t e = launch_jit(fn, nblocks, block, stream, a);
+    if (e == hipSuccess) e = hipGetLastError();
+    g_last_variant = "specialized complex";
+    if (e != hipSuccess) return hip_fail(e, "complex-energy adjoint launch");
+    const int n_red = ncols + (out_sum ? 2 * static_cast<int>(n_f) : 0);
+    hipLaunchKernelGGL(ami_adj_finalize_kernel, dim3(n_red), dim3(kRedThreads), 0, stream, partial, rows, ncols, 1,
+                       grad_beta, static_cast<double *>(nullptr), static_cast<double *>(nullptr), grad_freqs,
+                       2 * static_cast<int>(n_f), out_sum);
+    e = hipGetLastError();
+    return e == hipSuccess ? AMI_OK : hip_fail(e, "adjoint reduction launch");
+}
+
 AmiStatus amiEvaluateHubbard(AmiTerms *t, const double *k, int64_t n_e, int64_t stride_k, const double *q,
                              double hop_t, double mu, const double *ext_freqs, int64_t n_f, double beta,
                              double e_reg, double *out, double *out_sum, void *hip_stream) {
@@ -1146,7 +1206,10 @@ AmiStatus amiTermsSpecialize(AmiTerms *t, int32_t momentum) {
         kinds.push_back(kJitAdjFreq);
         kinds.push_back(kJitAdjLeaf);
     }
-    if (!taylor && small && !hub) kinds.push_back(kJitComplex);
+    if (!taylor && small && !hub) {
+        kinds.push_back(kJitComplex);
+        kinds.push_back(kJitComplexAdj);
+    }
     for (int k : kinds) {
         const AmiStatus st = jit_compile(t, hub, k);
         if (st != AMI_OK) return st;

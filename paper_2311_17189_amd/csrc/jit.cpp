@@ -139,6 +139,9 @@ AmiStatus compile(const std::string &src, std::vector<char> &code, std::string &
 }
 
 // Code object for (t, kind): from the handle, the disk cache, or a compilation.
+static_assert(sizeof(AmiTerms::jit_code) / sizeof(AmiTerms::jit_code[0]) == 2 * kJitKinds,
+              "one code object per input and kind");
+
 AmiStatus code_object(AmiTerms *t, bool hub, int kind) {
     const int slot = kJitKinds * (hub ? 1 : 0) + kind;
     std::vector<char> &code = t->jit_code[slot];
@@ -151,7 +154,7 @@ AmiStatus code_object(AmiTerms *t, bool hub, int kind) {
         err = "no specialized kernel: " + why;
         return fail(AMI_E_UNSUPPORTED, err);
     }
-    if (kind == kJitComplex)
+    if (kind == kJitComplex || kind == kJitComplexAdj)
         for (int o : t->tab.leaf_order)
             if (o > 0) {
                 err = "no complex-energy kernel for Taylor-coefficient leaves (poles of higher order)";
@@ -183,14 +186,16 @@ AmiStatus code_from_source(const std::string &src, std::vector<char> &code, std:
 }
 
 AmiStatus jit_compile(AmiTerms *t, bool hub, int kind) {
-    if (kind < kJitForward || kind >= kJitKinds || (kind == kJitMonteCarlo && !hub) || (kind == kJitComplex && hub))
+    if (kind < kJitForward || kind >= kJitKinds || (kind == kJitMonteCarlo && !hub) ||
+        ((kind == kJitComplex || kind == kJitComplexAdj) && hub))
         return fail(AMI_E_ARG, "no such specialized kernel");
     std::lock_guard<std::mutex> lock(t->jit_mu);
     return code_object(t, hub, kind);
 }
 
 AmiStatus jit_get(AmiTerms *t, bool hub, int kind, void **fn) {
-    if (kind < kJitForward || kind >= kJitKinds || (kind == kJitMonteCarlo && !hub) || (kind == kJitComplex && hub))
+    if (kind < kJitForward || kind >= kJitKinds || (kind == kJitMonteCarlo && !hub) ||
+        ((kind == kJitComplex || kind == kJitComplexAdj) && hub))
         return fail(AMI_E_ARG, "no such specialized kernel");
     std::lock_guard<std::mutex> lock(t->jit_mu);
     const int slot = kJitKinds * (hub ? 1 : 0) + kind;
@@ -209,8 +214,9 @@ AmiStatus jit_get(AmiTerms *t, bool hub, int kind, void **fn) {
     e = hipModuleLoadData(&mod, t->jit_code[slot].data());
     if (e != hipSuccess) return hip_fail(e, "hipModuleLoadData (specialized kernel)");
     hipFunction_t f = nullptr;
-    static const char *const kNames[kJitKinds] = {"ami_jit_fwd",  "ami_jit_adj",  "ami_jit_mc",   "ami_jit_cfwd",
-                                                  "ami_jit_sums", "ami_jit_freq", "ami_jit_adjf", "ami_jit_adjl"};
+    static const char *const kNames[kJitKinds] = {"ami_jit_fwd",  "ami_jit_adj",  "ami_jit_mc",
+                                                  "ami_jit_cfwd", "ami_jit_sums", "ami_jit_freq",
+                                                  "ami_jit_adjf", "ami_jit_adjl", "ami_jit_cadj"};
     e = hipModuleGetFunction(&f, mod, kNames[kind]);
     if (e != hipSuccess) {
         (void)hipModuleUnload(mod);
@@ -227,7 +233,8 @@ AmiStatus jit_get(AmiTerms *t, bool hub, int kind, void **fn) {
 }
 
 AmiStatus jit_loaded(AmiTerms *t, bool hub, int kind, void **fn) {
-    if (kind < kJitForward || kind >= kJitKinds || (kind == kJitMonteCarlo && !hub) || (kind == kJitComplex && hub))
+    if (kind < kJitForward || kind >= kJitKinds || (kind == kJitMonteCarlo && !hub) ||
+        ((kind == kJitComplex || kind == kJitComplexAdj) && hub))
         return fail(AMI_E_ARG, "no such specialized kernel");
     std::lock_guard<std::mutex> lock(t->jit_mu);
     const int slot = kJitKinds * (hub ? 1 : 0) + kind;

@@ -44,7 +44,8 @@ int jit_block(const AmiTerms *t, bool hub);
 // kernels & 32: per frequency, reciprocals and group products against them),
 // and the passes of the adjoint of large solutions that follow the first of
 // those (kernels & 64: per frequency, the group-sum and denominator
-// cotangents; kernels & 128: the leaf cotangents and the gradients).
+// cotangents; kernels & 128: the leaf cotangents and the gradients), and the
+// adjoint at complex energies (kernels & 256).
 std::string jit_source(const AmiTerms *t, bool hub, int kernels);
 
 // Source of one module of the persistent specialized batch: the generated
@@ -62,7 +63,8 @@ std::string jit_batch_source(const std::vector<const AmiTerms *> &items, const s
 
 // Kernels of the specialized evaluator.
 // kJitAdjFreq and kJitAdjLeaf are the frequency and leaf passes of the
-// adjoint of large solutions (after kJitSumsPass).
+// adjoint of large solutions (after kJitSumsPass); kJitComplexAdj is the
+// adjoint at complex energies (energy input only, as kJitComplex).
 enum JitKind {
     kJitForward = 0,
     kJitAdjoint = 1,
@@ -71,9 +73,10 @@ enum JitKind {
     kJitSumsPass = 4,
     kJitFreqPass = 5,
     kJitAdjFreq = 6,
-    kJitAdjLeaf = 7
+    kJitAdjLeaf = 7,
+    kJitComplexAdj = 8
 };
-constexpr int kJitKinds = 8;
+constexpr int kJitKinds = 9;
 
 // The specialized kernel of `kind` for the energy (hub = false) or momentum
 // input as a hipFunction_t: compiled (or fetched from the code-object cache)

@@ -31,7 +31,9 @@
 // AMI_JIT_BLOCK lanes per block (the host launches with the same value);
 // AMI_JIT_KERNELS selects the forward (1), the adjoint (2), the Monte-Carlo
 // integrator (4), the forward at complex energies (8), the two passes of the
-// two-pass forward (16, 32), or a sum of them
+// two-pass forward (16, 32), the frequency and leaf passes of the adjoint of
+// large solutions (64, 128), the adjoint at complex energies (256), or a sum
+// of them
 #if AMI_JIT_KERNELS & 1
 extern "C" __global__ __launch_bounds__(AMI_JIT_BLOCK) void ami_jit_fwd(ami::KArgs a) {
     if (a.n_f == 1) amijit::fwd_tile<AMI_JIT_HUB, true>(a, blockIdx.x);
@@ -39,12 +41,13 @@ extern "C" __global__ __launch_bounds__(AMI_JIT_BLOCK) void ami_jit_fwd(ami::KAr
 }
 #endif
 
-#if AMI_JIT_KERNELS & 2
 #if AMI_JIT_ADJ_WAVES > 0
 #define AMI_JIT_ADJ_ATTR __attribute__((amdgpu_waves_per_eu(AMI_JIT_ADJ_WAVES)))
 #else
 #define AMI_JIT_ADJ_ATTR
 #endif
+
+#if AMI_JIT_KERNELS & 2
 
 extern "C" __global__ __launch_bounds__(AMI_JIT_BLOCK) AMI_JIT_ADJ_ATTR void ami_jit_adj(ami::KArgs a) {
     __shared__ double park[amijit::kParkCols > 0 ? amijit::kParkCols * AMI_JIT_BLOCK : 1];
@@ -65,6 +68,12 @@ extern "C" __global__ __launch_bounds__(AMI_JIT_BLOCK) void ami_jit_mc(ami::KArg
 #if AMI_JIT_KERNELS & 8
 extern "C" __global__ __launch_bounds__(AMI_JIT_BLOCK) void ami_jit_cfwd(ami::KArgs a) {
     amijit::cfwd_tile(a, blockIdx.x);
+}
+#endif
+
+#if AMI_JIT_KERNELS & 256
+extern "C" __global__ __launch_bounds__(AMI_JIT_BLOCK) AMI_JIT_ADJ_ATTR void ami_jit_cadj(ami::KArgs a) {
+    amijit::cadj_tile(a, blockIdx.x);
 }
 #endif
 

@@ -815,4 +815,170 @@ __device__ __forceinline__ void cfwd_tile(const KArgs &a, int64_t tile) {
 }
 #endif
 
+#if AMI_JIT_KERNELS & 256
+// Adjoint at complex energies (energy input; interleaved complex128 rows,
+// strides in complex elements; grad_e complex [n_e][NE]).  Every quantity is
+// analytic in E, so the cotangents are complex, in the convention
+// Xbar = dL/dRe X + i dL/dIm X of the real objective L = Re sum conj(c) I;
+// through z = h(x), xbar += zbar conj(h'(x)).  Per frequency row:
+// FTbar_g += c conj(R_g) and, for the denominators, U_k rho_k = conj(Dbar_k)
+// with u_g = -FT_g conj(c) R_g as in the real adjoint (its real part scatters
+// to Re Ebar and w, minus its imaginary part to Im Ebar).  After the rows the
+// leaves are formed again (with f(-y)): Fbar from leaf_cotangents_c at
+// conj(F), V_l = Fbar_l conj(f'(y_l)) with f' = -f(y) f(-y), so that
+// xbar_l = beta V_l and dL/dbeta = sum_l Re(conj(V_l) x_l).  The values are
+// formed as in cfwd_tile.
+__device__ __forceinline__ void cadj_tile(const KArgs &a, int64_t blk) {
+#pragma clang fp contract(fast)
+    const int tid = threadIdx.x, B = blockDim.x, lane = tid & 63;
+    const int64_t row = blk * (B >> 6) + (tid >> 6);
+    const int64_t s = blk * B + tid;
+    const bool active = s < a.n_e;
+    const int64_t sc = active ? s : a.n_e - 1;
+
+    double Er[NE], Ei[NE];
+    const double *erow = a.energies + 2 * sc * a.stride_s;
+#pragma unroll
+    for (int i = 0; i < NE; ++i) {
+        Er[i] = erow[2 * i * a.stride_i];
+        Ei[i] = erow[2 * i * a.stride_i + 1];
+    }
+    double FTr[G], FTi[G], dEi[D];
+    {
+        double xr[L], xi[L], Fr[L], Fi[L];
+        leaf_args(Er, xr);
+        leaf_args(Ei, xi);
+#pragma unroll
+        for (int l = 0; l < L; ++l)
+            ami::leaf_complex(kBose[l], a.beta * (kBose[l] ? xr[l] + a.e_reg : xr[l]), a.beta * xi[l], Fr[l], Fi[l]);
+        group_sums_c(Fr, Fi, FTr, FTi);
+        double zr[NXA], zi[NXA], unused[D];
+#pragma unroll
+        for (int x = 0; x < NXA; ++x) zr[x] = zi[x] = 0.0;
+        den_args(Ei, zr, zi, dEi, unused);          // e_k . Im E
+    }
+    double FTBr[G], FTBi[G], gEr[NE], gEi[NE];
+#pragma unroll
+    for (int g = 0; g < G; ++g) FTBr[g] = FTBi[g] = 0.0;
+#pragma unroll
+    for (int i = 0; i < NE; ++i) gEr[i] = gEi[i] = 0.0;
+    double *gp = a.gpartial + row;                   // column c at gp[c * nrows]
+
+    for (int f = 0; f < a.n_f; ++f) {
+        double cr = 0.0, ci = 0.0;
+        if (active) {
+            if (a.g_out) {
+                cr = a.g_out[2 * (static_cast<int64_t>(f) * a.n_e + s)];
+                ci = a.g_out[2 * (static_cast<int64_t>(f) * a.n_e + s) + 1];
+            }
+            if (a.g_sum) {
+                cr += a.g_sum[2 * f];
+                ci += a.g_sum[2 * f + 1];
+            }
+        }
+        double wr[NXA], wi[NXA], dr[D], di[D], xr[D], xi[D], Rr[G], Ri[G];
+        load_freq(a, f, wr, wi);
+        den_args(Er, wr, wi, dr, di);
+#pragma unroll
+        for (int k = 0; k < D; ++k) {
+            const double im = di[k] + dEi[k];
+            const double inv = ami::rcp_nr(fma(dr[k], dr[k], im * im));
+            xr[k] = dr[k] * inv;
+            xi[k] = -im * inv;
+        }
+        group_products(xr, xi, Rr, Ri);
+        double acc_re = 0.0, acc_im = 0.0, ur[G], ui[G];
+#pragma unroll
+        for (int g = 0; g < G; ++g) {
+            acc_re = fma(FTr[g], Rr[g], fma(-FTi[g], Ri[g], acc_re));
+            acc_im = fma(FTr[g], Ri[g], fma(FTi[g], Rr[g], acc_im));
+            FTBr[g] += fma(cr, Rr[g], ci * Ri[g]);                  // c conj(R)
+            FTBi[g] += fma(ci, Rr[g], -cr * Ri[g]);
+            const double qr = fma(FTr[g], cr, FTi[g] * ci);         // q = FT conj(c)
+            const double qi = fma(FTi[g], cr, -FTr[g] * ci);
+            ur[g] = -fma(qr, Rr[g], -qi * Ri[g]);                   // u = -q R
+            ui[g] = -fma(qr, Ri[g], qi * Rr[g]);
+        }
+        double Ur[D], Ui[D], dR[D], dI[D], ndI[D];
+        den_cotangents(ur, ui, Ur, Ui);
+#pragma unroll
+        for (int k = 0; k < D; ++k) {
+            dR[k] = fma(Ur[k], xr[k], -Ui[k] * xi[k]);
+            dI[k] = fma(Ur[k], xi[k], Ui[k] * xr[k]);
+            ndI[k] = -dI[k];
+        }
+        double gwr[NXA], gwi[NXA], jr[NXA], ji[NXA];
+#pragma unroll
+        for (int xx = 0; xx < NXA; ++xx) gwr[xx] = gwi[xx] = jr[xx] = ji[xx] = 0.0;
+        den_scatter(dR, dI, gEr, gwr, gwi);
+        den_scatter(ndI, dR, gEi, jr, ji);          // its frequency part is not used
+        if (active && a.out) {
+            double2 v;
+            v.x = acc_re;
+            v.y = acc_im;
+            reinterpret_cast<double2 *>(a.out)[static_cast<int64_t>(f) * a.n_e + s] = v;
+        }
+        // this row's per-wave sums, as adj_tile: dL/dw, then the values' row sums
+        constexpr int NV = 2 * NX + 2, NV4 = (NV + 3) / 4 * 4;
+        double vv[NV4];
+        double *pp[NV4];
+#pragma unroll
+        for (int xx = 0; xx < NX; ++xx) {
+            vv[2 * xx] = active ? gwr[xx] : 0.0;
+            vv[2 * xx + 1] = active ? -gwi[xx] : 0.0;
+            pp[2 * xx] = gp + (ami::kAdjScalars + 2 * (f * NX + xx)) * a.nrows;
+            pp[2 * xx + 1] = pp[2 * xx] + a.nrows;
+        }
+        vv[2 * NX] = active ? acc_re : 0.0;
+        vv[2 * NX + 1] = active ? acc_im : 0.0;
+        pp[2 * NX] = a.partial ? a.partial + 2 * f * a.nrows + row : nullptr;
+        pp[2 * NX + 1] = a.partial ? pp[2 * NX] + a.nrows : nullptr;
+#pragma unroll
+        for (int c = NV; c < NV4; ++c) {
+            vv[c] = 0.0;
+            pp[c] = nullptr;
+        }
+#pragma unroll
+        for (int c = 0; c < NV4; c += 4)
+            ami::wave_store4(vv[c], vv[c + 1], vv[c + 2], vv[c + 3], lane, pp[c], pp[c + 1], pp[c + 2], pp[c + 3]);
+    }
+
+    double gbeta = 0.0;
+    {
+        double xr[L], xi[L], Fr[L], Fi[L], Mr[L], Mi[L], cFi[L], FBr[L], FBi[L], vr[L], vi[L];
+        leaf_args(Er, xr);
+        leaf_args(Ei, xi);
+#pragma unroll
+        for (int l = 0; l < L; ++l) {
+            if (kBose[l]) xr[l] += a.e_reg;
+            ami::leaf_complex_pair(kBose[l], a.beta * xr[l], a.beta * xi[l], Fr[l], Fi[l], Mr[l], Mi[l]);
+            cFi[l] = -Fi[l];
+            FBr[l] = FBi[l] = 0.0;
+        }
+        leaf_cotangents_c(Fr, cFi, FTBr, FTBi, FBr, FBi);
+#pragma unroll
+        for (int l = 0; l < L; ++l) {
+            const double dpr = -fma(Fr[l], Mr[l], -Fi[l] * Mi[l]);   // f'(y) = -f(y) f(-y)
+            const double dpi = -fma(Fr[l], Mi[l], Fi[l] * Mr[l]);
+            const double Vr = fma(FBr[l], dpr, FBi[l] * dpi);        // V = Fbar conj(f')
+            const double Vi = fma(FBi[l], dpr, -FBr[l] * dpi);
+            gbeta = fma(Vr, xr[l], fma(Vi, xi[l], gbeta));
+            vr[l] = Vr * a.beta;
+            vi[l] = Vi * a.beta;
+        }
+        leaf_scatter(vr, gEr);
+        leaf_scatter(vi, gEi);
+    }
+    if (active && a.grad_e) {
+        double *grow = a.grad_e + 2 * s * NE;
+#pragma unroll
+        for (int i = 0; i < NE; ++i) {
+            grow[2 * i] = gEr[i];
+            grow[2 * i + 1] = gEi[i];
+        }
+    }
+    ami::wave_store4(active ? gbeta : 0.0, 0.0, 0.0, 0.0, lane, gp, gp + a.nrows, gp + 2 * a.nrows, nullptr);
+}
+#endif
+
 }  // namespace amijit

@@ -1,7 +1,8 @@
 """Complex energies in the library, on the CPU: the generated functions of
 the complex-energy kernel (complex group sums over the diagram's own leaves
-and denominators) compiled on the host with the device leaf at a complex
-argument, compared with the oracle's values; the host-side refusals."""
+and denominators) and of its adjoint (complex leaf cotangents) compiled on
+the host with the device leaf at a complex argument, compared with the
+oracle's values and gradients; the host-side refusals."""
 import os
 import shutil
 import subprocess
@@ -10,9 +11,9 @@ import numpy as np
 import pytest
 
 from ami_inputs import complex_energies, matsubara_freqs, order2_example, random_self_energy, real_freqs
-from oracle.evaluate import evaluate_terms, term_magnitudes
+from oracle.evaluate import evaluate_terms, gradients, term_magnitudes
 
-from parity import check, far_from_poles, oracle_terms, pole_distance
+from parity import check, far_from_poles, gradient_scales, oracle_terms, pole_distance
 
 amd = pytest.importorskip("paper_2311_17189_amd")
 
@@ -21,7 +22,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CASES = [("o2", None), ("o3", (0, 3, 0)), ("o4", (0, 4, 1)), ("o5", (0, 5, 2))]
 
 
-def _harness(src, tmp_path, name):
+def _harness(src, tmp_path, name, driver="jit_check_complex.cpp"):
     cxx = shutil.which("g++")
     if cxx is None:
         pytest.skip("no host C++ compiler")
@@ -31,7 +32,7 @@ def _harness(src, tmp_path, name):
     gen.write_text(body)
     exe = str(tmp_path / name)
     subprocess.run([cxx, "-O1", "-std=c++17", "-ffp-contract=off", "-I", os.path.join(HERE, "cpu_math", "shim"),
-                    f'-DAMI_GENERATED="{gen}"', os.path.join(HERE, "cpu_math", "jit_check_complex.cpp"),
+                    f'-DAMI_GENERATED="{gen}"', os.path.join(HERE, "cpu_math", driver),
                     "-o", exe], check=True, capture_output=True, text=True)
     return exe
 
@@ -44,6 +45,47 @@ def _run(exe, beta, e_reg, w, E):
     res = subprocess.run([exe], input="\n".join(lines) + "\n", capture_output=True, text=True, check=True)
     out = np.array([[float(v) for v in l.split()] for l in res.stdout.strip().splitlines()])
     return (out[:, 0::2] + 1j * out[:, 1::2]).T
+
+
+@pytest.mark.parametrize("name,seed", CASES)
+@pytest.mark.parametrize("e_reg", [0.0, 0.03])
+def test_generated_complex_adjoint_matches_oracle(name, seed, e_reg, tmp_path):
+    """The adjoint at complex energies: dL/dRe E + i dL/dIm E per sample,
+    dL/dbeta and dL/dw summed, within 1e-10 of their rounding scales; the
+    values formed on the way within the forward's bar."""
+    d = order2_example() if seed is None else random_self_energy(seed[1], seed)
+    T = amd.Terms.from_diagram(d)
+    src = T.source(momentum=False)
+    assert "leaf_cotangents_c" in src
+    exe = _harness(src, tmp_path, name + "a", "jit_check_cadj.cpp")
+    beta = 4.0
+    E = complex_energies(120, d.n_eps, seed=(91, d.n_int), a=3.0, eta=0.05)
+    w = np.concatenate([matsubara_freqs(2, beta), real_freqs(1, 0.4, 0.4, 0.05)])
+    terms = oracle_terms(d)
+    E = np.ascontiguousarray(E[far_from_poles(terms, d.n_int, E, w)])
+    rng = np.random.default_rng(92)
+    cot = rng.standard_normal((len(w), len(E))) + 1j * rng.standard_normal((len(w), len(E)))
+    lines = [f"{len(E)} {len(w)} {beta!r} {e_reg!r}",
+             " ".join(f"{float(z.real)!r} {float(z.imag)!r}" for z in w)]
+    for s in range(len(E)):
+        lines.append(" ".join(f"{float(z.real)!r} {float(z.imag)!r}" for z in E[s]) + " " +
+                     " ".join(f"{float(c.real)!r} {float(c.imag)!r}" for c in cot[:, s]))
+    res = subprocess.run([exe], input="\n".join(lines) + "\n", capture_output=True, text=True, check=True)
+    out = np.array([[float(v) for v in l.split()] for l in res.stdout.strip().splitlines()])
+    n_f, ne = len(w), d.n_eps
+    vals = (out[:, 0:2 * n_f:2] + 1j * out[:, 1:2 * n_f:2]).T
+    gE = out[:, 2 * n_f:2 * n_f + 2 * ne:2] + 1j * out[:, 2 * n_f + 1:2 * n_f + 2 * ne:2]
+    gb = out[:, 2 * n_f + 2 * ne].sum()
+    rest = out[:, 2 * n_f + 2 * ne + 1:]
+    gw = (rest[:, 0::2] + 1j * rest[:, 1::2]).sum(axis=0)
+    ref = evaluate_terms(terms, d.n_int, E, w, beta, e_reg).astype(np.complex128)
+    scale = term_magnitudes(terms, d.n_int, E, w, beta, e_reg).astype(np.float64)
+    check(vals, ref, scale, pole_distance(terms, d.n_int, E, w), label=f"{name} complex adjoint values")
+    dE, db, dw = gradients(terms, d.n_int, E, w, beta, cot, e_reg)
+    sc = gradient_scales(terms, d.n_int, E, w, beta, cot, e_reg)
+    assert np.max(np.abs(gE - dE.astype(np.complex128)) / np.maximum(sc["E"], 1e-300)) <= 1e-10
+    assert abs(gb - float(db)) <= 1e-10 * sc["beta"]
+    assert np.max(np.abs(gw - dw.astype(np.complex128).ravel())) <= 1e-10 * sc["w"]
 
 
 @pytest.mark.parametrize("name,seed", CASES)

@@ -2,14 +2,18 @@
 complex-energy kernel) against the oracle, element by element on seeded
 inputs: sizes with ragged blocks, Matsubara and real frequencies, strided
 energies, the regulator, row sums, the real limit against amiEvaluate, and
-the refusals."""
+the refusals; the adjoint at complex energies (amiEvaluateComplexAdjoint)
+against the oracle's analytic gradients, in the real limit against
+amiEvaluateAdjoint, and its refusals."""
 import numpy as np
 import pytest
 
 from ami_inputs import (complex_energies, matsubara_freqs, order2_example, random_self_energy, real_freqs,
                         uniform_energies)
 
-from parity import check, oracle_terms, reference
+from oracle.evaluate import gradients
+
+from parity import check, far_from_poles, gradient_scales, oracle_terms, reference
 
 pytestmark = pytest.mark.gpu
 
@@ -93,7 +97,79 @@ def test_complex_refusals():
     with pytest.raises(amd.AmiError) as e:
         amd.evaluate_complex(T, E, w, 2.0)
     assert e.value.code == -7
+    with pytest.raises(amd.AmiError) as e:
+        amd.evaluate_complex_adjoint(T, E, w, 2.0, grad_out=torch.ones((2, 8), dtype=torch.complex128, device=DEV))
+    assert e.value.code == -7
     T2 = amd.Terms.from_diagram(order2_example())
     with pytest.raises(amd.AmiError) as e:
         amd.evaluate_complex(T2, torch.zeros((8, 3), dtype=torch.float64, device=DEV), w, 2.0)
     assert e.value.code == -1
+
+
+@pytest.mark.parametrize("order,i,beta,n_e,e_reg", [
+    (2, None, 5.0, 1000, 0.0), (3, 0, 2.0, 1500, 0.0), (4, 1, 5.0, 777, 0.0), (4, 6, 2.0, 600, 0.3),
+    (5, 2, 5.0, 300, 0.0), (6, 0, 5.0, 90, 0.0),
+])
+def test_complex_adjoint_vs_oracle(order, i, beta, n_e, e_reg):
+    """dL/dRe E + i dL/dIm E per sample, dL/dbeta and dL/dw within 1e-10 of
+    their rounding scales on samples away from poles; the values formed on the
+    way equal amiEvaluateComplex's, and their row sums."""
+    d = _diag(order, i)
+    eta = 0.25 / (beta * d.n_int)
+    E = complex_energies(n_e, d.n_eps, seed=(94, order, i or 0), a=3.0, eta=eta)
+    w = np.concatenate([matsubara_freqs(2, beta), real_freqs(1, -1.5, -1.5, 0.05)])
+    terms = oracle_terms(d)
+    E = np.ascontiguousarray(E[far_from_poles(terms, d.n_int, E, w)])
+    n = len(E)
+    rng = np.random.default_rng(95)
+    cot = rng.standard_normal((len(w), n)) + 1j * rng.standard_normal((len(w), n))
+    cot_sum = np.array([0.2 + 0.1j, -0.3j, 0.15])
+    T = amd.Terms.from_diagram(d)
+    Et, wt = torch.from_numpy(E).to(DEV), torch.from_numpy(w).to(DEV)
+    out = torch.empty((len(w), n), dtype=torch.complex128, device=DEV)
+    out_sum = torch.empty((len(w),), dtype=torch.complex128, device=DEV)
+    g_e, g_b, g_w = amd.evaluate_complex_adjoint(T, Et, wt, beta, e_reg, grad_out=torch.from_numpy(cot).to(DEV),
+                                                 grad_sum=torch.from_numpy(cot_sum).to(DEV), out=out,
+                                                 out_sum=out_sum)
+    fwd, _ = amd.evaluate_complex(T, Et, wt, beta, e_reg)
+    torch.cuda.synchronize()
+    assert amd.last_variant() == "specialized complex"
+    full = cot + cot_sum[:, None]
+    ref_e, ref_b, ref_w = gradients(terms, d.n_int, E, w, beta, full, e_reg)
+    sc = gradient_scales(terms, d.n_int, E, w, beta, full, e_reg)
+    ge = g_e.cpu().numpy()
+    assert np.max(np.abs(ge - ref_e.astype(np.complex128)) / np.maximum(sc["E"], 1e-300)) <= 1e-10
+    assert abs(float(g_b) - float(ref_b)) <= 1e-10 * sc["beta"]
+    assert np.max(np.abs(g_w.cpu().numpy() - ref_w.astype(np.complex128))) <= 1e-10 * sc["w"]
+    got = out.cpu().numpy()
+    ref, scale, dist = reference(d, E, w, beta, e_reg, terms=terms)
+    check(got, ref, scale, dist, label=f"complex adjoint values order {order}")
+    assert np.max(np.abs(got - fwd.cpu().numpy()) / scale) <= 1e-13
+    np.testing.assert_allclose(out_sum.cpu().numpy(), got.sum(axis=1), rtol=1e-12, atol=1e-12 * scale.sum())
+
+
+def test_complex_adjoint_real_limit_and_empty():
+    """At real energies (given as complex numbers) the real part of the energy
+    gradient, dL/dbeta and dL/dw equal amiEvaluateAdjoint's up to rounding;
+    no samples give zero reductions."""
+    d = random_self_energy(4, (0, 4, 3))
+    T = amd.Terms.from_diagram(d)
+    beta = 5.0
+    E = uniform_energies(1100, d.n_eps, seed=96, a=3.0)
+    w = np.concatenate([matsubara_freqs(2, beta), real_freqs(1, 0.5, 0.5, 0.05)])
+    terms = oracle_terms(d)
+    E = np.ascontiguousarray(E[far_from_poles(terms, d.n_int, E, w)])
+    cot = np.random.default_rng(97).standard_normal((len(w), len(E))) + 0.5j
+    Er, wt, ct = torch.from_numpy(E).to(DEV), torch.from_numpy(w).to(DEV), torch.from_numpy(cot).to(DEV)
+    ra, rb, rw = amd.evaluate_adjoint(T, Er, wt, beta, grad_out=ct)
+    ca, cb, cw = amd.evaluate_complex_adjoint(T, Er.to(torch.complex128), wt, beta, grad_out=ct)
+    torch.cuda.synchronize()
+    sc = gradient_scales(terms, d.n_int, E, w, beta, cot)
+    assert np.max(np.abs(ca.real.cpu().numpy() - ra.cpu().numpy()) / np.maximum(sc["E"], 1e-300)) <= 1e-12
+    assert abs(float(cb) - float(rb)) <= 1e-12 * sc["beta"]
+    assert np.max(np.abs((cw - rw).cpu().numpy())) <= 1e-12 * sc["w"]
+    z = torch.zeros((0, d.n_eps), dtype=torch.complex128, device=DEV)
+    g0, b0, w0 = amd.evaluate_complex_adjoint(T, z, wt, beta, grad_sum=torch.ones(len(w), dtype=torch.complex128,
+                                                                                    device=DEV))
+    torch.cuda.synchronize()
+    assert g0.shape == (0, d.n_eps) and float(b0) == 0.0 and torch.all(w0 == 0)

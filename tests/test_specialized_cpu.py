@@ -180,10 +180,11 @@ def test_source_limits_and_errors():
     assert e.value.code == -7
 
 
-@pytest.mark.parametrize("momentum,kernels", [(True, (1, 2)), (False, (1, 2, 8))])
+@pytest.mark.parametrize("momentum,kernels", [(True, (1, 2)), (False, (1, 2, 8, 256))])
 def test_hiprtc_compiles_the_generated_source(tmp_path, monkeypatch, momentum, kernels):
     """amiTermsSpecialize compiles every kernel of the input for gfx950 before
-    it needs a device (the complex-energy forward too, for the energy input);
+    it needs a device (the complex-energy forward and adjoint too, for the
+    energy input);
     here (no GPU) it then stops at the device query, leaving the code objects
     and their sources in the disk cache.  A second handle finds them there."""
     monkeypatch.setenv("AMIGPU_CACHE_DIR", str(tmp_path))
@@ -200,6 +201,7 @@ def test_hiprtc_compiles_the_generated_source(tmp_path, monkeypatch, momentum, k
     for p in objs:
         assert p.stat().st_size > 1000
     # one code object per kernel: forward 1, adjoint 2, complex-energy forward 8
+    # and adjoint 256
     found = sorted(k for p in srcs for k in kernels if f"#define AMI_JIT_KERNELS {k}\n" in p.read_text())
     assert found == sorted(kernels)
 
