@@ -231,6 +231,10 @@ AmiStatus amiEvaluateHubbard(AmiTerms *terms,
  * Leaves are accurate for |beta Im x| < 6e6; a Fermi leaf has poles at
  * beta x = i pi (2n+1), which the caller keeps away from.  Served by the
  * specialized kernels only (compiled on first use, as AMI_VARIANT_SPECIALIZED):
+ * in one pass up to 1024 terms; in two passes (the complex group sums and
+ * energies stored per sample in the chunked workspace of AMI_VARIANT_TWO_PASS,
+ * then evaluated per frequency row; at most 65535 rows) above, up to 4096
+ * terms, or at any size when the handle's variant is AMI_VARIANT_TWO_PASS.
  * AMI_E_UNSUPPORTED for solutions outside their form and for poles of higher
  * order (AMI_MULTIPOLE).  Its adjoint is amiEvaluateComplexAdjoint.
  */
@@ -448,7 +452,8 @@ AmiStatus amiSetTwoPassChunkBytes(int64_t bytes);
  * (its two passes where AUTO takes them), the adjoint AUTO uses (one pass up
  * to 128 terms, its passes above), and for solutions of at most 1024 terms
  * the complex-energy forward and its adjoint (amiEvaluateComplex,
- * amiEvaluateComplexAdjoint) for the energy input; all are compiled before a
+ * amiEvaluateComplexAdjoint) for the energy input, above that the two passes
+ * of the complex-energy forward; all are compiled before a
  * device is touched.  A solution with Taylor-coefficient leaves (AMI_MULTIPOLE)
  * gets no complex-energy kernels.
  */

@@ -570,17 +570,11 @@ std::string jit_source(const AmiTerms *t, bool hub, int kernels) {
     }
 
     // complex group sums (complex energies): each group's sum nested as the
-    // real group sums, in complex arithmetic
-    if (kernels & (8 | 256)) {
-        o << "__device__ __forceinline__ void group_sums_c(const double (&Fr)[L], const double (&Fi)[L], double "
-             "(&FTr)[G], double (&FTi)[G]) {\n";
-        auto leaf = [&](int l) {
-            CVal v;
-            v.kind = CVal::CPLX;
-            v.re = "Fr[" + std::to_string(l) + "]";
-            v.im = "Fi[" + std::to_string(l) + "]";
-            return v;
-        };
+    // real group sums, in complex arithmetic; `store`: each stored to the
+    // workspace as soon as it is formed (real part in column g, imaginary part
+    // in column G + g; the two-pass complex forward's first pass), the leaves
+    // a group reads taken through opaque copies as in group_sums_store
+    auto group_sums_c_body = [&](bool store) {
         for (int g = 0; g < G; ++g) {
             o << "  {\n";
             std::vector<HornerTerm> ts;
@@ -589,13 +583,44 @@ std::string jit_source(const AmiTerms *t, bool hub, int kernels) {
                 for (int j = 0; j < ni; ++j) h.leaves.push_back(tb.term_leaf[static_cast<size_t>(ti) * ni + j]);
                 ts.push_back(std::move(h));
             }
+            if (store) {
+                std::vector<int> used;
+                for (const HornerTerm &h : ts) used.insert(used.end(), h.leaves.begin(), h.leaves.end());
+                std::sort(used.begin(), used.end());
+                used.erase(std::unique(used.begin(), used.end()), used.end());
+                for (int l : used)
+                    o << "    double fr" << l << " = Fr[" << l << "], fi" << l << " = Fi[" << l << "]; AMI_OPAQUE(fr" << l
+                      << "); AMI_OPAQUE(fi" << l << ");\n";
+            }
+            auto leaf = [&](int l) {
+                CVal v;
+                v.kind = CVal::CPLX;
+                v.re = store ? "fr" + std::to_string(l) : "Fr[" + std::to_string(l) + "]";
+                v.im = store ? "fi" + std::to_string(l) : "Fi[" + std::to_string(l) + "]";
+                return v;
+            };
             int temps = 0;
             CMemo memo;
             const CVal v = horner_c(ts, leaf, o, temps, memo);
             const std::string re = v.kind == CVal::ZERO ? "0.0" : v.kind == CVal::CONST ? num(v.c) : v.re;
             const std::string im = v.kind == CVal::CPLX ? v.im : "0.0";
-            o << "    FTr[" << g << "] = " << re << "; FTi[" << g << "] = " << im << "; }\n";
+            if (store)
+                o << "    ami::ws_store(ws, ld, " << g << ", off, " << re << "); ami::ws_store(ws, ld, " << G + g
+                  << ", off, " << im << "); }\n";
+            else
+                o << "    FTr[" << g << "] = " << re << "; FTi[" << g << "] = " << im << "; }\n";
         }
+    };
+    if (kernels & (8 | 256)) {
+        o << "__device__ __forceinline__ void group_sums_c(const double (&Fr)[L], const double (&Fi)[L], double "
+             "(&FTr)[G], double (&FTi)[G]) {\n";
+        group_sums_c_body(false);
+        o << "}\n";
+    }
+    if (kernels & 512) {
+        o << "__device__ __forceinline__ void group_sums_c_store(const double (&Fr)[L], const double (&Fi)[L], "
+             "double *ws, int64_t ld, uint32_t off) {\n";
+        group_sums_c_body(true);
         o << "}\n";
     }
 
@@ -767,6 +792,50 @@ std::string jit_source(const AmiTerms *t, bool hub, int kernels) {
                 }
                 v.kind = CVal::REAL;
                 v.re = "ft" + std::to_string(g);
+            }
+            return v;
+        };
+        int temps = 0;
+        CMemo memo;
+        const CVal v = horner_c(ts, leaf, o, temps, memo);
+        auto comp = [&](bool imag) {
+            if (v.kind == CVal::ZERO) return std::string("0.0");
+            if (v.kind == CVal::CONST) return imag ? std::string("0.0") : num(v.c);
+            if (v.kind == CVal::REAL) return imag ? std::string("0.0") : v.re;
+            return imag ? v.im : v.re;
+        };
+        o << "    acc_re += " << comp(false) << ";\n    acc_im += " << comp(true) << ";\n";
+        o << "}\n";
+    }
+
+    // the second pass of the two-pass complex forward: as group_accumulate,
+    // with each stored FT_g complex (columns g and G + g)
+    if (kernels & 1024) {
+        o << "__device__ __forceinline__ void group_accumulate_c(const double (&xr)[D], const double (&xi)[D], "
+             "const double *ws, int64_t ld, uint32_t off, double &acc_re, double &acc_im) {\n";
+        std::vector<HornerTerm> ts;
+        for (int g = 0; g < G; ++g) {
+            HornerTerm h{1.0, {}};
+            for (int j = gbegin(g); j < gend(g); ++j) h.leaves.push_back(tb.group_den_list[j]);
+            h.leaves.push_back(D + g);
+            ts.push_back(std::move(h));
+        }
+        std::vector<bool> loaded(static_cast<size_t>(G), false);
+        auto leaf = [&](int k) {
+            CVal v;
+            v.kind = CVal::CPLX;
+            if (k < D) {
+                v.re = "xr[" + std::to_string(k) + "]";
+                v.im = "xi[" + std::to_string(k) + "]";
+            } else {
+                const int g = k - D;
+                if (!loaded[static_cast<size_t>(g)]) {
+                    o << "    const double ftr" << g << " = ami::ws_load(ws, ld, " << g << ", off), fti" << g
+                      << " = ami::ws_load(ws, ld, " << G + g << ", off);\n";
+                    loaded[static_cast<size_t>(g)] = true;
+                }
+                v.re = "ftr" + std::to_string(g);
+                v.im = "fti" + std::to_string(g);
             }
             return v;
         };
@@ -1279,9 +1348,9 @@ extern "C" AmiStatus amiTermsSource(const AmiTerms *t, int32_t momentum, char *b
     const bool hub = (momentum & 1) != 0, two_pass = (momentum & 2) != 0;
     std::string why;
     if (!jit_supported(t, hub, &why, two_pass)) return fail(AMI_E_UNSUPPORTED, "no specialized kernel: " + why);
-    int kernels = two_pass ? 48 | 64 | 128 : hub ? 7 : 11 | 256;
+    int kernels = two_pass ? (hub ? 48 | 64 | 128 : 48 | 64 | 128 | 512 | 1024) : hub ? 7 : 11 | 256;
     for (int o : t->tab.leaf_order)
-        if (o > 0) kernels &= ~(8 | 256);   // Taylor-coefficient leaves: no complex energies
+        if (o > 0) kernels &= ~(8 | 256 | 512 | 1024);   // Taylor-coefficient leaves: no complex energies
     const std::string src = jit_source(t, hub, kernels);
     *len = static_cast<int64_t>(src.size()) + 1;
     if (!buf) return AMI_OK;

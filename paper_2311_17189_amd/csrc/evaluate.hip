@@ -467,13 +467,15 @@ hipError_t launch_jit(void *fn, int64_t nblocks, int block, hipStream_t stream, 
 // fit the chunk workspace; per chunk the sums pass (one lane per sample) and
 // the frequency pass (a block per tile and frequency row), then one column reduction
 // of the per-wave partial sums for the row sums.
+// cplx: the complex-energy passes, whose group sums and energies take two
+// columns each.
 AmiStatus launch_two_pass(AmiTerms *t, DeviceTables *dt, bool hub, KArgs &a, double *out_sum, void *fn_sums,
-                          void *fn_freq, hipStream_t stream) {
+                          void *fn_freq, hipStream_t stream, bool cplx = false) {
     const int B = jit_block(t, hub);
     const int64_t tiles = (a.n_e + B - 1) / B;
     if (tiles > 0x7fffffffLL) return fail(AMI_E_ARG, "n_e too large");
     const int64_t rows = tiles * (B / 64);
-    const int64_t cols = static_cast<int64_t>(t->tab.G) + t->n_eps;
+    const int64_t cols = (cplx ? 2 : 1) * (static_cast<int64_t>(t->tab.G) + t->n_eps);
     const int64_t chunk_bytes = g_two_pass_chunk_bytes.load();
     int64_t ld = chunk_bytes / (cols * static_cast<int64_t>(sizeof(double))) / B * B;
     ld = std::max<int64_t>(B, std::min<int64_t>(ld, tiles * B));
@@ -500,7 +502,7 @@ AmiStatus launch_two_pass(AmiTerms *t, DeviceTables *dt, bool hub, KArgs &a, dou
         if (e == hipSuccess) e = launch_jit(fn_freq, (nb + 7) / 8 * 8 * a.n_f, B, stream, a);
     }
     if (e == hipSuccess) e = hipGetLastError();
-    g_last_variant = "specialized two-pass";
+    g_last_variant = cplx ? "specialized complex two-pass" : "specialized two-pass";
     if (e != hipSuccess) return hip_fail(e, "two-pass launch");
     if (out_sum) {
         hipLaunchKernelGGL(ami_colsum_kernel, dim3(ncols), dim3(kRedThreads), 0, stream, a.partial, rows,
@@ -904,6 +906,24 @@ AmiStatus amiEvaluateComplex(AmiTerms *t, const double *energies, int64_t n_e, i
     DeviceTables *dt = nullptr;
     st = upload(t, &dt);
     if (st != AMI_OK) return st;
+    // solutions above the one-pass size (or the forced two-pass variant): the
+    // complex group sums stored per sample, then evaluated per frequency row
+    if (t->tab.T > kJitMaxTerms || t->variant == AMI_VARIANT_TWO_PASS) {
+        void *fs = nullptr, *ff = nullptr;
+        st = jit_get(t, false, kJitComplexSums, &fs);
+        if (st == AMI_OK) st = jit_get(t, false, kJitComplexFreq, &ff);
+        if (st != AMI_OK) return st;
+        if (n_e == 0) return fill(out_sum, 2 * n_f, stream);
+        if (n_f > kTwoPassMaxFreqs) return fail(AMI_E_ARG, "the two-pass variant takes at most 65535 frequency rows");
+        KArgs a;
+        std::memset(&a, 0, sizeof(a));
+        a.energies = energies;
+        a.stride_s = stride_s;
+        a.stride_i = stride_i;
+        set_common(a, ext_freqs, n_f, beta, e_reg, n_e);
+        a.out = out;
+        return launch_two_pass(t, dt, false, a, out_sum, fs, ff, stream, true);
+    }
     void *fn = nullptr;
     st = jit_get(t, false, kJitComplex, &fn);
     if (st != AMI_OK) return st;
@@ -1209,6 +1229,10 @@ AmiStatus amiTermsSpecialize(AmiTerms *t, int32_t momentum) {
     if (!taylor && small && !hub) {
         kinds.push_back(kJitComplex);
         kinds.push_back(kJitComplexAdj);
+    }
+    if (!taylor && !small && !hub && t->tab.T <= kJitTwoPassMaxTerms) {
+        kinds.push_back(kJitComplexSums);
+        kinds.push_back(kJitComplexFreq);
     }
     for (int k : kinds) {
         const AmiStatus st = jit_compile(t, hub, k);

@@ -149,12 +149,13 @@ AmiStatus code_object(AmiTerms *t, bool hub, int kind) {
     std::string &err = t->jit_error[slot];
     if (!err.empty()) return fail(AMI_E_UNSUPPORTED, err);
     std::string why;
-    const bool passes = kind == kJitSumsPass || kind == kJitFreqPass || kind == kJitAdjFreq || kind == kJitAdjLeaf;
+    const bool passes = kind == kJitSumsPass || kind == kJitFreqPass || kind == kJitAdjFreq || kind == kJitAdjLeaf ||
+                        kind == kJitComplexSums || kind == kJitComplexFreq;
     if (!jit_supported(t, hub, &why, passes)) {
         err = "no specialized kernel: " + why;
         return fail(AMI_E_UNSUPPORTED, err);
     }
-    if (kind == kJitComplex || kind == kJitComplexAdj)
+    if (jit_kind_complex(kind))
         for (int o : t->tab.leaf_order)
             if (o > 0) {
                 err = "no complex-energy kernel for Taylor-coefficient leaves (poles of higher order)";
@@ -187,7 +188,7 @@ AmiStatus code_from_source(const std::string &src, std::vector<char> &code, std:
 
 AmiStatus jit_compile(AmiTerms *t, bool hub, int kind) {
     if (kind < kJitForward || kind >= kJitKinds || (kind == kJitMonteCarlo && !hub) ||
-        ((kind == kJitComplex || kind == kJitComplexAdj) && hub))
+        (jit_kind_complex(kind) && hub))
         return fail(AMI_E_ARG, "no such specialized kernel");
     std::lock_guard<std::mutex> lock(t->jit_mu);
     return code_object(t, hub, kind);
@@ -195,7 +196,7 @@ AmiStatus jit_compile(AmiTerms *t, bool hub, int kind) {
 
 AmiStatus jit_get(AmiTerms *t, bool hub, int kind, void **fn) {
     if (kind < kJitForward || kind >= kJitKinds || (kind == kJitMonteCarlo && !hub) ||
-        ((kind == kJitComplex || kind == kJitComplexAdj) && hub))
+        (jit_kind_complex(kind) && hub))
         return fail(AMI_E_ARG, "no such specialized kernel");
     std::lock_guard<std::mutex> lock(t->jit_mu);
     const int slot = kJitKinds * (hub ? 1 : 0) + kind;
@@ -214,9 +215,9 @@ AmiStatus jit_get(AmiTerms *t, bool hub, int kind, void **fn) {
     e = hipModuleLoadData(&mod, t->jit_code[slot].data());
     if (e != hipSuccess) return hip_fail(e, "hipModuleLoadData (specialized kernel)");
     hipFunction_t f = nullptr;
-    static const char *const kNames[kJitKinds] = {"ami_jit_fwd",  "ami_jit_adj",  "ami_jit_mc",
-                                                  "ami_jit_cfwd", "ami_jit_sums", "ami_jit_freq",
-                                                  "ami_jit_adjf", "ami_jit_adjl", "ami_jit_cadj"};
+    static const char *const kNames[kJitKinds] = {"ami_jit_fwd",  "ami_jit_adj",   "ami_jit_mc",   "ami_jit_cfwd",
+                                                  "ami_jit_sums", "ami_jit_freq",  "ami_jit_adjf", "ami_jit_adjl",
+                                                  "ami_jit_cadj", "ami_jit_csums", "ami_jit_cfreq"};
     e = hipModuleGetFunction(&f, mod, kNames[kind]);
     if (e != hipSuccess) {
         (void)hipModuleUnload(mod);
@@ -234,7 +235,7 @@ AmiStatus jit_get(AmiTerms *t, bool hub, int kind, void **fn) {
 
 AmiStatus jit_loaded(AmiTerms *t, bool hub, int kind, void **fn) {
     if (kind < kJitForward || kind >= kJitKinds || (kind == kJitMonteCarlo && !hub) ||
-        ((kind == kJitComplex || kind == kJitComplexAdj) && hub))
+        (jit_kind_complex(kind) && hub))
         return fail(AMI_E_ARG, "no such specialized kernel");
     std::lock_guard<std::mutex> lock(t->jit_mu);
     const int slot = kJitKinds * (hub ? 1 : 0) + kind;

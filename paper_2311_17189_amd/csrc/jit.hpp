@@ -44,8 +44,10 @@ int jit_block(const AmiTerms *t, bool hub);
 // kernels & 32: per frequency, reciprocals and group products against them),
 // and the passes of the adjoint of large solutions that follow the first of
 // those (kernels & 64: per frequency, the group-sum and denominator
-// cotangents; kernels & 128: the leaf cotangents and the gradients), and the
-// adjoint at complex energies (kernels & 256).
+// cotangents; kernels & 128: the leaf cotangents and the gradients), the
+// adjoint at complex energies (kernels & 256), and the two passes of the
+// forward at complex energies (kernels & 512: complex group sums and energies
+// stored per sample; kernels & 1024: per frequency, against them).
 std::string jit_source(const AmiTerms *t, bool hub, int kernels);
 
 // Source of one module of the persistent specialized batch: the generated
@@ -64,7 +66,9 @@ std::string jit_batch_source(const std::vector<const AmiTerms *> &items, const s
 // Kernels of the specialized evaluator.
 // kJitAdjFreq and kJitAdjLeaf are the frequency and leaf passes of the
 // adjoint of large solutions (after kJitSumsPass); kJitComplexAdj is the
-// adjoint at complex energies (energy input only, as kJitComplex).
+// adjoint at complex energies (energy input only, as kJitComplex);
+// kJitComplexSums and kJitComplexFreq the two passes of the forward at complex
+// energies (solutions above kJitMaxTerms terms).
 enum JitKind {
     kJitForward = 0,
     kJitAdjoint = 1,
@@ -74,9 +78,16 @@ enum JitKind {
     kJitFreqPass = 5,
     kJitAdjFreq = 6,
     kJitAdjLeaf = 7,
-    kJitComplexAdj = 8
+    kJitComplexAdj = 8,
+    kJitComplexSums = 9,
+    kJitComplexFreq = 10
 };
-constexpr int kJitKinds = 9;
+constexpr int kJitKinds = 11;
+
+// Kinds for the energy input only (complex energies).
+inline bool jit_kind_complex(int kind) {
+    return kind == kJitComplex || kind == kJitComplexAdj || kind == kJitComplexSums || kind == kJitComplexFreq;
+}
 
 // The specialized kernel of `kind` for the energy (hub = false) or momentum
 // input as a hipFunction_t: compiled (or fetched from the code-object cache)

@@ -32,8 +32,8 @@
 // AMI_JIT_KERNELS selects the forward (1), the adjoint (2), the Monte-Carlo
 // integrator (4), the forward at complex energies (8), the two passes of the
 // two-pass forward (16, 32), the frequency and leaf passes of the adjoint of
-// large solutions (64, 128), the adjoint at complex energies (256), or a sum
-// of them
+// large solutions (64, 128), the adjoint at complex energies (256), the two
+// passes of the forward at complex energies (512, 1024), or a sum of them
 #if AMI_JIT_KERNELS & 1
 extern "C" __global__ __launch_bounds__(AMI_JIT_BLOCK) void ami_jit_fwd(ami::KArgs a) {
     if (a.n_f == 1) amijit::fwd_tile<AMI_JIT_HUB, true>(a, blockIdx.x);
@@ -74,6 +74,23 @@ extern "C" __global__ __launch_bounds__(AMI_JIT_BLOCK) void ami_jit_cfwd(ami::KA
 #if AMI_JIT_KERNELS & 256
 extern "C" __global__ __launch_bounds__(AMI_JIT_BLOCK) AMI_JIT_ADJ_ATTR void ami_jit_cadj(ami::KArgs a) {
     amijit::cadj_tile(a, blockIdx.x);
+}
+#endif
+
+#if AMI_JIT_KERNELS & 512
+extern "C" __global__ __launch_bounds__(AMI_JIT_BLOCK) void ami_jit_csums(ami::KArgs a) {
+    amijit::csums_tile(a, blockIdx.x);
+}
+#endif
+
+#if AMI_JIT_KERNELS & 1024
+// the grid of ami_jit_freq: (tile, frequency) blocks dealt over the XCDs
+extern "C" __global__ __launch_bounds__(AMI_JIT_BLOCK) void ami_jit_cfreq(ami::KArgs a) {
+    const int64_t b = blockIdx.x, local = b >> 3;
+    const int f = static_cast<int>(local % a.n_f);
+    const int64_t tile = 8 * (local / a.n_f) + (b & 7);
+    if (tile * AMI_JIT_BLOCK >= a.n_chunk) return;
+    amijit::cfreq_tile(a, tile, f);
 }
 #endif
 

@@ -815,6 +815,86 @@ __device__ __forceinline__ void cfwd_tile(const KArgs &a, int64_t tile) {
 }
 #endif
 
+#if AMI_JIT_KERNELS & 512
+// Two-pass forward at complex energies, first pass (solutions too large for
+// cfwd_tile): one lane per sample of the chunk, complex leaves and group sums,
+// each group sum stored as soon as it is formed (real part in column g,
+// imaginary part in column G + g), the energies beside them (real parts in
+// columns 2 G + j, imaginary parts in 2 G + NE + j).  Lanes past the chunk
+// write rows that nothing reads (ld is a multiple of the block).
+__device__ __forceinline__ void csums_tile(const KArgs &a, int64_t tile) {
+    const int tid = threadIdx.x, B = blockDim.x;
+    const int64_t i = tile * B + tid;
+    const int64_t sc = a.s0 + (i < a.n_chunk ? i : a.n_chunk - 1);
+    double Er[NE], Ei[NE];
+    const double *erow = a.energies + 2 * sc * a.stride_s;
+#pragma unroll
+    for (int j = 0; j < NE; ++j) {
+        Er[j] = erow[2 * j * a.stride_i];
+        Ei[j] = erow[2 * j * a.stride_i + 1];
+    }
+    double xr[L], xi[L], Fr[L], Fi[L];
+    leaf_args(Er, xr);
+    leaf_args(Ei, xi);
+#pragma unroll
+    for (int l = 0; l < L; ++l)
+        ami::leaf_complex(kBose[l], a.beta * (kBose[l] ? xr[l] + a.e_reg : xr[l]), a.beta * xi[l], Fr[l], Fi[l]);
+    const uint32_t off = static_cast<uint32_t>(i) * 8u;   // i < ld <= 2^28 (host bound)
+    group_sums_c_store(Fr, Fi, a.work, a.ld, off);
+#pragma unroll
+    for (int j = 0; j < NE; ++j) {
+        ami::ws_store(a.work, a.ld, 2 * G + j, off, Er[j]);
+        ami::ws_store(a.work, a.ld, 2 * G + NE + j, off, Ei[j]);
+    }
+}
+#endif
+
+#if AMI_JIT_KERNELS & 1024
+// Two-pass forward at complex energies, second pass: block (tile, f) as
+// freq_tile, from the stored complex energies (the imaginary parts enter the
+// denominators' imaginary parts) and the stored complex group sums.
+__device__ __forceinline__ void cfreq_tile(const KArgs &a, int64_t tile, int f) {
+    const int tid = threadIdx.x, B = blockDim.x, lane = tid & 63;
+    const int64_t i = tile * B + tid;
+    const bool active = i < a.n_chunk;
+    const int64_t row = (a.s0 / B + tile) * (B >> 6) + (tid >> 6);
+    const uint32_t off = static_cast<uint32_t>(i) * 8u;   // i < ld <= 2^28 (host bound)
+    double Er[NE], Ei[NE];
+#pragma unroll
+    for (int j = 0; j < NE; ++j) {
+        Er[j] = ami::ws_load(a.work, a.ld, 2 * G + j, off);
+        Ei[j] = ami::ws_load(a.work, a.ld, 2 * G + NE + j, off);
+    }
+    double wr[NXA], wi[NXA], dr[D], di[D], xr[D], xi[D];
+    {
+        double zr[NXA], zi[NXA], unused[D];
+#pragma unroll
+        for (int x = 0; x < NXA; ++x) zr[x] = zi[x] = 0.0;
+        den_args(Ei, zr, zi, xi, unused);              // e_k . Im E (in xi for now)
+    }
+    load_freq(a, f, wr, wi);
+    den_args(Er, wr, wi, dr, di);
+#pragma unroll
+    for (int k = 0; k < D; ++k) {
+        const double im = di[k] + xi[k];
+        const double inv = ami::rcp_nr(fma(dr[k], dr[k], im * im));
+        xr[k] = dr[k] * inv;
+        xi[k] = -im * inv;
+    }
+    double acc_re = 0.0, acc_im = 0.0;
+    group_accumulate_c(xr, xi, a.work, a.ld, off, acc_re, acc_im);
+    if (active && a.out) {
+        double2 v;
+        v.x = acc_re;
+        v.y = acc_im;
+        reinterpret_cast<double2 *>(a.out)[static_cast<int64_t>(f) * a.n_e + a.s0 + i] = v;
+    }
+    if (a.partial)
+        ami::wave_store2(active ? acc_re : 0.0, active ? acc_im : 0.0, lane, a.partial + 2 * f * a.nrows + row,
+                         a.nrows);
+}
+#endif
+
 #if AMI_JIT_KERNELS & 256
 // Adjoint at complex energies (energy input; interleaved complex128 rows,
 // strides in complex elements; grad_e complex [n_e][NE]).  Every quantity is

@@ -47,6 +47,29 @@ def _run(exe, beta, e_reg, w, E):
     return (out[:, 0::2] + 1j * out[:, 1::2]).T
 
 
+# two-pass complex sources: o4 52 terms, o6 560, and an order-6 topology of
+# 2804 terms (above the one-pass size, where only these kernels serve)
+TWO_PASS_CASES = [("o4", (0, 4, 1), 150), ("o6", (0, 6, 0), 40), ("o6big", (5, 6, 2), 12)]
+
+
+@pytest.mark.parametrize("name,seed,n", TWO_PASS_CASES)
+def test_generated_complex_two_pass_matches_oracle(name, seed, n, tmp_path):
+    d = random_self_energy(seed[1], seed)
+    T = amd.Terms.from_diagram(d)
+    src = T.source(momentum=False, two_pass=True)
+    assert "group_sums_c_store" in src and "group_accumulate_c" in src
+    exe = _harness(src, tmp_path, name + "t", "jit_check_complex_two_pass.cpp")
+    beta, e_reg = 4.0, 0.02
+    E = complex_energies(3 * n, d.n_eps, seed=(93, d.n_int), a=3.0, eta=0.03)
+    w = np.concatenate([matsubara_freqs(1, beta), real_freqs(1, 0.7, 0.7, 0.05)])
+    terms = oracle_terms(d)
+    E = np.ascontiguousarray(E[far_from_poles(terms, d.n_int, E, w)][:n])
+    got = _run(exe, beta, e_reg, w, E)
+    ref = evaluate_terms(terms, d.n_int, E, w, beta, e_reg).astype(np.complex128)
+    scale = term_magnitudes(terms, d.n_int, E, w, beta, e_reg).astype(np.float64)
+    check(got, ref, scale, pole_distance(terms, d.n_int, E, w, e_reg), label=f"{name} complex two-pass")
+
+
 @pytest.mark.parametrize("name,seed", CASES)
 @pytest.mark.parametrize("e_reg", [0.0, 0.03])
 def test_generated_complex_adjoint_matches_oracle(name, seed, e_reg, tmp_path):

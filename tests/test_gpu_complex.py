@@ -2,7 +2,8 @@
 complex-energy kernel) against the oracle, element by element on seeded
 inputs: sizes with ragged blocks, Matsubara and real frequencies, strided
 energies, the regulator, row sums, the real limit against amiEvaluate, and
-the refusals; the adjoint at complex energies (amiEvaluateComplexAdjoint)
+the refusals; the two-pass complex forward (solutions above 1024 terms, or
+forced) with several chunks; the adjoint at complex energies (amiEvaluateComplexAdjoint)
 against the oracle's analytic gradients, in the real limit against
 amiEvaluateAdjoint, and its refusals."""
 import numpy as np
@@ -173,3 +174,42 @@ def test_complex_adjoint_real_limit_and_empty():
                                                                                     device=DEV))
     torch.cuda.synchronize()
     assert g0.shape == (0, d.n_eps) and float(b0) == 0.0 and torch.all(w0 == 0)
+
+
+@pytest.mark.parametrize("order,seed,n_e", [(4, (0, 4, 1), 3000), (6, (0, 6, 0), 700), (6, (5, 6, 2), 1100)])
+def test_complex_two_pass(order, seed, n_e):
+    """The two-pass complex forward against the oracle: forced at orders 4 and
+    6 (where the one-pass kernel also serves: equal to it up to rounding), and
+    by AUTO at order 6 with 2804 terms (above the one-pass size); the samples
+    in one chunk and in several (a ragged last one), bitwise alike."""
+    d = random_self_energy(order, seed)
+    T = amd.Terms.from_diagram(d)
+    big = T.info()["T"] > 1024
+    if not big:
+        T.set_variant(amd.VARIANT_TWO_PASS)
+    beta, e_reg = 5.0, 0.02
+    eta = 0.25 / (beta * d.n_int)
+    E = complex_energies(n_e, d.n_eps, seed=(98, order), a=3.0, eta=eta)
+    w = np.concatenate([matsubara_freqs(2, beta), real_freqs(2, -3.0, 3.0, 0.05)])
+    Et, wt = torch.from_numpy(E).to(DEV), torch.from_numpy(w).to(DEV)
+    out, s = amd.evaluate_complex(T, Et, wt, beta, e_reg, want_out=True, want_sum=True)
+    torch.cuda.synchronize()
+    assert amd.last_variant() == "specialized complex two-pass"
+    cols = 2 * (T.info()["G"] + d.n_eps)
+    try:
+        amd.set_two_pass_chunk_bytes(max(1 << 16, 256 * 8 * cols * 2))     # chunks of 512 samples
+        out2, s2 = amd.evaluate_complex(T, Et, wt, beta, e_reg, want_out=True, want_sum=True)
+        torch.cuda.synchronize()
+    finally:
+        amd.set_two_pass_chunk_bytes(256 << 20)
+    assert torch.equal(out, out2) and torch.equal(s, s2)
+    got = out.cpu().numpy()
+    ref, scale, dist = reference(d, E, w, beta, e_reg)
+    check(got, ref, scale, dist, label=f"complex two-pass order {order}")
+    np.testing.assert_allclose(s.cpu().numpy(), got.sum(axis=1), rtol=1e-12, atol=1e-12 * scale.sum())
+    if not big:
+        T.set_variant(amd.VARIANT_AUTO)
+        one, _ = amd.evaluate_complex(T, Et, wt, beta, e_reg)
+        torch.cuda.synchronize()
+        assert amd.last_variant() == "specialized complex"
+        assert np.max(np.abs(one.cpu().numpy() - got) / scale) <= 1e-13

@@ -110,6 +110,10 @@ def test_two_pass_refusals_and_frequency_limit():
     with pytest.raises(amd.AmiError) as e:           # the second kernel's grid height
         amd.evaluate(T, E, w, 5.0)
     assert e.value.code == -7
-    with pytest.raises(amd.AmiError) as e:           # forward only
-        amd.evaluate_adjoint(T, E, w[:1], 5.0, grad_sum=torch.ones(1, dtype=torch.complex128, device=DEV))
-    assert e.value.code == -7
+    # the adjoint under this variant runs in passes, its frequency rows in a
+    # loop of the kernel (no grid-height limit): many rows are taken
+    E2 = torch.from_numpy(uniform_energies(64, d.n_eps, seed=(35, 4), a=3.0)).to(DEV)
+    g_e, _, g_w = amd.evaluate_adjoint(T, E2, w, 5.0, grad_sum=torch.ones(len(w), dtype=torch.complex128, device=DEV))
+    torch.cuda.synchronize()
+    assert amd.last_variant() == "specialized passes"
+    assert g_e.shape == (64, d.n_eps) and g_w.shape == (65536, 1) and torch.isfinite(g_w).all()
