@@ -56,6 +56,9 @@ def parse():
     ap.add_argument("--batch-n-e", type=int, default=200_000)
     ap.add_argument("--no-configs", action="store_true",
                     help="skip the other workloads (C1-C3, large solutions)")
+    ap.add_argument("--sections", default="next,configs,large,batch",
+                    help="sections beside the headline step, comma-separated: next (the rows beyond the "
+                         "main path), configs (C1-C3), large (the adjoint of large solutions), batch")
     ap.add_argument("--copy-mib", type=int, default=0,
                     help="first copy a buffer of this many MiB device to device (a plain copy "
                          "kernel of known size, to scale hardware byte counters)")
@@ -309,8 +312,7 @@ def configs_section(args, torch, dev, stream):
     beta = 2, 5, 10 and 10^6 k-samples (forward, and the value-and-gradient
     step); C3, an order-4 topology on the 256-point real-frequency grid
     omega + 0.05i, omega in [-6, 6], at 10^6 k-samples (out is 4.1 GB: HBM
-    rate and FP64 fraction); and the adjoint of large solutions in passes
-    (order 5 and order 6 at 2 10^5 k-samples, one Matsubara frequency)."""
+    rate and FP64 fraction)."""
     import numpy as np
 
     import paper_2311_17189_amd as amd
@@ -401,7 +403,53 @@ def configs_section(args, torch, dev, stream):
         del out
     except amd.AmiError as e:
         res["C3_real_frequency_grid"] = f"not run: {e}"
-    # the adjoint of large solutions in passes: forward and value-and-gradient step
+    return res
+
+
+def large_section(args, torch, dev, stream):
+    """The adjoint of large solutions in passes (order 5 and order 6 at 2 10^5
+    k-samples, one Matsubara frequency): forward and value-and-gradient step,
+    each the median of 25 individually timed calls."""
+    import numpy as np
+
+    import paper_2311_17189_amd as amd
+    from ami_inputs import DEFAULT_Q, k_samples, matsubara_freqs, random_self_energy
+    from paper_2311_17189_amd import roofline as rl
+
+    q = np.array(DEFAULT_Q)
+    res = {}
+
+    def fwd_and_step(d, n_e, seed, beta, freqs):
+        T = amd.Terms.from_diagram(d)
+        T.upload()
+        T.specialize(momentum=True)
+        st = rl.structure_from_canonical(T.canonical())
+        k = torch.from_numpy(k_samples(n_e, d.n_int, seed=seed)).to(dev)
+        w = torch.from_numpy(freqs).to(dev)
+        n_f = w.shape[0]
+        out = torch.empty((n_f, n_e), dtype=torch.complex128, device=dev)
+        osum = torch.empty((n_f,), dtype=torch.complex128, device=dev)
+        gs = torch.ones((n_f,), dtype=torch.complex128, device=dev)
+        te = float(st.T) * n_e * n_f
+        fwd = lambda: amd.evaluate_hubbard(T, k, q, 1.0, 0.0, w, beta, want_sum=True, out=out, out_sum=osum,
+                                           stream=stream)
+        f_med, f_min = _median_ms(torch, stream, fwd)
+        ffl = rl.specialized_forward_flops(st, n_e, n_f, d.alpha)["total"]
+        row = {"terms": st.T, "n_e": n_e, "n_f": n_f, "beta": beta, "fwd_ms_median": f_med, "fwd_ms_min": f_min,
+               "fwd_kernel": amd.last_variant(), "fwd_term_evals_per_s": te / (f_med * 1e-3),
+               "fwd_frac_fp64_peak": ffl / (f_med * 1e-3) / rl.PEAK_FP64_VECTOR}
+        g = [None]
+
+        def step():
+            g[0] = amd.evaluate_hubbard_adjoint(T, k, q, 1.0, 0.0, w, beta, grad_sum=gs, out=out,
+                                                out_sum=osum, stream=stream, grads=g[0])
+        s_med, s_min = _median_ms(torch, stream, step)
+        sfl = rl.specialized_adjoint_flops(st, n_e, n_f, d.alpha, with_values=True)["total"]
+        row.update({"step_ms_median": s_med, "step_ms_min": s_min, "step_kernel": amd.last_variant(),
+                    "step_term_evals_per_s": te / (s_med * 1e-3),
+                    "step_frac_fp64_peak": sfl / (s_med * 1e-3) / rl.PEAK_FP64_VECTOR})
+        return row
+
     large = []
     for order, seed in ((5, (0, 5, 0)), (6, (0, 6, 0)), (6, (5, 6, 2))):
         try:
@@ -411,16 +459,16 @@ def configs_section(args, torch, dev, stream):
             large.append(row)
         except amd.AmiError as e:
             large.append({"order": order, "topology": list(seed), "error": str(e)})
-    res["large_adjoint_passes"] = large
-    return res
+    return large
 
 
 def next_rows_section(args, torch, dev, stream):
     """The rows built beyond the main path, each measured on the order-4
-    workload: complex energies (forward, energy input), poles of higher order
-    (the order-4 topology with one internal line taken twice, momentum input,
-    forward) and graph input (label + construct from the 4-column form); and a
-    large order-6 solution through the two-pass forward."""
+    workload: complex energies (forward and value-and-gradient step, energy
+    input), poles of higher order (the order-4 topology with one internal line
+    taken twice, momentum input, forward and step) and graph input (label +
+    construct from the 4-column form); and a large order-6 solution through
+    the two-pass forward, at real momenta and at complex energies."""
     import numpy as np
 
     import paper_2311_17189_amd as amd
@@ -449,6 +497,14 @@ def next_rows_section(args, torch, dev, stream):
             "kernel": amd.last_variant(), "ms": ms, "kernel_ms": kms,
             "term_evals_per_s": float(st.T) * n_e / (ms * 1e-3),
             "flops_per_launch": fl["total"], "frac_fp64_peak": fl["total"] / (kms * 1e-3) / rl.PEAK_FP64_VECTOR}
+        # its value-and-gradient step: dL/dRe E + i dL/dIm E, dL/dbeta, dL/dw of the summed values
+        gs = torch.ones((1,), dtype=torch.complex128, device=dev)
+        ms_a, kms_a = _timed_kernel(torch, amd, stream, lambda: amd.evaluate_complex_adjoint(
+            T, E, w, args.beta, grad_sum=gs, out=out, out_sum=osum, stream=stream), reps)
+        res["complex_adjoint"] = {
+            "workload": res["complex_energies"]["workload"] + "; value-and-gradient step (complex energy gradients)",
+            "kernel": amd.last_variant(), "ms": ms_a, "kernel_ms": kms_a,
+            "term_evals_per_s": float(st.T) * n_e / (ms_a * 1e-3)}
     except amd.AmiError as e:
         res["complex_energies"] = f"not run: {e}"
     # poles of higher order: one internal line repeated, its energy slot unused
@@ -476,6 +532,18 @@ def next_rows_section(args, torch, dev, stream):
             "terms": st.T, "leaf_orders": orders, "kernel": amd.last_variant(), "ms": ms, "kernel_ms": kms,
             "term_evals_per_s": float(st.T) * n_e / (ms * 1e-3),
             "flops_per_launch": fl["total"], "frac_fp64_peak": fl["total"] / (kms * 1e-3) / rl.PEAK_FP64_VECTOR}
+        # its value-and-gradient step (Taylor-coefficient leaves differentiated in the kernel)
+        gs = torch.ones((1,), dtype=torch.complex128, device=dev)
+        g = [None]
+
+        def mstep():
+            g[0] = amd.evaluate_hubbard_adjoint(T, k, q, 1.0, 0.0, w, args.beta, grad_sum=gs, out=out,
+                                                out_sum=osum, stream=stream, grads=g[0])
+        ms_a, kms_a = _timed_kernel(torch, amd, stream, mstep, reps)
+        res["multipole_adjoint"] = {
+            "workload": res["multipole"]["workload"] + "; value-and-gradient step",
+            "kernel": amd.last_variant(), "ms": ms_a, "kernel_ms": kms_a,
+            "term_evals_per_s": float(st.T) * n_e / (ms_a * 1e-3)}
     except amd.AmiError as e:
         res["multipole"] = f"not run: {e}"
     # a large solution through the two-pass forward: order 6, 2804 terms, the
@@ -500,6 +568,16 @@ def next_rows_section(args, torch, dev, stream):
             "kernel": amd.last_variant(), "ms": ms,
             "term_evals_per_s": float(st.T) * n_l * n_fl / (ms * 1e-3),
             "flops_per_call": fl["total"], "frac_fp64_peak": fl["total"] / (ms * 1e-3) / rl.PEAK_FP64_VECTOR}
+        # the same solution at complex energies (two passes: above the one-pass size)
+        eta = 0.25 / (args.beta * dl.n_int)
+        Ec = torch.from_numpy(complex_energies(n_l, dl.n_eps, seed=(104, 6, 2), a=3.0, eta=eta)).to(dev)
+        ms_c, _ = _timed_kernel(torch, amd, stream, lambda: amd.evaluate_complex(
+            T, Ec, wl, args.beta, out=out, out_sum=osum, want_sum=True, stream=stream), 5)
+        res["large_complex_two_pass"] = {
+            "workload": f"order-6 topology (5, 6, 2), {st.T} terms, {n_l} complex energy rows (|Im| < {eta:.3g}), "
+                        f"{n_fl} Matsubara frequencies, out + row sums",
+            "kernel": amd.last_variant(), "ms": ms_c,
+            "term_evals_per_s": float(st.T) * n_l * n_fl / (ms_c * 1e-3)}
     except amd.AmiError as e:
         res["large_two_pass"] = f"not run: {e}"
     # graph input: label and construct, host only
@@ -820,10 +898,18 @@ def main():
         "wall_s": wall,
     }
     res["ms_per_step_median"], res["ms_per_step_min"] = step_median
-    res["next_rows"] = next_rows_section(args, torch, dev, stream)
-    if not args.no_configs:
+    sections = {x.strip() for x in args.sections.split(",") if x.strip()}
+    if args.no_configs:
+        sections -= {"configs", "large"}
+    if args.no_batch:
+        sections.discard("batch")
+    if "next" in sections:
+        res["next_rows"] = next_rows_section(args, torch, dev, stream)
+    if "configs" in sections:
         res["configs"] = configs_section(args, torch, dev, stream)
-    if not args.no_batch:
+    if "large" in sections:
+        res["large_adjoint_passes"] = large_section(args, torch, dev, stream)
+    if "batch" in sections:
         res["batch"] = batch_section(args, torch, dev)
     if args.cpu_seconds > 0:
         res["cpu_baseline"] = cpu_baseline(d, k_host, q, args.beta, hop_t, mu, w_host,

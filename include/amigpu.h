@@ -413,7 +413,7 @@ AmiStatus amiIntegrateHubbard(AmiTerms *terms, int64_t n_samples, uint64_t seed,
  *   AMI_VARIANT_TWO_PASS     the specialized forward in two passes: a first
  *                            kernel stores every sample's group sums and
  *                            energies in a workspace (in chunks of at most
- *                            256 MB), a second evaluates, per frequency row,
+ *                            1 GiB), a second evaluates, per frequency row,
  *                            the denominators and the group products against
  *                            them; register use independent of the number of
  *                            groups; at most 65535 frequency rows per call.
@@ -435,9 +435,10 @@ enum { AMI_VARIANT_AUTO = 0, AMI_VARIANT_TABLES = 1, AMI_VARIANT_PACKED = 2, AMI
 AmiStatus amiSetVariant(AmiTerms *terms, int32_t variant);
 
 /*
- * amiSetTwoPassChunkBytes -- bound (bytes, >= 64 KiB; default 256 MB) on the
- * workspace of one chunk of samples of the two-pass forward, for every handle
- * of the process: a call with more samples than fit runs chunk after chunk.
+ * amiSetTwoPassChunkBytes -- bound (bytes, >= 64 KiB; default 1 GiB) on the
+ * workspace of one chunk of samples of the two-pass forward (real or complex
+ * energies) and of the adjoint in passes, for every handle of the process: a
+ * call with more samples than fit runs chunk after chunk.
  * Takes effect at the next call; the workspace never shrinks.
  */
 AmiStatus amiSetTwoPassChunkBytes(int64_t bytes);

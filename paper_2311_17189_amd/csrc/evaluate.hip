@@ -333,9 +333,11 @@ bool timer_pair(hipEvent_t &start, hipEvent_t &stop) {
 
 enum class Path { TABLES, PACKED, SPECIALIZED, TWO_PASS, ADJ_PASSES };
 
-// Workspace of one chunk of the two-pass forward (group sums and energies):
-// 256 MB unless amiSetTwoPassChunkBytes set another bound.
-std::atomic<int64_t> g_two_pass_chunk_bytes{int64_t(256) << 20};
+// Workspace of one chunk of the two-pass forward and of the adjoint in passes
+// (group sums, energies and their cotangents): 1 GiB unless
+// amiSetTwoPassChunkBytes set another bound (a chunk never exceeds what the
+// call's samples need).
+std::atomic<int64_t> g_two_pass_chunk_bytes{int64_t(1) << 30};
 // Frequency rows of one two-pass launch (its second kernel runs a block per
 // tile and frequency row; the bound keeps that grid below 2^31 blocks).
 constexpr int kTwoPassMaxFreqs = 65535;

@@ -72,8 +72,12 @@ extern "C" __global__ __launch_bounds__(AMI_JIT_BLOCK) void ami_jit_cfwd(ami::KA
 #endif
 
 #if AMI_JIT_KERNELS & 256
-extern "C" __global__ __launch_bounds__(AMI_JIT_BLOCK) AMI_JIT_ADJ_ATTR void ami_jit_cadj(ami::KArgs a) {
-    amijit::cadj_tile(a, blockIdx.x);
+#if AMI_JIT_CADJ_WAVES > 0
+__attribute__((amdgpu_waves_per_eu(AMI_JIT_CADJ_WAVES)))
+#endif
+extern "C" __global__ __launch_bounds__(AMI_JIT_BLOCK) void ami_jit_cadj(ami::KArgs a) {
+    __shared__ double park[amijit::kParkS ? 2 * amijit::L * AMI_JIT_BLOCK : 1];
+    amijit::cadj_tile(a, blockIdx.x, park);
 }
 #endif
 

@@ -896,6 +896,11 @@ __device__ __forceinline__ void cfreq_tile(const KArgs &a, int64_t tile, int f) 
 #endif
 
 #if AMI_JIT_KERNELS & 256
+// The complex adjoint's leaf slopes S_l (2 L doubles per lane) wait in LDS
+// through the reverse sweep where they fit in 80 KB per block (two blocks of
+// 256 lanes per CU) and the real adjoint parks its slopes too.
+constexpr bool kParkS = kParkDv && 2 * L * AMI_JIT_BLOCK * 8 <= 80 * 1024;
+
 // Adjoint at complex energies (energy input; interleaved complex128 rows,
 // strides in complex elements; grad_e complex [n_e][NE]).  Every quantity is
 // analytic in E, so the cotangents are complex, in the convention
@@ -905,10 +910,11 @@ __device__ __forceinline__ void cfreq_tile(const KArgs &a, int64_t tile, int f) 
 // with u_g = -FT_g conj(c) R_g as in the real adjoint (its real part scatters
 // to Re Ebar and w, minus its imaginary part to Im Ebar).  After the rows the
 // leaves are formed again (with f(-y)): Fbar from leaf_cotangents_c at
-// conj(F), V_l = Fbar_l conj(f'(y_l)) with f' = -f(y) f(-y), so that
+// conj(F), V_l = Fbar_l conj(f'(y_l)) with f' = -f(y) f(-y) (conj(f') waiting
+// in the park area where kParkS), so that
 // xbar_l = beta V_l and dL/dbeta = sum_l Re(conj(V_l) x_l).  The values are
 // formed as in cfwd_tile.
-__device__ __forceinline__ void cadj_tile(const KArgs &a, int64_t blk) {
+__device__ __forceinline__ void cadj_tile(const KArgs &a, int64_t blk, double *park) {
 #pragma clang fp contract(fast)
     const int tid = threadIdx.x, B = blockDim.x, lane = tid & 63;
     const int64_t row = blk * (B >> 6) + (tid >> 6);
@@ -1023,25 +1029,55 @@ __device__ __forceinline__ void cadj_tile(const KArgs &a, int64_t blk) {
             ami::wave_store4(vv[c], vv[c + 1], vv[c + 2], vv[c + 3], lane, pp[c], pp[c + 1], pp[c + 2], pp[c + 3]);
     }
 
+    // the leaves again: conj(F) for the reverse sweep and S = conj(f'(y)),
+    // formed leaf by leaf so that only these three pairs stay live through it
     double gbeta = 0.0;
     {
-        double xr[L], xi[L], Fr[L], Fi[L], Mr[L], Mi[L], cFi[L], FBr[L], FBi[L], vr[L], vi[L];
-        leaf_args(Er, xr);
-        leaf_args(Ei, xi);
+        // opaque copies of the energies: the compiler cannot match these
+        // evaluations with those before the rows and keep their intermediates
+        // live through them
+        double er[NE], ei[NE];
+#pragma unroll
+        for (int j = 0; j < NE; ++j) {
+            er[j] = Er[j];
+            ei[j] = Ei[j];
+            AMI_OPAQUE(er[j]);
+            AMI_OPAQUE(ei[j]);
+        }
+        double Fr[L], cFi[L], Sr[kParkS ? 1 : L], Si[kParkS ? 1 : L], FBr[L], FBi[L];
+        {
+            double xr[L], xi[L];
+            leaf_args(er, xr);
+            leaf_args(ei, xi);
+#pragma unroll
+            for (int l = 0; l < L; ++l) {
+                double fi, mr, mi;
+                ami::leaf_complex_pair(kBose[l], a.beta * (kBose[l] ? xr[l] + a.e_reg : xr[l]), a.beta * xi[l],
+                                       Fr[l], fi, mr, mi);
+                cFi[l] = -fi;
+                const double sr = -fma(Fr[l], mr, -fi * mi);   // conj(f') = -conj(f) conj(f(-y))
+                const double si = fma(Fr[l], mi, fi * mr);
+                if constexpr (kParkS) {
+                    park[(2 * l) * B + tid] = sr;
+                    park[(2 * l + 1) * B + tid] = si;
+                } else {
+                    Sr[kParkS ? 0 : l] = sr;
+                    Si[kParkS ? 0 : l] = si;
+                }
+                FBr[l] = FBi[l] = 0.0;
+            }
+        }
+        leaf_cotangents_c(Fr, cFi, FTBr, FTBi, FBr, FBi);
+        double xr[L], xi[L], vr[L], vi[L];
+        leaf_args(er, xr);
+        leaf_args(ei, xi);
 #pragma unroll
         for (int l = 0; l < L; ++l) {
             if (kBose[l]) xr[l] += a.e_reg;
-            ami::leaf_complex_pair(kBose[l], a.beta * xr[l], a.beta * xi[l], Fr[l], Fi[l], Mr[l], Mi[l]);
-            cFi[l] = -Fi[l];
-            FBr[l] = FBi[l] = 0.0;
-        }
-        leaf_cotangents_c(Fr, cFi, FTBr, FTBi, FBr, FBi);
-#pragma unroll
-        for (int l = 0; l < L; ++l) {
-            const double dpr = -fma(Fr[l], Mr[l], -Fi[l] * Mi[l]);   // f'(y) = -f(y) f(-y)
-            const double dpi = -fma(Fr[l], Mi[l], Fi[l] * Mr[l]);
-            const double Vr = fma(FBr[l], dpr, FBi[l] * dpi);        // V = Fbar conj(f')
-            const double Vi = fma(FBi[l], dpr, -FBr[l] * dpi);
+            const double sr = kParkS ? park[(2 * l) * B + tid] : Sr[kParkS ? 0 : l];
+            const double si = kParkS ? park[(2 * l + 1) * B + tid] : Si[kParkS ? 0 : l];
+            const double Vr = fma(FBr[l], sr, -FBi[l] * si);         // V = Fbar conj(f')
+            const double Vi = fma(FBr[l], si, FBi[l] * sr);
             gbeta = fma(Vr, xr[l], fma(Vi, xi[l], gbeta));
             vr[l] = Vr * a.beta;
             vi[l] = Vi * a.beta;

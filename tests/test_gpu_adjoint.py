@@ -426,7 +426,7 @@ def test_adjoint_passes_chunks_rows_and_values(order, seed):
         many = run()
         again = run()
     finally:
-        amd.set_two_pass_chunk_bytes(256 << 20)
+        amd.set_two_pass_chunk_bytes(1 << 30)
     for a, b, c in zip(one, many, again):
         assert np.array_equal(a, b) and np.array_equal(b, c)
     g_e, g_b, g_w, out, out_sum = many

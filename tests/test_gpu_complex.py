@@ -201,7 +201,7 @@ def test_complex_two_pass(order, seed, n_e):
         out2, s2 = amd.evaluate_complex(T, Et, wt, beta, e_reg, want_out=True, want_sum=True)
         torch.cuda.synchronize()
     finally:
-        amd.set_two_pass_chunk_bytes(256 << 20)
+        amd.set_two_pass_chunk_bytes(1 << 30)
     assert torch.equal(out, out2) and torch.equal(s, s2)
     got = out.cpu().numpy()
     ref, scale, dist = reference(d, E, w, beta, e_reg)

@@ -39,7 +39,7 @@ def test_mc_sums_match_oracle_on_the_same_draws(order, i, n, seed):
     assert np.all(np.abs(got - want) <= bound + 1e-300), (got, want, bound)
 
 
-@pytest.mark.parametrize("i,n,chunk", [(0, 600, 1 << 16), (9, 1500, 256 << 20)])
+@pytest.mark.parametrize("i,n,chunk", [(0, 600, 1 << 16), (9, 1500, 1 << 30)])
 def test_mc_two_pass_for_large_solutions(i, n, chunk):
     """A solution evaluated in two passes (order 6): the first pass draws the
     momenta, the sums match the oracle on the same draws; several chunks."""
@@ -58,7 +58,7 @@ def test_mc_two_pass_for_large_solutions(i, n, chunk):
         again = amd.integrate_hubbard(T, n, 9, q, t, mu, torch.from_numpy(w).to(DEV), beta)
         torch.cuda.synchronize()
     finally:
-        amd.set_two_pass_chunk_bytes(256 << 20)
+        amd.set_two_pass_chunk_bytes(1 << 30)
     assert torch.equal(sums, again)
     got = sums.cpu().numpy()
     k = draw_momenta(0, n, 2 * d.n_int, 9)

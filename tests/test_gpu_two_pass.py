@@ -25,7 +25,7 @@ DEV = "cuda"
 def small_chunks():
     amd.set_two_pass_chunk_bytes(1 << 16)        # a few hundred samples per chunk
     yield
-    amd.set_two_pass_chunk_bytes(256 << 20)
+    amd.set_two_pass_chunk_bytes(1 << 30)
 
 
 @pytest.mark.parametrize("i,n_e", [(0, 1500), (2, 700), (4, 600)])

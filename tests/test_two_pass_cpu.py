@@ -111,4 +111,4 @@ def test_two_pass_limits_and_chunk_setting():
     with pytest.raises(amd.AmiError) as e:
         amd.set_two_pass_chunk_bytes(1000)
     assert e.value.code == -1
-    amd.set_two_pass_chunk_bytes(256 << 20)
+    amd.set_two_pass_chunk_bytes(1 << 30)
