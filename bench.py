@@ -71,10 +71,14 @@ def cpu_baseline(d, k_all, q, beta, t, mu, w, target_s):
     float64 values (its plain evaluation of the flat terms, energies from
     momenta) on all cores -- the reported value -- and on one core, and the
     whole step (float64 values and the analytic gradients of the summed
-    integrand with the momentum chain rule, in long double) on all cores.
-    Each timing takes about target_s / 3 seconds."""
+    integrand with the momentum chain rule, in long double) on all cores;
+    each of these about target_s / 3 seconds.  Beside them: the oracle's own
+    long-double values on 10^4 samples (one process) and its construction time
+    for the diagram."""
     from oracle.construct import canonical, construct
+    t0 = time.perf_counter()
     terms = canonical(construct(d.alpha, d.eps, d.n_int, d.fermionic))
+    construct_ms = (time.perf_counter() - t0) * 1e3
     cores = min(len(os.sched_getaffinity(0)), 16)
     each = target_s / 3.0
     chunk = 1000
@@ -98,12 +102,22 @@ def cpu_baseline(d, k_all, q, beta, t, mu, w, target_s):
         el = time.perf_counter() - t0
         out[key] = {"term_evals_per_s": len(terms) * n * len(w) / el, "samples": n, "processes": n_proc,
                     "seconds": el}
+    # the oracle's own precision (long double) on 10^4 samples, one process
+    n_ld = min(len(k_all), 10_000)
+    t0 = time.perf_counter()
+    for i in range(0, n_ld, chunk):
+        _oracle_values_ld((terms, d, k_all[i:i + chunk], q, beta, t, mu, w))
+    el = time.perf_counter() - t0
+    out["values_longdouble_1core"] = {"term_evals_per_s": len(terms) * n_ld * len(w) / el, "samples": n_ld,
+                                      "processes": 1, "seconds": el}
     v = out["values_f64"]
     return {"value": v["term_evals_per_s"], "unit": "term-evals/s", "cores": cores, "kind": "oracle",
             "sample": f"first {v['samples']} of the same momentum samples, float64 values of the flat terms "
                       f"(energies from momenta), {v['samples'] // chunk} chunks of {chunk} over {cores} "
                       f"processes, {v['seconds']:.1f} s",
             "values_f64_1core": out["values_f64_1core"],
+            "values_longdouble_1core": out["values_longdouble_1core"],
+            "construct_ms": construct_ms,
             "step_values_and_gradients": dict(out["step"], note="float64 values and long-double analytic "
                                                                 "gradients w.r.t. k, mu, t, beta, w")}
 
@@ -115,6 +129,13 @@ def _oracle_values(args):
     terms, d, k, q, beta, t, mu, w = args
     E = energies_from_k(d.alpha, k, q, t, mu, dtype=np.float64)
     return evaluate_terms(terms, d.n_int, E, w, beta, dtype=np.float64).sum(axis=1)
+
+
+def _oracle_values_ld(args):
+    from oracle.evaluate import energies_from_k, evaluate_terms
+    terms, d, k, q, beta, t, mu, w = args
+    E = energies_from_k(d.alpha, k, q, t, mu)
+    return evaluate_terms(terms, d.n_int, E, w, beta).sum(axis=1)
 
 
 def _oracle_step(args):
