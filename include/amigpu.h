@@ -260,9 +260,14 @@ AmiStatus amiEvaluateComplex(AmiTerms *terms,
  * d(1/D)/dD = -1/D^2.  energies, strides, ext_freqs, beta, e_reg: as
  * amiEvaluateComplex; out / out_sum (device, or NULL) receive the forward
  * values on the way.  The sums over samples are reduced in a fixed order.
- * Served by one specialized kernel (compiled on first use; at most 1024
- * terms): AMI_E_UNSUPPORTED for solutions outside its form and for poles of
- * higher order.
+ * Served by the specialized kernels (compiled on first use): one pass up to
+ * 256 terms (up to 1024 under AMI_VARIANT_SPECIALIZED); above, or under
+ * AMI_VARIANT_TWO_PASS, passes over the chunked workspace of the two-pass
+ * variant (complex group sums and energies stored; per frequency row the
+ * values and the complex cotangents of group sums and denominators; then the
+ * leaves' complex cotangents by reverse sweeps), up to 4096 terms.
+ * AMI_E_UNSUPPORTED for solutions outside their form and for poles of higher
+ * order.
  */
 AmiStatus amiEvaluateComplexAdjoint(AmiTerms *terms,
                                     const double *energies, int64_t n_e, int64_t stride_s, int64_t stride_i,
@@ -452,9 +457,9 @@ AmiStatus amiSetTwoPassChunkBytes(int64_t bytes);
  * fails (amiLastError holds the compiler log).  The kernels are the forward
  * (its two passes where AUTO takes them), the adjoint AUTO uses (one pass up
  * to 128 terms, its passes above), and for solutions of at most 1024 terms
- * the complex-energy forward and its adjoint (amiEvaluateComplex,
- * amiEvaluateComplexAdjoint) for the energy input, above that the two passes
- * of the complex-energy forward; all are compiled before a
+ * the complex-energy forward and the kernels of its adjoint that AUTO uses
+ * (amiEvaluateComplex, amiEvaluateComplexAdjoint) for the energy input, above
+ * that the two passes of the complex-energy forward; all are compiled before a
  * device is touched.  A solution with Taylor-coefficient leaves (AMI_MULTIPOLE)
  * gets no complex-energy kernels.
  */

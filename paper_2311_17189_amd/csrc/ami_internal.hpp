@@ -121,8 +121,8 @@ struct AmiTerms {
     // complex energies, 4 and 5 the two passes of the two-pass forward) -- and
     // the modules loaded from them, one per device
     std::mutex jit_mu;
-    std::vector<char> jit_code[22];           // [2 inputs][kJitKinds]
-    std::string jit_error[22];                // why a compilation failed (not retried)
+    std::vector<char> jit_code[26];           // [2 inputs][kJitKinds]
+    std::string jit_error[26];                // why a compilation failed (not retried)
     struct JitModule {
         int device = -1, kind = 0;
         void *module = nullptr, *fn = nullptr;

@@ -395,6 +395,23 @@ int park_cols(const AmiTerms *t, bool hub) { return park_chain(t, hub) + (park_d
 // take more than 256 VGPRs runs at two waves with a few spills rather than at
 // one (order-4 topologies of 40-52 terms: 0.099-0.105 -> 0.081-0.086 ms per
 // 10^6-sample step)
+// Terms per nested part in the complex adjoint's leaf pass (each node holds
+// a complex value and a complex cotangent); AMIGPU_JIT_CADJ_PART overrides.
+int cadj_part_terms() {
+    const char *e = std::getenv("AMIGPU_JIT_CADJ_PART");
+    const int v = e ? std::atoi(e) : 0;
+    return v >= 1 && v <= 64 ? v : 64;
+}
+
+// occupancy floor of the complex adjoint's leaf pass (one wave: its spills
+// at two cost more than the occupancy, 196 terms 1.73 -> 1.25 ms, 560 terms
+// 2.63 -> 1.90 ms per 10^6-sample step); AMIGPU_JIT_CADJL_WAVES overrides
+int cadjl_waves() {
+    const char *e = std::getenv("AMIGPU_JIT_CADJL_WAVES");
+    const int v = e ? std::atoi(e) : -1;
+    return v >= 0 && v <= 8 ? v : 1;
+}
+
 int adj_waves() {
     const char *e = std::getenv("AMIGPU_JIT_ADJ_WAVES");
     if (!e) return 2;
@@ -430,6 +447,9 @@ std::string jit_source(const AmiTerms *t, bool hub, int kernels) {
     // floor cost more than the lost occupancy (196 terms: 1.11 -> 0.86 ms,
     // 560 terms: 6.8 -> 5.7 ms per 10^6-sample step at one wave)
     o << "#define AMI_JIT_CADJ_WAVES " << (tb.T <= kJitAutoAdjointTerms ? adj_waves() : 1) << "\n";
+    // the leaf pass of the complex adjoint in passes (its values per leaf and
+    // node are complex, twice the real pass's)
+    o << "#define AMI_JIT_CADJL_WAVES " << cadjl_waves() << "\n";
     o << "#include \"kargs.hpp\"\n";
     o << "namespace amijit {\n";
     o << "constexpr int NE = " << ne << ", NI = " << ni << ", NG = " << ng << ", NX = " << nx << ";\n";
@@ -952,25 +972,20 @@ std::string jit_source(const AmiTerms *t, bool hub, int kernels) {
         }
         o << "}\n";
     }
-    if (kernels & 128) {
-        // leaf pass: FB_l = sum_g FTB_g dFT_g/dF_l by a reverse sweep of each
-        // group's nested sum (the nodes recomputed, then their cotangents in
-        // reverse order: node h = F_a w + u passes h' w to F_a, h' F_a to w and
-        // h' to u).  A group's terms are nested in parts of at most
-        // kAdjLeafPartTerms (consecutive in canonical order), which bounds the
-        // node values live in a sweep; each leaf is formed just before the
-        // first part that reads it and its cotangent is scattered to the
-        // energies and to beta just after the last one.
-        struct Part {
-            int g;
-            std::vector<HNode> nodes;
-            HRef root;
-            std::vector<int> leaves;
-        };
-        std::vector<Part> parts;
+    // The leaf passes' parts: each group's terms nested in parts of at most
+    // kAdjLeafPartTerms (consecutive in canonical order), with the leaves
+    // each part reads and the first and last part that reads each leaf.
+    struct Part {
+        int g;
+        std::vector<HNode> nodes;
+        HRef root;
+        std::vector<int> leaves;
+    };
+    auto build_parts = [&](std::vector<Part> &parts, std::vector<int> &first_use, std::vector<int> &last_use,
+                           int part_terms) {
         for (int g = 0; g < G; ++g) {
-            for (int t0 = tb.group_start[g]; t0 < tb.group_start[g + 1]; t0 += kAdjLeafPartTerms) {
-                const int t1 = std::min(tb.group_start[g + 1], t0 + kAdjLeafPartTerms);
+            for (int t0 = tb.group_start[g]; t0 < tb.group_start[g + 1]; t0 += part_terms) {
+                const int t1 = std::min(tb.group_start[g + 1], t0 + part_terms);
                 std::vector<HornerTerm> ts;
                 for (int ti = t0; ti < t1; ++ti) {
                     HornerTerm h{tb.term_sign[ti], {}};
@@ -996,12 +1011,26 @@ std::string jit_source(const AmiTerms *t, bool hub, int kernels) {
                 parts.push_back(std::move(pt));
             }
         }
-        std::vector<int> first_use(static_cast<size_t>(L), -1), last_use(static_cast<size_t>(L), -1);
+        first_use.assign(static_cast<size_t>(L), -1);
+        last_use.assign(static_cast<size_t>(L), -1);
         for (size_t p = 0; p < parts.size(); ++p)
             for (int l : parts[p].leaves) {
                 if (first_use[l] < 0) first_use[l] = static_cast<int>(p);
                 last_use[l] = static_cast<int>(p);
             }
+    };
+    if (kernels & 128) {
+        // leaf pass: FB_l = sum_g FTB_g dFT_g/dF_l by a reverse sweep of each
+        // group's nested sum (the nodes recomputed, then their cotangents in
+        // reverse order: node h = F_a w + u passes h' w to F_a, h' F_a to w and
+        // h' to u).  A group's terms are nested in parts of at most
+        // kAdjLeafPartTerms (consecutive in canonical order), which bounds the
+        // node values live in a sweep; each leaf is formed just before the
+        // first part that reads it and its cotangent is scattered to the
+        // energies and to beta just after the last one.
+        std::vector<Part> parts;
+        std::vector<int> first_use, last_use;
+        build_parts(parts, first_use, last_use, kAdjLeafPartTerms);
         o << "__device__ __forceinline__ void leaf_pass(const double (&E)[NE], double beta, double e_reg, const double "
              "*ws, int64_t ld, uint32_t off, double (&gE)[NE], double &gbeta) {\n";
         o << kReverseContract;
@@ -1070,6 +1099,230 @@ std::string jit_source(const AmiTerms *t, bool hub, int kernels) {
                     if (c == 1.0) o << "    gE[" << i << "] += v;\n";
                     else if (c == -1.0) o << "    gE[" << i << "] -= v;\n";
                     else if (c != 0.0) o << "    gE[" << i << "] = fma(" << num(c) << ", v, gE[" << i << "]);\n";
+                }
+                o << "  }\n";
+            }
+            if ((p + 1) % kAdjLeafFenceParts == 0 && p + 1 < parts.size()) o << "  AMI_SCHED_FENCE();\n";
+        }
+        o << "}\n";
+    }
+
+    // The adjoint at complex energies in passes (after the complex two-pass
+    // forward's first pass stored FT_g and E_j, both complex, in the
+    // workspace: columns [0, G) Re FT, [G, 2G) Im FT, [2G, 2G + NE) Re E,
+    // [2G + NE, 2G + 2NE) Im E, then the denominators' energy cotangents
+    // (re NE, im NE) and the group-sum cotangents FTB_g (re G, im G)).  The
+    // cotangents are complex, Xbar = dL/dRe X + i dL/dIm X.
+    const std::string cge0 = "(2 * G + 2 * NE)", cftb0 = "(2 * G + 4 * NE)";
+    if (kernels & 2048) {
+        // frequency pass, one frequency row: per chunk of groups its own
+        // reciprocals (the energies' imaginary parts in the denominators),
+        // each group's R_g, the value FT_g R_g, FTB_g += c conj(R_g) (stored;
+        // added to the stored value after the first row), u_g = -FT_g conj(c)
+        // R_g summed per denominator, then U_k rho_k = conj(Dbar_k) scattered:
+        // its real part to Re Ebar and the frequencies, minus its imaginary
+        // part to Im Ebar
+        o << "template <bool FIRST>\n__device__ __forceinline__ void cadj_freq_row(const double (&Er)[NE], const double "
+             "(&Ei)[NE], const double (&wr)["
+          << NXA << "], const double (&wi)[" << NXA << "], double cr, double ci, double *ws, int64_t ld, uint32_t off, "
+             "double &acc_re, double &acc_im, double (&gEr)[NE], double (&gEi)[NE], double (&gwr)["
+          << NXA << "], double (&gwi)[" << NXA << "]) {\n";
+        for (int g0 = 0; g0 < G; g0 += kAdjChunkGroups) {
+            const int g1 = std::min(G, g0 + kAdjChunkGroups);
+            std::vector<int> ks;
+            for (int g = g0; g < g1; ++g)
+                for (int j = gbegin(g); j < gend(g); ++j) ks.push_back(tb.group_den_list[j]);
+            std::sort(ks.begin(), ks.end());
+            ks.erase(std::unique(ks.begin(), ks.end()), ks.end());
+            o << "  {\n    double xr[D], xi[D];\n";
+            for (int k : ks) {
+                Lin re, im;
+                for (int i = 0; i < ne; ++i) {
+                    re.add(tb.den_coef[static_cast<size_t>(k) * nc + i], idx("Er", i));
+                    im.add(tb.den_coef[static_cast<size_t>(k) * nc + i], idx("Ei", i));
+                }
+                for (int x = 0; x < nx; ++x) {
+                    const double a = tb.den_coef[static_cast<size_t>(k) * nc + ne + x];
+                    re.add(a, idx("wr", x));
+                    im.add(a, idx("wi", x));
+                }
+                o << "    { const double dr = " << re.str() << ", di = " << im.str()
+                  << ";\n      const double inv = ami::rcp_nr(fma(dr, dr, di * di));\n      xr[" << k
+                  << "] = dr * inv;\n      xi[" << k << "] = -di * inv; }\n";
+            }
+            for (int k : ks) o << "    double Ur" << k << " = 0.0, Ui" << k << " = 0.0;\n";
+            for (int g = g0; g < g1; ++g) {
+                o << "    { const double ftr = ami::ws_load(ws, ld, " << g << ", off), fti = ami::ws_load(ws, ld, "
+                  << G + g << ", off);\n";
+                o << "      double rr = 1.0, ri = 0.0, nr = 0.0;\n";
+                for (int j = gbegin(g); j < gend(g); ++j) {
+                    const std::string k = std::to_string(tb.group_den_list[j]);
+                    if (j == gbegin(g)) o << "      rr = xr[" << k << "]; ri = xi[" << k << "];\n";
+                    else
+                        o << "      nr = fma(rr, xr[" << k << "], -ri * xi[" << k << "]); ri = fma(rr, xi[" << k
+                          << "], ri * xr[" << k << "]); rr = nr;\n";
+                }
+                o << "      (void)nr;\n";
+                o << "      acc_re = fma(ftr, rr, fma(-fti, ri, acc_re));\n"
+                     "      acc_im = fma(ftr, ri, fma(fti, rr, acc_im));\n";
+                o << "      const double tbr = fma(cr, rr, ci * ri), tbi = fma(ci, rr, -cr * ri);\n";
+                const std::string cr_ = cftb0 + " + " + std::to_string(g), ci_ = cftb0 + " + " + std::to_string(G + g);
+                o << "      if constexpr (FIRST) {\n        ami::ws_store(ws, ld, " << cr_ << ", off, tbr);\n"
+                  << "        ami::ws_store(ws, ld, " << ci_ << ", off, tbi);\n      } else {\n"
+                  << "        ami::ws_store(ws, ld, " << cr_ << ", off, ami::ws_load(ws, ld, " << cr_ << ", off) + tbr);\n"
+                  << "        ami::ws_store(ws, ld, " << ci_ << ", off, ami::ws_load(ws, ld, " << ci_
+                  << ", off) + tbi);\n      }\n";
+                o << "      const double qr = fma(ftr, cr, fti * ci), qi = fma(fti, cr, -ftr * ci);\n";
+                o << "      const double ur = -fma(qr, rr, -qi * ri), ui = -fma(qr, ri, qi * rr);\n";
+                for (int j = gbegin(g); j < gend(g); ++j) {
+                    const std::string k = std::to_string(tb.group_den_list[j]);
+                    o << "      Ur" << k << " += ur; Ui" << k << " += ui;\n";
+                }
+                o << "    }\n";
+            }
+            for (int k : ks) {
+                o << "    { const double dR = fma(Ur" << k << ", xr[" << k << "], -Ui" << k << " * xi[" << k
+                  << "]), dI = fma(Ur" << k << ", xi[" << k << "], Ui" << k << " * xr[" << k << "]);\n";
+                for (int i = 0; i < ne; ++i) {
+                    const double c = tb.den_coef[static_cast<size_t>(k) * nc + i];
+                    if (c == 1.0) o << "      gEr[" << i << "] += dR; gEi[" << i << "] -= dI;\n";
+                    else if (c == -1.0) o << "      gEr[" << i << "] -= dR; gEi[" << i << "] += dI;\n";
+                    else if (c != 0.0)
+                        o << "      gEr[" << i << "] = fma(" << num(c) << ", dR, gEr[" << i << "]); gEi[" << i
+                          << "] = fma(" << num(-c) << ", dI, gEi[" << i << "]);\n";
+                }
+                for (int x = 0; x < nx; ++x) {
+                    const double a = tb.den_coef[static_cast<size_t>(k) * nc + ne + x];
+                    if (a == 0.0) continue;
+                    o << "      gwr[" << x << "] = fma(" << num(a) << ", dR, gwr[" << x << "]);\n";
+                    o << "      gwi[" << x << "] = fma(" << num(a) << ", dI, gwi[" << x << "]);\n";
+                }
+                o << "    }\n";
+            }
+            o << "  }\n";
+            if (g1 < G) o << "  AMI_SCHED_FENCE();\n";
+        }
+        o << "}\n";
+    }
+    if (kernels & 4096) {
+        // leaf pass at complex energies: the reverse sweep of each part of a
+        // group's nested sum in complex arithmetic; a node h = F_a w + u
+        // passes hbar conj(w) to F_a, hbar conj(F_a) to w and hbar to u.
+        // Each leaf is formed just before the first part that reads it; after
+        // the last one its pair again gives S = conj(f'(y)) = -conj(f(y) f(-y)),
+        // and V = Fbar S gives xbar = beta V to the energies and
+        // Re(conj(V) x) to beta.
+        std::vector<Part> parts;
+        std::vector<int> first_use, last_use;
+        build_parts(parts, first_use, last_use, cadj_part_terms());
+        o << "__device__ __forceinline__ void cleaf_pass(const double (&Er)[NE], const double (&Ei)[NE], double beta, "
+             "double e_reg, const double *ws, int64_t ld, uint32_t off, double (&gEr)[NE], double (&gEi)[NE], "
+             "double &gbeta) {\n";
+        o << kReverseContract;
+        o << "  (void)e_reg;\n";
+        for (int l = 0; l < L; ++l)
+            o << "  double Fr" << l << ", Fi" << l << ", FBr" << l << ", FBi" << l << ";\n";
+        auto arg = [&](int l, bool imag) {
+            Lin x;
+            for (int i = 0; i < ne; ++i) x.add(tb.leaf_coef[static_cast<size_t>(l) * ne + i], idx(imag ? "Ei" : "Er", i));
+            return x.str() + (!imag && tb.leaf_sigma[l] < 0 ? " + e_reg" : "");
+        };
+        // names of a reference's value: real and imaginary part (without its sign)
+        auto vre = [&](const HRef &r) -> std::string {
+            if (r.kind == HRef::LEAF) return "Fr" + std::to_string(r.idx);
+            if (r.kind == HRef::NODE) return "h" + std::to_string(r.idx) + "r";
+            return r.kind == HRef::CONST ? num(r.c) : std::string("0.0");
+        };
+        auto vim = [&](const HRef &r) -> std::string {
+            if (r.kind == HRef::LEAF) return "Fi" + std::to_string(r.idx);
+            if (r.kind == HRef::NODE) return "h" + std::to_string(r.idx) + "i";
+            return std::string("0.0");
+        };
+        auto sg = [](const HRef &r, const std::string &e) { return r.neg ? "(-" + e + ")" : e; };
+        for (size_t p = 0; p < parts.size(); ++p) {
+            const Part &pt = parts[p];
+            for (int l : pt.leaves) {
+                if (first_use[l] != static_cast<int>(p)) continue;
+                o << "  ami::leaf_complex(" << (tb.leaf_sigma[l] < 0 ? "true" : "false") << ", beta * ("
+                  << arg(l, false) << "), beta * (" << arg(l, true) << "), Fr" << l << ", Fi" << l << ");\n  FBr" << l
+                  << " = 0.0; FBi" << l << " = 0.0;\n";
+            }
+            o << "  { const double tbr = ami::ws_load(ws, ld, " << cftb0 << " + " << pt.g
+              << ", off), tbi = ami::ws_load(ws, ld, " << cftb0 << " + " << G + pt.g << ", off);\n";
+            // forward: node values
+            const size_t nn = pt.nodes.size();
+            for (size_t k = 0; k < nn; ++k) {
+                const HNode &n = pt.nodes[k];
+                const std::string far = "Fr" + std::to_string(n.a), fai = "Fi" + std::to_string(n.a);
+                // u's parts (signed)
+                std::string ur = "0.0", ui = "0.0";
+                if (n.u.kind == HRef::CONST) ur = num(n.u.c);
+                else if (n.u.kind != HRef::ZERO) {
+                    ur = sg(n.u, vre(n.u));
+                    ui = sg(n.u, vim(n.u));
+                }
+                std::string hr, hi;
+                if (n.w.kind == HRef::CONST) {
+                    hr = "fma(" + num(n.w.c) + ", " + far + ", " + ur + ")";
+                    hi = "fma(" + num(n.w.c) + ", " + fai + ", " + ui + ")";
+                } else {
+                    const std::string wr = sg(n.w, vre(n.w)), wi = sg(n.w, vim(n.w));
+                    hr = "fma(" + far + ", " + wr + ", fma(-" + fai + ", " + wi + ", " + ur + "))";
+                    hi = "fma(" + far + ", " + wi + ", fma(" + fai + ", " + wr + ", " + ui + "))";
+                }
+                o << "    const double h" << k << "r = " << hr << ", h" << k << "i = " << hi << ";\n";
+            }
+            for (size_t k = 0; k < nn; ++k) o << "    double hb" << k << "r = 0.0, hb" << k << "i = 0.0;\n";
+            // a cotangent (cr, ci) passed to reference r
+            auto pass = [&](const HRef &r, const std::string &cr, const std::string &ci) {
+                const char *op = r.neg ? " -= " : " += ";
+                if (r.kind == HRef::NODE)
+                    o << "    hb" << r.idx << "r" << op << cr << "; hb" << r.idx << "i" << op << ci << ";\n";
+                else if (r.kind == HRef::LEAF)
+                    o << "    FBr" << r.idx << op << cr << "; FBi" << r.idx << op << ci << ";\n";
+            };
+            pass(pt.root, "tbr", "tbi");
+            for (size_t kk = nn; kk-- > 0;) {
+                const HNode &n = pt.nodes[kk];
+                const std::string br = "hb" + std::to_string(kk) + "r", bi = "hb" + std::to_string(kk) + "i";
+                const std::string far = "Fr" + std::to_string(n.a), fai = "Fi" + std::to_string(n.a);
+                const std::string fbr = "FBr" + std::to_string(n.a), fbi = "FBi" + std::to_string(n.a);
+                if (n.w.kind == HRef::CONST) {
+                    o << "    " << fbr << " = fma(" << num(n.w.c) << ", " << br << ", " << fbr << "); " << fbi
+                      << " = fma(" << num(n.w.c) << ", " << bi << ", " << fbi << ");\n";
+                } else {
+                    // F_a += hbar conj(w) (w with its sign); w += hbar conj(F_a) (sign applied by pass)
+                    const std::string wr = sg(n.w, vre(n.w)), wi = sg(n.w, vim(n.w));
+                    o << "    " << fbr << " = fma(" << br << ", " << wr << ", fma(" << bi << ", " << wi << ", " << fbr
+                      << ")); " << fbi << " = fma(" << bi << ", " << wr << ", fma(-" << br << ", " << wi << ", " << fbi
+                      << "));\n";
+                    pass(n.w, "fma(" + br + ", " + far + ", " + bi + " * " + fai + ")",
+                         "fma(" + bi + ", " + far + ", -" + br + " * " + fai + ")");
+                }
+                pass(n.u, br, bi);
+            }
+            o << "  }\n";
+            for (int l : pt.leaves) {
+                if (last_use[l] != static_cast<int>(p)) continue;
+                // the slope from the leaf pair formed again, from opaque copies of
+                // its argument (else the compiler merges it with the first
+                // evaluation and keeps that one's values live through the sweep)
+                const std::string L_ = std::to_string(l);
+                o << "  { double yr = beta * (" << arg(l, false) << "), yi = beta * (" << arg(l, true)
+                  << ");\n    AMI_OPAQUE(yr); AMI_OPAQUE(yi);\n    double fr, fi, mr, mi;\n    ami::leaf_complex_pair("
+                  << (tb.leaf_sigma[l] < 0 ? "true" : "false")
+                  << ", yr, yi, fr, fi, mr, mi);\n    const double Sr = -fma(fr, mr, -fi * mi), Si = fma(fr, mi, fi * mr);\n";
+                o << "    const double Vr = fma(FBr" << L_ << ", Sr, -FBi" << L_ << " * Si), Vi = fma(FBr" << L_
+                  << ", Si, FBi" << L_ << " * Sr);\n";
+                o << "    gbeta = fma(Vr, " << arg(l, false) << ", fma(Vi, " << arg(l, true) << ", gbeta));\n";
+                o << "    const double vr = Vr * beta, vi = Vi * beta;\n";
+                for (int i = 0; i < ne; ++i) {
+                    const double c = tb.leaf_coef[static_cast<size_t>(l) * ne + i];
+                    if (c == 1.0) o << "    gEr[" << i << "] += vr; gEi[" << i << "] += vi;\n";
+                    else if (c == -1.0) o << "    gEr[" << i << "] -= vr; gEi[" << i << "] -= vi;\n";
+                    else if (c != 0.0)
+                        o << "    gEr[" << i << "] = fma(" << num(c) << ", vr, gEr[" << i << "]); gEi[" << i << "] = fma("
+                          << num(c) << ", vi, gEi[" << i << "]);\n";
                 }
                 o << "  }\n";
             }
@@ -1247,7 +1500,7 @@ std::string jit_batch_source(const std::vector<const AmiTerms *> &items, const s
     // the tile functions read the argument blocks through the constant address space
     o << "#define AMI_JIT_ARGS const __attribute__((address_space(4))) ami::KArgs\n";
     const char *const kSettings[] = {"AMI_JIT_HUB", "AMI_JIT_KERNELS", "AMI_JIT_BLOCK", "AMI_JIT_PARK_DV",
-                                     "AMI_JIT_ADJ_WAVES", "AMI_JIT_CADJ_WAVES"};
+                                     "AMI_JIT_ADJ_WAVES", "AMI_JIT_CADJ_WAVES", "AMI_JIT_CADJL_WAVES"};
     bool any_two = false;
     for (size_t j = 0; j < items.size(); ++j) {
         any_two = any_two || two_pass[j];
@@ -1353,9 +1606,9 @@ extern "C" AmiStatus amiTermsSource(const AmiTerms *t, int32_t momentum, char *b
     const bool hub = (momentum & 1) != 0, two_pass = (momentum & 2) != 0;
     std::string why;
     if (!jit_supported(t, hub, &why, two_pass)) return fail(AMI_E_UNSUPPORTED, "no specialized kernel: " + why);
-    int kernels = two_pass ? (hub ? 48 | 64 | 128 : 48 | 64 | 128 | 512 | 1024) : hub ? 7 : 11 | 256;
+    int kernels = two_pass ? (hub ? 48 | 64 | 128 : 48 | 64 | 128 | 512 | 1024 | 2048 | 4096) : hub ? 7 : 11 | 256;
     for (int o : t->tab.leaf_order)
-        if (o > 0) kernels &= ~(8 | 256 | 512 | 1024);   // Taylor-coefficient leaves: no complex energies
+        if (o > 0) kernels &= ~(8 | 256 | 512 | 1024 | 2048 | 4096);   // Taylor-coefficient leaves: no complex energies
     const std::string src = jit_source(t, hub, kernels);
     *len = static_cast<int64_t>(src.size()) + 1;
     if (!buf) return AMI_OK;

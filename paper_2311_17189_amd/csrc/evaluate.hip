@@ -637,15 +637,18 @@ struct AdjOut {
 // columns), then the chunk's 2 G + 2 NE columns of ld samples each.
 // fixed_ws: both in the allocation-free scratch (the chunk sized to what is
 // left), nothing allocated.
+// cplx: the passes at complex energies, whose workspace columns are complex
+// (4 G + 4 NE of them).
 AmiStatus launch_adjoint_passes(AmiTerms *t, DeviceTables *dt, bool hub, KArgs &a, const AdjOut &o, void *fn_sums,
-                                void *fn_freq, void *fn_leaf, hipStream_t stream, double *fixed_ws) {
+                                void *fn_freq, void *fn_leaf, hipStream_t stream, double *fixed_ws,
+                                bool cplx = false) {
     const int B = jit_block(t, hub);
     const int64_t tiles = (a.n_e + B - 1) / B;
     if (tiles > 0x7fffffffLL) return fail(AMI_E_ARG, "n_e too large");
     const int64_t rows = tiles * (B / 64);
     const int ncols = kAdjScalars + 2 * a.n_f * t->n_ext;
     const int nval = o.out_sum ? 2 * a.n_f : 0;
-    const int64_t cols = 2 * static_cast<int64_t>(t->tab.G) + 2 * t->n_eps;
+    const int64_t cols = (cplx ? 2 : 1) * (2 * static_cast<int64_t>(t->tab.G) + 2 * t->n_eps);
     const size_t n_part = static_cast<size_t>(rows) * (ncols + nval);
     int64_t ld = 0;
     double *ws = nullptr;
@@ -683,7 +686,7 @@ AmiStatus launch_adjoint_passes(AmiTerms *t, DeviceTables *dt, bool hub, KArgs &
         if (e == hipSuccess) e = launch_jit(fn_leaf, nb, B, stream, a);
     }
     if (e == hipSuccess) e = hipGetLastError();
-    g_last_variant = "specialized passes";
+    g_last_variant = cplx ? "specialized complex passes" : "specialized passes";
     if (e != hipSuccess) return hip_fail(e, "adjoint passes launch");
     hipLaunchKernelGGL(ami_adj_finalize_kernel, dim3(ncols + nval), dim3(kRedThreads), 0, stream, a.gpartial, rows,
                        ncols, 1, o.grad_beta, o.grad_mu, o.grad_t, o.grad_freqs, 2 * a.n_f, o.out_sum);
@@ -974,6 +977,38 @@ AmiStatus amiEvaluateComplexAdjoint(AmiTerms *t, const double *energies, int64_t
     DeviceTables *dt = nullptr;
     st = upload(t, &dt);
     if (st != AMI_OK) return st;
+    // above the one-pass complex adjoint's automatic size (unless the handle
+    // forces the specialized variant), or under the forced two-pass variant:
+    // the adjoint in passes at complex energies
+    if (t->variant == AMI_VARIANT_TWO_PASS ||
+        (t->variant != AMI_VARIANT_SPECIALIZED && t->tab.T > kJitAutoComplexAdjointTerms)) {
+        void *fs = nullptr, *ff = nullptr, *fl = nullptr;
+        st = jit_get(t, false, kJitComplexSums, &fs);
+        if (st == AMI_OK) st = jit_get(t, false, kJitComplexAdjFreq, &ff);
+        if (st == AMI_OK) st = jit_get(t, false, kJitComplexAdjLeaf, &fl);
+        if (st != AMI_OK) return st;
+        if (n_e == 0) {
+            st = fill(grad_beta, 1, stream);
+            if (st == AMI_OK) st = fill(out_sum, 2 * n_f, stream);
+            if (st == AMI_OK) st = fill(grad_freqs, 2 * n_f * t->n_ext, stream);
+            return st;
+        }
+        KArgs a;
+        std::memset(&a, 0, sizeof(a));
+        a.energies = energies;
+        a.stride_s = stride_s;
+        a.stride_i = stride_i;
+        set_common(a, ext_freqs, n_f, beta, e_reg, n_e);
+        a.g_out = grad_out;
+        a.g_sum = grad_sum;
+        a.grad_e = grad_energies;
+        a.out = out;
+        AdjOut o;
+        o.grad_beta = grad_beta;
+        o.grad_freqs = grad_freqs;
+        o.out_sum = out_sum;
+        return launch_adjoint_passes(t, dt, false, a, o, fs, ff, fl, stream, nullptr, true);
+    }
     void *fn = nullptr;
     st = jit_get(t, false, kJitComplexAdj, &fn);
     if (st != AMI_OK) return st;
@@ -1228,13 +1263,23 @@ AmiStatus amiTermsSpecialize(AmiTerms *t, int32_t momentum) {
         kinds.push_back(kJitAdjFreq);
         kinds.push_back(kJitAdjLeaf);
     }
-    if (!taylor && small && !hub) {
-        kinds.push_back(kJitComplex);
-        kinds.push_back(kJitComplexAdj);
-    }
-    if (!taylor && !small && !hub && t->tab.T <= kJitTwoPassMaxTerms) {
-        kinds.push_back(kJitComplexSums);
-        kinds.push_back(kJitComplexFreq);
+    // the complex-energy kernels AUTO uses: forward in one pass up to 1024
+    // terms, in two above; the adjoint in one pass up to 256 terms, in passes
+    // above
+    if (!taylor && !hub && t->tab.T <= kJitTwoPassMaxTerms) {
+        if (small) {
+            kinds.push_back(kJitComplex);
+        } else {
+            kinds.push_back(kJitComplexSums);
+            kinds.push_back(kJitComplexFreq);
+        }
+        if (t->tab.T <= kJitAutoComplexAdjointTerms) {
+            kinds.push_back(kJitComplexAdj);
+        } else {
+            if (small) kinds.push_back(kJitComplexSums);
+            kinds.push_back(kJitComplexAdjFreq);
+            kinds.push_back(kJitComplexAdjLeaf);
+        }
     }
     for (int k : kinds) {
         const AmiStatus st = jit_compile(t, hub, k);

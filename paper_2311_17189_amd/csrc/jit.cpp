@@ -150,7 +150,8 @@ AmiStatus code_object(AmiTerms *t, bool hub, int kind) {
     if (!err.empty()) return fail(AMI_E_UNSUPPORTED, err);
     std::string why;
     const bool passes = kind == kJitSumsPass || kind == kJitFreqPass || kind == kJitAdjFreq || kind == kJitAdjLeaf ||
-                        kind == kJitComplexSums || kind == kJitComplexFreq;
+                        kind == kJitComplexSums || kind == kJitComplexFreq || kind == kJitComplexAdjFreq ||
+                        kind == kJitComplexAdjLeaf;
     if (!jit_supported(t, hub, &why, passes)) {
         err = "no specialized kernel: " + why;
         return fail(AMI_E_UNSUPPORTED, err);
@@ -217,7 +218,8 @@ AmiStatus jit_get(AmiTerms *t, bool hub, int kind, void **fn) {
     hipFunction_t f = nullptr;
     static const char *const kNames[kJitKinds] = {"ami_jit_fwd",  "ami_jit_adj",   "ami_jit_mc",   "ami_jit_cfwd",
                                                   "ami_jit_sums", "ami_jit_freq",  "ami_jit_adjf", "ami_jit_adjl",
-                                                  "ami_jit_cadj", "ami_jit_csums", "ami_jit_cfreq"};
+                                                  "ami_jit_cadj", "ami_jit_csums", "ami_jit_cfreq", "ami_jit_cadjf",
+                                                  "ami_jit_cadjl"};
     e = hipModuleGetFunction(&f, mod, kNames[kind]);
     if (e != hipSuccess) {
         (void)hipModuleUnload(mod);

@@ -20,6 +20,11 @@ constexpr int kJitTwoPassMaxTerms = 4096;
 // terms: beyond it the straight-line reverse sweep outgrows the register file,
 // and the adjoint runs in passes over a workspace (up to kJitTwoPassMaxTerms).
 constexpr int kJitAutoAdjointTerms = 128;
+// The same switch for the adjoint at complex energies, whose passes hold
+// complex values per leaf and node (196 terms: one pass 0.84 ms, passes
+// 1.25 ms; 264: 1.46 ms one pass; 560: one pass 5.8 ms, passes 1.9 ms per
+// 10^6-sample step).
+constexpr int kJitAutoComplexAdjointTerms = 256;
 
 // Whether the adjoint of a solution above kJitAutoAdjointTerms can run in
 // passes (the two-pass form, no Taylor-coefficient leaves).
@@ -47,7 +52,10 @@ int jit_block(const AmiTerms *t, bool hub);
 // cotangents; kernels & 128: the leaf cotangents and the gradients), the
 // adjoint at complex energies (kernels & 256), and the two passes of the
 // forward at complex energies (kernels & 512: complex group sums and energies
-// stored per sample; kernels & 1024: per frequency, against them).
+// stored per sample; kernels & 1024: per frequency, against them), and the
+// passes of the adjoint at complex energies that follow the first of those
+// (kernels & 2048: per frequency, the complex group-sum and denominator
+// cotangents; kernels & 4096: the complex leaf cotangents and the gradients).
 std::string jit_source(const AmiTerms *t, bool hub, int kernels);
 
 // Source of one module of the persistent specialized batch: the generated
@@ -68,7 +76,9 @@ std::string jit_batch_source(const std::vector<const AmiTerms *> &items, const s
 // adjoint of large solutions (after kJitSumsPass); kJitComplexAdj is the
 // adjoint at complex energies (energy input only, as kJitComplex);
 // kJitComplexSums and kJitComplexFreq the two passes of the forward at complex
-// energies (solutions above kJitMaxTerms terms).
+// energies (solutions above kJitMaxTerms terms); kJitComplexAdjFreq and
+// kJitComplexAdjLeaf the frequency and leaf passes of the adjoint at complex
+// energies (after kJitComplexSums).
 enum JitKind {
     kJitForward = 0,
     kJitAdjoint = 1,
@@ -80,13 +90,16 @@ enum JitKind {
     kJitAdjLeaf = 7,
     kJitComplexAdj = 8,
     kJitComplexSums = 9,
-    kJitComplexFreq = 10
+    kJitComplexFreq = 10,
+    kJitComplexAdjFreq = 11,
+    kJitComplexAdjLeaf = 12
 };
-constexpr int kJitKinds = 11;
+constexpr int kJitKinds = 13;
 
 // Kinds for the energy input only (complex energies).
 inline bool jit_kind_complex(int kind) {
-    return kind == kJitComplex || kind == kJitComplexAdj || kind == kJitComplexSums || kind == kJitComplexFreq;
+    return kind == kJitComplex || kind == kJitComplexAdj || kind == kJitComplexSums || kind == kJitComplexFreq ||
+           kind == kJitComplexAdjFreq || kind == kJitComplexAdjLeaf;
 }
 
 // The specialized kernel of `kind` for the energy (hub = false) or momentum

@@ -33,7 +33,9 @@
 // integrator (4), the forward at complex energies (8), the two passes of the
 // two-pass forward (16, 32), the frequency and leaf passes of the adjoint of
 // large solutions (64, 128), the adjoint at complex energies (256), the two
-// passes of the forward at complex energies (512, 1024), or a sum of them
+// passes of the forward at complex energies (512, 1024), the frequency and
+// leaf passes of the adjoint at complex energies (2048, 4096), or a sum of
+// them
 #if AMI_JIT_KERNELS & 1
 extern "C" __global__ __launch_bounds__(AMI_JIT_BLOCK) void ami_jit_fwd(ami::KArgs a) {
     if (a.n_f == 1) amijit::fwd_tile<AMI_JIT_HUB, true>(a, blockIdx.x);
@@ -149,5 +151,23 @@ extern "C" __global__ __launch_bounds__(AMI_JIT_BLOCK) void ami_jit_freq(ami::KA
     const int64_t tile = 8 * (local / a.n_f) + (b & 7);
     if (tile * AMI_JIT_BLOCK >= a.n_chunk) return;
     amijit::freq_tile(a, tile, f);
+}
+#endif
+
+#if AMI_JIT_KERNELS & 2048
+#if AMI_JIT_ADJF_WAVES > 0
+__attribute__((amdgpu_waves_per_eu(AMI_JIT_ADJF_WAVES)))
+#endif
+extern "C" __global__ __launch_bounds__(AMI_JIT_BLOCK) void ami_jit_cadjf(ami::KArgs a) {
+    amijit::cadjf_tile(a, blockIdx.x);
+}
+#endif
+
+#if AMI_JIT_KERNELS & 4096
+#if AMI_JIT_CADJL_WAVES > 0
+__attribute__((amdgpu_waves_per_eu(AMI_JIT_CADJL_WAVES)))
+#endif
+extern "C" __global__ __launch_bounds__(AMI_JIT_BLOCK) void ami_jit_cadjl(ami::KArgs a) {
+    amijit::cadjl_tile(a, blockIdx.x);
 }
 #endif

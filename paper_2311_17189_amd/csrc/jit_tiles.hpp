@@ -895,6 +895,123 @@ __device__ __forceinline__ void cfreq_tile(const KArgs &a, int64_t tile, int f) 
 }
 #endif
 
+#if AMI_JIT_KERNELS & 2048
+// Adjoint at complex energies in passes, frequency pass (after the complex
+// two-pass forward's first pass stored FT_g and E_j): as adjf_tile, with the
+// generated cadj_freq_row; the energies' complex cotangents from the
+// denominators go to columns 2 G + 2 NE + j (real) and 2 G + 3 NE + j.
+__device__ __forceinline__ void cadjf_tile(const KArgs &a, int64_t tile) {
+    const int tid = threadIdx.x, B = blockDim.x, lane = tid & 63;
+    const int64_t i = tile * B + tid;
+    const bool active = i < a.n_chunk;
+    const int64_t s = a.s0 + i;
+    const int64_t row = (a.s0 / B + tile) * (B >> 6) + (tid >> 6);
+    const uint32_t off = static_cast<uint32_t>(i) * 8u;   // i < ld <= 2^28 (host bound)
+    double Er[NE], Ei[NE], gEr[NE], gEi[NE];
+#pragma unroll
+    for (int j = 0; j < NE; ++j) {
+        Er[j] = ami::ws_load(a.work, a.ld, 2 * G + j, off);
+        Ei[j] = ami::ws_load(a.work, a.ld, 2 * G + NE + j, off);
+        gEr[j] = gEi[j] = 0.0;
+    }
+    double *gp = a.gpartial + row;
+    for (int f = 0; f < a.n_f; ++f) {
+        double cr = 0.0, ci = 0.0;
+        if (active) {
+            if (a.g_out) {
+                cr = a.g_out[2 * (static_cast<int64_t>(f) * a.n_e + s)];
+                ci = a.g_out[2 * (static_cast<int64_t>(f) * a.n_e + s) + 1];
+            }
+            if (a.g_sum) {
+                cr += a.g_sum[2 * f];
+                ci += a.g_sum[2 * f + 1];
+            }
+        }
+        double wr[NXA], wi[NXA], gwr[NXA], gwi[NXA];
+        load_freq(a, f, wr, wi);
+#pragma unroll
+        for (int xx = 0; xx < NXA; ++xx) {
+            gwr[xx] = 0.0;
+            gwi[xx] = 0.0;
+        }
+        double acc_re = 0.0, acc_im = 0.0;
+        uint32_t off_f = off;                // opaque per row, as in adjf_tile
+        AMI_OPAQUE(off_f);
+        if (f == 0)
+            cadj_freq_row<true>(Er, Ei, wr, wi, cr, ci, a.work, a.ld, off_f, acc_re, acc_im, gEr, gEi, gwr, gwi);
+        else
+            cadj_freq_row<false>(Er, Ei, wr, wi, cr, ci, a.work, a.ld, off_f, acc_re, acc_im, gEr, gEi, gwr, gwi);
+        if (active && a.out) {
+            double2 v;
+            v.x = acc_re;
+            v.y = acc_im;
+            reinterpret_cast<double2 *>(a.out)[static_cast<int64_t>(f) * a.n_e + s] = v;
+        }
+        constexpr int NV = 2 * NX + 2, NV4 = (NV + 3) / 4 * 4;
+        double vv[NV4];
+        double *pp[NV4];
+#pragma unroll
+        for (int xx = 0; xx < NX; ++xx) {
+            vv[2 * xx] = active ? gwr[xx] : 0.0;
+            vv[2 * xx + 1] = active ? -gwi[xx] : 0.0;
+            pp[2 * xx] = gp + (ami::kAdjScalars + 2 * (f * NX + xx)) * a.nrows;
+            pp[2 * xx + 1] = pp[2 * xx] + a.nrows;
+        }
+        vv[2 * NX] = active ? acc_re : 0.0;
+        vv[2 * NX + 1] = active ? acc_im : 0.0;
+        pp[2 * NX] = a.partial ? a.partial + 2 * f * a.nrows + row : nullptr;
+        pp[2 * NX + 1] = a.partial ? pp[2 * NX] + a.nrows : nullptr;
+#pragma unroll
+        for (int c = NV; c < NV4; ++c) {
+            vv[c] = 0.0;
+            pp[c] = nullptr;
+        }
+#pragma unroll
+        for (int c = 0; c < NV4; c += 4)
+            ami::wave_store4(vv[c], vv[c + 1], vv[c + 2], vv[c + 3], lane, pp[c], pp[c + 1], pp[c + 2], pp[c + 3]);
+    }
+#pragma unroll
+    for (int j = 0; j < NE; ++j) {
+        ami::ws_store(a.work, a.ld, 2 * G + 2 * NE + j, off, gEr[j]);
+        ami::ws_store(a.work, a.ld, 2 * G + 3 * NE + j, off, gEi[j]);
+    }
+}
+#endif
+
+#if AMI_JIT_KERNELS & 4096
+// Adjoint at complex energies in passes, leaf pass: one lane per sample of
+// the chunk; the energies from the workspace, the generated cleaf_pass on the
+// stored energy cotangents of the denominators, then the complex gradient row
+// (interleaved) and the per-wave sum of dL/dbeta.
+__device__ __forceinline__ void cadjl_tile(const KArgs &a, int64_t tile) {
+    const int tid = threadIdx.x, B = blockDim.x, lane = tid & 63;
+    const int64_t i = tile * B + tid;
+    const bool active = i < a.n_chunk;
+    const int64_t s = a.s0 + i;
+    const int64_t row = (a.s0 / B + tile) * (B >> 6) + (tid >> 6);
+    const uint32_t off = static_cast<uint32_t>(i) * 8u;
+    double Er[NE], Ei[NE], gEr[NE], gEi[NE], gbeta = 0.0;
+#pragma unroll
+    for (int j = 0; j < NE; ++j) {
+        Er[j] = ami::ws_load(a.work, a.ld, 2 * G + j, off);
+        Ei[j] = ami::ws_load(a.work, a.ld, 2 * G + NE + j, off);
+        gEr[j] = ami::ws_load(a.work, a.ld, 2 * G + 2 * NE + j, off);
+        gEi[j] = ami::ws_load(a.work, a.ld, 2 * G + 3 * NE + j, off);
+    }
+    cleaf_pass(Er, Ei, a.beta, a.e_reg, a.work, a.ld, off, gEr, gEi, gbeta);
+    if (active && a.grad_e) {
+        double *grow = a.grad_e + 2 * s * NE;
+#pragma unroll
+        for (int j = 0; j < NE; ++j) {
+            grow[2 * j] = gEr[j];
+            grow[2 * j + 1] = gEi[j];
+        }
+    }
+    double *gp = a.gpartial + row;
+    ami::wave_store4(active ? gbeta : 0.0, 0.0, 0.0, 0.0, lane, gp, gp + a.nrows, gp + 2 * a.nrows, nullptr);
+}
+#endif
+
 #if AMI_JIT_KERNELS & 256
 // The complex adjoint's leaf slopes S_l (2 L doubles per lane) wait in LDS
 // through the reverse sweep where they fit in 80 KB per block (two blocks of

@@ -73,16 +73,35 @@ def test_generated_complex_two_pass_matches_oracle(name, seed, n, tmp_path):
 @pytest.mark.parametrize("name,seed", CASES)
 @pytest.mark.parametrize("e_reg", [0.0, 0.03])
 def test_generated_complex_adjoint_matches_oracle(name, seed, e_reg, tmp_path):
-    """The adjoint at complex energies: dL/dRe E + i dL/dIm E per sample,
-    dL/dbeta and dL/dw summed, within 1e-10 of their rounding scales; the
-    values formed on the way within the forward's bar."""
+    """The adjoint at complex energies in one pass: dL/dRe E + i dL/dIm E per
+    sample, dL/dbeta and dL/dw summed, within 1e-10 of their rounding scales;
+    the values formed on the way within the forward's bar."""
     d = order2_example() if seed is None else random_self_energy(seed[1], seed)
     T = amd.Terms.from_diagram(d)
     src = T.source(momentum=False)
     assert "leaf_cotangents_c" in src
-    exe = _harness(src, tmp_path, name + "a", "jit_check_cadj.cpp")
+    _check_complex_adjoint(d, _harness(src, tmp_path, name + "a", "jit_check_cadj.cpp"), e_reg, name)
+
+
+# the adjoint at complex energies in passes: o4 52 terms, o5 196, o6 560
+CADJ_PASS_CASES = [("o2", None, 0.0), ("o4", (0, 4, 1), 0.03), ("o5", (0, 5, 2), 0.0), ("o6", (0, 6, 0), 0.03)]
+
+
+@pytest.mark.parametrize("name,seed,e_reg", CADJ_PASS_CASES)
+def test_generated_complex_adjoint_passes_match_oracle(name, seed, e_reg, tmp_path):
+    """The same through the three passes (complex group sums stored, the
+    frequency pass, the leaf pass's complex reverse sweep)."""
+    d = order2_example() if seed is None else random_self_energy(seed[1], seed)
+    T = amd.Terms.from_diagram(d)
+    src = T.source(momentum=False, two_pass=True)
+    assert "cadj_freq_row" in src and "void cleaf_pass(" in src
+    n = 120 if seed is None or seed[1] < 6 else 30
+    _check_complex_adjoint(d, _harness(src, tmp_path, name + "ap", "jit_check_cadj_passes.cpp"), e_reg, name, n)
+
+
+def _check_complex_adjoint(d, exe, e_reg, name, n=120):
     beta = 4.0
-    E = complex_energies(120, d.n_eps, seed=(91, d.n_int), a=3.0, eta=0.05)
+    E = complex_energies(n, d.n_eps, seed=(91, d.n_int), a=3.0, eta=0.05)
     w = np.concatenate([matsubara_freqs(2, beta), real_freqs(1, 0.4, 0.4, 0.05)])
     terms = oracle_terms(d)
     E = np.ascontiguousarray(E[far_from_poles(terms, d.n_int, E, w)])

@@ -111,10 +111,14 @@ def test_complex_refusals():
     (2, None, 5.0, 1000, 0.0), (3, 0, 2.0, 1500, 0.0), (4, 1, 5.0, 777, 0.0), (4, 6, 2.0, 600, 0.3),
     (5, 2, 5.0, 300, 0.0), (6, 0, 5.0, 90, 0.0),
 ])
-def test_complex_adjoint_vs_oracle(order, i, beta, n_e, e_reg):
+@pytest.mark.parametrize("variant", [amd.VARIANT_AUTO, amd.VARIANT_SPECIALIZED, amd.VARIANT_TWO_PASS],
+                         ids=["auto", "one_pass", "passes"])
+def test_complex_adjoint_vs_oracle(order, i, beta, n_e, e_reg, variant):
     """dL/dRe E + i dL/dIm E per sample, dL/dbeta and dL/dw within 1e-10 of
     their rounding scales on samples away from poles; the values formed on the
-    way equal amiEvaluateComplex's, and their row sums."""
+    way equal amiEvaluateComplex's, and their row sums.  AUTO runs the one-pass
+    kernel up to 256 terms and the passes above; the two forced variants run
+    one each."""
     d = _diag(order, i)
     eta = 0.25 / (beta * d.n_int)
     E = complex_energies(n_e, d.n_eps, seed=(94, order, i or 0), a=3.0, eta=eta)
@@ -126,12 +130,16 @@ def test_complex_adjoint_vs_oracle(order, i, beta, n_e, e_reg):
     cot = rng.standard_normal((len(w), n)) + 1j * rng.standard_normal((len(w), n))
     cot_sum = np.array([0.2 + 0.1j, -0.3j, 0.15])
     T = amd.Terms.from_diagram(d)
+    T.set_variant(variant)
     Et, wt = torch.from_numpy(E).to(DEV), torch.from_numpy(w).to(DEV)
     out = torch.empty((len(w), n), dtype=torch.complex128, device=DEV)
     out_sum = torch.empty((len(w),), dtype=torch.complex128, device=DEV)
     g_e, g_b, g_w = amd.evaluate_complex_adjoint(T, Et, wt, beta, e_reg, grad_out=torch.from_numpy(cot).to(DEV),
                                                  grad_sum=torch.from_numpy(cot_sum).to(DEV), out=out,
                                                  out_sum=out_sum)
+    passes = variant == amd.VARIANT_TWO_PASS or (variant == amd.VARIANT_AUTO and T.info()["T"] > 256)
+    assert amd.last_variant() == ("specialized complex passes" if passes else "specialized complex")
+    T.set_variant(amd.VARIANT_AUTO)
     fwd, _ = amd.evaluate_complex(T, Et, wt, beta, e_reg)
     torch.cuda.synchronize()
     assert amd.last_variant() == "specialized complex"
@@ -213,3 +221,53 @@ def test_complex_two_pass(order, seed, n_e):
         torch.cuda.synchronize()
         assert amd.last_variant() == "specialized complex"
         assert np.max(np.abs(one.cpu().numpy() - got) / scale) <= 1e-13
+
+
+@pytest.mark.parametrize("order,seed,n_e", [(5, (0, 5, 0), 1100), (6, (5, 6, 2), 300)])
+def test_complex_adjoint_passes_chunks_and_large(order, seed, n_e):
+    """The adjoint at complex energies in passes: at order 6 with 2804 terms
+    (beyond the one-pass kernel), the samples in one chunk and in several (a
+    ragged last one) and two frequency rows, bitwise alike, against the
+    oracle's gradients (on a sampled subset at 2804 terms)."""
+    d = random_self_energy(order, seed)
+    T = amd.Terms.from_diagram(d)
+    beta, e_reg = 5.0, 0.02
+    eta = 0.25 / (beta * d.n_int)
+    E = complex_energies(n_e, d.n_eps, seed=(99, order), a=3.0, eta=eta)
+    w = np.concatenate([matsubara_freqs(1, beta), real_freqs(1, -1.5, -1.5, 0.05)])
+    terms = oracle_terms(d)
+    E = np.ascontiguousarray(E[far_from_poles(terms, d.n_int, E, w)])
+    n = len(E)
+    rng = np.random.default_rng(100)
+    cot = rng.standard_normal((len(w), n)) + 1j * rng.standard_normal((len(w), n))
+    Et, wt, ct = torch.from_numpy(E).to(DEV), torch.from_numpy(w).to(DEV), torch.from_numpy(cot).to(DEV)
+
+    def run():
+        out = torch.empty((len(w), n), dtype=torch.complex128, device=DEV)
+        g = amd.evaluate_complex_adjoint(T, Et, wt, beta, e_reg, grad_out=ct, out=out)
+        torch.cuda.synchronize()
+        assert amd.last_variant() == "specialized complex passes"
+        return [x.cpu().numpy() for x in g] + [out.cpu().numpy()]
+
+    one = run()
+    cols = 4 * (T.info()["G"] + d.n_eps)
+    try:
+        amd.set_two_pass_chunk_bytes(max(1 << 16, 256 * 8 * cols * 2))     # chunks of 512 samples
+        many = run()
+    finally:
+        amd.set_two_pass_chunk_bytes(1 << 30)
+    for a, b in zip(one, many):
+        assert np.array_equal(a, b)
+    g_e, g_b, g_w, out = one
+    pick = np.arange(n) if n <= 400 else np.random.default_rng(101).choice(n, 400, replace=False)
+    sub = np.sort(pick[:40]) if order == 6 else np.sort(pick)
+    ref_e, _, _ = gradients(terms, d.n_int, E[sub], w, beta, cot[:, sub], e_reg)
+    sc = gradient_scales(terms, d.n_int, E[sub], w, beta, cot[:, sub], e_reg)
+    assert np.max(np.abs(g_e[sub] - ref_e.astype(np.complex128)) / np.maximum(sc["E"], 1e-300)) <= 1e-10
+    if order < 6:                       # the reductions over every sample
+        _, ref_b, ref_w = gradients(terms, d.n_int, E, w, beta, cot, e_reg)
+        scf = gradient_scales(terms, d.n_int, E, w, beta, cot, e_reg)
+        assert abs(float(g_b) - float(ref_b)) <= 1e-10 * scf["beta"]
+        assert np.max(np.abs(g_w - ref_w.astype(np.complex128))) <= 1e-10 * scf["w"]
+    ref, scale, dist = reference(d, E[sub], w, beta, e_reg, terms=terms)
+    check(out[:, sub], ref, scale, dist, label=f"complex adjoint passes values order {order}")
