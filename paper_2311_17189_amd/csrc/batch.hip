@@ -343,7 +343,9 @@ AmiStatus create_spec_persistent(const AmiBatchItem *items, int n_items, const A
     for (int i = 0; i < n_items; ++i) cost[i] = sample_cost(items[i].terms, items[i].n_f) * items[i].n_e;
     // kernel groups: per pass, the items by the occupancy of their own kernel
     // of that pass (most waves first, then by cost), cut at kSpecGroupTerms
-    // terms; a group's kernel runs at the occupancy its own code allows
+    // terms; a group's kernel runs at the occupancy its own code allows.  In
+    // the first pass the two-pass items' groups come first and hold no
+    // one-pass item, so that their frequency passes wait for them alone.
     struct KGroup {
         int pass;
         std::vector<int> items;
@@ -354,13 +356,16 @@ AmiStatus create_spec_persistent(const AmiBatchItem *items, int n_items, const A
         std::vector<int> order;
         for (int i = 0; i < n_items; ++i)
             if (pass == 1 || two[i]) order.push_back(i);
-        std::stable_sort(order.begin(), order.end(),
-                         [&](int x, int y) { return wv[x] != wv[y] ? wv[x] > wv[y] : cost[x] > cost[y]; });
+        std::stable_sort(order.begin(), order.end(), [&](int x, int y) {
+            if (pass == 1 && two[x] != two[y]) return two[x] > two[y];
+            return wv[x] != wv[y] ? wv[x] > wv[y] : cost[x] > cost[y];
+        });
         int64_t terms_in = 0;
         bool fresh = true;
         for (int i : order) {
             const int64_t T = items[i].terms->tab.T;
-            if (fresh || wv[groups.back().items[0]] != wv[i] || terms_in + T > kSpecGroupTerms) {
+            const int head = fresh ? -1 : groups.back().items[0];
+            if (fresh || wv[head] != wv[i] || two[head] != two[i] || terms_in + T > kSpecGroupTerms) {
                 groups.push_back(KGroup{pass, {}});
                 terms_in = 0;
                 fresh = false;
@@ -424,8 +429,13 @@ AmiStatus create_spec_persistent(const AmiBatchItem *items, int n_items, const A
     // one after another
     std::vector<double> tile_cost(n_items);
     for (int i = 0; i < n_items; ++i) tile_cost[i] = sample_cost(items[i].terms, items[i].n_f) * B;
+    // Each group's work goes into eight lists, one per XCD: a unit (an
+    // item's tile range with all its frequency rows in the second pass) goes
+    // to the list with the least cost so far, so the rows of a tile read its
+    // stored group sums through one XCD's L2.
     std::vector<SpecWork> wl;
     std::vector<int64_t> w0(G, 0), nw(G, 0);
+    std::vector<int> xoffs(G * 9, 0);
     for (size_t g = 0; g < G; ++g) {
         const int pass = groups[g].pass;
         // pass 1 of a two-pass item: leaves and group sums only (about a
@@ -439,21 +449,32 @@ AmiStatus create_spec_persistent(const AmiBatchItem *items, int n_items, const A
         std::vector<int> by_cost = groups[g].items;
         std::stable_sort(by_cost.begin(), by_cost.end(), [&](int x, int y) { return cost[x] > cost[y]; });
         w0[g] = static_cast<int64_t>(wl.size());
+        std::vector<SpecWork> lists[8];
+        double load[8] = {0.0};
         for (int i : by_cost) {
             const int64_t per = std::max<int64_t>(1, static_cast<int64_t>(target / unit(i)));
             const int rows_per = pass == 2 ? static_cast<int>(items[i].n_f) : 1;
-            for (int64_t t0 = 0; t0 < tiles[i]; t0 += per)
+            for (int64_t t0 = 0; t0 < tiles[i]; t0 += per) {
+                const int64_t nt = std::min<int64_t>(per, tiles[i] - t0);
+                const int x = static_cast<int>(std::min_element(load, load + 8) - load);
+                load[x] += unit(i) * static_cast<double>(nt) * rows_per;
                 for (int f = 0; f < rows_per; ++f) {
                     SpecWork w;
                     std::memset(&w, 0, sizeof(w));
                     w.item = i;
                     w.tile0 = t0;
-                    w.ntiles = static_cast<int32_t>(std::min<int64_t>(per, tiles[i] - t0));
+                    w.ntiles = static_cast<int32_t>(nt);
                     w.f = pass == 2 ? f : -1;
-                    wl.push_back(w);
+                    lists[x].push_back(w);
                 }
+            }
+        }
+        for (int x = 0; x < 8; ++x) {
+            xoffs[g * 9 + x] = static_cast<int>(static_cast<int64_t>(wl.size()) - w0[g]);
+            wl.insert(wl.end(), lists[x].begin(), lists[x].end());
         }
         nw[g] = static_cast<int64_t>(wl.size()) - w0[g];
+        xoffs[g * 9 + 8] = static_cast<int>(nw[g]);
     }
     if (wl.size() > 0x7fffffffu - 65536u) return batch_fail_free(b, fail(AMI_E_ARG, "too many work items"));
 
@@ -477,9 +498,10 @@ AmiStatus create_spec_persistent(const AmiBatchItem *items, int n_items, const A
     auto al = [](size_t x) { return (x + 255) & ~size_t(255); };
     const size_t sz_args = sizeof(KArgs) * n_items;
     const size_t off_work = al(sz_args);
-    const size_t off_jobs = al(off_work + sizeof(SpecWork) * std::max<size_t>(wl.size(), 1));
+    const size_t off_xoff = al(off_work + sizeof(SpecWork) * std::max<size_t>(wl.size(), 1));
+    const size_t off_jobs = al(off_xoff + sizeof(int) * xoffs.size());
     const size_t off_ctr = al(off_jobs + sizeof(ColJob) * std::max<int64_t>(n_jobs, 1));
-    const size_t off_part = al(off_ctr + sizeof(unsigned int) * kCounterStride * G);
+    const size_t off_part = al(off_ctr + sizeof(unsigned int) * kCounterStride * 8 * G);
     const size_t off_ws = al(off_part + sizeof(double) * std::max<int64_t>(part_total, 1));
     const size_t total = off_ws + sizeof(double) * std::max<int64_t>(ws_total, 1);
     e = hipMalloc(&b->blob, total);
@@ -513,6 +535,7 @@ AmiStatus create_spec_persistent(const AmiBatchItem *items, int n_items, const A
     std::vector<unsigned char> host(off_part, 0);
     std::memcpy(host.data(), args.data(), sz_args);
     if (!wl.empty()) std::memcpy(host.data() + off_work, wl.data(), sizeof(SpecWork) * wl.size());
+    std::memcpy(host.data() + off_xoff, xoffs.data(), sizeof(int) * xoffs.size());
     if (!jobs.empty()) std::memcpy(host.data() + off_jobs, jobs.data(), sizeof(ColJob) * jobs.size());
     e = hipMemcpy(b->blob, host.data(), off_part, hipMemcpyHostToDevice);
     if (e != hipSuccess) return batch_fail_free(b, hip_fail(e, "persistent batch upload"));
@@ -526,21 +549,22 @@ AmiStatus create_spec_persistent(const AmiBatchItem *items, int n_items, const A
     unsigned int *d_ctr = reinterpret_cast<unsigned int *>(base + off_ctr);
     hipGraphNode_t n_reset = nullptr;
     {
-        if (G > 1024) return batch_fail_free(b, fail(AMI_E_ARG, "too many groups"));
-        int n_ctr = static_cast<int>(G);
+        if (8 * G > 1024) return batch_fail_free(b, fail(AMI_E_ARG, "too many groups"));
+        int n_ctr = static_cast<int>(8 * G);     // eight per group, one per work list
         void *kp[] = {&d_ctr, &n_ctr};
         hipKernelNodeParams p;
         std::memset(&p, 0, sizeof(p));
         p.func = reinterpret_cast<void *>(&ami_batch_reset_kernel);
         p.gridDim = dim3(1);
-        p.blockDim = dim3(static_cast<unsigned>(std::max<size_t>(64, (G + 63) / 64 * 64)));
+        p.blockDim = dim3(static_cast<unsigned>(std::max<size_t>(64, (8 * G + 63) / 64 * 64)));
         p.kernelParams = kp;
         e = hipGraphAddKernelNode(&n_reset, b->graph, nullptr, 0, &p);
         if (e != hipSuccess) return batch_fail_free(b, hip_fail(e, "graph reset node"));
     }
-    // every first-pass kernel after the reset, side by side; every frequency-
-    // pass kernel after all of them; the row sums after everything
-    std::vector<hipGraphNode_t> first, all;
+    // every first-pass kernel after the reset, side by side; each frequency-
+    // pass kernel after the first-pass kernels that hold its items' first
+    // passes; the row sums after everything
+    std::vector<hipGraphNode_t> first_of(static_cast<size_t>(n_items), nullptr), all;
     for (int pass = 1; pass <= 2; ++pass)
         for (size_t g = 0; g < G; ++g) {
             if (groups[g].pass != pass || nw[g] == 0) continue;
@@ -553,9 +577,9 @@ AmiStatus create_spec_persistent(const AmiBatchItem *items, int n_items, const A
             const int per_cu = std::max(1, std::min(gw, tun.waves_per_cu / (B / 64)));
             const KArgs *d_args = reinterpret_cast<const KArgs *>(base);
             const SpecWork *d_work = reinterpret_cast<const SpecWork *>(base + off_work) + w0[g];
-            int n_work = static_cast<int>(nw[g]);
-            unsigned int *ctr = d_ctr + g * kCounterStride;
-            void *kp[] = {&d_args, &d_work, &n_work, &ctr};
+            const int *d_xoff = reinterpret_cast<const int *>(base + off_xoff) + g * 9;
+            unsigned int *ctr = d_ctr + g * 8 * kCounterStride;
+            void *kp[] = {&d_args, &d_work, &d_xoff, &ctr};
             hipKernelNodeParams p;
             std::memset(&p, 0, sizeof(p));
             p.func = reinterpret_cast<void *>(kfn[g]);
@@ -563,10 +587,19 @@ AmiStatus create_spec_persistent(const AmiBatchItem *items, int n_items, const A
             p.blockDim = dim3(B);
             p.kernelParams = kp;
             hipGraphNode_t node = nullptr;
-            const std::vector<hipGraphNode_t> &deps = pass == 1 ? std::vector<hipGraphNode_t>{n_reset} : first;
+            std::vector<hipGraphNode_t> deps;
+            if (pass == 1) {
+                deps.push_back(n_reset);
+            } else {
+                for (int i : groups[g].items)
+                    if (first_of[i] && std::find(deps.begin(), deps.end(), first_of[i]) == deps.end())
+                        deps.push_back(first_of[i]);
+                if (deps.empty()) deps.push_back(n_reset);
+            }
             e = hipGraphAddKernelNode(&node, b->graph, deps.data(), deps.size(), &p);
             if (e != hipSuccess) return batch_fail_free(b, hip_fail(e, "graph persistent node"));
-            if (pass == 1) first.push_back(node);
+            if (pass == 1)
+                for (int i : groups[g].items) first_of[i] = node;
             all.push_back(node);
             b->grid += static_cast<int>(p.gridDim.x);
         }

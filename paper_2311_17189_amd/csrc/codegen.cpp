@@ -1530,17 +1530,25 @@ std::string jit_batch_source(const std::vector<const AmiTerms *> &items, const s
          "}  // namespace amibatch\n";
     for (int phase = 1; phase <= 2; ++phase) {
         if (!(phases & phase) || (phase == 2 && !any_two)) continue;
+        // eight work lists, one per XCD (xoff[x] .. xoff[x + 1] of work, with
+        // their counters 16 apart): a block drains the list of its own XCD
+        // first (block b runs on XCD b mod 8), then the others in turn, so
+        // every block has tried every list before it exits
         o << "extern \"C\" __global__ __launch_bounds__(" << block << ") void ami_batch_p" << phase
-          << "(const ami::KArgs *args, const amibatch::Work *work, int n_work, unsigned int *counter) {\n"
+          << "(const ami::KArgs *args, const amibatch::Work *work, const int *xoff, unsigned int *counter) {\n"
              "  __shared__ int next;\n"
              "  const amibatch::cwork cw = (amibatch::cwork)(work);\n"
              "  const amibatch::cargs ca = (amibatch::cargs)(args);\n"
-             "  for (;;) {\n"
-             "    if (threadIdx.x == 0) next = static_cast<int>(atomicAdd(counter, 1u));\n"
+             "  const int x0 = static_cast<int>(blockIdx.x & 7u);\n"
+             "  for (int k = 0; k < 8; ++k) {\n"
+             "   const int x = (x0 + k) & 7, begin = xoff[x], n_work = xoff[x + 1] - begin;\n"
+             "   for (;;) {\n"
+             "    if (threadIdx.x == 0) next = static_cast<int>(atomicAdd(counter + 16 * x, 1u));\n"
              "    __syncthreads();\n"
-             "    const int wi = __builtin_amdgcn_readfirstlane(next);\n"
+             "    const int wj = __builtin_amdgcn_readfirstlane(next);\n"
              "    __syncthreads();\n"
-             "    if (wi >= n_work) break;\n"
+             "    if (wj >= n_work) break;\n"
+             "    const int wi = begin + wj;\n"
              "    const int item = cw[wi].item, ntiles = cw[wi].ntiles, f = cw[wi].f;\n"
              "    const int64_t tile0 = cw[wi].tile0;\n"
              "    const __attribute__((address_space(4))) ami::KArgs &a = ca[item];\n"
@@ -1560,7 +1568,7 @@ std::string jit_batch_source(const std::vector<const AmiTerms *> &items, const s
                   << "::freq_tile(a, t, f);\n      break;\n";
             }
         }
-        o << "    default: break;\n    }\n  }\n}\n";
+        o << "    default: break;\n    }\n   }\n  }\n}\n";
     }
     return o.str();
 }
