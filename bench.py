@@ -599,6 +599,22 @@ def next_rows_section(args, torch, dev, stream):
                         f"{n_fl} Matsubara frequencies, out + row sums",
             "kernel": amd.last_variant(), "ms": ms_c,
             "term_evals_per_s": float(st.T) * n_l * n_fl / (ms_c * 1e-3)}
+        # the adjoint at complex energies in passes: order 6, 560 terms, one frequency
+        dm = random_self_energy(6, (0, 6, 0))
+        Tm = amd.Terms.from_diagram(dm)
+        Tm.specialize(momentum=False)
+        stm = rl.structure_from_canonical(Tm.canonical())
+        em = 0.25 / (args.beta * dm.n_int)
+        Em = torch.from_numpy(complex_energies(n_l, dm.n_eps, seed=(105, 6, 0), a=3.0, eta=em)).to(dev)
+        om = torch.empty((1, n_l), dtype=torch.complex128, device=dev)
+        sm = torch.empty((1,), dtype=torch.complex128, device=dev)
+        gs = torch.ones((1,), dtype=torch.complex128, device=dev)
+        ms_a, _ = _timed_kernel(torch, amd, stream, lambda: amd.evaluate_complex_adjoint(
+            Tm, Em, w, args.beta, grad_sum=gs, out=om, out_sum=sm, stream=stream), 5)
+        res["large_complex_adjoint"] = {
+            "workload": f"order-6 topology (0, 6, 0), {stm.T} terms, {n_l} complex energy rows (|Im| < {em:.3g}), "
+                        "1 Matsubara frequency; value-and-gradient step",
+            "kernel": amd.last_variant(), "ms": ms_a, "term_evals_per_s": float(stm.T) * n_l / (ms_a * 1e-3)}
     except amd.AmiError as e:
         res["large_two_pass"] = f"not run: {e}"
     # graph input: label and construct, host only
