@@ -12,8 +12,8 @@ from __future__ import annotations
 
 import torch
 
-from ._lib import (Terms, evaluate, evaluate_adjoint, evaluate_hubbard,
-                   evaluate_hubbard_adjoint)
+from ._lib import (Terms, evaluate, evaluate_adjoint, evaluate_complex, evaluate_complex_adjoint,
+                   evaluate_hubbard, evaluate_hubbard_adjoint)
 
 
 def _value(x) -> float:
@@ -57,6 +57,36 @@ class AmiEvaluate(torch.autograd.Function):
         energies, ext_freqs = ctx.saved_tensors
         g_e, g_b, g_w = evaluate_adjoint(ctx.terms, energies.detach(), ext_freqs.detach(),
                                          ctx.beta, ctx.e_reg, grad_out=grad_out, grad_sum=grad_sum)
+        return (None, g_e if ctx.needs_input_grad[1] else None,
+                g_w.reshape(ext_freqs.shape) if ctx.needs_input_grad[2] else None,
+                _grad_for(ctx, 3, ctx.beta_meta, g_b), None)
+
+
+class AmiEvaluateComplex(torch.autograd.Function):
+    """``(out [N_F, N_E], out_sum [N_F]) = AmiEvaluateComplex.apply(terms,
+    energies, ext_freqs, beta, e_reg)`` at complex energies (complex128
+    [N_E, nE], Sec. 5.1.3), with gradients for the energies and the external
+    frequencies in torch's convention for complex inputs (dL/dRe + i dL/dIm,
+    which is what amiEvaluateComplexAdjoint returns) and for beta, at fixed
+    e_reg."""
+
+    @staticmethod
+    def forward(ctx, terms: Terms, energies, ext_freqs, beta, e_reg: float = 0.0):
+        b = _value(beta)
+        out, out_sum = evaluate_complex(terms, energies.detach(), ext_freqs.detach(), b, e_reg,
+                                        want_out=True, want_sum=True)
+        ctx.terms = terms
+        ctx.e_reg = e_reg
+        ctx.beta = b
+        ctx.beta_meta = _meta(beta)
+        ctx.save_for_backward(energies, ext_freqs)
+        return out, out_sum
+
+    @staticmethod
+    def backward(ctx, grad_out, grad_sum):
+        energies, ext_freqs = ctx.saved_tensors
+        g_e, g_b, g_w = evaluate_complex_adjoint(ctx.terms, energies.detach(), ext_freqs.detach(), ctx.beta,
+                                                 ctx.e_reg, grad_out=grad_out, grad_sum=grad_sum)
         return (None, g_e if ctx.needs_input_grad[1] else None,
                 g_w.reshape(ext_freqs.shape) if ctx.needs_input_grad[2] else None,
                 _grad_for(ctx, 3, ctx.beta_meta, g_b), None)

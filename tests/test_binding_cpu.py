@@ -92,3 +92,27 @@ def test_hubbard_tensor_scalars_get_gradients_on_their_devices(monkeypatch):
     s.real.sum().backward()
     assert float(t.grad) == 2.0 and float(beta.grad) == 3.0 and mu.grad is None
     assert t.grad.shape == t.shape and w.grad.shape == w.shape
+
+
+def test_complex_energy_function_passes_gradients_through(monkeypatch):
+    """AmiEvaluateComplex hands torch the adjoint's complex energy gradient as
+    it is (torch's convention for complex inputs), a number beta gets none."""
+    calls = []
+
+    def fwd(terms, E, w, beta, e_reg, want_out=True, want_sum=True):
+        calls.append(("fwd", beta))
+        return torch.zeros((w.shape[0], E.shape[0]), dtype=torch.complex128), torch.zeros(w.shape[0],
+                                                                                          dtype=torch.complex128)
+
+    def adj(terms, E, w, beta, e_reg, grad_out=None, grad_sum=None):
+        calls.append(("adj", beta))
+        return torch.full_like(E, 2.0 - 1.0j), torch.tensor(3.0, dtype=torch.float64), torch.zeros_like(w)
+
+    monkeypatch.setattr(ag, "evaluate_complex", fwd)
+    monkeypatch.setattr(ag, "evaluate_complex_adjoint", adj)
+    E = torch.zeros((3, 2), dtype=torch.complex128, requires_grad=True)
+    w = torch.zeros((2, 1), dtype=torch.complex128)
+    out, s = ag.AmiEvaluateComplex.apply(None, E, w, 5.0)
+    (out.real.sum() + s.real.sum()).backward()
+    assert torch.equal(E.grad, torch.full_like(E, 2.0 - 1.0j))
+    assert calls == [("fwd", 5.0), ("adj", 5.0)]

@@ -271,3 +271,17 @@ def test_complex_adjoint_passes_chunks_and_large(order, seed, n_e):
         assert np.max(np.abs(g_w - ref_w.astype(np.complex128))) <= 1e-10 * scf["w"]
     ref, scale, dist = reference(d, E[sub], w, beta, e_reg, terms=terms)
     check(out[:, sub], ref, scale, dist, label=f"complex adjoint passes values order {order}")
+
+
+def test_complex_autograd_gradcheck():
+    """AmiEvaluateComplex through torch's gradient check at complex energies
+    (torch takes complex inputs' gradients as dL/dRe + i dL/dIm), beta as a
+    host tensor, a Matsubara and a real frequency."""
+    from paper_2311_17189_amd.autograd import AmiEvaluateComplex
+    d = random_self_energy(3, (0, 3, 1))
+    T = amd.Terms.from_diagram(d)
+    E = torch.from_numpy(complex_energies(6, d.n_eps, seed=102, a=2.0, eta=0.05)).to(DEV).requires_grad_(True)
+    w = torch.tensor([[1j * np.pi / 2.0], [0.3 + 0.1j]], dtype=torch.complex128, device=DEV, requires_grad=True)
+    beta = torch.tensor(2.0, dtype=torch.float64, requires_grad=True)
+    assert torch.autograd.gradcheck(lambda e, ww, b: AmiEvaluateComplex.apply(T, e, ww, b), (E, w, beta),
+                                    eps=1e-6, atol=1e-6, rtol=1e-5)
