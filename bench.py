@@ -333,7 +333,8 @@ def configs_section(args, torch, dev, stream):
     beta = 2, 5, 10 and 10^6 k-samples (forward, and the value-and-gradient
     step); C3, an order-4 topology on the 256-point real-frequency grid
     omega + 0.05i, omega in [-6, 6], at 10^6 k-samples (out is 4.1 GB: HBM
-    rate and FP64 fraction)."""
+    rate and FP64 fraction); C4, the C3 topology's adjoint with a per-sample
+    cotangent (grad_out) at 10^6 k-samples."""
     import numpy as np
 
     import paper_2311_17189_amd as amd
@@ -424,6 +425,28 @@ def configs_section(args, torch, dev, stream):
         del out
     except amd.AmiError as e:
         res["C3_real_frequency_grid"] = f"not run: {e}"
+    # C4: the C3 topology's adjoint with a per-sample cotangent grad_out (16 MB read)
+    try:
+        d = random_self_energy(4, (0, 4, 1))
+        n_e, beta = 1_000_000, 5.0
+        T, st, k, w, out, osum, _ = prepare(d, n_e, (114, 4, 1), matsubara_freqs(1, beta))
+        rng = np.random.default_rng(115)
+        go = torch.from_numpy(rng.standard_normal((1, n_e)) + 1j * rng.standard_normal((1, n_e))).to(dev)
+        g = [None]
+
+        def c4():
+            g[0] = amd.evaluate_hubbard_adjoint(T, k, q, 1.0, 0.0, w, beta, grad_out=go, stream=stream, grads=g[0])
+        a_med, a_min = _median_ms(torch, stream, c4)
+        afl = rl.specialized_adjoint_flops(st, n_e, 1, d.alpha)["total"]
+        nbytes = n_e * 2 * d.n_int * 8 + n_e * 16 + n_e * 2 * d.n_int * 8
+        res["C4_adjoint_grad_out"] = {
+            "workload": "order-4 topology (0, 4, 1), 10^6 k-samples, beta=5, i pi/beta; adjoint with a per-sample "
+                        "cotangent grad_out [1, 10^6] complex128 -> grad_k [10^6, 8], grad_mu, grad_t, grad_beta, grad_w",
+            "kernel": amd.last_variant(), "ms_median": a_med, "ms_min": a_min,
+            "term_evals_per_s": float(st.T) * n_e / (a_med * 1e-3), "algorithmic_bytes": nbytes,
+            "flops": afl, "frac_fp64_peak": afl / (a_med * 1e-3) / rl.PEAK_FP64_VECTOR}
+    except amd.AmiError as e:
+        res["C4_adjoint_grad_out"] = f"not run: {e}"
     return res
 
 
