@@ -285,3 +285,31 @@ def test_complex_autograd_gradcheck():
     beta = torch.tensor(2.0, dtype=torch.float64, requires_grad=True)
     assert torch.autograd.gradcheck(lambda e, ww, b: AmiEvaluateComplex.apply(T, e, ww, b), (E, w, beta),
                                     eps=1e-6, atol=1e-6, rtol=1e-5)
+
+
+@pytest.mark.parametrize("variant", [amd.VARIANT_AUTO, amd.VARIANT_TWO_PASS], ids=["one_pass", "passes"])
+def test_complex_adjoint_strided_inputs(variant):
+    """Energies read from a strided view and from a transposed one give the
+    same bits as a contiguous copy, in one pass and in passes."""
+    d = random_self_energy(3, (0, 3, 0))
+    T = amd.Terms.from_diagram(d)
+    T.set_variant(variant)
+    beta = 3.0
+    big = complex_energies(777, d.n_eps + 3, seed=103, a=3.0, eta=0.03)
+    w = torch.from_numpy(np.concatenate([matsubara_freqs(1, beta), real_freqs(1, 0.5, 0.5, 0.05)])).to(DEV)
+    Eb = torch.from_numpy(big).to(DEV)
+    views = [Eb[:, 1:1 + d.n_eps], Eb[:, 1:1 + d.n_eps].contiguous(),
+             Eb[:, 1:1 + d.n_eps].contiguous().t().contiguous().t()]
+    assert views[0].stride() == (d.n_eps + 3, 1) and views[2].stride() == (1, 777)
+    cot = torch.from_numpy(np.random.default_rng(104).standard_normal((2, 777)) + 0.3j).to(DEV)
+    res = []
+    for E in views:
+        out = torch.empty((2, 777), dtype=torch.complex128, device=DEV)
+        g = amd.evaluate_complex_adjoint(T, E, w, beta, grad_out=cot, out=out)
+        torch.cuda.synchronize()
+        res.append([x.cpu() for x in g] + [out.cpu()])
+    assert amd.last_variant() == ("specialized complex passes" if variant == amd.VARIANT_TWO_PASS
+                                  else "specialized complex")
+    for r in res[1:]:
+        for a, b in zip(res[0], r):
+            assert torch.equal(a, b)
