@@ -412,6 +412,19 @@ int cadjl_waves() {
     return v >= 0 && v <= 8 ? v : 1;
 }
 
+}  // namespace
+
+// Terms per part of the one-pass adjoint's nested leaf-cotangent sweep when
+// AMIGPU_JIT_NESTED_COTANGENTS names it (0: per-term products), else -1.
+int jit_nested_override() {
+    const char *e = std::getenv("AMIGPU_JIT_NESTED_COTANGENTS");
+    if (!e) return -1;
+    const int v = std::atoi(e);
+    return v >= 0 && v <= 64 ? v : 0;
+}
+
+namespace {
+
 int adj_waves() {
     const char *e = std::getenv("AMIGPU_JIT_ADJ_WAVES");
     if (!e) return 2;
@@ -425,7 +438,8 @@ int adj_waves() {
 // blocks per CU), else 128
 int jit_block(const AmiTerms *t, bool hub) { return park_cols(t, hub) * 256 * 8 <= 80 * 1024 ? 256 : 128; }
 
-std::string jit_source(const AmiTerms *t, bool hub, int kernels) {
+std::string jit_source(const AmiTerms *t, bool hub, int kernels, int nested_part) {
+    if (nested_part < 0) nested_part = std::max(0, jit_nested_override());
     const Tables &tb = t->tab;
     const int ne = t->n_eps, ni = t->n_int, ng = t->n_g, nx = t->n_ext, nf = t->n_freq;
     // a solution whose terms hold no denominators gets one phantom
@@ -1371,10 +1385,48 @@ std::string jit_source(const AmiTerms *t, bool hub, int kernels) {
     }
     o << "}\n";
 
-    // leaf cotangents by prefix/suffix products over each term's leaves
+    // leaf cotangents: by a reverse sweep of each group's nested sum (parts of
+    // at most kAdjLeafPartTerms terms, as the leaf pass of the adjoint in
+    // passes), or by prefix/suffix products over each term's leaves
     o << "__device__ __forceinline__ void leaf_cotangents(const double (&F)[L], const double (&FTB)[G], double "
          "(&FB)[L]) {\n";
     o << kReverseContract;
+    if (nested_part > 0) {
+        std::vector<Part> parts;
+        std::vector<int> first_use, last_use;
+        build_parts(parts, first_use, last_use, nested_part);
+        auto fname = [](int l) { return "F[" + std::to_string(l) + "]"; };
+        for (size_t p = 0; p < parts.size(); ++p) {
+            const Part &pt = parts[p];
+            if (p > 0) o << "  AMI_SCHED_FENCE();\n";
+            o << "  {\n";
+            horner_emit(pt.nodes, fname, o);
+            const size_t nn = pt.nodes.size();
+            for (size_t k = 0; k < nn; ++k) o << "    double hb" << k << " = 0.0;\n";
+            auto pass = [&](const HRef &r, const std::string &c) {
+                if (r.kind == HRef::NODE) o << "    hb" << r.idx << (r.neg ? " -= " : " += ") << c << ";\n";
+                else if (r.kind == HRef::LEAF) o << "    FB[" << r.idx << "]" << (r.neg ? " -= " : " += ") << c << ";\n";
+            };
+            pass(pt.root, "FTB[" + std::to_string(pt.g) + "]");
+            for (size_t kk = nn; kk-- > 0;) {
+                const HNode &n = pt.nodes[kk];
+                const std::string hb = "hb" + std::to_string(kk), fa = fname(n.a),
+                                  fb = "FB[" + std::to_string(n.a) + "]";
+                if (n.w.kind == HRef::CONST) {
+                    if (n.w.c == 1.0) o << "    " << fb << " += " << hb << ";\n";
+                    else if (n.w.c == -1.0) o << "    " << fb << " -= " << hb << ";\n";
+                    else o << "    " << fb << " = fma(" << num(n.w.c) << ", " << hb << ", " << fb << ");\n";
+                } else {
+                    const std::string wn = href_name(n.w, fname);
+                    o << "    " << fb << " = fma(" << (n.w.neg ? "-" : "") << wn << ", " << hb << ", " << fb << ");\n";
+                    pass(n.w, fa + " * " + hb);
+                }
+                pass(n.u, hb);
+            }
+            o << "  }\n";
+        }
+        o << "}\n";
+    } else {
     for (int g = 0; g < G; ++g) {
         for (int ti = tb.group_start[g]; ti < tb.group_start[g + 1]; ++ti) {
             const double s = tb.term_sign[ti];
@@ -1403,6 +1455,7 @@ std::string jit_source(const AmiTerms *t, bool hub, int kernels) {
         }
     }
     o << "}\n";
+    }
 
     // the same at complex energies: FB_l += sum over the terms holding l of
     // s FTB_g prod_(others) F, in complex arithmetic (the caller passes

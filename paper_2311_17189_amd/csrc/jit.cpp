@@ -142,6 +142,46 @@ AmiStatus compile(const std::string &src, std::vector<char> &code, std::string &
 static_assert(sizeof(AmiTerms::jit_code) / sizeof(AmiTerms::jit_code[0]) == 2 * kJitKinds,
               "one code object per input and kind");
 
+// An unsigned value of a code object's kernel metadata built here (the
+// AMDGPU msgpack note of its one kernel): the integer after the fixstr key,
+// or -1.
+int64_t code_meta(const std::vector<char> &code, const char *key) {
+    const size_t n = std::strlen(key);
+    if (n == 0 || n > 31) return -1;
+    std::string pat(1, static_cast<char>(0xa0 | n));
+    pat += key;
+    const std::string bytes(code.begin(), code.end());
+    const size_t at = bytes.find(pat);
+    if (at == std::string::npos) return -1;
+    size_t i = at + pat.size();
+    auto byte = [&](size_t j) -> int64_t {
+        return j < bytes.size() ? static_cast<unsigned char>(bytes[j]) : -1;
+    };
+    const int64_t tag = byte(i);
+    if (tag < 0) return -1;
+    if (tag <= 0x7f) return tag;                                        // positive fixint
+    int len = tag == 0xcc ? 1 : tag == 0xcd ? 2 : tag == 0xce ? 4 : 0;  // uint8/16/32
+    if (len == 0) return -1;
+    int64_t v = 0;
+    for (int k = 1; k <= len; ++k) {
+        const int64_t b = byte(i + k);
+        if (b < 0) return -1;
+        v = (v << 8) | b;
+    }
+    return v;
+}
+
+// Whether the second of two compiled forms of one kernel is the better one:
+// no more private (spill) memory, and at least the waves per SIMD its VGPRs
+// allow; unreadable metadata keeps the first.
+bool prefer_second(const std::vector<char> &a, const std::vector<char> &b) {
+    const int64_t va = code_meta(a, ".vgpr_count"), vb = code_meta(b, ".vgpr_count");
+    const int64_t pa = code_meta(a, ".private_segment_fixed_size"), pb = code_meta(b, ".private_segment_fixed_size");
+    if (va <= 0 || vb <= 0 || pa < 0 || pb < 0) return false;
+    auto waves = [](int64_t v) { return std::min<int64_t>(8, 512 / ((v + 7) / 8 * 8)); };
+    return pb <= pa && waves(vb) >= waves(va);
+}
+
 AmiStatus code_object(AmiTerms *t, bool hub, int kind) {
     const int slot = kJitKinds * (hub ? 1 : 0) + kind;
     std::vector<char> &code = t->jit_code[slot];
@@ -162,6 +202,19 @@ AmiStatus code_object(AmiTerms *t, bool hub, int kind) {
                 err = "no complex-energy kernel for Taylor-coefficient leaves (poles of higher order)";
                 return fail(AMI_E_UNSUPPORTED, err);
             }
+    if (kind == kJitAdjoint && jit_nested_override() < 0) {
+        // the one-pass adjoint in both forms of its leaf-cotangent sweep; the
+        // nested one is kept where it spills no more and keeps the occupancy
+        // (order 4, 52 terms: 63.5 -> 61.0 us per 10^6-sample step; where its
+        // node values push the kernel over a register boundary it loses)
+        std::vector<char> nested;
+        AmiStatus st = code_from_source(jit_source(t, hub, 1 << kind, 0), code, err);
+        if (st != AMI_OK) return fail(st, err);
+        st = code_from_source(jit_source(t, hub, 1 << kind, kJitNestedPartTerms), nested, err);
+        if (st != AMI_OK) return fail(st, err);
+        if (prefer_second(code, nested)) code.swap(nested);
+        return AMI_OK;
+    }
     const AmiStatus st = code_from_source(jit_source(t, hub, 1 << kind), code, err);
     return st == AMI_OK ? AMI_OK : fail(st, err);
 }

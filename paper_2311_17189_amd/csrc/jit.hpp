@@ -56,7 +56,18 @@ int jit_block(const AmiTerms *t, bool hub);
 // passes of the adjoint at complex energies that follow the first of those
 // (kernels & 2048: per frequency, the complex group-sum and denominator
 // cotangents; kernels & 4096: the complex leaf cotangents and the gradients).
-std::string jit_source(const AmiTerms *t, bool hub, int kernels);
+// nested_part: terms per part of the one-pass adjoint's leaf cotangents as a
+// reverse sweep of the nested group sums (0: per-term prefix/suffix products;
+// -1: the AMIGPU_JIT_NESTED_COTANGENTS override, else per-term products).
+std::string jit_source(const AmiTerms *t, bool hub, int kernels, int nested_part = -1);
+
+// The part size named by AMIGPU_JIT_NESTED_COTANGENTS, or -1.
+int jit_nested_override();
+
+// Terms per part of the nested leaf-cotangent sweep the one-pass adjoint
+// tries beside the per-term products (the code object kept is chosen from
+// the two compiled ones' registers and spills).
+constexpr int kJitNestedPartTerms = 4;
 
 // Source of one module of the persistent specialized batch: the generated
 // functions of every item (forward in one pass, or the two-pass forward where

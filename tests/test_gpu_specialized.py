@@ -33,7 +33,8 @@ def test_specialize_ahead_and_cache_across_handles(tmp_path, monkeypatch):
         torch.cuda.synchronize()
         assert amd.last_variant() == "specialized"
         outs.append((o, s))
-    assert len(list(tmp_path.glob("*.hsaco"))) == 2          # forward and adjoint, once
+    # forward and adjoint (both forms of its leaf-cotangent sweep), once
+    assert len(list(tmp_path.glob("*.hsaco"))) == 3
     assert torch.equal(outs[0][0], outs[1][0]) and torch.equal(outs[0][1], outs[1][1])
     ref, scale, dist, _ = reference_hubbard(d, k, q, t, mu, w, beta)
     check(outs[0][0].cpu().numpy(), ref, scale, dist, label="cached specialized")

@@ -87,7 +87,9 @@ def _check_multipole(name, exe, label):
 
 
 @pytest.mark.parametrize("name", list(CASES))
-def test_generated_multipole_values_and_gradients_match_oracle(name, tmp_path):
+@pytest.mark.parametrize("nested", ["0", "4"], ids=["term_products", "nested_sweep"])
+def test_generated_multipole_values_and_gradients_match_oracle(name, nested, tmp_path, monkeypatch):
+    monkeypatch.setenv("AMIGPU_JIT_NESTED_COTANGENTS", nested)
     T = amd.Terms(*CASES[name], multipole=True)
     src = T.source(momentum=False)
     assert "taylor_slopes" in src and "constexpr bool kTaylor = true;" in src
@@ -105,8 +107,9 @@ def test_generated_multipole_adjoint_passes_match_oracle(name, tmp_path):
 def test_multipole_source_has_adjoint_not_complex(tmp_path, monkeypatch):
     """The generated source of a multipole solution holds the forward kernel
     and the adjoint (Taylor-coefficient leaves with their slopes), not the
-    complex-energy kernel; amiTermsSpecialize compiles those two (here, with
-    no device, it then stops at the device query)."""
+    complex-energy kernel; amiTermsSpecialize compiles those (the adjoint in
+    both forms of its leaf-cotangent sweep; here, with no device, it then
+    stops at the device query)."""
     monkeypatch.setenv("AMIGPU_CACHE_DIR", str(tmp_path))
     T = amd.Terms(*DOUBLE, multipole=True)
     src = T.source(momentum=False)
@@ -114,7 +117,8 @@ def test_multipole_source_has_adjoint_not_complex(tmp_path, monkeypatch):
     with pytest.raises(amd.AmiError) as e:
         T.specialize(momentum=False)
     assert e.value.code == -5 and "hipGetDevice" in str(e.value)
-    assert len([p for p in tmp_path.iterdir() if p.name.endswith(".hsaco")]) == 2
+    # the forward, and the adjoint in both forms of its leaf-cotangent sweep
+    assert len([p for p in tmp_path.iterdir() if p.name.endswith(".hsaco")]) == 3
 
 
 @pytest.mark.parametrize("name", list(CASES))

@@ -62,7 +62,12 @@ CASES = [("o2", None), ("o3", (0, 3, 0)), ("o4", (0, 4, 1)), ("o4b", (0, 4, 3)),
 
 
 @pytest.mark.parametrize("name,seed", CASES)
-def test_generated_energy_kernels_match_oracle(name, seed, tmp_path):
+@pytest.mark.parametrize("nested", ["0", "4"], ids=["term_products", "nested_sweep"])
+def test_generated_energy_kernels_match_oracle(name, seed, nested, tmp_path, monkeypatch):
+    """Values and gradients of the generated one-pass functions, with the
+    leaf cotangents from per-term products and from the reverse sweep of the
+    nested group sums (parts of four terms)."""
+    monkeypatch.setenv("AMIGPU_JIT_NESTED_COTANGENTS", nested)
     d = order2_example() if seed is None else random_self_energy(seed[1], seed)
     T = amd.Terms.from_diagram(d)
     exe = _harness(T.source(momentum=False), tmp_path, name)
@@ -86,7 +91,9 @@ def test_generated_energy_kernels_match_oracle(name, seed, tmp_path):
 
 
 @pytest.mark.parametrize("name,seed", CASES)
-def test_generated_momentum_kernels_match_oracle(name, seed, tmp_path):
+@pytest.mark.parametrize("nested", ["0", "4"], ids=["term_products", "nested_sweep"])
+def test_generated_momentum_kernels_match_oracle(name, seed, nested, tmp_path, monkeypatch):
+    monkeypatch.setenv("AMIGPU_JIT_NESTED_COTANGENTS", nested)
     d = order2_example() if seed is None else random_self_energy(seed[1], seed)
     T = amd.Terms.from_diagram(d)
     exe = _harness(T.source(momentum=True), tmp_path, name + "k")
@@ -197,13 +204,14 @@ def test_hiprtc_compiles_the_generated_source(tmp_path, monkeypatch, momentum, k
             assert e.code == -5 and "hipGetDevice" in str(e), str(e)
     srcs = sorted(p for p in tmp_path.iterdir() if p.name.endswith(".hip"))
     objs = sorted(p for p in tmp_path.iterdir() if p.name.endswith(".hsaco"))
-    assert len(srcs) == len(objs) == len(kernels)
+    # one code object per kernel (forward 1, adjoint 2, complex-energy forward
+    # 8 and adjoint 256), the one-pass adjoint in both forms of its
+    # leaf-cotangent sweep
+    assert len(srcs) == len(objs) == len(kernels) + 1
     for p in objs:
         assert p.stat().st_size > 1000
-    # one code object per kernel: forward 1, adjoint 2, complex-energy forward 8
-    # and adjoint 256
     found = sorted(k for p in srcs for k in kernels if f"#define AMI_JIT_KERNELS {k}\n" in p.read_text())
-    assert found == sorted(kernels)
+    assert found == sorted(kernels + (2,))
 
 
 def test_persistent_batch_module_compiles(tmp_path, monkeypatch):
