@@ -261,7 +261,7 @@ AmiStatus amiEvaluateComplex(AmiTerms *terms,
  * amiEvaluateComplex; out / out_sum (device, or NULL) receive the forward
  * values on the way.  The sums over samples are reduced in a fixed order.
  * Served by the specialized kernels (compiled on first use): one pass up to
- * 256 terms (up to 1024 under AMI_VARIANT_SPECIALIZED); above, or under
+ * 512 terms (up to 1024 under AMI_VARIANT_SPECIALIZED); above, or under
  * AMI_VARIANT_TWO_PASS, passes over the chunked workspace of the two-pass
  * variant (complex group sums and energies stored; per frequency row the
  * values and the complex cotangents of group sums and denominators; then the

@@ -1464,6 +1464,81 @@ std::string jit_source(const AmiTerms *t, bool hub, int kernels, int nested_part
     o << "__device__ __forceinline__ void leaf_cotangents_c(const double (&Fr)[L], const double (&Fi)[L], const double "
          "(&FTBr)[G], const double (&FTBi)[G], double (&FBr)[L], double (&FBi)[L]) {\n";
     o << kReverseContract;
+    if (nested_part > 0) {
+        // the reverse sweep of each group's nested sum at the given conj(F):
+        // its node values are the conjugates of the true ones (real
+        // coefficients), so a node h = F_a w + u passes hbar w to F_a and
+        // hbar F_a to w as plain complex products
+        std::vector<Part> parts;
+        std::vector<int> first_use, last_use;
+        build_parts(parts, first_use, last_use, nested_part);
+        auto vre = [&](const HRef &r) -> std::string {
+            if (r.kind == HRef::LEAF) return "Fr[" + std::to_string(r.idx) + "]";
+            if (r.kind == HRef::NODE) return "h" + std::to_string(r.idx) + "r";
+            return r.kind == HRef::CONST ? num(r.c) : std::string("0.0");
+        };
+        auto vim = [&](const HRef &r) -> std::string {
+            if (r.kind == HRef::LEAF) return "Fi[" + std::to_string(r.idx) + "]";
+            if (r.kind == HRef::NODE) return "h" + std::to_string(r.idx) + "i";
+            return std::string("0.0");
+        };
+        auto sg = [](const HRef &r, const std::string &e) { return r.neg ? "(-" + e + ")" : e; };
+        for (size_t p = 0; p < parts.size(); ++p) {
+            const Part &pt = parts[p];
+            if (p > 0) o << "  AMI_SCHED_FENCE();\n";
+            o << "  {\n";
+            const size_t nn = pt.nodes.size();
+            for (size_t k = 0; k < nn; ++k) {
+                const HNode &n = pt.nodes[k];
+                const std::string far = "Fr[" + std::to_string(n.a) + "]", fai = "Fi[" + std::to_string(n.a) + "]";
+                std::string ur = "0.0", ui = "0.0";
+                if (n.u.kind == HRef::CONST) ur = num(n.u.c);
+                else if (n.u.kind != HRef::ZERO) {
+                    ur = sg(n.u, vre(n.u));
+                    ui = sg(n.u, vim(n.u));
+                }
+                std::string hr, hi;
+                if (n.w.kind == HRef::CONST) {
+                    hr = "fma(" + num(n.w.c) + ", " + far + ", " + ur + ")";
+                    hi = "fma(" + num(n.w.c) + ", " + fai + ", " + ui + ")";
+                } else {
+                    const std::string wr = sg(n.w, vre(n.w)), wi = sg(n.w, vim(n.w));
+                    hr = "fma(" + far + ", " + wr + ", fma(-" + fai + ", " + wi + ", " + ur + "))";
+                    hi = "fma(" + far + ", " + wi + ", fma(" + fai + ", " + wr + ", " + ui + "))";
+                }
+                o << "    const double h" << k << "r = " << hr << ", h" << k << "i = " << hi << ";\n";
+            }
+            for (size_t k = 0; k < nn; ++k) o << "    double hb" << k << "r = 0.0, hb" << k << "i = 0.0;\n";
+            auto pass = [&](const HRef &r, const std::string &cr, const std::string &ci) {
+                const char *op = r.neg ? " -= " : " += ";
+                if (r.kind == HRef::NODE)
+                    o << "    hb" << r.idx << "r" << op << cr << "; hb" << r.idx << "i" << op << ci << ";\n";
+                else if (r.kind == HRef::LEAF)
+                    o << "    FBr[" << r.idx << "]" << op << cr << "; FBi[" << r.idx << "]" << op << ci << ";\n";
+            };
+            pass(pt.root, "FTBr[" + std::to_string(pt.g) + "]", "FTBi[" + std::to_string(pt.g) + "]");
+            for (size_t kk = nn; kk-- > 0;) {
+                const HNode &n = pt.nodes[kk];
+                const std::string br = "hb" + std::to_string(kk) + "r", bi = "hb" + std::to_string(kk) + "i";
+                const std::string far = "Fr[" + std::to_string(n.a) + "]", fai = "Fi[" + std::to_string(n.a) + "]";
+                const std::string fbr = "FBr[" + std::to_string(n.a) + "]", fbi = "FBi[" + std::to_string(n.a) + "]";
+                if (n.w.kind == HRef::CONST) {
+                    o << "    " << fbr << " = fma(" << num(n.w.c) << ", " << br << ", " << fbr << "); " << fbi
+                      << " = fma(" << num(n.w.c) << ", " << bi << ", " << fbi << ");\n";
+                } else {
+                    const std::string wr = sg(n.w, vre(n.w)), wi = sg(n.w, vim(n.w));
+                    o << "    " << fbr << " = fma(" << br << ", " << wr << ", fma(-" << bi << ", " << wi << ", " << fbr
+                      << ")); " << fbi << " = fma(" << br << ", " << wi << ", fma(" << bi << ", " << wr << ", " << fbi
+                      << "));\n";
+                    pass(n.w, "fma(" + br + ", " + far + ", -" + bi + " * " + fai + ")",
+                         "fma(" + br + ", " + fai + ", " + bi + " * " + far + ")");
+                }
+                pass(n.u, br, bi);
+            }
+            o << "  }\n";
+        }
+        o << "}\n";
+    } else {
     for (int g = 0; g < G; ++g) {
         for (int ti = tb.group_start[g]; ti < tb.group_start[g + 1]; ++ti) {
             const double s = tb.term_sign[ti];
@@ -1506,6 +1581,7 @@ std::string jit_source(const AmiTerms *t, bool hub, int kernels, int nested_part
         }
     }
     o << "}\n";
+    }
     }
     }  // adj_fns
 

@@ -1264,7 +1264,7 @@ AmiStatus amiTermsSpecialize(AmiTerms *t, int32_t momentum) {
         kinds.push_back(kJitAdjLeaf);
     }
     // the complex-energy kernels AUTO uses: forward in one pass up to 1024
-    // terms, in two above; the adjoint in one pass up to 256 terms, in passes
+    // terms, in two above; the adjoint in one pass up to 512 terms, in passes
     // above
     if (!taylor && !hub && t->tab.T <= kJitTwoPassMaxTerms) {
         if (small) {

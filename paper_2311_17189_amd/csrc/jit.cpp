@@ -202,8 +202,8 @@ AmiStatus code_object(AmiTerms *t, bool hub, int kind) {
                 err = "no complex-energy kernel for Taylor-coefficient leaves (poles of higher order)";
                 return fail(AMI_E_UNSUPPORTED, err);
             }
-    if (kind == kJitAdjoint && jit_nested_override() < 0) {
-        // the one-pass adjoint in both forms of its leaf-cotangent sweep; the
+    if ((kind == kJitAdjoint || kind == kJitComplexAdj) && jit_nested_override() < 0) {
+        // the one-pass adjoints in both forms of their leaf-cotangent sweep; the
         // nested one is kept where it spills no more and keeps the occupancy
         // (order 4, 52 terms: 63.5 -> 61.0 us per 10^6-sample step; where its
         // node values push the kernel over a register boundary it loses)

@@ -21,10 +21,9 @@ constexpr int kJitTwoPassMaxTerms = 4096;
 // and the adjoint runs in passes over a workspace (up to kJitTwoPassMaxTerms).
 constexpr int kJitAutoAdjointTerms = 128;
 // The same switch for the adjoint at complex energies, whose passes hold
-// complex values per leaf and node (196 terms: one pass 0.84 ms, passes
-// 1.25 ms; 264: 1.46 ms one pass; 560: one pass 5.8 ms, passes 1.9 ms per
-// 10^6-sample step).
-constexpr int kJitAutoComplexAdjointTerms = 256;
+// complex values per leaf and node (per 10^6-sample step: 264 terms one pass
+// 0.91 ms, passes 1.75 ms; 380: 1.30 / 3.18 ms; 560: 2.21 / 1.91 ms).
+constexpr int kJitAutoComplexAdjointTerms = 512;
 
 // Whether the adjoint of a solution above kJitAutoAdjointTerms can run in
 // passes (the two-pass form, no Taylor-coefficient leaves).

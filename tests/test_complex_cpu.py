@@ -72,10 +72,12 @@ def test_generated_complex_two_pass_matches_oracle(name, seed, n, tmp_path):
 
 @pytest.mark.parametrize("name,seed", CASES)
 @pytest.mark.parametrize("e_reg", [0.0, 0.03])
-def test_generated_complex_adjoint_matches_oracle(name, seed, e_reg, tmp_path):
+@pytest.mark.parametrize("nested", ["0", "4"], ids=["term_products", "nested_sweep"])
+def test_generated_complex_adjoint_matches_oracle(name, seed, e_reg, nested, tmp_path, monkeypatch):
     """The adjoint at complex energies in one pass: dL/dRe E + i dL/dIm E per
     sample, dL/dbeta and dL/dw summed, within 1e-10 of their rounding scales;
     the values formed on the way within the forward's bar."""
+    monkeypatch.setenv("AMIGPU_JIT_NESTED_COTANGENTS", nested)
     d = order2_example() if seed is None else random_self_energy(seed[1], seed)
     T = amd.Terms.from_diagram(d)
     src = T.source(momentum=False)

@@ -117,7 +117,7 @@ def test_complex_adjoint_vs_oracle(order, i, beta, n_e, e_reg, variant):
     """dL/dRe E + i dL/dIm E per sample, dL/dbeta and dL/dw within 1e-10 of
     their rounding scales on samples away from poles; the values formed on the
     way equal amiEvaluateComplex's, and their row sums.  AUTO runs the one-pass
-    kernel up to 256 terms and the passes above; the two forced variants run
+    kernel up to 512 terms and the passes above; the two forced variants run
     one each."""
     d = _diag(order, i)
     eta = 0.25 / (beta * d.n_int)
@@ -137,7 +137,7 @@ def test_complex_adjoint_vs_oracle(order, i, beta, n_e, e_reg, variant):
     g_e, g_b, g_w = amd.evaluate_complex_adjoint(T, Et, wt, beta, e_reg, grad_out=torch.from_numpy(cot).to(DEV),
                                                  grad_sum=torch.from_numpy(cot_sum).to(DEV), out=out,
                                                  out_sum=out_sum)
-    passes = variant == amd.VARIANT_TWO_PASS or (variant == amd.VARIANT_AUTO and T.info()["T"] > 256)
+    passes = variant == amd.VARIANT_TWO_PASS or (variant == amd.VARIANT_AUTO and T.info()["T"] > 512)
     assert amd.last_variant() == ("specialized complex passes" if passes else "specialized complex")
     T.set_variant(amd.VARIANT_AUTO)
     fwd, _ = amd.evaluate_complex(T, Et, wt, beta, e_reg)
@@ -231,6 +231,7 @@ def test_complex_adjoint_passes_chunks_and_large(order, seed, n_e):
     oracle's gradients (on a sampled subset at 2804 terms)."""
     d = random_self_energy(order, seed)
     T = amd.Terms.from_diagram(d)
+    T.set_variant(amd.VARIANT_TWO_PASS)      # AUTO takes the one-pass kernel at 264 terms
     beta, e_reg = 5.0, 0.02
     eta = 0.25 / (beta * d.n_int)
     E = complex_energies(n_e, d.n_eps, seed=(99, order), a=3.0, eta=eta)
