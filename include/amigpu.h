@@ -433,6 +433,17 @@ AmiStatus amiIntegrateHubbard(AmiTerms *terms, int64_t n_samples, uint64_t seed,
  * A forced variant that cannot serve a call fails it (AMI_E_UNSUPPORTED, or
  * AMI_E_HIP when the run-time compilation fails); AUTO falls back in the order
  * above and amiLastVariant names what ran and why.
+ *
+ * Tuning overrides of the generated kernels, read from the environment when a
+ * kernel is generated (each changes the source, so the disk cache keeps the
+ * forms apart): AMIGPU_JIT_ADJ_WAVES (one-pass adjoint's waves per SIMD floor,
+ * default 2), AMIGPU_JIT_PARK_DV (0/1: the adjoint's leaf slopes in LDS),
+ * AMIGPU_JIT_NESTED_COTANGENTS (terms per part of the one-pass adjoints'
+ * nested leaf-cotangent sweep, 0 for per-term products; by default both forms
+ * are compiled and the one whose code object spills no more and keeps the
+ * occupancy is kept), AMIGPU_JIT_CADJ_PART and AMIGPU_JIT_CADJL_WAVES (terms
+ * per part and waves floor of the complex adjoint's leaf pass, defaults 64
+ * and 1).
  */
 enum { AMI_VARIANT_AUTO = 0, AMI_VARIANT_TABLES = 1, AMI_VARIANT_PACKED = 2, AMI_VARIANT_SPECIALIZED = 3,
        AMI_VARIANT_TWO_PASS = 4 };
