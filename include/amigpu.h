@@ -596,8 +596,9 @@ typedef struct {
  * tiles with the two-pass items' first pass, then their frequency pass), the
  * items grouped by the occupancy of their own kernel of that pass -- holding
  * every item's generated tile functions and a persistent kernel that pulls
- * (item, tile range, frequency row) work items from its own counter; the graph
- * runs counter reset -> the first-pass kernels side by side -> the
+ * (item, tile range, range of frequency rows) work items from its own
+ * counters; the graph runs counter reset -> the first-pass kernels side by
+ * side -> the
  * frequency-pass kernels -> fixed-order row sums; out and out_sum equal an
  * AUTO evaluate call's bit for bit.
  */

@@ -21,7 +21,7 @@ from typing import Dict, List, Optional
 # specialized tile functions in persistent kernels over a few tilings, then the
 # packed persistent kernels over a grid of tilings
 DEFAULT_CANDIDATES: List[Dict[str, int]] = [{"block": 0, "waves_per_cu": 8, "tile_factor": 1, "kernels": 0}] + [
-    {"block": 0, "waves_per_cu": w, "tile_factor": f, "kernels": 2} for w, f in ((32, 4), (16, 2), (32, 1))
+    {"block": 0, "waves_per_cu": w, "tile_factor": f, "kernels": 2} for w, f in ((32, 2), (32, 4), (16, 2))
 ] + [
     {"block": b, "waves_per_cu": w, "tile_factor": f, "kernels": 1}
     for b in (0, 64, 128) for w in (4, 8, 16) for f in (1, 4)

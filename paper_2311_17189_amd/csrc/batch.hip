@@ -113,8 +113,8 @@ __global__ __launch_bounds__(256) void ami_batch_kernel(const BatchDesc *desc, c
     }
 }
 
-// counters are kCounterStride apart (one per class)
-constexpr int kCounterStride = 16;
+// counters are kCounterStride apart (one per class or work list)
+constexpr int kCounterStride = kBatchCounterStride;
 constexpr int kMaxClasses = 16;
 
 __global__ void ami_batch_reset_kernel(unsigned int *counters, int n) {
@@ -291,7 +291,7 @@ __global__ __launch_bounds__(kRedThreads) void ami_batch_colsum_kernel(const Col
 struct SpecWork {
     int32_t item, ntiles;
     int64_t tile0;
-    int32_t f, pad;
+    int32_t f, nf;
 };
 
 // Terms per compiled group of the persistent specialized batch (groups are
@@ -376,7 +376,8 @@ AmiStatus create_spec_persistent(const AmiBatchItem *items, int n_items, const A
     }
     // generated sources, compiled side by side (no device needed), then loaded
     const size_t G = groups.size();
-    std::vector<std::string> srcs(G), errs(G);
+    std::vector<std::string> srcs(G), forced(G), plain(G), errs(G);
+    std::vector<int> own(G, 1);
     std::vector<std::vector<char>> codes(G);
     std::vector<AmiStatus> sts(G, AMI_OK);
     for (size_t g = 0; g < G; ++g) {
@@ -388,15 +389,40 @@ AmiStatus create_spec_persistent(const AmiBatchItem *items, int n_items, const A
             one.push_back(items[i].n_f == 1 ? 1 : 0);
             labels.push_back(i);
         }
-        srcs[g] = jit_batch_source(ts, tp, one, hub, B, groups[g].pass, labels);
+        own[g] = (groups[g].pass == 1 ? waves1 : waves2)[groups[g].items[0]];
+        srcs[g] = jit_batch_source(ts, tp, one, hub, B, groups[g].pass, labels, true, 0);
+        forced[g] = jit_batch_source(ts, tp, one, hub, B, groups[g].pass, labels, true, own[g]);
+        plain[g] = jit_batch_source(ts, tp, one, hub, B, groups[g].pass, labels, false, 0);
     }
     {
+        // a group's kernel as it compiles, claiming work ahead, where that
+        // keeps the occupancy of its items' own kernels of the pass (read from
+        // the compiled code's metadata); else compiled for that occupancy,
+        // where that spills nothing; else without the claim ahead, where that
+        // keeps more waves
+        auto waves_meta = [](const std::vector<char> &code) {
+            const int64_t v = code_meta(code, ".vgpr_count");
+            return v <= 0 ? int64_t(0) : std::min<int64_t>(8, 512 / ((v + 7) / 8 * 8));
+        };
         std::vector<std::thread> pool;
         std::atomic<size_t> next{0};
         const unsigned n_thr = std::max(1u, std::min<unsigned>(8u, static_cast<unsigned>(G)));
         for (unsigned k = 0; k < n_thr; ++k)
             pool.emplace_back([&]() {
-                for (size_t g = next++; g < G; g = next++) sts[g] = code_from_source(srcs[g], codes[g], errs[g]);
+                for (size_t g = next++; g < G; g = next++) {
+                    sts[g] = code_from_source(srcs[g], codes[g], errs[g]);
+                    if (sts[g] != AMI_OK || waves_meta(codes[g]) >= own[g]) continue;
+                    std::vector<char> alt;
+                    std::string alt_err;
+                    if (code_from_source(forced[g], alt, alt_err) == AMI_OK && waves_meta(alt) >= own[g] &&
+                        code_meta(alt, ".private_segment_fixed_size") == 0) {
+                        codes[g].swap(alt);
+                        continue;
+                    }
+                    alt.clear();
+                    if (code_from_source(plain[g], alt, alt_err) == AMI_OK && waves_meta(alt) > waves_meta(codes[g]))
+                        codes[g].swap(alt);
+                }
             });
         for (auto &th : pool) th.join();
     }
@@ -421,12 +447,26 @@ AmiStatus create_spec_persistent(const AmiBatchItem *items, int n_items, const A
         if (e != hipSuccess) return batch_fail_free(b, fail(AMI_E_HIP, std::string("hipModuleGetFunction ") + name));
     }
 
-    // work lists: per group, each item's tiles in work items of about
-    // tile_factor times the group's most expensive tile, the items from the
-    // most to the least expensive with their work items together (a CU then
-    // mostly runs one item's code at a time); in the frequency pass a work
-    // item is a tile range at one frequency row, the rows of a range queued
-    // one after another
+    // resident blocks per CU of each group's kernel, from its own VGPRs (one
+    // wave of each block per SIMD), capped by the tuning
+    std::vector<int> per_cu(G, 1);
+    for (size_t g = 0; g < G; ++g) {
+        int regs = 0;
+        e = hipFuncGetAttribute(&regs, HIP_FUNC_ATTRIBUTE_NUM_REGS, kfn[g]);
+        if (e != hipSuccess) return batch_fail_free(b, hip_fail(e, "hipFuncGetAttribute"));
+        const int gw = std::max(1, std::min(8, 512 / std::max(8, (regs + 7) / 8 * 8)));
+        per_cu[g] = std::max(1, std::min(gw, tun.waves_per_cu / (B / 64)));
+    }
+
+    // work lists: per group, each item's tiles (and, in the frequency pass,
+    // rows) in work items of about tile_factor times the group's most
+    // expensive unit -- a tile, or a tile at one row -- but no larger than a
+    // quarter of the group's work per resident block, so that a list has work
+    // for every block and its tail stays short; the items from the most to
+    // the least expensive with their work items together (a CU then mostly
+    // runs one item's code at a time); in the frequency pass a work item is a
+    // tile range at a range of rows, the rows of a tile range queued one
+    // after another
     std::vector<double> tile_cost(n_items);
     for (int i = 0; i < n_items; ++i) tile_cost[i] = sample_cost(items[i].terms, items[i].n_f) * B;
     // Each group's work goes into eight lists, one per XCD: a unit (an
@@ -443,28 +483,37 @@ AmiStatus create_spec_persistent(const AmiBatchItem *items, int n_items, const A
         auto unit = [&](int i) {
             return !two[i] ? tile_cost[i] : pass == 1 ? tile_cost[i] / 5 : tile_cost[i] / items[i].n_f;
         };
-        double max_tile = 0.0;
-        for (int i : groups[g].items) max_tile = std::max(max_tile, unit(i));
-        const double target = max_tile * tun.tile_factor;
+        auto rows_of = [&](int i) { return pass == 2 ? static_cast<int64_t>(items[i].n_f) : int64_t(1); };
+        double max_unit = 0.0, total = 0.0;
+        for (int i : groups[g].items) {
+            max_unit = std::max(max_unit, unit(i));
+            total += unit(i) * static_cast<double>(tiles[i] * rows_of(i));
+        }
+        const double slots = static_cast<double>(n_cu) * per_cu[g];
+        const double target = std::min(max_unit * tun.tile_factor, total / (4.0 * slots));
         std::vector<int> by_cost = groups[g].items;
         std::stable_sort(by_cost.begin(), by_cost.end(), [&](int x, int y) { return cost[x] > cost[y]; });
         w0[g] = static_cast<int64_t>(wl.size());
         std::vector<SpecWork> lists[8];
         double load[8] = {0.0};
         for (int i : by_cost) {
+            // units per work item: rows first, then whole tiles of all rows
             const int64_t per = std::max<int64_t>(1, static_cast<int64_t>(target / unit(i)));
-            const int rows_per = pass == 2 ? static_cast<int>(items[i].n_f) : 1;
-            for (int64_t t0 = 0; t0 < tiles[i]; t0 += per) {
-                const int64_t nt = std::min<int64_t>(per, tiles[i] - t0);
+            const int64_t rows = rows_of(i);
+            const int64_t nr = std::min(per, rows);
+            const int64_t per_t = nr < rows ? 1 : std::max<int64_t>(1, per / rows);
+            for (int64_t t0 = 0; t0 < tiles[i]; t0 += per_t) {
+                const int64_t nt = std::min<int64_t>(per_t, tiles[i] - t0);
                 const int x = static_cast<int>(std::min_element(load, load + 8) - load);
-                load[x] += unit(i) * static_cast<double>(nt) * rows_per;
-                for (int f = 0; f < rows_per; ++f) {
+                load[x] += unit(i) * static_cast<double>(nt * rows);
+                for (int64_t f0 = 0; f0 < rows; f0 += nr) {
                     SpecWork w;
                     std::memset(&w, 0, sizeof(w));
                     w.item = i;
                     w.tile0 = t0;
                     w.ntiles = static_cast<int32_t>(nt);
-                    w.f = pass == 2 ? f : -1;
+                    w.f = pass == 2 ? static_cast<int32_t>(f0) : -1;
+                    w.nf = pass == 2 ? static_cast<int32_t>(std::min(nr, rows - f0)) : 0;
                     lists[x].push_back(w);
                 }
             }
@@ -568,13 +617,6 @@ AmiStatus create_spec_persistent(const AmiBatchItem *items, int n_items, const A
     for (int pass = 1; pass <= 2; ++pass)
         for (size_t g = 0; g < G; ++g) {
             if (groups[g].pass != pass || nw[g] == 0) continue;
-            // resident blocks per CU from the kernel's own VGPRs (one wave of
-            // each block per SIMD), capped by the tuning
-            int regs = 0;
-            e = hipFuncGetAttribute(&regs, HIP_FUNC_ATTRIBUTE_NUM_REGS, kfn[g]);
-            if (e != hipSuccess) return batch_fail_free(b, hip_fail(e, "hipFuncGetAttribute"));
-            const int gw = std::max(1, std::min(8, 512 / std::max(8, (regs + 7) / 8 * 8)));
-            const int per_cu = std::max(1, std::min(gw, tun.waves_per_cu / (B / 64)));
             const KArgs *d_args = reinterpret_cast<const KArgs *>(base);
             const SpecWork *d_work = reinterpret_cast<const SpecWork *>(base + off_work) + w0[g];
             const int *d_xoff = reinterpret_cast<const int *>(base + off_xoff) + g * 9;
@@ -583,7 +625,7 @@ AmiStatus create_spec_persistent(const AmiBatchItem *items, int n_items, const A
             hipKernelNodeParams p;
             std::memset(&p, 0, sizeof(p));
             p.func = reinterpret_cast<void *>(kfn[g]);
-            p.gridDim = dim3(static_cast<unsigned>(std::min<int64_t>(static_cast<int64_t>(n_cu) * per_cu, nw[g])));
+            p.gridDim = dim3(static_cast<unsigned>(std::min<int64_t>(static_cast<int64_t>(n_cu) * per_cu[g], nw[g])));
             p.blockDim = dim3(B);
             p.kernelParams = kp;
             hipGraphNode_t node = nullptr;

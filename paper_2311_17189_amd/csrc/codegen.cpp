@@ -1622,7 +1622,7 @@ std::string jit_source(const AmiTerms *t, bool hub, int kernels, int nested_part
 
 std::string jit_batch_source(const std::vector<const AmiTerms *> &items, const std::vector<int> &two_pass,
                              const std::vector<int> &one_row, bool hub, int block, int phases,
-                             const std::vector<int> &labels) {
+                             const std::vector<int> &labels, bool claim_ahead, int waves) {
     std::ostringstream o;
     o << "// generated: persistent batch of " << items.size() << " specialized evaluators\n";
     o << "#include \"kargs.hpp\"\n";
@@ -1648,21 +1648,26 @@ std::string jit_batch_source(const std::vector<const AmiTerms *> &items, const s
         o << "#include \"jit_tiles.hpp\"\n#undef amijit\n";
     }
     // the persistent kernels: every block takes work items (item, first tile,
-    // tile count, frequency row) from its counter until the list is done (every
-    // wave sees the counter pass n_work and exits) and runs the item's own tile
-    // function on each tile; the first kernel runs the one-pass forward tiles
-    // and the two-pass items' first pass, the second their frequency pass
+    // tile count, first frequency row, row count) from its counter until the
+    // list is done (every wave sees the counter pass n_work and exits) and runs
+    // the item's own tile function on each tile (and row); the first kernel
+    // runs the one-pass forward tiles and the two-pass items' first pass, the
+    // second their frequency pass.  With claim_ahead the claim of the next
+    // work item is issued before the current one runs, so that its round trip
+    // overlaps the work.
     o << "namespace amibatch {\n"
-         "struct Work {\n  int32_t item, ntiles;\n  int64_t tile0;\n  int32_t f, pad;\n};\n"
+         "struct Work {\n  int32_t item, ntiles;\n  int64_t tile0;\n  int32_t f, nf;\n};\n"
          "typedef const __attribute__((address_space(4))) Work *cwork;\n"
          "typedef const __attribute__((address_space(4))) ami::KArgs *cargs;\n"
          "}  // namespace amibatch\n";
+    const std::string stride = std::to_string(kBatchCounterStride);
     for (int phase = 1; phase <= 2; ++phase) {
         if (!(phases & phase) || (phase == 2 && !any_two)) continue;
         // eight work lists, one per XCD (xoff[x] .. xoff[x + 1] of work, with
-        // their counters 16 apart): a block drains the list of its own XCD
-        // first (block b runs on XCD b mod 8), then the others in turn, so
-        // every block has tried every list before it exits
+        // their counters kBatchCounterStride apart): a block drains the list
+        // of its own XCD first (block b runs on XCD b mod 8), then the others
+        // in turn, so every block has tried every list before it exits
+        if (waves > 0) o << "__attribute__((amdgpu_waves_per_eu(" << waves << ")))\n";
         o << "extern \"C\" __global__ __launch_bounds__(" << block << ") void ami_batch_p" << phase
           << "(const ami::KArgs *args, const amibatch::Work *work, const int *xoff, unsigned int *counter) {\n"
              "  __shared__ int next;\n"
@@ -1671,33 +1676,46 @@ std::string jit_batch_source(const std::vector<const AmiTerms *> &items, const s
              "  const int x0 = static_cast<int>(blockIdx.x & 7u);\n"
              "  for (int k = 0; k < 8; ++k) {\n"
              "   const int x = (x0 + k) & 7, begin = xoff[x], n_work = xoff[x + 1] - begin;\n"
-             "   for (;;) {\n"
-             "    if (threadIdx.x == 0) next = static_cast<int>(atomicAdd(counter + 16 * x, 1u));\n"
-             "    __syncthreads();\n"
-             "    const int wj = __builtin_amdgcn_readfirstlane(next);\n"
-             "    __syncthreads();\n"
-             "    if (wj >= n_work) break;\n"
-             "    const int wi = begin + wj;\n"
-             "    const int item = cw[wi].item, ntiles = cw[wi].ntiles, f = cw[wi].f;\n"
+             "   unsigned int *const ctr = counter + " << stride << " * x;\n"
+             "   if (threadIdx.x == 0) next = static_cast<int>(atomicAdd(ctr, 1u));\n"
+             "   __syncthreads();\n"
+             "   int wj = __builtin_amdgcn_readfirstlane(next);\n"
+             "   __syncthreads();\n"
+             "   while (wj < n_work) {\n";
+        if (claim_ahead)
+            o << "    unsigned int claim = 0u;\n"
+                 "    if (threadIdx.x == 0) claim = atomicAdd(ctr, 1u);\n";
+        o << "    const int wi = begin + wj;\n"
+             "    const int item = cw[wi].item, ntiles = cw[wi].ntiles, f = cw[wi].f, nf = cw[wi].nf;\n"
              "    const int64_t tile0 = cw[wi].tile0;\n"
              "    const __attribute__((address_space(4))) ami::KArgs &a = ca[item];\n"
              "    (void)f;\n"
+             "    (void)nf;\n"
              "    switch (item) {\n";
         for (size_t j = 0; j < items.size(); ++j) {
             const std::string ns = "amijit_b" + std::to_string(j);
             const std::string h = hub ? "true" : "false";
             const int label = labels.empty() ? static_cast<int>(j) : labels[j];
             if (phase == 1) {
-                o << "    case " << label << ":\n      for (int64_t t = tile0; t < tile0 + ntiles; ++t) ";
+                o << "    case " << label << ":\n      for (int64_t t = tile0; t < tile0 + ntiles; ++t) {\n"
+                  << "        asm volatile(\"\" ::: \"memory\");   // each tile loads its own inputs\n        ";
                 if (two_pass[j]) o << ns << "::sums_tile<" << h << ">(a, t);\n";
                 else o << ns << "::fwd_tile<" << h << ", " << (one_row[j] ? "true" : "false") << ">(a, t);\n";
-                o << "      break;\n";
+                o << "      }\n      break;\n";
             } else if (two_pass[j]) {
-                o << "    case " << label << ":\n      for (int64_t t = tile0; t < tile0 + ntiles; ++t) " << ns
-                  << "::freq_tile(a, t, f);\n      break;\n";
+                o << "    case " << label << ":\n      for (int64_t t = tile0; t < tile0 + ntiles; ++t)\n"
+                  << "        for (int r = f; r < f + nf; ++r) {\n"
+                  << "          asm volatile(\"\" ::: \"memory\");   // each row loads its own inputs\n"
+                  << "          " << ns << "::freq_tile(a, t, r);\n        }\n      break;\n";
             }
         }
-        o << "    default: break;\n    }\n   }\n  }\n}\n";
+        o << "    default: break;\n    }\n";
+        o << (claim_ahead ? "    if (threadIdx.x == 0) next = static_cast<int>(claim);\n"
+                          : "    if (threadIdx.x == 0) next = static_cast<int>(atomicAdd(ctr, 1u));\n");
+        o << "    __syncthreads();\n"
+             "    wj = __builtin_amdgcn_readfirstlane(next);\n"
+             "    __syncthreads();\n"
+             "   }\n  }\n}\n";
     }
     return o.str();
 }

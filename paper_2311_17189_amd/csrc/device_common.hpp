@@ -364,12 +364,19 @@ __device__ __forceinline__ double wave_sum(double v) {
 // workspace with leading dimension ld: the column's base is wave-uniform and
 // the offset a 32-bit lane value, which the compiler turns into a load or store
 // with a scalar base and no vector address arithmetic.
+__device__ __forceinline__ uint64_t ws_column(const double *ws, int64_t ld, int c) {
+    const uint64_t p = reinterpret_cast<uint64_t>(ws + c * ld);
+    const uint32_t lo = __builtin_amdgcn_readfirstlane(static_cast<uint32_t>(p));
+    const uint32_t hi = __builtin_amdgcn_readfirstlane(static_cast<uint32_t>(p >> 32));
+    return (static_cast<uint64_t>(hi) << 32) | lo;
+}
+
 __device__ __forceinline__ double ws_load(const double *ws, int64_t ld, int c, uint32_t off) {
-    return *reinterpret_cast<const double *>(reinterpret_cast<const char *>(ws + c * ld) + off);
+    return *reinterpret_cast<const double *>(ws_column(ws, ld, c) + off);
 }
 
 __device__ __forceinline__ void ws_store(double *ws, int64_t ld, int c, uint32_t off, double v) {
-    *reinterpret_cast<double *>(reinterpret_cast<char *>(ws + c * ld) + off) = v;
+    *reinterpret_cast<double *>(ws_column(ws, ld, c) + off) = v;
 }
 
 // gfx950 lane exchanges of a double, as two 32-bit halves: swap32 exchanges

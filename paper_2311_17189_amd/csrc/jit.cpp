@@ -142,35 +142,6 @@ AmiStatus compile(const std::string &src, std::vector<char> &code, std::string &
 static_assert(sizeof(AmiTerms::jit_code) / sizeof(AmiTerms::jit_code[0]) == 2 * kJitKinds,
               "one code object per input and kind");
 
-// An unsigned value of a code object's kernel metadata built here (the
-// AMDGPU msgpack note of its one kernel): the integer after the fixstr key,
-// or -1.
-int64_t code_meta(const std::vector<char> &code, const char *key) {
-    const size_t n = std::strlen(key);
-    if (n == 0 || n > 31) return -1;
-    std::string pat(1, static_cast<char>(0xa0 | n));
-    pat += key;
-    const std::string bytes(code.begin(), code.end());
-    const size_t at = bytes.find(pat);
-    if (at == std::string::npos) return -1;
-    size_t i = at + pat.size();
-    auto byte = [&](size_t j) -> int64_t {
-        return j < bytes.size() ? static_cast<unsigned char>(bytes[j]) : -1;
-    };
-    const int64_t tag = byte(i);
-    if (tag < 0) return -1;
-    if (tag <= 0x7f) return tag;                                        // positive fixint
-    int len = tag == 0xcc ? 1 : tag == 0xcd ? 2 : tag == 0xce ? 4 : 0;  // uint8/16/32
-    if (len == 0) return -1;
-    int64_t v = 0;
-    for (int k = 1; k <= len; ++k) {
-        const int64_t b = byte(i + k);
-        if (b < 0) return -1;
-        v = (v << 8) | b;
-    }
-    return v;
-}
-
 // Whether the second of two compiled forms of one kernel is the better one:
 // no more private (spill) memory, and at least the waves per SIMD its VGPRs
 // allow; unreadable metadata keeps the first.
@@ -220,6 +191,35 @@ AmiStatus code_object(AmiTerms *t, bool hub, int kind) {
 }
 
 }  // namespace
+
+// An unsigned value of a code object's kernel metadata built here (the
+// AMDGPU msgpack note of its one kernel): the integer after the fixstr key,
+// or -1.
+int64_t code_meta(const std::vector<char> &code, const char *key) {
+    const size_t n = std::strlen(key);
+    if (n == 0 || n > 31) return -1;
+    std::string pat(1, static_cast<char>(0xa0 | n));
+    pat += key;
+    const std::string bytes(code.begin(), code.end());
+    const size_t at = bytes.find(pat);
+    if (at == std::string::npos) return -1;
+    size_t i = at + pat.size();
+    auto byte = [&](size_t j) -> int64_t {
+        return j < bytes.size() ? static_cast<unsigned char>(bytes[j]) : -1;
+    };
+    const int64_t tag = byte(i);
+    if (tag < 0) return -1;
+    if (tag <= 0x7f) return tag;                                        // positive fixint
+    int len = tag == 0xcc ? 1 : tag == 0xcd ? 2 : tag == 0xce ? 4 : 0;  // uint8/16/32
+    if (len == 0) return -1;
+    int64_t v = 0;
+    for (int k = 1; k <= len; ++k) {
+        const int64_t b = byte(i + k);
+        if (b < 0) return -1;
+        v = (v << 8) | b;
+    }
+    return v;
+}
 
 AmiStatus code_from_source(const std::string &src, std::vector<char> &code, std::string &err) {
     const std::string dir = cache_dir();

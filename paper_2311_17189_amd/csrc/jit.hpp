@@ -68,6 +68,10 @@ int jit_nested_override();
 // the two compiled ones' registers and spills).
 constexpr int kJitNestedPartTerms = 4;
 
+// Unsigned ints between two work-list counters of a persistent batch kernel
+// (one 128-byte cache line each).
+constexpr int kBatchCounterStride = 32;
+
 // Source of one module of the persistent specialized batch: the generated
 // functions of every item (forward in one pass, or the two-pass forward where
 // two_pass[j] is set; one_row[j]: the one-pass tile for exactly one frequency
@@ -75,11 +79,19 @@ constexpr int kJitNestedPartTerms = 4;
 // lanes per block, and the persistent kernels selected by `phases`:
 // ami_batch_p1 (phases & 1: one-pass tiles and the two-pass items' first
 // pass) and ami_batch_p2 (phases & 2, with any two-pass item: their frequency
-// pass, a work item being a tile range at one row).
+// pass, a work item being a tile range at a range of rows).  The kernels take
+// eight counters kBatchCounterStride apart, one per work list.
 // A work item names its item by labels[j] (by j when labels is empty).
+// claim_ahead: a block claims its next work item before it runs the current
+// one (the claim's round trip overlaps the work, for a register more);
+// waves > 0: the kernels are compiled for at least that many waves per SIMD.
 std::string jit_batch_source(const std::vector<const AmiTerms *> &items, const std::vector<int> &two_pass,
                              const std::vector<int> &one_row, bool hub, int block, int phases,
-                             const std::vector<int> &labels);
+                             const std::vector<int> &labels, bool claim_ahead = true, int waves = 0);
+
+// An unsigned value of the kernel metadata of a code object built here (the
+// integer after the key in its one kernel's note), or -1.
+int64_t code_meta(const std::vector<char> &code, const char *key);
 
 // Kernels of the specialized evaluator.
 // kJitAdjFreq and kJitAdjLeaf are the frequency and leaf passes of the

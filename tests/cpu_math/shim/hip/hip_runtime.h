@@ -18,6 +18,7 @@ inline double __shfl_xor(double v, int, int) { return v; }
 // one lane per "wave" on the host: cross-lane moves return the lane's own value
 inline int __builtin_amdgcn_mov_dpp(int src, int, int, int, bool) { return src; }
 inline int __builtin_amdgcn_readlane(int v, int) { return v; }
+inline unsigned __builtin_amdgcn_readfirstlane(unsigned v) { return v; }
 struct AmiLanePair {
     unsigned v[2];
     unsigned operator[](int i) const { return v[i]; }
