@@ -598,9 +598,8 @@ typedef struct {
  * every item's generated tile functions and a persistent kernel that pulls
  * (item, tile range, range of frequency rows) work items from its own
  * counters; the graph runs counter reset -> the first-pass kernels side by
- * side -> the
- * frequency-pass kernels -> fixed-order row sums; out and out_sum equal an
- * AUTO evaluate call's bit for bit.
+ * side -> the frequency-pass kernels -> fixed-order row sums; out and out_sum
+ * equal an AUTO evaluate call's bit for bit.
  */
 AmiStatus amiBatchCreate(const AmiBatchItem *items, int32_t n_items, const AmiBatchTuning *tuning,
                          AmiBatch **out);
