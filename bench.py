@@ -414,6 +414,10 @@ def configs_section(args, torch, dev, stream):
         f_med, f_min = _median_ms(torch, stream, fwd, reps=21)
         nbytes = n_e * 2 * d.n_int * 8 + 256 * n_e * 16 + 256 * 16
         fl = rl.specialized_forward_flops(st, n_e, 256, d.alpha)["total"]
+        # a plain write kernel of known size on the same buffer (torch's fill of
+        # out): the write rate this GPU reaches, beside the vendor figure
+        z_med, _ = _median_ms(torch, stream, out.zero_, reps=11)
+        zbytes = out.numel() * out.element_size()
         res["C3_real_frequency_grid"] = {
             "workload": "order-4 topology (0, 4, 1), 10^6 k-samples, 256 real frequencies omega + 0.05i, "
                         "omega in [-6, 6], beta=5, out [256, 10^6] complex128 (4.1 GB) + row sums",
@@ -421,6 +425,8 @@ def configs_section(args, torch, dev, stream):
             "term_evals_per_s": float(st.T) * n_e * 256 / (f_med * 1e-3),
             "algorithmic_bytes": nbytes, "hbm_gb_per_s": nbytes / (f_med * 1e-3) / 1e9,
             "frac_hbm_peak": nbytes / (f_med * 1e-3) / rl.PEAK_HBM,
+            "plain_write_gb_per_s": zbytes / (z_med * 1e-3) / 1e9,
+            "frac_of_plain_write": (nbytes / f_med) / (zbytes / z_med),
             "flops": fl, "frac_fp64_peak": fl / (f_med * 1e-3) / rl.PEAK_FP64_VECTOR}
         del out
     except amd.AmiError as e:
